@@ -1,0 +1,59 @@
+"""Pins of the oracle's coupled step: exact momentum exchange between the
+filaments and the normal fluid, and the LIA ring-decay trend (Sec. III.A)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import coupled, lbm, vfm
+from oracle.lbm import Lattice
+from oracle.vfm import VortexParams
+
+
+def _ring32_state():
+    cfg = wl.config_ring32()
+    L = cfg["lattice"]
+    lat = Lattice(L["nx"], L["ny"], L["nz"], tau=L["tau"], walls=L["walls"])
+    vp = VortexParams(**cfg["vortex"])
+    st = coupled.make_state(cfg["rho"], cfg["u"], cfg["pos"], cfg["nxt"], lat)
+    return lat, vp, st
+
+
+def test_coupled_step_momentum_exchange():
+    """Periodic box: the normal fluid gains exactly the total spread force,
+    which equals the sum of the point forces (no walls)."""
+    lat, vp, st = _ring32_state()
+    j0 = lbm.momentum(st.f).sum(axis=(1, 2, 3))
+    st1 = coupled.coupled_step(st, lat, vp)
+    j1 = lbm.momentum(st1.f).sum(axis=(1, 2, 3))
+    np.testing.assert_allclose(j1 - j0, st1.force.sum(axis=(1, 2, 3)), rtol=1e-9, atol=1e-18)
+    _, ub = lbm.bare_velocity(st.f, lat)
+    st1v = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, None, lat, vp, want_force=True)
+    np.testing.assert_allclose(st1.force.sum(axis=(1, 2, 3)), st1v["force"].sum(axis=0), rtol=1e-12)
+    # the ring drags the fluid along its direction of travel (+z)
+    assert st1.force.sum(axis=(1, 2, 3))[2] > 0
+
+
+def test_lia_ring_decay_trend():
+    """One-way VFM, fluid at rest: R^2 falls linearly in time, with slope
+    2 alpha R V where V is the self-induced speed (Sec. III.A, Eq. R(t),
+    there with beta_ind's ln(R/a) in place of the full ring constant)."""
+    lat = Lattice(48, 48, 48)
+    vp = VortexParams(kappa=0.1, alpha=0.2, alpha_p=0.0, coupling=False, remesh=False)
+    pos, nxt = wl.ring((24.0, 24.0, 24.0), 8.0, (0, 0, 1), 64)
+    prv = coupled.prev_from_next(nxt)
+    ub = np.zeros((3,) + lat.shape)
+    R2 = []
+    for _ in range(40):
+        c = pos.mean(axis=0)
+        R2.append(((pos[:, :2] - c[:2]) ** 2).sum(axis=1).mean())
+        pos, _ = coupled.filament_rk4(pos, nxt, prv, ub, None, lat, vp)
+    R2 = np.array(R2)
+    slope = np.polyfit(np.arange(40), R2, 1)[0]
+    V = 0.1 / (4 * np.pi * 8.0) * (math.log(64 / 1e-3) - 0.5) * 1.0073
+    assert slope == pytest.approx(-2 * 0.2 * 8.0 * V, rel=0.02)
+    # the paper's beta_ind = kappa/(4 pi) ln(R/a) gives the same trend to ~20%
+    beta_ind = 0.1 / (4 * np.pi) * math.log(8.0 / 1e-3)
+    assert abs(slope / (-2 * 0.2 * beta_ind) - 1) < 0.3

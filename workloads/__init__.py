@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/bench and the
+oracle.  Holds no arithmetic of the method itself: only initial filament
+geometry (rings), initial density/velocity fields, and plain-data workload
+presets.  Both sides turn (rho, u) into populations themselves.
+
+Generators use numpy ``Generator(PCG64(seed))``.
+"""
+
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------- filaments
+
+
+def ring(center, radius, normal, n_pts, phase=0.5):
+    """Closed ring of ``n_pts`` points at angles 2 pi (j + phase) / n_pts,
+    ordered so that the ring's self-induced motion is along +normal.
+    Returns (pos (n, 3) float64, nxt (n,) int64)."""
+    n = np.asarray(normal, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    # e1, e2 with e1 x e2 = n
+    a = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(a, n)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    th = 2.0 * np.pi * (np.arange(n_pts) + phase) / n_pts
+    pos = (np.asarray(center, dtype=np.float64)[None, :]
+           + radius * (np.cos(th)[:, None] * e1[None, :] + np.sin(th)[:, None] * e2[None, :]))
+    nxt = (np.arange(n_pts) + 1) % n_pts
+    return pos, nxt.astype(np.int64)
+
+
+def concat_loops(loops):
+    """Concatenate (pos, nxt) loops into one point set with global links."""
+    if not loops:
+        return np.zeros((0, 3)), np.zeros(0, dtype=np.int64)
+    pos, nxt, off = [], [], 0
+    for p, n in loops:
+        pos.append(p)
+        nxt.append(n + off)
+        off += p.shape[0]
+    return np.concatenate(pos, axis=0), np.concatenate(nxt).astype(np.int64)
+
+
+def random_unit(rng):
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def random_rings(seed, n_rings, r_lo, r_hi, dims, walls, dxi_max, margin=1.0):
+    """``n_rings`` rings with radii U[r_lo, r_hi], normals uniform on the
+    sphere, centres uniform (kept a radius + margin away from walls);
+    ring spacing 2 pi R / ceil(2 pi R / dxi_max) <= dxi_max."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    loops = []
+    for _ in range(n_rings):
+        R = rng.uniform(r_lo, r_hi)
+        c = np.empty(3)
+        for a in range(3):
+            if walls[a]:
+                lo, hi = R + margin - 0.5, dims[a] - 0.5 - R - margin
+                c[a] = rng.uniform(lo, hi) if hi > lo else 0.5 * (dims[a] - 1)
+            else:
+                c[a] = rng.uniform(0.0, dims[a])
+        nrm = random_unit(rng)
+        npts = int(math.ceil(2.0 * math.pi * R / dxi_max))
+        loops.append(ring(c, R, nrm, npts, phase=rng.uniform(0.0, 1.0)))
+    return concat_loops(loops)
+
+
+# ------------------------------------------------------------ lattice init
+
+
+def velocity_field(seed, dims, u0, sigma):
+    """rho = 1, u = u0 + N(0, sigma^2) per component per node.
+    Returns rho (nz, ny, nx), u (3, nz, ny, nx), float64."""
+    nx, ny, nz = dims
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = np.empty((3, nz, ny, nx))
+    for a in range(3):
+        u[a] = u0[a]
+    if sigma > 0:
+        u += rng.normal(0.0, sigma, size=u.shape)
+    rho = np.ones((nz, ny, nx))
+    return rho, u
+
+
+# ------------------------------------------------------------- presets
+# Plain data.  Lattice keys: nx, ny, nz, tau, walls (per axis), plane_lo,
+# plane_hi, plane_u, body_force, precision ("f64" | "f32" | "f16").
+# Vortex keys mirror the oracle's VortexParams.
+
+VORTEX_DEFAULTS = dict(
+    kappa=0.1, core_a=1e-3, core_c=0.5, alpha=0.2, alpha_p=0.01,
+    rho_s_over_rho_n=1.35, dxi_min=0.70, dxi_max=0.95, reconnect_dist=0.95,
+    remesh=True, reconnect=False, min_loop_pts=5, coupling=True,
+    mass_balance=False, vs_applied=(0.0, 0.0, 0.0),
+)
+
+
+def lattice_preset(nx, ny, nz, tau=0.8, walls=(False, False, False), plane_lo=False,
+                   plane_hi=False, plane_u=(0.0, 0.0, 0.0), body_force=(0.0, 0.0, 0.0),
+                   precision="f64"):
+    return dict(nx=nx, ny=ny, nz=nz, tau=tau, walls=tuple(walls), plane_lo=plane_lo,
+                plane_hi=plane_hi, plane_u=tuple(plane_u), body_force=tuple(body_force),
+                precision=precision)
+
+
+def vortex_preset(**kw):
+    v = dict(VORTEX_DEFAULTS)
+    v.update(kw)
+    return v
+
+
+def config_ring32(precision="f64"):
+    """Plain small case: 32^3 periodic, tau 0.8, u = (0,0,0.01) + N(0,1e-4^2),
+    one ring R = 8 of 64 points (half-spacing phase), 100 steps."""
+    lat = lattice_preset(32, 32, 32, tau=0.8, precision=precision)
+    vor = vortex_preset()
+    rho, u = velocity_field(1, (32, 32, 32), (0.0, 0.0, 0.01), 1e-4)
+    pos, nxt = ring((16.0, 16.0, 16.0), 8.0, (0.0, 0.0, 1.0), 64, phase=0.5)
+    return dict(name="ring32", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
+                steps=100)
+
+
+# Body force for a mean duct velocity of 0.02 in a 64x64 square duct,
+# tau = 0.8 (nu = 0.1): G = 28.45 nu U / W^2 (laminar square-duct relation).
+COUNTERFLOW_G = 28.45 * 0.1 * 0.02 / (64.0 * 64.0)
+
+
+def config_counterflow(precision="f32", n_rings=200, nz=256, nxy=64, seed=2):
+    """Counterflow channel: 64x64x256, bounce-back walls on x and y, periodic
+    z, Guo body force along z for a mean v_n of about 0.02, 200 rings with
+    R ~ U[4, 12], remeshing spacing 1.0 (dxi_min = 0.737 keeps the paper's
+    0.70/0.95 ratio), mass balance on z, 1000 steps."""
+    lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(True, True, False),
+                         body_force=(0.0, 0.0, COUNTERFLOW_G * (64.0 / nxy) ** 2),
+                         precision=precision)
+    vor = vortex_preset(dxi_max=1.0, dxi_min=0.70 / 0.95, reconnect_dist=1.0,
+                        mass_balance=True)
+    rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.02), 0.0)
+    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (nxy, nxy, nz), (True, True, False), 1.0)
+    return dict(name="counterflow_64x64x256", lattice=lat, vortex=vor, rho=rho, u=u,
+                pos=pos, nxt=nxt, steps=1000)
+
+
+def config_heater(precision="f32", n_rings=1500, nxy=128, nz=512, seed=3):
+    """Closed channel with heater: 128x128x512, walls on x and y, velocity
+    planes z = 0 / z = nz-1 at v_n = 0.03 z, 1500 rings R ~ U[3, 7.6],
+    reconnection on, mass balance on z, 2000 steps."""
+    lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(True, True, False), plane_lo=True,
+                         plane_hi=True, plane_u=(0.0, 0.0, 0.03), precision=precision)
+    vor = vortex_preset(reconnect=True, mass_balance=True)
+    rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.03), 0.0)
+    pos, nxt = random_rings(seed, n_rings, 3.0, 7.6, (nxy, nxy, nz), (True, True, False), 0.95)
+    return dict(name="heater_128x128x512", lattice=lat, vortex=vor, rho=rho, u=u,
+                pos=pos, nxt=nxt, steps=2000)
+
+
+def config_tangle(precision="f16", n=256, n_rings=2000, seed=4):
+    """Precision form: 256^3 periodic, u = 0.02 z + N(0, 1e-4^2), random tangle
+    of 2000 rings R ~ U[4, 12] (about 1e5 points), mass balance on z."""
+    lat = lattice_preset(n, n, n, tau=0.8, precision=precision)
+    vor = vortex_preset(mass_balance=True)
+    rho, u = velocity_field(seed, (n, n, n), (0.0, 0.0, 0.02), 1e-4)
+    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (n, n, n), (False, False, False), 0.95)
+    return dict(name="tangle_256", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
+                steps=100)

@@ -1,0 +1,194 @@
+/*
+ * vlb.h -- C ABI of the coupled vortex-filament / lattice-Boltzmann step
+ * (S. Inui and M. Tsubota, arXiv:2108.04435, Sec. II) on AMD gfx950.
+ *
+ * One "run" is one simulation: a D3Q19 normal-fluid lattice (Sec. II.B)
+ * plus a set of closed vortex filaments (Sec. II.A), coupled through the
+ * mutual-friction force (Sec. II.B).  All state lives in ONE caller-owned
+ * block of device memory (the workspace); the library never allocates
+ * device memory.  All device work is enqueued on ONE caller-owned HIP
+ * stream, given at creation.
+ *
+ * Conventions
+ *  - Every function returns a vlb_status (0 = success, negative = error);
+ *    no C++ exception crosses this boundary.  After an error,
+ *    vlb_last_error(run) returns a message (NULL-run errors go to
+ *    vlb_last_error(NULL)).
+ *  - "host" pointers are ordinary CPU memory, read or written synchronously
+ *    before the call returns.  "device" pointers are device memory on the
+ *    run's GPU; the copy is enqueued on the run's stream and the call
+ *    synchronises that stream before returning.
+ *  - Lattice fields are stored z-major: index = (z * ny + y) * nx + x.
+ *    Vector fields are three such blocks (x, y, z components).
+ *  - Lattice units: dx = dt = 1, c_s^2 = 1/3 (Sec. II.B, Step 1).
+ *  - Deferred device errors (capacity overflow, non-finite values) are
+ *    latched on the device and returned by the next vlb_sync /
+ *    vlb_read_* call.
+ *  - A run is not thread-safe; different runs may be used from different
+ *    threads.
+ */
+#ifndef VLB_H
+#define VLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vlb_run vlb_run; /* opaque host handle, owned by the library */
+
+typedef enum {
+  VLB_OK = 0,
+  VLB_EINVAL = -1,    /* invalid argument; nothing was changed             */
+  VLB_ENOSPACE = -2,  /* workspace smaller than vlb_query_footprint        */
+  VLB_EDEVICE = -3,   /* a HIP call failed                                  */
+  VLB_ESTATE = -4,    /* call out of order (e.g. step before any fields)    */
+  VLB_ECAPACITY = -5, /* filament points or reconnection candidates
+                         exceeded their capacity; the step that overflowed
+                         skipped the operation that needed the room         */
+  VLB_ENUMERIC = -6   /* NaN/Inf met in the normal-fluid or line velocity   */
+} vlb_status;
+
+/* Precision of the normal-fluid populations and of the Biot-Savart sum.  */
+typedef enum {
+  VLB_F64 = 0, /* plain path: populations, LBM and Biot-Savart in FP64     */
+  VLB_F32 = 1, /* populations stored as FP32 deviations f_i - w_i (rho0=1),
+                  FP32 LBM arithmetic, FP32 Biot-Savart                    */
+  VLB_F16 = 2  /* populations stored as FP16 deviations scaled by 2^10,
+                  FP32 arithmetic, FP32 Biot-Savart                        */
+} vlb_precision;
+
+/* Lattice and normal fluid (Sec. II.B).                                    */
+typedef struct {
+  int32_t nx, ny, nz;     /* nodes per axis, each >= 4                      */
+  int32_t precision;      /* vlb_precision                                  */
+  double tau;             /* BGK relaxation time (Sec. II.B, Eq. BGK), > 1/2 */
+  uint32_t wall_axes;     /* bit a (0=x,1=y,2=z): axis a is closed by two
+                             halfway bounce-back walls half a cell outside
+                             its first and last node; otherwise periodic   */
+  int32_t plane_lo;       /* 1: nodes z = 0 carry f^eq(1, plane_u) before
+                             each collision (heater plane, Sec. III.C, IV)  */
+  int32_t plane_hi;       /* 1: the same on z = nz-1 (cooler plane)         */
+  int32_t reserved0;
+  double plane_u[3];      /* velocity imposed on the planes                 */
+  double body_force[3];   /* uniform Guo body force added at every node     */
+} vlb_lattice_desc;
+
+/* Vortex filaments and coupling (Sec. II.A, II.B, III.B, III.C).            */
+typedef struct {
+  double kappa;           /* circulation quantum in lattice units           */
+  double core_a;          /* vortex core radius a                           */
+  double core_c;          /* LIA core constant C in ln(2 sqrt(l+ l-)/(e^C a)) */
+  double alpha, alpha_p;  /* mutual friction coefficients (Eq. E of M)      */
+  double rho_s_over_rho_n;/* rho_s / rho_n                                  */
+  double dxi_min, dxi_max;/* remeshing bounds on segment length (Sec. II.A) */
+  double reconnect_dist;  /* leg exchange below this distance (Sec. III.B)  */
+  double vs_applied[3];   /* externally applied superflow v_s,a (Eq. B-S)   */
+  int32_t remesh;         /* 1: keep segments inside [dxi_min, dxi_max]     */
+  int32_t reconnect;      /* 1: reconnection on                             */
+  int32_t min_loop_pts;   /* loops with fewer points are removed (>= 3)     */
+  int32_t coupling;       /* 1: the mutual-friction force acts on the
+                             normal fluid; 0: prescribed normal fluid       */
+  int32_t mass_balance;   /* 1: superflow V_s(z) from mass conservation
+                             along z (Sec. III.C, Eq. mass cons); z must be
+                             periodic                                       */
+  int32_t reserved0;
+  int64_t n_cap;          /* capacity in filament points (>= 1)             */
+  int64_t recon_cap;      /* capacity in reconnection candidates per step   */
+} vlb_vortex_desc;
+
+/* Bytes of device workspace a run with these descriptors needs.           */
+int vlb_query_footprint(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
+                        uint64_t* bytes);
+
+/* Create a run inside the caller's device workspace (>= footprint bytes,
+ * 256-byte aligned) on the caller's stream (hipStream_t, may be NULL for the
+ * null stream).  Populations start at equilibrium f^eq(rho = 1, u = 0);
+ * there are no filaments.  The workspace and stream must outlive the run.  */
+int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
+                       void* dev_workspace, uint64_t ws_bytes, void* hip_stream,
+                       vlb_run** out);
+
+/* Populations <- f^eq(rho, u) (Sec. II.B, Step 1).  rho: device, nx*ny*nz
+ * doubles; u: device, 3*nx*ny*nz doubles.  Resets the step counter and the
+ * spread force field.                                                      */
+int vlb_write_fields(vlb_run* run, const double* rho_dev, const double* u_dev);
+
+/* Replace the filaments by n_pts points (host xyz[n][3], lattice units) on
+ * closed loops given by next (host, n ints, a permutation whose cycles are
+ * the loops).  Positions on periodic axes are wrapped into [0, L).       */
+int vlb_seed_vortices(vlb_run* run, int64_t n_pts, const double* xyz_host,
+                      const int32_t* next_host);
+
+/* Enqueue n_steps coupled steps (Sec. II): filament RK4 with the
+ * Biot-Savart + LIA velocity and the Schwarz equation of motion, force
+ * spreading, one forced LBM update, remeshing / reconnection.  Returns
+ * after enqueueing (asynchronous).                                         */
+int vlb_step(vlb_run* run, int64_t n_steps);
+
+/* Wait for the run's stream; return a latched device error if any.         */
+int vlb_sync(vlb_run* run);
+
+/* Density and bare velocity sum(c_i f_i)/sum(f_i) of the current
+ * populations (velocity planes applied).  Device outputs: rho (cells) and
+ * u (3*cells) doubles; either may be NULL.                                  */
+int vlb_read_fields(vlb_run* run, double* rho_dev, double* u_dev);
+
+/* Current populations f_i (full value, not deviation) as doubles, device
+ * output of 19*cells, population-major (i slowest), in the library's fixed
+ * D3Q19 order: rest, +x,-x,+y,-y,+z,-z, (+1,+1,0),(-1,-1,0),(+1,-1,0),
+ * (-1,+1,0), (+1,0,+1),(-1,0,-1),(+1,0,-1),(-1,0,+1), (0,+1,+1),(0,-1,-1),
+ * (0,+1,-1),(0,-1,+1).                                                      */
+int vlb_read_populations(vlb_run* run, double* f_dev);
+
+/* The force field spread by the last step (or vlb_eval_line_velocity):
+ * device output of 3*cells doubles (body force not included).               */
+int vlb_read_force(vlb_run* run, double* force_dev);
+
+/* Current filaments: up to cap points into host xyz[cap][3] and next[cap];
+ * *n_pts receives the point count (also when it exceeds cap, then
+ * VLB_ENOSPACE and nothing is copied).                                     */
+int vlb_read_filaments(vlb_run* run, int64_t cap, double* xyz_host, int32_t* next_host,
+                       int64_t* n_pts);
+
+/* Evaluate, at the current positions and normal fluid and without
+ * advancing, what the first RK stage of a step computes: per point the
+ * superfluid velocity v_s (non-local Biot-Savart + LIA + applied +
+ * mass-balance superflow), the interpolated normal-fluid velocity v_n, the
+ * line velocity ds/dt and the mutual-friction force g on the normal fluid;
+ * host outputs of n_pts*3 doubles each (any may be NULL).  When coupling is
+ * on, the force is also spread into the force field (see vlb_read_force). */
+int vlb_eval_line_velocity(vlb_run* run, double* vs_host, double* vn_host,
+                           double* sdot_host, double* force_host);
+
+/* Apply only the topology phase of a step (remeshing, reconnection,
+ * small-loop removal, compaction) to the current filaments.  stats_host
+ * (may be NULL) receives 4 int64: deleted, inserted, reconnections, points
+ * removed with small loops.                                                */
+int vlb_apply_topology(vlb_run* run, int64_t* stats_host);
+
+/* Number of completed steps.                                               */
+int vlb_get_step(vlb_run* run, int64_t* step);
+
+/* Kernel timing with HIP events recorded on the run's stream around every
+ * launch of the named kernel class: 0 = Biot-Savart pair sum, 1 = LBM
+ * collide+stream.  vlb_set_timing(run, 1) clears and enables; the totals
+ * are read (after a sync) with vlb_get_timing.                             */
+int vlb_set_timing(vlb_run* run, int32_t enable);
+int vlb_get_timing(vlb_run* run, int32_t kernel_class, double* total_ms, int64_t* launches);
+
+/* Algorithmic work of the last step: lattice node updates and Biot-Savart
+ * (target, segment) pairs summed over the RK stages.                      */
+int vlb_get_work(vlb_run* run, int64_t* node_updates, int64_t* bs_pairs);
+
+/* Release the host handle.  The workspace is the caller's to free.         */
+int vlb_destroy(vlb_run* run);
+
+const char* vlb_last_error(const vlb_run* run);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VLB_H */

@@ -1,0 +1,304 @@
+"""Coupled vortex-filament / lattice-Boltzmann step for superfluid 4He on
+AMD gfx950 (S. Inui and M. Tsubota, arXiv:2108.04435, Sec. II).
+
+This package is a thin ctypes binding over the HIP library ``libvlb.so``
+(C ABI in ``include/vlb.h``).  It only marshals arguments: device memory
+(the run's workspace and field buffers) comes from PyTorch tensors, the
+stream is PyTorch's current stream, and every step of the method runs in
+the library's kernels.  There is no CPU fallback: if the library is not
+built, importing ``Run`` works but creating one raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvlb.so")
+
+VLB_OK = 0
+VLB_EINVAL = -1
+VLB_ENOSPACE = -2
+VLB_EDEVICE = -3
+VLB_ESTATE = -4
+VLB_ECAPACITY = -5
+VLB_ENUMERIC = -6
+
+PRECISION = {"f64": 0, "f32": 1, "f16": 2}
+
+# Exported symbols, in the order of include/vlb.h.
+SYMBOLS = [
+    "vlb_query_footprint", "vlb_create_lattice", "vlb_write_fields", "vlb_seed_vortices",
+    "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
+    "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology", "vlb_get_step",
+    "vlb_set_timing", "vlb_get_timing", "vlb_get_work", "vlb_destroy", "vlb_last_error",
+]
+
+
+class LatticeDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("wall_axes", ctypes.c_uint32),
+        ("plane_lo", ctypes.c_int32), ("plane_hi", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("plane_u", ctypes.c_double * 3),
+        ("body_force", ctypes.c_double * 3),
+    ]
+
+
+class VortexDesc(ctypes.Structure):
+    _fields_ = [
+        ("kappa", ctypes.c_double), ("core_a", ctypes.c_double), ("core_c", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("alpha_p", ctypes.c_double),
+        ("rho_s_over_rho_n", ctypes.c_double),
+        ("dxi_min", ctypes.c_double), ("dxi_max", ctypes.c_double),
+        ("reconnect_dist", ctypes.c_double),
+        ("vs_applied", ctypes.c_double * 3),
+        ("remesh", ctypes.c_int32), ("reconnect", ctypes.c_int32),
+        ("min_loop_pts", ctypes.c_int32), ("coupling", ctypes.c_int32),
+        ("mass_balance", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
+    ]
+
+
+class VlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vlb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libvlb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"{p} is missing: build it with `python -m paper_2108_04435_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.vlb_query_footprint.argtypes = [ctypes.POINTER(LatticeDesc), ctypes.POINTER(VortexDesc),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+    lib.vlb_create_lattice.argtypes = [ctypes.POINTER(LatticeDesc), ctypes.POINTER(VortexDesc),
+                                       vp, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    lib.vlb_write_fields.argtypes = [vp, vp, vp]
+    lib.vlb_seed_vortices.argtypes = [vp, i64, vp, vp]
+    lib.vlb_step.argtypes = [vp, i64]
+    lib.vlb_sync.argtypes = [vp]
+    lib.vlb_read_fields.argtypes = [vp, vp, vp]
+    lib.vlb_read_populations.argtypes = [vp, vp]
+    lib.vlb_read_force.argtypes = [vp, vp]
+    lib.vlb_read_filaments.argtypes = [vp, i64, vp, vp, ctypes.POINTER(i64)]
+    lib.vlb_eval_line_velocity.argtypes = [vp, vp, vp, vp, vp]
+    lib.vlb_apply_topology.argtypes = [vp, vp]
+    lib.vlb_get_step.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.vlb_set_timing.argtypes = [vp, ctypes.c_int32]
+    lib.vlb_get_timing.argtypes = [vp, ctypes.c_int32, dp, ctypes.POINTER(i64)]
+    lib.vlb_get_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.vlb_destroy.argtypes = [vp]
+    lib.vlb_last_error.argtypes = [vp]
+    lib.vlb_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def lattice_desc(lat: dict) -> LatticeDesc:
+    d = LatticeDesc()
+    d.nx, d.ny, d.nz = int(lat["nx"]), int(lat["ny"]), int(lat["nz"])
+    d.precision = PRECISION[lat.get("precision", "f64")]
+    d.tau = float(lat.get("tau", 0.8))
+    walls = lat.get("walls", (False, False, False))
+    d.wall_axes = sum(1 << a for a in range(3) if walls[a])
+    d.plane_lo = int(bool(lat.get("plane_lo", False)))
+    d.plane_hi = int(bool(lat.get("plane_hi", False)))
+    for a in range(3):
+        d.plane_u[a] = float(lat.get("plane_u", (0, 0, 0))[a])
+        d.body_force[a] = float(lat.get("body_force", (0, 0, 0))[a])
+    return d
+
+
+def vortex_desc(vor: dict, n_cap: int, recon_cap: int = 1 << 16) -> VortexDesc:
+    d = VortexDesc()
+    for k in ("kappa", "core_a", "core_c", "alpha", "alpha_p", "rho_s_over_rho_n", "dxi_min",
+              "dxi_max", "reconnect_dist"):
+        setattr(d, k, float(vor[k]))
+    for a in range(3):
+        d.vs_applied[a] = float(vor.get("vs_applied", (0, 0, 0))[a])
+    d.remesh = int(bool(vor.get("remesh", True)))
+    d.reconnect = int(bool(vor.get("reconnect", False)))
+    d.min_loop_pts = int(vor.get("min_loop_pts", 5))
+    d.coupling = int(bool(vor.get("coupling", True)))
+    d.mass_balance = int(bool(vor.get("mass_balance", False)))
+    d.n_cap = int(n_cap)
+    d.recon_cap = int(recon_cap)
+    return d
+
+
+class Run:
+    """One coupled simulation resident on a GPU.
+
+    ``lattice`` / ``vortex`` are plain dicts (keys as in LatticeDesc /
+    VortexDesc; ``walls`` is a per-axis bool triple, ``precision`` one of
+    "f64", "f32", "f16")."""
+
+    def __init__(self, lattice: dict, vortex: dict, n_cap: int, device=0, recon_cap=1 << 16,
+                 stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.lat = dict(lattice)
+        self.ld = lattice_desc(lattice)
+        self.vd = vortex_desc(vortex, n_cap, recon_cap)
+        self.shape = (self.ld.nz, self.ld.ny, self.ld.nx)
+        self.cells = self.ld.nx * self.ld.ny * self.ld.nz
+        nbytes = ctypes.c_uint64(0)
+        self._check(self.lib.vlb_query_footprint(ctypes.byref(self.ld), ctypes.byref(self.vd),
+                                                 ctypes.byref(nbytes)), None)
+        self.footprint = int(nbytes.value)
+        self.ws = torch.empty(self.footprint + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.vlb_create_lattice(ctypes.byref(self.ld), ctypes.byref(self.vd),
+                                                ctypes.c_void_p(self._ws_ptr),
+                                                ctypes.c_uint64(self.footprint),
+                                                ctypes.c_void_p(self.stream.cuda_stream),
+                                                ctypes.byref(h)), None)
+        self.h = h
+        self.n_cap = int(n_cap)
+
+    # ----------------------------------------------------------- plumbing
+    def _check(self, code, h="self"):
+        if code != VLB_OK:
+            hh = self.h if h == "self" else None
+            msg = self.lib.vlb_last_error(hh)
+            raise VlbError(code, msg.decode() if msg else "")
+
+    def _dev(self, arr, shape):
+        t = self.torch.as_tensor(np.ascontiguousarray(arr, dtype=np.float64)).reshape(shape)
+        return t.to(self.device).contiguous()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- state
+    def write_fields(self, rho, u):
+        r = self._dev(rho, self.shape)
+        v = self._dev(u, (3,) + self.shape)
+        self._check(self.lib.vlb_write_fields(self.h, ctypes.c_void_p(r.data_ptr()),
+                                              ctypes.c_void_p(v.data_ptr())))
+
+    def seed(self, pos, nxt):
+        p = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        n = np.ascontiguousarray(nxt, dtype=np.int32).reshape(-1)
+        self._check(self.lib.vlb_seed_vortices(self.h, p.shape[0], p.ctypes.data_as(ctypes.c_void_p),
+                                               n.ctypes.data_as(ctypes.c_void_p)))
+
+    def step(self, n=1):
+        self._check(self.lib.vlb_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.vlb_sync(self.h))
+
+    def read_fields(self):
+        torch = self.torch
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.vlb_read_fields(self.h, ctypes.c_void_p(rho.data_ptr()),
+                                             ctypes.c_void_p(u.data_ptr())))
+        return rho.cpu().numpy(), u.cpu().numpy()
+
+    def read_populations(self):
+        f = self.torch.empty((19,) + self.shape, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.vlb_read_populations(self.h, ctypes.c_void_p(f.data_ptr())))
+        return f.cpu().numpy()
+
+    def read_force(self):
+        F = self.torch.empty((3,) + self.shape, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.vlb_read_force(self.h, ctypes.c_void_p(F.data_ptr())))
+        return F.cpu().numpy()
+
+    def n_points(self):
+        n = ctypes.c_int64(0)
+        code = self.lib.vlb_read_filaments(self.h, 0, None, None, ctypes.byref(n))
+        if code not in (VLB_OK, VLB_ENOSPACE):
+            self._check(code)
+        return int(n.value)
+
+    def read_filaments(self):
+        n = self.n_points()
+        pos = np.zeros((n, 3))
+        nxt = np.zeros(n, dtype=np.int32)
+        m = ctypes.c_int64(0)
+        self._check(self.lib.vlb_read_filaments(self.h, n, pos.ctypes.data_as(ctypes.c_void_p),
+                                                nxt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(m)))
+        return pos, nxt.astype(np.int64)
+
+    def eval_line_velocity(self):
+        n = self.n_points()
+        out = {k: np.zeros((n, 3)) for k in ("vs", "vn", "sdot", "force")}
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        self._check(self.lib.vlb_eval_line_velocity(self.h, ptr(out["vs"]), ptr(out["vn"]),
+                                                    ptr(out["sdot"]), ptr(out["force"])))
+        return out
+
+    def apply_topology(self):
+        st = np.zeros(4, dtype=np.int64)
+        self._check(self.lib.vlb_apply_topology(self.h, st.ctypes.data_as(ctypes.c_void_p)))
+        return dict(deleted=int(st[0]), inserted=int(st[1]), reconnections=int(st[2]),
+                    loops_removed_pts=int(st[3]))
+
+    def get_step(self):
+        s = ctypes.c_int64(0)
+        self._check(self.lib.vlb_get_step(self.h, ctypes.byref(s)))
+        return int(s.value)
+
+    def set_timing(self, on=True):
+        self._check(self.lib.vlb_set_timing(self.h, 1 if on else 0))
+
+    def timing(self, cls):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        self._check(self.lib.vlb_get_timing(self.h, int(cls), ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def work(self):
+        a = ctypes.c_int64(0)
+        b = ctypes.c_int64(0)
+        self._check(self.lib.vlb_get_work(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+
+def run_from_config(cfg: dict, n_cap=None, device=0, recon_cap=1 << 16):
+    """Create a run from a workload dict (lattice, vortex, rho, u, pos, nxt)."""
+    n = cfg["pos"].shape[0]
+    cap = n_cap if n_cap is not None else max(64, int(n * 1.5) + 64)
+    r = Run(cfg["lattice"], cfg["vortex"], cap, device=device, recon_cap=recon_cap)
+    r.write_fields(cfg["rho"], cfg["u"])
+    if n:
+        r.seed(cfg["pos"], cfg["nxt"])
+    return r

@@ -1,0 +1,565 @@
+// C ABI of the vlb library (declared in include/vlb.h): argument checks,
+// workspace layout, and the order of device work inside one coupled step.
+#include "vlb_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+using namespace vlb;
+
+struct vlb_run {
+  Run r;
+};
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_err;
+
+int fail(vlb_run* h, int code, const std::string& msg) {
+  if (h) {
+    h->r.err = msg;
+  } else {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_err = msg;
+  }
+  return code;
+}
+
+int hip_fail(vlb_run* h, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(h, VLB_EDEVICE, m);
+}
+
+#define HIP_OR_FAIL(h, call)                       \
+  do {                                             \
+    hipError_t _e = (call);                        \
+    if (_e != hipSuccess) return hip_fail(h, _e, #call); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(char* b) : base(b) {}
+  void* take(size_t bytes) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+size_t elt_size(int prec) { return prec == VLB_F64 ? 8 : (prec == VLB_F32 ? 4 : 2); }
+
+int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::string& msg) {
+  if (!lat || !vor) { msg = "null descriptor"; return VLB_EINVAL; }
+  if (lat->nx < 4 || lat->ny < 4 || lat->nz < 4) { msg = "every lattice dimension must be >= 4"; return VLB_EINVAL; }
+  const double cells = (double)lat->nx * lat->ny * lat->nz;
+  if (cells > 1.0e9) { msg = "lattice larger than 1e9 nodes"; return VLB_EINVAL; }
+  if (lat->precision < 0 || lat->precision > 2) { msg = "precision must be VLB_F64, VLB_F32 or VLB_F16"; return VLB_EINVAL; }
+  if (!(lat->tau > 0.5)) { msg = "tau must exceed 1/2 (positive viscosity)"; return VLB_EINVAL; }
+  if (lat->wall_axes & ~7u) { msg = "wall_axes uses bits 0..2 only"; return VLB_EINVAL; }
+  if ((lat->plane_lo || lat->plane_hi) && (lat->wall_axes & 4u)) { msg = "velocity planes need a periodic z axis"; return VLB_EINVAL; }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(lat->plane_u[a]) || !std::isfinite(lat->body_force[a])) { msg = "non-finite plane velocity or body force"; return VLB_EINVAL; }
+  if (vor->n_cap < 1 || vor->n_cap > (1LL << 28)) { msg = "n_cap must be in [1, 2^28]"; return VLB_EINVAL; }
+  if (!(vor->kappa > 0) || !(vor->core_a > 0)) { msg = "kappa and core_a must be positive"; return VLB_EINVAL; }
+  if (!(vor->dxi_min > 0) || !(vor->dxi_max > vor->dxi_min)) { msg = "need 0 < dxi_min < dxi_max"; return VLB_EINVAL; }
+  if (vor->min_loop_pts < 3) { msg = "min_loop_pts must be >= 3"; return VLB_EINVAL; }
+  if (vor->mass_balance && (lat->wall_axes & 4u)) { msg = "mass balance needs a periodic z axis"; return VLB_EINVAL; }
+  if (vor->reconnect) {
+    if (!(vor->reconnect_dist > 0)) { msg = "reconnect_dist must be positive"; return VLB_EINVAL; }
+    if (vor->recon_cap < 1 || vor->recon_cap > (1LL << 26)) { msg = "recon_cap must be in [1, 2^26]"; return VLB_EINVAL; }
+  }
+  return VLB_OK;
+}
+
+int bits_for(unsigned long long v) {  // smallest b with v < 2^b
+  int b = 1;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+// Carve the workspace (base == nullptr: only measure).
+size_t layout(Run& r, char* base) {
+  Bump B(base);
+  const long long cells = r.cells;
+  const long long nc = r.ncap;
+  const size_t fe = r.prec == VLB_F64 ? 8 : 4;
+  r.pops = B.take(19 * cells * elt_size(r.prec));
+  r.force = B.take(3 * cells * fe);
+  r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
+  r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
+  double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage};
+  for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
+  int32_t** ibufs[] = {&r.nxt, &r.prv, &r.nxt_t, &r.prv_t, &r.stage_i, &r.flag_a, &r.flag_b,
+                       &r.scan_a, &r.scan_b, &r.used};
+  for (int32_t** p : ibufs) *p = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
+  r.bsX = (uint32_t*)B.take(3 * nc * sizeof(uint32_t));
+  r.bsD = B.take(3 * nc * fe);
+  size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
+  const size_t mb = (size_t)r.geom.nz * 32 * sizeof(double);
+  r.bsP = B.take(pbytes > mb ? pbytes : mb);
+  r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
+  r.keys_a = (uint32_t*)B.take(nc * sizeof(uint32_t));
+  r.keys_b = (uint32_t*)B.take(nc * sizeof(uint32_t));
+  r.vals_a = (int32_t*)B.take(nc * sizeof(int32_t));
+  r.vals_b = (int32_t*)B.take(nc * sizeof(int32_t));
+  r.sort_tmp_bytes = sort_tmp_bytes(nc);
+  r.sort_tmp = B.take(r.sort_tmp_bytes);
+  if (r.vor.reconnect) {
+    const long long rc = r.rcap;
+    r.rc_i = (int32_t*)B.take(rc * sizeof(int32_t));
+    r.rc_j = (int32_t*)B.take(rc * sizeof(int32_t));
+    r.rc_idx_a = (int32_t*)B.take(rc * sizeof(int32_t));
+    r.rc_idx_b = (int32_t*)B.take(rc * sizeof(int32_t));
+    r.rc_key_a = (uint64_t*)B.take(rc * sizeof(uint64_t));
+    r.rc_key_b = (uint64_t*)B.take(rc * sizeof(uint64_t));
+    r.rc_sort_tmp_bytes = rc_sort_tmp_bytes(rc);
+    r.rc_sort_tmp = B.take(r.rc_sort_tmp_bytes);
+  }
+  return (B.off + kAlign - 1) / kAlign * kAlign;
+}
+
+void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
+  r.lat = *lat;
+  r.vor = *vor;
+  r.prec = lat->precision;
+  r.cells = (long long)lat->nx * lat->ny * lat->nz;
+  r.ncap = vor->n_cap;
+  r.rcap = vor->reconnect ? vor->recon_cap : 0;
+  Geom& g = r.geom;
+  g.nx = lat->nx;
+  g.ny = lat->ny;
+  g.nz = lat->nz;
+  for (int a = 0; a < 3; ++a) g.wall[a] = (lat->wall_axes >> a) & 1u;
+  g.plane_lo = lat->plane_lo ? 1 : 0;
+  g.plane_hi = lat->plane_hi ? 1 : 0;
+  g.cells = r.cells;
+  for (int a = 0; a < 3; ++a) {
+    g.plane_u[a] = lat->plane_u[a];
+    g.body[a] = lat->body_force[a];
+  }
+  g.omega = 1.0 / lat->tau;
+  g.fpref = 1.0 - 1.0 / (2.0 * lat->tau);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    BsAxes& ax = r.bsax;
+    ax.L[a] = (double)n[a];
+    ax.periodic[a] = !g.wall[a];
+    if (ax.periodic[a]) {
+      ax.q[a] = 4294967296.0 / (double)n[a];
+      ax.off[a] = 0.0;
+      ax.invq_d[a] = (double)n[a] / 4294967296.0;
+    } else {
+      int k = 0;
+      while ((double)(n[a] + 2) * std::ldexp(1.0, k + 1) <= 2147483648.0) ++k;
+      ax.q[a] = std::ldexp(1.0, k);
+      ax.off[a] = 1.0;
+      ax.invq_d[a] = std::ldexp(1.0, -k);
+    }
+    ax.invq_f[a] = (float)ax.invq_d[a];
+  }
+  r.bsS = bs_chunks(r.ncap);
+  // spreading bins: lower stencil corner, n (+1 on wall axes) per axis
+  const unsigned long long ext = (unsigned long long)(n[0] + g.wall[0]) * (n[1] + g.wall[1]) * (n[2] + g.wall[2]);
+  r.key_bits = bits_for(ext);  // pad key 2^bits - 1 >= ext
+  if (r.key_bits > 32) r.key_bits = 32;
+  // reconnection bins of edge >= reconnect distance
+  if (vor->reconnect) {
+    const double h0 = vor->reconnect_dist * (1.0 + 1e-9);
+    unsigned long long tot = 1;
+    for (int a = 0; a < 3; ++a) {
+      int nb = (int)std::floor((double)n[a] / h0);
+      if (nb < 1) nb = 1;
+      r.bin_n[a] = nb;
+      r.bin_h[a] = (double)n[a] / nb;
+      tot *= (unsigned long long)nb;
+    }
+    r.bin_bits = bits_for(tot);
+    if (r.bin_bits > 32) r.bin_bits = 32;
+  }
+}
+
+}  // namespace
+
+namespace vlb {
+
+void time_begin(Run& r, int cls, hipEvent_t* b) {
+  *b = nullptr;
+  if (!r.timing) return;
+  hipEvent_t e0;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  hipEventRecord(e0, r.stream);
+  *b = e0;
+  (void)cls;
+}
+
+void time_end(Run& r, int cls, hipEvent_t b) {
+  if (!r.timing || !b) return;
+  hipEvent_t e1;
+  if (hipEventCreate(&e1) != hipSuccess) return;
+  hipEventRecord(e1, r.stream);
+  r.ev_used[cls].emplace_back(b, e1);
+}
+
+}  // namespace vlb
+
+namespace {
+
+void drop_events(Run& r) {
+  for (int c = 0; c < 2; ++c) {
+    for (auto& p : r.ev_used[c]) {
+      hipEventDestroy(p.first);
+      hipEventDestroy(p.second);
+    }
+    r.ev_used[c].clear();
+  }
+}
+
+// wrap as in the kernels: periodic into [0, L), walls mirrored
+double wrap_host(double x, double L, bool periodic) {
+  if (periodic) {
+    if (x < 0.0) x = x + L;
+    if (x >= L) x = x - L;
+    if (x >= L) x = 0.0;
+  } else {
+    const double lo = -0.5, hi = L - 0.5;
+    if (x < lo) x = 2.0 * lo - x;
+    if (x > hi) x = 2.0 * hi - x;
+  }
+  return x;
+}
+
+int read_count(vlb_run* h, int32_t* out) {
+  Run& r = h->r;
+  HIP_OR_FAIL(h, hipMemcpyAsync(out, r.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  return VLB_OK;
+}
+
+int latched(vlb_run* h) {
+  Run& r = h->r;
+  int32_t flags = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(&flags, r.cnt + 7, sizeof(int32_t), hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  if (flags) {
+    HIP_OR_FAIL(h, hipMemsetAsync(r.cnt + 7, 0, sizeof(int32_t), r.stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+    if (flags & kFlagNumeric) return fail(h, VLB_ENUMERIC, "non-finite line velocity");
+    if (flags & kFlagCapacity) return fail(h, VLB_ECAPACITY, "filament points exceeded n_cap; insertion skipped");
+    if (flags & kFlagReconCap) return fail(h, VLB_ECAPACITY, "reconnection candidates exceeded recon_cap; reconnection skipped");
+  }
+  return VLB_OK;
+}
+
+int copy_soa_to_host(vlb_run* h, const double* dev_soa, int n, double* host_aos) {
+  Run& r = h->r;
+  std::vector<double> tmp(3 * (size_t)n);
+  for (int a = 0; a < 3; ++a)
+    HIP_OR_FAIL(h, hipMemcpyAsync(tmp.data() + (size_t)a * n, dev_soa + a * r.ncap,
+                                  n * sizeof(double), hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  for (int j = 0; j < n; ++j)
+    for (int a = 0; a < 3; ++a) host_aos[3 * (size_t)j + a] = tmp[(size_t)a * n + j];
+  return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlb_query_footprint(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, uint64_t* bytes) {
+  std::string msg;
+  const int c = check_desc(lat, vor, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (!bytes) return fail(nullptr, VLB_EINVAL, "bytes is NULL");
+  Run r;
+  init_run(r, lat, vor);
+  *bytes = layout(r, nullptr);
+  return VLB_OK;
+}
+
+int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, void* dev_workspace,
+                       uint64_t ws_bytes, void* hip_stream, vlb_run** out) {
+  std::string msg;
+  const int c = check_desc(lat, vor, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (!out || !dev_workspace) return fail(nullptr, VLB_EINVAL, "out or workspace is NULL");
+  if ((uintptr_t)dev_workspace % kAlign) return fail(nullptr, VLB_EINVAL, "workspace must be 256-byte aligned");
+  vlb_run* h = new (std::nothrow) vlb_run();
+  if (!h) return fail(nullptr, VLB_EINVAL, "out of host memory");
+  Run& r = h->r;
+  init_run(r, lat, vor);
+  const size_t need = layout(r, nullptr);
+  if (ws_bytes < need) {
+    delete h;
+    return fail(nullptr, VLB_ENOSPACE, "workspace smaller than vlb_query_footprint");
+  }
+  r.ws = (char*)dev_workspace;
+  r.ws_bytes = ws_bytes;
+  layout(r, r.ws);
+  r.stream = (hipStream_t)hip_stream;
+  hipGetDevice(&r.device);
+  // populations at rest, no force, no points
+  hipError_t e = hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r.stream);
+  if (e != hipSuccess) {
+    std::string m = std::string("initialising the workspace: ") + hipGetErrorString(e);
+    delete h;
+    return fail(nullptr, VLB_EDEVICE, m);
+  }
+  r.parity = 0;
+  r.has_fields = true;
+  *out = h;
+  return VLB_OK;
+}
+
+int vlb_write_fields(vlb_run* h, const double* rho_dev, const double* u_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!rho_dev || !u_dev) return fail(h, VLB_EINVAL, "rho and u are required");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, lbm_init_eq(r, rho_dev, u_dev));
+  HIP_OR_FAIL(h, hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream));
+  HIP_OR_FAIL(h, hipMemsetAsync(r.cnt + 1, 0, sizeof(int32_t), r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  r.step = 0;
+  r.has_fields = true;
+  return VLB_OK;
+}
+
+int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_t* next) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  Run& r = h->r;
+  if (n_pts < 0 || n_pts > r.ncap) return fail(h, VLB_EINVAL, "n_pts must be in [0, n_cap]");
+  if (n_pts > 0 && (!xyz || !next)) return fail(h, VLB_EINVAL, "xyz and next are required");
+  const int n = (int)n_pts;
+  std::vector<int32_t> prv(n, -1);
+  for (int j = 0; j < n; ++j) {
+    const int k = next[j];
+    if (k < 0 || k >= n) return fail(h, VLB_EINVAL, "next[] out of range");
+    if (prv[k] != -1) return fail(h, VLB_EINVAL, "next[] is not a permutation");
+    prv[k] = j;
+  }
+  std::vector<double> soa(3 * (size_t)n);
+  const int dims[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
+  for (int j = 0; j < n; ++j)
+    for (int a = 0; a < 3; ++a) {
+      const double x = xyz[3 * (size_t)j + a];
+      if (!std::isfinite(x)) return fail(h, VLB_EINVAL, "non-finite position");
+      soa[(size_t)a * n + j] = wrap_host(x, (double)dims[a], !r.geom.wall[a]);
+    }
+  // loops shorter than min_loop_pts are accepted here and removed by the
+  // next topology pass
+  if (n > 0) {
+    for (int a = 0; a < 3; ++a)
+      HIP_OR_FAIL(h, hipMemcpyAsync(r.pos + a * r.ncap, soa.data() + (size_t)a * n, n * sizeof(double),
+                                    hipMemcpyHostToDevice, r.stream));
+    HIP_OR_FAIL(h, hipMemcpyAsync(r.nxt, next, n * sizeof(int32_t), hipMemcpyHostToDevice, r.stream));
+    HIP_OR_FAIL(h, hipMemcpyAsync(r.prv, prv.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, r.stream));
+  }
+  if (n > 0) r.has_points = true;
+  int32_t c0 = n;
+  HIP_OR_FAIL(h, hipMemcpyAsync(r.cnt, &c0, sizeof(int32_t), hipMemcpyHostToDevice, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  return VLB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int one_step(vlb_run* h) {
+  Run& r = h->r;
+  if (r.vor.mass_balance) HIP_OR_FAIL(h, lbm_mass_balance(r));
+  if (!r.has_points) {  // never seeded: the normal fluid alone
+    HIP_OR_FAIL(h, lbm_step(r));
+    r.step += 1;
+    r.last_nodes += r.cells;
+    return VLB_OK;
+  }
+  // filament RK4: stage positions s^n (pos) -> ya -> yb -> ya -> pos
+  double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
+  double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
+  for (int s = 0; s < 4; ++s) {
+    HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
+    HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
+    HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
+    if (s == 0 && r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
+  }
+  HIP_OR_FAIL(h, lbm_step(r));
+  HIP_OR_FAIL(h, topo_update(r));
+  r.step += 1;
+  r.last_nodes += r.cells;
+  return VLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlb_step(vlb_run* h, int64_t n_steps) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (n_steps < 0) return fail(h, VLB_EINVAL, "n_steps must be >= 0");
+  for (int64_t s = 0; s < n_steps; ++s) {
+    const int c = one_step(h);
+    if (c != VLB_OK) return c;
+  }
+  return VLB_OK;
+}
+
+int vlb_sync(vlb_run* h) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
+int vlb_read_fields(vlb_run* h, double* rho_dev, double* u_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  HIP_OR_FAIL(h, lbm_read_fields(h->r, rho_dev, u_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
+int vlb_read_populations(vlb_run* h, double* f_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!f_dev) return fail(h, VLB_EINVAL, "f is NULL");
+  HIP_OR_FAIL(h, lbm_read_pops(h->r, f_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
+int vlb_read_force(vlb_run* h, double* force_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!force_dev) return fail(h, VLB_EINVAL, "force is NULL");
+  HIP_OR_FAIL(h, lbm_read_force(h->r, force_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
+int vlb_read_filaments(vlb_run* h, int64_t cap, double* xyz, int32_t* next, int64_t* n_pts) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!n_pts) return fail(h, VLB_EINVAL, "n_pts is NULL");
+  int32_t n = 0;
+  int c = read_count(h, &n);
+  if (c != VLB_OK) return c;
+  *n_pts = n;
+  if (n > cap) return fail(h, VLB_ENOSPACE, "more points than cap");
+  if (n > 0) {
+    if (xyz) {
+      c = copy_soa_to_host(h, h->r.pos, n, xyz);
+      if (c != VLB_OK) return c;
+    }
+    if (next) {
+      HIP_OR_FAIL(h, hipMemcpyAsync(next, h->r.nxt, n * sizeof(int32_t), hipMemcpyDeviceToHost, h->r.stream));
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+    }
+  }
+  return latched(h);
+}
+
+int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, double* force) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  Run& r = h->r;
+  if (r.vor.mass_balance) HIP_OR_FAIL(h, lbm_mass_balance(r));
+  HIP_OR_FAIL(h, bs_prep(r, r.pos));
+  HIP_OR_FAIL(h, bs_sum(r, r.pos));
+  HIP_OR_FAIL(h, fil_finalize(r, 1, r.pos, r.ya, 1));
+  if (r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
+  int32_t n = 0;
+  int c = read_count(h, &n);
+  if (c != VLB_OK) return c;
+  const double* src[4] = {r.vs1, r.vn1, r.sd1, r.gpt};
+  double* dst[4] = {vs, vn, sdot, force};
+  for (int k = 0; k < 4; ++k)
+    if (dst[k] && n > 0) {
+      c = copy_soa_to_host(h, src[k], n, dst[k]);
+      if (c != VLB_OK) return c;
+    }
+  return latched(h);
+}
+
+int vlb_apply_topology(vlb_run* h, int64_t* stats) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, topo_update(r));
+  int32_t c[8];
+  HIP_OR_FAIL(h, hipMemcpyAsync(c, r.cnt, sizeof(c), hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  if (stats) {
+    stats[0] = c[3];
+    stats[1] = c[2];
+    stats[2] = c[4];
+    stats[3] = c[5];
+  }
+  return latched(h);
+}
+
+int vlb_get_step(vlb_run* h, int64_t* step) {
+  if (!h || !step) return fail(h, VLB_EINVAL, "null argument");
+  *step = h->r.step;
+  return VLB_OK;
+}
+
+int vlb_set_timing(vlb_run* h, int32_t enable) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  drop_events(r);
+  r.timing = enable != 0;
+  r.last_nodes = 0;
+  r.last_pairs = 0;
+  HIP_OR_FAIL(h, hipMemsetAsync(r.cnt + 16, 0, 8 * sizeof(int32_t), r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  return VLB_OK;
+}
+
+int vlb_get_timing(vlb_run* h, int32_t cls, double* total_ms, int64_t* launches) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (cls < 0 || cls > 1 || !total_ms || !launches) return fail(h, VLB_EINVAL, "bad timing query");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  double tot = 0.0;
+  for (auto& p : r.ev_used[cls]) {
+    float ms = 0.f;
+    HIP_OR_FAIL(h, hipEventElapsedTime(&ms, p.first, p.second));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)r.ev_used[cls].size();
+  return VLB_OK;
+}
+
+int vlb_get_work(vlb_run* h, int64_t* node_updates, int64_t* bs_pairs) {
+  if (!h || !node_updates || !bs_pairs) return fail(h, VLB_EINVAL, "null argument");
+  Run& r = h->r;
+  long long acc = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(&acc, r.cnt + 16, sizeof(long long), hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  *node_updates = r.last_nodes;
+  *bs_pairs = acc;
+  return VLB_OK;
+}
+
+int vlb_destroy(vlb_run* h) {
+  if (!h) return VLB_OK;
+  hipStreamSynchronize(h->r.stream);
+  drop_events(h->r);
+  delete h;
+  return VLB_OK;
+}
+
+const char* vlb_last_error(const vlb_run* h) {
+  if (h) return h->r.err.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  return g_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Biot-Savart non-local superfluid velocity (paper Sec. II.A, Eq.
+// Biot-Savart): every target point j sums the exact straight-segment
+// integral over all segments k = (s_k, s_next(k)) except the two that touch
+// it (k = prev(j) and k = j; their divergent contribution is the LIA term).
+//
+// Layout and decomposition:
+//  * per point: 32-bit grid coordinates X (3 x u32, SoA) and the segment
+//    vector d_k = s_next(k) - s_k (nearest image; FP32 or FP64, SoA);
+//  * a 2-D grid: blockIdx.x picks 256 consecutive targets (one per thread),
+//    blockIdx.y one contiguous chunk of sources; the chunk is staged through
+//    LDS in tiles of 256 sources and every thread walks the tile;
+//  * the separation R1 = s_k - r is the wrapped integer difference of the
+//    grid coordinates, converted to floating point: exact nearest periodic
+//    image and a relative (not absolute) rounding error for near pairs;
+//  * each chunk writes one partial sum per target; the finalize kernel adds
+//    the chunks in a fixed order (no atomics, bitwise reproducible).
+#include "vlb_internal.h"
+
+namespace vlb {
+
+namespace {
+
+constexpr int kTile = 256;
+
+// Grid coordinates and segment vectors of the points at positions Y.
+template <class T>
+__global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
+                       int32_t* __restrict__ cnt, long long ncap, BsAxes ax,
+                       uint32_t* __restrict__ X, T* __restrict__ D) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  // work counter: (target, segment) pairs of the sum that follows
+  if (j == 0 && n > 2) *(long long*)(cnt + 16) += (long long)n * (n - 2);
+  if (j >= n) return;
+  const int k = nxt[j];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double y = Y[a * ncap + j];
+    const double s = floor((y + ax.off[a]) * ax.q[a]);
+    X[a * ncap + j] = ax.periodic[a] ? (uint32_t)(long long)s : (uint32_t)(int)(long long)s;
+    double d = Y[a * ncap + k] - y;
+    if (ax.periodic[a]) {
+      if (d > 0.5 * ax.L[a])
+        d = d - ax.L[a];
+      else if (d < -0.5 * ax.L[a])
+        d = d + ax.L[a];
+    }
+    D[a * ncap + j] = (T)d;
+  }
+}
+
+// FP32 pair sum.  Per pair: R1 from the grid difference, R2 = R1 + d_k,
+// v = (R1 x R2) (1/|R1| + 1/|R2|) / (|R1||R2| + R1.R2) written with the
+// inverse norms as (R1 x R2) (i1 + i2) i1 i2 / (1 + (R1.R2) i1 i2).
+template <bool kCheck>
+__device__ inline void bs_tile_f32(const uint32_t* sx, const uint32_t* sy, const uint32_t* sz,
+                                   const float* dx, const float* dy, const float* dz, int cnt,
+                                   int t0, uint32_t xt, uint32_t yt, uint32_t zt, float iqx,
+                                   float iqy, float iqz, int jj, int pj, float& ax, float& ay,
+                                   float& az) {
+#pragma unroll 4
+  for (int s = 0; s < cnt; ++s) {
+    const float r1x = (float)(int)(sx[s] - xt) * iqx;
+    const float r1y = (float)(int)(sy[s] - yt) * iqy;
+    const float r1z = (float)(int)(sz[s] - zt) * iqz;
+    const float r2x = r1x + dx[s];
+    const float r2y = r1y + dy[s];
+    const float r2z = r1z + dz[s];
+    const float n1 = r1x * r1x + r1y * r1y + r1z * r1z;
+    const float n2 = r2x * r2x + r2y * r2y + r2z * r2z;
+    const float i1 = __builtin_amdgcn_rsqf(n1);
+    const float i2 = __builtin_amdgcn_rsqf(n2);
+    const float crx = r1y * r2z - r1z * r2y;
+    const float cry = r1z * r2x - r1x * r2z;
+    const float crz = r1x * r2y - r1y * r2x;
+    const float dt = r1x * r2x + r1y * r2y + r1z * r2z;
+    const float a = i1 * i2;
+    const float den = fmaf(dt, a, 1.0f);
+    float f = (i1 + i2) * a * __builtin_amdgcn_rcpf(den);
+    if (kCheck) {
+      const int k = t0 + s;
+      f = (k == jj || k == pj) ? 0.0f : f;
+    }
+    ax = fmaf(f, crx, ax);
+    ay = fmaf(f, cry, ay);
+    az = fmaf(f, crz, az);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
+                                               const float* __restrict__ D,
+                                               const int32_t* __restrict__ prv,
+                                               const int32_t* __restrict__ cntp, long long ncap,
+                                               int S, float iqx, float iqy, float iqz,
+                                               float* __restrict__ P) {
+  const int n = cntp[0];
+  const int j0 = blockIdx.x * 256;
+  if (j0 >= n) return;
+  const int j = j0 + threadIdx.x;
+  const bool valid = j < n;
+  const int per = (((n + S - 1) / S) + kTile - 1) / kTile * kTile;
+  const int kb = blockIdx.y * per;
+  const int ke = min(n, kb + per);
+  const uint32_t xt = valid ? X[j] : 0u;
+  const uint32_t yt = valid ? X[ncap + j] : 0u;
+  const uint32_t zt = valid ? X[2 * ncap + j] : 0u;
+  const int pj = valid ? prv[j] : -1;
+  const int jj = valid ? j : -1;
+  __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
+  __shared__ float dx[kTile], dy[kTile], dz[kTile];
+  float ax = 0.f, ay = 0.f, az = 0.f;
+  for (int t0 = kb; t0 < ke; t0 += kTile) {
+    const int k = t0 + threadIdx.x;
+    if (k < ke) {
+      sx[threadIdx.x] = X[k];
+      sy[threadIdx.x] = X[ncap + k];
+      sz[threadIdx.x] = X[2 * ncap + k];
+      dx[threadIdx.x] = D[k];
+      dy[threadIdx.x] = D[ncap + k];
+      dz[threadIdx.x] = D[2 * ncap + k];
+    }
+    __syncthreads();
+    const int cnt = min(kTile, ke - t0);
+    const bool hit = valid && ((jj >= t0 && jj < t0 + cnt) || (pj >= t0 && pj < t0 + cnt));
+    if (__any(hit))
+      bs_tile_f32<true>(sx, sy, sz, dx, dy, dz, cnt, t0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+    else
+      bs_tile_f32<false>(sx, sy, sz, dx, dy, dz, cnt, t0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+    __syncthreads();
+  }
+  if (valid) {
+    float* out = P + (long long)blockIdx.y * 3 * ncap;
+    out[j] = ax;
+    out[ncap + j] = ay;
+    out[2 * ncap + j] = az;
+  }
+}
+
+// FP64 pair sum (plain path): FP64 separations at the image chosen on the
+// grid, the closed form exactly as written, IEEE sqrt and division.
+__global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
+                                               const double* __restrict__ D,
+                                               const double* __restrict__ Y,
+                                               const int32_t* __restrict__ prv,
+                                               const int32_t* __restrict__ cntp, long long ncap,
+                                               int S, double Lx, double Ly, double Lz,
+                                               double* __restrict__ P) {
+  const int n = cntp[0];
+  const int j0 = blockIdx.x * 256;
+  if (j0 >= n) return;
+  const int j = j0 + threadIdx.x;
+  const bool valid = j < n;
+  const int per = (((n + S - 1) / S) + kTile - 1) / kTile * kTile;
+  const int kb = blockIdx.y * per;
+  const int ke = min(n, kb + per);
+  const uint32_t xt = valid ? X[j] : 0u;
+  const uint32_t yt = valid ? X[ncap + j] : 0u;
+  const uint32_t zt = valid ? X[2 * ncap + j] : 0u;
+  const double px = valid ? Y[j] : 0.0;
+  const double py = valid ? Y[ncap + j] : 0.0;
+  const double pz = valid ? Y[2 * ncap + j] : 0.0;
+  const int pj = valid ? prv[j] : -1;
+  __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
+  __shared__ double qx[kTile], qy[kTile], qz[kTile];
+  __shared__ double dx[kTile], dy[kTile], dz[kTile];
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  for (int t0 = kb; t0 < ke; t0 += kTile) {
+    const int k = t0 + threadIdx.x;
+    if (k < ke) {
+      sx[threadIdx.x] = X[k];
+      sy[threadIdx.x] = X[ncap + k];
+      sz[threadIdx.x] = X[2 * ncap + k];
+      qx[threadIdx.x] = Y[k];
+      qy[threadIdx.x] = Y[ncap + k];
+      qz[threadIdx.x] = Y[2 * ncap + k];
+      dx[threadIdx.x] = D[k];
+      dy[threadIdx.x] = D[ncap + k];
+      dz[threadIdx.x] = D[2 * ncap + k];
+    }
+    __syncthreads();
+    const int cnt = min(kTile, ke - t0);
+    if (valid) {
+      for (int s = 0; s < cnt; ++s) {
+        const int kk = t0 + s;
+        if (kk == j || kk == pj) continue;
+        // image shift from the grid: wrapped minus raw difference / 2^32
+        const long long hx = ((long long)(int)(sx[s] - xt) - ((long long)sx[s] - (long long)xt)) >> 32;
+        const long long hy = ((long long)(int)(sy[s] - yt) - ((long long)sy[s] - (long long)yt)) >> 32;
+        const long long hz = ((long long)(int)(sz[s] - zt) - ((long long)sz[s] - (long long)zt)) >> 32;
+        const double r1x = (qx[s] - px) + (double)hx * Lx;
+        const double r1y = (qy[s] - py) + (double)hy * Ly;
+        const double r1z = (qz[s] - pz) + (double)hz * Lz;
+        const double r2x = r1x + dx[s];
+        const double r2y = r1y + dy[s];
+        const double r2z = r1z + dz[s];
+        const double n1 = sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
+        const double n2 = sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
+        const double crx = r1y * r2z - r1z * r2y;
+        const double cry = r1z * r2x - r1x * r2z;
+        const double crz = r1x * r2y - r1y * r2x;
+        const double dt = r1x * r2x + r1y * r2y + r1z * r2z;
+        const double fac = (n1 + n2) / (n1 * n2 * (n1 * n2 + dt));
+        ax += crx * fac;
+        ay += cry * fac;
+        az += crz * fac;
+      }
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    double* out = P + (long long)blockIdx.y * 3 * ncap;
+    out[j] = ax;
+    out[ncap + j] = ay;
+    out[2 * ncap + j] = az;
+  }
+}
+
+}  // namespace
+
+int bs_chunks(long long ncap) {
+  const long long tb = (ncap + 255) / 256;
+  long long S = 4096 / (tb > 0 ? tb : 1);
+  const long long maxS = ncap / 512;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  if (S > 128) S = 128;
+  return (int)S;
+}
+
+hipError_t bs_prep(Run& r, const double* Y) {
+  const int nb = (int)((r.ncap + 255) / 256);
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_prep<double>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
+                       r.bsax, r.bsX, (double*)r.bsD);
+  else
+    hipLaunchKernelGGL(k_prep<float>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
+                       r.bsax, r.bsX, (float*)r.bsD);
+  return hipGetLastError();
+}
+
+hipError_t bs_sum(Run& r, const double* Y) {
+  const int tb = (int)((r.ncap + 255) / 256);
+  dim3 grid(tb, r.bsS);
+  hipEvent_t b = nullptr;
+  time_begin(r, 0, &b);
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD, Y,
+                       r.prv, r.cnt, r.ncap, r.bsS, r.bsax.L[0], r.bsax.L[1], r.bsax.L[2],
+                       (double*)r.bsP);
+  else
+    hipLaunchKernelGGL(k_bs_f32, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
+                       r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
+                       r.bsax.invq_f[2], (float*)r.bsP);
+  time_end(r, 0, b);
+  return hipGetLastError();
+}
+
+}  // namespace vlb

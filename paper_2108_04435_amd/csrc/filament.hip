@@ -1,0 +1,489 @@
+// Per-point filament kernels (paper Sec. II.A and II.B):
+//  * finalize: sum of the Biot-Savart partials, local geometry and LIA term,
+//    mass-balance superflow, two-point-delta interpolation of the normal
+//    fluid, Schwarz line velocity, mutual-friction force and the RK4
+//    bookkeeping of one stage;
+//  * spreading of the point forces onto the lattice, without atomics:
+//    points are binned by the cell of their stencil's lower corner with a
+//    stable radix sort; each touched node is then owned by exactly one bin
+//    and gathers the contributions of the (at most 8) bins around it in a
+//    fixed order.
+#include "vlb_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+namespace vlb {
+
+namespace {
+
+struct FinArgs {
+  const void* pops;
+  int prec;
+  int parity;
+  Geom g;
+  const double* Y;
+  double* Ynext;
+  double* pos;
+  double* ksum;
+  const int32_t* nxt;
+  const int32_t* prv;
+  int32_t* cnt;
+  const void* P;
+  int S;
+  long long ncap;
+  const double* Vs;
+  int mass_balance;
+  int stage;
+  int eval_only;
+  int coupling;
+  double kappa;
+  double bs_scale;    // kappa / (4 pi)
+  double ea;          // e^C a
+  double alpha, alpha_p;
+  double rs_rn;
+  double vs_app[3];
+  double* vs1;
+  double* vn1;
+  double* sd1;
+  double* gpt;
+};
+
+// Nearest-image separation on the filament axes (wall axes: plain).
+__device__ inline double mimg(double d, double L, int periodic) {
+  if (periodic) {
+    if (d > 0.5 * L)
+      d = d - L;
+    else if (d < -0.5 * L)
+      d = d + L;
+  }
+  return d;
+}
+
+// Periodic axes wrap into [0, L); wall axes mirror a point that crossed
+// the wall plane at -1/2 or n - 1/2.
+__device__ inline double wrap_coord(double x, double L, int periodic) {
+  if (periodic) {
+    if (x < 0.0) x = x + L;
+    if (x >= L) x = x - L;
+    if (x >= L) x = 0.0;
+  } else {
+    const double lo = -0.5, hi = L - 0.5;
+    if (x < lo) x = 2.0 * lo - x;
+    if (x > hi) x = 2.0 * hi - x;
+  }
+  return x;
+}
+
+// Bare normal-fluid velocity at a point: delta_2pt weights on the 8
+// surrounding nodes; nodes beyond a wall carry zero velocity.
+template <class S>
+__device__ void interp_vn(const S* M, const Geom& g, int parity, double px, double py, double pz,
+                          double v[3]) {
+  using T = typename Store<S>::T;
+  const double b[3] = {floor(px), floor(py), floor(pz)};
+  const double fr[3] = {px - b[0], py - b[1], pz - b[2]};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  v[0] = v[1] = v[2] = 0.0;
+  for (int o = 0; o < 8; ++o) {
+    const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    int node[3];
+    double w = 1.0;
+    bool ghost = false;
+    for (int a = 0; a < 3; ++a) {
+      int c = (int)b[a] + off[a];
+      w *= off[a] ? fr[a] : 1.0 - fr[a];
+      if (c < 0 || c >= n[a]) {
+        if (g.wall[a])
+          ghost = true;
+        else
+          c = c < 0 ? c + n[a] : c - n[a];
+      }
+      node[a] = c;
+    }
+    if (ghost) continue;
+    double ux, uy, uz;
+    if (is_plane(g, node[2])) {
+      ux = g.plane_u[0];
+      uy = g.plane_u[1];
+      uz = g.plane_u[2];
+    } else {
+      T d[19];
+      load_node<S>(M, g, parity, node[0], node[1], node[2], d);
+      T drho, jx, jy, jz;
+      moments<T>(d, drho, jx, jy, jz);
+      const double rho = 1.0 + (double)drho;
+      ux = (double)jx / rho;
+      uy = (double)jy / rho;
+      uz = (double)jz / rho;
+    }
+    v[0] += w * ux;
+    v[1] += w * uy;
+    v[2] += w * uz;
+  }
+}
+
+template <class S, class PT>
+__global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = A.cnt[0];
+  if (j >= n) return;
+  const long long nc = A.ncap;
+  const Geom& g = A.g;
+  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+  const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
+
+  // non-local Biot-Savart: chunk partials added in a fixed order
+  double vs[3] = {0.0, 0.0, 0.0};
+  const PT* P = (const PT*)A.P;
+  for (int s = 0; s < A.S; ++s)
+    for (int a = 0; a < 3; ++a) vs[a] += (double)P[((long long)s * 3 + a) * nc + j];
+  for (int a = 0; a < 3; ++a) vs[a] *= A.bs_scale;
+
+  // local geometry (three-point derivatives on a non-uniform arc length)
+  const int jn = A.nxt[j], jp = A.prv[j];
+  double p[3], dp[3], dm[3];
+  for (int a = 0; a < 3; ++a) {
+    p[a] = A.Y[a * nc + j];
+    dp[a] = mimg(A.Y[a * nc + jn] - p[a], L[a], per[a]);
+    dm[a] = mimg(p[a] - A.Y[a * nc + jp], L[a], per[a]);
+  }
+  const double lp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
+  const double lm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
+  const double den = lp * lm * (lp + lm);
+  double sp[3], spp[3];
+  for (int a = 0; a < 3; ++a) {
+    sp[a] = (lm * lm * dp[a] + lp * lp * dm[a]) / den;
+    spp[a] = 2.0 * (lm * dp[a] - lp * dm[a]) / den;
+  }
+  const double sn = sqrt(sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]);
+  for (int a = 0; a < 3; ++a) sp[a] /= sn;
+  // LIA: beta s' x s'', beta = kappa/(4 pi) ln(2 sqrt(l+ l-) / (e^C a))
+  const double beta = A.bs_scale * log(2.0 * sqrt(lp * lm) / A.ea);
+  vs[0] += beta * (sp[1] * spp[2] - sp[2] * spp[1]);
+  vs[1] += beta * (sp[2] * spp[0] - sp[0] * spp[2]);
+  vs[2] += beta * (sp[0] * spp[1] - sp[1] * spp[0]);
+  for (int a = 0; a < 3; ++a) vs[a] += A.vs_app[a];
+  if (A.mass_balance) {
+    const double fz = floor(p[2]);
+    const double t = p[2] - fz;
+    int i0 = (int)fz, i1 = i0 + 1;
+    i0 = ((i0 % g.nz) + g.nz) % g.nz;
+    i1 = ((i1 % g.nz) + g.nz) % g.nz;
+    vs[2] += (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];
+  }
+
+  // normal-fluid velocity at the point
+  double vn[3];
+  if (A.prec == VLB_F64)
+    interp_vn<double>((const double*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
+  else if (A.prec == VLB_F32)
+    interp_vn<float>((const float*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
+  else
+    interp_vn<__half>((const __half*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
+
+  // Schwarz equation of motion (Sec. II.A, Eq. E of M)
+  const double w[3] = {vn[0] - vs[0], vn[1] - vs[1], vn[2] - vs[2]};
+  const double sxw[3] = {sp[1] * w[2] - sp[2] * w[1], sp[2] * w[0] - sp[0] * w[2],
+                         sp[0] * w[1] - sp[1] * w[0]};
+  const double ssw[3] = {sp[1] * sxw[2] - sp[2] * sxw[1], sp[2] * sxw[0] - sp[0] * sxw[2],
+                         sp[0] * sxw[1] - sp[1] * sxw[0]};
+  double sd[3];
+  for (int a = 0; a < 3; ++a) sd[a] = vs[a] + A.alpha * sxw[a] - A.alpha_p * ssw[a];
+  if (!(isfinite(sd[0]) && isfinite(sd[1]) && isfinite(sd[2])))
+    atomicOr(&A.cnt[7], kFlagNumeric);
+
+  if (A.stage == 1) {
+    for (int a = 0; a < 3; ++a) {
+      A.vs1[a * nc + j] = vs[a];
+      A.vn1[a * nc + j] = vn[a];
+      A.sd1[a * nc + j] = sd[a];
+    }
+    // reaction on the normal fluid (Magnus balance), per point, with the
+    // line length (l+ + l-)/2 carried by the point
+    const double r[3] = {sd[0] - vs[0], sd[1] - vs[1], sd[2] - vs[2]};
+    const double sxr[3] = {sp[1] * r[2] - sp[2] * r[1], sp[2] * r[0] - sp[0] * r[2],
+                           sp[0] * r[1] - sp[1] * r[0]};
+    const double dxi = 0.5 * (lp + lm);
+    for (int a = 0; a < 3; ++a) A.gpt[a * nc + j] = A.coupling ? A.rs_rn * A.kappa * sxr[a] * dxi : 0.0;
+  }
+  if (A.eval_only) return;
+
+  // RK4: ksum = k1 + 2 k2 + 2 k3 + k4, stage positions s^n + c k
+  for (int a = 0; a < 3; ++a) {
+    const double s0 = A.pos[a * nc + j];
+    double ks;
+    double y;
+    switch (A.stage) {
+      case 1:
+        ks = sd[a];
+        y = s0 + 0.5 * sd[a];
+        break;
+      case 2:
+        ks = A.ksum[a * nc + j] + 2.0 * sd[a];
+        y = s0 + 0.5 * sd[a];
+        break;
+      case 3:
+        ks = A.ksum[a * nc + j] + 2.0 * sd[a];
+        y = s0 + sd[a];
+        break;
+      default:
+        ks = A.ksum[a * nc + j] + sd[a];
+        y = s0 + ks / 6.0;
+        break;
+    }
+    A.ksum[a * nc + j] = ks;
+    A.Ynext[a * nc + j] = wrap_coord(y, L[a], per[a]);
+  }
+}
+
+// ----------------------------------------------------------- spreading
+
+struct SpreadGeom {
+  int n[3];
+  int wall[3];
+  int ext[3];  // bins per axis: n (periodic) or n + 1 (wall: lower corner -1..n-1)
+};
+
+__device__ inline uint32_t base_key(const SpreadGeom& sg, const double p[3], int b[3]) {
+  for (int a = 0; a < 3; ++a) {
+    int c = (int)floor(p[a]);
+    if (sg.wall[a]) {
+      c += 1;  // lower corner -1 .. n-1 -> 0 .. n
+    } else {
+      c = c < 0 ? c + sg.n[a] : (c >= sg.n[a] ? c - sg.n[a] : c);
+    }
+    b[a] = c;
+  }
+  return (uint32_t)(((long long)b[2] * sg.ext[1] + b[1]) * sg.ext[0] + b[0]);
+}
+
+__global__ void k_spread_keys(const double* __restrict__ pos, const int32_t* __restrict__ cnt,
+                              long long ncap, SpreadGeom sg, uint32_t pad, uint32_t* __restrict__ keys,
+                              int32_t* __restrict__ vals) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncap) return;
+  const int n = cnt[0];
+  uint32_t k = pad;
+  if (j < n) {
+    const double p[3] = {pos[j], pos[ncap + j], pos[2 * ncap + j]};
+    int b[3];
+    k = base_key(sg, p, b);
+  }
+  keys[j] = k;
+  vals[j] = j;
+}
+
+// first index in [0, n) with keys[idx] >= k
+__device__ inline int lower_bound_u32(const uint32_t* keys, int n, uint32_t k) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <class FT>
+__global__ void k_spread_clear(FT* __restrict__ F, long long cells, const int32_t* __restrict__ touched,
+                               const int32_t* __restrict__ cnt) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cnt[1]) return;
+  const int node = touched[s];
+  if (node < 0) return;
+  F[node] = FT(0);
+  F[cells + node] = FT(0);
+  F[2 * cells + node] = FT(0);
+}
+
+template <class FT>
+__global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
+                                const double* __restrict__ pos, const double* __restrict__ gpt,
+                                int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
+                                long long cells, FT* __restrict__ F, int32_t* __restrict__ touched) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  if (r == 0) cnt[1] = 8 * n;
+  if (r >= n) return;
+  const uint32_t me = skey[r];
+  if (r > 0 && skey[r - 1] == me) {
+    for (int o = 0; o < 8; ++o) touched[8 * r + o] = -1;
+    return;
+  }
+  // decode my bin (lower corner of the stencil, bin coordinates)
+  int b[3];
+  b[0] = (int)(me % (uint32_t)sg.ext[0]);
+  b[1] = (int)((me / (uint32_t)sg.ext[0]) % (uint32_t)sg.ext[1]);
+  b[2] = (int)(me / ((uint32_t)sg.ext[0] * (uint32_t)sg.ext[1]));
+  for (int o = 0; o < 8; ++o) {
+    const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    int e[3];    // node in bin coordinates
+    int lat[3];  // node in lattice coordinates
+    bool ghost = false;
+    for (int a = 0; a < 3; ++a) {
+      e[a] = b[a] + off[a];
+      if (sg.wall[a]) {
+        lat[a] = e[a] - 1;
+        if (lat[a] < 0 || lat[a] >= sg.n[a]) ghost = true;
+      } else {
+        if (e[a] >= sg.n[a]) e[a] -= sg.n[a];
+        lat[a] = e[a];
+      }
+    }
+    if (ghost) {
+      touched[8 * r + o] = -1;
+      continue;
+    }
+    // the bins whose stencil contains this node: e - o' for o' in {0,1}^3
+    int lo[8], hi[8];
+    bool owner = true;
+    for (int q = 0; q < 8 && owner; ++q) {
+      const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+      int c[3];
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        c[a] = e[a] - oq[a];
+        if (sg.wall[a]) {
+          if (c[a] < 0) ok = false;
+        } else if (c[a] < 0) {
+          c[a] += sg.n[a];
+        }
+      }
+      lo[q] = hi[q] = 0;
+      if (!ok) continue;
+      const uint32_t k = (uint32_t)(((long long)c[2] * sg.ext[1] + c[1]) * sg.ext[0] + c[0]);
+      const int l = lower_bound_u32(skey, n, k);
+      if (l < n && skey[l] == k) {
+        if (k < me) owner = false;
+        lo[q] = l;
+        hi[q] = lower_bound_u32(skey, n, k + 1);
+      }
+    }
+    if (!owner) {
+      touched[8 * r + o] = -1;
+      continue;
+    }
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 8; ++q) {
+      const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+      for (int t = lo[q]; t < hi[q]; ++t) {
+        const int pidx = sval[t];
+        double w = 1.0;
+        for (int a = 0; a < 3; ++a) {
+          const double x = pos[a * ncap + pidx];
+          const double fr = x - floor(x);
+          w *= oq[a] ? fr : 1.0 - fr;
+        }
+        for (int a = 0; a < 3; ++a) f[a] += w * gpt[a * ncap + pidx];
+      }
+    }
+    const long long node = ((long long)lat[2] * sg.n[1] + lat[1]) * sg.n[0] + lat[0];
+    F[node] = (FT)f[0];
+    F[cells + node] = (FT)f[1];
+    F[2 * cells + node] = (FT)f[2];
+    touched[8 * r + o] = (int32_t)node;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline int nblocks(long long n, int b) { return (int)((n + b - 1) / b); }
+
+SpreadGeom spread_geom(const Run& r) {
+  SpreadGeom sg;
+  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
+  for (int a = 0; a < 3; ++a) {
+    sg.n[a] = n[a];
+    sg.wall[a] = r.geom.wall[a];
+    sg.ext[a] = n[a] + (r.geom.wall[a] ? 1 : 0);
+  }
+  return sg;
+}
+
+}  // namespace
+
+size_t sort_tmp_bytes(long long n) {
+  size_t bytes = 0;
+  rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                            (int32_t*)nullptr, (int32_t*)nullptr, (unsigned int)n, 0u, 32u,
+                            (hipStream_t)0);
+  return bytes;
+}
+
+hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only) {
+  FinArgs A;
+  A.pops = r.pops;
+  A.prec = r.prec;
+  A.parity = r.parity;
+  A.g = r.geom;
+  A.Y = Y;
+  A.Ynext = Ynext;
+  A.pos = r.pos;
+  A.ksum = r.ksum;
+  A.nxt = r.nxt;
+  A.prv = r.prv;
+  A.cnt = r.cnt;
+  A.P = r.bsP;
+  A.S = r.bsS;
+  A.ncap = r.ncap;
+  A.Vs = r.Vs;
+  A.mass_balance = r.vor.mass_balance;
+  A.stage = stage;
+  A.eval_only = eval_only;
+  A.coupling = r.vor.coupling;
+  A.kappa = r.vor.kappa;
+  A.bs_scale = r.vor.kappa / (4.0 * M_PI);
+  A.ea = exp(r.vor.core_c) * r.vor.core_a;
+  A.alpha = r.vor.alpha;
+  A.alpha_p = r.vor.alpha_p;
+  A.rs_rn = r.vor.rho_s_over_rho_n;
+  for (int a = 0; a < 3; ++a) A.vs_app[a] = r.vor.vs_applied[a];
+  A.vs1 = r.vs1;
+  A.vn1 = r.vn1;
+  A.sd1 = r.sd1;
+  A.gpt = r.gpt;
+  const int nb = nblocks(r.ncap, 256);
+  switch (r.prec) {
+    case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;
+    case VLB_F32: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
+    default: hipLaunchKernelGGL((k_finalize<__half, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t fil_clear_force(Run& r) {
+  const int nb = nblocks(8 * r.ncap, 256);
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_spread_clear<double>, dim3(nb), dim3(256), 0, r.stream, (double*)r.force, r.cells, r.touched, r.cnt);
+  else
+    hipLaunchKernelGGL(k_spread_clear<float>, dim3(nb), dim3(256), 0, r.stream, (float*)r.force, r.cells, r.touched, r.cnt);
+  return hipGetLastError();
+}
+
+hipError_t fil_spread(Run& r) {
+  hipError_t e = fil_clear_force(r);
+  if (e != hipSuccess) return e;
+  const SpreadGeom sg = spread_geom(r);
+  const uint32_t pad = (r.key_bits >= 32) ? 0xFFFFFFFFu : ((1u << r.key_bits) - 1u);
+  const int nb = nblocks(r.ncap, 256);
+  hipLaunchKernelGGL(k_spread_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, sg,
+                     pad, r.keys_a, r.vals_a);
+  size_t bytes = r.sort_tmp_bytes;
+  e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
+                                (unsigned int)r.ncap, 0u, (unsigned int)r.key_bits, r.stream);
+  if (e != hipSuccess) return e;
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
+                       r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
+  else
+    hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
+                       r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
+  return hipGetLastError();
+}
+
+}  // namespace vlb

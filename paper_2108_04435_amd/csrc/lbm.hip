@@ -1,0 +1,319 @@
+// Normal fluid on the D3Q19 lattice (paper Sec. II.B): forced BGK
+// collision and streaming in one pass, AA access pattern in a single
+// structure-of-arrays population array.
+//
+// Memory holds deviations d_i = f_i - w_i.  An even pass reads the
+// populations of a node from its own slots and writes the post-collision
+// values into the opposite slots of the same node; an odd pass reads
+// population i of x from slot opp(i) of x - c_i and writes the new
+// population i to slot i of x + c_i, which restores the natural layout.  A
+// neighbour beyond a wall is replaced by the node itself with the reflected
+// slot (halfway bounce-back).  Each node's 19 slots are read and written by
+// that node's thread only, so the update is in place and race-free.
+#include "vlb_internal.h"
+
+namespace vlb {
+
+namespace {
+
+// Post-collision deviation (Sec. II.B, Eqs. LBM 1-3 collapsed):
+// f''' = f - (f - f^eq)/tau + F, with f^eq and the Cheng-Li/Guo term F built
+// from rho and u = (sum c f + g/2)/rho.
+template <class S, int P>
+__global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
+                                                        const typename Store<S>::T* __restrict__ F,
+                                                        Geom g, int nbx, int nby, int nblk) {
+  using T = typename Store<S>::T;
+  const int t = xcd_remap(blockIdx.x, nblk);
+  const int bxi = t % nbx;
+  const int rr = t / nbx;
+  const int byi = rr % nby;
+  const int z = rr / nby;
+  const int x = bxi * blockDim.x + threadIdx.x;
+  const int y = byi * blockDim.y + threadIdx.y;
+  if (x >= g.nx || y >= g.ny) return;
+  const long long c = ((long long)z * g.ny + y) * g.nx + x;
+
+  T d[19];
+  load_node<S>(M, g, P, x, y, z, d);
+  if (is_plane(g, z)) {
+    const T ux = T(g.plane_u[0]), uy = T(g.plane_u[1]), uz = T(g.plane_u[2]);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = eq_dev<T>(i, T(0), T(1), ux, uy, uz);
+  }
+  T gx = T(g.body[0]), gy = T(g.body[1]), gz = T(g.body[2]);
+  if (F) {
+    gx += F[c];
+    gy += F[g.cells + c];
+    gz += F[2 * g.cells + c];
+  }
+  T drho, jx, jy, jz;
+  moments<T>(d, drho, jx, jy, jz);
+  const T rho = T(1) + drho;
+  const T inv = T(1) / rho;
+  const T ux = (jx + T(0.5) * gx) * inv;
+  const T uy = (jy + T(0.5) * gy) * inv;
+  const T uz = (jz + T(0.5) * gz) * inv;
+  const T om = T(g.omega);
+  const T pref = T(g.fpref);
+  const T ug = ux * gx + uy * gy + uz * gz;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
+    const T cg = T(cx(i)) * gx + T(cy(i)) * gy + T(cz(i)) * gz;
+    const T deq = eq_dev<T>(i, drho, rho, ux, uy, uz);
+    const T Fi = pref * T(wq(i)) * (T(3) * (cg - ug) + T(9) * cu * cg);
+    const T dn = d[i] - om * (d[i] - deq) + Fi;
+    if (P == 0) {
+      Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
+    } else {
+      const long long s = neighbour(g, x, y, z, cx(i), cy(i), cz(i));
+      if (s >= 0)
+        Store<S>::st(M + (long long)i * g.cells + s, dn);
+      else
+        Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
+    }
+  }
+}
+
+template <class S>
+__global__ void k_init_eq(S* __restrict__ M, const double* __restrict__ rho,
+                          const double* __restrict__ u, Geom g) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  const double r = rho[c];
+  const double ux = u[c], uy = u[g.cells + c], uz = u[2 * g.cells + c];
+  const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+    const double feq = wq(i) * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    Store<S>::st(M + (long long)i * g.cells + c, (typename Store<S>::T)(feq - wq(i)));
+  }
+}
+
+// Effective density and bare velocity of node c (velocity planes applied).
+template <class S>
+__device__ inline void node_rho_u(const S* M, const Geom& g, int parity, int x, int y, int z,
+                                  double& rho, double& ux, double& uy, double& uz) {
+  using T = typename Store<S>::T;
+  if (is_plane(g, z)) {
+    rho = 1.0;
+    ux = g.plane_u[0];
+    uy = g.plane_u[1];
+    uz = g.plane_u[2];
+    return;
+  }
+  T d[19];
+  load_node<S>(M, g, parity, x, y, z, d);
+  T drho, jx, jy, jz;
+  moments<T>(d, drho, jx, jy, jz);
+  rho = 1.0 + (double)drho;
+  ux = (double)jx / rho;
+  uy = (double)jy / rho;
+  uz = (double)jz / rho;
+}
+
+template <class S>
+__global__ void k_read_fields(const S* __restrict__ M, Geom g, int parity, double* rho_out,
+                              double* u_out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  double rho, ux, uy, uz;
+  node_rho_u<S>(M, g, parity, x, y, z, rho, ux, uy, uz);
+  if (rho_out) rho_out[c] = rho;
+  if (u_out) {
+    u_out[c] = ux;
+    u_out[g.cells + c] = uy;
+    u_out[2 * g.cells + c] = uz;
+  }
+}
+
+template <class S>
+__global__ void k_read_pops(const S* __restrict__ M, Geom g, int parity, double* f) {
+  using T = typename Store<S>::T;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  T d[19];
+  load_node<S>(M, g, parity, x, y, z, d);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) f[(long long)i * g.cells + c] = wq(i) + (double)d[i];
+}
+
+template <class T>
+__global__ void k_read_force(const T* __restrict__ F, long long n, double* out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) out[c] = F ? (double)F[c] : 0.0;
+}
+
+// Mass-balance superflow (Sec. III.C, Eq. mass cons): partial sums of the
+// bare u_z over parts of each z slice, then one value per slice.
+template <class S>
+__global__ __launch_bounds__(256) void k_slice_partial(const S* __restrict__ M, Geom g, int parity,
+                                                       int nparts, double* __restrict__ part) {
+  const int z = blockIdx.x / nparts;
+  const int p = blockIdx.x % nparts;
+  const long long area = (long long)g.nx * g.ny;
+  const long long per = (area + nparts - 1) / nparts;
+  const long long k0 = p * per;
+  const long long k1 = min(area, k0 + per);
+  double acc = 0.0;
+  for (long long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const int x = (int)(k % g.nx);
+    const int y = (int)(k / g.nx);
+    double rho, ux, uy, uz;
+    node_rho_u<S>(M, g, parity, x, y, z, rho, ux, uy, uz);
+    acc += uz;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_slice_final(const double* __restrict__ part, int nz, int nparts, double scale,
+                              double* __restrict__ Vs) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nz) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += part[z * nparts + p];
+  Vs[z] = scale * s;
+}
+
+inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
+
+template <class S>
+hipError_t launch_collide(Run& r) {
+  using T = typename Store<S>::T;
+  const Geom& g = r.geom;
+  const int bx = g.nx < 64 ? g.nx : 64;
+  const int by = 256 / bx;
+  const int nbx = (g.nx + bx - 1) / bx;
+  const int nby = (g.ny + by - 1) / by;
+  const int nblk = nbx * nby * g.nz;
+  const T* F = (r.vor.coupling && r.ncap > 0) ? (const T*)r.force : nullptr;
+  dim3 blk(bx, by);
+  if (r.parity == 0)
+    hipLaunchKernelGGL((k_collide_stream<S, 0>), dim3(nblk), blk, 0, r.stream, (S*)r.pops, F, g,
+                       nbx, nby, nblk);
+  else
+    hipLaunchKernelGGL((k_collide_stream<S, 1>), dim3(nblk), blk, 0, r.stream, (S*)r.pops, F, g,
+                       nbx, nby, nblk);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t lbm_step(Run& r) {
+  hipEvent_t b = nullptr;
+  time_begin(r, 1, &b);
+  hipError_t e;
+  switch (r.prec) {
+    case VLB_F64: e = launch_collide<double>(r); break;
+    case VLB_F32: e = launch_collide<float>(r); break;
+    default: e = launch_collide<__half>(r); break;
+  }
+  time_end(r, 1, b);
+  r.parity ^= 1;
+  return e;
+}
+
+hipError_t lbm_init_eq(Run& r, const double* rho, const double* u) {
+  const int nb = blocks_for(r.cells, 256);
+  switch (r.prec) {
+    case VLB_F64:
+      hipLaunchKernelGGL(k_init_eq<double>, dim3(nb), dim3(256), 0, r.stream, (double*)r.pops, rho, u, r.geom);
+      break;
+    case VLB_F32:
+      hipLaunchKernelGGL(k_init_eq<float>, dim3(nb), dim3(256), 0, r.stream, (float*)r.pops, rho, u, r.geom);
+      break;
+    default:
+      hipLaunchKernelGGL(k_init_eq<__half>, dim3(nb), dim3(256), 0, r.stream, (__half*)r.pops, rho, u, r.geom);
+      break;
+  }
+  r.parity = 0;
+  return hipGetLastError();
+}
+
+hipError_t lbm_read_fields(Run& r, double* rho, double* u) {
+  const int nb = blocks_for(r.cells, 256);
+  switch (r.prec) {
+    case VLB_F64:
+      hipLaunchKernelGGL(k_read_fields<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.pops, r.geom, r.parity, rho, u);
+      break;
+    case VLB_F32:
+      hipLaunchKernelGGL(k_read_fields<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.pops, r.geom, r.parity, rho, u);
+      break;
+    default:
+      hipLaunchKernelGGL(k_read_fields<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, rho, u);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t lbm_read_pops(Run& r, double* f) {
+  const int nb = blocks_for(r.cells, 256);
+  switch (r.prec) {
+    case VLB_F64:
+      hipLaunchKernelGGL(k_read_pops<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.pops, r.geom, r.parity, f);
+      break;
+    case VLB_F32:
+      hipLaunchKernelGGL(k_read_pops<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.pops, r.geom, r.parity, f);
+      break;
+    default:
+      hipLaunchKernelGGL(k_read_pops<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, f);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t lbm_read_force(Run& r, double* out) {
+  const long long n = 3 * r.cells;
+  const int nb = blocks_for(n, 256);
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_read_force<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.force, n, out);
+  else
+    hipLaunchKernelGGL(k_read_force<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.force, n, out);
+  return hipGetLastError();
+}
+
+int slice_parts(const Geom& g) {
+  const long long area = (long long)g.nx * g.ny;
+  long long p = area / 2048;
+  if (p < 1) p = 1;
+  if (p > 32) p = 32;
+  return (int)p;
+}
+
+hipError_t lbm_mass_balance(Run& r) {
+  const Geom& g = r.geom;
+  const int np = slice_parts(g);
+  double* part = (double*)r.bsP;  // reuse the Biot-Savart partial buffer (free at this point)
+  const int nb = g.nz * np;
+  switch (r.prec) {
+    case VLB_F64:
+      hipLaunchKernelGGL(k_slice_partial<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.pops, g, r.parity, np, part);
+      break;
+    case VLB_F32:
+      hipLaunchKernelGGL(k_slice_partial<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.pops, g, r.parity, np, part);
+      break;
+    default:
+      hipLaunchKernelGGL(k_slice_partial<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, g, r.parity, np, part);
+      break;
+  }
+  const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
+  hipLaunchKernelGGL(k_slice_final, dim3(blocks_for(g.nz, 256)), dim3(256), 0, r.stream, part, g.nz, np, scale, r.Vs);
+  return hipGetLastError();
+}
+
+}  // namespace vlb

@@ -1,0 +1,505 @@
+// Filament topology (paper Sec. II.A: segment lengths kept between dxi_min
+// and dxi_max; Sec. II.A / III.B: legs of two vortices exchanged when they
+// come within the resolution), made data-parallel and deterministic:
+//  * remeshing: a point whose incoming segment is shorter than dxi_min is
+//    deleted unless its predecessor is also such a point; every remaining
+//    segment longer than dxi_max gets its midpoint, appended after the old
+//    points in ascending segment order;
+//  * reconnection: candidate pairs (i < j, more than two links apart,
+//    closer than the reconnection distance, exchange not lengthening the
+//    line) are found through a cell binning, sorted by (d^2, i, j) and
+//    applied greedily, each point at most once;
+//  * loops with fewer than min_loop_pts points are removed, and the point
+//    arrays are compacted in index order.
+// All decisions compare FP64 squared distances summed as dx*dx + dy*dy +
+// dz*dz with no fused multiply-add, so the integer outcome is a fixed
+// function of the positions.
+#include "vlb_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#pragma clang fp contract(off)
+
+namespace vlb {
+
+namespace {
+
+struct TopoGeom {
+  double L[3];
+  int periodic[3];
+};
+
+__device__ inline double sq3(const double d[3]) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(d[0], d[0]), __dmul_rn(d[1], d[1])), __dmul_rn(d[2], d[2]));
+}
+
+// d = s_j - s_i at the nearest periodic image
+__device__ inline void sep(const double* __restrict__ pos, long long nc, int i, int j,
+                           const TopoGeom& tg, double d[3]) {
+  for (int a = 0; a < 3; ++a) {
+    double x = __dsub_rn(pos[a * nc + j], pos[a * nc + i]);
+    if (tg.periodic[a]) {
+      if (x > 0.5 * tg.L[a])
+        x = __dsub_rn(x, tg.L[a]);
+      else if (x < -0.5 * tg.L[a])
+        x = __dadd_rn(x, tg.L[a]);
+    }
+    d[a] = x;
+  }
+}
+
+__device__ inline double wrap1(double x, double L, int periodic) {
+  if (periodic) {
+    if (x < 0.0) x = __dadd_rn(x, L);
+    if (x >= L) x = __dsub_rn(x, L);
+    if (x >= L) x = 0.0;
+  } else {
+    const double lo = -0.5, hi = L - 0.5;
+    if (x < lo) x = __dsub_rn(2.0 * lo, x);
+    if (x > hi) x = __dsub_rn(2.0 * hi, x);
+  }
+  return x;
+}
+
+// ---- single-workgroup exclusive scan of n ints (n read from *np)
+__global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in,
+                                                    int32_t* __restrict__ out,
+                                                    const int32_t* __restrict__ np,
+                                                    int32_t* __restrict__ total) {
+  __shared__ int32_t s[1024];
+  const int n = *np;
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b = t * per;
+  const int e = min(n, b + per);
+  int acc = 0;
+  for (int k = b; k < e; ++k) acc += in[k];
+  s[t] = acc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = (t >= off) ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  int run = s[t] - acc;  // exclusive prefix of this thread's range
+  for (int k = b; k < e; ++k) {
+    const int v = in[k];
+    out[k] = run;
+    run += v;
+  }
+  if (t == 1023) *total = s[1023];
+}
+
+__global__ void k_reset_stats(int32_t* cnt) {
+  if (threadIdx.x == 0) {
+    cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
+    cnt[9] = cnt[0];
+  }
+}
+
+__global__ void k_rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ prv,
+                          const int32_t* __restrict__ cnt, long long nc, TopoGeom tg, double mn2,
+                          int32_t* __restrict__ cand) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[0]) return;
+  double d[3];
+  sep(pos, nc, prv[j], j, tg, d);
+  cand[j] = sq3(d) < mn2 ? 1 : 0;
+}
+
+__global__ void k_rm_del(const int32_t* __restrict__ prv, int32_t* __restrict__ cnt,
+                         const int32_t* __restrict__ cand, int32_t* __restrict__ del) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[0]) return;
+  const int dd = (cand[j] && !cand[prv[j]]) ? 1 : 0;
+  del[j] = dd;
+  if (dd) atomicAdd(&cnt[3], 1);
+}
+
+__global__ void k_rm_relink(int32_t* __restrict__ nxt, int32_t* __restrict__ prv,
+                            const int32_t* __restrict__ cnt, const int32_t* __restrict__ del) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[0] || !del[j]) return;
+  const int p = prv[j], q = nxt[j];
+  nxt[p] = q;
+  prv[q] = p;
+}
+
+__global__ void k_rm_insmark(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                             const int32_t* __restrict__ cnt, long long nc, TopoGeom tg,
+                             double mx2, const int32_t* __restrict__ del, int32_t* __restrict__ ins) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[0]) return;
+  int v = 0;
+  if (!del[j]) {
+    double d[3];
+    sep(pos, nc, j, nxt[j], tg, d);
+    v = sq3(d) > mx2 ? 1 : 0;
+  }
+  ins[j] = v;
+}
+
+__global__ void k_rm_insert(double* __restrict__ pos, int32_t* __restrict__ nxt,
+                            int32_t* __restrict__ prv, int32_t* __restrict__ cnt, long long nc,
+                            TopoGeom tg, int32_t* __restrict__ del, const int32_t* __restrict__ ins,
+                            const int32_t* __restrict__ rank) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  const int M = cnt[2];
+  const bool fits = (long long)n + M <= nc;
+  if (j == 0) {
+    cnt[9] = fits ? n + M : n;
+    if (!fits && M > 0) atomicOr(&cnt[7], kFlagCapacity);
+  }
+  if (j >= n || !fits || !ins[j]) return;
+  const int q = n + rank[j];
+  const int k = nxt[j];
+  double d[3];
+  sep(pos, nc, j, k, tg, d);
+  for (int a = 0; a < 3; ++a)
+    pos[a * nc + q] = wrap1(__dadd_rn(pos[a * nc + j], 0.5 * d[a]), tg.L[a], tg.periodic[a]);
+  nxt[j] = q;
+  prv[q] = j;
+  nxt[q] = k;
+  prv[k] = q;
+  del[q] = 0;
+}
+
+// alive = not deleted and not on a loop with fewer than min_pts points
+__global__ void k_small(const int32_t* __restrict__ nxt, int32_t* __restrict__ cnt,
+                        const int32_t* __restrict__ del, int min_pts, int32_t* __restrict__ alive) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[9]) return;
+  if (del[j]) {
+    alive[j] = 0;
+    return;
+  }
+  int p = nxt[j];
+  int steps = 1;
+  while (p != j && steps < min_pts) {
+    p = nxt[p];
+    ++steps;
+  }
+  const int dead = (p == j && steps < min_pts) ? 1 : 0;
+  alive[j] = 1 - dead;
+  if (dead) atomicAdd(&cnt[5], 1);
+}
+
+__global__ void k_compact_scatter(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                                  const int32_t* __restrict__ prv, const int32_t* __restrict__ cnt,
+                                  long long nc, const int32_t* __restrict__ alive,
+                                  const int32_t* __restrict__ idx, double* __restrict__ pos_t,
+                                  int32_t* __restrict__ nxt_t, int32_t* __restrict__ prv_t) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[9] || !alive[j]) return;
+  const int q = idx[j];
+  for (int a = 0; a < 3; ++a) pos_t[a * nc + q] = pos[a * nc + j];
+  nxt_t[q] = idx[nxt[j]];
+  prv_t[q] = idx[prv[j]];
+}
+
+__global__ void k_compact_copy(double* __restrict__ pos, int32_t* __restrict__ nxt,
+                               int32_t* __restrict__ prv, int32_t* __restrict__ cnt, long long nc,
+                               const double* __restrict__ pos_t, const int32_t* __restrict__ nxt_t,
+                               const int32_t* __restrict__ prv_t) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = cnt[8];
+  if (q == 0) cnt[0] = nn;
+  if (q >= nn) return;
+  for (int a = 0; a < 3; ++a) pos[a * nc + q] = pos_t[a * nc + q];
+  nxt[q] = nxt_t[q];
+  prv[q] = prv_t[q];
+}
+
+__global__ void k_fill(int32_t* __restrict__ p, long long n, int32_t v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---- reconnection
+struct BinGeom {
+  int nb[3];
+  double h[3];
+  double off[3];  // 0.5 on wall axes (range starts at -1/2), 0 on periodic
+  int periodic[3];
+};
+
+__device__ inline int bin_of(double x, const BinGeom& bg, int a) {
+  int b = (int)floor((x + bg.off[a]) / bg.h[a]);
+  if (b < 0) b = 0;
+  if (b >= bg.nb[a]) b = bg.nb[a] - 1;
+  return b;
+}
+
+__global__ void k_rc_keys(const double* __restrict__ pos, const int32_t* __restrict__ cnt,
+                          long long nc, BinGeom bg, uint32_t pad, uint32_t* __restrict__ keys,
+                          int32_t* __restrict__ vals) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  uint32_t k = pad;
+  if (j < cnt[0]) {
+    const int bx = bin_of(pos[j], bg, 0);
+    const int by = bin_of(pos[nc + j], bg, 1);
+    const int bz = bin_of(pos[2 * nc + j], bg, 2);
+    k = (uint32_t)(((long long)bz * bg.nb[1] + by) * bg.nb[0] + bx);
+  }
+  keys[j] = k;
+  vals[j] = j;
+}
+
+__device__ inline int lower_bound_u32(const uint32_t* keys, int n, uint32_t k) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Offsets of the neighbouring bins along one axis (no duplicates when the
+// periodic axis has fewer than 3 bins).
+__device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
+  int m = 0;
+  for (int o = -1; o <= 1; ++o) {
+    int c = b + o;
+    if (bg.periodic[a]) {
+      if (bg.nb[a] == 1 && o != 0) continue;
+      if (bg.nb[a] == 2 && o == -1) continue;
+      c = (c + bg.nb[a]) % bg.nb[a];
+    } else if (c < 0 || c >= bg.nb[a]) {
+      continue;
+    }
+    out[m++] = c;
+  }
+  return m;
+}
+
+// Visit every candidate partner j > i of point i; calls f(j, d2).
+template <class Fn>
+__device__ inline void rc_visit(int i, const double* __restrict__ pos,
+                                const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
+                                const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
+                                int n, long long nc, const TopoGeom& tg, const BinGeom& bg,
+                                double d2max, Fn f) {
+  const int b[3] = {bin_of(pos[i], bg, 0), bin_of(pos[nc + i], bg, 1), bin_of(pos[2 * nc + i], bg, 2)};
+  int ox[3], oy[3], oz[3];
+  const int mx = bin_offsets(bg, 0, b[0], ox);
+  const int my = bin_offsets(bg, 1, b[1], oy);
+  const int mz = bin_offsets(bg, 2, b[2], oz);
+  const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
+  for (int iz = 0; iz < mz; ++iz)
+    for (int iy = 0; iy < my; ++iy)
+      for (int ix = 0; ix < mx; ++ix) {
+        const uint32_t k = (uint32_t)(((long long)oz[iz] * bg.nb[1] + oy[iy]) * bg.nb[0] + ox[ix]);
+        int t = lower_bound_u32(skey, n, k);
+        for (; t < n && skey[t] == k; ++t) {
+          const int j = sval[t];
+          if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
+          double d[3];
+          sep(pos, nc, i, j, tg, d);
+          const double d2 = sq3(d);
+          if (!(d2 < d2max)) continue;
+          const int nj = nxt[j];
+          double ea[3], eb[3], ec[3], ee[3];
+          sep(pos, nc, i, ni, tg, ea);
+          sep(pos, nc, j, nj, tg, eb);
+          sep(pos, nc, i, nj, tg, ec);
+          sep(pos, nc, j, ni, tg, ee);
+          const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
+          const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
+          if (after <= before) f(j, d2);
+        }
+      }
+}
+
+__global__ void k_rc_count(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                           const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
+                           const int32_t* __restrict__ sval, const int32_t* __restrict__ cnt,
+                           long long nc, TopoGeom tg, BinGeom bg, double d2max,
+                           int32_t* __restrict__ count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  if (i >= n) return;
+  int c = 0;
+  rc_visit(i, pos, nxt, prv, skey, sval, n, nc, tg, bg, d2max, [&](int, double) { ++c; });
+  count[i] = c;
+}
+
+__global__ void k_rc_write(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                           const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
+                           const int32_t* __restrict__ sval, int32_t* __restrict__ cnt,
+                           long long nc, TopoGeom tg, BinGeom bg, double d2max,
+                           const int32_t* __restrict__ off, long long rcap,
+                           int32_t* __restrict__ ci, int32_t* __restrict__ cj,
+                           uint64_t* __restrict__ ckey, int32_t* __restrict__ cidx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  if (i == 0 && cnt[6] > rcap) atomicOr(&cnt[7], kFlagReconCap);
+  if (i >= n || cnt[6] > rcap) return;
+  const int o0 = off[i];
+  int m = 0;
+  rc_visit(i, pos, nxt, prv, skey, sval, n, nc, tg, bg, d2max, [&](int j, double d2) {
+    const int at = o0 + m;
+    // insertion into the run [o0, at) kept sorted by j
+    int p = at;
+    while (p > o0 && cj[p - 1] > j) {
+      cj[p] = cj[p - 1];
+      ckey[p] = ckey[p - 1];
+      --p;
+    }
+    cj[p] = j;
+    ckey[p] = (uint64_t)__double_as_longlong(d2);
+    ++m;
+  });
+  for (int t = o0; t < o0 + m; ++t) {
+    ci[t] = i;
+    cidx[t] = t;
+  }
+}
+
+__global__ void k_rc_pad(const int32_t* __restrict__ cnt, long long rcap, uint64_t* __restrict__ ckey,
+                         int32_t* __restrict__ cidx) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rcap) return;
+  const long long tot = cnt[6];
+  if (tot > rcap) return;
+  if (t >= tot) {
+    ckey[t] = ~(uint64_t)0;
+    cidx[t] = (int32_t)t;
+  }
+}
+
+// Greedy application in sorted order (one thread: the sequence matters).
+__global__ void k_rc_greedy(int32_t* __restrict__ nxt, int32_t* __restrict__ prv,
+                            int32_t* __restrict__ cnt, long long rcap,
+                            const int32_t* __restrict__ ci, const int32_t* __restrict__ cj,
+                            const int32_t* __restrict__ sidx, int32_t* __restrict__ used) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const long long tot = cnt[6];
+  if (tot > rcap) return;
+  int nrec = 0;
+  for (long long c = 0; c < tot; ++c) {
+    const int id = sidx[c];
+    const int i = ci[id], j = cj[id];
+    if (used[i] || used[j]) continue;
+    const int a = nxt[i], b = nxt[j];
+    nxt[i] = b;
+    prv[b] = i;
+    nxt[j] = a;
+    prv[a] = j;
+    used[i] = 1;
+    used[j] = 1;
+    ++nrec;
+  }
+  cnt[4] = nrec;
+}
+
+__global__ void k_set_bound(int32_t* cnt) {
+  if (threadIdx.x == 0) cnt[9] = cnt[0];
+}
+
+inline int nb_of(long long n, int b) { return (int)((n + b - 1) / b); }
+
+TopoGeom topo_geom(const Run& r) {
+  TopoGeom tg;
+  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
+  for (int a = 0; a < 3; ++a) {
+    tg.L[a] = (double)n[a];
+    tg.periodic[a] = !r.geom.wall[a];
+  }
+  return tg;
+}
+
+BinGeom bin_geom(const Run& r) {
+  BinGeom bg;
+  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
+  for (int a = 0; a < 3; ++a) {
+    bg.nb[a] = r.bin_n[a];
+    bg.h[a] = r.bin_h[a];
+    bg.periodic[a] = !r.geom.wall[a];
+    bg.off[a] = r.geom.wall[a] ? 0.5 : 0.0;
+    (void)n;
+  }
+  return bg;
+}
+
+hipError_t small_and_compact(Run& r, int32_t* del) {
+  const int nb = nb_of(r.ncap, 256);
+  hipLaunchKernelGGL(k_small, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.cnt, del,
+                     r.vor.min_loop_pts, r.scan_a);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt + 9, r.cnt + 8);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv,
+                     r.cnt, r.ncap, r.scan_a, r.scan_b, r.pos_t, r.nxt_t, r.prv_t);
+  hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
+                     r.ncap, r.pos_t, r.nxt_t, r.prv_t);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t rc_sort_tmp_bytes(long long n) {
+  size_t bytes = 0;
+  rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                            (int32_t*)nullptr, (int32_t*)nullptr, (unsigned int)n, 0u, 64u,
+                            (hipStream_t)0);
+  return bytes;
+}
+
+hipError_t topo_update(Run& r) {
+  const TopoGeom tg = topo_geom(r);
+  const int nb = nb_of(r.ncap, 256);
+  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, r.stream, r.cnt);
+  int32_t* del = r.flag_b;
+  if (r.vor.remesh) {
+    const double mn2 = r.vor.dxi_min * r.vor.dxi_min;
+    const double mx2 = r.vor.dxi_max * r.vor.dxi_max;
+    hipLaunchKernelGGL(k_rm_cand, dim3(nb), dim3(256), 0, r.stream, r.pos, r.prv, r.cnt, r.ncap, tg, mn2, r.flag_a);
+    hipLaunchKernelGGL(k_rm_del, dim3(nb), dim3(256), 0, r.stream, r.prv, r.cnt, r.flag_a, del);
+    hipLaunchKernelGGL(k_rm_relink, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, del);
+    hipLaunchKernelGGL(k_rm_insmark, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap, tg, mx2, del, r.scan_a);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 2);
+    hipLaunchKernelGGL(k_rm_insert, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
+                       r.ncap, tg, del, r.scan_a, r.scan_b);
+  } else {
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, del, r.ncap, 0);
+  }
+  hipError_t e = small_and_compact(r, del);
+  if (e != hipSuccess) return e;
+
+  if (r.vor.reconnect) {
+    const BinGeom bg = bin_geom(r);
+    const double d2max = r.vor.reconnect_dist * r.vor.reconnect_dist;
+    const uint32_t pad = (r.bin_bits >= 32) ? 0xFFFFFFFFu : ((1u << r.bin_bits) - 1u);
+    hipLaunchKernelGGL(k_rc_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, bg, pad, r.keys_a, r.vals_a);
+    size_t bytes = r.sort_tmp_bytes;
+    e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
+                                  (unsigned int)r.ncap, 0u, (unsigned int)r.bin_bits, r.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rc_count, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
+                       r.vals_b, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 6);
+    hipLaunchKernelGGL(k_rc_write, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
+                       r.vals_b, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i, r.rc_j,
+                       r.rc_key_a, r.rc_idx_a);
+    hipLaunchKernelGGL(k_rc_pad, dim3(nb_of(r.rcap, 256)), dim3(256), 0, r.stream, r.cnt, r.rcap,
+                       r.rc_key_a, r.rc_idx_a);
+    bytes = r.rc_sort_tmp_bytes;
+    e = rocprim::radix_sort_pairs(r.rc_sort_tmp, bytes, r.rc_key_a, r.rc_key_b, r.rc_idx_a,
+                                  r.rc_idx_b, (unsigned int)r.rcap, 0u, 64u, r.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, r.used, r.ncap, 0);
+    hipLaunchKernelGGL(k_rc_greedy, dim3(1), dim3(64), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,
+                       r.rc_i, r.rc_j, r.rc_idx_b, r.used);
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, del, r.ncap, 0);
+    hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(64), 0, r.stream, r.cnt);
+    e = small_and_compact(r, del);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vlb

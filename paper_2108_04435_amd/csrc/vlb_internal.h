@@ -1,0 +1,286 @@
+// Internal declarations of the vlb library: run state, workspace layout,
+// D3Q19 tables and the population access rules shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vlb.h"
+
+namespace vlb {
+
+// ------------------------------------------------------------------ D3Q19
+// Velocity set of the paper's Table I (Sec. II.B): index 0 rest, 1-6 the
+// axis neighbours (weight 1/18), 7-18 the face diagonals (weight 1/36).
+// Opposite pairs are (2k-1, 2k) for k >= 1.
+__host__ __device__ constexpr int cx(int i) {
+  constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return t[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+  constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+  constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return t[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wq(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// FP16 storage keeps deviations scaled by 2^10 (exact power-of-two scale).
+constexpr float kHalfScale = 1024.0f;
+constexpr float kHalfInvScale = 1.0f / 1024.0f;
+
+// Storage traits: memory holds deviations d_i = f_i - w_i (rho0 = 1).
+template <class S> struct Store;
+template <> struct Store<double> {
+  using T = double;
+  __device__ static T ld(const double* p) { return *p; }
+  __device__ static void st(double* p, T v) { *p = v; }
+};
+template <> struct Store<float> {
+  using T = float;
+  __device__ static T ld(const float* p) { return *p; }
+  __device__ static void st(float* p, T v) { *p = v; }
+};
+template <> struct Store<__half> {
+  using T = float;
+  __device__ static T ld(const __half* p) { return __half2float(*p) * kHalfInvScale; }
+  __device__ static void st(__half* p, T v) { *p = __float2half_rn(v * kHalfScale); }
+};
+
+// Lattice description as passed to kernels.
+struct Geom {
+  int nx, ny, nz;
+  int wall[3];
+  int plane_lo, plane_hi;
+  long long cells;
+  double plane_u[3];
+  double body[3];
+  double omega;       // 1/tau
+  double fpref;       // 1 - 1/(2 tau)
+};
+
+// Index of node (x, y, z) + (dx, dy, dz), or -1 when that node lies beyond
+// a wall (periodic axes wrap).
+__device__ inline long long neighbour(const Geom& g, int x, int y, int z, int dx, int dy, int dz) {
+  int xx = x + dx, yy = y + dy, zz = z + dz;
+  if (xx < 0 || xx >= g.nx) {
+    if (g.wall[0]) return -1;
+    xx = xx < 0 ? xx + g.nx : xx - g.nx;
+  }
+  if (yy < 0 || yy >= g.ny) {
+    if (g.wall[1]) return -1;
+    yy = yy < 0 ? yy + g.ny : yy - g.ny;
+  }
+  if (zz < 0 || zz >= g.nz) {
+    if (g.wall[2]) return -1;
+    zz = zz < 0 ? zz + g.nz : zz - g.nz;
+  }
+  return ((long long)zz * g.ny + yy) * g.nx + xx;
+}
+
+// Deviations of the populations at node (x, y, z) at a time whose storage
+// parity is P (0: natural layout, population i of node x in slot i of x;
+// 1: the AA-swapped layout written by an even step: population i of x sits
+// in slot opp(i) of x - c_i, or in slot i of x itself when x - c_i is
+// beyond a wall -- the halfway bounce-back).
+template <class S>
+__device__ inline void load_node(const S* __restrict__ M, const Geom& g, int parity, int x, int y,
+                                 int z, typename Store<S>::T d[19]) {
+  const long long c = ((long long)z * g.ny + y) * g.nx + x;
+  if (parity == 0) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = Store<S>::ld(M + (long long)i * g.cells + c);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      long long s = neighbour(g, x, y, z, -cx(i), -cy(i), -cz(i));
+      d[i] = (s >= 0) ? Store<S>::ld(M + (long long)opp(i) * g.cells + s)
+                      : Store<S>::ld(M + (long long)i * g.cells + c);
+    }
+  }
+}
+
+__device__ inline bool is_plane(const Geom& g, int z) {
+  return (g.plane_lo && z == 0) || (g.plane_hi && z == g.nz - 1);
+}
+
+// Equilibrium deviation f^eq_i(rho, u) - w_i for rho = 1 + drho.
+template <class T>
+__device__ inline T eq_dev(int i, T drho, T rho, T ux, T uy, T uz) {
+  const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
+  const T uu = ux * ux + uy * uy + uz * uz;
+  return T(wq(i)) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
+}
+
+// Density deviation and momentum of a node's deviations.
+template <class T>
+__device__ inline void moments(const T d[19], T& drho, T& jx, T& jy, T& jz) {
+  T r = 0, a = 0, b = 0, c = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    r += d[i];
+    if (cx(i)) a += T(cx(i)) * d[i];
+    if (cy(i)) b += T(cy(i)) * d[i];
+    if (cz(i)) c += T(cz(i)) * d[i];
+  }
+  drho = r;
+  jx = a;
+  jy = b;
+  jz = c;
+}
+
+// Map a hardware workgroup id to a logical tile id so that the workgroups
+// one XCD receives (hardware ids k, k+8, k+16, ... go round-robin to the 8
+// XCDs) cover one contiguous range of tiles, which keeps stencil halos
+// inside that XCD's L2.
+__device__ inline int xcd_remap(int hw, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int k = hw & 7, j = hw >> 3;
+  return (k < r) ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j;
+}
+
+// Biot-Savart grid: a coordinate is represented by a 32-bit integer so that
+// periodic separations wrap exactly in two's complement.
+struct BsAxes {
+  double q[3];      // grid steps per lattice unit
+  double off[3];    // added before scaling (1 on wall axes, 0 on periodic)
+  float invq_f[3];  // lattice units per grid step, FP32
+  double invq_d[3];
+  double L[3];
+  int periodic[3];
+};
+
+// Workspace-resident state of a run.
+struct Run {
+  vlb_lattice_desc lat;
+  vlb_vortex_desc vor;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  Geom geom;
+  BsAxes bsax;
+  int prec = 0;
+  long long cells = 0;
+  long long ncap = 0;
+
+  // lattice
+  void* pops = nullptr;   // 19 * cells storage values (deviations)
+  void* force = nullptr;  // 3 * cells (double for F64, float otherwise)
+  int32_t* touched = nullptr;  // 8 * ncap node indices written by spreading
+  double* Vs = nullptr;        // nz slice superflow
+
+  // filaments
+  double* pos = nullptr;   // 3 * ncap, SoA
+  double* ya = nullptr;
+  double* yb = nullptr;
+  double* ksum = nullptr;
+  double* vs1 = nullptr;
+  double* vn1 = nullptr;
+  double* sd1 = nullptr;
+  double* gpt = nullptr;
+  int32_t* nxt = nullptr;
+  int32_t* prv = nullptr;
+  double* pos_t = nullptr;  // compaction scratch
+  int32_t* nxt_t = nullptr;
+  int32_t* prv_t = nullptr;
+
+  // Biot-Savart
+  uint32_t* bsX = nullptr;  // 3 * ncap grid coordinates
+  void* bsD = nullptr;      // 3 * ncap segment vectors (float or double)
+  void* bsP = nullptr;      // S * 3 * ncap partial sums
+  int bsS = 1;
+
+  // counters on the device: [0] n points, [1] n touched slots,
+  // [2] inserted, [3] deleted, [4] reconnections, [5] small-loop points,
+  // [6] candidates, [7] error flags
+  int32_t* cnt = nullptr;
+
+  // sorting / scans
+  uint32_t* keys_a = nullptr;
+  uint32_t* keys_b = nullptr;
+  int32_t* vals_a = nullptr;
+  int32_t* vals_b = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int key_bits = 32;
+  int32_t* flag_a = nullptr;  // per point int flags
+  int32_t* flag_b = nullptr;
+  int32_t* scan_a = nullptr;
+  int32_t* scan_b = nullptr;
+
+  // reconnection
+  long long rcap = 0;
+  int bin_n[3] = {1, 1, 1};
+  double bin_h[3] = {1, 1, 1};
+  int bin_bits = 32;
+  int32_t* rc_i = nullptr;
+  int32_t* rc_j = nullptr;
+  uint64_t* rc_key_a = nullptr;
+  uint64_t* rc_key_b = nullptr;
+  int32_t* rc_idx_a = nullptr;
+  int32_t* rc_idx_b = nullptr;
+  void* rc_sort_tmp = nullptr;
+  size_t rc_sort_tmp_bytes = 0;
+  int32_t* used = nullptr;
+
+  // staging for host <-> device filament copies
+  double* stage = nullptr;  // 3 * ncap doubles
+  int32_t* stage_i = nullptr;
+
+  int64_t step = 0;
+  int parity = 0;
+  bool has_fields = false;
+  bool has_points = false;  // set once filaments were seeded
+
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[2];
+
+  int64_t last_nodes = 0;
+  int64_t last_pairs = 0;
+
+  std::string err;
+};
+
+// error flag bits in cnt[7]
+constexpr int kFlagCapacity = 1;
+constexpr int kFlagNumeric = 2;
+constexpr int kFlagReconCap = 4;
+
+// ---- launchers (one per .hip file)
+hipError_t lbm_init_eq(Run& r, const double* rho, const double* u);
+hipError_t lbm_step(Run& r);
+hipError_t lbm_read_fields(Run& r, double* rho, double* u);
+hipError_t lbm_read_pops(Run& r, double* f);
+hipError_t lbm_read_force(Run& r, double* out);
+hipError_t lbm_mass_balance(Run& r);
+
+hipError_t bs_prep(Run& r, const double* Y);
+hipError_t bs_sum(Run& r, const double* Y);
+int bs_chunks(long long ncap);
+
+hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only);
+hipError_t fil_spread(Run& r);
+hipError_t fil_clear_force(Run& r);
+hipError_t fil_seed(Run& r, long long n);
+
+hipError_t topo_update(Run& r);
+
+size_t sort_tmp_bytes(long long n);
+size_t rc_sort_tmp_bytes(long long n);
+
+// timing helpers (api.cpp)
+void time_begin(Run& r, int cls, hipEvent_t* b);
+void time_end(Run& r, int cls, hipEvent_t b);
+
+}  // namespace vlb

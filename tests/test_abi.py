@@ -1,0 +1,128 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/vlb.h declares, the ctypes structures match the C layout, and the
+host-side argument checks and footprint query work without a GPU."""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_2108_04435_amd as vlb
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vlb.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vlb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_symbols():
+    assert _declared() == sorted(vlb.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vlb.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", vlb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (vlb_[a-z_]+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_struct_layout_matches_c():
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "vlb.h"
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("lat %zu\nvor %zu\n", sizeof(vlb_lattice_desc), sizeof(vlb_vortex_desc));
+  O(vlb_lattice_desc, tau); O(vlb_lattice_desc, wall_axes); O(vlb_lattice_desc, plane_u);
+  O(vlb_lattice_desc, body_force); O(vlb_vortex_desc, vs_applied); O(vlb_vortex_desc, remesh);
+  O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap);
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    vals = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    assert int(vals["lat"]) == ctypes.sizeof(vlb.LatticeDesc)
+    assert int(vals["vor"]) == ctypes.sizeof(vlb.VortexDesc)
+    for key, v in vals.items():
+        if "." in key:
+            st, f = key.split(".")
+            cls = vlb.LatticeDesc if st == "vlb_lattice_desc" else vlb.VortexDesc
+            assert getattr(cls, f).offset == int(v), key
+
+
+def _query(lat, vor, n_cap=100, recon_cap=1000):
+    lib = vlb.load_library()
+    ld = vlb.lattice_desc(lat)
+    vd = vlb.vortex_desc(vor, n_cap, recon_cap)
+    nb = ctypes.c_uint64(0)
+    code = lib.vlb_query_footprint(ctypes.byref(ld), ctypes.byref(vd), ctypes.byref(nb))
+    return code, nb.value, lib.vlb_last_error(None).decode()
+
+
+def test_footprint_grows_with_lattice_and_precision():
+    vor = wl.vortex_preset()
+    sizes = {}
+    for p in ("f64", "f32", "f16"):
+        code, nb, _ = _query(wl.lattice_preset(32, 32, 32, precision=p), vor)
+        assert code == vlb.VLB_OK
+        sizes[p] = nb
+    cells = 32 ** 3
+    # populations dominate: 19 values per node of 8 / 4 / 2 bytes
+    assert sizes["f64"] - sizes["f32"] >= 19 * cells * 4
+    assert sizes["f32"] - sizes["f16"] >= 19 * cells * 2
+    code, big, _ = _query(wl.lattice_preset(64, 64, 64, precision="f32"), vor)
+    assert big > 7 * sizes["f32"]
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(nx=3), ">= 4"),
+    (dict(precision="f64", walls=(False, False, True), plane_lo=True), "planes"),
+])
+def test_invalid_lattice_rejected(bad, msg):
+    lat = wl.lattice_preset(16, 16, 16)
+    lat.update(bad)
+    code, _, err = _query(lat, wl.vortex_preset())
+    assert code == vlb.VLB_EINVAL
+    assert msg in err
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(dxi_min=1.0, dxi_max=0.9), "dxi_min"),
+    (dict(min_loop_pts=2), "min_loop_pts"),
+    (dict(kappa=0.0), "kappa"),
+])
+def test_invalid_vortex_rejected(bad, msg):
+    vor = wl.vortex_preset()
+    vor.update(bad)
+    code, _, err = _query(wl.lattice_preset(16, 16, 16), vor)
+    assert code == vlb.VLB_EINVAL
+    assert msg in err
+
+
+def test_mass_balance_needs_periodic_z():
+    lat = wl.lattice_preset(16, 16, 16, walls=(False, False, True))
+    code, _, err = _query(lat, wl.vortex_preset(mass_balance=True))
+    assert code == vlb.VLB_EINVAL and "mass balance" in err
+
+
+def test_zero_capacity_rejected():
+    code, _, err = _query(wl.lattice_preset(16, 16, 16), wl.vortex_preset(), n_cap=0)
+    assert code == vlb.VLB_EINVAL

@@ -1,0 +1,99 @@
+"""GPU parity of the normal-fluid update (collide + stream, walls, planes,
+body force) against the oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import lbm
+from tests._cases import oracle_lattice, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2108_04435_amd as vlb  # noqa: E402
+
+LBM_CASES = {
+    "periodic": dict(n=(12, 10, 9), walls=(False, False, False), planes=False, body=(1e-5, -2e-5, 3e-5)),
+    "walls_xy": dict(n=(11, 13, 10), walls=(True, True, False), planes=False, body=(0.0, 0.0, 4e-5)),
+    "walls_xyz": dict(n=(9, 8, 10), walls=(True, True, True), planes=False, body=(2e-5, 0.0, 1e-5)),
+    "planes": dict(n=(10, 12, 14), walls=(True, True, False), planes=True, body=(0.0, 0.0, 0.0)),
+}
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+def _run_case(name, precision, steps):
+    c = LBM_CASES[name]
+    lat = wl.lattice_preset(*c["n"], tau=0.8, walls=c["walls"], plane_lo=c["planes"],
+                            plane_hi=c["planes"], plane_u=(0.0, 0.0, 0.02),
+                            body_force=c["body"], precision=precision)
+    vor = wl.vortex_preset()
+    rho, u = wl.velocity_field(31, c["n"], (0.01, -0.005, 0.02), 3e-3)
+    rho = rho + 0.01 * np.random.default_rng(32).standard_normal(rho.shape)
+    say("lbm", name, precision, steps)
+    run = vlb.Run(lat, vor, n_cap=1)
+    run.write_fields(rho, u)
+    run.step(steps)
+    run.sync()
+    olat = oracle_lattice(lat)
+    f = lbm.init_equilibrium(rho, u)
+    zero = np.zeros((3,) + olat.shape)
+    for _ in range(steps):
+        f = lbm.lbm_step(f, zero, olat)
+    return run, f, olat, rho
+
+
+@pytest.mark.parametrize("name", list(LBM_CASES))
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_lbm_f64_populations(name, steps):
+    run, f, olat, _ = _run_case(name, "f64", steps)
+    fg = run.read_populations()
+    np.testing.assert_allclose(fg, f, rtol=0, atol=1e-14)
+    rho_g, u_g = run.read_fields()
+    rho_o, u_o = lbm.bare_velocity(f, olat)
+    np.testing.assert_allclose(rho_g, rho_o, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(u_g, u_o, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", list(LBM_CASES))
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_lbm_reduced_precision(name, precision):
+    steps = 20
+    run, f, olat, _ = _run_case(name, precision, steps)
+    rho_g, u_g = run.read_fields()
+    rho_o, u_o = lbm.bare_velocity(f, olat)
+    err = rel_l2(u_g, u_o)
+    say("velocity L2 rel", precision, name, err)
+    assert err <= TOL[precision]
+    assert np.abs(rho_g - rho_o).max() < (1e-6 if precision == "f32" else 2e-4)
+
+
+def test_lbm_mass_conserved_f64():
+    """Walls + periodic, no planes: total mass exact over 50 steps."""
+    run, f, olat, rho0 = _run_case("walls_xy", "f64", 50)
+    rho_g, _ = run.read_fields()
+    assert abs(rho_g.sum() - rho0.sum()) / rho0.sum() < 1e-13
+
+
+def test_poiseuille_gpu_f64():
+    """Exact discrete Poiseuille profile reached by the GPU (plane channel,
+    walls on y, body force along x)."""
+    H, tau, g = 8, 1.0, 1e-6
+    lat = wl.lattice_preset(4, H, 4, tau=tau, walls=(False, True, False), body_force=(g, 0, 0),
+                            precision="f64")
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
+    rho = np.ones((4, H, 4))
+    u = np.zeros((3, 4, H, 4))
+    say("poiseuille gpu")
+    run.write_fields(rho, u)
+    run.step(3000)
+    _, ub = run.read_fields()
+    nu = (tau - 0.5) / 3
+    y = np.arange(H) - (H - 1) / 2
+    exact = (g / (2 * nu)) * ((H / 2) ** 2 - y ** 2 + (16 * (tau - 0.5) ** 2 - 3) / 12)
+    ux = ub[0, 1, :, 2] + 0.5 * g  # force-shifted velocity (rho = 1)
+    assert np.abs(ux / exact - 1).max() < 1e-9

@@ -1,0 +1,194 @@
+"""GPU parity of the filament side and of the coupled step against the
+oracle, through the C ABI: line velocity (Biot-Savart + LIA + superflow +
+interpolation + Schwarz), mutual-friction force and its spreading, full
+coupled steps, topology (exact integers)."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import coupled, lbm, topology, vfm
+from tests._cases import oracle_state, rel_l2, say, small_channel, small_periodic
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2108_04435_amd as vlb  # noqa: E402
+
+# velocity tolerance (relative L2 over all points / nodes)
+TOL = {"f64": 1e-10, "f32": 1e-5, "f16": 1e-3}
+
+CASES = {
+    "ring32": lambda p: wl.config_ring32(precision=p),
+    "channel": lambda p: small_channel(precision=p),
+    "periodic": lambda p: small_periodic(precision=p),
+    "heater": lambda p: small_channel(precision=p, planes=True, seed=23),
+}
+
+
+def _oracle_eval(cfg):
+    lat, vp, st = oracle_state(cfg)
+    _, ub = lbm.bare_velocity(st.f, lat)
+    Vs = lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n) if vp.mass_balance else None
+    out = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, Vs, lat, vp, want_force=True)
+    F = vfm.spread(out["force"], st.pos, lat)
+    return out, F, st
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
+def test_line_velocity_and_force(case, precision):
+    cfg = CASES[case](precision)
+    say("eval", case, precision, cfg["pos"].shape[0], "points")
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    ref, F_o, st = _oracle_eval(cfg)
+    pos_g, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    np.testing.assert_array_equal(pos_g, st.pos)
+    tol = TOL[precision]
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= tol, (k, err)
+    errF = rel_l2(F_g, F_o)
+    say("spread force", errF)
+    assert errF <= tol
+
+
+@pytest.mark.parametrize("case", ["ring32", "channel", "heater"])
+def test_coupled_steps_f64(case):
+    cfg = CASES[case]("f64")
+    steps = 12
+    say("coupled", case, steps)
+    run = vlb.run_from_config(cfg)
+    run.step(steps)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    for _ in range(steps):
+        st = coupled.coupled_step(st, lat, vp)
+    pos_g, nxt_g = run.read_filaments()
+    # no topology event may differ: compare integer links exactly
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    d = vfm.min_image(pos_g - st.pos, lat)
+    assert np.abs(d).max() < 1e-10
+    rho_g, u_g = run.read_fields()
+    rho_o, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) < 1e-10
+    np.testing.assert_allclose(rho_g, rho_o, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_coupled_steps_reduced_precision(precision):
+    cfg = small_channel(precision=precision)
+    steps = 10
+    say("coupled reduced", precision)
+    run = vlb.run_from_config(cfg)
+    run.step(steps)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    for _ in range(steps):
+        st = coupled.coupled_step(st, lat, vp)
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    err = rel_l2(u_g, u_o)
+    say("velocity", err)
+    assert err <= TOL[precision]
+    pos_g, nxt_g = run.read_filaments()
+    if nxt_g.shape == st.nxt.shape and (nxt_g == st.nxt).all():
+        d = vfm.min_image(pos_g - st.pos, lat)
+        assert np.abs(d).max() < (1e-4 if precision == "f32" else 1e-2)
+
+
+def _perturbed_rings(seed, n_rings, dims, walls, amp):
+    pos, nxt = wl.random_rings(seed, n_rings, 2.5, 5.0, dims, walls, 0.95)
+    rng = np.random.default_rng(seed + 100)
+    pos = pos + amp * rng.standard_normal(pos.shape)
+    return pos, nxt
+
+
+@pytest.mark.parametrize("walls", [(False, False, False), (True, True, False)])
+def test_remesh_exact(walls):
+    dims = (24, 24, 32)
+    lat = wl.lattice_preset(*dims, walls=walls, precision="f64")
+    vor = wl.vortex_preset()
+    pos, nxt = _perturbed_rings(41, 12, dims, walls, 0.3)
+    say("remesh", walls, pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0])
+    run.seed(pos, nxt)
+    stats = run.apply_topology()
+    pos_g, nxt_g = run.read_filaments()
+    from tests._cases import oracle_lattice, oracle_vortex
+    olat = oracle_lattice(lat)
+    p0 = vfm.wrap_positions(pos, olat)
+    p1, n1, q1, st = topology.topology_update(p0, nxt, coupled.prev_from_next(nxt), olat,
+                                              oracle_vortex(vor))
+    say("stats gpu", stats, "oracle", st)
+    assert stats["deleted"] == st["deleted"] and stats["inserted"] == st["inserted"]
+    assert st["deleted"] > 0 and st["inserted"] > 0
+    np.testing.assert_array_equal(nxt_g, n1)
+    np.testing.assert_array_equal(pos_g, p1)
+
+
+def test_reconnection_exact():
+    dims = (16, 16, 16)
+    lat = wl.lattice_preset(*dims, precision="f64")
+    vor = wl.vortex_preset(reconnect=True, remesh=False)
+    # antiparallel lines 0.3 apart (pairwise annihilation) plus a tangle of
+    # perturbed rings with many close approaches
+    n = 20
+    z = (np.arange(n) + 0.5) * 16 / n
+    a = np.stack([np.full(n, 7.0), np.full(n, 8.0), z], 1)
+    b = np.stack([np.full(n, 7.3), np.full(n, 8.0), z], 1)
+    rp, rn = _perturbed_rings(43, 25, dims, (False,) * 3, 0.2)
+    pos = np.concatenate([a, b, rp])
+    nxt = np.concatenate([(np.arange(n) + 1) % n, n + (np.arange(n) - 1) % n, rn + 2 * n])
+    say("reconnect", pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0], recon_cap=1 << 14)
+    run.seed(pos, nxt)
+    stats = run.apply_topology()
+    pos_g, nxt_g = run.read_filaments()
+    from tests._cases import oracle_lattice, oracle_vortex
+    olat = oracle_lattice(lat)
+    p0 = vfm.wrap_positions(pos, olat)
+    p1, n1, q1, st = topology.topology_update(p0, nxt, coupled.prev_from_next(nxt), olat,
+                                              oracle_vortex(vor))
+    say("stats gpu", stats, "oracle", st)
+    assert st["reconnections"] >= 20
+    assert stats["reconnections"] == st["reconnections"]
+    np.testing.assert_array_equal(nxt_g, n1)
+    np.testing.assert_array_equal(pos_g, p1)
+
+
+def test_no_vortices_is_pure_lbm():
+    cfg = small_channel(precision="f64")
+    say("no vortices")
+    run = vlb.Run(cfg["lattice"], cfg["vortex"], n_cap=16)
+    run.write_fields(cfg["rho"], cfg["u"])
+    run.step(4)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    f = st.f
+    for _ in range(4):
+        f = lbm.lbm_step(f, np.zeros((3,) + lat.shape), lat)
+    np.testing.assert_allclose(run.read_populations(), f, rtol=0, atol=1e-14)
+    assert run.n_points() == 0
+
+
+def test_capacity_overflow_reported():
+    dims = (24, 24, 24)
+    lat = wl.lattice_preset(*dims, precision="f64")
+    vor = wl.vortex_preset()
+    # a ring with spacing 1.9: every segment gets a midpoint -> 2x points
+    pos, nxt = wl.ring((12.0, 12.0, 12.0), 6.0, (0, 0, 1), 20)
+    run = vlb.Run(lat, vor, n_cap=25)
+    run.seed(pos, nxt)
+    say("capacity")
+    with pytest.raises(vlb.VlbError) as ei:
+        run.apply_topology()
+    assert ei.value.code == vlb.VLB_ECAPACITY
+    assert run.n_points() == 20  # insertion skipped, state intact

@@ -1,0 +1,265 @@
+"""Benchmark of the coupled VFM-LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload: the counterflow channel, 64x64x256 lattice with bounce-back
+walls on x and y, periodic z, Guo body force for a mean normal-fluid velocity
+of about 0.02, 200 seeded rings (R ~ U[4,12], ~1.0e4 points), remeshing
+spacing 1.0, mass balance on z, FP32 deviation storage and FP32
+Biot-Savart.  Inputs are synthetic and already resident in HBM when the
+timed region starts.  One step = one pass of the whole coupled step
+(mass-balance superflow, 4 RK stages of Biot-Savart + LIA + interpolation +
+Schwarz, force spreading, LBM collide+stream, remeshing).
+
+Prints ONE JSON line.  ``value`` is coupled steps per second on the one GPU;
+``roofline`` is for the dominant kernel (the Biot-Savart pair sum), timed
+with HIP events on the run's stream over the timed steps; ``cpu_baseline``
+times the FP64 oracle on the host on a bounded sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 work of one (target, segment) pair of the straight-segment
+# Biot-Savart closed form, counting a fused multiply-add as 2 flops and a
+# reciprocal / reciprocal square root as 1: separation 3, second end 3, two
+# squared norms 10, two inverse norms 2, cross product 9, dot 5, product of
+# inverse norms 1, denominator 2, numerator 2, reciprocal 1, scale 1,
+# accumulation 6.
+FLOPS_PER_PAIR = 45
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
+
+WORKLOADS = ("counterflow", "ring32", "heater", "tangle")
+
+
+def make_workload(name, precision=None):
+    import workloads as wl
+
+    if name == "counterflow":
+        cfg = wl.config_counterflow(precision=precision or "f32")
+    elif name == "ring32":
+        cfg = wl.config_ring32(precision=precision or "f64")
+    elif name == "heater":
+        cfg = wl.config_heater(precision=precision or "f32")
+    elif name == "tangle":
+        cfg = wl.config_tangle(precision=precision or "f16")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return cfg
+
+
+def traffic_record(kernel_src):
+    """HBM bytes per launch of the Biot-Savart kernel from committed
+    rocprofv3 counter runs, if they were taken on the current source."""
+    path = os.path.join(ROOT, "profiles", "bs_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, n_sample=4096):
+    """Oracle (plain FP64 numpy) on the host: one full LBM update of the
+    lattice plus the Biot-Savart sum for a sample of targets against all
+    segments, scaled to one coupled step (4 Biot-Savart evaluations)."""
+    from oracle import coupled, lbm, vfm
+    from oracle.lbm import Lattice
+    from oracle.vfm import VortexParams
+
+    L = cfg["lattice"]
+    lat = Lattice(L["nx"], L["ny"], L["nz"], tau=L["tau"], walls=tuple(L["walls"]),
+                  plane_lo=L["plane_lo"], plane_hi=L["plane_hi"], plane_u=tuple(L["plane_u"]),
+                  body_force=tuple(L["body_force"]))
+    vp = VortexParams(**{k: cfg["vortex"][k] for k in VortexParams.__dataclass_fields__})
+    st = coupled.make_state(cfg["rho"], cfg["u"], cfg["pos"], cfg["nxt"], lat)
+    n = st.pos.shape[0]
+    m = min(n, n_sample)
+    t0 = time.perf_counter()
+    _, ub = lbm.bare_velocity(st.f, lat)
+    if vp.mass_balance:
+        lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n)
+    lbm.lbm_step(st.f, np.zeros((3,) + lat.shape), lat)
+    t1 = time.perf_counter()
+    vfm.biot_savart_nonlocal(st.pos, st.nxt, st.prv, lat, vp.kappa, targets=np.arange(m))
+    t2 = time.perf_counter()
+    t_step = (t1 - t0) + 4.0 * (t2 - t1) * n / m
+    return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
+                sample=f"one FP64 LBM update of all {lat.nx}x{lat.ny}x{lat.nz} nodes plus the "
+                       f"Biot-Savart sum for {m} of {n} targets over all segments, scaled to one "
+                       f"coupled step (4 evaluations); numpy, single thread; "
+                       f"measured {t2 - t0:.1f} s")
+
+
+def lbm_only(torch, vlb, wl, n, precision, steps=20):
+    """Normal-fluid update alone on an n^3 periodic lattice (working set far
+    above the 256 MB last-level cache): kernel GB/s from HIP events."""
+    lat = wl.lattice_preset(n, n, n, tau=0.8, precision=precision)
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
+    rho, u = wl.velocity_field(4, (n, n, n), (0.0, 0.0, 0.02), 1e-4)
+    run.write_fields(rho, u)
+    del rho, u
+    run.step(4)
+    run.sync()
+    run.set_timing(True, reserve=4 * steps)
+    run.step(steps)
+    run.sync()
+    ms, k = run.timing(1)
+    b = {"f64": 8, "f32": 4, "f16": 2}[precision]
+    bytes_node = 2 * 19 * b
+    cells = n ** 3
+    gbs = bytes_node * cells * k / (ms * 1e-3) / 1e9
+    run.close()
+    return dict(lattice=f"{n}^3", precision=precision, kernel_ms=ms / k,
+                glups=cells * k / (ms * 1e-3) / 1e9, bytes_per_node=bytes_node,
+                achieved_GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="counterflow", choices=WORKLOADS)
+    ap.add_argument("--precision", default=None, choices=("f64", "f32", "f16"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lbm-probe", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_04435_amd as vlb
+    import workloads as wl
+
+    if not os.path.exists(vlb.LIB_PATH):
+        from paper_2108_04435_amd import build as b
+        b.build()
+
+    torch.cuda.set_device(0)
+    cfg = make_workload(args.workload, args.precision)
+    lat = cfg["lattice"]
+    n0 = cfg["pos"].shape[0]
+    run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256,
+                              recon_cap=1 << 18)
+    cells = lat["nx"] * lat["ny"] * lat["nz"]
+
+    run.step(args.warmup)
+    run.sync()
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    run.set_timing(True, reserve=2 * 6 * K + 64)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        run.step(1)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run.sync()
+    wall = t1 - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    bs_ms, bs_n = run.timing(0)
+    lbm_ms, lbm_n = run.timing(1)
+    nodes, pairs = run.work()
+    n_end = run.n_points()
+
+    value = K / wall
+    pairs_per_launch = pairs / max(bs_n, 1)
+    bs_avg_s = bs_ms * 1e-3 / max(bs_n, 1)
+    achieved = FLOPS_PER_PAIR * pairs_per_launch / bs_avg_s / 1e12 if bs_n else 0.0
+    src = os.path.join(ROOT, "paper_2108_04435_amd", "csrc", "bs.hip")
+    roofline = {
+        "bound": "alu",
+        "kernel": "k_bs_f32" if lat["precision"] != "f64" else "k_bs_f64",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "traffic": traffic_record(src),
+        "avg_launch_us": round(bs_avg_s * 1e6, 2),
+        "pairs_per_launch": int(pairs_per_launch),
+        "flops_per_pair": FLOPS_PER_PAIR,
+    }
+    b = {"f64": 8, "f32": 4, "f16": 2}[lat["precision"]]
+    lbm_bytes = 2 * 19 * b * cells
+    lbm_avg = lbm_ms * 1e-3 / max(lbm_n, 1)
+    out = {
+        "metric": "coupled steps/s (LBM MLUPS + Biot-Savart Gpairs/s), FP32/FP16 vs FP64; p99",
+        "value": round(value, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32"}[lat["precision"]],
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["name"],
+            "lattice": [lat["nx"], lat["ny"], lat["nz"]],
+            "precision": lat["precision"],
+            "points_start": int(n0),
+            "points_end": int(n_end),
+            "walls": list(lat["walls"]),
+            "mass_balance": bool(cfg["vortex"]["mass_balance"]),
+            "reconnect": bool(cfg["vortex"]["reconnect"]),
+        },
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "mlups": round(cells * K / wall / 1e6, 1),
+        "bs_gpairs_s": round(pairs / wall / 1e9, 2),
+        "bs_kernel_gpairs_s": round(pairs / (bs_ms * 1e-3) / 1e9, 2) if bs_ms else None,
+        "lbm_kernel": {"avg_launch_us": round(lbm_avg * 1e6, 2),
+                       "glups": round(cells / lbm_avg / 1e9, 2) if lbm_n else None,
+                       "algorithmic_GBs": round(lbm_bytes / lbm_avg / 1e9, 1) if lbm_n else None,
+                       "note": "working set fits the 256 MB last-level cache"},
+        "roofline": roofline,
+    }
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * x.numel()
+        del x, y
+
+    if not args.no_lbm_probe:
+        out["lbm_256cubed"] = [lbm_only(torch, vlb, wl, 256, p) for p in ("f32", "f16")]
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

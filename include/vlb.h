@@ -173,8 +173,10 @@ int vlb_get_step(vlb_run* run, int64_t* step);
 
 /* Kernel timing with HIP events recorded on the run's stream around every
  * launch of the named kernel class: 0 = Biot-Savart pair sum, 1 = LBM
- * collide+stream.  vlb_set_timing(run, 1) clears and enables; the totals
- * are read (after a sync) with vlb_get_timing.                             */
+ * collide+stream.  vlb_set_timing(run, e) clears the totals and enables
+ * timing for e > 0 (e > 1 also pre-creates e events so that no event is
+ * created while the timed steps are enqueued), disables it for e = 0; the
+ * totals are read (after a sync) with vlb_get_timing.                      */
 int vlb_set_timing(vlb_run* run, int32_t enable);
 int vlb_get_timing(vlb_run* run, int32_t kernel_class, double* total_ms, int64_t* launches);
 

@@ -36,13 +36,59 @@ def compact(pos, nxt, prv, alive):
     return pos2, nxt2, prv2
 
 
+CHAIN_LIMIT = 32
+
+
+def _deletion_flags(cand, nxt, prv):
+    """Which deletion candidates go in one pass (reading R10).  Along a run
+    of consecutive candidates the 1st, 3rd, 5th, ... go: candidate k is
+    deleted when the number c of candidates directly before it (walking
+    back along prv, at most CHAIN_LIMIT) is even and below the limit.  A
+    loop made only of candidates is counted from its lowest index, and its
+    last point is kept when the loop length is odd.  No two neighbours are
+    ever deleted in the same pass."""
+    N = cand.shape[0]
+    dele = np.zeros(N, dtype=bool)
+    for k in range(N):
+        if not cand[k]:
+            continue
+        c = 0
+        p = prv[k]
+        while c < CHAIN_LIMIT and cand[p] and p != k:
+            c += 1
+            p = prv[p]
+        if p == k:  # the whole loop (c + 1 points) is candidates
+            L = c + 1
+            members = [k]
+            q = nxt[k]
+            while q != k:
+                members.append(q)
+                q = nxt[q]
+            m = min(members)
+            pos = 0
+            q = m
+            while q != k:
+                pos += 1
+                q = nxt[q]
+            dele[k] = (pos % 2 == 0) and not (pos == L - 1 and L % 2 == 1)
+        else:
+            dele[k] = (c < CHAIN_LIMIT) and (c % 2 == 0)
+    return dele
+
+
 def remesh(pos, nxt, prv, lat: Lattice, dxi_min, dxi_max):
     """Keep segment lengths inside [dxi_min, dxi_max] (Sec. II.A; reading R10).
 
     1. Deletion.  Point k is a candidate when its incoming segment
-       (prv[k] -> k) is shorter than dxi_min.  A candidate is deleted unless
-       its predecessor is a candidate too, so no two neighbours go in one
-       pass; the predecessor and successor of a deleted point are joined.
+       (prv[k] -> k) is shorter than dxi_min and the chord prv[k] -> nxt[k]
+       that would replace its two segments is not longer than dxi_max (so a
+       deletion never calls for a new insertion: with the paper's bounds,
+       dxi_max < 2 dxi_min, a split segment has halves below dxi_min, and
+       deleting one of them would recreate the long segment every pass).
+       Along each run of consecutive
+       candidates every other one is deleted (see _deletion_flags), so no
+       two neighbours go in one pass; the predecessor and successor of a
+       deleted point are joined.
     2. Insertion, on the joined loops.  Every segment j -> nxt[j] longer than
        dxi_max gets one new point at its midpoint (nearest image, wrapped),
        appended after the old points in ascending j.
@@ -56,10 +102,9 @@ def remesh(pos, nxt, prv, lat: Lattice, dxi_min, dxi_max):
     cand = np.zeros(N, dtype=bool)
     for k in range(N):
         d = min_image((pos[k] - pos[prv[k]])[None, :], lat)[0]
-        cand[k] = _sq(d) < mn2
-    dele = np.zeros(N, dtype=bool)
-    for k in range(N):
-        dele[k] = cand[k] and not cand[prv[k]]
+        chord = min_image((pos[nxt[k]] - pos[prv[k]])[None, :], lat)[0]
+        cand[k] = (_sq(d) < mn2) and (_sq(chord) <= mx2)
+    dele = _deletion_flags(cand, nxt, prv)
     for k in range(N):
         if dele[k]:
             p, n = prv[k], nxt[k]

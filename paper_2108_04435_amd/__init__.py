@@ -277,8 +277,8 @@ class Run:
         self._check(self.lib.vlb_get_step(self.h, ctypes.byref(s)))
         return int(s.value)
 
-    def set_timing(self, on=True):
-        self._check(self.lib.vlb_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on=True, reserve=0):
+        self._check(self.lib.vlb_set_timing(self.h, (max(1, int(reserve)) if on else 0)))
 
     def timing(self, cls):
         ms = ctypes.c_double(0)

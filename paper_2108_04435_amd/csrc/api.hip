@@ -190,20 +190,33 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
 
 namespace vlb {
 
+// Events come from a pool filled by vlb_set_timing, so that timing a run
+// creates no events inside the timed region (the pool grows if it runs dry).
+static hipEvent_t take_event(Run& r) {
+  if (!r.ev_pool.empty()) {
+    hipEvent_t e = r.ev_pool.back();
+    r.ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
 void time_begin(Run& r, int cls, hipEvent_t* b) {
   *b = nullptr;
+  (void)cls;
   if (!r.timing) return;
-  hipEvent_t e0;
-  if (hipEventCreate(&e0) != hipSuccess) return;
+  hipEvent_t e0 = take_event(r);
+  if (!e0) return;
   hipEventRecord(e0, r.stream);
   *b = e0;
-  (void)cls;
 }
 
 void time_end(Run& r, int cls, hipEvent_t b) {
   if (!r.timing || !b) return;
-  hipEvent_t e1;
-  if (hipEventCreate(&e1) != hipSuccess) return;
+  hipEvent_t e1 = take_event(r);
+  if (!e1) return;
   hipEventRecord(e1, r.stream);
   r.ev_used[cls].emplace_back(b, e1);
 }
@@ -212,14 +225,21 @@ void time_end(Run& r, int cls, hipEvent_t b) {
 
 namespace {
 
-void drop_events(Run& r) {
+// Return recorded events to the pool.
+void recycle_events(Run& r) {
   for (int c = 0; c < 2; ++c) {
     for (auto& p : r.ev_used[c]) {
-      hipEventDestroy(p.first);
-      hipEventDestroy(p.second);
+      r.ev_pool.push_back(p.first);
+      r.ev_pool.push_back(p.second);
     }
     r.ev_used[c].clear();
   }
+}
+
+void drop_events(Run& r) {
+  recycle_events(r);
+  for (hipEvent_t e : r.ev_pool) hipEventDestroy(e);
+  r.ev_pool.clear();
 }
 
 // wrap as in the kernels: periodic into [0, L), walls mirrored
@@ -512,8 +532,14 @@ int vlb_set_timing(vlb_run* h, int32_t enable) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   Run& r = h->r;
   HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
-  drop_events(r);
+  recycle_events(r);
   r.timing = enable != 0;
+  // enable > 1 pre-creates that many events
+  while (enable > 1 && (int64_t)r.ev_pool.size() < enable) {
+    hipEvent_t e = nullptr;
+    HIP_OR_FAIL(h, hipEventCreate(&e));
+    r.ev_pool.push_back(e);
+  }
   r.last_nodes = 0;
   r.last_pairs = 0;
   HIP_OR_FAIL(h, hipMemsetAsync(r.cnt + 16, 0, 8 * sizeof(int32_t), r.stream));

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   if (j0 >= n) return;
   const int j = j0 + threadIdx.x;
   const bool valid = j < n;
-  const int per = (((n + S - 1) / S) + kTile - 1) / kTile * kTile;
+  const int per = (n + S - 1) / S;
   const int kb = blockIdx.y * per;
   const int ke = min(n, kb + per);
   const uint32_t xt = valid ? X[j] : 0u;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   if (j0 >= n) return;
   const int j = j0 + threadIdx.x;
   const bool valid = j < n;
-  const int per = (((n + S - 1) / S) + kTile - 1) / kTile * kTile;
+  const int per = (n + S - 1) / S;
   const int kb = blockIdx.y * per;
   const int ke = min(n, kb + per);
   const uint32_t xt = valid ? X[j] : 0u;

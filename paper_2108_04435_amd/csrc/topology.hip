@@ -1,8 +1,9 @@
 // Filament topology (paper Sec. II.A: segment lengths kept between dxi_min
 // and dxi_max; Sec. II.A / III.B: legs of two vortices exchanged when they
 // come within the resolution), made data-parallel and deterministic:
-//  * remeshing: a point whose incoming segment is shorter than dxi_min is
-//    deleted unless its predecessor is also such a point; every remaining
+//  * remeshing: of the points whose incoming segment is shorter than
+//    dxi_min and whose removal leaves a chord no longer than dxi_max, every
+//    other one along each run is deleted; every remaining
 //    segment longer than dxi_max gets its midpoint, appended after the old
 //    points in ascending segment order;
 //  * reconnection: candidate pairs (i < j, more than two links apart,
@@ -98,21 +99,55 @@ __global__ void k_reset_stats(int32_t* cnt) {
   }
 }
 
-__global__ void k_rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ prv,
-                          const int32_t* __restrict__ cnt, long long nc, TopoGeom tg, double mn2,
+// Deletion candidate: incoming segment shorter than dxi_min, and the chord
+// that would replace the point's two segments not longer than dxi_max.
+__global__ void k_rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                          const int32_t* __restrict__ prv, const int32_t* __restrict__ cnt,
+                          long long nc, TopoGeom tg, double mn2, double mx2,
                           int32_t* __restrict__ cand) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cnt[0]) return;
-  double d[3];
+  double d[3], c[3];
   sep(pos, nc, prv[j], j, tg, d);
-  cand[j] = sq3(d) < mn2 ? 1 : 0;
+  sep(pos, nc, prv[j], nxt[j], tg, c);
+  cand[j] = (sq3(d) < mn2 && sq3(c) <= mx2) ? 1 : 0;
 }
 
-__global__ void k_rm_del(const int32_t* __restrict__ prv, int32_t* __restrict__ cnt,
-                         const int32_t* __restrict__ cand, int32_t* __restrict__ del) {
+// Along each run of consecutive deletion candidates every other point is
+// deleted: candidate j goes when the number c of candidates directly before
+// it (walking back, at most kChainLimit) is even and below the limit; a
+// loop made only of candidates is counted from its lowest index and keeps
+// its last point when its length is odd.  No two neighbours are deleted.
+constexpr int kChainLimit = 32;
+
+__global__ void k_rm_del(const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
+                         int32_t* __restrict__ cnt, const int32_t* __restrict__ cand,
+                         int32_t* __restrict__ del) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= cnt[0]) return;
-  const int dd = (cand[j] && !cand[prv[j]]) ? 1 : 0;
+  int dd = 0;
+  if (cand[j]) {
+    int c = 0, p = prv[j];
+    while (c < kChainLimit && cand[p] && p != j) {
+      ++c;
+      p = prv[p];
+    }
+    if (p == j) {
+      const int L = c + 1;
+      int m = j, tm = 0, q = j;
+      for (int t = 1; t < L; ++t) {
+        q = nxt[q];
+        if (q < m) {
+          m = q;
+          tm = t;
+        }
+      }
+      const int pos = (L - tm) % L;
+      dd = ((pos & 1) == 0 && !(pos == L - 1 && (L & 1))) ? 1 : 0;
+    } else {
+      dd = (c < kChainLimit && (c & 1) == 0) ? 1 : 0;
+    }
+  }
   del[j] = dd;
   if (dd) atomicAdd(&cnt[3], 1);
 }
@@ -457,8 +492,8 @@ hipError_t topo_update(Run& r) {
   if (r.vor.remesh) {
     const double mn2 = r.vor.dxi_min * r.vor.dxi_min;
     const double mx2 = r.vor.dxi_max * r.vor.dxi_max;
-    hipLaunchKernelGGL(k_rm_cand, dim3(nb), dim3(256), 0, r.stream, r.pos, r.prv, r.cnt, r.ncap, tg, mn2, r.flag_a);
-    hipLaunchKernelGGL(k_rm_del, dim3(nb), dim3(256), 0, r.stream, r.prv, r.cnt, r.flag_a, del);
+    hipLaunchKernelGGL(k_rm_cand, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt, r.ncap, tg, mn2, mx2, r.flag_a);
+    hipLaunchKernelGGL(k_rm_del, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, r.flag_a, del);
     hipLaunchKernelGGL(k_rm_relink, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, del);
     hipLaunchKernelGGL(k_rm_insmark, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap, tg, mx2, del, r.scan_a);
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 2);

@@ -78,14 +78,41 @@ def test_no_two_neighbours_deleted():
            (11.7, 10.0, 10.0), (11.7, 10.9, 10.0), (10.9, 10.9, 10.0), (10.0, 10.9, 10.0)]
     pos, nxt, prv = _loop(pts)
     p2, n2, q2, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)
-    # candidates 1, 2, 3 (incoming segments 0.3 long); only 1 is deleted
+    # incoming segments of 1, 2, 3 are 0.3 long; 3 is no candidate because
+    # dropping it would leave the chord 10.6 -> 11.7 = 1.1 > dxi_max; of the
+    # run (1, 2) every other one goes: only 1, never two neighbours
     assert nd == 1
+    np.testing.assert_allclose(p2[1], [10.6, 10.0, 10.0])
+
+
+def test_deletion_never_forces_insertion():
+    # a split segment: halves 0.5 < dxi_min, but the merged chord 1.0 >
+    # dxi_max, so nothing is deleted and the split is stable
+    pts = [(10.0, 10.0, 10.0), (10.9, 10.0, 10.0), (11.4, 10.0, 10.0), (11.9, 10.0, 10.0),
+           (11.9, 10.9, 10.0), (11.0, 10.9, 10.0), (10.1, 10.9, 10.0)]
+    pos, nxt, prv = _loop(pts)
+    p2, n2, q2, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)
+    assert nd == 0 and ni == 0
+    np.testing.assert_array_equal(p2, pos)
+
+
+def test_all_candidate_loop_thinned():
+    # a loop of 7 points 0.3 apart: all candidates; positions 0, 2, 4 from
+    # the lowest index go, the last (6) stays because 7 is odd
+    th = 2 * np.pi * np.arange(7) / 7
+    R = 0.3 / (2 * np.sin(np.pi / 7))
+    pts = np.stack([10 + R * np.cos(th), 10 + R * np.sin(th), np.full(7, 10.0)], axis=1)
+    pos, nxt, prv = _loop(pts)
+    cand = np.ones(7, dtype=bool)
+    dele = topology._deletion_flags(cand, nxt, prv)
+    assert dele.tolist() == [True, False, True, False, True, False, False]
 
 
 def test_remesh_keeps_links_consistent():
-    pos, nxt = wl.random_rings(9, 20, 3.0, 6.0, (32, 32, 32), (False,) * 3, 0.95)
+    # dense rings (spacing <= 0.5: deletions) with noise (long segments: insertions)
+    pos, nxt = wl.random_rings(9, 20, 3.0, 6.0, (32, 32, 32), (False,) * 3, 0.5)
     rng = np.random.default_rng(9)
-    pos = pos + 0.25 * rng.standard_normal(pos.shape)
+    pos = pos + 0.2 * rng.standard_normal(pos.shape)
     pos = vfm.wrap_positions(pos, LAT)
     prv = coupled.prev_from_next(nxt)
     p2, n2, q2, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)

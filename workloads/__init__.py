@@ -48,24 +48,66 @@ def random_unit(rng):
     return v / np.linalg.norm(v)
 
 
-def random_rings(seed, n_rings, r_lo, r_hi, dims, walls, dxi_max, margin=1.0):
+def _too_close(grid, cell, pts, dims, walls, min_sep):
+    """Any already placed point within min_sep of one of ``pts``?"""
+    for p in pts:
+        base = np.floor(p / cell).astype(int)
+        for off in np.ndindex(3, 3, 3):
+            key = []
+            for a in range(3):
+                k = base[a] + off[a] - 1
+                n = int(math.ceil(dims[a] / cell))
+                if not walls[a]:
+                    k %= n
+                key.append(k)
+            for q in grid.get(tuple(key), ()):
+                d = q - p
+                for a in range(3):
+                    if not walls[a]:
+                        d[a] -= dims[a] * round(d[a] / dims[a])
+                if d @ d < min_sep * min_sep:
+                    return True
+    return False
+
+
+def random_rings(seed, n_rings, r_lo, r_hi, dims, walls, dxi_max, margin=1.0, min_sep=0.0,
+                 max_tries=200):
     """``n_rings`` rings with radii U[r_lo, r_hi], normals uniform on the
     sphere, centres uniform (kept a radius + margin away from walls);
-    ring spacing 2 pi R / ceil(2 pi R / dxi_max) <= dxi_max."""
+    ring spacing 2 pi R / ceil(2 pi R / dxi_max) <= dxi_max.  With
+    ``min_sep`` > 0 a ring is redrawn while one of its points lies closer
+    than min_sep to a point of an earlier ring (no near-intersections at
+    the start)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     loops = []
+    grid = {}
+    cell = max(min_sep, 1e-9)
     for _ in range(n_rings):
-        R = rng.uniform(r_lo, r_hi)
-        c = np.empty(3)
-        for a in range(3):
-            if walls[a]:
-                lo, hi = R + margin - 0.5, dims[a] - 0.5 - R - margin
-                c[a] = rng.uniform(lo, hi) if hi > lo else 0.5 * (dims[a] - 1)
-            else:
-                c[a] = rng.uniform(0.0, dims[a])
-        nrm = random_unit(rng)
-        npts = int(math.ceil(2.0 * math.pi * R / dxi_max))
-        loops.append(ring(c, R, nrm, npts, phase=rng.uniform(0.0, 1.0)))
+        for _try in range(max_tries):
+            R = rng.uniform(r_lo, r_hi)
+            c = np.empty(3)
+            for a in range(3):
+                if walls[a]:
+                    lo, hi = R + margin - 0.5, dims[a] - 0.5 - R - margin
+                    c[a] = rng.uniform(lo, hi) if hi > lo else 0.5 * (dims[a] - 1)
+                else:
+                    c[a] = rng.uniform(0.0, dims[a])
+            nrm = random_unit(rng)
+            npts = int(math.ceil(2.0 * math.pi * R / dxi_max))
+            lp = ring(c, R, nrm, npts, phase=rng.uniform(0.0, 1.0))
+            if min_sep <= 0:
+                break
+            wrapped = lp[0].copy()
+            for a in range(3):
+                if not walls[a]:
+                    wrapped[:, a] %= dims[a]
+            if not _too_close(grid, cell, wrapped, dims, walls, min_sep):
+                break
+        loops.append(lp)
+        if min_sep > 0:
+            for p in wrapped:
+                key = tuple(int(k) for k in np.floor(p / cell))
+                grid.setdefault(key, []).append(p)
     return concat_loops(loops)
 
 
@@ -132,15 +174,17 @@ COUNTERFLOW_G = 28.45 * 0.1 * 0.02 / (64.0 * 64.0)
 def config_counterflow(precision="f32", n_rings=200, nz=256, nxy=64, seed=2):
     """Counterflow channel: 64x64x256, bounce-back walls on x and y, periodic
     z, Guo body force along z for a mean v_n of about 0.02, 200 rings with
-    R ~ U[4, 12], remeshing spacing 1.0 (dxi_min = 0.737 keeps the paper's
-    0.70/0.95 ratio), mass balance on z, 1000 steps."""
+    R ~ U[4, 12] placed at least 2 apart, remeshing spacing 1.0
+    (dxi_min = 0.737 keeps the paper's 0.70/0.95 ratio), reconnection (part
+    of the filament model), mass balance on z, 1000 steps."""
     lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(True, True, False),
                          body_force=(0.0, 0.0, COUNTERFLOW_G * (64.0 / nxy) ** 2),
                          precision=precision)
     vor = vortex_preset(dxi_max=1.0, dxi_min=0.70 / 0.95, reconnect_dist=1.0,
-                        mass_balance=True)
+                        reconnect=True, mass_balance=True)
     rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.02), 0.0)
-    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (nxy, nxy, nz), (True, True, False), 1.0)
+    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (nxy, nxy, nz), (True, True, False), 1.0,
+                            min_sep=2.0)
     return dict(name="counterflow_64x64x256", lattice=lat, vortex=vor, rho=rho, u=u,
                 pos=pos, nxt=nxt, steps=1000)
 
@@ -153,7 +197,8 @@ def config_heater(precision="f32", n_rings=1500, nxy=128, nz=512, seed=3):
                          plane_hi=True, plane_u=(0.0, 0.0, 0.03), precision=precision)
     vor = vortex_preset(reconnect=True, mass_balance=True)
     rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.03), 0.0)
-    pos, nxt = random_rings(seed, n_rings, 3.0, 7.6, (nxy, nxy, nz), (True, True, False), 0.95)
+    pos, nxt = random_rings(seed, n_rings, 3.0, 7.6, (nxy, nxy, nz), (True, True, False), 0.95,
+                            min_sep=1.5)
     return dict(name="heater_128x128x512", lattice=lat, vortex=vor, rho=rho, u=u,
                 pos=pos, nxt=nxt, steps=2000)
 
@@ -164,6 +209,7 @@ def config_tangle(precision="f16", n=256, n_rings=2000, seed=4):
     lat = lattice_preset(n, n, n, tau=0.8, precision=precision)
     vor = vortex_preset(mass_balance=True)
     rho, u = velocity_field(seed, (n, n, n), (0.0, 0.0, 0.02), 1e-4)
-    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (n, n, n), (False, False, False), 0.95)
+    pos, nxt = random_rings(seed, n_rings, 4.0, 12.0, (n, n, n), (False, False, False), 0.95,
+                            min_sep=1.5)
     return dict(name="tangle_256", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
                 steps=100)

@@ -71,7 +71,7 @@ def traffic_record(kernel_src):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, n_sample=4096):
+def cpu_baseline(cfg, n_sample=8192):
     """Oracle (plain FP64 numpy) on the host: one full LBM update of the
     lattice plus the Biot-Savart sum for a sample of targets against all
     segments, scaled to one coupled step (4 Biot-Savart evaluations)."""

@@ -103,8 +103,7 @@ size_t layout(Run& r, char* base) {
   r.bsX = (uint32_t*)B.take(3 * nc * sizeof(uint32_t));
   r.bsD = B.take(3 * nc * fe);
   size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
-  const size_t mb = (size_t)r.geom.nz * 32 * sizeof(double);
-  r.bsP = B.take(pbytes > mb ? pbytes : mb);
+  r.bsP = B.take(pbytes);
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
   r.keys_a = (uint32_t*)B.take(nc * sizeof(uint32_t));
   r.keys_b = (uint32_t*)B.take(nc * sizeof(uint32_t));
@@ -117,12 +116,17 @@ size_t layout(Run& r, char* base) {
     r.rc_i = (int32_t*)B.take(rc * sizeof(int32_t));
     r.rc_j = (int32_t*)B.take(rc * sizeof(int32_t));
     r.rc_idx_a = (int32_t*)B.take(rc * sizeof(int32_t));
-    r.rc_idx_b = (int32_t*)B.take(rc * sizeof(int32_t));
     r.rc_key_a = (uint64_t*)B.take(rc * sizeof(uint64_t));
-    r.rc_key_b = (uint64_t*)B.take(rc * sizeof(uint64_t));
-    r.rc_sort_tmp_bytes = rc_sort_tmp_bytes(rc);
-    r.rc_sort_tmp = B.take(r.rc_sort_tmp_bytes);
+    r.rc_best = (uint64_t*)B.take((nc + 1) * sizeof(uint64_t));
+    r.rc_bidx = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   }
+  r.ub = B.take(3 * cells * fe);
+  {
+    int bx, by, nbx, nby;
+    moment_tiles(r.geom, bx, by, nbx, nby);
+    r.part = (double*)B.take((size_t)nbx * nby * r.geom.nz * sizeof(double));
+  }
+  r.bins = (int32_t*)B.take((size_t)r.nbins_table * sizeof(int32_t));
   return (B.off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -170,6 +174,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   const unsigned long long ext = (unsigned long long)(n[0] + g.wall[0]) * (n[1] + g.wall[1]) * (n[2] + g.wall[2]);
   r.key_bits = bits_for(ext);  // pad key 2^bits - 1 >= ext
   if (r.key_bits > 32) r.key_bits = 32;
+  r.nbins_table = (long long)ext;
   // reconnection bins of edge >= reconnect distance
   if (vor->reconnect) {
     const double h0 = vor->reconnect_dist * (1.0 + 1e-9);
@@ -183,6 +188,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
     }
     r.bin_bits = bits_for(tot);
     if (r.bin_bits > 32) r.bin_bits = 32;
+    if ((long long)tot > r.nbins_table) r.nbins_table = (long long)tot;
   }
 }
 
@@ -330,6 +336,7 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   hipError_t e = hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r.bins, 0xFF, (size_t)r.nbins_table * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r.stream);
   if (e != hipSuccess) {
     std::string m = std::string("initialising the workspace: ") + hipGetErrorString(e);
@@ -398,13 +405,14 @@ namespace {
 
 int one_step(vlb_run* h) {
   Run& r = h->r;
-  if (r.vor.mass_balance) HIP_OR_FAIL(h, lbm_mass_balance(r));
   if (!r.has_points) {  // never seeded: the normal fluid alone
     HIP_OR_FAIL(h, lbm_step(r));
     r.step += 1;
     r.last_nodes += r.cells;
     return VLB_OK;
   }
+  // bare velocity field and mass-balance superflow of f^n
+  HIP_OR_FAIL(h, lbm_moments(r));
   // filament RK4: stage positions s^n (pos) -> ya -> yb -> ya -> pos
   double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
@@ -488,7 +496,7 @@ int vlb_read_filaments(vlb_run* h, int64_t cap, double* xyz, int32_t* next, int6
 int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, double* force) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   Run& r = h->r;
-  if (r.vor.mass_balance) HIP_OR_FAIL(h, lbm_mass_balance(r));
+  HIP_OR_FAIL(h, lbm_moments(r));
   HIP_OR_FAIL(h, bs_prep(r, r.pos));
   HIP_OR_FAIL(h, bs_sum(r, r.pos));
   HIP_OR_FAIL(h, fil_finalize(r, 1, r.pos, r.ya, 1));

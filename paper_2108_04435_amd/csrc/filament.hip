@@ -17,9 +17,7 @@ namespace vlb {
 namespace {
 
 struct FinArgs {
-  const void* pops;
-  int prec;
-  int parity;
+  const void* ub;  // bare normal-fluid velocity field of the step
   Geom g;
   const double* Y;
   double* Ynext;
@@ -74,12 +72,11 @@ __device__ inline double wrap_coord(double x, double L, int periodic) {
   return x;
 }
 
-// Bare normal-fluid velocity at a point: delta_2pt weights on the 8
-// surrounding nodes; nodes beyond a wall carry zero velocity.
-template <class S>
-__device__ void interp_vn(const S* M, const Geom& g, int parity, double px, double py, double pz,
-                          double v[3]) {
-  using T = typename Store<S>::T;
+// Normal-fluid velocity at a point: delta_2pt weights on the 8 surrounding
+// nodes of the step's bare-velocity field; nodes beyond a wall carry zero.
+template <class UT>
+__device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, double py,
+                          double pz, double v[3]) {
   const double b[3] = {floor(px), floor(py), floor(pz)};
   const double fr[3] = {px - b[0], py - b[1], pz - b[2]};
   const int n[3] = {g.nx, g.ny, g.nz};
@@ -101,28 +98,14 @@ __device__ void interp_vn(const S* M, const Geom& g, int parity, double px, doub
       node[a] = c;
     }
     if (ghost) continue;
-    double ux, uy, uz;
-    if (is_plane(g, node[2])) {
-      ux = g.plane_u[0];
-      uy = g.plane_u[1];
-      uz = g.plane_u[2];
-    } else {
-      T d[19];
-      load_node<S>(M, g, parity, node[0], node[1], node[2], d);
-      T drho, jx, jy, jz;
-      moments<T>(d, drho, jx, jy, jz);
-      const double rho = 1.0 + (double)drho;
-      ux = (double)jx / rho;
-      uy = (double)jy / rho;
-      uz = (double)jz / rho;
-    }
-    v[0] += w * ux;
-    v[1] += w * uy;
-    v[2] += w * uz;
+    const long long c = ((long long)node[2] * g.ny + node[1]) * g.nx + node[0];
+    v[0] += w * (double)ub[c];
+    v[1] += w * (double)ub[g.cells + c];
+    v[2] += w * (double)ub[2 * g.cells + c];
   }
 }
 
-template <class S, class PT>
+template <class UT, class PT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = A.cnt[0];
@@ -174,12 +157,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
 
   // normal-fluid velocity at the point
   double vn[3];
-  if (A.prec == VLB_F64)
-    interp_vn<double>((const double*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
-  else if (A.prec == VLB_F32)
-    interp_vn<float>((const float*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
-  else
-    interp_vn<__half>((const __half*)A.pops, g, A.parity, p[0], p[1], p[2], vn);
+  interp_vn<UT>((const UT*)A.ub, g, p[0], p[1], p[2], vn);
 
   // Schwarz equation of motion (Sec. II.A, Eq. E of M)
   const double w[3] = {vn[0] - vs[0], vn[1] - vs[1], vn[2] - vs[2]};
@@ -273,17 +251,15 @@ __global__ void k_spread_keys(const double* __restrict__ pos, const int32_t* __r
   vals[j] = j;
 }
 
-// first index in [0, n) with keys[idx] >= k
-__device__ inline int lower_bound_u32(const uint32_t* keys, int n, uint32_t k) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (keys[mid] < k)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
+// Dense bin table: bins[key] = first sorted entry of that bin, -1 if empty.
+// Marked after each sort and cleared again after use, so it is all -1
+// between uses.
+__global__ void k_bin_mark(const uint32_t* __restrict__ skey, const int32_t* __restrict__ cnt,
+                           int32_t* __restrict__ bins, int value_is_index) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cnt[0]) return;
+  if (r > 0 && skey[r - 1] == skey[r]) return;
+  bins[skey[r]] = value_is_index ? r : -1;
 }
 
 template <class FT>
@@ -300,6 +276,7 @@ __global__ void k_spread_clear(FT* __restrict__ F, long long cells, const int32_
 
 template <class FT>
 __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
+                                const int32_t* __restrict__ bins,
                                 const double* __restrict__ pos, const double* __restrict__ gpt,
                                 int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
                                 long long cells, FT* __restrict__ F, int32_t* __restrict__ touched) {
@@ -354,11 +331,13 @@ __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t
       lo[q] = hi[q] = 0;
       if (!ok) continue;
       const uint32_t k = (uint32_t)(((long long)c[2] * sg.ext[1] + c[1]) * sg.ext[0] + c[0]);
-      const int l = lower_bound_u32(skey, n, k);
-      if (l < n && skey[l] == k) {
+      const int l = bins[k];
+      if (l >= 0) {
         if (k < me) owner = false;
+        int h = l + 1;
+        while (h < n && skey[h] == k) ++h;
         lo[q] = l;
-        hi[q] = lower_bound_u32(skey, n, k + 1);
+        hi[q] = h;
       }
     }
     if (!owner) {
@@ -407,6 +386,12 @@ SpreadGeom spread_geom(const Run& r) {
 
 }  // namespace
 
+hipError_t bins_mark(Run& r, int set) {
+  hipLaunchKernelGGL(k_bin_mark, dim3(nblocks(r.ncap, 256)), dim3(256), 0, r.stream, r.keys_b, r.cnt,
+                     r.bins, set);
+  return hipGetLastError();
+}
+
 size_t sort_tmp_bytes(long long n) {
   size_t bytes = 0;
   rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
@@ -417,9 +402,7 @@ size_t sort_tmp_bytes(long long n) {
 
 hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only) {
   FinArgs A;
-  A.pops = r.pops;
-  A.prec = r.prec;
-  A.parity = r.parity;
+  A.ub = r.ub;
   A.g = r.geom;
   A.Y = Y;
   A.Ynext = Ynext;
@@ -450,8 +433,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   const int nb = nblocks(r.ncap, 256);
   switch (r.prec) {
     case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;
-    case VLB_F32: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
-    default: hipLaunchKernelGGL((k_finalize<__half, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
+    default: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
   }
   return hipGetLastError();
 }
@@ -477,12 +459,14 @@ hipError_t fil_spread(Run& r) {
   e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
                                 (unsigned int)r.ncap, 0u, (unsigned int)r.key_bits, r.stream);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.cnt, r.bins, 1);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
-                       r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
+                       r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
   else
     hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
-                       r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
+                       r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
+  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.cnt, r.bins, 0);
   return hipGetLastError();
 }
 

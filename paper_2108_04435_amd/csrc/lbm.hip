@@ -152,33 +152,42 @@ __global__ void k_read_force(const T* __restrict__ F, long long n, double* out) 
   if (c < n) out[c] = F ? (double)F[c] : 0.0;
 }
 
-// Mass-balance superflow (Sec. III.C, Eq. mass cons): partial sums of the
-// bare u_z over parts of each z slice, then one value per slice.
-template <class S>
-__global__ __launch_bounds__(256) void k_slice_partial(const S* __restrict__ M, Geom g, int parity,
-                                                       int nparts, double* __restrict__ part) {
-  const int z = blockIdx.x / nparts;
-  const int p = blockIdx.x % nparts;
-  const long long area = (long long)g.nx * g.ny;
-  const long long per = (area + nparts - 1) / nparts;
-  const long long k0 = p * per;
-  const long long k1 = min(area, k0 + per);
-  double acc = 0.0;
-  for (long long k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    const int x = (int)(k % g.nx);
-    const int y = (int)(k / g.nx);
+// Bare normal-fluid velocity u_b = sum(c f)/sum(f) of every node (velocity
+// planes applied), written once per step for the interpolation onto the
+// filaments, fused with the per-block partial sums of u_z that the
+// mass-balance superflow needs (Sec. III.C, Eq. mass cons).  Blocks tile one
+// z slice each, so a slice's partials are contiguous.
+template <class S, class UT>
+__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ M, Geom g, int parity,
+                                                int nbx, int nby, UT* __restrict__ ub,
+                                                double* __restrict__ part) {
+  const int t = blockIdx.x;  // slice-major: t = (z * nby + by) * nbx + bx
+  const int bxi = t % nbx;
+  const int rr = t / nbx;
+  const int byi = rr % nby;
+  const int z = rr / nby;
+  const int x = bxi * blockDim.x + threadIdx.x;
+  const int y = byi * blockDim.y + threadIdx.y;
+  double uzv = 0.0;
+  if (x < g.nx && y < g.ny) {
     double rho, ux, uy, uz;
     node_rho_u<S>(M, g, parity, x, y, z, rho, ux, uy, uz);
-    acc += uz;
+    const long long c = ((long long)z * g.ny + y) * g.nx + x;
+    ub[c] = (UT)ux;
+    ub[g.cells + c] = (UT)uy;
+    ub[2 * g.cells + c] = (UT)uz;
+    uzv = uz;
   }
   __shared__ double red[256];
-  red[threadIdx.x] = acc;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nt = blockDim.x * blockDim.y;
+  red[tid] = uzv;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if (tid < s && tid + s < nt) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (tid == 0) part[t] = red[0];
 }
 
 __global__ void k_slice_final(const double* __restrict__ part, int nz, int nparts, double scale,
@@ -186,7 +195,7 @@ __global__ void k_slice_final(const double* __restrict__ part, int nz, int npart
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= nz) return;
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[z * nparts + p];
+  for (int p = 0; p < nparts; ++p) s += part[(long long)z * nparts + p];
   Vs[z] = scale * s;
 }
 
@@ -287,32 +296,34 @@ hipError_t lbm_read_force(Run& r, double* out) {
   return hipGetLastError();
 }
 
-int slice_parts(const Geom& g) {
-  const long long area = (long long)g.nx * g.ny;
-  long long p = area / 2048;
-  if (p < 1) p = 1;
-  if (p > 32) p = 32;
-  return (int)p;
+void moment_tiles(const Geom& g, int& bx, int& by, int& nbx, int& nby) {
+  bx = g.nx < 64 ? g.nx : 64;
+  by = 256 / bx;
+  nbx = (g.nx + bx - 1) / bx;
+  nby = (g.ny + by - 1) / by;
 }
 
-hipError_t lbm_mass_balance(Run& r) {
+hipError_t lbm_moments(Run& r) {
   const Geom& g = r.geom;
-  const int np = slice_parts(g);
-  double* part = (double*)r.bsP;  // reuse the Biot-Savart partial buffer (free at this point)
-  const int nb = g.nz * np;
+  int bx, by, nbx, nby;
+  moment_tiles(g, bx, by, nbx, nby);
+  const int nb = nbx * nby * g.nz;
+  dim3 blk(bx, by);
   switch (r.prec) {
     case VLB_F64:
-      hipLaunchKernelGGL(k_slice_partial<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.pops, g, r.parity, np, part);
+      hipLaunchKernelGGL((k_moments<double, double>), dim3(nb), blk, 0, r.stream, (const double*)r.pops, g, r.parity, nbx, nby, (double*)r.ub, r.part);
       break;
     case VLB_F32:
-      hipLaunchKernelGGL(k_slice_partial<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.pops, g, r.parity, np, part);
+      hipLaunchKernelGGL((k_moments<float, float>), dim3(nb), blk, 0, r.stream, (const float*)r.pops, g, r.parity, nbx, nby, (float*)r.ub, r.part);
       break;
     default:
-      hipLaunchKernelGGL(k_slice_partial<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, g, r.parity, np, part);
+      hipLaunchKernelGGL((k_moments<__half, float>), dim3(nb), blk, 0, r.stream, (const __half*)r.pops, g, r.parity, nbx, nby, (float*)r.ub, r.part);
       break;
   }
-  const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
-  hipLaunchKernelGGL(k_slice_final, dim3(blocks_for(g.nz, 256)), dim3(256), 0, r.stream, part, g.nz, np, scale, r.Vs);
+  if (r.vor.mass_balance) {
+    const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
+    hipLaunchKernelGGL(k_slice_final, dim3(blocks_for(g.nz, 256)), dim3(256), 0, r.stream, r.part, g.nz, nbx * nby, scale, r.Vs);
+  }
   return hipGetLastError();
 }
 

@@ -8,8 +8,8 @@
 //    points in ascending segment order;
 //  * reconnection: candidate pairs (i < j, more than two links apart,
 //    closer than the reconnection distance, exchange not lengthening the
-//    line) are found through a cell binning, sorted by (d^2, i, j) and
-//    applied greedily, each point at most once;
+//    line) are found through a cell binning and taken greedily in ascending
+//    (d^2, i, j), each point at most once;
 //  * loops with fewer than min_loop_pts points are removed, and the point
 //    arrays are compacted in index order.
 // All decisions compare FP64 squared distances summed as dx*dx + dy*dy +
@@ -62,34 +62,44 @@ __device__ inline double wrap1(double x, double L, int periodic) {
   return x;
 }
 
-// ---- single-workgroup exclusive scan of n ints (n read from *np)
+// ---- single-workgroup exclusive scan of n ints (n read from *np): tiles
+// of 1024 consecutive values (coalesced), wave prefix sums with shuffles,
+// wave totals combined in LDS, a running carry between tiles.
 __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in,
                                                     int32_t* __restrict__ out,
                                                     const int32_t* __restrict__ np,
                                                     int32_t* __restrict__ total) {
-  __shared__ int32_t s[1024];
+  __shared__ int32_t wsum[16];
   const int n = *np;
   const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int b = t * per;
-  const int e = min(n, b + per);
-  int acc = 0;
-  for (int k = b; k < e; ++k) acc += in[k];
-  s[t] = acc;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = (t >= off) ? s[t - off] : 0;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int k = base + t;
+    const int v = k < n ? in[k] : 0;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    s[t] += v;
+    if (w == 0) {
+      int s = lane < 16 ? wsum[lane] : 0;
+      for (int off = 1; off < 16; off <<= 1) {
+        const int y = __shfl_up(s, off, 64);
+        if (lane >= off) s += y;
+      }
+      if (lane < 16) wsum[lane] = s;
+    }
+    __syncthreads();
+    const int wpre = w > 0 ? wsum[w - 1] : 0;
+    if (k < n) out[k] = carry + wpre + x - v;
+    carry += wsum[15];
     __syncthreads();
   }
-  int run = s[t] - acc;  // exclusive prefix of this thread's range
-  for (int k = b; k < e; ++k) {
-    const int v = in[k];
-    out[k] = run;
-    run += v;
-  }
-  if (t == 1023) *total = s[1023];
+  if (t == 0) *total = carry;
 }
 
 __global__ void k_reset_stats(int32_t* cnt) {
@@ -283,18 +293,6 @@ __global__ void k_rc_keys(const double* __restrict__ pos, const int32_t* __restr
   vals[j] = j;
 }
 
-__device__ inline int lower_bound_u32(const uint32_t* keys, int n, uint32_t k) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (keys[mid] < k)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // Offsets of the neighbouring bins along one axis (no duplicates when the
 // periodic axis has fewer than 3 bins).
 __device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
@@ -318,6 +316,7 @@ template <class Fn>
 __device__ inline void rc_visit(int i, const double* __restrict__ pos,
                                 const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
                                 const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
+                                const int32_t* __restrict__ bins,
                                 int n, long long nc, const TopoGeom& tg, const BinGeom& bg,
                                 double d2max, Fn f) {
   const int b[3] = {bin_of(pos[i], bg, 0), bin_of(pos[nc + i], bg, 1), bin_of(pos[2 * nc + i], bg, 2)};
@@ -330,7 +329,8 @@ __device__ inline void rc_visit(int i, const double* __restrict__ pos,
     for (int iy = 0; iy < my; ++iy)
       for (int ix = 0; ix < mx; ++ix) {
         const uint32_t k = (uint32_t)(((long long)oz[iz] * bg.nb[1] + oy[iy]) * bg.nb[0] + ox[ix]);
-        int t = lower_bound_u32(skey, n, k);
+        int t = bins[k];
+        if (t < 0) continue;
         for (; t < n && skey[t] == k; ++t) {
           const int j = sval[t];
           if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
@@ -353,20 +353,22 @@ __device__ inline void rc_visit(int i, const double* __restrict__ pos,
 
 __global__ void k_rc_count(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
                            const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
-                           const int32_t* __restrict__ sval, const int32_t* __restrict__ cnt,
+                           const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
+                           const int32_t* __restrict__ cnt,
                            long long nc, TopoGeom tg, BinGeom bg, double d2max,
                            int32_t* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
   if (i >= n) return;
   int c = 0;
-  rc_visit(i, pos, nxt, prv, skey, sval, n, nc, tg, bg, d2max, [&](int, double) { ++c; });
+  rc_visit(i, pos, nxt, prv, skey, sval, bins, n, nc, tg, bg, d2max, [&](int, double) { ++c; });
   count[i] = c;
 }
 
 __global__ void k_rc_write(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
                            const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
-                           const int32_t* __restrict__ sval, int32_t* __restrict__ cnt,
+                           const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
+                           int32_t* __restrict__ cnt,
                            long long nc, TopoGeom tg, BinGeom bg, double d2max,
                            const int32_t* __restrict__ off, long long rcap,
                            int32_t* __restrict__ ci, int32_t* __restrict__ cj,
@@ -377,7 +379,7 @@ __global__ void k_rc_write(const double* __restrict__ pos, const int32_t* __rest
   if (i >= n || cnt[6] > rcap) return;
   const int o0 = off[i];
   int m = 0;
-  rc_visit(i, pos, nxt, prv, skey, sval, n, nc, tg, bg, d2max, [&](int j, double d2) {
+  rc_visit(i, pos, nxt, prv, skey, sval, bins, n, nc, tg, bg, d2max, [&](int j, double d2) {
     const int at = o0 + m;
     // insertion into the run [o0, at) kept sorted by j
     int p = at;
@@ -396,41 +398,88 @@ __global__ void k_rc_write(const double* __restrict__ pos, const int32_t* __rest
   }
 }
 
-__global__ void k_rc_pad(const int32_t* __restrict__ cnt, long long rcap, uint64_t* __restrict__ ckey,
-                         int32_t* __restrict__ cidx) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= rcap) return;
-  const long long tot = cnt[6];
+// Greedy matching in ascending (d^2, i, j), computed in rounds: a live
+// candidate whose key is the smallest among the live candidates at both of
+// its points is taken (the globally smallest one always is, and no
+// candidate of smaller key can claim its points later), its points are
+// used, and every candidate touching a used point dies.  The set taken is
+// exactly the one of the sequential greedy pass.  Taken exchanges are
+// disjoint, so their link updates do not interact.  One workgroup; values
+// that atomics update are read and written with device-scope atomics.
+__global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
+                                                   int32_t* __restrict__ prv,
+                                                   int32_t* __restrict__ cnt, long long rcap,
+                                                   const int32_t* __restrict__ ci,
+                                                   const int32_t* __restrict__ cj,
+                                                   const uint64_t* __restrict__ ckey,
+                                                   int32_t* __restrict__ live,
+                                                   uint64_t* __restrict__ bkey,
+                                                   int32_t* __restrict__ bidx,
+                                                   int32_t* __restrict__ used) {
+  __shared__ int s_live;
+  __shared__ int s_taken;
+  const int tot = cnt[6];
   if (tot > rcap) return;
-  if (t >= tot) {
-    ckey[t] = ~(uint64_t)0;
-    cidx[t] = (int32_t)t;
+  const int t = threadIdx.x;
+  for (int c = t; c < tot; c += blockDim.x) live[c] = 1;
+  if (t == 0) s_taken = 0;
+  __syncthreads();
+  for (int round = 0; round <= tot; ++round) {
+    for (int c = t; c < tot; c += blockDim.x)
+      if (live[c]) {
+        __hip_atomic_store(&bkey[ci[c]], ~(uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bkey[cj[c]], ~(uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bidx[ci[c]], 0x7fffffff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bidx[cj[c]], 0x7fffffff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    __syncthreads();
+    for (int c = t; c < tot; c += blockDim.x)
+      if (live[c]) {
+        atomicMin((unsigned long long*)&bkey[ci[c]], (unsigned long long)ckey[c]);
+        atomicMin((unsigned long long*)&bkey[cj[c]], (unsigned long long)ckey[c]);
+      }
+    __syncthreads();
+    for (int c = t; c < tot; c += blockDim.x)
+      if (live[c]) {
+        const uint64_t k = ckey[c];
+        if (__hip_atomic_load(&bkey[ci[c]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k)
+          atomicMin(&bidx[ci[c]], c);
+        if (__hip_atomic_load(&bkey[cj[c]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k)
+          atomicMin(&bidx[cj[c]], c);
+      }
+    __syncthreads();
+    for (int c = t; c < tot; c += blockDim.x)
+      if (live[c]) {
+        const int i = ci[c], j = cj[c];
+        if (__hip_atomic_load(&bidx[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == c &&
+            __hip_atomic_load(&bidx[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == c) {
+          const int a = nxt[i], b = nxt[j];
+          nxt[i] = b;
+          prv[b] = i;
+          nxt[j] = a;
+          prv[a] = j;
+          used[i] = 1;
+          used[j] = 1;
+          live[c] = 0;
+          atomicAdd(&s_taken, 1);
+        }
+      }
+    if (t == 0) s_live = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int c = t; c < tot; c += blockDim.x)
+      if (live[c]) {
+        if (used[ci[c]] || used[cj[c]])
+          live[c] = 0;
+        else
+          ++mine;
+      }
+    if (mine) atomicAdd(&s_live, mine);
+    __syncthreads();
+    if (s_live == 0) break;
+    __syncthreads();
   }
-}
-
-// Greedy application in sorted order (one thread: the sequence matters).
-__global__ void k_rc_greedy(int32_t* __restrict__ nxt, int32_t* __restrict__ prv,
-                            int32_t* __restrict__ cnt, long long rcap,
-                            const int32_t* __restrict__ ci, const int32_t* __restrict__ cj,
-                            const int32_t* __restrict__ sidx, int32_t* __restrict__ used) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const long long tot = cnt[6];
-  if (tot > rcap) return;
-  int nrec = 0;
-  for (long long c = 0; c < tot; ++c) {
-    const int id = sidx[c];
-    const int i = ci[id], j = cj[id];
-    if (used[i] || used[j]) continue;
-    const int a = nxt[i], b = nxt[j];
-    nxt[i] = b;
-    prv[b] = i;
-    nxt[j] = a;
-    prv[a] = j;
-    used[i] = 1;
-    used[j] = 1;
-    ++nrec;
-  }
-  cnt[4] = nrec;
+  if (t == 0) cnt[4] = s_taken;
 }
 
 __global__ void k_set_bound(int32_t* cnt) {
@@ -476,14 +525,6 @@ hipError_t small_and_compact(Run& r, int32_t* del) {
 
 }  // namespace
 
-size_t rc_sort_tmp_bytes(long long n) {
-  size_t bytes = 0;
-  rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                            (int32_t*)nullptr, (int32_t*)nullptr, (unsigned int)n, 0u, 64u,
-                            (hipStream_t)0);
-  return bytes;
-}
-
 hipError_t topo_update(Run& r) {
   const TopoGeom tg = topo_geom(r);
   const int nb = nb_of(r.ncap, 256);
@@ -514,21 +555,19 @@ hipError_t topo_update(Run& r) {
     e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
                                   (unsigned int)r.ncap, 0u, (unsigned int)r.bin_bits, r.stream);
     if (e != hipSuccess) return e;
+    e = bins_mark(r, 1);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rc_count, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
-                       r.vals_b, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
+                       r.vals_b, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
     hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 6);
     hipLaunchKernelGGL(k_rc_write, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
-                       r.vals_b, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i, r.rc_j,
-                       r.rc_key_a, r.rc_idx_a);
-    hipLaunchKernelGGL(k_rc_pad, dim3(nb_of(r.rcap, 256)), dim3(256), 0, r.stream, r.cnt, r.rcap,
-                       r.rc_key_a, r.rc_idx_a);
-    bytes = r.rc_sort_tmp_bytes;
-    e = rocprim::radix_sort_pairs(r.rc_sort_tmp, bytes, r.rc_key_a, r.rc_key_b, r.rc_idx_a,
-                                  r.rc_idx_b, (unsigned int)r.rcap, 0u, 64u, r.stream);
+                       r.vals_b, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i,
+                       r.rc_j, r.rc_key_a, r.rc_idx_a);
+    e = bins_mark(r, 0);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, r.used, r.ncap, 0);
-    hipLaunchKernelGGL(k_rc_greedy, dim3(1), dim3(64), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,
-                       r.rc_i, r.rc_j, r.rc_idx_b, r.used);
+    hipLaunchKernelGGL(k_rc_match, dim3(1), dim3(1024), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,
+                       r.rc_i, r.rc_j, r.rc_key_a, r.rc_idx_a, r.rc_best, r.rc_bidx, r.used);
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, del, r.ncap, 0);
     hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(64), 0, r.stream, r.cnt);
     e = small_and_compact(r, del);

@@ -178,6 +178,10 @@ struct Run {
   void* force = nullptr;  // 3 * cells (double for F64, float otherwise)
   int32_t* touched = nullptr;  // 8 * ncap node indices written by spreading
   double* Vs = nullptr;        // nz slice superflow
+  void* ub = nullptr;          // 3 * cells bare velocity of the current step
+  double* part = nullptr;      // per-block partial sums of u_z
+  int32_t* bins = nullptr;     // dense bin -> first sorted entry table (-1 = empty)
+  long long nbins_table = 0;
 
   // filaments
   double* pos = nullptr;   // 3 * ncap, SoA
@@ -225,12 +229,10 @@ struct Run {
   int bin_bits = 32;
   int32_t* rc_i = nullptr;
   int32_t* rc_j = nullptr;
-  uint64_t* rc_key_a = nullptr;
-  uint64_t* rc_key_b = nullptr;
-  int32_t* rc_idx_a = nullptr;
-  int32_t* rc_idx_b = nullptr;
-  void* rc_sort_tmp = nullptr;
-  size_t rc_sort_tmp_bytes = 0;
+  uint64_t* rc_key_a = nullptr;  // candidate keys (bits of d^2)
+  int32_t* rc_idx_a = nullptr;   // candidate liveness during matching
+  uint64_t* rc_best = nullptr;   // per point: smallest live key
+  int32_t* rc_bidx = nullptr;    // per point: smallest live candidate of that key
   int32_t* used = nullptr;
 
   // staging for host <-> device filament copies
@@ -263,7 +265,8 @@ hipError_t lbm_step(Run& r);
 hipError_t lbm_read_fields(Run& r, double* rho, double* u);
 hipError_t lbm_read_pops(Run& r, double* f);
 hipError_t lbm_read_force(Run& r, double* out);
-hipError_t lbm_mass_balance(Run& r);
+hipError_t lbm_moments(Run& r);
+void moment_tiles(const Geom& g, int& bx, int& by, int& nbx, int& nby);
 
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r, const double* Y);
@@ -277,7 +280,7 @@ hipError_t fil_seed(Run& r, long long n);
 hipError_t topo_update(Run& r);
 
 size_t sort_tmp_bytes(long long n);
-size_t rc_sort_tmp_bytes(long long n);
+hipError_t bins_mark(Run& r, int set);
 
 // timing helpers (api.cpp)
 void time_begin(Run& r, int cls, hipEvent_t* b);

@@ -180,9 +180,30 @@ int vlb_get_step(vlb_run* run, int64_t* step);
 int vlb_set_timing(vlb_run* run, int32_t enable);
 int vlb_get_timing(vlb_run* run, int32_t kernel_class, double* total_ms, int64_t* launches);
 
+/* Average duration of one launch of a kernel class (0 = Biot-Savart pair
+ * sum at the current positions, 1 = LBM collide+stream) over reps >= 1
+ * launches enqueued back to back between two HIP events on the run's
+ * stream.  The Biot-Savart timing leaves the state unchanged; the LBM one
+ * advances the normal fluid by reps updates (force field as last spread).
+ * Synchronises the stream.                                                 */
+int vlb_time_kernel(vlb_run* run, int32_t kernel_class, int32_t reps, double* avg_ms);
+
 /* Algorithmic work of the last step: lattice node updates and Biot-Savart
  * (target, segment) pairs summed over the RK stages.                      */
 int vlb_get_work(vlb_run* run, int64_t* node_updates, int64_t* bs_pairs);
+
+/* Graph-captured steps.  vlb_graph_create records n_steps coupled steps of
+ * the run (n_steps even, so that the population layout returns to the same
+ * AA parity) into an executable HIP graph by stream capture on the run's
+ * stream (which must not be the null stream); nothing is executed.  Each
+ * vlb_graph_launch enqueues the whole graph on the run's stream and
+ * advances the run's step counter by n_steps; it returns VLB_ESTATE if the
+ * run was stepped by an odd number of steps since the capture.  The graph
+ * holds the run's pointers: destroy it before the run.                     */
+typedef struct vlb_graph vlb_graph;
+int vlb_graph_create(vlb_run* run, int64_t n_steps, vlb_graph** out);
+int vlb_graph_launch(vlb_graph* graph);
+int vlb_graph_destroy(vlb_graph* graph);
 
 /* Release the host handle.  The workspace is the caller's to free.         */
 int vlb_destroy(vlb_run* run);

@@ -32,7 +32,8 @@ SYMBOLS = [
     "vlb_query_footprint", "vlb_create_lattice", "vlb_write_fields", "vlb_seed_vortices",
     "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
     "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology", "vlb_get_step",
-    "vlb_set_timing", "vlb_get_timing", "vlb_get_work", "vlb_destroy", "vlb_last_error",
+    "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
+    "vlb_graph_launch", "vlb_graph_destroy", "vlb_destroy", "vlb_last_error",
 ]
 
 
@@ -104,7 +105,11 @@ def load_library(path=None):
     lib.vlb_get_step.argtypes = [vp, ctypes.POINTER(i64)]
     lib.vlb_set_timing.argtypes = [vp, ctypes.c_int32]
     lib.vlb_get_timing.argtypes = [vp, ctypes.c_int32, dp, ctypes.POINTER(i64)]
+    lib.vlb_time_kernel.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp]
     lib.vlb_get_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.vlb_graph_create.argtypes = [vp, i64, ctypes.POINTER(vp)]
+    lib.vlb_graph_launch.argtypes = [vp]
+    lib.vlb_graph_destroy.argtypes = [vp]
     lib.vlb_destroy.argtypes = [vp]
     lib.vlb_last_error.argtypes = [vp]
     lib.vlb_last_error.restype = ctypes.c_char_p
@@ -195,9 +200,26 @@ class Run:
         return t.to(self.device).contiguous()
 
     def close(self):
+        for g in list(getattr(self, "_graphs", {}).values()):
+            self.lib.vlb_graph_destroy(g)
+        self._graphs = {}
         if getattr(self, "h", None):
             self.lib.vlb_destroy(self.h)
             self.h = None
+
+    def graph(self, n_steps):
+        """Executable graph of n_steps (even) coupled steps, cached per size."""
+        if not hasattr(self, "_graphs"):
+            self._graphs = {}
+        if n_steps not in self._graphs:
+            g = ctypes.c_void_p()
+            self._check(self.lib.vlb_graph_create(self.h, int(n_steps), ctypes.byref(g)))
+            self._graphs[n_steps] = g
+        return self._graphs[n_steps]
+
+    def step_graph(self, n_steps):
+        """Advance n_steps (even) coupled steps with one graph launch."""
+        self._check(self.lib.vlb_graph_launch(self.graph(n_steps)))
 
     def __del__(self):
         try:
@@ -285,6 +307,11 @@ class Run:
         n = ctypes.c_int64(0)
         self._check(self.lib.vlb_get_timing(self.h, int(cls), ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+    def time_kernel(self, cls, reps=20):
+        ms = ctypes.c_double(0)
+        self._check(self.lib.vlb_time_kernel(self.h, int(cls), int(reps), ctypes.byref(ms)))
+        return float(ms.value)
 
     def work(self):
         a = ctypes.c_int64(0)

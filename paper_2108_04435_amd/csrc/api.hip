@@ -14,6 +14,13 @@ struct vlb_run {
   Run r;
 };
 
+struct vlb_graph {
+  vlb_run* run = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t n_steps = 0;
+  int parity = 0;
+};
+
 namespace {
 
 std::mutex g_err_mu;
@@ -101,7 +108,7 @@ size_t layout(Run& r, char* base) {
                        &r.scan_a, &r.scan_b, &r.used};
   for (int32_t** p : ibufs) *p = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   r.bsX = (uint32_t*)B.take(3 * nc * sizeof(uint32_t));
-  r.bsD = B.take(3 * nc * fe);
+  r.bsD = B.take(4 * nc * fe);
   size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
@@ -168,6 +175,31 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
       ax.invq_d[a] = std::ldexp(1.0, -k);
     }
     ax.invq_f[a] = (float)ax.invq_d[a];
+  }
+  {
+    // one power-of-two grid step for all axes when every periodic axis has
+    // the same power-of-two length and the wall axes fit that step
+    BsAxes& ax = r.bsax;
+    double q = 0.0;
+    for (int a = 0; a < 3; ++a)
+      if (ax.periodic[a]) q = ax.q[a];
+    if (q == 0.0)
+      for (int a = 0; a < 3; ++a) q = (q == 0.0 || ax.q[a] < q) ? ax.q[a] : q;
+    int ex = 0;
+    bool ok = std::frexp(q, &ex) == 0.5;
+    for (int a = 0; a < 3 && ok; ++a) {
+      if (ax.periodic[a])
+        ok = ax.q[a] == q;
+      else
+        ok = (double)(n[a] + 2) * q <= 2147483648.0;
+    }
+    ax.uniform = ok ? 1 : 0;
+    if (ok)
+      for (int a = 0; a < 3; ++a) {
+        ax.q[a] = q;
+        ax.invq_d[a] = 1.0 / q;
+        ax.invq_f[a] = (float)ax.invq_d[a];
+      }
   }
   r.bsS = bs_chunks(r.ncap);
   // spreading bins: lower stencil corner, n (+1 on wall axes) per axis
@@ -571,6 +603,34 @@ int vlb_get_timing(vlb_run* h, int32_t cls, double* total_ms, int64_t* launches)
   return VLB_OK;
 }
 
+int vlb_time_kernel(vlb_run* h, int32_t cls, int32_t reps, double* avg_ms) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (cls < 0 || cls > 1 || reps < 1 || !avg_ms) return fail(h, VLB_EINVAL, "bad kernel timing request");
+  Run& r = h->r;
+  const bool was = r.timing;
+  r.timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OR_FAIL(h, hipEventCreate(&e0));
+  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  if (cls == 0) HIP_OR_FAIL(h, bs_prep(r, r.pos));
+  HIP_OR_FAIL(h, hipEventRecord(e0, r.stream));
+  for (int k = 0; k < reps; ++k) {
+    if (cls == 0)
+      HIP_OR_FAIL(h, bs_sum(r, r.pos));
+    else
+      HIP_OR_FAIL(h, lbm_step(r));
+  }
+  HIP_OR_FAIL(h, hipEventRecord(e1, r.stream));
+  HIP_OR_FAIL(h, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  r.timing = was;
+  *avg_ms = (double)ms / reps;
+  return latched(h);
+}
+
 int vlb_get_work(vlb_run* h, int64_t* node_updates, int64_t* bs_pairs) {
   if (!h || !node_updates || !bs_pairs) return fail(h, VLB_EINVAL, "null argument");
   Run& r = h->r;
@@ -579,6 +639,64 @@ int vlb_get_work(vlb_run* h, int64_t* node_updates, int64_t* bs_pairs) {
   HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
   *node_updates = r.last_nodes;
   *bs_pairs = acc;
+  return VLB_OK;
+}
+
+int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!out || n_steps < 2 || (n_steps & 1)) return fail(h, VLB_EINVAL, "n_steps must be even and >= 2");
+  Run& r = h->r;
+  if (!r.stream) return fail(h, VLB_EINVAL, "graph capture needs a non-null stream");
+  const int64_t step0 = r.step, nodes0 = r.last_nodes;
+  const int parity0 = r.parity;
+  const bool timing0 = r.timing;
+  r.timing = false;
+  HIP_OR_FAIL(h, hipStreamBeginCapture(r.stream, hipStreamCaptureModeRelaxed));
+  int code = VLB_OK;
+  for (int64_t k = 0; k < n_steps && code == VLB_OK; ++k) code = one_step(h);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(r.stream, &graph);
+  r.step = step0;
+  r.last_nodes = nodes0;
+  r.parity = parity0;
+  r.timing = timing0;
+  if (code != VLB_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return code;
+  }
+  if (ec != hipSuccess) return hip_fail(h, ec, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(h, ei, "hipGraphInstantiate");
+  vlb_graph* g = new (std::nothrow) vlb_graph();
+  if (!g) {
+    hipGraphExecDestroy(exec);
+    return fail(h, VLB_EINVAL, "out of host memory");
+  }
+  g->run = h;
+  g->exec = exec;
+  g->n_steps = n_steps;
+  g->parity = parity0;
+  *out = g;
+  return VLB_OK;
+}
+
+int vlb_graph_launch(vlb_graph* g) {
+  if (!g || !g->run) return fail(nullptr, VLB_EINVAL, "graph is NULL");
+  vlb_run* h = g->run;
+  Run& r = h->r;
+  if (r.parity != g->parity) return fail(h, VLB_ESTATE, "run parity differs from the captured one");
+  HIP_OR_FAIL(h, hipGraphLaunch(g->exec, r.stream));
+  r.step += g->n_steps;
+  r.last_nodes += g->n_steps * r.cells;
+  return VLB_OK;
+}
+
+int vlb_graph_destroy(vlb_graph* g) {
+  if (!g) return VLB_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  delete g;
   return VLB_OK;
 }
 

@@ -22,10 +22,13 @@ namespace {
 
 constexpr int kTile = 256;
 
-// Grid coordinates and segment vectors of the points at positions Y.
+// Grid coordinates and segment vectors of the points at positions Y.  The
+// FP32 path stores the segment vector in grid units when all axes share one
+// grid step (uniform) and in lattice units otherwise, plus its squared
+// length; the FP64 path stores the vector in lattice units.
 template <class T>
 __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
-                       int32_t* __restrict__ cnt, long long ncap, BsAxes ax,
+                       int32_t* __restrict__ cnt, long long ncap, BsAxes ax, int uniform,
                        uint32_t* __restrict__ X, T* __restrict__ D) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
@@ -33,6 +36,7 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
   if (j == 0 && n > 2) *(long long*)(cnt + 16) += (long long)n * (n - 2);
   if (j >= n) return;
   const int k = nxt[j];
+  T dd = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double y = Y[a * ncap + j];
@@ -45,37 +49,47 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
       else if (d < -0.5 * ax.L[a])
         d = d + ax.L[a];
     }
-    D[a * ncap + j] = (T)d;
+    const T dv = uniform ? (T)(d * ax.q[a]) : (T)d;
+    D[a * ncap + j] = dv;
+    dd += dv * dv;
   }
+  if (sizeof(T) == 4) D[3 * ncap + j] = dd;
 }
 
-// FP32 pair sum.  Per pair: R1 from the grid difference, R2 = R1 + d_k,
-// v = (R1 x R2) (1/|R1| + 1/|R2|) / (|R1||R2| + R1.R2) written with the
-// inverse norms as (R1 x R2) (i1 + i2) i1 i2 / (1 + (R1.R2) i1 i2).
-template <bool kCheck>
+// FP32 pair sum.  Per pair, with R1 = s_k - r (from the grid difference)
+// and d = s_next(k) - s_k:
+//   R1 x R2 = R1 x d,  R1.R2 = |R1|^2 + R1.d,  |R2|^2 = |R1|^2 + 2 R1.d + |d|^2,
+//   v = (R1 x R2) (i1 + i2) i1 i2 / (1 + (R1.R2) i1 i2),  i_m = 1/|R_m|,
+// the closed form (|R1| + |R2|) / (|R1||R2| (|R1||R2| + R1.R2)) rewritten with
+// inverse norms.  Uniform grid: R1 stays in grid units and the result is
+// rescaled once per target (v is homogeneous of degree -1 in R).
+template <bool kCheck, bool kUniform>
 __device__ inline void bs_tile_f32(const uint32_t* sx, const uint32_t* sy, const uint32_t* sz,
-                                   const float* dx, const float* dy, const float* dz, int cnt,
-                                   int t0, uint32_t xt, uint32_t yt, uint32_t zt, float iqx,
-                                   float iqy, float iqz, int jj, int pj, float& ax, float& ay,
-                                   float& az) {
+                                   const float* dx, const float* dy, const float* dz,
+                                   const float* dq, int cnt, int t0, uint32_t xt, uint32_t yt,
+                                   uint32_t zt, float iqx, float iqy, float iqz, int jj, int pj,
+                                   float& ax, float& ay, float& az) {
 #pragma unroll 4
   for (int s = 0; s < cnt; ++s) {
-    const float r1x = (float)(int)(sx[s] - xt) * iqx;
-    const float r1y = (float)(int)(sy[s] - yt) * iqy;
-    const float r1z = (float)(int)(sz[s] - zt) * iqz;
-    const float r2x = r1x + dx[s];
-    const float r2y = r1y + dy[s];
-    const float r2z = r1z + dz[s];
+    float r1x = (float)(int)(sx[s] - xt);
+    float r1y = (float)(int)(sy[s] - yt);
+    float r1z = (float)(int)(sz[s] - zt);
+    if (!kUniform) {
+      r1x *= iqx;
+      r1y *= iqy;
+      r1z *= iqz;
+    }
+    const float ex = dx[s], ey = dy[s], ez = dz[s];
+    const float t = r1x * ex + r1y * ey + r1z * ez;
     const float n1 = r1x * r1x + r1y * r1y + r1z * r1z;
-    const float n2 = r2x * r2x + r2y * r2y + r2z * r2z;
+    const float n2 = fmaf(2.0f, t, n1 + dq[s]);
     const float i1 = __builtin_amdgcn_rsqf(n1);
     const float i2 = __builtin_amdgcn_rsqf(n2);
-    const float crx = r1y * r2z - r1z * r2y;
-    const float cry = r1z * r2x - r1x * r2z;
-    const float crz = r1x * r2y - r1y * r2x;
-    const float dt = r1x * r2x + r1y * r2y + r1z * r2z;
+    const float crx = r1y * ez - r1z * ey;
+    const float cry = r1z * ex - r1x * ez;
+    const float crz = r1x * ey - r1y * ex;
     const float a = i1 * i2;
-    const float den = fmaf(dt, a, 1.0f);
+    const float den = fmaf(n1 + t, a, 1.0f);
     float f = (i1 + i2) * a * __builtin_amdgcn_rcpf(den);
     if (kCheck) {
       const int k = t0 + s;
@@ -87,6 +101,7 @@ __device__ inline void bs_tile_f32(const uint32_t* sx, const uint32_t* sy, const
   }
 }
 
+template <bool kUniform>
 __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
                                                const float* __restrict__ D,
                                                const int32_t* __restrict__ prv,
@@ -107,7 +122,7 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   const int pj = valid ? prv[j] : -1;
   const int jj = valid ? j : -1;
   __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
-  __shared__ float dx[kTile], dy[kTile], dz[kTile];
+  __shared__ float dx[kTile], dy[kTile], dz[kTile], dq[kTile];
   float ax = 0.f, ay = 0.f, az = 0.f;
   for (int t0 = kb; t0 < ke; t0 += kTile) {
     const int k = t0 + threadIdx.x;
@@ -118,14 +133,17 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
       dx[threadIdx.x] = D[k];
       dy[threadIdx.x] = D[ncap + k];
       dz[threadIdx.x] = D[2 * ncap + k];
+      dq[threadIdx.x] = D[3 * ncap + k];
     }
     __syncthreads();
     const int cnt = min(kTile, ke - t0);
     const bool hit = valid && ((jj >= t0 && jj < t0 + cnt) || (pj >= t0 && pj < t0 + cnt));
     if (__any(hit))
-      bs_tile_f32<true>(sx, sy, sz, dx, dy, dz, cnt, t0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+      bs_tile_f32<true, kUniform>(sx, sy, sz, dx, dy, dz, dq, cnt, t0, xt, yt, zt, iqx, iqy, iqz,
+                                  jj, pj, ax, ay, az);
     else
-      bs_tile_f32<false>(sx, sy, sz, dx, dy, dz, cnt, t0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+      bs_tile_f32<false, kUniform>(sx, sy, sz, dx, dy, dz, dq, cnt, t0, xt, yt, zt, iqx, iqy, iqz,
+                                   jj, pj, ax, ay, az);
     __syncthreads();
   }
   if (valid) {
@@ -231,10 +249,10 @@ hipError_t bs_prep(Run& r, const double* Y) {
   const int nb = (int)((r.ncap + 255) / 256);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_prep<double>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, r.bsX, (double*)r.bsD);
+                       r.bsax, 0, r.bsX, (double*)r.bsD);
   else
     hipLaunchKernelGGL(k_prep<float>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, r.bsX, (float*)r.bsD);
+                       r.bsax, r.bsax.uniform, r.bsX, (float*)r.bsD);
   return hipGetLastError();
 }
 
@@ -247,8 +265,12 @@ hipError_t bs_sum(Run& r, const double* Y) {
     hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD, Y,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.L[0], r.bsax.L[1], r.bsax.L[2],
                        (double*)r.bsP);
+  else if (r.bsax.uniform)
+    hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
+                       r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
+                       r.bsax.invq_f[2], (float*)r.bsP);
   else
-    hipLaunchKernelGGL(k_bs_f32, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
+    hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
                        r.bsax.invq_f[2], (float*)r.bsP);
   time_end(r, 0, b);

@@ -4,13 +4,11 @@
 //    fluid, Schwarz line velocity, mutual-friction force and the RK4
 //    bookkeeping of one stage;
 //  * spreading of the point forces onto the lattice, without atomics:
-//    points are binned by the cell of their stencil's lower corner with a
-//    stable radix sort; each touched node is then owned by exactly one bin
+//    points are binned by the cell of their stencil's lower corner with the
+//    library's stable radix sort; each touched node is then owned by exactly one bin
 //    and gathers the contributions of the (at most 8) bins around it in a
 //    fixed order.
 #include "vlb_internal.h"
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 namespace vlb {
 
@@ -36,6 +34,7 @@ struct FinArgs {
   int coupling;
   double kappa;
   double bs_scale;    // kappa / (4 pi)
+  double nl_scale;    // kappa / (4 pi) times the grid step when the sum ran in grid units
   double ea;          // e^C a
   double alpha, alpha_p;
   double rs_rn;
@@ -120,7 +119,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   const PT* P = (const PT*)A.P;
   for (int s = 0; s < A.S; ++s)
     for (int a = 0; a < 3; ++a) vs[a] += (double)P[((long long)s * 3 + a) * nc + j];
-  for (int a = 0; a < 3; ++a) vs[a] *= A.bs_scale;
+  for (int a = 0; a < 3; ++a) vs[a] *= A.nl_scale;
 
   // local geometry (three-point derivatives on a non-uniform arc length)
   const int jn = A.nxt[j], jp = A.prv[j];
@@ -274,96 +273,96 @@ __global__ void k_spread_clear(FT* __restrict__ F, long long cells, const int32_
   F[2 * cells + node] = FT(0);
 }
 
+// One thread per (sorted entry, stencil corner).  Only the first entry of
+// each bin acts: the node at that corner of the bin's stencil is written by
+// the occupied bin of smallest key among the (up to 8) bins whose stencils
+// contain it, which gathers those bins' points in a fixed order.
 template <class FT>
 __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
                                 const int32_t* __restrict__ bins,
                                 const double* __restrict__ pos, const double* __restrict__ gpt,
                                 int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
                                 long long cells, FT* __restrict__ F, int32_t* __restrict__ touched) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
-  if (r == 0) cnt[1] = 8 * n;
+  if (id == 0) cnt[1] = 8 * n;
+  const int r = (int)(id >> 3);
+  const int o = (int)(id & 7);
   if (r >= n) return;
   const uint32_t me = skey[r];
   if (r > 0 && skey[r - 1] == me) {
-    for (int o = 0; o < 8; ++o) touched[8 * r + o] = -1;
+    touched[id] = -1;
     return;
   }
-  // decode my bin (lower corner of the stencil, bin coordinates)
   int b[3];
   b[0] = (int)(me % (uint32_t)sg.ext[0]);
   b[1] = (int)((me / (uint32_t)sg.ext[0]) % (uint32_t)sg.ext[1]);
   b[2] = (int)(me / ((uint32_t)sg.ext[0] * (uint32_t)sg.ext[1]));
-  for (int o = 0; o < 8; ++o) {
-    const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
-    int e[3];    // node in bin coordinates
-    int lat[3];  // node in lattice coordinates
-    bool ghost = false;
-    for (int a = 0; a < 3; ++a) {
-      e[a] = b[a] + off[a];
-      if (sg.wall[a]) {
-        lat[a] = e[a] - 1;
-        if (lat[a] < 0 || lat[a] >= sg.n[a]) ghost = true;
-      } else {
-        if (e[a] >= sg.n[a]) e[a] -= sg.n[a];
-        lat[a] = e[a];
-      }
+  const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+  int e[3];    // node in bin coordinates
+  int lat[3];  // node in lattice coordinates
+  bool ghost = false;
+  for (int a = 0; a < 3; ++a) {
+    e[a] = b[a] + off[a];
+    if (sg.wall[a]) {
+      lat[a] = e[a] - 1;
+      if (lat[a] < 0 || lat[a] >= sg.n[a]) ghost = true;
+    } else {
+      if (e[a] >= sg.n[a]) e[a] -= sg.n[a];
+      lat[a] = e[a];
     }
-    if (ghost) {
-      touched[8 * r + o] = -1;
-      continue;
-    }
-    // the bins whose stencil contains this node: e - o' for o' in {0,1}^3
-    int lo[8], hi[8];
-    bool owner = true;
-    for (int q = 0; q < 8 && owner; ++q) {
-      const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
-      int c[3];
-      bool ok = true;
-      for (int a = 0; a < 3; ++a) {
-        c[a] = e[a] - oq[a];
-        if (sg.wall[a]) {
-          if (c[a] < 0) ok = false;
-        } else if (c[a] < 0) {
-          c[a] += sg.n[a];
-        }
-      }
-      lo[q] = hi[q] = 0;
-      if (!ok) continue;
-      const uint32_t k = (uint32_t)(((long long)c[2] * sg.ext[1] + c[1]) * sg.ext[0] + c[0]);
-      const int l = bins[k];
-      if (l >= 0) {
-        if (k < me) owner = false;
-        int h = l + 1;
-        while (h < n && skey[h] == k) ++h;
-        lo[q] = l;
-        hi[q] = h;
-      }
-    }
-    if (!owner) {
-      touched[8 * r + o] = -1;
-      continue;
-    }
-    double f[3] = {0.0, 0.0, 0.0};
-    for (int q = 0; q < 8; ++q) {
-      const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
-      for (int t = lo[q]; t < hi[q]; ++t) {
-        const int pidx = sval[t];
-        double w = 1.0;
-        for (int a = 0; a < 3; ++a) {
-          const double x = pos[a * ncap + pidx];
-          const double fr = x - floor(x);
-          w *= oq[a] ? fr : 1.0 - fr;
-        }
-        for (int a = 0; a < 3; ++a) f[a] += w * gpt[a * ncap + pidx];
-      }
-    }
-    const long long node = ((long long)lat[2] * sg.n[1] + lat[1]) * sg.n[0] + lat[0];
-    F[node] = (FT)f[0];
-    F[cells + node] = (FT)f[1];
-    F[2 * cells + node] = (FT)f[2];
-    touched[8 * r + o] = (int32_t)node;
   }
+  if (ghost) {
+    touched[id] = -1;
+    return;
+  }
+  // the bins whose stencil contains this node: e - o' for o' in {0,1}^3
+  uint32_t kq[8];
+  int lo[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+    int c[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      c[a] = e[a] - oq[a];
+      if (sg.wall[a]) {
+        if (c[a] < 0) ok = false;
+      } else if (c[a] < 0) {
+        c[a] += sg.n[a];
+      }
+    }
+    kq[q] = (uint32_t)(((long long)c[2] * sg.ext[1] + c[1]) * sg.ext[0] + c[0]);
+    lo[q] = ok ? bins[kq[q]] : -1;
+  }
+  bool owner = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (lo[q] >= 0 && kq[q] < me) owner = false;
+  if (!owner) {
+    touched[id] = -1;
+    return;
+  }
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < 8; ++q) {
+    if (lo[q] < 0) continue;
+    const int oq[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+    for (int t = lo[q]; t < n && skey[t] == kq[q]; ++t) {
+      const int pidx = sval[t];
+      double w = 1.0;
+      for (int a = 0; a < 3; ++a) {
+        const double x = pos[a * ncap + pidx];
+        const double fr = x - floor(x);
+        w *= oq[a] ? fr : 1.0 - fr;
+      }
+      for (int a = 0; a < 3; ++a) f[a] += w * gpt[a * ncap + pidx];
+    }
+  }
+  const long long node = ((long long)lat[2] * sg.n[1] + lat[1]) * sg.n[0] + lat[0];
+  F[node] = (FT)f[0];
+  F[cells + node] = (FT)f[1];
+  F[2 * cells + node] = (FT)f[2];
+  touched[id] = (int32_t)node;
 }
 
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
@@ -386,18 +385,10 @@ SpreadGeom spread_geom(const Run& r) {
 
 }  // namespace
 
-hipError_t bins_mark(Run& r, int set) {
-  hipLaunchKernelGGL(k_bin_mark, dim3(nblocks(r.ncap, 256)), dim3(256), 0, r.stream, r.keys_b, r.cnt,
+hipError_t bins_mark(Run& r, const uint32_t* skey, int set) {
+  hipLaunchKernelGGL(k_bin_mark, dim3(nblocks(r.ncap, 256)), dim3(256), 0, r.stream, skey, r.cnt,
                      r.bins, set);
   return hipGetLastError();
-}
-
-size_t sort_tmp_bytes(long long n) {
-  size_t bytes = 0;
-  rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                            (int32_t*)nullptr, (int32_t*)nullptr, (unsigned int)n, 0u, 32u,
-                            (hipStream_t)0);
-  return bytes;
 }
 
 hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only) {
@@ -421,6 +412,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.coupling = r.vor.coupling;
   A.kappa = r.vor.kappa;
   A.bs_scale = r.vor.kappa / (4.0 * M_PI);
+  A.nl_scale = (r.prec != VLB_F64 && r.bsax.uniform) ? A.bs_scale * r.bsax.q[0] : A.bs_scale;
   A.ea = exp(r.vor.core_c) * r.vor.core_a;
   A.alpha = r.vor.alpha;
   A.alpha_p = r.vor.alpha_p;
@@ -455,18 +447,19 @@ hipError_t fil_spread(Run& r) {
   const int nb = nblocks(r.ncap, 256);
   hipLaunchKernelGGL(k_spread_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, sg,
                      pad, r.keys_a, r.vals_a);
-  size_t bytes = r.sort_tmp_bytes;
-  e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
-                                (unsigned int)r.ncap, 0u, (unsigned int)r.key_bits, r.stream);
+  uint32_t* sk = nullptr;
+  int32_t* sv = nullptr;
+  e = sort_pairs(r, r.key_bits, &sk, &sv);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.cnt, r.bins, 1);
+  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, sk, r.cnt, r.bins, 1);
+  const int nb8 = nblocks(8 * r.ncap, 256);
   if (r.prec == VLB_F64)
-    hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
+    hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
                        r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
   else
-    hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.vals_b,
+    hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
                        r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
-  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, r.keys_b, r.cnt, r.bins, 0);
+  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, sk, r.cnt, r.bins, 0);
   return hipGetLastError();
 }
 

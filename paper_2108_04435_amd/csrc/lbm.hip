@@ -35,7 +35,19 @@ __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
   const long long c = ((long long)z * g.ny + y) * g.nx + x;
 
   T d[19];
-  load_node<S>(M, g, P, x, y, z, d);
+  Nbr nb;
+  if (P == 1) make_nbr(g, x, y, z, nb);
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) d[i] = Store<S>::ld(M + (long long)i * g.cells + c);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const long long s = nbr_index(nb, -cx(i), -cy(i), -cz(i));
+      d[i] = (s >= 0) ? Store<S>::ld(M + (long long)opp(i) * g.cells + s)
+                      : Store<S>::ld(M + (long long)i * g.cells + c);
+    }
+  }
   if (is_plane(g, z)) {
     const T ux = T(g.plane_u[0]), uy = T(g.plane_u[1]), uz = T(g.plane_u[2]);
 #pragma unroll
@@ -67,7 +79,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
     if (P == 0) {
       Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
     } else {
-      const long long s = neighbour(g, x, y, z, cx(i), cy(i), cz(i));
+      const long long s = nbr_index(nb, cx(i), cy(i), cz(i));
       if (s >= 0)
         Store<S>::st(M + (long long)i * g.cells + s, dn);
       else

@@ -17,8 +17,6 @@
 // function of the positions.
 #include "vlb_internal.h"
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #pragma clang fp contract(off)
 
 namespace vlb {
@@ -63,22 +61,25 @@ __device__ inline double wrap1(double x, double L, int periodic) {
 }
 
 // ---- single-workgroup exclusive scan of n ints (n read from *np): tiles
-// of 1024 consecutive values (coalesced), wave prefix sums with shuffles,
-// wave totals combined in LDS, a running carry between tiles.
+// of 4096 values, 4 consecutive values per thread, wave prefix sums with
+// shuffles, wave totals combined in LDS, a running carry between tiles.
 __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in,
                                                     int32_t* __restrict__ out,
-                                                    const int32_t* __restrict__ np,
+                                                    const int32_t* __restrict__ np, int nconst,
                                                     int32_t* __restrict__ total) {
   __shared__ int32_t wsum[16];
-  const int n = *np;
+  const int n = np ? *np : nconst;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
   int carry = 0;
-  for (int base = 0; base < n; base += 1024) {
-    const int k = base + t;
-    const int v = k < n ? in[k] : 0;
-    int x = v;
+  for (int base = 0; base < n; base += 4096) {
+    const int k0 = base + 4 * t;
+    int v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? in[k0 + q] : 0;
+    const int mine = v[0] + v[1] + v[2] + v[3];
+    int x = mine;
     for (int off = 1; off < 64; off <<= 1) {
       const int y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
@@ -94,8 +95,12 @@ __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ 
       if (lane < 16) wsum[lane] = s;
     }
     __syncthreads();
-    const int wpre = w > 0 ? wsum[w - 1] : 0;
-    if (k < n) out[k] = carry + wpre + x - v;
+    int run = carry + (w > 0 ? wsum[w - 1] : 0) + x - mine;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (k0 + q < n) out[k0 + q] = run;
+      run += v[q];
+    }
     carry += wsum[15];
     __syncthreads();
   }
@@ -311,7 +316,8 @@ __device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
   return m;
 }
 
-// Visit every candidate partner j > i of point i; calls f(j, d2).
+// Visit every candidate partner j > i of point i; calls f(j, d2).  The 27
+// neighbouring bins are looked up first (independent loads), then walked.
 template <class Fn>
 __device__ inline void rc_visit(int i, const double* __restrict__ pos,
                                 const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
@@ -324,31 +330,39 @@ __device__ inline void rc_visit(int i, const double* __restrict__ pos,
   const int mx = bin_offsets(bg, 0, b[0], ox);
   const int my = bin_offsets(bg, 1, b[1], oy);
   const int mz = bin_offsets(bg, 2, b[2], oz);
+  uint32_t kk[27];
+  int first[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int ix = q % 3, iy = (q / 3) % 3, iz = q / 9;
+    const bool ok = ix < mx && iy < my && iz < mz;
+    kk[q] = ok ? (uint32_t)(((long long)oz[ok ? iz : 0] * bg.nb[1] + oy[ok ? iy : 0]) * bg.nb[0] +
+                            ox[ok ? ix : 0])
+               : 0u;
+    first[q] = ok ? bins[kk[q]] : -1;
+  }
   const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
-  for (int iz = 0; iz < mz; ++iz)
-    for (int iy = 0; iy < my; ++iy)
-      for (int ix = 0; ix < mx; ++ix) {
-        const uint32_t k = (uint32_t)(((long long)oz[iz] * bg.nb[1] + oy[iy]) * bg.nb[0] + ox[ix]);
-        int t = bins[k];
-        if (t < 0) continue;
-        for (; t < n && skey[t] == k; ++t) {
-          const int j = sval[t];
-          if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
-          double d[3];
-          sep(pos, nc, i, j, tg, d);
-          const double d2 = sq3(d);
-          if (!(d2 < d2max)) continue;
-          const int nj = nxt[j];
-          double ea[3], eb[3], ec[3], ee[3];
-          sep(pos, nc, i, ni, tg, ea);
-          sep(pos, nc, j, nj, tg, eb);
-          sep(pos, nc, i, nj, tg, ec);
-          sep(pos, nc, j, ni, tg, ee);
-          const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
-          const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
-          if (after <= before) f(j, d2);
-        }
-      }
+  for (int q = 0; q < 27; ++q) {
+    if (first[q] < 0) continue;
+    const uint32_t k = kk[q];
+    for (int t = first[q]; t < n && skey[t] == k; ++t) {
+      const int j = sval[t];
+      if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
+      double d[3];
+      sep(pos, nc, i, j, tg, d);
+      const double d2 = sq3(d);
+      if (!(d2 < d2max)) continue;
+      const int nj = nxt[j];
+      double ea[3], eb[3], ec[3], ee[3];
+      sep(pos, nc, i, ni, tg, ea);
+      sep(pos, nc, j, nj, tg, eb);
+      sep(pos, nc, i, nj, tg, ec);
+      sep(pos, nc, j, ni, tg, ee);
+      const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
+      const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
+      if (after <= before) f(j, d2);
+    }
+  }
 }
 
 __global__ void k_rc_count(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
@@ -515,7 +529,7 @@ hipError_t small_and_compact(Run& r, int32_t* del) {
   const int nb = nb_of(r.ncap, 256);
   hipLaunchKernelGGL(k_small, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.cnt, del,
                      r.vor.min_loop_pts, r.scan_a);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt + 9, r.cnt + 8);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt + 9, 0, r.cnt + 8);
   hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv,
                      r.cnt, r.ncap, r.scan_a, r.scan_b, r.pos_t, r.nxt_t, r.prv_t);
   hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
@@ -524,6 +538,12 @@ hipError_t small_and_compact(Run& r, int32_t* del) {
 }
 
 }  // namespace
+
+hipError_t scan_excl(Run& r, const int32_t* in, int32_t* out, const int32_t* np, int n,
+                     int32_t* total) {
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, in, out, np, n, total);
+  return hipGetLastError();
+}
 
 hipError_t topo_update(Run& r) {
   const TopoGeom tg = topo_geom(r);
@@ -537,7 +557,7 @@ hipError_t topo_update(Run& r) {
     hipLaunchKernelGGL(k_rm_del, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, r.flag_a, del);
     hipLaunchKernelGGL(k_rm_relink, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, del);
     hipLaunchKernelGGL(k_rm_insmark, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap, tg, mx2, del, r.scan_a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 2);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 2);
     hipLaunchKernelGGL(k_rm_insert, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
                        r.ncap, tg, del, r.scan_a, r.scan_b);
   } else {
@@ -551,19 +571,19 @@ hipError_t topo_update(Run& r) {
     const double d2max = r.vor.reconnect_dist * r.vor.reconnect_dist;
     const uint32_t pad = (r.bin_bits >= 32) ? 0xFFFFFFFFu : ((1u << r.bin_bits) - 1u);
     hipLaunchKernelGGL(k_rc_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, bg, pad, r.keys_a, r.vals_a);
-    size_t bytes = r.sort_tmp_bytes;
-    e = rocprim::radix_sort_pairs(r.sort_tmp, bytes, r.keys_a, r.keys_b, r.vals_a, r.vals_b,
-                                  (unsigned int)r.ncap, 0u, (unsigned int)r.bin_bits, r.stream);
+    uint32_t* sk = nullptr;
+    int32_t* sv = nullptr;
+    e = sort_pairs(r, r.bin_bits, &sk, &sv);
     if (e != hipSuccess) return e;
-    e = bins_mark(r, 1);
+    e = bins_mark(r, sk, 1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rc_count, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
-                       r.vals_b, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, r.cnt + 6);
-    hipLaunchKernelGGL(k_rc_write, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.keys_b,
-                       r.vals_b, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i,
+    hipLaunchKernelGGL(k_rc_count, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk,
+                       sv, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 6);
+    hipLaunchKernelGGL(k_rc_write, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk,
+                       sv, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i,
                        r.rc_j, r.rc_key_a, r.rc_idx_a);
-    e = bins_mark(r, 0);
+    e = bins_mark(r, sk, 0);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, r.used, r.ncap, 0);
     hipLaunchKernelGGL(k_rc_match, dim3(1), dim3(1024), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,

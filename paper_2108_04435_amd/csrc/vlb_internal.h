@@ -87,6 +87,41 @@ __device__ inline long long neighbour(const Geom& g, int x, int y, int z, int dx
   return ((long long)zz * g.ny + yy) * g.nx + xx;
 }
 
+// Offsets of the 3 x 3 x 3 neighbourhood of one node, per axis: index of
+// the node (x+dx, y+dy, z+dz) is zo[dz+1] + yo[dy+1] + xo[dx+1], negative
+// when that node lies beyond a wall (periodic axes wrap).
+struct Nbr {
+  long long zo[3], yo[3], xo[3];
+};
+constexpr long long kBeyond = -(1LL << 40);
+
+__device__ inline void make_nbr(const Geom& g, int x, int y, int z, Nbr& nb) {
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    int xx = x + d, yy = y + d, zz = z + d;
+    bool vx = true, vy = true, vz = true;
+    if (xx < 0 || xx >= g.nx) {
+      if (g.wall[0]) vx = false;
+      xx = xx < 0 ? xx + g.nx : xx - g.nx;
+    }
+    if (yy < 0 || yy >= g.ny) {
+      if (g.wall[1]) vy = false;
+      yy = yy < 0 ? yy + g.ny : yy - g.ny;
+    }
+    if (zz < 0 || zz >= g.nz) {
+      if (g.wall[2]) vz = false;
+      zz = zz < 0 ? zz + g.nz : zz - g.nz;
+    }
+    nb.xo[d + 1] = vx ? (long long)xx : kBeyond;
+    nb.yo[d + 1] = vy ? (long long)yy * g.nx : kBeyond;
+    nb.zo[d + 1] = vz ? (long long)zz * g.ny * g.nx : kBeyond;
+  }
+}
+
+__device__ inline long long nbr_index(const Nbr& nb, int dx, int dy, int dz) {
+  return nb.zo[dz + 1] + nb.yo[dy + 1] + nb.xo[dx + 1];
+}
+
 // Deviations of the populations at node (x, y, z) at a time whose storage
 // parity is P (0: natural layout, population i of node x in slot i of x;
 // 1: the AA-swapped layout written by an even step: population i of x sits
@@ -100,9 +135,11 @@ __device__ inline void load_node(const S* __restrict__ M, const Geom& g, int par
 #pragma unroll
     for (int i = 0; i < 19; ++i) d[i] = Store<S>::ld(M + (long long)i * g.cells + c);
   } else {
+    Nbr nb;
+    make_nbr(g, x, y, z, nb);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
-      long long s = neighbour(g, x, y, z, -cx(i), -cy(i), -cz(i));
+      const long long s = nbr_index(nb, -cx(i), -cy(i), -cz(i));
       d[i] = (s >= 0) ? Store<S>::ld(M + (long long)opp(i) * g.cells + s)
                       : Store<S>::ld(M + (long long)i * g.cells + c);
     }
@@ -157,6 +194,7 @@ struct BsAxes {
   double invq_d[3];
   double L[3];
   int periodic[3];
+  int uniform;      // 1: one grid step q for all axes (FP32 sum in grid units)
 };
 
 // Workspace-resident state of a run.
@@ -280,7 +318,9 @@ hipError_t fil_seed(Run& r, long long n);
 hipError_t topo_update(Run& r);
 
 size_t sort_tmp_bytes(long long n);
-hipError_t bins_mark(Run& r, int set);
+hipError_t bins_mark(Run& r, const uint32_t* skey, int set);
+hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres);
+hipError_t scan_excl(Run& r, const int32_t* in, int32_t* out, const int32_t* np, int n, int32_t* total);
 
 // timing helpers (api.cpp)
 void time_begin(Run& r, int cls, hipEvent_t* b);

@@ -213,3 +213,46 @@ def config_tangle(precision="f16", n=256, n_rings=2000, seed=4):
                             min_sep=1.5)
     return dict(name="tangle_256", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
                 steps=100)
+
+
+# ------------------------------------------------------------- serving
+
+SERVE_LATTICES = ((32, 32, 32), (64, 64, 64), (64, 64, 256), (128, 128, 256))
+
+
+def serving_requests(seed=5, n_requests=64, rate=2.0, lattices=SERVE_LATTICES,
+                     points=(1000, 20000), steps=(500, 2000), alpha=(0.1, 0.3),
+                     alpha_p=(0.0, 0.02), vn=(0.01, 0.04), precision="f32"):
+    """Request stream of counterflow runs: exponential inter-arrival times
+    (mean 1/rate s); lattice uniform from ``lattices`` (cubes periodic with
+    a uniform initial v_n along z, elongated ones with walls on x, y and a
+    Guo body force for a mean v_n); filament points U[points] from rings
+    R ~ U[4, min(12, min(dims)/4)]; alpha, alpha', v_n uniform; steps
+    U{steps}.  Returns a list of dicts (arrival, steps, cfg)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        dims = lattices[rng.integers(len(lattices))]
+        target = int(rng.integers(points[0], points[1] + 1))
+        a = rng.uniform(*alpha)
+        ap = rng.uniform(*alpha_p)
+        v = rng.uniform(*vn)
+        nsteps = int(rng.integers(steps[0], steps[1] + 1))
+        cube = dims[0] == dims[2]
+        walls = (False, False, False) if cube else (True, True, False)
+        W = float(dims[0])
+        body = (0.0, 0.0, 0.0) if cube else (0.0, 0.0, 28.45 * 0.1 * v / (W * W))
+        lat = lattice_preset(*dims, tau=0.8, walls=walls, body_force=body, precision=precision)
+        vor = vortex_preset(alpha=a, alpha_p=ap, reconnect=True, mass_balance=True)
+        r_hi = min(12.0, min(dims) / 4.0)
+        r_mean = 0.5 * (4.0 + r_hi)
+        per_ring = 2.0 * math.pi * r_mean / 0.95
+        n_rings = max(1, int(round(target / per_ring)))
+        rho, u = velocity_field(seed * 1000 + rid, dims, (0.0, 0.0, v), 0.0)
+        pos, nxt = random_rings(seed * 1000 + rid, n_rings, 4.0, r_hi, dims, walls, 0.95)
+        out.append(dict(rid=rid, arrival=t, steps=nsteps,
+                        cfg=dict(name=f"req{rid}", lattice=lat, vortex=vor, rho=rho, u=u,
+                                 pos=pos, nxt=nxt, steps=nsteps)))
+    return out

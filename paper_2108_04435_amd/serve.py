@@ -73,7 +73,7 @@ def footprint(cfg, n_cap, recon_cap):
 
 class Server:
     def __init__(self, budget_bytes, max_slots=16, chunk=10, device=0, keep_fields=False,
-                 cap_factor=2.0, recon_cap=1 << 16):
+                 cap_factor=6.0, recon_cap=1 << 16):
         import torch
 
         if chunk < 2 or chunk % 2:
@@ -89,7 +89,7 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
 
     def _n_cap(self, cfg):
-        return max(64, int(cfg["pos"].shape[0] * self.cap_factor) + 256)
+        return max(4096, int(cfg["pos"].shape[0] * self.cap_factor) + 256)
 
     def _admit(self, req, slot, now):
         torch = self.torch
@@ -192,6 +192,7 @@ def summarize(results, makespan):
     return dict(
         requests=len(results),
         errors=sum(1 for r in results if r.error),
+        error_list=[(r.rid, r.error) for r in results if r.error][:8],
         makespan_s=round(makespan, 3),
         latency_p50_s=round(float(np.percentile(lat, 50)), 4),
         latency_p99_s=round(float(np.percentile(lat, 99)), 4),

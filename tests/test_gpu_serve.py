@@ -47,7 +47,7 @@ def test_mix_equals_alone_bitwise():
 
 def test_budget_limits_residency():
     reqs = _requests()[:4]
-    fp = max(serve.footprint(r["cfg"], max(64, int(r["cfg"]["pos"].shape[0] * 2.0) + 256), 1 << 16)
+    fp = max(serve.footprint(r["cfg"], max(4096, int(r["cfg"]["pos"].shape[0] * 6.0) + 256), 1 << 16)
              for r in reqs)
     say("budget", fp)
     srv = serve.Server(budget_bytes=fp + fp // 2, max_slots=4, chunk=4)

@@ -125,6 +125,8 @@ size_t layout(Run& r, char* base) {
     r.rc_idx_a = (int32_t*)B.take(rc * sizeof(int32_t));
     r.rc_key_a = (uint64_t*)B.take(rc * sizeof(uint64_t));
     r.rc_best = (uint64_t*)B.take((nc + 1) * sizeof(uint64_t));
+    r.rc_slot_j = (int32_t*)B.take(8 * (nc + 1) * sizeof(int32_t));
+    r.rc_slot_k = (uint64_t*)B.take(8 * (nc + 1) * sizeof(uint64_t));
     r.rc_bidx = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   }
   r.ub = B.take(3 * cells * fe);
@@ -449,7 +451,8 @@ int one_step(vlb_run* h) {
   double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
   for (int s = 0; s < 4; ++s) {
-    HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
+    // FP32: stages 2-4 use the grid coordinates the previous finalize wrote
+    if (s == 0 || r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
     if (s == 0 && r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));

@@ -4,8 +4,9 @@
 // it (k = prev(j) and k = j; their divergent contribution is the LIA term).
 //
 // Layout and decomposition:
-//  * per point: 32-bit grid coordinates X (3 x u32, SoA) and the segment
-//    vector d_k = s_next(k) - s_k (nearest image; FP32 or FP64, SoA);
+//  * per point: 32-bit grid coordinates X (3 x u32, SoA); the segment
+//    vector d_k = s_next(k) - s_k is the wrapped grid difference in the FP32
+//    sum and an FP64 nearest-image vector in the FP64 sum;
 //  * a 2-D grid: blockIdx.x picks 256 consecutive targets (one per thread),
 //    blockIdx.y one contiguous chunk of sources; the chunk is staged through
 //    LDS in tiles of 256 sources and every thread walks the tile;
@@ -22,21 +23,17 @@ namespace {
 
 constexpr int kTile = 256;
 
-// Grid coordinates and segment vectors of the points at positions Y.  The
-// FP32 path stores the segment vector in grid units when all axes share one
-// grid step (uniform) and in lattice units otherwise, plus its squared
-// length; the FP64 path stores the vector in lattice units.
+// Grid coordinates of the points at positions Y, and for the FP64 path the
+// segment vectors (nearest image, lattice units).  The FP32 sum takes each
+// segment vector as the wrapped grid difference to the successor.
 template <class T>
 __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
-                       int32_t* __restrict__ cnt, long long ncap, BsAxes ax, int uniform,
+                       const int32_t* __restrict__ cnt, long long ncap, BsAxes ax,
                        uint32_t* __restrict__ X, T* __restrict__ D) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
-  // work counter: (target, segment) pairs of the sum that follows
-  if (j == 0 && n > 2) *(long long*)(cnt + 16) += (long long)n * (n - 2);
   if (j >= n) return;
   const int k = nxt[j];
-  T dd = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double y = Y[a * ncap + j];
@@ -49,11 +46,8 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
       else if (d < -0.5 * ax.L[a])
         d = d + ax.L[a];
     }
-    const T dv = uniform ? (T)(d * ax.q[a]) : (T)d;
-    D[a * ncap + j] = dv;
-    dd += dv * dv;
+    if (sizeof(T) == 8) D[a * ncap + j] = (T)d;
   }
-  if (sizeof(T) == 4) D[3 * ncap + j] = dd;
 }
 
 // FP32 pair sum.  Per pair, with R1 = s_k - r (from the grid difference)
@@ -103,12 +97,15 @@ __device__ inline void bs_tile_f32(const uint32_t* sx, const uint32_t* sy, const
 
 template <bool kUniform>
 __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
-                                               const float* __restrict__ D,
+                                               const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
-                                               const int32_t* __restrict__ cntp, long long ncap,
+                                               int32_t* __restrict__ cntp, long long ncap,
                                                int S, float iqx, float iqy, float iqz,
                                                float* __restrict__ P) {
   const int n = cntp[0];
+  // work counter: (target, segment) pairs of this sum
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
+    *(long long*)(cntp + 16) += (long long)n * (n - 2);
   const int j0 = blockIdx.x * 256;
   if (j0 >= n) return;
   const int j = j0 + threadIdx.x;
@@ -127,13 +124,24 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   for (int t0 = kb; t0 < ke; t0 += kTile) {
     const int k = t0 + threadIdx.x;
     if (k < ke) {
-      sx[threadIdx.x] = X[k];
-      sy[threadIdx.x] = X[ncap + k];
-      sz[threadIdx.x] = X[2 * ncap + k];
-      dx[threadIdx.x] = D[k];
-      dy[threadIdx.x] = D[ncap + k];
-      dz[threadIdx.x] = D[2 * ncap + k];
-      dq[threadIdx.x] = D[3 * ncap + k];
+      // segment vector: wrapped grid difference to the successor
+      const int kn = nxt[k];
+      const uint32_t ax0 = X[k], ay0 = X[ncap + k], az0 = X[2 * ncap + k];
+      float ex = (float)(int)(X[kn] - ax0);
+      float ey = (float)(int)(X[ncap + kn] - ay0);
+      float ez = (float)(int)(X[2 * ncap + kn] - az0);
+      if (!kUniform) {
+        ex *= iqx;
+        ey *= iqy;
+        ez *= iqz;
+      }
+      sx[threadIdx.x] = ax0;
+      sy[threadIdx.x] = ay0;
+      sz[threadIdx.x] = az0;
+      dx[threadIdx.x] = ex;
+      dy[threadIdx.x] = ey;
+      dz[threadIdx.x] = ez;
+      dq[threadIdx.x] = ex * ex + ey * ey + ez * ez;
     }
     __syncthreads();
     const int cnt = min(kTile, ke - t0);
@@ -160,10 +168,12 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
                                                const double* __restrict__ D,
                                                const double* __restrict__ Y,
                                                const int32_t* __restrict__ prv,
-                                               const int32_t* __restrict__ cntp, long long ncap,
+                                               int32_t* __restrict__ cntp, long long ncap,
                                                int S, double Lx, double Ly, double Lz,
                                                double* __restrict__ P) {
   const int n = cntp[0];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
+    *(long long*)(cntp + 16) += (long long)n * (n - 2);
   const int j0 = blockIdx.x * 256;
   if (j0 >= n) return;
   const int j = j0 + threadIdx.x;
@@ -237,8 +247,8 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
 
 int bs_chunks(long long ncap) {
   const long long tb = (ncap + 255) / 256;
-  long long S = 4096 / (tb > 0 ? tb : 1);
-  const long long maxS = ncap / 512;
+  long long S = 8192 / (tb > 0 ? tb : 1);
+  const long long maxS = ncap / 256;
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   if (S > 128) S = 128;
@@ -249,10 +259,10 @@ hipError_t bs_prep(Run& r, const double* Y) {
   const int nb = (int)((r.ncap + 255) / 256);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_prep<double>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, 0, r.bsX, (double*)r.bsD);
+                       r.bsax, r.bsX, (double*)r.bsD);
   else
     hipLaunchKernelGGL(k_prep<float>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, r.bsax.uniform, r.bsX, (float*)r.bsD);
+                       r.bsax, r.bsX, (float*)r.bsD);
   return hipGetLastError();
 }
 
@@ -266,11 +276,11 @@ hipError_t bs_sum(Run& r, const double* Y) {
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.L[0], r.bsax.L[1], r.bsax.L[2],
                        (double*)r.bsP);
   else if (r.bsax.uniform)
-    hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
+    hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
                        r.bsax.invq_f[2], (float*)r.bsP);
   else
-    hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, r.stream, r.bsX, (const float*)r.bsD,
+    hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
                        r.bsax.invq_f[2], (float*)r.bsP);
   time_end(r, 0, b);

@@ -43,6 +43,8 @@ struct FinArgs {
   double* vn1;
   double* sd1;
   double* gpt;
+  uint32_t* X;      // grid coordinates of the next stage's positions (FP32 sum), or null
+  BsAxes ax;
 };
 
 // Nearest-image separation on the filament axes (wall axes: plain).
@@ -209,7 +211,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
         break;
     }
     A.ksum[a * nc + j] = ks;
-    A.Ynext[a * nc + j] = wrap_coord(y, L[a], per[a]);
+    const double yw = wrap_coord(y, L[a], per[a]);
+    A.Ynext[a * nc + j] = yw;
+    if (A.X) {
+      const double sgrid = floor((yw + A.ax.off[a]) * A.ax.q[a]);
+      A.X[a * nc + j] = A.ax.periodic[a] ? (uint32_t)(long long)sgrid : (uint32_t)(int)(long long)sgrid;
+    }
   }
 }
 
@@ -422,6 +429,9 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.vn1 = r.vn1;
   A.sd1 = r.sd1;
   A.gpt = r.gpt;
+  // the FP32 sum of the next stage reads grid coordinates written here
+  A.X = (r.prec != VLB_F64 && stage < 4 && !eval_only) ? r.bsX : nullptr;
+  A.ax = r.bsax;
   const int nb = nblocks(r.ncap, 256);
   switch (r.prec) {
     case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;

@@ -1,12 +1,15 @@
-// Stable LSD radix sort of (uint32 key, int32 value) pairs, 8-bit digits,
-// used to bin filament points by lattice cell (force spreading) and by
-// reconnection cell.  No atomics: inside a wave, the lanes that hold the
-// same digit are found with 8 ballots (one per digit bit); their count and
-// each lane's rank among them come from population counts.  Per pass:
-//   1. per-tile digit counts (tiles of 1024 keys, 4 rounds of 256 threads),
-//   2. exclusive scan of the counts in digit-major, tile-minor order,
-//   3. stable scatter: tile offset + running count of the digit in the
-//      tile + earlier waves of the round + rank inside the wave.
+// Stable LSD radix sort of (uint32 key, int32 value) pairs, used to bin
+// filament points by lattice cell (force spreading) and by reconnection
+// cell.  Digits of up to 11 bits (2 passes for keys of up to 22 bits).  No
+// atomics: inside a wave, the lanes holding the same digit are found with
+// one ballot per digit bit; their count and each lane's rank among them
+// come from population counts.  Per pass three kernels:
+//   1. per-tile digit counts (tiles of 1024 keys, 4 rounds of 256 threads);
+//   2. digit offsets of every tile (keys of smaller digits anywhere plus
+//      keys of the same digit in earlier tiles), one workgroup;
+//   3. stable scatter: each key goes to its tile's digit offset + running
+//      count of its digit in the tile + earlier waves of the round + rank
+//      inside the wave.
 // Keys beyond the live points are padded by the caller with the largest
 // key, so they sort to the end.  Nothing is allocated and no memset is
 // issued, so the sort can be captured in a HIP graph.
@@ -19,12 +22,13 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRounds = 4;
 constexpr int kTileKeys = kThreads * kRounds;
+constexpr int kMaxBits = 11;
+constexpr int kMaxBins = 1 << kMaxBits;
 
 // Lanes of this wave whose (valid) digit equals this lane's digit.
-__device__ inline uint64_t peer_mask(uint32_t d, bool valid) {
+__device__ inline uint64_t peer_mask(uint32_t d, bool valid, int bits) {
   uint64_t m = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < bits; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t x = __ballot(valid && bit);
     m &= bit ? x : ~x;
@@ -33,44 +37,89 @@ __device__ inline uint64_t peer_mask(uint32_t d, bool valid) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_rs_count(const uint32_t* __restrict__ keys, int n,
-                                                       int shift, int ntiles,
+                                                       int shift, int bits, int ntiles,
                                                        int32_t* __restrict__ counts) {
-  __shared__ int32_t cw[4][256];
+  __shared__ int32_t cw[4][kMaxBins];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int q = t; q < 4 * 256; q += kThreads) (&cw[0][0])[q] = 0;
+  const int nbins = 1 << bits;
+  const uint32_t mask = (uint32_t)nbins - 1u;
+  for (int q = t; q < 4 * kMaxBins; q += kThreads) (&cw[0][0])[q] = 0;
   __syncthreads();
   const int base = blockIdx.x * kTileKeys;
   for (int q = 0; q < kRounds; ++q) {
     const int idx = base + q * kThreads + t;
     const bool valid = idx < n;
-    const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
-    const uint64_t m = peer_mask(d, valid);
+    const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+    const uint64_t m = peer_mask(d, valid, bits);
     if (valid && (int)(__ffsll((unsigned long long)m) - 1) == lane) cw[w][d] += __popcll(m);
   }
   __syncthreads();
-  counts[t * ntiles + blockIdx.x] = cw[0][t] + cw[1][t] + cw[2][t] + cw[3][t];
+  for (int d = t; d < nbins; d += kThreads)
+    counts[(long long)d * ntiles + blockIdx.x] = cw[0][d] + cw[1][d] + cw[2][d] + cw[3][d];
+}
+
+// Digit offsets of every tile, once per pass (one workgroup): offs[d][b] =
+// number of keys with a smaller digit + keys of digit d in tiles before b.
+__global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__ counts, int bits,
+                                                     int ntiles, int32_t* __restrict__ offs) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int nbins = 1 << bits;
+  const int per = (nbins + 1023) / 1024;  // digits per thread
+  int tot = 0;
+  for (int u = 0; u < per; ++u) {
+    const int d = t * per + u;
+    if (d < nbins) {
+      const int32_t* row = counts + (long long)d * ntiles;
+      for (int b = 0; b < ntiles; ++b) tot += row[b];
+    }
+  }
+  part[t] = tot;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int acc = part[t] - tot;
+  for (int u = 0; u < per; ++u) {
+    const int d = t * per + u;
+    if (d < nbins) {
+      const int32_t* row = counts + (long long)d * ntiles;
+      int32_t* orow = offs + (long long)d * ntiles;
+      for (int b = 0; b < ntiles; ++b) {
+        const int c = row[b];
+        orow[b] = acc;
+        acc += c;
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                          const int32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout,
                                                          int32_t* __restrict__ vout, int n,
-                                                         int shift, int ntiles,
+                                                         int shift, int bits, int ntiles,
                                                          const int32_t* __restrict__ offs) {
-  __shared__ int32_t run[256];
-  __shared__ int32_t cw[4][256];
+  __shared__ int32_t run[kMaxBins];
+  __shared__ int32_t cw[4][kMaxBins];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  run[t] = offs[t * ntiles + blockIdx.x];
+  const int nbins = 1 << bits;
+  const uint32_t mask = (uint32_t)nbins - 1u;
+  for (int d = t; d < nbins; d += kThreads) run[d] = offs[(long long)d * ntiles + blockIdx.x];
+  __syncthreads();
   const int base = blockIdx.x * kTileKeys;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   for (int q = 0; q < kRounds; ++q) {
-    for (int e = lane; e < 256; e += 64) cw[w][e] = 0;
+    for (int e = lane; e < nbins; e += 64) cw[w][e] = 0;
     const int idx = base + q * kThreads + t;
     const bool valid = idx < n;
     const uint32_t k = valid ? kin[idx] : 0u;
     const int32_t v = valid ? vin[idx] : 0;
-    const uint32_t d = (k >> shift) & 255u;
-    const uint64_t m = peer_mask(d, valid);
+    const uint32_t d = (k >> shift) & mask;
+    const uint64_t m = peer_mask(d, valid, bits);
     const int rank = __popcll(m & lt);
     __syncthreads();
     if (valid && (int)(__ffsll((unsigned long long)m) - 1) == lane) cw[w][d] = __popcll(m);
@@ -82,19 +131,16 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
       vout[dst] = v;
     }
     __syncthreads();
-    run[t] += cw[0][t] + cw[1][t] + cw[2][t] + cw[3][t];
+    for (int d2 = t; d2 < nbins; d2 += kThreads) run[d2] += cw[0][d2] + cw[1][d2] + cw[2][d2] + cw[3][d2];
     __syncthreads();
   }
 }
 
 }  // namespace
 
-hipError_t scan_excl(Run& r, const int32_t* in, int32_t* out, const int32_t* np, int n,
-                     int32_t* total);
-
 size_t sort_tmp_bytes(long long n) {
   const long long ntiles = (n + kTileKeys - 1) / kTileKeys;
-  return (size_t)(2 * 256 * ntiles + 16) * sizeof(int32_t);
+  return (size_t)(2 * kMaxBins * ntiles + 16) * sizeof(int32_t);
 }
 
 // Sort ncap pairs (keys_a, vals_a) by the low `bits` bits of the key.
@@ -104,20 +150,21 @@ hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres) {
   const int n = (int)r.ncap;
   const int ntiles = (n + kTileKeys - 1) / kTileKeys;
   int32_t* counts = (int32_t*)r.sort_tmp;
-  int32_t* offs = counts + 256 * ntiles;
-  int32_t* total = offs + 256 * ntiles;
+  int32_t* offs = counts + (long long)kMaxBins * ntiles;
   uint32_t* kin = r.keys_a;
   uint32_t* kout = r.keys_b;
   int32_t* vin = r.vals_a;
   int32_t* vout = r.vals_b;
-  const int passes = (bits + 7) / 8;
+  const int passes = (bits + kMaxBits - 1) / kMaxBits;
+  const int dbits = (bits + passes - 1) / passes;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, n, shift, ntiles, counts);
-    hipError_t e = scan_excl(r, counts, offs, nullptr, 256 * ntiles, total);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, vin, kout, vout, n,
-                       shift, ntiles, offs);
+    const int shift = dbits * p;
+    const int pb = (shift + dbits <= bits) ? dbits : bits - shift;
+    hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, n, shift, pb,
+                       ntiles, counts);
+    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, r.stream, counts, pb, ntiles, offs);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, vin, kout,
+                       vout, n, shift, pb, ntiles, offs);
     uint32_t* tk = kin;
     kin = kout;
     kout = tk;

@@ -365,50 +365,62 @@ __device__ inline void rc_visit(int i, const double* __restrict__ pos,
   }
 }
 
-__global__ void k_rc_count(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                           const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
-                           const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
-                           const int32_t* __restrict__ cnt,
-                           long long nc, TopoGeom tg, BinGeom bg, double d2max,
-                           int32_t* __restrict__ count) {
+// One search per point: candidates j > i go into the point's own slots
+// (at most kSlots, kept sorted by j), with their count; a point with more
+// candidates than slots latches the reconnection-capacity flag, and the
+// step then skips reconnection (the candidate set must be complete).  The
+// kernel also clears the point's `used` flag for the matching.
+constexpr int kSlots = 8;
+
+__global__ void k_rc_find(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                          const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
+                          const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
+                          int32_t* __restrict__ cnt, long long nc, TopoGeom tg, BinGeom bg,
+                          double d2max, int32_t* __restrict__ count, int32_t* __restrict__ slot_j,
+                          uint64_t* __restrict__ slot_k, int32_t* __restrict__ used) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
   if (i >= n) return;
-  int c = 0;
-  rc_visit(i, pos, nxt, prv, skey, sval, bins, n, nc, tg, bg, d2max, [&](int, double) { ++c; });
-  count[i] = c;
-}
-
-__global__ void k_rc_write(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                           const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
-                           const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
-                           int32_t* __restrict__ cnt,
-                           long long nc, TopoGeom tg, BinGeom bg, double d2max,
-                           const int32_t* __restrict__ off, long long rcap,
-                           int32_t* __restrict__ ci, int32_t* __restrict__ cj,
-                           uint64_t* __restrict__ ckey, int32_t* __restrict__ cidx) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = cnt[0];
-  if (i == 0 && cnt[6] > rcap) atomicOr(&cnt[7], kFlagReconCap);
-  if (i >= n || cnt[6] > rcap) return;
-  const int o0 = off[i];
+  used[i] = 0;
   int m = 0;
+  int32_t* sj = slot_j + (long long)i * kSlots;
+  uint64_t* sk = slot_k + (long long)i * kSlots;
   rc_visit(i, pos, nxt, prv, skey, sval, bins, n, nc, tg, bg, d2max, [&](int j, double d2) {
-    const int at = o0 + m;
-    // insertion into the run [o0, at) kept sorted by j
-    int p = at;
-    while (p > o0 && cj[p - 1] > j) {
-      cj[p] = cj[p - 1];
-      ckey[p] = ckey[p - 1];
-      --p;
+    if (m < kSlots) {
+      int p = m;
+      while (p > 0 && sj[p - 1] > j) {
+        sj[p] = sj[p - 1];
+        sk[p] = sk[p - 1];
+        --p;
+      }
+      sj[p] = j;
+      sk[p] = (uint64_t)__double_as_longlong(d2);
     }
-    cj[p] = j;
-    ckey[p] = (uint64_t)__double_as_longlong(d2);
     ++m;
   });
-  for (int t = o0; t < o0 + m; ++t) {
-    ci[t] = i;
-    cidx[t] = t;
+  if (m > kSlots) {
+    atomicOr(&cnt[7], kFlagReconCap);
+    atomicOr(&cnt[10], 1);
+  }
+  count[i] = m < kSlots ? m : kSlots;
+}
+
+// Candidates in (i, j) order into the compact list; overflow of the list or
+// of a point's slots leaves the list empty (reconnection skipped).
+__global__ void k_rc_compact(const int32_t* __restrict__ count, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ slot_j, const uint64_t* __restrict__ slot_k,
+                             int32_t* __restrict__ cnt, long long rcap, int32_t* __restrict__ ci,
+                             int32_t* __restrict__ cj, uint64_t* __restrict__ ckey) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = cnt[0];
+  const bool skip = cnt[10] != 0 || cnt[6] > rcap;
+  if (i == 0 && cnt[6] > rcap) atomicOr(&cnt[7], kFlagReconCap);
+  if (i >= n || skip) return;
+  const int o = off[i];
+  for (int m = 0; m < count[i]; ++m) {
+    ci[o + m] = i;
+    cj[o + m] = slot_j[(long long)i * kSlots + m];
+    ckey[o + m] = slot_k[(long long)i * kSlots + m];
   }
 }
 
@@ -429,12 +441,16 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
                                                    int32_t* __restrict__ live,
                                                    uint64_t* __restrict__ bkey,
                                                    int32_t* __restrict__ bidx,
-                                                   int32_t* __restrict__ used) {
+                                                   int32_t* __restrict__ used,
+                                                   int32_t* __restrict__ del_out) {
   __shared__ int s_live;
   __shared__ int s_taken;
-  const int tot = cnt[6];
-  if (tot > rcap) return;
   const int t = threadIdx.x;
+  const int n = cnt[0];
+  // prepare the small-loop pass that follows: nothing deleted, bound n
+  for (int j = t; j < n; j += blockDim.x) del_out[j] = 0;
+  if (t == 0) cnt[9] = n;
+  const int tot = (cnt[10] != 0 || cnt[6] > rcap) ? 0 : cnt[6];
   for (int c = t; c < tot; c += blockDim.x) live[c] = 1;
   if (t == 0) s_taken = 0;
   __syncthreads();
@@ -493,12 +509,12 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
     if (s_live == 0) break;
     __syncthreads();
   }
-  if (t == 0) cnt[4] = s_taken;
+  if (t == 0) {
+    cnt[4] = s_taken;
+    cnt[10] = 0;
+  }
 }
 
-__global__ void k_set_bound(int32_t* cnt) {
-  if (threadIdx.x == 0) cnt[9] = cnt[0];
-}
 
 inline int nb_of(long long n, int b) { return (int)((n + b - 1) / b); }
 
@@ -577,19 +593,16 @@ hipError_t topo_update(Run& r) {
     if (e != hipSuccess) return e;
     e = bins_mark(r, sk, 1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rc_count, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk,
-                       sv, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 6);
-    hipLaunchKernelGGL(k_rc_write, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk,
-                       sv, r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_b, r.rcap, r.rc_i,
-                       r.rc_j, r.rc_key_a, r.rc_idx_a);
+    hipLaunchKernelGGL(k_rc_find, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk, sv,
+                       r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a, r.rc_slot_j, r.rc_slot_k,
+                       r.used);
     e = bins_mark(r, sk, 0);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, r.used, r.ncap, 0);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 6);
+    hipLaunchKernelGGL(k_rc_compact, dim3(nb), dim3(256), 0, r.stream, r.scan_a, r.scan_b,
+                       r.rc_slot_j, r.rc_slot_k, r.cnt, r.rcap, r.rc_i, r.rc_j, r.rc_key_a);
     hipLaunchKernelGGL(k_rc_match, dim3(1), dim3(1024), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,
-                       r.rc_i, r.rc_j, r.rc_key_a, r.rc_idx_a, r.rc_best, r.rc_bidx, r.used);
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, del, r.ncap, 0);
-    hipLaunchKernelGGL(k_set_bound, dim3(1), dim3(64), 0, r.stream, r.cnt);
+                       r.rc_i, r.rc_j, r.rc_key_a, r.rc_idx_a, r.rc_best, r.rc_bidx, r.used, del);
     e = small_and_compact(r, del);
     if (e != hipSuccess) return e;
   }

@@ -244,7 +244,8 @@ struct Run {
 
   // counters on the device: [0] n points, [1] n touched slots,
   // [2] inserted, [3] deleted, [4] reconnections, [5] small-loop points,
-  // [6] candidates, [7] error flags
+  // [6] candidates, [7] error flags, [8] compacted count, [9] bound of the
+  // small-loop pass, [10] candidate-slot overflow, [16..17] pair counter
   int32_t* cnt = nullptr;
 
   // sorting / scans
@@ -269,6 +270,8 @@ struct Run {
   int32_t* rc_j = nullptr;
   uint64_t* rc_key_a = nullptr;  // candidate keys (bits of d^2)
   int32_t* rc_idx_a = nullptr;   // candidate liveness during matching
+  int32_t* rc_slot_j = nullptr;  // per point: up to 8 candidate partners
+  uint64_t* rc_slot_k = nullptr; // per point: their keys
   uint64_t* rc_best = nullptr;   // per point: smallest live key
   int32_t* rc_bidx = nullptr;    // per point: smallest live candidate of that key
   int32_t* used = nullptr;

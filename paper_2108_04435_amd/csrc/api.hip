@@ -118,7 +118,15 @@ size_t layout(Run& r, char* base) {
   r.vals_b = (int32_t*)B.take(nc * sizeof(int32_t));
   r.sort_tmp_bytes = sort_tmp_bytes(nc);
   r.sort_tmp = B.take(r.sort_tmp_bytes);
+  {
+    const long long nw = (nc + 255) / 256 * 4;  // waves of the per-point grids
+    r.wmask = (uint64_t*)B.take(nw * sizeof(uint64_t));
+    r.wpre = (int32_t*)B.take((nw + 1) * sizeof(int32_t));
+  }
   if (r.vor.reconnect) {
+    r.rc_head = (int32_t*)B.take((size_t)r.rc_nbins * sizeof(int32_t));
+    r.rc_next = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
+    r.rc_keyp = (uint32_t*)B.take((nc + 1) * sizeof(uint32_t));
     const long long rc = r.rcap;
     r.rc_i = (int32_t*)B.take(rc * sizeof(int32_t));
     r.rc_j = (int32_t*)B.take(rc * sizeof(int32_t));
@@ -220,9 +228,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
       r.bin_h[a] = (double)n[a] / nb;
       tot *= (unsigned long long)nb;
     }
-    r.bin_bits = bits_for(tot);
-    if (r.bin_bits > 32) r.bin_bits = 32;
-    if ((long long)tot > r.nbins_table) r.nbins_table = (long long)tot;
+    r.rc_nbins = (long long)tot;
   }
 }
 
@@ -371,6 +377,8 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.bins, 0xFF, (size_t)r.nbins_table * sizeof(int32_t), r.stream);
+  if (e == hipSuccess && r.rc_head)
+    e = hipMemsetAsync(r.rc_head, 0xFF, (size_t)r.rc_nbins * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r.stream);
   if (e != hipSuccess) {
     std::string m = std::string("initialising the workspace: ") + hipGetErrorString(e);

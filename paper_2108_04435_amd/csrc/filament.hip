@@ -106,22 +106,49 @@ __device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, d
   }
 }
 
+// 64 points per block of 256 threads: the four waves add the Biot-Savart
+// chunk partials of the block's points (wave g takes chunks g, g + 4, ...,
+// four chunks' loads in flight at a time), wave 0 combines the four sums in
+// a fixed order and does the per-point work.
+constexpr int kFinPts = 64;
+
 template <class UT, class PT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double red[3][3][kFinPts];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int j = blockIdx.x * kFinPts + lane;
   const int n = A.cnt[0];
-  if (j >= n) return;
   const long long nc = A.ncap;
-  const Geom& g = A.g;
-  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
-  const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
 
   // non-local Biot-Savart: chunk partials added in a fixed order
   double vs[3] = {0.0, 0.0, 0.0};
-  const PT* P = (const PT*)A.P;
-  for (int s = 0; s < A.S; ++s)
-    for (int a = 0; a < 3; ++a) vs[a] += (double)P[((long long)s * 3 + a) * nc + j];
-  for (int a = 0; a < 3; ++a) vs[a] *= A.nl_scale;
+  if (j < n) {
+    const PT* __restrict__ P = (const PT*)A.P;
+    int s = grp;
+    for (; s + 12 < A.S; s += 16) {
+      PT v[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[u][a] = P[((long long)(s + 4 * u) * 3 + a) * nc + j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vs[a] += (double)v[u][a];
+    }
+    for (; s < A.S; s += 4)
+      for (int a = 0; a < 3; ++a) vs[a] += (double)P[((long long)s * 3 + a) * nc + j];
+  }
+  if (grp > 0)
+    for (int a = 0; a < 3; ++a) red[grp - 1][a][lane] = vs[a];
+  __syncthreads();
+  if (grp > 0 || j >= n) return;
+  for (int a = 0; a < 3; ++a)
+    vs[a] = (((vs[a] + red[0][a][lane]) + red[1][a][lane]) + red[2][a][lane]) * A.nl_scale;
+
+  const Geom& g = A.g;
+  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+  const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
 
   // local geometry (three-point derivatives on a non-uniform arc length)
   const int jn = A.nxt[j], jp = A.prv[j];
@@ -392,12 +419,6 @@ SpreadGeom spread_geom(const Run& r) {
 
 }  // namespace
 
-hipError_t bins_mark(Run& r, const uint32_t* skey, int set) {
-  hipLaunchKernelGGL(k_bin_mark, dim3(nblocks(r.ncap, 256)), dim3(256), 0, r.stream, skey, r.cnt,
-                     r.bins, set);
-  return hipGetLastError();
-}
-
 hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only) {
   FinArgs A;
   A.ub = r.ub;
@@ -432,7 +453,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   // the FP32 sum of the next stage reads grid coordinates written here
   A.X = (r.prec != VLB_F64 && stage < 4 && !eval_only) ? r.bsX : nullptr;
   A.ax = r.bsax;
-  const int nb = nblocks(r.ncap, 256);
+  const int nb = nblocks(r.ncap, kFinPts);
   switch (r.prec) {
     case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;
     default: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(256), 0, r.stream, A); break;

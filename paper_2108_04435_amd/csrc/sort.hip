@@ -6,7 +6,8 @@
 // come from population counts.  Per pass three kernels:
 //   1. per-tile digit counts (tiles of 1024 keys, 4 rounds of 256 threads);
 //   2. digit offsets of every tile (keys of smaller digits anywhere plus
-//      keys of the same digit in earlier tiles), one workgroup;
+//      keys of the same digit in earlier tiles): a one-workgroup exclusive
+//      scan of the digit-major count table;
 //   3. stable scatter: each key goes to its tile's digit offset + running
 //      count of its digit in the tile + earlier waves of the round + rank
 //      inside the wave.
@@ -59,41 +60,66 @@ __global__ __launch_bounds__(kThreads) void k_rs_count(const uint32_t* __restric
 }
 
 // Digit offsets of every tile, once per pass (one workgroup): offs[d][b] =
-// number of keys with a smaller digit + keys of digit d in tiles before b.
-__global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__ counts, int bits,
-                                                     int ntiles, int32_t* __restrict__ offs) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
-  const int nbins = 1 << bits;
-  const int per = (nbins + 1023) / 1024;  // digits per thread
-  int tot = 0;
-  for (int u = 0; u < per; ++u) {
-    const int d = t * per + u;
-    if (d < nbins) {
-      const int32_t* row = counts + (long long)d * ntiles;
-      for (int b = 0; b < ntiles; ++b) tot += row[b];
-    }
-  }
-  part[t] = tot;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int acc = part[t] - tot;
-  for (int u = 0; u < per; ++u) {
-    const int d = t * per + u;
-    if (d < nbins) {
-      const int32_t* row = counts + (long long)d * ntiles;
-      int32_t* orow = offs + (long long)d * ntiles;
-      for (int b = 0; b < ntiles; ++b) {
-        const int c = row[b];
-        orow[b] = acc;
-        acc += c;
+// number of keys with a smaller digit + keys of digit d in tiles before b,
+// i.e. the exclusive prefix of the digit-major count table read as one
+// array.  Each thread takes 16 consecutive entries per round (vector loads
+// where the round is full).
+__global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__ counts, int M,
+                                                     int32_t* __restrict__ offs) {
+  __shared__ int32_t wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int carry = 0;
+  for (int base = 0; base < M; base += 16 * 1024) {
+    const int k0 = base + 16 * t;
+    const bool full = k0 + 16 <= M;
+    int v[16];
+    if (full) {
+      const int4* p = reinterpret_cast<const int4*>(counts + k0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int4 x = p[q];
+        v[4 * q] = x.x;
+        v[4 * q + 1] = x.y;
+        v[4 * q + 2] = x.z;
+        v[4 * q + 3] = x.w;
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (k0 + q < M) ? counts[k0 + q] : 0;
     }
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) mine += v[q];
+    int x = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int u = 0; u < 16; ++u) {
+      before += u < w ? wsum[u] : 0;
+      all += wsum[u];
+    }
+    int run = carry + before + x - mine;
+    int o[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      o[q] = run;
+      run += v[q];
+    }
+    if (full) {
+      int4* p = reinterpret_cast<int4*>(offs + k0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (k0 + q < M) offs[k0 + q] = o[q];
+    }
+    carry += all;
+    __syncthreads();
   }
 }
 
@@ -140,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restr
 
 size_t sort_tmp_bytes(long long n) {
   const long long ntiles = (n + kTileKeys - 1) / kTileKeys;
-  return (size_t)(2 * kMaxBins * ntiles + 16) * sizeof(int32_t);
+  return (size_t)(2 * (((long long)kMaxBins * ntiles + 63) & ~63LL) + 16) * sizeof(int32_t);
 }
 
 // Sort ncap pairs (keys_a, vals_a) by the low `bits` bits of the key.
@@ -150,7 +176,7 @@ hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres) {
   const int n = (int)r.ncap;
   const int ntiles = (n + kTileKeys - 1) / kTileKeys;
   int32_t* counts = (int32_t*)r.sort_tmp;
-  int32_t* offs = counts + (long long)kMaxBins * ntiles;
+  int32_t* offs = counts + (((long long)kMaxBins * ntiles + 63) & ~63LL);
   uint32_t* kin = r.keys_a;
   uint32_t* kout = r.keys_b;
   int32_t* vin = r.vals_a;
@@ -162,7 +188,7 @@ hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres) {
     const int pb = (shift + dbits <= bits) ? dbits : bits - shift;
     hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, n, shift, pb,
                        ntiles, counts);
-    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, r.stream, counts, pb, ntiles, offs);
+    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, r.stream, counts, ntiles << pb, offs);
     hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, vin, kout,
                        vout, n, shift, pb, ntiles, offs);
     uint32_t* tk = kin;

@@ -60,24 +60,37 @@ __device__ inline double wrap1(double x, double L, int periodic) {
   return x;
 }
 
-// ---- single-workgroup exclusive scan of n ints (n read from *np): tiles
-// of 4096 values, 4 consecutive values per thread, wave prefix sums with
-// shuffles, wave totals combined in LDS, a running carry between tiles.
-__global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in,
-                                                    int32_t* __restrict__ out,
-                                                    const int32_t* __restrict__ np, int nconst,
-                                                    int32_t* __restrict__ total) {
-  __shared__ int32_t wsum[16];
-  const int n = np ? *np : nconst;
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int w = t >> 6;
+// ---- ranks of flagged points without a separate scan kernel.  Every wave
+// stores the ballot of its flags and their count; the last block of the
+// grid to arrive (integer ticket, reset by that block) turns the per-wave
+// counts into exclusive prefixes.  The rank of a flagged point x is then
+// pre[x / 64] + the flags below it in its wave.
+constexpr int kBlock = 256;
+
+__device__ inline uint64_t lanes_below(int lane) {
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__device__ inline int flag_rank(const uint64_t* __restrict__ mask, const int32_t* __restrict__ pre,
+                                int x) {
+  const int w = x >> 6;
+  return pre[w] + __popcll(mask[w] & lanes_below(x & 63));
+}
+
+__device__ inline bool flag_bit(const uint64_t* __restrict__ mask, int x) {
+  return (mask[x >> 6] >> (x & 63)) & 1ull;
+}
+
+// Exclusive scan of a[0..n) in place by one block of kBlock threads.
+__device__ void block_scan_inplace(int32_t* a, int n, int32_t* total) {
+  __shared__ int32_t wsum[kBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int carry = 0;
-  for (int base = 0; base < n; base += 4096) {
+  for (int base = 0; base < n; base += 4 * kBlock) {
     const int k0 = base + 4 * t;
     int v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? in[k0 + q] : 0;
+    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? a[k0 + q] : 0;
     const int mine = v[0] + v[1] + v[2] + v[3];
     int x = mine;
     for (int off = 1; off < 64; off <<= 1) {
@@ -86,46 +99,61 @@ __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ 
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    if (w == 0) {
-      int s = lane < 16 ? wsum[lane] : 0;
-      for (int off = 1; off < 16; off <<= 1) {
-        const int y = __shfl_up(s, off, 64);
-        if (lane >= off) s += y;
-      }
-      if (lane < 16) wsum[lane] = s;
+    int before = 0, all = 0;
+    for (int u = 0; u < kBlock / 64; ++u) {
+      before += u < w ? wsum[u] : 0;
+      all += wsum[u];
     }
-    __syncthreads();
-    int run = carry + (w > 0 ? wsum[w - 1] : 0) + x - mine;
+    int run = carry + before + x - mine;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (k0 + q < n) out[k0 + q] = run;
+      if (k0 + q < n) a[k0 + q] = run;
       run += v[q];
     }
-    carry += wsum[15];
+    carry += all;
     __syncthreads();
   }
   if (t == 0) *total = carry;
 }
 
-__global__ void k_reset_stats(int32_t* cnt) {
-  if (threadIdx.x == 0) {
-    cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
-    cnt[9] = cnt[0];
+// Called by every thread of every block of a one-dimensional grid of kBlock
+// threads (no thread may have returned before).
+__device__ void wave_scan_commit(bool flag, uint64_t* __restrict__ mask, int32_t* __restrict__ pre,
+                                 int32_t* ticket, int32_t* total) {
+  __shared__ int s_last;
+  const int t = threadIdx.x;
+  const int w = (blockIdx.x * kBlock + t) >> 6;
+  const uint64_t m = __ballot(flag);
+  if ((t & 63) == 0) {
+    mask[w] = m;
+    pre[w] = __popcll(m);
   }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) s_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  block_scan_inplace(pre, gridDim.x * (kBlock / 64), total);
+  if (t == 0) *ticket = 0;
+}
+
+__global__ void k_reset_stats(int32_t* cnt) {
+  if (threadIdx.x == 0) cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
 }
 
 // Deletion candidate: incoming segment shorter than dxi_min, and the chord
 // that would replace the point's two segments not longer than dxi_max.
-__global__ void k_rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                          const int32_t* __restrict__ prv, const int32_t* __restrict__ cnt,
-                          long long nc, TopoGeom tg, double mn2, double mx2,
-                          int32_t* __restrict__ cand) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[0]) return;
-  double d[3], c[3];
-  sep(pos, nc, prv[j], j, tg, d);
-  sep(pos, nc, prv[j], nxt[j], tg, c);
-  cand[j] = (sq3(d) < mn2 && sq3(c) <= mx2) ? 1 : 0;
+__device__ inline bool rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                               const int32_t* __restrict__ prv, long long nc, const TopoGeom& tg,
+                               double mn2, double mx2, int j) {
+  const int p = prv[j];
+  double d[3];
+  sep(pos, nc, p, j, tg, d);
+  if (!(sq3(d) < mn2)) return false;
+  double c[3];
+  sep(pos, nc, p, nxt[j], tg, c);
+  return sq3(c) <= mx2;
 }
 
 // Along each run of consecutive deletion candidates every other point is
@@ -133,17 +161,24 @@ __global__ void k_rm_cand(const double* __restrict__ pos, const int32_t* __restr
 // it (walking back, at most kChainLimit) is even and below the limit; a
 // loop made only of candidates is counted from its lowest index and keeps
 // its last point when its length is odd.  No two neighbours are deleted.
+// Candidacy of the points walked over is evaluated on the way.  Block 0
+// also clears the step's statistics counters.
 constexpr int kChainLimit = 32;
 
-__global__ void k_rm_del(const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
-                         int32_t* __restrict__ cnt, const int32_t* __restrict__ cand,
-                         int32_t* __restrict__ del) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[0]) return;
+__global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ pos,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ prv,
+                                                    int32_t* __restrict__ cnt, long long nc,
+                                                    TopoGeom tg, double mn2, double mx2,
+                                                    int32_t* __restrict__ del) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int n = cnt[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
+  if (j >= n) return;
   int dd = 0;
-  if (cand[j]) {
+  if (rm_cand(pos, nxt, prv, nc, tg, mn2, mx2, j)) {
     int c = 0, p = prv[j];
-    while (c < kChainLimit && cand[p] && p != j) {
+    while (c < kChainLimit && p != j && rm_cand(pos, nxt, prv, nc, tg, mn2, mx2, p)) {
       ++c;
       p = prv[p];
     }
@@ -157,44 +192,62 @@ __global__ void k_rm_del(const int32_t* __restrict__ nxt, const int32_t* __restr
           tm = t;
         }
       }
-      const int pos = (L - tm) % L;
-      dd = ((pos & 1) == 0 && !(pos == L - 1 && (L & 1))) ? 1 : 0;
+      const int ps = (L - tm) % L;
+      dd = ((ps & 1) == 0 && !(ps == L - 1 && (L & 1))) ? 1 : 0;
     } else {
       dd = (c < kChainLimit && (c & 1) == 0) ? 1 : 0;
     }
   }
   del[j] = dd;
-  if (dd) atomicAdd(&cnt[3], 1);
 }
 
-__global__ void k_rm_relink(int32_t* __restrict__ nxt, int32_t* __restrict__ prv,
-                            const int32_t* __restrict__ cnt, const int32_t* __restrict__ del) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[0] || !del[j]) return;
-  const int p = prv[j], q = nxt[j];
-  nxt[p] = q;
-  prv[q] = p;
-}
-
-__global__ void k_rm_insmark(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                             const int32_t* __restrict__ cnt, long long nc, TopoGeom tg,
-                             double mx2, const int32_t* __restrict__ del, int32_t* __restrict__ ins) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[0]) return;
-  int v = 0;
-  if (!del[j]) {
-    double d[3];
-    sep(pos, nc, j, nxt[j], tg, d);
-    v = sq3(d) > mx2 ? 1 : 0;
+// Deleted points are unlinked; every kept point whose segment (to its
+// successor after the unlinking) is longer than dxi_max is flagged for a
+// midpoint, and the flags are ranked.  A kept point may read its successor
+// link before or after the deleted successor rewrote it: both lead to the
+// same new successor, since deleted points have kept neighbours.
+__global__ __launch_bounds__(kBlock) void k_rm_link(const double* __restrict__ pos,
+                                                    int32_t* __restrict__ nxt,
+                                                    int32_t* __restrict__ prv,
+                                                    int32_t* __restrict__ cnt, long long nc,
+                                                    TopoGeom tg, double mx2,
+                                                    const int32_t* __restrict__ del,
+                                                    uint64_t* __restrict__ imask,
+                                                    int32_t* __restrict__ ipre,
+                                                    int32_t* ticket) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int n = cnt[0];
+  const bool valid = j < n;
+  const int dj = valid ? del[j] : 0;
+  bool ins = false;
+  if (valid) {
+    if (dj) {
+      const int p = prv[j], q = nxt[j];
+      __hip_atomic_store(&nxt[p], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prv[q] = p;
+    } else {
+      int s = __hip_atomic_load(&nxt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (del[s]) s = nxt[s];
+      double d[3];
+      sep(pos, nc, j, s, tg, d);
+      ins = sq3(d) > mx2;
+    }
   }
-  ins[j] = v;
+  const uint64_t dm = __ballot(dj != 0);
+  if ((threadIdx.x & 63) == 0 && dm) atomicAdd(&cnt[3], (int)__popcll(dm));
+  wave_scan_commit(ins, imask, ipre, ticket, cnt + 2);
 }
 
-__global__ void k_rm_insert(double* __restrict__ pos, int32_t* __restrict__ nxt,
-                            int32_t* __restrict__ prv, int32_t* __restrict__ cnt, long long nc,
-                            TopoGeom tg, int32_t* __restrict__ del, const int32_t* __restrict__ ins,
-                            const int32_t* __restrict__ rank) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Midpoints of the flagged segments, appended at n + rank in ascending
+// segment order; all or none (capacity).
+__global__ __launch_bounds__(kBlock) void k_rm_insert(double* __restrict__ pos,
+                                                      int32_t* __restrict__ nxt,
+                                                      int32_t* __restrict__ prv,
+                                                      int32_t* __restrict__ cnt, long long nc,
+                                                      TopoGeom tg, int32_t* __restrict__ del,
+                                                      const uint64_t* __restrict__ imask,
+                                                      const int32_t* __restrict__ ipre) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
   const int n = cnt[0];
   const int M = cnt[2];
   const bool fits = (long long)n + M <= nc;
@@ -202,8 +255,9 @@ __global__ void k_rm_insert(double* __restrict__ pos, int32_t* __restrict__ nxt,
     cnt[9] = fits ? n + M : n;
     if (!fits && M > 0) atomicOr(&cnt[7], kFlagCapacity);
   }
-  if (j >= n || !fits || !ins[j]) return;
-  const int q = n + rank[j];
+  if (j >= n || !fits || !flag_bit(imask, j)) return;
+  const int q = n + flag_rank(imask, ipre, j);
+  if (q >= nc) return;
   const int k = nxt[j];
   double d[3];
   sep(pos, nc, j, k, tg, d);
@@ -216,58 +270,7 @@ __global__ void k_rm_insert(double* __restrict__ pos, int32_t* __restrict__ nxt,
   del[q] = 0;
 }
 
-// alive = not deleted and not on a loop with fewer than min_pts points
-__global__ void k_small(const int32_t* __restrict__ nxt, int32_t* __restrict__ cnt,
-                        const int32_t* __restrict__ del, int min_pts, int32_t* __restrict__ alive) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[9]) return;
-  if (del[j]) {
-    alive[j] = 0;
-    return;
-  }
-  int p = nxt[j];
-  int steps = 1;
-  while (p != j && steps < min_pts) {
-    p = nxt[p];
-    ++steps;
-  }
-  const int dead = (p == j && steps < min_pts) ? 1 : 0;
-  alive[j] = 1 - dead;
-  if (dead) atomicAdd(&cnt[5], 1);
-}
-
-__global__ void k_compact_scatter(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                                  const int32_t* __restrict__ prv, const int32_t* __restrict__ cnt,
-                                  long long nc, const int32_t* __restrict__ alive,
-                                  const int32_t* __restrict__ idx, double* __restrict__ pos_t,
-                                  int32_t* __restrict__ nxt_t, int32_t* __restrict__ prv_t) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[9] || !alive[j]) return;
-  const int q = idx[j];
-  for (int a = 0; a < 3; ++a) pos_t[a * nc + q] = pos[a * nc + j];
-  nxt_t[q] = idx[nxt[j]];
-  prv_t[q] = idx[prv[j]];
-}
-
-__global__ void k_compact_copy(double* __restrict__ pos, int32_t* __restrict__ nxt,
-                               int32_t* __restrict__ prv, int32_t* __restrict__ cnt, long long nc,
-                               const double* __restrict__ pos_t, const int32_t* __restrict__ nxt_t,
-                               const int32_t* __restrict__ prv_t) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nn = cnt[8];
-  if (q == 0) cnt[0] = nn;
-  if (q >= nn) return;
-  for (int a = 0; a < 3; ++a) pos[a * nc + q] = pos_t[a * nc + q];
-  nxt[q] = nxt_t[q];
-  prv[q] = prv_t[q];
-}
-
-__global__ void k_fill(int32_t* __restrict__ p, long long n, int32_t v) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-// ---- reconnection
+// ---- reconnection bins
 struct BinGeom {
   int nb[3];
   double h[3];
@@ -282,22 +285,105 @@ __device__ inline int bin_of(double x, const BinGeom& bg, int a) {
   return b;
 }
 
-__global__ void k_rc_keys(const double* __restrict__ pos, const int32_t* __restrict__ cnt,
-                          long long nc, BinGeom bg, uint32_t pad, uint32_t* __restrict__ keys,
-                          int32_t* __restrict__ vals) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nc) return;
-  uint32_t k = pad;
-  if (j < cnt[0]) {
-    const int bx = bin_of(pos[j], bg, 0);
-    const int by = bin_of(pos[nc + j], bg, 1);
-    const int bz = bin_of(pos[2 * nc + j], bg, 2);
-    k = (uint32_t)(((long long)bz * bg.nb[1] + by) * bg.nb[0] + bx);
+// Small-loop pass over the points below the bound: a point is alive when
+// it is kept (not deleted / alive before) and its loop has at least
+// min_pts points.  Optionally the alive points are pushed on per-bin lists
+// for the reconnection search (integer exchange on the bin head; the order
+// inside a list is irrelevant, every consumer sorts what it collects), or
+// the lists of an earlier pass are cleared, or the alive points are ranked
+// for the compaction.
+struct SmallArgs {
+  const double* pos;
+  const int32_t* nxt;
+  int32_t* cnt;
+  long long nc;
+  int bound9;               // 1: bound = cnt[9]; 0: bound = cnt[0], and cnt[9] := bound
+  const int32_t* dead_in;   // 1 = deleted (or null)
+  const int32_t* alive_in;  // 1 = alive before this pass (or null)
+  int32_t* alive_out;       // or null
+  int min_pts;
+  int rc_mode;              // 0: none, 1: push on bin lists, 2: clear bin heads
+  BinGeom bg;
+  int32_t* rc_head;
+  int32_t* rc_next;
+  uint32_t* rc_key;
+  uint64_t* mask;           // ranks of the alive points (null: none)
+  int32_t* pre;
+  int32_t* ticket;
+};
+
+__global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int bound = A.bound9 ? A.cnt[9] : A.cnt[0];
+  if (!A.bound9 && j == 0) A.cnt[9] = bound;
+  const bool valid = j < bound;
+  bool in = valid;
+  if (in && A.dead_in) in = A.dead_in[j] == 0;
+  if (in && A.alive_in) in = A.alive_in[j] != 0;
+  bool alive = false;
+  if (in) {
+    int p = A.nxt[j];
+    int steps = 1;
+    while (p != j && steps < A.min_pts) {
+      p = A.nxt[p];
+      ++steps;
+    }
+    alive = !(p == j && steps < A.min_pts);
   }
-  keys[j] = k;
-  vals[j] = j;
+  if (valid && A.alive_out) A.alive_out[j] = alive ? 1 : 0;
+  const uint64_t dm = __ballot(in && !alive);
+  if ((threadIdx.x & 63) == 0 && dm) atomicAdd(&A.cnt[5], (int)__popcll(dm));
+  if (A.rc_mode == 1 && alive) {
+    const long long nc = A.nc;
+    const int bx = bin_of(A.pos[j], A.bg, 0);
+    const int by = bin_of(A.pos[nc + j], A.bg, 1);
+    const int bz = bin_of(A.pos[2 * nc + j], A.bg, 2);
+    const uint32_t key = (uint32_t)(((long long)bz * A.bg.nb[1] + by) * A.bg.nb[0] + bx);
+    A.rc_key[j] = key;
+    A.rc_next[j] = atomicExch(&A.rc_head[key], j);
+  }
+  if (A.rc_mode == 2 && in) A.rc_head[A.rc_key[j]] = -1;
+  if (A.mask) wave_scan_commit(alive, A.mask, A.pre, A.ticket, A.cnt + 8);
 }
 
+// Stable compaction of the alive points into the scratch arrays, links
+// renumbered through the ranks; then copied back.
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(const double* __restrict__ pos,
+                                                            const int32_t* __restrict__ nxt,
+                                                            const int32_t* __restrict__ prv,
+                                                            const int32_t* __restrict__ cnt,
+                                                            long long nc,
+                                                            const uint64_t* __restrict__ mask,
+                                                            const int32_t* __restrict__ pre,
+                                                            double* __restrict__ pos_t,
+                                                            int32_t* __restrict__ nxt_t,
+                                                            int32_t* __restrict__ prv_t) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= cnt[9] || !flag_bit(mask, j)) return;
+  const int q = flag_rank(mask, pre, j);
+  if (q >= nc) return;
+  for (int a = 0; a < 3; ++a) pos_t[a * nc + q] = pos[a * nc + j];
+  nxt_t[q] = flag_rank(mask, pre, nxt[j]);
+  prv_t[q] = flag_rank(mask, pre, prv[j]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_copy(double* __restrict__ pos,
+                                                         int32_t* __restrict__ nxt,
+                                                         int32_t* __restrict__ prv,
+                                                         int32_t* __restrict__ cnt, long long nc,
+                                                         const double* __restrict__ pos_t,
+                                                         const int32_t* __restrict__ nxt_t,
+                                                         const int32_t* __restrict__ prv_t) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  const int nn = cnt[8];
+  if (q == 0) cnt[0] = nn;
+  if (q >= nn) return;
+  for (int a = 0; a < 3; ++a) pos[a * nc + q] = pos_t[a * nc + q];
+  nxt[q] = nxt_t[q];
+  prv[q] = prv_t[q];
+}
+
+// ---- reconnection search
 // Offsets of the neighbouring bins along one axis (no duplicates when the
 // periodic axis has fewer than 3 bins).
 __device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
@@ -316,37 +402,57 @@ __device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
   return m;
 }
 
-// Visit every candidate partner j > i of point i; calls f(j, d2).  The 27
-// neighbouring bins are looked up first (independent loads), then walked.
-template <class Fn>
-__device__ inline void rc_visit(int i, const double* __restrict__ pos,
-                                const int32_t* __restrict__ nxt, const int32_t* __restrict__ prv,
-                                const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
-                                const int32_t* __restrict__ bins,
-                                int n, long long nc, const TopoGeom& tg, const BinGeom& bg,
-                                double d2max, Fn f) {
+// One search per alive point i: every alive j > i in the 27 neighbouring
+// bins, more than two links away, closer than the reconnection distance,
+// whose exchange does not lengthen the line, goes into i's slots (at most
+// kSlots, kept sorted by j) with the bits of d^2 as its key; the count is
+// stored.  A point with more candidates than slots latches the
+// reconnection-capacity flag and the step skips reconnection (the
+// candidate set must be complete).  The heads of the 27 bins are loaded
+// first (independent loads) into LDS.  Also clears the point's `used` flag.
+constexpr int kSlots = 8;
+
+__global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ pos,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ prv,
+                                                    const int32_t* __restrict__ head,
+                                                    const int32_t* __restrict__ lnext,
+                                                    const int32_t* __restrict__ alive,
+                                                    int32_t* __restrict__ cnt, long long nc,
+                                                    TopoGeom tg, BinGeom bg, double d2max,
+                                                    int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ slot_j,
+                                                    uint64_t* __restrict__ slot_k,
+                                                    int32_t* __restrict__ used) {
+  __shared__ int32_t hq[27][kBlock];
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * kBlock + t;
+  if (i >= cnt[9]) return;
+  used[i] = 0;
+  if (!alive[i]) {
+    count[i] = 0;
+    return;
+  }
   const int b[3] = {bin_of(pos[i], bg, 0), bin_of(pos[nc + i], bg, 1), bin_of(pos[2 * nc + i], bg, 2)};
   int ox[3], oy[3], oz[3];
   const int mx = bin_offsets(bg, 0, b[0], ox);
   const int my = bin_offsets(bg, 1, b[1], oy);
   const int mz = bin_offsets(bg, 2, b[2], oz);
-  uint32_t kk[27];
-  int first[27];
 #pragma unroll
   for (int q = 0; q < 27; ++q) {
     const int ix = q % 3, iy = (q / 3) % 3, iz = q / 9;
     const bool ok = ix < mx && iy < my && iz < mz;
-    kk[q] = ok ? (uint32_t)(((long long)oz[ok ? iz : 0] * bg.nb[1] + oy[ok ? iy : 0]) * bg.nb[0] +
-                            ox[ok ? ix : 0])
-               : 0u;
-    first[q] = ok ? bins[kk[q]] : -1;
+    const long long key = ok ? ((long long)oz[ok ? iz : 0] * bg.nb[1] + oy[ok ? iy : 0]) * bg.nb[0] +
+                                   ox[ok ? ix : 0]
+                             : 0;
+    hq[q][t] = ok ? head[key] : -1;
   }
   const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
+  int32_t* sj = slot_j + (long long)i * kSlots;
+  uint64_t* sk = slot_k + (long long)i * kSlots;
+  int m = 0;
   for (int q = 0; q < 27; ++q) {
-    if (first[q] < 0) continue;
-    const uint32_t k = kk[q];
-    for (int t = first[q]; t < n && skey[t] == k; ++t) {
-      const int j = sval[t];
+    for (int j = hq[q][t]; j >= 0; j = lnext[j]) {
       if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
       double d[3];
       sep(pos, nc, i, j, tg, d);
@@ -360,44 +466,20 @@ __device__ inline void rc_visit(int i, const double* __restrict__ pos,
       sep(pos, nc, j, ni, tg, ee);
       const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
       const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
-      if (after <= before) f(j, d2);
+      if (!(after <= before)) continue;
+      if (m < kSlots) {
+        int p = m;
+        while (p > 0 && sj[p - 1] > j) {
+          sj[p] = sj[p - 1];
+          sk[p] = sk[p - 1];
+          --p;
+        }
+        sj[p] = j;
+        sk[p] = (uint64_t)__double_as_longlong(d2);
+      }
+      ++m;
     }
   }
-}
-
-// One search per point: candidates j > i go into the point's own slots
-// (at most kSlots, kept sorted by j), with their count; a point with more
-// candidates than slots latches the reconnection-capacity flag, and the
-// step then skips reconnection (the candidate set must be complete).  The
-// kernel also clears the point's `used` flag for the matching.
-constexpr int kSlots = 8;
-
-__global__ void k_rc_find(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                          const int32_t* __restrict__ prv, const uint32_t* __restrict__ skey,
-                          const int32_t* __restrict__ sval, const int32_t* __restrict__ bins,
-                          int32_t* __restrict__ cnt, long long nc, TopoGeom tg, BinGeom bg,
-                          double d2max, int32_t* __restrict__ count, int32_t* __restrict__ slot_j,
-                          uint64_t* __restrict__ slot_k, int32_t* __restrict__ used) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = cnt[0];
-  if (i >= n) return;
-  used[i] = 0;
-  int m = 0;
-  int32_t* sj = slot_j + (long long)i * kSlots;
-  uint64_t* sk = slot_k + (long long)i * kSlots;
-  rc_visit(i, pos, nxt, prv, skey, sval, bins, n, nc, tg, bg, d2max, [&](int j, double d2) {
-    if (m < kSlots) {
-      int p = m;
-      while (p > 0 && sj[p - 1] > j) {
-        sj[p] = sj[p - 1];
-        sk[p] = sk[p - 1];
-        --p;
-      }
-      sj[p] = j;
-      sk[p] = (uint64_t)__double_as_longlong(d2);
-    }
-    ++m;
-  });
   if (m > kSlots) {
     atomicOr(&cnt[7], kFlagReconCap);
     atomicOr(&cnt[10], 1);
@@ -405,52 +487,79 @@ __global__ void k_rc_find(const double* __restrict__ pos, const int32_t* __restr
   count[i] = m < kSlots ? m : kSlots;
 }
 
-// Candidates in (i, j) order into the compact list; overflow of the list or
-// of a point's slots leaves the list empty (reconnection skipped).
-__global__ void k_rc_compact(const int32_t* __restrict__ count, const int32_t* __restrict__ off,
-                             const int32_t* __restrict__ slot_j, const uint64_t* __restrict__ slot_k,
-                             int32_t* __restrict__ cnt, long long rcap, int32_t* __restrict__ ci,
-                             int32_t* __restrict__ cj, uint64_t* __restrict__ ckey) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = cnt[0];
-  const bool skip = cnt[10] != 0 || cnt[6] > rcap;
-  if (i == 0 && cnt[6] > rcap) atomicOr(&cnt[7], kFlagReconCap);
-  if (i >= n || skip) return;
-  const int o = off[i];
-  for (int m = 0; m < count[i]; ++m) {
-    ci[o + m] = i;
-    cj[o + m] = slot_j[(long long)i * kSlots + m];
-    ckey[o + m] = slot_k[(long long)i * kSlots + m];
-  }
-}
-
-// Greedy matching in ascending (d^2, i, j), computed in rounds: a live
-// candidate whose key is the smallest among the live candidates at both of
-// its points is taken (the globally smallest one always is, and no
-// candidate of smaller key can claim its points later), its points are
-// used, and every candidate touching a used point dies.  The set taken is
-// exactly the one of the sequential greedy pass.  Taken exchanges are
-// disjoint, so their link updates do not interact.  One workgroup; values
-// that atomics update are read and written with device-scope atomics.
+// Greedy matching in ascending (d^2, i, j), one workgroup.  First the
+// per-point slots are gathered into one list in (i, j) order (a block scan
+// of the counts); a slot overflow or a list longer than its capacity
+// leaves the list empty.  Then rounds: a live candidate whose key is the
+// smallest among the live candidates at both of its points is taken (the
+// globally smallest one always is, and no candidate of smaller key can
+// claim its points later), its points are used, and every candidate
+// touching a used point dies.  The set taken is exactly the one of the
+// sequential greedy pass.  Taken exchanges are disjoint, so their link
+// updates do not interact.  Values that atomics update are read and
+// written with device-scope atomics.
 __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
                                                    int32_t* __restrict__ prv,
                                                    int32_t* __restrict__ cnt, long long rcap,
-                                                   const int32_t* __restrict__ ci,
-                                                   const int32_t* __restrict__ cj,
-                                                   const uint64_t* __restrict__ ckey,
+                                                   const int32_t* __restrict__ count,
+                                                   const int32_t* __restrict__ slot_j,
+                                                   const uint64_t* __restrict__ slot_k,
+                                                   int32_t* __restrict__ ci,
+                                                   int32_t* __restrict__ cj,
+                                                   uint64_t* __restrict__ ckey,
                                                    int32_t* __restrict__ live,
                                                    uint64_t* __restrict__ bkey,
                                                    int32_t* __restrict__ bidx,
-                                                   int32_t* __restrict__ used,
-                                                   int32_t* __restrict__ del_out) {
+                                                   int32_t* __restrict__ used) {
+  __shared__ int32_t wsum[16];
   __shared__ int s_live;
   __shared__ int s_taken;
-  const int t = threadIdx.x;
-  const int n = cnt[0];
-  // prepare the small-loop pass that follows: nothing deleted, bound n
-  for (int j = t; j < n; j += blockDim.x) del_out[j] = 0;
-  if (t == 0) cnt[9] = n;
-  const int tot = (cnt[10] != 0 || cnt[6] > rcap) ? 0 : cnt[6];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int n = cnt[9];
+  const bool overflow = cnt[10] != 0;
+  // gather the slots: exclusive scan of the counts, 4 points per thread
+  int carry = 0;
+  for (int base = 0; base < n; base += 4096) {
+    const int k0 = base + 4 * t;
+    int v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? count[k0 + q] : 0;
+    const int mine = v[0] + v[1] + v[2] + v[3];
+    int x = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int u = 0; u < 16; ++u) {
+      before += u < w ? wsum[u] : 0;
+      all += wsum[u];
+    }
+    int run = carry + before + x - mine;
+    if (!overflow) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        for (int m = 0; m < v[q]; ++m) {
+          const int o = run + m;
+          if (o < rcap) {
+            ci[o] = k0 + q;
+            cj[o] = slot_j[(long long)(k0 + q) * kSlots + m];
+            ckey[o] = slot_k[(long long)(k0 + q) * kSlots + m];
+          }
+        }
+        run += v[q];
+      }
+    }
+    carry += all;
+    __syncthreads();
+  }
+  if (t == 0) {
+    cnt[6] = carry;
+    if (carry > rcap) atomicOr(&cnt[7], kFlagReconCap);
+  }
+  const int tot = (overflow || carry > rcap) ? 0 : carry;
   for (int c = t; c < tot; c += blockDim.x) live[c] = 1;
   if (t == 0) s_taken = 0;
   __syncthreads();
@@ -515,7 +624,6 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
   }
 }
 
-
 inline int nb_of(long long n, int b) { return (int)((n + b - 1) / b); }
 
 TopoGeom topo_geom(const Run& r) {
@@ -530,82 +638,84 @@ TopoGeom topo_geom(const Run& r) {
 
 BinGeom bin_geom(const Run& r) {
   BinGeom bg;
-  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
   for (int a = 0; a < 3; ++a) {
     bg.nb[a] = r.bin_n[a];
     bg.h[a] = r.bin_h[a];
     bg.periodic[a] = !r.geom.wall[a];
     bg.off[a] = r.geom.wall[a] ? 0.5 : 0.0;
-    (void)n;
   }
   return bg;
 }
 
-hipError_t small_and_compact(Run& r, int32_t* del) {
-  const int nb = nb_of(r.ncap, 256);
-  hipLaunchKernelGGL(k_small, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.cnt, del,
-                     r.vor.min_loop_pts, r.scan_a);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt + 9, 0, r.cnt + 8);
-  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv,
-                     r.cnt, r.ncap, r.scan_a, r.scan_b, r.pos_t, r.nxt_t, r.prv_t);
-  hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
-                     r.ncap, r.pos_t, r.nxt_t, r.prv_t);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t scan_excl(Run& r, const int32_t* in, int32_t* out, const int32_t* np, int n,
-                     int32_t* total) {
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, in, out, np, n, total);
-  return hipGetLastError();
-}
-
+// Topology of one step: remeshing (mark, unlink + rank the midpoints,
+// insert), then the small-loop pass, the reconnection search and matching
+// and a second small-loop pass, and one compaction.  The reconnection runs
+// on the uncompacted arrays: deleted points and removed small loops are
+// unlinked from the alive ones, and renumbering by a stable compaction
+// keeps the (d^2, i, j) order of every candidate pair, so the outcome is
+// the one of compacting before reconnecting.
 hipError_t topo_update(Run& r) {
   const TopoGeom tg = topo_geom(r);
-  const int nb = nb_of(r.ncap, 256);
-  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, r.stream, r.cnt);
+  const int nb = nb_of(r.ncap, kBlock);
   int32_t* del = r.flag_b;
+  int32_t* ticket = r.cnt + 12;
   if (r.vor.remesh) {
     const double mn2 = r.vor.dxi_min * r.vor.dxi_min;
     const double mx2 = r.vor.dxi_max * r.vor.dxi_max;
-    hipLaunchKernelGGL(k_rm_cand, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt, r.ncap, tg, mn2, mx2, r.flag_a);
-    hipLaunchKernelGGL(k_rm_del, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, r.flag_a, del);
-    hipLaunchKernelGGL(k_rm_relink, dim3(nb), dim3(256), 0, r.stream, r.nxt, r.prv, r.cnt, del);
-    hipLaunchKernelGGL(k_rm_insmark, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap, tg, mx2, del, r.scan_a);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 2);
-    hipLaunchKernelGGL(k_rm_insert, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
-                       r.ncap, tg, del, r.scan_a, r.scan_b);
+    hipLaunchKernelGGL(k_rm_mark, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
+                       r.ncap, tg, mn2, mx2, del);
+    hipLaunchKernelGGL(k_rm_link, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv, r.cnt,
+                       r.ncap, tg, mx2, del, r.wmask, r.wpre, ticket);
+    hipLaunchKernelGGL(k_rm_insert, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                       r.cnt, r.ncap, tg, del, r.wmask, r.wpre);
   } else {
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, r.stream, del, r.ncap, 0);
+    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, r.stream, r.cnt);
   }
-  hipError_t e = small_and_compact(r, del);
-  if (e != hipSuccess) return e;
-
+  SmallArgs A{};
+  A.pos = r.pos;
+  A.nxt = r.nxt;
+  A.cnt = r.cnt;
+  A.nc = r.ncap;
+  A.bound9 = r.vor.remesh ? 1 : 0;
+  A.dead_in = r.vor.remesh ? del : nullptr;
+  A.min_pts = r.vor.min_loop_pts;
+  A.ticket = ticket;
   if (r.vor.reconnect) {
     const BinGeom bg = bin_geom(r);
+    A.bg = bg;
+    A.rc_head = r.rc_head;
+    A.rc_next = r.rc_next;
+    A.rc_key = r.rc_keyp;
+    A.alive_out = r.flag_a;
+    A.rc_mode = 1;
+    hipLaunchKernelGGL(k_small_pass, dim3(nb), dim3(kBlock), 0, r.stream, A);
     const double d2max = r.vor.reconnect_dist * r.vor.reconnect_dist;
-    const uint32_t pad = (r.bin_bits >= 32) ? 0xFFFFFFFFu : ((1u << r.bin_bits) - 1u);
-    hipLaunchKernelGGL(k_rc_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, bg, pad, r.keys_a, r.vals_a);
-    uint32_t* sk = nullptr;
-    int32_t* sv = nullptr;
-    e = sort_pairs(r, r.bin_bits, &sk, &sv);
-    if (e != hipSuccess) return e;
-    e = bins_mark(r, sk, 1);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rc_find, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.prv, sk, sv,
-                       r.bins, r.cnt, r.ncap, tg, bg, d2max, r.scan_a, r.rc_slot_j, r.rc_slot_k,
-                       r.used);
-    e = bins_mark(r, sk, 0);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, r.stream, r.scan_a, r.scan_b, r.cnt, 0, r.cnt + 6);
-    hipLaunchKernelGGL(k_rc_compact, dim3(nb), dim3(256), 0, r.stream, r.scan_a, r.scan_b,
-                       r.rc_slot_j, r.rc_slot_k, r.cnt, r.rcap, r.rc_i, r.rc_j, r.rc_key_a);
+    hipLaunchKernelGGL(k_rc_find, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                       r.rc_head, r.rc_next, r.flag_a, r.cnt, r.ncap, tg, bg, d2max, r.scan_a,
+                       r.rc_slot_j, r.rc_slot_k, r.used);
     hipLaunchKernelGGL(k_rc_match, dim3(1), dim3(1024), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,
-                       r.rc_i, r.rc_j, r.rc_key_a, r.rc_idx_a, r.rc_best, r.rc_bidx, r.used, del);
-    e = small_and_compact(r, del);
-    if (e != hipSuccess) return e;
+                       r.scan_a, r.rc_slot_j, r.rc_slot_k, r.rc_i, r.rc_j, r.rc_key_a,
+                       r.rc_idx_a, r.rc_best, r.rc_bidx, r.used);
+    SmallArgs B = A;
+    B.bound9 = 1;
+    B.dead_in = nullptr;
+    B.alive_in = r.flag_a;
+    B.alive_out = nullptr;
+    B.rc_mode = 2;
+    B.mask = r.wmask;
+    B.pre = r.wpre;
+    hipLaunchKernelGGL(k_small_pass, dim3(nb), dim3(kBlock), 0, r.stream, B);
+  } else {
+    A.mask = r.wmask;
+    A.pre = r.wpre;
+    hipLaunchKernelGGL(k_small_pass, dim3(nb), dim3(kBlock), 0, r.stream, A);
   }
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                     r.cnt, r.ncap, r.wmask, r.wpre, r.pos_t, r.nxt_t, r.prv_t);
+  hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                     r.cnt, r.ncap, r.pos_t, r.nxt_t, r.prv_t);
   return hipGetLastError();
 }
 

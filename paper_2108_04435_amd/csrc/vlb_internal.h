@@ -218,7 +218,7 @@ struct Run {
   double* Vs = nullptr;        // nz slice superflow
   void* ub = nullptr;          // 3 * cells bare velocity of the current step
   double* part = nullptr;      // per-block partial sums of u_z
-  int32_t* bins = nullptr;     // dense bin -> first sorted entry table (-1 = empty)
+  int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
   long long nbins_table = 0;
 
   // filaments
@@ -245,7 +245,8 @@ struct Run {
   // counters on the device: [0] n points, [1] n touched slots,
   // [2] inserted, [3] deleted, [4] reconnections, [5] small-loop points,
   // [6] candidates, [7] error flags, [8] compacted count, [9] bound of the
-  // small-loop pass, [10] candidate-slot overflow, [16..17] pair counter
+  // small-loop pass, [10] candidate-slot overflow, [12] last-block ticket
+  // (zero between kernels), [16..17] pair counter
   int32_t* cnt = nullptr;
 
   // sorting / scans
@@ -260,12 +261,17 @@ struct Run {
   int32_t* flag_b = nullptr;
   int32_t* scan_a = nullptr;
   int32_t* scan_b = nullptr;
+  uint64_t* wmask = nullptr;  // per-wave flag ballots
+  int32_t* wpre = nullptr;    // per-wave exclusive prefix counts
 
   // reconnection
   long long rcap = 0;
   int bin_n[3] = {1, 1, 1};
   double bin_h[3] = {1, 1, 1};
-  int bin_bits = 32;
+  long long rc_nbins = 0;
+  int32_t* rc_head = nullptr;    // per bin: last point pushed (-1 = empty)
+  int32_t* rc_next = nullptr;    // per point: next point of its bin list
+  uint32_t* rc_keyp = nullptr;   // per point: its bin
   int32_t* rc_i = nullptr;
   int32_t* rc_j = nullptr;
   uint64_t* rc_key_a = nullptr;  // candidate keys (bits of d^2)
@@ -321,9 +327,7 @@ hipError_t fil_seed(Run& r, long long n);
 hipError_t topo_update(Run& r);
 
 size_t sort_tmp_bytes(long long n);
-hipError_t bins_mark(Run& r, const uint32_t* skey, int set);
 hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres);
-hipError_t scan_excl(Run& r, const int32_t* in, int32_t* out, const int32_t* np, int n, int32_t* total);
 
 // timing helpers (api.cpp)
 void time_begin(Run& r, int cls, hipEvent_t* b);

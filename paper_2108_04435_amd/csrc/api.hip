@@ -112,6 +112,7 @@ size_t layout(Run& r, char* base) {
   size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
+  r.marked = (uint32_t*)B.take(nc * sizeof(uint32_t));
   r.keys_a = (uint32_t*)B.take(nc * sizeof(uint32_t));
   r.keys_b = (uint32_t*)B.take(nc * sizeof(uint32_t));
   r.vals_a = (int32_t*)B.take(nc * sizeof(int32_t));
@@ -138,11 +139,6 @@ size_t layout(Run& r, char* base) {
     r.rc_bidx = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   }
   r.ub = B.take(3 * cells * fe);
-  {
-    int bx, by, nbx, nby;
-    moment_tiles(r.geom, bx, by, nbx, nby);
-    r.part = (double*)B.take((size_t)nbx * nby * r.geom.nz * sizeof(double));
-  }
   r.bins = (int32_t*)B.take((size_t)r.nbins_table * sizeof(int32_t));
   return (B.off + kAlign - 1) / kAlign * kAlign;
 }
@@ -377,6 +373,7 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.bins, 0xFF, (size_t)r.nbins_table * sizeof(int32_t), r.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r.marked, 0xFF, (size_t)r.ncap * sizeof(uint32_t), r.stream);
   if (e == hipSuccess && r.rc_head)
     e = hipMemsetAsync(r.rc_head, 0xFF, (size_t)r.rc_nbins * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(r.stream);
@@ -437,6 +434,8 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
   if (n > 0) r.has_points = true;
   int32_t c0 = n;
   HIP_OR_FAIL(h, hipMemcpyAsync(r.cnt, &c0, sizeof(int32_t), hipMemcpyHostToDevice, r.stream));
+  // grid coordinates of the seeded positions (FP32 sum of the first step)
+  if (n > 0 && r.prec != VLB_F64) HIP_OR_FAIL(h, bs_prep(r, r.pos));
   HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
   return VLB_OK;
 }
@@ -459,8 +458,10 @@ int one_step(vlb_run* h) {
   double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
   for (int s = 0; s < 4; ++s) {
-    // FP32: stages 2-4 use the grid coordinates the previous finalize wrote
-    if (s == 0 || r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
+    // FP32: the grid coordinates of every stage's positions were written by
+    // the kernel that wrote the positions (seeding and the topology's copy
+    // for stage 1, the previous finalize for stages 2-4)
+    if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
     if (s == 0 && r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));

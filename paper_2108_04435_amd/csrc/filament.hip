@@ -3,11 +3,11 @@
 //    mass-balance superflow, two-point-delta interpolation of the normal
 //    fluid, Schwarz line velocity, mutual-friction force and the RK4
 //    bookkeeping of one stage;
-//  * spreading of the point forces onto the lattice, without atomics:
-//    points are binned by the cell of their stencil's lower corner with the
-//    library's stable radix sort; each touched node is then owned by exactly one bin
-//    and gathers the contributions of the (at most 8) bins around it in a
-//    fixed order.
+//  * spreading of the point forces onto the lattice, without atomics on
+//    the forces: points are binned by the cell of their stencil's lower
+//    corner with the library's stable radix sort; each touched node is then
+//    owned by exactly one bin and gathers the contributions of the (at most
+//    8) bins around it in a fixed order.
 #include "vlb_internal.h"
 
 namespace vlb {
@@ -268,43 +268,61 @@ __device__ inline uint32_t base_key(const SpreadGeom& sg, const double p[3], int
   return (uint32_t)(((long long)b[2] * sg.ext[1] + b[1]) * sg.ext[0] + b[0]);
 }
 
-__global__ void k_spread_keys(const double* __restrict__ pos, const int32_t* __restrict__ cnt,
-                              long long ncap, SpreadGeom sg, uint32_t pad, uint32_t* __restrict__ keys,
-                              int32_t* __restrict__ vals) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncap) return;
-  const int n = cnt[0];
-  uint32_t k = pad;
-  if (j < n) {
-    const double p[3] = {pos[j], pos[ncap + j], pos[2 * ncap + j]};
-    int b[3];
-    k = base_key(sg, p, b);
+// Spreading preparation, one launch with two roles by block:
+//  * blocks [0, ntiles): binning keys of a tile of points (padded with the
+//    largest key beyond the live points) and the tile's digit counts for
+//    the first pass of the sort;
+//  * the other blocks: zero the force at the nodes the previous spreading
+//    wrote, and clear the previous spreading's bin marks.
+template <class FT>
+__global__ __launch_bounds__(kSortThreads) void k_spread_prepare(
+    const double* __restrict__ pos, const int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
+    uint32_t pad, int dbits, int ntiles, uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+    int32_t* __restrict__ counts, FT* __restrict__ F, long long cells,
+    const int32_t* __restrict__ touched, const uint32_t* __restrict__ marked,
+    int32_t* __restrict__ bins) {
+  __shared__ int32_t hist[kSortMaxBins];
+  if ((int)blockIdx.x < ntiles) {
+    const int j = blockIdx.x * kSortThreads + threadIdx.x;
+    const int n = cnt[0];
+    uint32_t k = pad;
+    if (j < n) {
+      const double p[3] = {pos[j], pos[ncap + j], pos[2 * ncap + j]};
+      int b[3];
+      k = base_key(sg, p, b);
+    }
+    if (j < ncap) {
+      keys[j] = k;
+      vals[j] = j;
+    }
+    sort_tile_count(k, j < ncap, 0, dbits, ntiles, blockIdx.x, hist, counts);
+    return;
   }
-  keys[j] = k;
-  vals[j] = j;
+  const long long s = (long long)(blockIdx.x - ntiles) * kSortThreads + threadIdx.x;
+  if (s < cnt[1]) {
+    const int node = touched[s];
+    if (node >= 0) {
+      F[node] = FT(0);
+      F[cells + node] = FT(0);
+      F[2 * cells + node] = FT(0);
+    }
+  }
+  if (s < ncap) {
+    const uint32_t mk = marked[s];
+    if (mk != 0xFFFFFFFFu) bins[mk] = -1;
+  }
 }
 
 // Dense bin table: bins[key] = first sorted entry of that bin, -1 if empty.
-// Marked after each sort and cleared again after use, so it is all -1
-// between uses.
+// The marked keys are listed so that the next spreading clears them.
 __global__ void k_bin_mark(const uint32_t* __restrict__ skey, const int32_t* __restrict__ cnt,
-                           int32_t* __restrict__ bins, int value_is_index) {
+                           long long ncap, int32_t* __restrict__ bins,
+                           uint32_t* __restrict__ marked) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= cnt[0]) return;
-  if (r > 0 && skey[r - 1] == skey[r]) return;
-  bins[skey[r]] = value_is_index ? r : -1;
-}
-
-template <class FT>
-__global__ void k_spread_clear(FT* __restrict__ F, long long cells, const int32_t* __restrict__ touched,
-                               const int32_t* __restrict__ cnt) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cnt[1]) return;
-  const int node = touched[s];
-  if (node < 0) return;
-  F[node] = FT(0);
-  F[cells + node] = FT(0);
-  F[2 * cells + node] = FT(0);
+  if (r >= ncap) return;
+  const bool head = r < cnt[0] && (r == 0 || skey[r - 1] != skey[r]);
+  if (head) bins[skey[r]] = r;
+  marked[r] = head ? skey[r] : 0xFFFFFFFFu;
 }
 
 // One thread per (sorted entry, stencil corner).  Only the first entry of
@@ -461,28 +479,28 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   return hipGetLastError();
 }
 
-hipError_t fil_clear_force(Run& r) {
-  const int nb = nblocks(8 * r.ncap, 256);
-  if (r.prec == VLB_F64)
-    hipLaunchKernelGGL(k_spread_clear<double>, dim3(nb), dim3(256), 0, r.stream, (double*)r.force, r.cells, r.touched, r.cnt);
-  else
-    hipLaunchKernelGGL(k_spread_clear<float>, dim3(nb), dim3(256), 0, r.stream, (float*)r.force, r.cells, r.touched, r.cnt);
-  return hipGetLastError();
-}
-
 hipError_t fil_spread(Run& r) {
-  hipError_t e = fil_clear_force(r);
-  if (e != hipSuccess) return e;
   const SpreadGeom sg = spread_geom(r);
   const uint32_t pad = (r.key_bits >= 32) ? 0xFFFFFFFFu : ((1u << r.key_bits) - 1u);
-  const int nb = nblocks(r.ncap, 256);
-  hipLaunchKernelGGL(k_spread_keys, dim3(nb), dim3(256), 0, r.stream, r.pos, r.cnt, r.ncap, sg,
-                     pad, r.keys_a, r.vals_a);
+  const int ntiles = sort_tiles(r.ncap);
+  int dbits = 0;
+  sort_first_digit(r.key_bits, &dbits);
+  const int nclear = nblocks(8 * r.ncap, kSortThreads);
+  if (r.prec == VLB_F64)
+    hipLaunchKernelGGL(k_spread_prepare<double>, dim3(ntiles + nclear), dim3(kSortThreads), 0,
+                       r.stream, r.pos, r.cnt, r.ncap, sg, pad, dbits, ntiles, r.keys_a, r.vals_a,
+                       sort_counts(r), (double*)r.force, r.cells, r.touched, r.marked, r.bins);
+  else
+    hipLaunchKernelGGL(k_spread_prepare<float>, dim3(ntiles + nclear), dim3(kSortThreads), 0,
+                       r.stream, r.pos, r.cnt, r.ncap, sg, pad, dbits, ntiles, r.keys_a, r.vals_a,
+                       sort_counts(r), (float*)r.force, r.cells, r.touched, r.marked, r.bins);
   uint32_t* sk = nullptr;
   int32_t* sv = nullptr;
-  e = sort_pairs(r, r.key_bits, &sk, &sv);
+  hipError_t e = sort_pairs(r, r.key_bits, 1, &sk, &sv);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, sk, r.cnt, r.bins, 1);
+  const int nb = nblocks(r.ncap, 256);
+  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, sk, r.cnt, r.ncap, r.bins,
+                     r.marked);
   const int nb8 = nblocks(8 * r.ncap, 256);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
@@ -490,7 +508,6 @@ hipError_t fil_spread(Run& r) {
   else
     hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
                        r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
-  hipLaunchKernelGGL(k_bin_mark, dim3(nb), dim3(256), 0, r.stream, sk, r.cnt, r.bins, 0);
   return hipGetLastError();
 }
 

@@ -166,49 +166,41 @@ __global__ void k_read_force(const T* __restrict__ F, long long n, double* out) 
 
 // Bare normal-fluid velocity u_b = sum(c f)/sum(f) of every node (velocity
 // planes applied), written once per step for the interpolation onto the
-// filaments, fused with the per-block partial sums of u_z that the
-// mass-balance superflow needs (Sec. III.C, Eq. mass cons).  Blocks tile one
-// z slice each, so a slice's partials are contiguous.
+// filaments, fused with the mean of u_z over each z slice that the
+// mass-balance superflow needs (Sec. III.C, Eq. mass cons): one block per
+// slice walks the slice in tiles (x fastest), each thread adds its nodes'
+// u_z in order, the block adds the threads' sums in a fixed tree, and
+// Vs[z] = scale * sum.
 template <class S, class UT>
-__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ M, Geom g, int parity,
-                                                int nbx, int nby, UT* __restrict__ ub,
-                                                double* __restrict__ part) {
-  const int t = blockIdx.x;  // slice-major: t = (z * nby + by) * nbx + bx
-  const int bxi = t % nbx;
-  const int rr = t / nbx;
-  const int byi = rr % nby;
-  const int z = rr / nby;
-  const int x = bxi * blockDim.x + threadIdx.x;
-  const int y = byi * blockDim.y + threadIdx.y;
+__global__ __launch_bounds__(1024) void k_moments(const S* __restrict__ M, Geom g, int parity,
+                                                 UT* __restrict__ ub, double scale,
+                                                 double* __restrict__ Vs) {
+  const int z = blockIdx.x;
   double uzv = 0.0;
-  if (x < g.nx && y < g.ny) {
-    double rho, ux, uy, uz;
-    node_rho_u<S>(M, g, parity, x, y, z, rho, ux, uy, uz);
-    const long long c = ((long long)z * g.ny + y) * g.nx + x;
-    ub[c] = (UT)ux;
-    ub[g.cells + c] = (UT)uy;
-    ub[2 * g.cells + c] = (UT)uz;
-    uzv = uz;
-  }
-  __shared__ double red[256];
+  for (int y0 = 0; y0 < g.ny; y0 += blockDim.y)
+    for (int x0 = 0; x0 < g.nx; x0 += blockDim.x) {
+      const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+      if (x < g.nx && y < g.ny) {
+        double rho, ux, uy, uz;
+        node_rho_u<S>(M, g, parity, x, y, z, rho, ux, uy, uz);
+        const long long c = ((long long)z * g.ny + y) * g.nx + x;
+        ub[c] = (UT)ux;
+        ub[g.cells + c] = (UT)uy;
+        ub[2 * g.cells + c] = (UT)uz;
+        uzv += uz;
+      }
+    }
+  if (!Vs) return;
+  __shared__ double red[1024];
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int nt = blockDim.x * blockDim.y;
   red[tid] = uzv;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if (tid < s && tid + s < nt) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) part[t] = red[0];
-}
-
-__global__ void k_slice_final(const double* __restrict__ part, int nz, int nparts, double scale,
-                              double* __restrict__ Vs) {
-  const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= nz) return;
-  double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(long long)z * nparts + p];
-  Vs[z] = scale * s;
+  if (tid == 0) Vs[z] = scale * red[0];
 }
 
 inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
@@ -308,33 +300,24 @@ hipError_t lbm_read_force(Run& r, double* out) {
   return hipGetLastError();
 }
 
-void moment_tiles(const Geom& g, int& bx, int& by, int& nbx, int& nby) {
-  bx = g.nx < 64 ? g.nx : 64;
-  by = 256 / bx;
-  nbx = (g.nx + bx - 1) / bx;
-  nby = (g.ny + by - 1) / by;
-}
-
 hipError_t lbm_moments(Run& r) {
   const Geom& g = r.geom;
-  int bx, by, nbx, nby;
-  moment_tiles(g, bx, by, nbx, nby);
-  const int nb = nbx * nby * g.nz;
+  const int bx = g.nx < 64 ? g.nx : 64;
+  int by = 1024 / bx;
+  if (by > g.ny) by = g.ny;
   dim3 blk(bx, by);
+  double* Vs = r.vor.mass_balance ? r.Vs : nullptr;
+  const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
   switch (r.prec) {
     case VLB_F64:
-      hipLaunchKernelGGL((k_moments<double, double>), dim3(nb), blk, 0, r.stream, (const double*)r.pops, g, r.parity, nbx, nby, (double*)r.ub, r.part);
+      hipLaunchKernelGGL((k_moments<double, double>), dim3(g.nz), blk, 0, r.stream, (const double*)r.pops, g, r.parity, (double*)r.ub, scale, Vs);
       break;
     case VLB_F32:
-      hipLaunchKernelGGL((k_moments<float, float>), dim3(nb), blk, 0, r.stream, (const float*)r.pops, g, r.parity, nbx, nby, (float*)r.ub, r.part);
+      hipLaunchKernelGGL((k_moments<float, float>), dim3(g.nz), blk, 0, r.stream, (const float*)r.pops, g, r.parity, (float*)r.ub, scale, Vs);
       break;
     default:
-      hipLaunchKernelGGL((k_moments<__half, float>), dim3(nb), blk, 0, r.stream, (const __half*)r.pops, g, r.parity, nbx, nby, (float*)r.ub, r.part);
+      hipLaunchKernelGGL((k_moments<__half, float>), dim3(g.nz), blk, 0, r.stream, (const __half*)r.pops, g, r.parity, (float*)r.ub, scale, Vs);
       break;
-  }
-  if (r.vor.mass_balance) {
-    const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
-    hipLaunchKernelGGL(k_slice_final, dim3(blocks_for(g.nz, 256)), dim3(256), 0, r.stream, r.part, g.nz, nbx * nby, scale, r.Vs);
   }
   return hipGetLastError();
 }

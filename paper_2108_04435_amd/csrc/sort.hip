@@ -1,69 +1,41 @@
 // Stable LSD radix sort of (uint32 key, int32 value) pairs, used to bin
-// filament points by lattice cell (force spreading) and by reconnection
-// cell.  Digits of up to 11 bits (2 passes for keys of up to 22 bits).  No
-// atomics: inside a wave, the lanes holding the same digit are found with
-// one ballot per digit bit; their count and each lane's rank among them
-// come from population counts.  Per pass three kernels:
-//   1. per-tile digit counts (tiles of 1024 keys, 4 rounds of 256 threads);
+// filament points by lattice cell for the force spreading.  Digits of up to
+// 11 bits (2 passes for keys of up to 22 bits), one tile of 1024 keys per
+// block of 1024 threads, one key per thread.  Inside a wave the lanes
+// holding the same digit are found with one ballot per digit bit; their
+// count and each lane's rank among them come from population counts.  Per
+// pass three kernels:
+//   1. per-tile digit counts (LDS histogram; the first pass can be fused
+//      into the kernel that produces the keys);
 //   2. digit offsets of every tile (keys of smaller digits anywhere plus
 //      keys of the same digit in earlier tiles): a one-workgroup exclusive
 //      scan of the digit-major count table;
-//   3. stable scatter: each key goes to its tile's digit offset + running
-//      count of its digit in the tile + earlier waves of the round + rank
-//      inside the wave.
+//   3. stable scatter: the waves of a tile take turns in order; each key
+//      goes to the running offset of its digit + its rank inside the wave,
+//      and the lowest lane of each digit group advances that offset.
 // Keys beyond the live points are padded by the caller with the largest
-// key, so they sort to the end.  Nothing is allocated and no memset is
-// issued, so the sort can be captured in a HIP graph.
+// key, so they sort to the end.  Nothing is allocated, no global atomics
+// and no memset are issued, so the sort can be captured in a HIP graph.
 #include "vlb_internal.h"
 
 namespace vlb {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kRounds = 4;
-constexpr int kTileKeys = kThreads * kRounds;
-constexpr int kMaxBits = 11;
-constexpr int kMaxBins = 1 << kMaxBits;
-
-// Lanes of this wave whose (valid) digit equals this lane's digit.
-__device__ inline uint64_t peer_mask(uint32_t d, bool valid, int bits) {
-  uint64_t m = __ballot(valid);
-  for (int b = 0; b < bits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t x = __ballot(valid && bit);
-    m &= bit ? x : ~x;
-  }
-  return m;
-}
-
-__global__ __launch_bounds__(kThreads) void k_rs_count(const uint32_t* __restrict__ keys, int n,
-                                                       int shift, int bits, int ntiles,
-                                                       int32_t* __restrict__ counts) {
-  __shared__ int32_t cw[4][kMaxBins];
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const int nbins = 1 << bits;
-  const uint32_t mask = (uint32_t)nbins - 1u;
-  for (int q = t; q < 4 * kMaxBins; q += kThreads) (&cw[0][0])[q] = 0;
-  __syncthreads();
-  const int base = blockIdx.x * kTileKeys;
-  for (int q = 0; q < kRounds; ++q) {
-    const int idx = base + q * kThreads + t;
-    const bool valid = idx < n;
-    const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
-    const uint64_t m = peer_mask(d, valid, bits);
-    if (valid && (int)(__ffsll((unsigned long long)m) - 1) == lane) cw[w][d] += __popcll(m);
-  }
-  __syncthreads();
-  for (int d = t; d < nbins; d += kThreads)
-    counts[(long long)d * ntiles + blockIdx.x] = cw[0][d] + cw[1][d] + cw[2][d] + cw[3][d];
+__global__ __launch_bounds__(kSortThreads) void k_rs_count(const uint32_t* __restrict__ keys,
+                                                           int n, int shift, int bits, int ntiles,
+                                                           int32_t* __restrict__ counts) {
+  __shared__ int32_t hist[kSortMaxBins];
+  const int idx = blockIdx.x * kSortThreads + threadIdx.x;
+  const bool valid = idx < n;
+  const uint32_t k = valid ? keys[idx] : 0u;
+  sort_tile_count(k, valid, shift, bits, ntiles, blockIdx.x, hist, counts);
 }
 
 // Digit offsets of every tile, once per pass (one workgroup): offs[d][b] =
-// number of keys with a smaller digit + keys of digit d in tiles before b,
-// i.e. the exclusive prefix of the digit-major count table read as one
-// array.  Each thread takes 16 consecutive entries per round (vector loads
-// where the round is full).
+// exclusive prefix of the digit-major count table read as one array.  Each
+// thread takes 16 consecutive entries per round (vector loads where the
+// round is full).
 __global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__ counts, int M,
                                                      int32_t* __restrict__ offs) {
   __shared__ int32_t wsum[16];
@@ -123,74 +95,77 @@ __global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
-                                                         const int32_t* __restrict__ vin,
-                                                         uint32_t* __restrict__ kout,
-                                                         int32_t* __restrict__ vout, int n,
-                                                         int shift, int bits, int ntiles,
-                                                         const int32_t* __restrict__ offs) {
-  __shared__ int32_t run[kMaxBins];
-  __shared__ int32_t cw[4][kMaxBins];
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                             const int32_t* __restrict__ vin,
+                                                             uint32_t* __restrict__ kout,
+                                                             int32_t* __restrict__ vout, int n,
+                                                             int shift, int bits, int ntiles,
+                                                             const int32_t* __restrict__ offs) {
+  __shared__ int32_t run[kSortMaxBins];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int nbins = 1 << bits;
-  const uint32_t mask = (uint32_t)nbins - 1u;
-  for (int d = t; d < nbins; d += kThreads) run[d] = offs[(long long)d * ntiles + blockIdx.x];
-  __syncthreads();
-  const int base = blockIdx.x * kTileKeys;
+  for (int d = t; d < nbins; d += kSortThreads) run[d] = offs[(long long)d * ntiles + blockIdx.x];
+  const int idx = blockIdx.x * kSortThreads + t;
+  const bool valid = idx < n;
+  const uint32_t k = valid ? kin[idx] : 0u;
+  const int32_t v = valid ? vin[idx] : 0;
+  const uint32_t d = (k >> shift) & (uint32_t)(nbins - 1);
+  const uint64_t m = sort_peer_mask(d, valid, bits);
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  for (int q = 0; q < kRounds; ++q) {
-    for (int e = lane; e < nbins; e += 64) cw[w][e] = 0;
-    const int idx = base + q * kThreads + t;
-    const bool valid = idx < n;
-    const uint32_t k = valid ? kin[idx] : 0u;
-    const int32_t v = valid ? vin[idx] : 0;
-    const uint32_t d = (k >> shift) & mask;
-    const uint64_t m = peer_mask(d, valid, bits);
-    const int rank = __popcll(m & lt);
+  const int rank = __popcll(m & lt);
+  const bool leader = valid && rank == 0;
+  for (int turn = 0; turn < kSortThreads / 64; ++turn) {
     __syncthreads();
-    if (valid && (int)(__ffsll((unsigned long long)m) - 1) == lane) cw[w][d] = __popcll(m);
-    __syncthreads();
-    if (valid) {
-      int dst = run[d] + rank;
-      for (int u = 0; u < w; ++u) dst += cw[u][d];
-      kout[dst] = k;
-      vout[dst] = v;
+    if (turn == w && valid) {
+      const int b = run[d];
+      kout[b + rank] = k;
+      vout[b + rank] = v;
+      if (leader) run[d] = b + __popcll(m);
     }
-    __syncthreads();
-    for (int d2 = t; d2 < nbins; d2 += kThreads) run[d2] += cw[0][d2] + cw[1][d2] + cw[2][d2] + cw[3][d2];
-    __syncthreads();
   }
 }
 
 }  // namespace
 
 size_t sort_tmp_bytes(long long n) {
-  const long long ntiles = (n + kTileKeys - 1) / kTileKeys;
-  return (size_t)(2 * (((long long)kMaxBins * ntiles + 63) & ~63LL) + 16) * sizeof(int32_t);
+  const long long ntiles = (n + kSortThreads - 1) / kSortThreads;
+  return (size_t)(2 * (((long long)kSortMaxBins * ntiles + 63) & ~63LL) + 16) * sizeof(int32_t);
 }
 
+int sort_tiles(long long n) { return (int)((n + kSortThreads - 1) / kSortThreads); }
+
+void sort_first_digit(int bits, int* dbits) {
+  const int passes = (bits + kSortMaxBits - 1) / kSortMaxBits;
+  const int db = (bits + passes - 1) / passes;
+  *dbits = db < bits ? db : bits;
+}
+
+int32_t* sort_counts(Run& r) { return (int32_t*)r.sort_tmp; }
+
 // Sort ncap pairs (keys_a, vals_a) by the low `bits` bits of the key.
-// Result pointers are returned (they alternate between the a and b
-// buffers with the number of passes).
-hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres) {
+// first_counted: the tile counts of the first pass are already in the
+// count table.  Result pointers are returned (they alternate between the a
+// and b buffers with the number of passes).
+hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int32_t** vres) {
   const int n = (int)r.ncap;
-  const int ntiles = (n + kTileKeys - 1) / kTileKeys;
+  const int ntiles = sort_tiles(n);
   int32_t* counts = (int32_t*)r.sort_tmp;
-  int32_t* offs = counts + (((long long)kMaxBins * ntiles + 63) & ~63LL);
+  int32_t* offs = counts + (((long long)kSortMaxBins * ntiles + 63) & ~63LL);
   uint32_t* kin = r.keys_a;
   uint32_t* kout = r.keys_b;
   int32_t* vin = r.vals_a;
   int32_t* vout = r.vals_b;
-  const int passes = (bits + kMaxBits - 1) / kMaxBits;
+  const int passes = (bits + kSortMaxBits - 1) / kSortMaxBits;
   const int dbits = (bits + passes - 1) / passes;
   for (int p = 0; p < passes; ++p) {
     const int shift = dbits * p;
     const int pb = (shift + dbits <= bits) ? dbits : bits - shift;
-    hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, n, shift, pb,
-                       ntiles, counts);
+    if (p > 0 || !first_counted)
+      hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kSortThreads), 0, r.stream, kin, n, shift,
+                         pb, ntiles, counts);
     hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, r.stream, counts, ntiles << pb, offs);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kThreads), 0, r.stream, kin, vin, kout,
-                       vout, n, shift, pb, ntiles, offs);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, r.stream, kin, vin,
+                       kout, vout, n, shift, pb, ntiles, offs);
     uint32_t* tk = kin;
     kin = kout;
     kout = tk;

@@ -367,18 +367,28 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(const double* __rest
   prv_t[q] = flag_rank(mask, pre, prv[j]);
 }
 
+// The copy also writes the 32-bit grid coordinates of the new positions
+// for the FP32 Biot-Savart sum of the next step (X non-null).
 __global__ __launch_bounds__(kBlock) void k_compact_copy(double* __restrict__ pos,
                                                          int32_t* __restrict__ nxt,
                                                          int32_t* __restrict__ prv,
                                                          int32_t* __restrict__ cnt, long long nc,
                                                          const double* __restrict__ pos_t,
                                                          const int32_t* __restrict__ nxt_t,
-                                                         const int32_t* __restrict__ prv_t) {
+                                                         const int32_t* __restrict__ prv_t,
+                                                         uint32_t* __restrict__ X, BsAxes ax) {
   const int q = blockIdx.x * kBlock + threadIdx.x;
   const int nn = cnt[8];
   if (q == 0) cnt[0] = nn;
   if (q >= nn) return;
-  for (int a = 0; a < 3; ++a) pos[a * nc + q] = pos_t[a * nc + q];
+  for (int a = 0; a < 3; ++a) {
+    const double y = pos_t[a * nc + q];
+    pos[a * nc + q] = y;
+    if (X) {
+      const double g = floor((y + ax.off[a]) * ax.q[a]);
+      X[a * nc + q] = ax.periodic[a] ? (uint32_t)(long long)g : (uint32_t)(int)(long long)g;
+    }
+  }
   nxt[q] = nxt_t[q];
   prv[q] = prv_t[q];
 }
@@ -451,8 +461,17 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
   int32_t* sj = slot_j + (long long)i * kSlots;
   uint64_t* sk = slot_k + (long long)i * kSlots;
   int m = 0;
-  for (int q = 0; q < 27; ++q) {
-    for (int j = hq[q][t]; j >= 0; j = lnext[j]) {
+  // one flat walk over the entries of all 27 lists (empty lists are
+  // skipped in LDS), so a wave steps as often as its longest walk
+  int q = 0;
+  int j = hq[0][t];
+  for (;;) {
+    while (j < 0 && q < 26) j = hq[++q][t];
+    if (j < 0) break;
+    const int jc = j;
+    j = lnext[jc];
+    {
+      const int j = jc;
       if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
       double d[3];
       sep(pos, nc, i, j, tg, d);
@@ -715,7 +734,8 @@ hipError_t topo_update(Run& r) {
   hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
                      r.cnt, r.ncap, r.wmask, r.wpre, r.pos_t, r.nxt_t, r.prv_t);
   hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
-                     r.cnt, r.ncap, r.pos_t, r.nxt_t, r.prv_t);
+                     r.cnt, r.ncap, r.pos_t, r.nxt_t, r.prv_t,
+                     r.prec == VLB_F64 ? nullptr : r.bsX, r.bsax);
   return hipGetLastError();
 }
 

@@ -197,6 +197,38 @@ struct BsAxes {
   int uniform;      // 1: one grid step q for all axes (FP32 sum in grid units)
 };
 
+// Radix-sort tiles: one key per thread, one tile per block.
+constexpr int kSortThreads = 1024;
+constexpr int kSortMaxBits = 11;
+constexpr int kSortMaxBins = 1 << kSortMaxBits;
+
+// Lanes of this wave whose (valid) digit equals this lane's digit.
+__device__ inline uint64_t sort_peer_mask(uint32_t d, bool valid, int bits) {
+  uint64_t m = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t x = __ballot(valid && bit);
+    m &= bit ? x : ~x;
+  }
+  return m;
+}
+
+// Digit histogram of one tile (one key per thread of a kSortThreads block;
+// every thread calls it): LDS integer adds by the lowest lane of each digit
+// group; counts[d * ntiles + tile] receives the tile's count of digit d.
+__device__ inline void sort_tile_count(uint32_t key, bool valid, int shift, int bits, int ntiles,
+                                       int tile, int32_t* hist, int32_t* __restrict__ counts) {
+  const int t = threadIdx.x, lane = t & 63;
+  const int nbins = 1 << bits;
+  for (int e = t; e < nbins; e += kSortThreads) hist[e] = 0;
+  __syncthreads();
+  const uint32_t d = (key >> shift) & (uint32_t)(nbins - 1);
+  const uint64_t m = sort_peer_mask(d, valid, bits);
+  if (valid && (int)(__ffsll((unsigned long long)m) - 1) == lane) atomicAdd(&hist[d], (int)__popcll(m));
+  __syncthreads();
+  for (int e = t; e < nbins; e += kSortThreads) counts[(long long)e * ntiles + tile] = hist[e];
+}
+
 // Workspace-resident state of a run.
 struct Run {
   vlb_lattice_desc lat;
@@ -217,8 +249,8 @@ struct Run {
   int32_t* touched = nullptr;  // 8 * ncap node indices written by spreading
   double* Vs = nullptr;        // nz slice superflow
   void* ub = nullptr;          // 3 * cells bare velocity of the current step
-  double* part = nullptr;      // per-block partial sums of u_z
   int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
+  uint32_t* marked = nullptr;  // per sorted entry: the bin it marked (all ones: none)
   long long nbins_table = 0;
 
   // filaments
@@ -313,7 +345,6 @@ hipError_t lbm_read_fields(Run& r, double* rho, double* u);
 hipError_t lbm_read_pops(Run& r, double* f);
 hipError_t lbm_read_force(Run& r, double* out);
 hipError_t lbm_moments(Run& r);
-void moment_tiles(const Geom& g, int& bx, int& by, int& nbx, int& nby);
 
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r, const double* Y);
@@ -321,13 +352,15 @@ int bs_chunks(long long ncap);
 
 hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only);
 hipError_t fil_spread(Run& r);
-hipError_t fil_clear_force(Run& r);
 hipError_t fil_seed(Run& r, long long n);
 
 hipError_t topo_update(Run& r);
 
 size_t sort_tmp_bytes(long long n);
-hipError_t sort_pairs(Run& r, int bits, uint32_t** kres, int32_t** vres);
+int sort_tiles(long long n);
+void sort_first_digit(int bits, int* dbits);
+int32_t* sort_counts(Run& r);
+hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int32_t** vres);
 
 // timing helpers (api.cpp)
 void time_begin(Run& r, int cls, hipEvent_t* b);

@@ -6,8 +6,11 @@
  * plus a set of closed vortex filaments (Sec. II.A), coupled through the
  * mutual-friction force (Sec. II.B).  All state lives in ONE caller-owned
  * block of device memory (the workspace); the library never allocates
- * device memory.  All device work is enqueued on ONE caller-owned HIP
- * stream, given at creation.
+ * device memory.  Device work is ordered on ONE caller-owned HIP stream,
+ * given at creation: inside vlb_step and a graph, the lattice part of a
+ * step runs on a second, library-owned stream (default priority) forked
+ * from the caller's stream at the start of the call and joined back to it
+ * at the end, so to the caller every call is ordered on its stream.
  *
  * Conventions
  *  - Every function returns a vlb_status (0 = success, negative = error);
@@ -104,8 +107,10 @@ int vlb_query_footprint(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
 
 /* Create a run inside the caller's device workspace (>= footprint bytes,
  * 256-byte aligned) on the caller's stream (hipStream_t, may be NULL for the
- * null stream).  Populations start at equilibrium f^eq(rho = 1, u = 0);
- * there are no filaments.  The workspace and stream must outlive the run.  */
+ * null stream); the library creates its side stream and six events here
+ * (VLB_EDEVICE if that fails) and releases them in vlb_destroy.
+ * Populations start at equilibrium f^eq(rho = 1, u = 0); there are no
+ * filaments.  The workspace and stream must outlive the run.               */
 int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
                        void* dev_workspace, uint64_t ws_bytes, void* hip_stream,
                        vlb_run** out);
@@ -124,10 +129,12 @@ int vlb_seed_vortices(vlb_run* run, int64_t n_pts, const double* xyz_host,
 /* Enqueue n_steps coupled steps (Sec. II): filament RK4 with the
  * Biot-Savart + LIA velocity and the Schwarz equation of motion, force
  * spreading, one forced LBM update, remeshing / reconnection.  Returns
- * after enqueueing (asynchronous).                                         */
+ * after enqueueing (asynchronous).  The filament stages stay on the run's
+ * stream; the moments, the spreading and the LBM update go to the side
+ * stream, with event dependencies where the two parts exchange data.      */
 int vlb_step(vlb_run* run, int64_t n_steps);
 
-/* Wait for the run's stream; return a latched device error if any.         */
+/* Wait for the run's streams; return a latched device error if any.       */
 int vlb_sync(vlb_run* run);
 
 /* Density and bare velocity sum(c_i f_i)/sum(f_i) of the current

@@ -86,6 +86,19 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
   return VLB_OK;
 }
 
+void release_streams(Run& r) {
+  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_spread, &r.ev_fin4, &r.ev_join};
+  for (hipEvent_t* ev : evs)
+    if (*ev) {
+      hipEventDestroy(*ev);
+      *ev = nullptr;
+    }
+  if (r.side) {
+    hipStreamDestroy(r.side);
+    r.side = nullptr;
+  }
+}
+
 int bits_for(unsigned long long v) {  // smallest b with v < 2^b
   int b = 1;
   while (b < 64 && (v >> b) != 0) ++b;
@@ -368,8 +381,12 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   layout(r, r.ws);
   r.stream = (hipStream_t)hip_stream;
   hipGetDevice(&r.device);
+  hipError_t e = hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking);
+  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_spread, &r.ev_fin4, &r.ev_join};
+  for (hipEvent_t* ev : evs)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   // populations at rest, no force, no points
-  hipError_t e = hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.bins, 0xFF, (size_t)r.nbins_table * sizeof(int32_t), r.stream);
@@ -379,6 +396,7 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   if (e == hipSuccess) e = hipStreamSynchronize(r.stream);
   if (e != hipSuccess) {
     std::string m = std::string("initialising the workspace: ") + hipGetErrorString(e);
+    release_streams(r);
     delete h;
     return fail(nullptr, VLB_EDEVICE, m);
   }
@@ -444,7 +462,27 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
 
 namespace {
 
-int one_step(vlb_run* h) {
+// Launchers enqueue on r.stream; this points it at another stream for a
+// scope.
+struct OnStream {
+  Run& r;
+  hipStream_t saved;
+  OnStream(Run& run, hipStream_t s) : r(run), saved(run.stream) { r.stream = s; }
+  ~OnStream() { r.stream = saved; }
+};
+
+// One coupled step on two streams.  The caller's stream (main) carries the
+// filament part: the four RK4 stages (Biot-Savart sum + finalize) and the
+// topology.  The library's side stream carries the lattice part: the
+// moments of f^n, the spreading of the stage-1 forces and the LBM update.
+// Dependencies (events): finalize 1 needs the moments (velocity field and
+// superflow); the spreading needs finalize 1 (point forces); finalize 4
+// rewrites the positions the spreading reads, so it waits for it; the next
+// step's moments overwrite the velocity field the stages read, so the side
+// stream waits for finalize 4.  The first step forks the side stream from
+// main, the last one joins it back, so a call's work is ordered on the
+// caller's stream as a whole.
+int one_step(vlb_run* h, bool first, bool last) {
   Run& r = h->r;
   if (!r.has_points) {  // never seeded: the normal fluid alone
     HIP_OR_FAIL(h, lbm_step(r));
@@ -452,22 +490,50 @@ int one_step(vlb_run* h) {
     r.last_nodes += r.cells;
     return VLB_OK;
   }
-  // bare velocity field and mass-balance superflow of f^n
-  HIP_OR_FAIL(h, lbm_moments(r));
+  hipStream_t M = r.stream, S = r.side;
+  if (first) {
+    HIP_OR_FAIL(h, hipEventRecord(r.ev_fork, M));
+    HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fork, 0));
+  }
+  {
+    OnStream on(r, S);
+    // bare velocity field and mass-balance superflow of f^n
+    HIP_OR_FAIL(h, lbm_moments(r));
+  }
+  HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   // filament RK4: stage positions s^n (pos) -> ya -> yb -> ya -> pos
   double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
+  const bool spread = r.vor.coupling != 0;
   for (int s = 0; s < 4; ++s) {
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
     if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
+    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
+    if (s == 3 && spread) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_spread, 0));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
-    if (s == 0 && r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
+    if (s == 0) {
+      if (spread) {
+        HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
+        HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
+      }
+      OnStream on(r, S);
+      if (spread) {
+        HIP_OR_FAIL(h, fil_spread(r));
+        HIP_OR_FAIL(h, hipEventRecord(r.ev_spread, S));
+      }
+      HIP_OR_FAIL(h, lbm_step(r));
+    }
   }
-  HIP_OR_FAIL(h, lbm_step(r));
+  HIP_OR_FAIL(h, hipEventRecord(r.ev_fin4, M));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
   HIP_OR_FAIL(h, topo_update(r));
+  if (last) {
+    HIP_OR_FAIL(h, hipEventRecord(r.ev_join, S));
+    HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_join, 0));
+  }
   r.step += 1;
   r.last_nodes += r.cells;
   return VLB_OK;
@@ -481,7 +547,7 @@ int vlb_step(vlb_run* h, int64_t n_steps) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   if (n_steps < 0) return fail(h, VLB_EINVAL, "n_steps must be >= 0");
   for (int64_t s = 0; s < n_steps; ++s) {
-    const int c = one_step(h);
+    const int c = one_step(h, s == 0, s == n_steps - 1);
     if (c != VLB_OK) return c;
   }
   return VLB_OK;
@@ -490,6 +556,7 @@ int vlb_step(vlb_run* h, int64_t n_steps) {
 int vlb_sync(vlb_run* h) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  if (h->r.side) HIP_OR_FAIL(h, hipStreamSynchronize(h->r.side));
   return latched(h);
 }
 
@@ -665,7 +732,7 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   r.timing = false;
   HIP_OR_FAIL(h, hipStreamBeginCapture(r.stream, hipStreamCaptureModeRelaxed));
   int code = VLB_OK;
-  for (int64_t k = 0; k < n_steps && code == VLB_OK; ++k) code = one_step(h);
+  for (int64_t k = 0; k < n_steps && code == VLB_OK; ++k) code = one_step(h, k == 0, k == n_steps - 1);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(r.stream, &graph);
   r.step = step0;
@@ -715,7 +782,9 @@ int vlb_graph_destroy(vlb_graph* g) {
 int vlb_destroy(vlb_run* h) {
   if (!h) return VLB_OK;
   hipStreamSynchronize(h->r.stream);
+  if (h->r.side) hipStreamSynchronize(h->r.side);
   drop_events(h->r);
+  release_streams(h->r);
   delete h;
   return VLB_OK;
 }

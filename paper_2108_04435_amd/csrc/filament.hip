@@ -106,33 +106,92 @@ __device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, d
   }
 }
 
-// 64 points per block of 256 threads: the four waves add the Biot-Savart
+// 64 points per block of 256 threads.  The four waves add the Biot-Savart
 // chunk partials of the block's points (wave g takes chunks g, g + 4, ...,
-// four chunks' loads in flight at a time), wave 0 combines the four sums in
-// a fixed order and does the per-point work.
+// eight chunks' loads in flight at a time); before its share, wave 1
+// interpolates the normal-fluid velocity and wave 2 evaluates the local
+// geometry and the LIA term, so that these load chains overlap.  Wave 0
+// then combines the parts in a fixed order and does the rest per point.
 constexpr int kFinPts = 64;
 
 template <class UT, class PT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
-  __shared__ double red[3][3][kFinPts];
+  __shared__ double red[3][3][kFinPts];  // chunk sums of waves 1..3
+  __shared__ double s_vn[3][kFinPts];    // wave 1: normal-fluid velocity
+  __shared__ double s_geo[8][kFinPts];   // wave 2: s' (3), LIA (3), l+, l-
+  __shared__ double s_rk[7][kFinPts];    // wave 3: s^n (3), ksum (3), superflow
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int j = blockIdx.x * kFinPts + lane;
   const int n = A.cnt[0];
+  const bool live = j < n;
   const long long nc = A.ncap;
+  const Geom& g = A.g;
+  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+  const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
+
+  if (live && grp == 1) {
+    double vn[3];
+    interp_vn<UT>((const UT*)A.ub, g, A.Y[j], A.Y[nc + j], A.Y[2 * nc + j], vn);
+    for (int a = 0; a < 3; ++a) s_vn[a][lane] = vn[a];
+  }
+  if (live && grp == 2) {
+    // local geometry (three-point derivatives on a non-uniform arc length)
+    const int jn = A.nxt[j], jp = A.prv[j];
+    double dp[3], dm[3];
+    for (int a = 0; a < 3; ++a) {
+      const double pa = A.Y[a * nc + j];
+      dp[a] = mimg(A.Y[a * nc + jn] - pa, L[a], per[a]);
+      dm[a] = mimg(pa - A.Y[a * nc + jp], L[a], per[a]);
+    }
+    const double lp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
+    const double lm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
+    const double den = lp * lm * (lp + lm);
+    double sp[3], spp[3];
+    for (int a = 0; a < 3; ++a) {
+      sp[a] = (lm * lm * dp[a] + lp * lp * dm[a]) / den;
+      spp[a] = 2.0 * (lm * dp[a] - lp * dm[a]) / den;
+    }
+    const double sn = sqrt(sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]);
+    for (int a = 0; a < 3; ++a) sp[a] /= sn;
+    // LIA: beta s' x s'', beta = kappa/(4 pi) ln(2 sqrt(l+ l-) / (e^C a))
+    const double beta = A.bs_scale * log(2.0 * sqrt(lp * lm) / A.ea);
+    s_geo[3][lane] = beta * (sp[1] * spp[2] - sp[2] * spp[1]);
+    s_geo[4][lane] = beta * (sp[2] * spp[0] - sp[0] * spp[2]);
+    s_geo[5][lane] = beta * (sp[0] * spp[1] - sp[1] * spp[0]);
+    for (int a = 0; a < 3; ++a) s_geo[a][lane] = sp[a];
+    s_geo[6][lane] = lp;
+    s_geo[7][lane] = lm;
+  }
+  if (live && grp == 3) {
+    if (!A.eval_only)
+      for (int a = 0; a < 3; ++a) {
+        s_rk[a][lane] = A.pos[a * nc + j];
+        s_rk[3 + a][lane] = A.stage > 1 ? A.ksum[a * nc + j] : 0.0;
+      }
+    if (A.mass_balance) {
+      const double pz = A.Y[2 * nc + j];
+      const double fz = floor(pz);
+      const double t = pz - fz;
+      int i0 = (int)fz, i1 = i0 + 1;
+      i0 = ((i0 % g.nz) + g.nz) % g.nz;
+      i1 = ((i1 % g.nz) + g.nz) % g.nz;
+      s_rk[6][lane] = (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];
+    }
+  }
 
   // non-local Biot-Savart: chunk partials added in a fixed order
   double vs[3] = {0.0, 0.0, 0.0};
-  if (j < n) {
+  if (live) {
     const PT* __restrict__ P = (const PT*)A.P;
     int s = grp;
-    for (; s + 12 < A.S; s += 16) {
-      PT v[4][3];
+    for (; s + 28 < A.S; s += 32) {
+      PT v[8][3];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int a = 0; a < 3; ++a) v[u][a] = P[((long long)(s + 4 * u) * 3 + a) * nc + j];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int a = 0; a < 3; ++a) vs[a] += (double)v[u][a];
     }
@@ -142,50 +201,21 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   if (grp > 0)
     for (int a = 0; a < 3; ++a) red[grp - 1][a][lane] = vs[a];
   __syncthreads();
-  if (grp > 0 || j >= n) return;
+  if (grp > 0 || !live) return;
   for (int a = 0; a < 3; ++a)
     vs[a] = (((vs[a] + red[0][a][lane]) + red[1][a][lane]) + red[2][a][lane]) * A.nl_scale;
 
-  const Geom& g = A.g;
-  const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
-  const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
-
-  // local geometry (three-point derivatives on a non-uniform arc length)
-  const int jn = A.nxt[j], jp = A.prv[j];
-  double p[3], dp[3], dm[3];
+  double sp[3];
   for (int a = 0; a < 3; ++a) {
-    p[a] = A.Y[a * nc + j];
-    dp[a] = mimg(A.Y[a * nc + jn] - p[a], L[a], per[a]);
-    dm[a] = mimg(p[a] - A.Y[a * nc + jp], L[a], per[a]);
+    sp[a] = s_geo[a][lane];
+    vs[a] += s_geo[3 + a][lane];
   }
-  const double lp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
-  const double lm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
-  const double den = lp * lm * (lp + lm);
-  double sp[3], spp[3];
-  for (int a = 0; a < 3; ++a) {
-    sp[a] = (lm * lm * dp[a] + lp * lp * dm[a]) / den;
-    spp[a] = 2.0 * (lm * dp[a] - lp * dm[a]) / den;
-  }
-  const double sn = sqrt(sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]);
-  for (int a = 0; a < 3; ++a) sp[a] /= sn;
-  // LIA: beta s' x s'', beta = kappa/(4 pi) ln(2 sqrt(l+ l-) / (e^C a))
-  const double beta = A.bs_scale * log(2.0 * sqrt(lp * lm) / A.ea);
-  vs[0] += beta * (sp[1] * spp[2] - sp[2] * spp[1]);
-  vs[1] += beta * (sp[2] * spp[0] - sp[0] * spp[2]);
-  vs[2] += beta * (sp[0] * spp[1] - sp[1] * spp[0]);
+  const double lp = s_geo[6][lane], lm = s_geo[7][lane];
   for (int a = 0; a < 3; ++a) vs[a] += A.vs_app[a];
-  if (A.mass_balance) {
-    const double fz = floor(p[2]);
-    const double t = p[2] - fz;
-    int i0 = (int)fz, i1 = i0 + 1;
-    i0 = ((i0 % g.nz) + g.nz) % g.nz;
-    i1 = ((i1 % g.nz) + g.nz) % g.nz;
-    vs[2] += (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];
-  }
+  if (A.mass_balance) vs[2] += s_rk[6][lane];
 
   // normal-fluid velocity at the point
-  double vn[3];
-  interp_vn<UT>((const UT*)A.ub, g, p[0], p[1], p[2], vn);
+  const double vn[3] = {s_vn[0][lane], s_vn[1][lane], s_vn[2][lane]};
 
   // Schwarz equation of motion (Sec. II.A, Eq. E of M)
   const double w[3] = {vn[0] - vs[0], vn[1] - vs[1], vn[2] - vs[2]};
@@ -216,7 +246,8 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
 
   // RK4: ksum = k1 + 2 k2 + 2 k3 + k4, stage positions s^n + c k
   for (int a = 0; a < 3; ++a) {
-    const double s0 = A.pos[a * nc + j];
+    const double s0 = s_rk[a][lane];
+    const double kp = s_rk[3 + a][lane];
     double ks;
     double y;
     switch (A.stage) {
@@ -225,15 +256,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
         y = s0 + 0.5 * sd[a];
         break;
       case 2:
-        ks = A.ksum[a * nc + j] + 2.0 * sd[a];
+        ks = kp + 2.0 * sd[a];
         y = s0 + 0.5 * sd[a];
         break;
       case 3:
-        ks = A.ksum[a * nc + j] + 2.0 * sd[a];
+        ks = kp + 2.0 * sd[a];
         y = s0 + sd[a];
         break;
       default:
-        ks = A.ksum[a * nc + j] + sd[a];
+        ks = kp + sd[a];
         y = s0 + ks / 6.0;
         break;
     }

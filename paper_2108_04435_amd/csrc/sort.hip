@@ -34,21 +34,23 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_count(const uint32_t* __res
 
 // Digit offsets of every tile, once per pass (one workgroup): offs[d][b] =
 // exclusive prefix of the digit-major count table read as one array.  Each
-// thread takes 16 consecutive entries per round (vector loads where the
-// round is full).
+// thread takes kScanPer consecutive entries per round (vector loads where
+// the round is full), so a table of up to 32768 entries is one round.
+constexpr int kScanPer = 32;
+
 __global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__ counts, int M,
                                                      int32_t* __restrict__ offs) {
   __shared__ int32_t wsum[16];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int carry = 0;
-  for (int base = 0; base < M; base += 16 * 1024) {
-    const int k0 = base + 16 * t;
-    const bool full = k0 + 16 <= M;
-    int v[16];
+  for (int base = 0; base < M; base += kScanPer * 1024) {
+    const int k0 = base + kScanPer * t;
+    const bool full = k0 + kScanPer <= M;
+    int v[kScanPer];
     if (full) {
       const int4* p = reinterpret_cast<const int4*>(counts + k0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kScanPer / 4; ++q) {
         const int4 x = p[q];
         v[4 * q] = x.x;
         v[4 * q + 1] = x.y;
@@ -57,11 +59,11 @@ __global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = (k0 + q < M) ? counts[k0 + q] : 0;
+      for (int q = 0; q < kScanPer; ++q) v[q] = (k0 + q < M) ? counts[k0 + q] : 0;
     }
     int mine = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) mine += v[q];
+    for (int q = 0; q < kScanPer; ++q) mine += v[q];
     int x = mine;
     for (int off = 1; off < 64; off <<= 1) {
       const int y = __shfl_up(x, off, 64);
@@ -75,20 +77,20 @@ __global__ __launch_bounds__(1024) void k_rs_offsets(const int32_t* __restrict__
       all += wsum[u];
     }
     int run = carry + before + x - mine;
-    int o[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      o[q] = run;
-      run += v[q];
+    for (int q = 0; q < kScanPer; ++q) {
+      const int c = v[q];
+      v[q] = run;
+      run += c;
     }
     if (full) {
       int4* p = reinterpret_cast<int4*>(offs + k0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+      for (int q = 0; q < kScanPer / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     } else {
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (k0 + q < M) offs[k0 + q] = o[q];
+      for (int q = 0; q < kScanPer; ++q)
+        if (k0 + q < M) offs[k0 + q] = v[q];
     }
     carry += all;
     __syncthreads();

@@ -295,6 +295,7 @@ __device__ inline int bin_of(double x, const BinGeom& bg, int a) {
 struct SmallArgs {
   const double* pos;
   const int32_t* nxt;
+  const int32_t* prv;
   int32_t* cnt;
   long long nc;
   int bound9;               // 1: bound = cnt[9]; 0: bound = cnt[0], and cnt[9] := bound
@@ -322,13 +323,19 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
   if (in && A.alive_in) in = A.alive_in[j] != 0;
   bool alive = false;
   if (in) {
-    int p = A.nxt[j];
-    int steps = 1;
-    while (p != j && steps < A.min_pts) {
-      p = A.nxt[p];
-      ++steps;
+    // the loop is shorter than min_pts iff nxt^k(j) = j for some k <=
+    // min_pts - 1; walking i links forward (f) and back (b) together,
+    // f == prv^(i-1)(j) tests k = 2i - 1 and f == b tests k = 2i
+    const int m1 = A.min_pts - 1;
+    int f = j, b = j;
+    bool small = false;
+    for (int i = 1; 2 * i - 1 <= m1 && !small; ++i) {
+      const int bp = b;
+      f = A.nxt[f];
+      b = A.prv[b];
+      small = f == bp || (2 * i <= m1 && f == b);
     }
-    alive = !(p == j && steps < A.min_pts);
+    alive = !small;
   }
   if (valid && A.alive_out) A.alive_out[j] = alive ? 1 : 0;
   const uint64_t dm = __ballot(in && !alive);
@@ -695,6 +702,7 @@ hipError_t topo_update(Run& r) {
   SmallArgs A{};
   A.pos = r.pos;
   A.nxt = r.nxt;
+  A.prv = r.prv;
   A.cnt = r.cnt;
   A.nc = r.ncap;
   A.bound9 = r.vor.remesh ? 1 : 0;

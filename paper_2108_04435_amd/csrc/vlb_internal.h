@@ -233,7 +233,10 @@ __device__ inline void sort_tile_count(uint32_t key, bool valid, int shift, int 
 struct Run {
   vlb_lattice_desc lat;
   vlb_vortex_desc vor;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the caller's stream: every call's work joins it
+  hipStream_t side = nullptr;    // library stream for the lattice part of a step
+  hipEvent_t ev_fork = nullptr, ev_mom = nullptr, ev_fin1 = nullptr, ev_spread = nullptr,
+             ev_fin4 = nullptr, ev_join = nullptr;
   int device = 0;
   char* ws = nullptr;
   uint64_t ws_bytes = 0;

@@ -115,7 +115,7 @@ size_t layout(Run& r, char* base) {
   r.force = B.take(3 * cells * fe);
   r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
   r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
-  double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage};
+  double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage, &r.sfrac};
   for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
   int32_t** ibufs[] = {&r.nxt, &r.prv, &r.nxt_t, &r.prv_t, &r.stage_i, &r.flag_a, &r.flag_b,
                        &r.scan_a, &r.scan_b, &r.used};
@@ -476,12 +476,15 @@ struct OnStream {
 // topology.  The library's side stream carries the lattice part: the
 // moments of f^n, the spreading of the stage-1 forces and the LBM update.
 // Dependencies (events): finalize 1 needs the moments (velocity field and
-// superflow); the spreading needs finalize 1 (point forces); finalize 4
-// rewrites the positions the spreading reads, so it waits for it; the next
-// step's moments overwrite the velocity field the stages read, so the side
-// stream waits for finalize 4.  The first step forks the side stream from
-// main, the last one joins it back, so a call's work is ordered on the
-// caller's stream as a whole.
+// superflow); the spreading needs finalize 1, which leaves it the point
+// forces, bin keys, stencil offsets and point count, so the spreading reads
+// nothing the later stages or the topology rewrite.  The LBM update and the
+// next step's moments (which overwrite the velocity field the stages read)
+// wait for finalize 4: they run beside the topology, a phase of short
+// latency-bound kernels, rather than beside the compute-bound Biot-Savart
+// sums.  The first step of a call forks the side
+// stream from main and computes its own moments; the last one joins the
+// side stream back, so a call's work is ordered on the caller's stream.
 int one_step(vlb_run* h, bool first, bool last) {
   Run& r = h->r;
   if (!r.has_points) {  // never seeded: the normal fluid alone
@@ -494,42 +497,43 @@ int one_step(vlb_run* h, bool first, bool last) {
   if (first) {
     HIP_OR_FAIL(h, hipEventRecord(r.ev_fork, M));
     HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fork, 0));
-  }
-  {
     OnStream on(r, S);
     // bare velocity field and mass-balance superflow of f^n
     HIP_OR_FAIL(h, lbm_moments(r));
+    HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   }
-  HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   // filament RK4: stage positions s^n (pos) -> ya -> yb -> ya -> pos
   double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
   const bool spread = r.vor.coupling != 0;
   for (int s = 0; s < 4; ++s) {
+    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
     if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
-    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
-    if (s == 3 && spread) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_spread, 0));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
-    if (s == 0) {
-      if (spread) {
-        HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
-        HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
-      }
+    if (s == 0 && spread) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
+    // the side stream's work is enqueued after the main stream's next
+    // kernel, so that a graph keeps the main chain on one queue
+    if (s == 1 && spread) {
+      HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
       OnStream on(r, S);
-      if (spread) {
-        HIP_OR_FAIL(h, fil_spread(r));
-        HIP_OR_FAIL(h, hipEventRecord(r.ev_spread, S));
-      }
-      HIP_OR_FAIL(h, lbm_step(r));
+      HIP_OR_FAIL(h, fil_spread(r));
     }
   }
   HIP_OR_FAIL(h, hipEventRecord(r.ev_fin4, M));
-  HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
   HIP_OR_FAIL(h, topo_update(r));
+  HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
+  {
+    OnStream on(r, S);
+    HIP_OR_FAIL(h, lbm_step(r));
+    if (!last) {
+      HIP_OR_FAIL(h, lbm_moments(r));  // f^(n+1): moments of the next step
+      HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
+    }
+  }
   if (last) {
     HIP_OR_FAIL(h, hipEventRecord(r.ev_join, S));
     HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_join, 0));

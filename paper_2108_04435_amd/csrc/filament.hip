@@ -14,6 +14,37 @@ namespace vlb {
 
 namespace {
 
+// Spreading bins: the lattice cell of the stencil's lower corner.
+struct SpreadGeom {
+  int n[3];
+  int wall[3];
+  int ext[3];  // bins per axis: n (periodic) or n + 1 (wall: lower corner -1..n-1)
+};
+
+__device__ inline uint32_t base_key(const SpreadGeom& sg, const double p[3], int b[3]) {
+  for (int a = 0; a < 3; ++a) {
+    int c = (int)floor(p[a]);
+    if (sg.wall[a]) {
+      c += 1;  // lower corner -1 .. n-1 -> 0 .. n
+    } else {
+      c = c < 0 ? c + sg.n[a] : (c >= sg.n[a] ? c - sg.n[a] : c);
+    }
+    b[a] = c;
+  }
+  return (uint32_t)(((long long)b[2] * sg.ext[1] + b[1]) * sg.ext[0] + b[0]);
+}
+
+SpreadGeom spread_geom(const Run& r) {
+  SpreadGeom sg;
+  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
+  for (int a = 0; a < 3; ++a) {
+    sg.n[a] = n[a];
+    sg.wall[a] = r.geom.wall[a];
+    sg.ext[a] = n[a] + (r.geom.wall[a] ? 1 : 0);
+  }
+  return sg;
+}
+
 struct FinArgs {
   const void* ub;  // bare normal-fluid velocity field of the step
   Geom g;
@@ -45,6 +76,11 @@ struct FinArgs {
   double* gpt;
   uint32_t* X;      // grid coordinates of the next stage's positions (FP32 sum), or null
   BsAxes ax;
+  // stage 1 with spreading: per point, the bin key and the fractional
+  // stencil offsets of the step's positions, and the point count
+  SpreadGeom sg;
+  uint32_t* skeys;  // or null
+  double* sfrac;
 };
 
 // Nearest-image separation on the filament axes (wall axes: plain).
@@ -130,10 +166,17 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
 
   if (live && grp == 1) {
+    const double p[3] = {A.Y[j], A.Y[nc + j], A.Y[2 * nc + j]};
     double vn[3];
-    interp_vn<UT>((const UT*)A.ub, g, A.Y[j], A.Y[nc + j], A.Y[2 * nc + j], vn);
+    interp_vn<UT>((const UT*)A.ub, g, p[0], p[1], p[2], vn);
     for (int a = 0; a < 3; ++a) s_vn[a][lane] = vn[a];
+    if (A.skeys) {
+      int b[3];
+      A.skeys[j] = base_key(A.sg, p, b);
+      for (int a = 0; a < 3; ++a) A.sfrac[a * nc + j] = p[a] - floor(p[a]);
+    }
   }
+  if (A.skeys && blockIdx.x == 0 && threadIdx.x == 0) A.cnt[11] = n;
   if (live && grp == 2) {
     // local geometry (three-point derivatives on a non-uniform arc length)
     const int jn = A.nxt[j], jp = A.prv[j];
@@ -280,29 +323,11 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
 
 // ----------------------------------------------------------- spreading
 
-struct SpreadGeom {
-  int n[3];
-  int wall[3];
-  int ext[3];  // bins per axis: n (periodic) or n + 1 (wall: lower corner -1..n-1)
-};
-
-__device__ inline uint32_t base_key(const SpreadGeom& sg, const double p[3], int b[3]) {
-  for (int a = 0; a < 3; ++a) {
-    int c = (int)floor(p[a]);
-    if (sg.wall[a]) {
-      c += 1;  // lower corner -1 .. n-1 -> 0 .. n
-    } else {
-      c = c < 0 ? c + sg.n[a] : (c >= sg.n[a] ? c - sg.n[a] : c);
-    }
-    b[a] = c;
-  }
-  return (uint32_t)(((long long)b[2] * sg.ext[1] + b[1]) * sg.ext[0] + b[0]);
-}
-
 // Spreading preparation, one launch with two roles by block:
-//  * blocks [0, ntiles): binning keys of a tile of points (padded with the
-//    largest key beyond the live points) and the tile's digit counts for
-//    the first pass of the sort;
+//  * blocks [0, ntiles): a tile of the binning keys (written by the
+//    stage-1 finalize for the live points, padded here with the largest
+//    key beyond them) and the tile's digit counts for the first pass of
+//    the sort;
 //  * the other blocks: zero the force at the nodes the previous spreading
 //    wrote, and clear the previous spreading's bin marks.
 template <class FT>
@@ -315,13 +340,9 @@ __global__ __launch_bounds__(kSortThreads) void k_spread_prepare(
   __shared__ int32_t hist[kSortMaxBins];
   if ((int)blockIdx.x < ntiles) {
     const int j = blockIdx.x * kSortThreads + threadIdx.x;
-    const int n = cnt[0];
+    const int n = cnt[11];
     uint32_t k = pad;
-    if (j < n) {
-      const double p[3] = {pos[j], pos[ncap + j], pos[2 * ncap + j]};
-      int b[3];
-      k = base_key(sg, p, b);
-    }
+    if (j < n) k = keys[j];
     if (j < ncap) {
       keys[j] = k;
       vals[j] = j;
@@ -351,7 +372,7 @@ __global__ void k_bin_mark(const uint32_t* __restrict__ skey, const int32_t* __r
                            uint32_t* __restrict__ marked) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ncap) return;
-  const bool head = r < cnt[0] && (r == 0 || skey[r - 1] != skey[r]);
+  const bool head = r < cnt[11] && (r == 0 || skey[r - 1] != skey[r]);
   if (head) bins[skey[r]] = r;
   marked[r] = head ? skey[r] : 0xFFFFFFFFu;
 }
@@ -363,11 +384,11 @@ __global__ void k_bin_mark(const uint32_t* __restrict__ skey, const int32_t* __r
 template <class FT>
 __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t* __restrict__ sval,
                                 const int32_t* __restrict__ bins,
-                                const double* __restrict__ pos, const double* __restrict__ gpt,
+                                const double* __restrict__ sfrac, const double* __restrict__ gpt,
                                 int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
                                 long long cells, FT* __restrict__ F, int32_t* __restrict__ touched) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = cnt[0];
+  const int n = cnt[11];
   if (id == 0) cnt[1] = 8 * n;
   const int r = (int)(id >> 3);
   const int o = (int)(id & 7);
@@ -434,8 +455,7 @@ __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t
       const int pidx = sval[t];
       double w = 1.0;
       for (int a = 0; a < 3; ++a) {
-        const double x = pos[a * ncap + pidx];
-        const double fr = x - floor(x);
+        const double fr = sfrac[a * ncap + pidx];
         w *= oq[a] ? fr : 1.0 - fr;
       }
       for (int a = 0; a < 3; ++a) f[a] += w * gpt[a * ncap + pidx];
@@ -454,17 +474,6 @@ __global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
 }
 
 inline int nblocks(long long n, int b) { return (int)((n + b - 1) / b); }
-
-SpreadGeom spread_geom(const Run& r) {
-  SpreadGeom sg;
-  const int n[3] = {r.geom.nx, r.geom.ny, r.geom.nz};
-  for (int a = 0; a < 3; ++a) {
-    sg.n[a] = n[a];
-    sg.wall[a] = r.geom.wall[a];
-    sg.ext[a] = n[a] + (r.geom.wall[a] ? 1 : 0);
-  }
-  return sg;
-}
 
 }  // namespace
 
@@ -502,6 +511,9 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   // the FP32 sum of the next stage reads grid coordinates written here
   A.X = (r.prec != VLB_F64 && stage < 4 && !eval_only) ? r.bsX : nullptr;
   A.ax = r.bsax;
+  A.sg = spread_geom(r);
+  A.skeys = (stage == 1 && r.vor.coupling) ? r.keys_a : nullptr;
+  A.sfrac = r.sfrac;
   const int nb = nblocks(r.ncap, kFinPts);
   switch (r.prec) {
     case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;
@@ -535,10 +547,10 @@ hipError_t fil_spread(Run& r) {
   const int nb8 = nblocks(8 * r.ncap, 256);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_spread_gather<double>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
-                       r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
+                       r.bins, r.sfrac, r.gpt, r.cnt, r.ncap, sg, r.cells, (double*)r.force, r.touched);
   else
     hipLaunchKernelGGL(k_spread_gather<float>, dim3(nb8), dim3(256), 0, r.stream, sk, sv,
-                       r.bins, r.pos, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
+                       r.bins, r.sfrac, r.gpt, r.cnt, r.ncap, sg, r.cells, (float*)r.force, r.touched);
   return hipGetLastError();
 }
 

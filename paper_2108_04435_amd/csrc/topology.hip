@@ -303,7 +303,9 @@ struct SmallArgs {
   const int32_t* alive_in;  // 1 = alive before this pass (or null)
   int32_t* alive_out;       // or null
   int min_pts;
-  int rc_mode;              // 0: none, 1: push on bin lists, 2: clear bin heads
+  int rc_mode;              // 0: none, 1: push on bin lists (and zero the
+                            // candidate counts), 2: clear bin heads
+  int32_t* rc_count;
   BinGeom bg;
   int32_t* rc_head;
   int32_t* rc_next;
@@ -338,6 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
     alive = !small;
   }
   if (valid && A.alive_out) A.alive_out[j] = alive ? 1 : 0;
+  if (valid && A.rc_mode == 1) A.rc_count[j] = 0;
   const uint64_t dm = __ballot(in && !alive);
   if ((threadIdx.x & 63) == 0 && dm) atomicAdd(&A.cnt[5], (int)__popcll(dm));
   if (A.rc_mode == 1 && alive) {
@@ -419,14 +422,16 @@ __device__ inline int bin_offsets(const BinGeom& bg, int a, int b, int out[3]) {
   return m;
 }
 
-// One search per alive point i: every alive j > i in the 27 neighbouring
-// bins, more than two links away, closer than the reconnection distance,
-// whose exchange does not lengthen the line, goes into i's slots (at most
-// kSlots, kept sorted by j) with the bits of d^2 as its key; the count is
-// stored.  A point with more candidates than slots latches the
-// reconnection-capacity flag and the step skips reconnection (the
-// candidate set must be complete).  The heads of the 27 bins are loaded
-// first (independent loads) into LDS.  Also clears the point's `used` flag.
+// One thread per (alive point i, neighbouring bin q): every alive j > i in
+// bin q, more than two links away, closer than the reconnection distance,
+// whose exchange does not lengthen the line, takes the next of i's slots
+// (integer add on i's count) with the bits of d^2 as its key.  The slot
+// order depends on timing; the matching kernel orders each point's slots
+// by j, so the candidate list is a fixed function of the positions.  A
+// point with more candidates than slots latches the reconnection-capacity
+// flag and the step skips reconnection (the candidate set must be
+// complete).  The counts start at zero (first small-loop pass); the q = 0
+// thread clears the point's `used` flag.
 constexpr int kSlots = 8;
 
 __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ pos,
@@ -441,76 +446,48 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
                                                     int32_t* __restrict__ slot_j,
                                                     uint64_t* __restrict__ slot_k,
                                                     int32_t* __restrict__ used) {
-  __shared__ int32_t hq[27][kBlock];
-  const int t = threadIdx.x;
-  const int i = blockIdx.x * kBlock + t;
+  const long long id = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int i = (int)(id / 27), q = (int)(id % 27);
   if (i >= cnt[9]) return;
-  used[i] = 0;
-  if (!alive[i]) {
-    count[i] = 0;
-    return;
-  }
+  if (q == 0) used[i] = 0;
+  if (!alive[i]) return;
   const int b[3] = {bin_of(pos[i], bg, 0), bin_of(pos[nc + i], bg, 1), bin_of(pos[2 * nc + i], bg, 2)};
   int ox[3], oy[3], oz[3];
   const int mx = bin_offsets(bg, 0, b[0], ox);
   const int my = bin_offsets(bg, 1, b[1], oy);
   const int mz = bin_offsets(bg, 2, b[2], oz);
-#pragma unroll
-  for (int q = 0; q < 27; ++q) {
-    const int ix = q % 3, iy = (q / 3) % 3, iz = q / 9;
-    const bool ok = ix < mx && iy < my && iz < mz;
-    const long long key = ok ? ((long long)oz[ok ? iz : 0] * bg.nb[1] + oy[ok ? iy : 0]) * bg.nb[0] +
-                                   ox[ok ? ix : 0]
-                             : 0;
-    hq[q][t] = ok ? head[key] : -1;
-  }
+  const int ix = q % 3, iy = (q / 3) % 3, iz = q / 9;
+  if (ix >= mx || iy >= my || iz >= mz) return;
+  const long long key = ((long long)oz[iz] * bg.nb[1] + oy[iy]) * bg.nb[0] + ox[ix];
+  int j = head[key];
+  if (j < 0) return;
   const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
-  int32_t* sj = slot_j + (long long)i * kSlots;
-  uint64_t* sk = slot_k + (long long)i * kSlots;
-  int m = 0;
-  // one flat walk over the entries of all 27 lists (empty lists are
-  // skipped in LDS), so a wave steps as often as its longest walk
-  int q = 0;
-  int j = hq[0][t];
-  for (;;) {
-    while (j < 0 && q < 26) j = hq[++q][t];
-    if (j < 0) break;
+  while (j >= 0) {
     const int jc = j;
     j = lnext[jc];
-    {
-      const int j = jc;
-      if (j <= i || j == ni || j == nni || j == pi || j == ppi) continue;
-      double d[3];
-      sep(pos, nc, i, j, tg, d);
-      const double d2 = sq3(d);
-      if (!(d2 < d2max)) continue;
-      const int nj = nxt[j];
-      double ea[3], eb[3], ec[3], ee[3];
-      sep(pos, nc, i, ni, tg, ea);
-      sep(pos, nc, j, nj, tg, eb);
-      sep(pos, nc, i, nj, tg, ec);
-      sep(pos, nc, j, ni, tg, ee);
-      const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
-      const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
-      if (!(after <= before)) continue;
-      if (m < kSlots) {
-        int p = m;
-        while (p > 0 && sj[p - 1] > j) {
-          sj[p] = sj[p - 1];
-          sk[p] = sk[p - 1];
-          --p;
-        }
-        sj[p] = j;
-        sk[p] = (uint64_t)__double_as_longlong(d2);
-      }
-      ++m;
+    if (jc <= i || jc == ni || jc == nni || jc == pi || jc == ppi) continue;
+    double d[3];
+    sep(pos, nc, i, jc, tg, d);
+    const double d2 = sq3(d);
+    if (!(d2 < d2max)) continue;
+    const int nj = nxt[jc];
+    double ea[3], eb[3], ec[3], ee[3];
+    sep(pos, nc, i, ni, tg, ea);
+    sep(pos, nc, jc, nj, tg, eb);
+    sep(pos, nc, i, nj, tg, ec);
+    sep(pos, nc, jc, ni, tg, ee);
+    const double before = __dadd_rn(sqrt(sq3(ea)), sqrt(sq3(eb)));
+    const double after = __dadd_rn(sqrt(sq3(ec)), sqrt(sq3(ee)));
+    if (!(after <= before)) continue;
+    const int slot = atomicAdd(&count[i], 1);
+    if (slot < kSlots) {
+      slot_j[(long long)i * kSlots + slot] = jc;
+      slot_k[(long long)i * kSlots + slot] = (uint64_t)__double_as_longlong(d2);
+    } else {
+      atomicOr(&cnt[7], kFlagReconCap);
+      atomicOr(&cnt[10], 1);
     }
   }
-  if (m > kSlots) {
-    atomicOr(&cnt[7], kFlagReconCap);
-    atomicOr(&cnt[10], 1);
-  }
-  count[i] = m < kSlots ? m : kSlots;
 }
 
 // Greedy matching in ascending (d^2, i, j), one workgroup.  First the
@@ -543,13 +520,14 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = cnt[9];
   const bool overflow = cnt[10] != 0;
-  // gather the slots: exclusive scan of the counts, 4 points per thread
+  // gather the slots in (i, j) order: exclusive scan of the counts, 4
+  // points per thread; a point's slots go to their rank by j
   int carry = 0;
   for (int base = 0; base < n; base += 4096) {
     const int k0 = base + 4 * t;
     int v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? count[k0 + q] : 0;
+    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? min(count[k0 + q], kSlots) : 0;
     const int mine = v[0] + v[1] + v[2] + v[3];
     int x = mine;
     for (int off = 1; off < 64; off <<= 1) {
@@ -567,11 +545,15 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
     if (!overflow) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        const int32_t* sj = slot_j + (long long)(k0 + q) * kSlots;
         for (int m = 0; m < v[q]; ++m) {
-          const int o = run + m;
+          const int jm = sj[m];
+          int rk = 0;
+          for (int u = 0; u < v[q]; ++u) rk += sj[u] < jm ? 1 : 0;
+          const int o = run + rk;
           if (o < rcap) {
             ci[o] = k0 + q;
-            cj[o] = slot_j[(long long)(k0 + q) * kSlots + m];
+            cj[o] = jm;
             ckey[o] = slot_k[(long long)(k0 + q) * kSlots + m];
           }
         }
@@ -715,11 +697,12 @@ hipError_t topo_update(Run& r) {
     A.rc_head = r.rc_head;
     A.rc_next = r.rc_next;
     A.rc_key = r.rc_keyp;
+    A.rc_count = r.scan_a;
     A.alive_out = r.flag_a;
     A.rc_mode = 1;
     hipLaunchKernelGGL(k_small_pass, dim3(nb), dim3(kBlock), 0, r.stream, A);
     const double d2max = r.vor.reconnect_dist * r.vor.reconnect_dist;
-    hipLaunchKernelGGL(k_rc_find, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+    hipLaunchKernelGGL(k_rc_find, dim3(nb_of(27 * r.ncap, kBlock)), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
                        r.rc_head, r.rc_next, r.flag_a, r.cnt, r.ncap, tg, bg, d2max, r.scan_a,
                        r.rc_slot_j, r.rc_slot_k, r.used);
     hipLaunchKernelGGL(k_rc_match, dim3(1), dim3(1024), 0, r.stream, r.nxt, r.prv, r.cnt, r.rcap,

@@ -265,6 +265,7 @@ struct Run {
   double* vn1 = nullptr;
   double* sd1 = nullptr;
   double* gpt = nullptr;
+  double* sfrac = nullptr;  // 3 * ncap stencil offsets of the spread positions
   int32_t* nxt = nullptr;
   int32_t* prv = nullptr;
   double* pos_t = nullptr;  // compaction scratch
@@ -280,8 +281,9 @@ struct Run {
   // counters on the device: [0] n points, [1] n touched slots,
   // [2] inserted, [3] deleted, [4] reconnections, [5] small-loop points,
   // [6] candidates, [7] error flags, [8] compacted count, [9] bound of the
-  // small-loop pass, [10] candidate-slot overflow, [12] last-block ticket
-  // (zero between kernels), [16..17] pair counter
+  // small-loop pass, [10] candidate-slot overflow, [11] points of the
+  // spreading in flight, [12] last-block ticket (zero between kernels),
+  // [16..17] pair counter
   int32_t* cnt = nullptr;
 
   // sorting / scans

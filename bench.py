@@ -11,9 +11,13 @@ timed region starts.  One step = one pass of the whole coupled step
 (mass-balance superflow, 4 RK stages of Biot-Savart + LIA + interpolation +
 Schwarz, force spreading, LBM collide+stream, remeshing).
 
+The run advances in launches of a HIP graph holding 10 captured steps
+(``--graph 0``: steps enqueued one by one).
+
 Prints ONE JSON line.  ``value`` is coupled steps per second on the one GPU;
-``roofline`` is for the dominant kernel (the Biot-Savart pair sum), timed
-with HIP events on the run's stream over the timed steps; ``cpu_baseline``
+``roofline`` is for the dominant kernel (the Biot-Savart pair sum), its
+launch duration measured with HIP events on the run's stream (50 launches
+back to back at the final state, after the timed steps); ``cpu_baseline``
 times the FP64 oracle on the host on a bounded sample of the same workload.
 """
 
@@ -72,10 +76,10 @@ def traffic_record(kernel_src):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, n_sample=8192):
+def cpu_baseline(cfg, n_evals=2):
     """Oracle (plain FP64 numpy) on the host: one full LBM update of the
-    lattice plus the Biot-Savart sum for a sample of targets against all
-    segments, scaled to one coupled step (4 Biot-Savart evaluations)."""
+    lattice plus n_evals full Biot-Savart sums (every target against every
+    segment), scaled to one coupled step (4 Biot-Savart evaluations)."""
     from oracle import coupled, lbm, vfm
     from oracle.lbm import Lattice
     from oracle.vfm import VortexParams
@@ -87,20 +91,20 @@ def cpu_baseline(cfg, n_sample=8192):
     vp = VortexParams(**{k: cfg["vortex"][k] for k in VortexParams.__dataclass_fields__})
     st = coupled.make_state(cfg["rho"], cfg["u"], cfg["pos"], cfg["nxt"], lat)
     n = st.pos.shape[0]
-    m = min(n, n_sample)
     t0 = time.perf_counter()
     _, ub = lbm.bare_velocity(st.f, lat)
     if vp.mass_balance:
         lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n)
     lbm.lbm_step(st.f, np.zeros((3,) + lat.shape), lat)
     t1 = time.perf_counter()
-    vfm.biot_savart_nonlocal(st.pos, st.nxt, st.prv, lat, vp.kappa, targets=np.arange(m))
+    for _ in range(n_evals):
+        vfm.biot_savart_nonlocal(st.pos, st.nxt, st.prv, lat, vp.kappa)
     t2 = time.perf_counter()
-    t_step = (t1 - t0) + 4.0 * (t2 - t1) * n / m
+    t_step = (t1 - t0) + 4.0 * (t2 - t1) / n_evals
     return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
-                sample=f"one FP64 LBM update of all {lat.nx}x{lat.ny}x{lat.nz} nodes plus the "
-                       f"Biot-Savart sum for {m} of {n} targets over all segments, scaled to one "
-                       f"coupled step (4 evaluations); numpy, single thread; "
+                sample=f"one FP64 LBM update of all {lat.nx}x{lat.ny}x{lat.nz} nodes plus "
+                       f"{n_evals} full Biot-Savart sums ({n} targets x all segments), scaled to "
+                       f"one coupled step (4 evaluations); numpy, single thread; "
                        f"measured {t2 - t0:.1f} s")
 
 
@@ -167,7 +171,7 @@ def main():
     ap.add_argument("--workload", default="counterflow", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=("f64", "f32", "f16"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", type=int, default=0,
+    ap.add_argument("--graph", type=int, default=10,
                     help="advance in HIP-graph launches of this many steps (even); 0: direct")
     ap.add_argument("--no-lbm-probe", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
@@ -221,6 +225,7 @@ def main():
     nev = K // unit
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(nev)]
+    # per-launch kernel events inside the steps only when stepping directly
     run.set_timing(not G, reserve=2 * 6 * K + 64)  # also zeroes the work counters
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -234,22 +239,21 @@ def main():
     run.sync()
     wall = t1 - t0
     step_ms = np.array([a.elapsed_time(b) for a, b in ev]) / unit
-    if G:
-        bs_ms = lbm_ms = 0.0
-        bs_n = lbm_n = 0
-    else:
-        bs_ms, bs_n = run.timing(0)
-        lbm_ms, lbm_n = run.timing(1)
     nodes, pairs = run.work()
+    in_step = None
+    if not G:
+        bs_ms, bs_n = run.timing(0)
+        in_step = {"bs_avg_launch_us": round(bs_ms * 1e3 / max(bs_n, 1), 2),
+                   "bs_pairs_per_launch": int(pairs / max(bs_n, 1)),
+                   "note": "HIP events around every launch inside the steps (adds event overhead)"}
     n_end = run.n_points()
     # the dominant kernel alone, launched back to back on the final state
-    # (per-launch event pairs inside the step add their own overhead)
     bs_iso_ms = run.time_kernel(0, reps=50)
     pairs_iso = n_end * (n_end - 2)
+    # the LBM update alone (advances the fluid; after the timed region)
+    lbm_iso_ms = run.time_kernel(1, reps=20)
 
     value = K / wall
-    pairs_per_launch = pairs / max(bs_n, 1)
-    bs_avg_s = bs_ms * 1e-3 / max(bs_n, 1)
     achieved = FLOPS_PER_PAIR * pairs_iso / (bs_iso_ms * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_2108_04435_amd", "csrc", "bs.hip")
     roofline = {
@@ -263,12 +267,10 @@ def main():
         "avg_launch_us": round(bs_iso_ms * 1e3, 2),
         "pairs_per_launch": int(pairs_iso),
         "flops_per_pair": FLOPS_PER_PAIR,
-        "in_step_event_avg_launch_us": round(bs_avg_s * 1e6, 2),
-        "in_step_pairs_per_launch": int(pairs_per_launch),
+        "in_step": in_step,
     }
     b = {"f64": 8, "f32": 4, "f16": 2}[lat["precision"]]
     lbm_bytes = 2 * 19 * b * cells
-    lbm_avg = lbm_ms * 1e-3 / max(lbm_n, 1)
     out = {
         "metric": "coupled steps/s (LBM MLUPS + Biot-Savart Gpairs/s), FP32/FP16 vs FP64; p99",
         "value": round(value, 3),
@@ -295,13 +297,14 @@ def main():
         "graph_steps": G,
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "step_time_basis": (f"per graph launch of {G} steps / {G}" if G else "per step"),
         "mlups": round(cells * K / wall / 1e6, 1),
         "bs_gpairs_s": round(pairs / wall / 1e9, 2),
-        "bs_kernel_gpairs_s": round(pairs / (bs_ms * 1e-3) / 1e9, 2) if bs_ms else None,
-        "lbm_kernel": None if G else {"avg_launch_us": round(lbm_avg * 1e6, 2),
-                       "glups": round(cells / lbm_avg / 1e9, 2) if lbm_n else None,
-                       "algorithmic_GBs": round(lbm_bytes / lbm_avg / 1e9, 1) if lbm_n else None,
-                       "note": "working set fits the 256 MB last-level cache"},
+        "bs_kernel_gpairs_s": round(pairs_iso / (bs_iso_ms * 1e-3) / 1e9, 2),
+        "lbm_kernel": {"avg_launch_us": round(lbm_iso_ms * 1e3, 2),
+                       "glups": round(cells / (lbm_iso_ms * 1e-3) / 1e9, 2),
+                       "algorithmic_GBs": round(lbm_bytes / (lbm_iso_ms * 1e-3) / 1e9, 1),
+                       "note": "20 launches back to back; this lattice fits the 256 MB last-level cache"},
         "roofline": roofline,
     }
     run.close()

@@ -517,22 +517,26 @@ int one_step(vlb_run* h, bool first, bool last) {
     if (s == 0 && spread) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
     // the side stream's work is enqueued after the main stream's next
     // kernel, so that a graph keeps the main chain on one queue
-    if (s == 1 && spread) {
-      HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
+    if (s == 1) {
+      if (spread) HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
       OnStream on(r, S);
-      HIP_OR_FAIL(h, fil_spread(r));
+      if (spread) HIP_OR_FAIL(h, fil_spread(r));
+      // the LBM update on a narrow grid beside the Biot-Savart sums
+      r.lbm_narrow = true;
+      const hipError_t le = lbm_step(r);
+      r.lbm_narrow = false;
+      if (le != hipSuccess) return hip_fail(h, le, "lbm_step(r)");
     }
   }
   HIP_OR_FAIL(h, hipEventRecord(r.ev_fin4, M));
   HIP_OR_FAIL(h, topo_update(r));
-  HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
-  {
+  if (!last) {
+    // f^(n+1): moments of the next step, once the stages stopped reading
+    // the velocity field
+    HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
     OnStream on(r, S);
-    HIP_OR_FAIL(h, lbm_step(r));
-    if (!last) {
-      HIP_OR_FAIL(h, lbm_moments(r));  // f^(n+1): moments of the next step
-      HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
-    }
+    HIP_OR_FAIL(h, lbm_moments(r));
+    HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   }
   if (last) {
     HIP_OR_FAIL(h, hipEventRecord(r.ev_join, S));

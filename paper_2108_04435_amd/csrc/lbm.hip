@@ -20,18 +20,10 @@ namespace {
 // f''' = f - (f - f^eq)/tau + F, with f^eq and the Cheng-Li/Guo term F built
 // from rho and u = (sum c f + g/2)/rho.
 template <class S, int P>
-__global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
-                                                        const typename Store<S>::T* __restrict__ F,
-                                                        Geom g, int nbx, int nby, int nblk) {
+__device__ __forceinline__ void collide_node(S* __restrict__ M,
+                                             const typename Store<S>::T* __restrict__ F,
+                                             const Geom& g, int x, int y, int z) {
   using T = typename Store<S>::T;
-  const int t = xcd_remap(blockIdx.x, nblk);
-  const int bxi = t % nbx;
-  const int rr = t / nbx;
-  const int byi = rr % nby;
-  const int z = rr / nby;
-  const int x = bxi * blockDim.x + threadIdx.x;
-  const int y = byi * blockDim.y + threadIdx.y;
-  if (x >= g.nx || y >= g.ny) return;
   const long long c = ((long long)z * g.ny + y) * g.nx + x;
 
   T d[19];
@@ -85,6 +77,26 @@ __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
       else
         Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
     }
+  }
+}
+
+// Tiles of 64 x 4 nodes (x, y) of one z slice; hardware blocks are mapped
+// so that the blocks of one XCD cover one contiguous range of tiles.  The
+// grid may be smaller than the tile count (a multiple of 8): each block
+// then walks tiles b, b + grid, ..., which stay on its XCD's range.
+template <class S, int P>
+__global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
+                                                        const typename Store<S>::T* __restrict__ F,
+                                                        Geom g, int nbx, int nby, int nblk) {
+  for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
+    const int t = xcd_remap(it, nblk);
+    const int bxi = t % nbx;
+    const int rr = t / nbx;
+    const int byi = rr % nby;
+    const int z = rr / nby;
+    const int x = bxi * blockDim.x + threadIdx.x;
+    const int y = byi * blockDim.y + threadIdx.y;
+    if (x < g.nx && y < g.ny) collide_node<S, P>(M, F, g, x, y, z);
   }
 }
 
@@ -216,11 +228,15 @@ hipError_t launch_collide(Run& r) {
   const int nblk = nbx * nby * g.nz;
   const T* F = (r.vor.coupling && r.ncap > 0) ? (const T*)r.force : nullptr;
   dim3 blk(bx, by);
+  // beside the filament kernels the update runs on a narrow grid (two
+  // blocks per CU), leaving most CU slots to the other stream
+  int grid = nblk;
+  if (r.lbm_narrow && grid > 512) grid = 512;
   if (r.parity == 0)
-    hipLaunchKernelGGL((k_collide_stream<S, 0>), dim3(nblk), blk, 0, r.stream, (S*)r.pops, F, g,
+    hipLaunchKernelGGL((k_collide_stream<S, 0>), dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g,
                        nbx, nby, nblk);
   else
-    hipLaunchKernelGGL((k_collide_stream<S, 1>), dim3(nblk), blk, 0, r.stream, (S*)r.pops, F, g,
+    hipLaunchKernelGGL((k_collide_stream<S, 1>), dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g,
                        nbx, nby, nblk);
   return hipGetLastError();
 }

@@ -325,6 +325,7 @@ struct Run {
 
   int64_t step = 0;
   int parity = 0;
+  bool lbm_narrow = false;  // LBM update launched beside the filament kernels
   bool has_fields = false;
   bool has_points = false;  // set once filaments were seeded
 

@@ -478,11 +478,11 @@ struct OnStream {
 // Dependencies (events): finalize 1 needs the moments (velocity field and
 // superflow); the spreading needs finalize 1, which leaves it the point
 // forces, bin keys, stencil offsets and point count, so the spreading reads
-// nothing the later stages or the topology rewrite.  The LBM update and the
-// next step's moments (which overwrite the velocity field the stages read)
-// wait for finalize 4: they run beside the topology, a phase of short
-// latency-bound kernels, rather than beside the compute-bound Biot-Savart
-// sums.  The first step of a call forks the side
+// nothing the later stages or the topology rewrite.  The LBM update follows
+// the spreading on the side stream, launched on a narrow grid (two blocks
+// per CU) so that it leaves most CU slots to the filament kernels beside
+// it.  The next step's moments overwrite the velocity field the stages
+// read, so they wait for finalize 4 and run beside the topology.  The first step of a call forks the side
 // stream from main and computes its own moments; the last one joins the
 // side stream back, so a call's work is ordered on the caller's stream.
 int one_step(vlb_run* h, bool first, bool last) {

@@ -48,8 +48,10 @@ typedef enum {
   VLB_EDEVICE = -3,   /* a HIP call failed                                  */
   VLB_ESTATE = -4,    /* call out of order (e.g. step before any fields)    */
   VLB_ECAPACITY = -5, /* filament points or reconnection candidates
-                         exceeded their capacity; the step that overflowed
-                         skipped the operation that needed the room         */
+                         exceeded their capacity (n_cap; recon_cap in the
+                         step, or 8 candidates at one point); the step that
+                         overflowed skipped the operation that needed the
+                         room                                               */
   VLB_ENUMERIC = -6   /* NaN/Inf met in the normal-fluid or line velocity   */
 } vlb_status;
 

@@ -328,7 +328,9 @@ int latched(vlb_run* h) {
     HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
     if (flags & kFlagNumeric) return fail(h, VLB_ENUMERIC, "non-finite line velocity");
     if (flags & kFlagCapacity) return fail(h, VLB_ECAPACITY, "filament points exceeded n_cap; insertion skipped");
-    if (flags & kFlagReconCap) return fail(h, VLB_ECAPACITY, "reconnection candidates exceeded recon_cap; reconnection skipped");
+    if (flags & kFlagReconCap)
+      return fail(h, VLB_ECAPACITY,
+                  "reconnection candidates exceeded recon_cap (or 8 at one point); reconnection skipped");
   }
   return VLB_OK;
 }
@@ -535,7 +537,10 @@ int one_step(vlb_run* h, bool first, bool last) {
     // the velocity field
     HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
     OnStream on(r, S);
-    HIP_OR_FAIL(h, lbm_moments(r));
+    r.lbm_narrow = true;
+    const hipError_t me = lbm_moments(r);
+    r.lbm_narrow = false;
+    if (me != hipSuccess) return hip_fail(h, me, "lbm_moments(r)");
     HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   }
   if (last) {

@@ -319,7 +319,9 @@ hipError_t lbm_read_force(Run& r, double* out) {
 hipError_t lbm_moments(Run& r) {
   const Geom& g = r.geom;
   const int bx = g.nx < 64 ? g.nx : 64;
-  int by = 1024 / bx;
+  // beside the filament kernels: 256 threads per slice block, else 1024
+  int by = (r.lbm_narrow ? 256 : 1024) / bx;
+  if (by < 1) by = 1;
   if (by > g.ny) by = g.ny;
   dim3 blk(bx, by);
   double* Vs = r.vor.mass_balance ? r.Vs : nullptr;

@@ -238,3 +238,116 @@ def test_graph_replay_matches_direct_steps():
         assert graphed.get_step() == 12
         direct.close()
         graphed.close()
+
+
+def test_one_call_equals_single_steps():
+    """n steps in one call (the next step's moments computed at the end of
+    the previous step on the side stream) are bitwise equal to n calls of
+    one step (each forking and joining the side stream)."""
+    cfg = small_channel(precision="f32", reconnect=True, seed=26)
+    say("one call vs single steps")
+    a = vlb.run_from_config(cfg)
+    b = vlb.run_from_config(cfg)
+    a.step(6)
+    for _ in range(6):
+        b.step(1)
+    a.sync()
+    b.sync()
+    for x, y in zip(_final_state(a), _final_state(b)):
+        np.testing.assert_array_equal(x, y)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_uncoupled_run(precision):
+    """Coupling off: the filaments move in the normal fluid, which evolves
+    as if they were absent (no spreading, no force in the LBM update)."""
+    cfg = small_channel(precision=precision)
+    cfg["vortex"] = dict(cfg["vortex"], coupling=False)
+    steps = 6
+    say("uncoupled", precision)
+    run = vlb.run_from_config(cfg)
+    run.step(steps)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    assert not vp.coupling
+    for _ in range(steps):
+        st = coupled.coupled_step(st, lat, vp)
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) <= TOL[precision]
+    pos_g, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    d = vfm.min_image(pos_g - st.pos, lat)
+    assert np.abs(d).max() < (1e-10 if precision == "f64" else 1e-4)
+    assert np.abs(run.read_force()).max() == 0.0
+
+
+def test_all_loops_vanish():
+    """A loop shorter than the minimum is removed by the first topology
+    pass; the run continues with no points as a pure LBM run."""
+    cfg = small_channel(precision="f64")
+    pos, nxt = wl.ring((8.0, 8.0, 16.0), 0.6, (0, 0, 1), 4)
+    cfg = dict(cfg, pos=pos, nxt=nxt)
+    say("all loops vanish")
+    run = vlb.run_from_config(cfg)
+    run.step(3)
+    run.sync()
+    assert run.n_points() == 0
+    lat, vp, st = oracle_state(cfg)
+    for _ in range(3):
+        st = coupled.coupled_step(st, lat, vp)
+    assert st.pos.shape[0] == 0
+    np.testing.assert_allclose(run.read_populations(), st.f, rtol=0, atol=1e-12)
+
+
+def _bundle(n_b, r=0.4, nz=20, L=16.0):
+    """Line A along +z through (8, 8) and n_b lines along -z at distance r
+    around it: every point of A has one exchange candidate on each B line."""
+    z = (np.arange(nz) + 0.5) * L / nz
+    pos = [np.stack([np.full(nz, 8.0), np.full(nz, 8.0), z], 1)]
+    nxt = [(np.arange(nz) + 1) % nz]
+    for m in range(n_b):
+        ang = 2 * np.pi * m / n_b
+        pos.append(np.stack([np.full(nz, 8.0 + r * np.cos(ang)), np.full(nz, 8.0 + r * np.sin(ang)), z], 1))
+        nxt.append((m + 1) * nz + (np.arange(nz) - 1) % nz)
+    return np.concatenate(pos), np.concatenate(nxt)
+
+
+def test_reconnection_slot_overflow_skips():
+    """More candidates at one point than its slots: the step reports
+    VLB_ECAPACITY and leaves the links unchanged (reconnection skipped)."""
+    lat = wl.lattice_preset(16, 16, 16, precision="f64")
+    vor = wl.vortex_preset(reconnect=True, remesh=False)
+    pos, nxt = _bundle(9)
+    say("slot overflow", pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0], recon_cap=1 << 14)
+    run.seed(pos, nxt)
+    with pytest.raises(vlb.VlbError) as ei:
+        run.apply_topology()
+    assert ei.value.code == vlb.VLB_ECAPACITY
+    _, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, nxt)
+    # with slots to spare (4 lines) the same kind of bundle reconnects
+    pos4, nxt4 = _bundle(4)
+    run4 = vlb.Run(lat, vor, n_cap=2 * pos4.shape[0], recon_cap=1 << 14)
+    run4.seed(pos4, nxt4)
+    stats = run4.apply_topology()
+    assert stats["reconnections"] > 0
+
+
+def test_reconnection_list_capacity_skips():
+    """More candidates in the step than recon_cap: VLB_ECAPACITY, links
+    unchanged."""
+    lat = wl.lattice_preset(16, 16, 16, precision="f64")
+    vor = wl.vortex_preset(reconnect=True, remesh=False)
+    pos, nxt = _bundle(2)
+    say("list capacity", pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0], recon_cap=4)
+    run.seed(pos, nxt)
+    with pytest.raises(vlb.VlbError) as ei:
+        run.apply_topology()
+    assert ei.value.code == vlb.VLB_ECAPACITY
+    _, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, nxt)

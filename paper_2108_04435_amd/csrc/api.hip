@@ -121,7 +121,7 @@ size_t layout(Run& r, char* base) {
                        &r.scan_a, &r.scan_b, &r.used};
   for (int32_t** p : ibufs) *p = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   r.bsX = (uint32_t*)B.take(3 * nc * sizeof(uint32_t));
-  r.bsD = B.take(4 * nc * fe);
+  r.bsD = B.take((r.prec == VLB_F64 ? 6 : 4) * nc * fe);  // FP64: d (3) and residuals (3)
   size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));

@@ -24,8 +24,11 @@ namespace {
 constexpr int kTile = 256;
 
 // Grid coordinates of the points at positions Y, and for the FP64 path the
-// segment vectors (nearest image, lattice units).  The FP32 sum takes each
-// segment vector as the wrapped grid difference to the successor.
+// segment vectors (nearest image, lattice units) and the residuals
+// rho = (y + off) - X / q of the positions below their grid value (taken
+// with the unwrapped grid value), so that y_s - y_t of the image the grid
+// difference chooses is (X_s - X_t) / q + rho_s - rho_t.  The FP32 sum
+// takes each segment vector as the wrapped grid difference to the successor.
 template <class T>
 __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
                        const int32_t* __restrict__ cnt, long long ncap, BsAxes ax,
@@ -46,7 +49,10 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
       else if (d < -0.5 * ax.L[a])
         d = d + ax.L[a];
     }
-    if (sizeof(T) == 8) D[a * ncap + j] = (T)d;
+    if (sizeof(T) == 8) {
+      D[a * ncap + j] = (T)d;
+      D[(3 + a) * ncap + j] = (T)((y + ax.off[a]) - s * ax.invq_d[a]);
+    }
   }
 }
 
@@ -162,14 +168,72 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   }
 }
 
-// FP64 pair sum (plain path): FP64 separations at the image chosen on the
-// grid, the closed form exactly as written, IEEE sqrt and division.
+// FP64 pair sum (plain path).  R1 = (X_s - X_t) / q + (rho_s - rho_t): the
+// wrapped grid difference picks the image (the same decision as the FP32
+// sum), the residuals restore the FP64 separation of that image to
+// rounding; R2 = R1 + d.  The closed form is evaluated with the inverse
+// norms and the reciprocal of the hardware approximations, each refined by
+// two Newton steps (a few ulp), and the same checked / unchecked tile split
+// as the FP32 sum.
+__device__ inline double rsq_nr(double n) {
+  double y = __builtin_amdgcn_rsq(n);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(n * y), y, 1.0);  // 1 - n y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ inline double rcp_nr(double d) {
+  double q = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d, q, 1.0);
+    q = fma(q, e, q);
+  }
+  return q;
+}
+
+template <bool kCheck>
+__device__ inline void bs_tile_f64(const uint32_t* sx, const uint32_t* sy, const uint32_t* sz,
+                                   const double* rx, const double* ry, const double* rz,
+                                   const double* dx, const double* dy, const double* dz, int cnt,
+                                   int t0, uint32_t xt, uint32_t yt, uint32_t zt, double rtx,
+                                   double rty, double rtz, double gx, double gy, double gz, int jj,
+                                   int pj, double& ax, double& ay, double& az) {
+#pragma unroll 2
+  for (int s = 0; s < cnt; ++s) {
+    const double r1x = fma((double)(int)(sx[s] - xt), gx, rx[s] - rtx);
+    const double r1y = fma((double)(int)(sy[s] - yt), gy, ry[s] - rty);
+    const double r1z = fma((double)(int)(sz[s] - zt), gz, rz[s] - rtz);
+    const double ex = dx[s], ey = dy[s], ez = dz[s];
+    const double r2x = r1x + ex, r2y = r1y + ey, r2z = r1z + ez;
+    const double n1 = r1x * r1x + r1y * r1y + r1z * r1z;
+    const double n2 = r2x * r2x + r2y * r2y + r2z * r2z;
+    const double u = r1x * r2x + r1y * r2y + r1z * r2z;
+    const double crx = r1y * ez - r1z * ey;
+    const double cry = r1z * ex - r1x * ez;
+    const double crz = r1x * ey - r1y * ex;
+    const double i1 = rsq_nr(n1);
+    const double i2 = rsq_nr(n2);
+    const double a = i1 * i2;
+    double f = (i1 + i2) * a * rcp_nr(fma(u, a, 1.0));
+    if (kCheck) {
+      const int k = t0 + s;
+      f = (k == jj || k == pj) ? 0.0 : f;
+    }
+    ax = fma(f, crx, ax);
+    ay = fma(f, cry, ay);
+    az = fma(f, crz, az);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
                                                const double* __restrict__ D,
-                                               const double* __restrict__ Y,
                                                const int32_t* __restrict__ prv,
                                                int32_t* __restrict__ cntp, long long ncap,
-                                               int S, double Lx, double Ly, double Lz,
+                                               int S, double gx, double gy, double gz,
                                                double* __restrict__ P) {
   const int n = cntp[0];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
@@ -184,12 +248,13 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   const uint32_t xt = valid ? X[j] : 0u;
   const uint32_t yt = valid ? X[ncap + j] : 0u;
   const uint32_t zt = valid ? X[2 * ncap + j] : 0u;
-  const double px = valid ? Y[j] : 0.0;
-  const double py = valid ? Y[ncap + j] : 0.0;
-  const double pz = valid ? Y[2 * ncap + j] : 0.0;
+  const double rtx = valid ? D[3 * ncap + j] : 0.0;
+  const double rty = valid ? D[4 * ncap + j] : 0.0;
+  const double rtz = valid ? D[5 * ncap + j] : 0.0;
   const int pj = valid ? prv[j] : -1;
+  const int jj = valid ? j : -1;
   __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
-  __shared__ double qx[kTile], qy[kTile], qz[kTile];
+  __shared__ double rx[kTile], ry[kTile], rz[kTile];
   __shared__ double dx[kTile], dy[kTile], dz[kTile];
   double ax = 0.0, ay = 0.0, az = 0.0;
   for (int t0 = kb; t0 < ke; t0 += kTile) {
@@ -198,41 +263,22 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
       sx[threadIdx.x] = X[k];
       sy[threadIdx.x] = X[ncap + k];
       sz[threadIdx.x] = X[2 * ncap + k];
-      qx[threadIdx.x] = Y[k];
-      qy[threadIdx.x] = Y[ncap + k];
-      qz[threadIdx.x] = Y[2 * ncap + k];
       dx[threadIdx.x] = D[k];
       dy[threadIdx.x] = D[ncap + k];
       dz[threadIdx.x] = D[2 * ncap + k];
+      rx[threadIdx.x] = D[3 * ncap + k];
+      ry[threadIdx.x] = D[4 * ncap + k];
+      rz[threadIdx.x] = D[5 * ncap + k];
     }
     __syncthreads();
     const int cnt = min(kTile, ke - t0);
-    if (valid) {
-      for (int s = 0; s < cnt; ++s) {
-        const int kk = t0 + s;
-        if (kk == j || kk == pj) continue;
-        // image shift from the grid: wrapped minus raw difference / 2^32
-        const long long hx = ((long long)(int)(sx[s] - xt) - ((long long)sx[s] - (long long)xt)) >> 32;
-        const long long hy = ((long long)(int)(sy[s] - yt) - ((long long)sy[s] - (long long)yt)) >> 32;
-        const long long hz = ((long long)(int)(sz[s] - zt) - ((long long)sz[s] - (long long)zt)) >> 32;
-        const double r1x = (qx[s] - px) + (double)hx * Lx;
-        const double r1y = (qy[s] - py) + (double)hy * Ly;
-        const double r1z = (qz[s] - pz) + (double)hz * Lz;
-        const double r2x = r1x + dx[s];
-        const double r2y = r1y + dy[s];
-        const double r2z = r1z + dz[s];
-        const double n1 = sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
-        const double n2 = sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
-        const double crx = r1y * r2z - r1z * r2y;
-        const double cry = r1z * r2x - r1x * r2z;
-        const double crz = r1x * r2y - r1y * r2x;
-        const double dt = r1x * r2x + r1y * r2y + r1z * r2z;
-        const double fac = (n1 + n2) / (n1 * n2 * (n1 * n2 + dt));
-        ax += crx * fac;
-        ay += cry * fac;
-        az += crz * fac;
-      }
-    }
+    const bool hit = valid && ((jj >= t0 && jj < t0 + cnt) || (pj >= t0 && pj < t0 + cnt));
+    if (__any(hit))
+      bs_tile_f64<true>(sx, sy, sz, rx, ry, rz, dx, dy, dz, cnt, t0, xt, yt, zt, rtx, rty, rtz,
+                        gx, gy, gz, jj, pj, ax, ay, az);
+    else
+      bs_tile_f64<false>(sx, sy, sz, rx, ry, rz, dx, dy, dz, cnt, t0, xt, yt, zt, rtx, rty, rtz,
+                         gx, gy, gz, jj, pj, ax, ay, az);
     __syncthreads();
   }
   if (valid) {
@@ -272,9 +318,9 @@ hipError_t bs_sum(Run& r, const double* Y) {
   hipEvent_t b = nullptr;
   time_begin(r, 0, &b);
   if (r.prec == VLB_F64)
-    hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD, Y,
-                       r.prv, r.cnt, r.ncap, r.bsS, r.bsax.L[0], r.bsax.L[1], r.bsax.L[2],
-                       (double*)r.bsP);
+    hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD,
+                       r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_d[0], r.bsax.invq_d[1],
+                       r.bsax.invq_d[2], (double*)r.bsP);
   else if (r.bsax.uniform)
     hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],

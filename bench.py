@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 # numerator and scale 3, accumulation 6.
 FLOPS_PER_PAIR = 41
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X published FP64 vector peak
 PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
 
 WORKLOADS = ("counterflow", "ring32", "heater", "tangle", "serve")
@@ -256,14 +257,16 @@ def main():
     value = K / wall
     achieved = FLOPS_PER_PAIR * pairs_iso / (bs_iso_ms * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_2108_04435_amd", "csrc", "bs.hip")
+    f64 = lat["precision"] == "f64"
+    peak = PEAK_FP64_VECTOR_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS
     roofline = {
         "bound": "alu",
-        "kernel": "k_bs_f32" if lat["precision"] != "f64" else "k_bs_f64",
+        "kernel": "k_bs_f64" if f64 else "k_bs_f32",
         "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_VECTOR_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": traffic_record(src),
+        "frac": round(achieved / peak, 4),
+        "traffic": None if f64 else traffic_record(src),
         "avg_launch_us": round(bs_iso_ms * 1e3, 2),
         "pairs_per_launch": int(pairs_iso),
         "flops_per_pair": FLOPS_PER_PAIR,

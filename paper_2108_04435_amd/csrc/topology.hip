@@ -462,7 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
   int j = head[key];
   if (j < 0) return;
   const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
-  while (j >= 0) {
+  const int bound = cnt[9];
+  for (int guard = 0; j >= 0 && guard < bound; ++guard) {  // bounded by the point count
     const int jc = j;
     j = lnext[jc];
     if (jc <= i || jc == ni || jc == nni || jc == pi || jc == ppi) continue;

@@ -133,6 +133,25 @@ def lbm_only(torch, vlb, wl, n, precision, steps=20):
                 achieved_GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
 
 
+def hbm_copy(torch, nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy far above the last-level cache: the
+    practical HBM rate (read + write bytes over time) beside the peak."""
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    return dict(bytes=2 * nbytes, ms=round(ms, 4), GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
+
+
 def serve_bench(args):
     """Served form: 64 counterflow requests arriving as a Poisson stream at
     2/s, lattices {32^3, 64^3, 64x64x256, 128x128x256}, 1k-20k points,
@@ -326,6 +345,7 @@ def main():
     if not args.no_lbm_probe:
         out["lbm_256cubed"] = [lbm_only(torch, vlb, wl, 256, p) for p in ("f32", "f16")]
         torch.cuda.empty_cache()
+        out["hbm_copy"] = hbm_copy(torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)

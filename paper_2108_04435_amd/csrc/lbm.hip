@@ -19,7 +19,7 @@ namespace {
 // Post-collision deviation (Sec. II.B, Eqs. LBM 1-3 collapsed):
 // f''' = f - (f - f^eq)/tau + F, with f^eq and the Cheng-Li/Guo term F built
 // from rho and u = (sum c f + g/2)/rho.
-template <class S, int P>
+template <class S, int P, bool NT>
 __device__ __forceinline__ void collide_node(S* __restrict__ M,
                                              const typename Store<S>::T* __restrict__ F,
                                              const Geom& g, int x, int y, int z) {
@@ -31,13 +31,13 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
   if (P == 1) make_nbr(g, x, y, z, nb);
   if (P == 0) {
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = Store<S>::ld(M + (long long)i * g.cells + c);
+    for (int i = 0; i < 19; ++i) d[i] = pop_ld<S, NT>(M + (long long)i * g.cells + c);
   } else {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const long long s = nbr_index(nb, -cx(i), -cy(i), -cz(i));
-      d[i] = (s >= 0) ? Store<S>::ld(M + (long long)opp(i) * g.cells + s)
-                      : Store<S>::ld(M + (long long)i * g.cells + c);
+      d[i] = (s >= 0) ? pop_ld<S, NT>(M + (long long)opp(i) * g.cells + s)
+                      : pop_ld<S, NT>(M + (long long)i * g.cells + c);
     }
   }
   if (is_plane(g, z)) {
@@ -69,13 +69,13 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
     const T Fi = pref * T(wq(i)) * (T(3) * (cg - ug) + T(9) * cu * cg);
     const T dn = d[i] - om * (d[i] - deq) + Fi;
     if (P == 0) {
-      Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
+      pop_st<S, NT>(M + (long long)opp(i) * g.cells + c, dn);
     } else {
       const long long s = nbr_index(nb, cx(i), cy(i), cz(i));
       if (s >= 0)
-        Store<S>::st(M + (long long)i * g.cells + s, dn);
+        pop_st<S, NT>(M + (long long)i * g.cells + s, dn);
       else
-        Store<S>::st(M + (long long)opp(i) * g.cells + c, dn);
+        pop_st<S, NT>(M + (long long)opp(i) * g.cells + c, dn);
     }
   }
 }
@@ -84,7 +84,7 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
 // so that the blocks of one XCD cover one contiguous range of tiles.  The
 // grid may be smaller than the tile count (a multiple of 8): each block
 // then walks tiles b, b + grid, ..., which stay on its XCD's range.
-template <class S, int P>
+template <class S, int P, bool NT>
 __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
                                                         const typename Store<S>::T* __restrict__ F,
                                                         Geom g, int nbx, int nby, int nblk) {
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
     const int z = rr / nby;
     const int x = bxi * blockDim.x + threadIdx.x;
     const int y = byi * blockDim.y + threadIdx.y;
-    if (x < g.nx && y < g.ny) collide_node<S, P>(M, F, g, x, y, z);
+    if (x < g.nx && y < g.ny) collide_node<S, P, NT>(M, F, g, x, y, z);
   }
 }
 
@@ -217,6 +217,11 @@ __global__ __launch_bounds__(1024) void k_moments(const S* __restrict__ M, Geom 
 
 inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
 
+// Population arrays above this size are streamed with non-temporal hints
+// (the last-level cache is 256 MB; smaller lattices stay resident in it
+// from one step to the next).
+constexpr double kStreamBytes = 192.0 * (1 << 20);
+
 template <class S>
 hipError_t launch_collide(Run& r) {
   using T = typename Store<S>::T;
@@ -226,18 +231,18 @@ hipError_t launch_collide(Run& r) {
   const int nbx = (g.nx + bx - 1) / bx;
   const int nby = (g.ny + by - 1) / by;
   const int nblk = nbx * nby * g.nz;
-  const T* F = (r.vor.coupling && r.ncap > 0) ? (const T*)r.force : nullptr;
+  // the spread force field exists once filaments were seeded into a coupled run
+  const T* F = (r.vor.coupling && r.has_points) ? (const T*)r.force : nullptr;
   dim3 blk(bx, by);
   // beside the filament kernels the update runs on a narrow grid (two
   // blocks per CU), leaving most CU slots to the other stream
   int grid = nblk;
   if (r.lbm_narrow && grid > 512) grid = 512;
-  if (r.parity == 0)
-    hipLaunchKernelGGL((k_collide_stream<S, 0>), dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g,
-                       nbx, nby, nblk);
-  else
-    hipLaunchKernelGGL((k_collide_stream<S, 1>), dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g,
-                       nbx, nby, nblk);
+  // populations far above the last-level cache: non-temporal accesses
+  const bool nt = 19.0 * (double)g.cells * sizeof(S) > kStreamBytes;
+  auto kern = r.parity == 0 ? (nt ? k_collide_stream<S, 0, true> : k_collide_stream<S, 0, false>)
+                            : (nt ? k_collide_stream<S, 1, true> : k_collide_stream<S, 1, false>);
+  hipLaunchKernelGGL(kern, dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g, nbx, nby, nblk);
   return hipGetLastError();
 }
 

@@ -39,22 +39,47 @@ constexpr float kHalfScale = 1024.0f;
 constexpr float kHalfInvScale = 1.0f / 1024.0f;
 
 // Storage traits: memory holds deviations d_i = f_i - w_i (rho0 = 1).
+// Population storage; the _nt forms carry the non-temporal hint, for
+// lattices far larger than the last-level cache (every value is read once
+// and written once per update).
 template <class S> struct Store;
 template <> struct Store<double> {
   using T = double;
   __device__ static T ld(const double* p) { return *p; }
   __device__ static void st(double* p, T v) { *p = v; }
+  __device__ static T ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void st_nt(double* p, T v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<float> {
   using T = float;
   __device__ static T ld(const float* p) { return *p; }
   __device__ static void st(float* p, T v) { *p = v; }
+  __device__ static T ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void st_nt(float* p, T v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<__half> {
   using T = float;
   __device__ static T ld(const __half* p) { return __half2float(*p) * kHalfInvScale; }
   __device__ static void st(__half* p, T v) { *p = __float2half_rn(v * kHalfScale); }
+  __device__ static T ld_nt(const __half* p) {
+    const unsigned short u = __builtin_nontemporal_load((const unsigned short*)p);
+    return __half2float(__ushort_as_half(u)) * kHalfInvScale;
+  }
+  __device__ static void st_nt(__half* p, T v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * kHalfScale)), (unsigned short*)p);
+  }
 };
+template <class S, bool NT>
+__device__ inline typename Store<S>::T pop_ld(const S* p) {
+  return NT ? Store<S>::ld_nt(p) : Store<S>::ld(p);
+}
+template <class S, bool NT>
+__device__ inline void pop_st(S* p, typename Store<S>::T v) {
+  if (NT)
+    Store<S>::st_nt(p, v);
+  else
+    Store<S>::st(p, v);
+}
 
 // Lattice description as passed to kernels.
 struct Geom {

@@ -21,13 +21,22 @@ struct SpreadGeom {
   int ext[3];  // bins per axis: n (periodic) or n + 1 (wall: lower corner -1..n-1)
 };
 
+// floor of a coordinate as an int; 0 for a non-finite or absurd value, so
+// that a position that blew up still yields an index inside the lattice
+// (the non-finite line velocity is reported by its own flag)
+__device__ inline int ifloor_safe(double x) {
+  const double f = floor(x);
+  return (f > -1.0e9 && f < 1.0e9) ? (int)f : 0;
+}
+
 __device__ inline uint32_t base_key(const SpreadGeom& sg, const double p[3], int b[3]) {
   for (int a = 0; a < 3; ++a) {
-    int c = (int)floor(p[a]);
+    int c = ifloor_safe(p[a]);
     if (sg.wall[a]) {
       c += 1;  // lower corner -1 .. n-1 -> 0 .. n
+      c = c < 0 ? 0 : (c > sg.n[a] ? sg.n[a] : c);
     } else {
-      c = c < 0 ? c + sg.n[a] : (c >= sg.n[a] ? c - sg.n[a] : c);
+      c = ((c % sg.n[a]) + sg.n[a]) % sg.n[a];
     }
     b[a] = c;
   }
@@ -116,6 +125,7 @@ __device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, d
                           double pz, double v[3]) {
   const double b[3] = {floor(px), floor(py), floor(pz)};
   const double fr[3] = {px - b[0], py - b[1], pz - b[2]};
+  const int ib[3] = {ifloor_safe(px), ifloor_safe(py), ifloor_safe(pz)};
   const int n[3] = {g.nx, g.ny, g.nz};
   v[0] = v[1] = v[2] = 0.0;
   for (int o = 0; o < 8; ++o) {
@@ -124,13 +134,13 @@ __device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, d
     double w = 1.0;
     bool ghost = false;
     for (int a = 0; a < 3; ++a) {
-      int c = (int)b[a] + off[a];
+      int c = ib[a] + off[a];
       w *= off[a] ? fr[a] : 1.0 - fr[a];
       if (c < 0 || c >= n[a]) {
         if (g.wall[a])
           ghost = true;
         else
-          c = c < 0 ? c + n[a] : c - n[a];
+          c = ((c % n[a]) + n[a]) % n[a];
       }
       node[a] = c;
     }
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
       const double pz = A.Y[2 * nc + j];
       const double fz = floor(pz);
       const double t = pz - fz;
-      int i0 = (int)fz, i1 = i0 + 1;
+      int i0 = ifloor_safe(pz), i1 = i0 + 1;
       i0 = ((i0 % g.nz) + g.nz) % g.nz;
       i1 = ((i1 % g.nz) + g.nz) % g.nz;
       s_rk[6][lane] = (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];

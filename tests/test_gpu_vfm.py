@@ -351,3 +351,20 @@ def test_reconnection_list_capacity_skips():
     assert ei.value.code == vlb.VLB_ECAPACITY
     _, nxt_g = run.read_filaments()
     np.testing.assert_array_equal(nxt_g, nxt)
+
+
+def test_nonfinite_velocity_is_flagged():
+    """A non-finite normal-fluid field makes the line velocity non-finite:
+    the step latches VLB_ENUMERIC, reported by the next sync; positions
+    that blew up still index inside the lattice (no fault)."""
+    cfg = small_channel(precision="f64")
+    u = cfg["u"].copy()
+    u[:] = np.nan
+    cfg = dict(cfg, u=u)
+    say("non-finite")
+    run = vlb.run_from_config(cfg)
+    run.step(2)
+    with pytest.raises(vlb.VlbError) as ei:
+        run.sync()
+    assert ei.value.code == vlb.VLB_ENUMERIC
+    run.close()

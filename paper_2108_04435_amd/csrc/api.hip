@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <new>
 
 using namespace vlb;
@@ -19,6 +20,7 @@ struct vlb_graph {
   hipGraphExec_t exec = nullptr;
   int64_t n_steps = 0;
   int parity = 0;
+  int point_parity = 0;
 };
 
 namespace {
@@ -531,7 +533,7 @@ int one_step(vlb_run* h, bool first, bool last) {
     }
   }
   HIP_OR_FAIL(h, hipEventRecord(r.ev_fin4, M));
-  HIP_OR_FAIL(h, topo_update(r));
+  HIP_OR_FAIL(h, topo_update(r, true));
   if (!last) {
     // f^(n+1): moments of the next step, once the stages stopped reading
     // the velocity field
@@ -641,7 +643,7 @@ int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, dou
 int vlb_apply_topology(vlb_run* h, int64_t* stats) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   Run& r = h->r;
-  HIP_OR_FAIL(h, topo_update(r));
+  HIP_OR_FAIL(h, topo_update(r, false));
   int32_t c[8];
   HIP_OR_FAIL(h, hipMemcpyAsync(c, r.cnt, sizeof(c), hipMemcpyDeviceToHost, r.stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
@@ -741,6 +743,7 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   if (!r.stream) return fail(h, VLB_EINVAL, "graph capture needs a non-null stream");
   const int64_t step0 = r.step, nodes0 = r.last_nodes;
   const int parity0 = r.parity;
+  const int pparity0 = r.point_parity;
   const bool timing0 = r.timing;
   r.timing = false;
   HIP_OR_FAIL(h, hipStreamBeginCapture(r.stream, hipStreamCaptureModeRelaxed));
@@ -752,6 +755,12 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   r.last_nodes = nodes0;
   r.parity = parity0;
   r.timing = timing0;
+  if (r.point_parity != pparity0) {  // an odd number of compactions was captured
+    std::swap(r.pos, r.pos_t);
+    std::swap(r.nxt, r.nxt_t);
+    std::swap(r.prv, r.prv_t);
+    r.point_parity = pparity0;
+  }
   if (code != VLB_OK) {
     if (graph) hipGraphDestroy(graph);
     return code;
@@ -770,6 +779,7 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   g->exec = exec;
   g->n_steps = n_steps;
   g->parity = parity0;
+  g->point_parity = pparity0;
   *out = g;
   return VLB_OK;
 }
@@ -778,7 +788,8 @@ int vlb_graph_launch(vlb_graph* g) {
   if (!g || !g->run) return fail(nullptr, VLB_EINVAL, "graph is NULL");
   vlb_run* h = g->run;
   Run& r = h->r;
-  if (r.parity != g->parity) return fail(h, VLB_ESTATE, "run parity differs from the captured one");
+  if (r.parity != g->parity || r.point_parity != g->point_parity)
+    return fail(h, VLB_ESTATE, "run parity differs from the captured one");
   HIP_OR_FAIL(h, hipGraphLaunch(g->exec, r.stream));
   r.step += g->n_steps;
   r.last_nodes += g->n_steps * r.cells;

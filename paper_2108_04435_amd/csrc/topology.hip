@@ -15,6 +15,8 @@
 // All decisions compare FP64 squared distances summed as dx*dx + dy*dy +
 // dz*dz with no fused multiply-add, so the integer outcome is a fixed
 // function of the positions.
+#include <utility>
+
 #include "vlb_internal.h"
 
 #pragma clang fp contract(off)
@@ -356,23 +358,39 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
   if (A.mask) wave_scan_commit(alive, A.mask, A.pre, A.ticket, A.cnt + 8);
 }
 
-// Stable compaction of the alive points into the scratch arrays, links
-// renumbered through the ranks; then copied back.
+// Stable compaction of the alive points into the other point arrays, links
+// renumbered through the ranks.  In a step the two sets of point arrays
+// then swap roles (no copy back); the standalone topology call copies back.
+// With X non-null the grid coordinates of the compacted positions are
+// written for the FP32 Biot-Savart sum of the next step, and the point
+// count is set (when no copy follows).
+__device__ inline uint32_t grid_coord(double y, const BsAxes& ax, int a) {
+  const double g = floor((y + ax.off[a]) * ax.q[a]);
+  return ax.periodic[a] ? (uint32_t)(long long)g : (uint32_t)(int)(long long)g;
+}
+
 __global__ __launch_bounds__(kBlock) void k_compact_scatter(const double* __restrict__ pos,
                                                             const int32_t* __restrict__ nxt,
                                                             const int32_t* __restrict__ prv,
-                                                            const int32_t* __restrict__ cnt,
+                                                            int32_t* __restrict__ cnt,
                                                             long long nc,
                                                             const uint64_t* __restrict__ mask,
                                                             const int32_t* __restrict__ pre,
                                                             double* __restrict__ pos_t,
                                                             int32_t* __restrict__ nxt_t,
-                                                            int32_t* __restrict__ prv_t) {
+                                                            int32_t* __restrict__ prv_t,
+                                                            int set_count,
+                                                            uint32_t* __restrict__ X, BsAxes ax) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (set_count && j == 0) cnt[0] = cnt[8];
   if (j >= cnt[9] || !flag_bit(mask, j)) return;
   const int q = flag_rank(mask, pre, j);
   if (q >= nc) return;
-  for (int a = 0; a < 3; ++a) pos_t[a * nc + q] = pos[a * nc + j];
+  for (int a = 0; a < 3; ++a) {
+    const double y = pos[a * nc + j];
+    pos_t[a * nc + q] = y;
+    if (X) X[a * nc + q] = grid_coord(y, ax, a);
+  }
   nxt_t[q] = flag_rank(mask, pre, nxt[j]);
   prv_t[q] = flag_rank(mask, pre, prv[j]);
 }
@@ -394,10 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_compact_copy(double* __restrict__ po
   for (int a = 0; a < 3; ++a) {
     const double y = pos_t[a * nc + q];
     pos[a * nc + q] = y;
-    if (X) {
-      const double g = floor((y + ax.off[a]) * ax.q[a]);
-      X[a * nc + q] = ax.periodic[a] ? (uint32_t)(long long)g : (uint32_t)(int)(long long)g;
-    }
+    if (X) X[a * nc + q] = grid_coord(y, ax, a);
   }
   nxt[q] = nxt_t[q];
   prv[q] = prv_t[q];
@@ -665,7 +680,7 @@ BinGeom bin_geom(const Run& r) {
 // unlinked from the alive ones, and renumbering by a stable compaction
 // keeps the (d^2, i, j) order of every candidate pair, so the outcome is
 // the one of compacting before reconnecting.
-hipError_t topo_update(Run& r) {
+hipError_t topo_update(Run& r, bool swap) {
   const TopoGeom tg = topo_geom(r);
   const int nb = nb_of(r.ncap, kBlock);
   int32_t* del = r.flag_b;
@@ -723,11 +738,21 @@ hipError_t topo_update(Run& r) {
     A.pre = r.wpre;
     hipLaunchKernelGGL(k_small_pass, dim3(nb), dim3(kBlock), 0, r.stream, A);
   }
-  hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
-                     r.cnt, r.ncap, r.wmask, r.wpre, r.pos_t, r.nxt_t, r.prv_t);
-  hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
-                     r.cnt, r.ncap, r.pos_t, r.nxt_t, r.prv_t,
-                     r.prec == VLB_F64 ? nullptr : r.bsX, r.bsax);
+  uint32_t* X = r.prec == VLB_F64 ? nullptr : r.bsX;
+  if (swap) {
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                       r.cnt, r.ncap, r.wmask, r.wpre, r.pos_t, r.nxt_t, r.prv_t, 1, X, r.bsax);
+    std::swap(r.pos, r.pos_t);
+    std::swap(r.nxt, r.nxt_t);
+    std::swap(r.prv, r.prv_t);
+    r.point_parity ^= 1;
+  } else {
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                       r.cnt, r.ncap, r.wmask, r.wpre, r.pos_t, r.nxt_t, r.prv_t, 0, nullptr,
+                       r.bsax);
+    hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(kBlock), 0, r.stream, r.pos, r.nxt, r.prv,
+                       r.cnt, r.ncap, r.pos_t, r.nxt_t, r.prv_t, X, r.bsax);
+  }
   return hipGetLastError();
 }
 

@@ -293,7 +293,7 @@ struct Run {
   double* sfrac = nullptr;  // 3 * ncap stencil offsets of the spread positions
   int32_t* nxt = nullptr;
   int32_t* prv = nullptr;
-  double* pos_t = nullptr;  // compaction scratch
+  double* pos_t = nullptr;  // the other point-array set (compaction target)
   int32_t* nxt_t = nullptr;
   int32_t* prv_t = nullptr;
 
@@ -350,6 +350,7 @@ struct Run {
 
   int64_t step = 0;
   int parity = 0;
+  int point_parity = 0;     // which of the two point-array sets is current
   bool lbm_narrow = false;  // LBM update launched beside the filament kernels
   bool has_fields = false;
   bool has_points = false;  // set once filaments were seeded
@@ -385,7 +386,9 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
 hipError_t fil_spread(Run& r);
 hipError_t fil_seed(Run& r, long long n);
 
-hipError_t topo_update(Run& r);
+// swap: compact into the other point arrays and swap them (steps); else
+// compact and copy back (the standalone call)
+hipError_t topo_update(Run& r, bool swap);
 
 size_t sort_tmp_bytes(long long n);
 int sort_tiles(long long n);

@@ -368,3 +368,31 @@ def test_nonfinite_velocity_is_flagged():
         run.sync()
     assert ei.value.code == vlb.VLB_ENUMERIC
     run.close()
+
+
+def test_graph_rejects_odd_parity():
+    """A graph captured at one AA / point-array parity refuses to launch
+    after an odd number of direct steps, and launches again after the next
+    one; the replay then matches direct stepping."""
+    cfg = small_channel(precision="f32", seed=27)
+    say("graph parity")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = vlb.run_from_config(cfg)
+        d = vlb.run_from_config(cfg)
+        g.graph(2)
+        g.step(1)
+        d.step(1)
+        with pytest.raises(vlb.VlbError) as ei:
+            g.step_graph(2)
+        assert ei.value.code == vlb.VLB_ESTATE
+        g.step(1)
+        d.step(1)
+        g.step_graph(2)
+        d.step(2)
+        g.sync()
+        d.sync()
+        for x, y in zip(_final_state(g), _final_state(d)):
+            np.testing.assert_array_equal(x, y)
+        g.close()
+        d.close()

@@ -109,7 +109,7 @@ int vlb_query_footprint(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
 
 /* Create a run inside the caller's device workspace (>= footprint bytes,
  * 256-byte aligned) on the caller's stream (hipStream_t, may be NULL for the
- * null stream); the library creates its side stream and six events here
+ * null stream); the library creates its side stream and four events here
  * (VLB_EDEVICE if that fails) and releases them in vlb_destroy.
  * Populations start at equilibrium f^eq(rho = 1, u = 0); there are no
  * filaments.  The workspace and stream must outlive the run.               */

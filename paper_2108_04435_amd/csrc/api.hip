@@ -89,7 +89,7 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
 }
 
 void release_streams(Run& r) {
-  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_spread, &r.ev_fin4, &r.ev_join};
+  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_join};
   for (hipEvent_t* ev : evs)
     if (*ev) {
       hipEventDestroy(*ev);
@@ -116,6 +116,7 @@ size_t layout(Run& r, char* base) {
   r.pops = B.take(19 * cells * elt_size(r.prec));
   r.force = B.take(3 * cells * fe);
   r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
+  r.Vs_next = (double*)B.take(r.geom.nz * sizeof(double));
   r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
   double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage, &r.sfrac};
   for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
@@ -154,6 +155,7 @@ size_t layout(Run& r, char* base) {
     r.rc_bidx = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
   }
   r.ub = B.take(3 * cells * fe);
+  r.ub_next = B.take(3 * cells * fe);
   r.bins = (int32_t*)B.take((size_t)r.nbins_table * sizeof(int32_t));
   return (B.off + kAlign - 1) / kAlign * kAlign;
 }
@@ -386,7 +388,7 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   r.stream = (hipStream_t)hip_stream;
   hipGetDevice(&r.device);
   hipError_t e = hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking);
-  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_spread, &r.ev_fin4, &r.ev_join};
+  hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_join};
   for (hipEvent_t* ev : evs)
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   // populations at rest, no force, no points
@@ -511,39 +513,44 @@ int one_step(vlb_run* h, bool first, bool last) {
   double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
   const bool spread = r.vor.coupling != 0;
   for (int s = 0; s < 4; ++s) {
-    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
     if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
+    // the first finalize reads the velocity field and the superflow
+    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
-    if (s == 0 && spread) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
+    // finalize 1 leaves the spreading everything it reads, and it follows
+    // the previous step's last reads of the field the next moments overwrite
+    if (s == 0) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
     // the side stream's work is enqueued after the main stream's next
     // kernel, so that a graph keeps the main chain on one queue
     if (s == 1) {
-      if (spread) HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
+      HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
       OnStream on(r, S);
       if (spread) HIP_OR_FAIL(h, fil_spread(r));
-      // the LBM update on a narrow grid beside the Biot-Savart sums
+      // the LBM update on a narrow grid beside the Biot-Savart sums, then
+      // the moments of f^(n+1) into the next step's field (the stages of
+      // this step still read the current one)
       r.lbm_narrow = true;
-      const hipError_t le = lbm_step(r);
+      hipError_t le = lbm_step(r);
+      if (le == hipSuccess && !last) {
+        std::swap(r.ub, r.ub_next);
+        std::swap(r.Vs, r.Vs_next);
+        le = lbm_moments(r);
+        std::swap(r.ub, r.ub_next);
+        std::swap(r.Vs, r.Vs_next);
+      }
       r.lbm_narrow = false;
-      if (le != hipSuccess) return hip_fail(h, le, "lbm_step(r)");
+      if (le != hipSuccess) return hip_fail(h, le, "lbm_step / lbm_moments");
+      if (!last) HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
     }
   }
-  HIP_OR_FAIL(h, hipEventRecord(r.ev_fin4, M));
   HIP_OR_FAIL(h, topo_update(r, true));
   if (!last) {
-    // f^(n+1): moments of the next step, once the stages stopped reading
-    // the velocity field
-    HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin4, 0));
-    OnStream on(r, S);
-    r.lbm_narrow = true;
-    const hipError_t me = lbm_moments(r);
-    r.lbm_narrow = false;
-    if (me != hipSuccess) return hip_fail(h, me, "lbm_moments(r)");
-    HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
+    std::swap(r.ub, r.ub_next);
+    std::swap(r.Vs, r.Vs_next);
   }
   if (last) {
     HIP_OR_FAIL(h, hipEventRecord(r.ev_join, S));
@@ -745,6 +752,12 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   const int parity0 = r.parity;
   const int pparity0 = r.point_parity;
   const bool timing0 = r.timing;
+  // velocity fields: every call (and so every launch) starts with fresh
+  // moments into the current one, so only the host's choice is restored
+  void* const ub0 = r.ub;
+  void* const ubn0 = r.ub_next;
+  double* const vs0 = r.Vs;
+  double* const vsn0 = r.Vs_next;
   r.timing = false;
   HIP_OR_FAIL(h, hipStreamBeginCapture(r.stream, hipStreamCaptureModeRelaxed));
   int code = VLB_OK;
@@ -755,6 +768,10 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   r.last_nodes = nodes0;
   r.parity = parity0;
   r.timing = timing0;
+  r.ub = ub0;
+  r.ub_next = ubn0;
+  r.Vs = vs0;
+  r.Vs_next = vsn0;
   if (r.point_parity != pparity0) {  // an odd number of compactions was captured
     std::swap(r.pos, r.pos_t);
     std::swap(r.nxt, r.nxt_t);

@@ -7,9 +7,12 @@
 //  * per point: 32-bit grid coordinates X (3 x u32, SoA); the segment
 //    vector d_k = s_next(k) - s_k is the wrapped grid difference in the FP32
 //    sum and an FP64 nearest-image vector in the FP64 sum;
-//  * a 2-D grid: blockIdx.x picks 256 consecutive targets (one per thread),
-//    blockIdx.y one contiguous chunk of sources; the chunk is staged through
-//    LDS in tiles of 256 sources and every thread walks the tile;
+//  * a 2-D grid: blockIdx.x picks 64 consecutive targets (one per lane of
+//    every wave), blockIdx.y one contiguous chunk of sources; the chunk is
+//    staged through LDS in tiles of 256 sources, each of the block's 4
+//    waves walks its own quarter of the tile, and the 4 wave sums are added
+//    in LDS in a fixed order at the end (fewer, longer chunks than with one
+//    wave per target, so fewer partial sums to write and to add);
 //  * the separation R1 = s_k - r is the wrapped integer difference of the
 //    grid coordinates, converted to floating point: exact nearest periodic
 //    image and a relative (not absolute) rounding error for near pairs;
@@ -22,6 +25,16 @@ namespace vlb {
 namespace {
 
 constexpr int kTile = 256;
+constexpr int kTargets = 64;  // targets per block, one per lane of each wave
+
+// Quarter of a staged tile of cnt sources walked by wave w: [lo, hi) (empty
+// when lo >= hi), lo a multiple of 4 so that the unrolled loop reads the
+// tile with 16-byte loads.
+__device__ inline void wave_range(int cnt, int w, int& lo, int& hi) {
+  const int q = (((cnt + 3) >> 2) + 3) & ~3;
+  lo = w * q;
+  hi = __builtin_amdgcn_readfirstlane(min(cnt, lo + q));
+}
 
 // Grid coordinates of the points at positions Y, and for the FP64 path the
 // segment vectors (nearest image, lattice units) and the residuals
@@ -112,9 +125,11 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   // work counter: (target, segment) pairs of this sum
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
     *(long long*)(cntp + 16) += (long long)n * (n - 2);
-  const int j0 = blockIdx.x * 256;
+  const int j0 = blockIdx.x * kTargets;
   if (j0 >= n) return;
-  const int j = j0 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int j = j0 + lane;
   const bool valid = j < n;
   const int per = (n + S - 1) / S;
   const int kb = blockIdx.y * per;
@@ -124,8 +139,9 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   const uint32_t zt = valid ? X[2 * ncap + j] : 0u;
   const int pj = valid ? prv[j] : -1;
   const int jj = valid ? j : -1;
-  __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
-  __shared__ float dx[kTile], dy[kTile], dz[kTile], dq[kTile];
+  __shared__ __align__(16) uint32_t sx[kTile], sy[kTile], sz[kTile];
+  __shared__ __align__(16) float dx[kTile], dy[kTile], dz[kTile], dq[kTile];
+  __shared__ float red[3][3][kTargets];  // sums of waves 1..3
   float ax = 0.f, ay = 0.f, az = 0.f;
   for (int t0 = kb; t0 < ke; t0 += kTile) {
     const int k = t0 + threadIdx.x;
@@ -150,21 +166,31 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
       dq[threadIdx.x] = ex * ex + ey * ey + ez * ez;
     }
     __syncthreads();
-    const int cnt = min(kTile, ke - t0);
-    const bool hit = valid && ((jj >= t0 && jj < t0 + cnt) || (pj >= t0 && pj < t0 + cnt));
-    if (__any(hit))
-      bs_tile_f32<true, kUniform>(sx, sy, sz, dx, dy, dz, dq, cnt, t0, xt, yt, zt, iqx, iqy, iqz,
-                                  jj, pj, ax, ay, az);
-    else
-      bs_tile_f32<false, kUniform>(sx, sy, sz, dx, dy, dz, dq, cnt, t0, xt, yt, zt, iqx, iqy, iqz,
-                                   jj, pj, ax, ay, az);
+    int lo, hi;
+    wave_range(min(kTile, ke - t0), w, lo, hi);
+    if (lo < hi) {
+      const int s0 = t0 + lo, s1 = t0 + hi;
+      const bool hit = valid && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      if (__any(hit))
+        bs_tile_f32<true, kUniform>(sx + lo, sy + lo, sz + lo, dx + lo, dy + lo, dz + lo, dq + lo,
+                                    hi - lo, s0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+      else
+        bs_tile_f32<false, kUniform>(sx + lo, sy + lo, sz + lo, dx + lo, dy + lo, dz + lo, dq + lo,
+                                     hi - lo, s0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
+    }
     __syncthreads();
   }
-  if (valid) {
+  if (w > 0) {
+    red[w - 1][0][lane] = ax;
+    red[w - 1][1][lane] = ay;
+    red[w - 1][2][lane] = az;
+  }
+  __syncthreads();
+  if (w == 0 && valid) {
     float* out = P + (long long)blockIdx.y * 3 * ncap;
-    out[j] = ax;
-    out[ncap + j] = ay;
-    out[2 * ncap + j] = az;
+    out[j] = ((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
+    out[ncap + j] = ((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
+    out[2 * ncap + j] = ((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
   }
 }
 
@@ -238,9 +264,11 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   const int n = cntp[0];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
     *(long long*)(cntp + 16) += (long long)n * (n - 2);
-  const int j0 = blockIdx.x * 256;
+  const int j0 = blockIdx.x * kTargets;
   if (j0 >= n) return;
-  const int j = j0 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int j = j0 + lane;
   const bool valid = j < n;
   const int per = (n + S - 1) / S;
   const int kb = blockIdx.y * per;
@@ -253,9 +281,10 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   const double rtz = valid ? D[5 * ncap + j] : 0.0;
   const int pj = valid ? prv[j] : -1;
   const int jj = valid ? j : -1;
-  __shared__ uint32_t sx[kTile], sy[kTile], sz[kTile];
-  __shared__ double rx[kTile], ry[kTile], rz[kTile];
-  __shared__ double dx[kTile], dy[kTile], dz[kTile];
+  __shared__ __align__(16) uint32_t sx[kTile], sy[kTile], sz[kTile];
+  __shared__ __align__(16) double rx[kTile], ry[kTile], rz[kTile];
+  __shared__ __align__(16) double dx[kTile], dy[kTile], dz[kTile];
+  __shared__ double red[3][3][kTargets];  // sums of waves 1..3
   double ax = 0.0, ay = 0.0, az = 0.0;
   for (int t0 = kb; t0 < ke; t0 += kTile) {
     const int k = t0 + threadIdx.x;
@@ -271,34 +300,45 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
       rz[threadIdx.x] = D[5 * ncap + k];
     }
     __syncthreads();
-    const int cnt = min(kTile, ke - t0);
-    const bool hit = valid && ((jj >= t0 && jj < t0 + cnt) || (pj >= t0 && pj < t0 + cnt));
-    if (__any(hit))
-      bs_tile_f64<true>(sx, sy, sz, rx, ry, rz, dx, dy, dz, cnt, t0, xt, yt, zt, rtx, rty, rtz,
-                        gx, gy, gz, jj, pj, ax, ay, az);
-    else
-      bs_tile_f64<false>(sx, sy, sz, rx, ry, rz, dx, dy, dz, cnt, t0, xt, yt, zt, rtx, rty, rtz,
-                         gx, gy, gz, jj, pj, ax, ay, az);
+    int lo, hi;
+    wave_range(min(kTile, ke - t0), w, lo, hi);
+    if (lo < hi) {
+      const int s0 = t0 + lo, s1 = t0 + hi;
+      const bool hit = valid && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      if (__any(hit))
+        bs_tile_f64<true>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
+                          dz + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj, pj, ax,
+                          ay, az);
+      else
+        bs_tile_f64<false>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
+                           dz + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj, pj, ax,
+                           ay, az);
+    }
     __syncthreads();
   }
-  if (valid) {
+  if (w > 0) {
+    red[w - 1][0][lane] = ax;
+    red[w - 1][1][lane] = ay;
+    red[w - 1][2][lane] = az;
+  }
+  __syncthreads();
+  if (w == 0 && valid) {
     double* out = P + (long long)blockIdx.y * 3 * ncap;
-    out[j] = ax;
-    out[ncap + j] = ay;
-    out[2 * ncap + j] = az;
+    out[j] = ((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
+    out[ncap + j] = ((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
+    out[2 * ncap + j] = ((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
   }
 }
 
 }  // namespace
 
-// Source chunks S: about 16384 blocks over the target tiles, at least half
-// a tile of sources per chunk, at most 256 chunks.  More, shorter chunks
-// measured faster at 1e4 points (more blocks in flight per CU); the chunk
-// partials are added by the finalize kernel.
+// Source chunks S: about 16384 blocks over the target blocks, at least 512
+// sources per chunk (128 per wave), at most 256 chunks; the chunk partials
+// are added by the finalize kernel.
 int bs_chunks(long long ncap) {
-  const long long tb = (ncap + 255) / 256;
+  const long long tb = (ncap + kTargets - 1) / kTargets;
   long long S = 16384 / (tb > 0 ? tb : 1);
-  const long long maxS = ncap / 128;
+  const long long maxS = ncap / 512;
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   if (S > 256) S = 256;
@@ -317,7 +357,7 @@ hipError_t bs_prep(Run& r, const double* Y) {
 }
 
 hipError_t bs_sum(Run& r, const double* Y) {
-  const int tb = (int)((r.ncap + 255) / 256);
+  const int tb = (int)((r.ncap + kTargets - 1) / kTargets);
   dim3 grid(tb, r.bsS);
   hipEvent_t b = nullptr;
   time_begin(r, 0, &b);

@@ -236,20 +236,20 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   double vs[3] = {0.0, 0.0, 0.0};
   if (live) {
     const PT* __restrict__ P = (const PT*)A.P;
-    int s = grp;
-    for (; s + 28 < A.S; s += 32) {
+    // batches of up to 8 chunks, all loads of a batch in flight together;
+    // chunks beyond S read as zero (adding them changes nothing)
+    for (int s = grp; s < A.S; s += 32) {
       PT v[8][3];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[u][a] = P[((long long)(s + 4 * u) * 3 + a) * nc + j];
+        for (int a = 0; a < 3; ++a)
+          v[u][a] = (s + 4 * u < A.S) ? P[((long long)(s + 4 * u) * 3 + a) * nc + j] : (PT)0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int a = 0; a < 3; ++a) vs[a] += (double)v[u][a];
     }
-    for (; s < A.S; s += 4)
-      for (int a = 0; a < 3; ++a) vs[a] += (double)P[((long long)s * 3 + a) * nc + j];
   }
   if (grp > 0)
     for (int a = 0; a < 3; ++a) red[grp - 1][a][lane] = vs[a];

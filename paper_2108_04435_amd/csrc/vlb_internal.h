@@ -260,8 +260,7 @@ struct Run {
   vlb_vortex_desc vor;
   hipStream_t stream = nullptr;  // the caller's stream: every call's work joins it
   hipStream_t side = nullptr;    // library stream for the lattice part of a step
-  hipEvent_t ev_fork = nullptr, ev_mom = nullptr, ev_fin1 = nullptr, ev_spread = nullptr,
-             ev_fin4 = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_mom = nullptr, ev_fin1 = nullptr, ev_join = nullptr;
   int device = 0;
   char* ws = nullptr;
   uint64_t ws_bytes = 0;
@@ -277,6 +276,11 @@ struct Run {
   int32_t* touched = nullptr;  // 8 * ncap node indices written by spreading
   double* Vs = nullptr;        // nz slice superflow
   void* ub = nullptr;          // 3 * cells bare velocity of the current step
+  // the same for the next step: its moments are taken right after the LBM
+  // update while the stages of this step still read ub (swapped at the
+  // end of the step)
+  double* Vs_next = nullptr;
+  void* ub_next = nullptr;
   int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
   uint32_t* marked = nullptr;  // per sorted entry: the bin it marked (all ones: none)
   long long nbins_table = 0;

@@ -75,7 +75,7 @@ struct FinArgs {
   double kappa;
   double bs_scale;    // kappa / (4 pi)
   double nl_scale;    // kappa / (4 pi) times the grid step when the sum ran in grid units
-  double ea;          // e^C a
+  double ln2_ea;      // ln(2 / (e^C a))
   double alpha, alpha_p;
   double rs_rn;
   double vs_app[3];
@@ -171,25 +171,45 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   const int n = A.cnt[0];
   const bool live = j < n;
   const long long nc = A.ncap;
+  // The loads do not wait for the point count: every slot below the
+  // capacity is read (indices clamped into the arrays, non-finite values
+  // harmless), and only live points write.
+  const bool slot = j < nc;
+  // the first batch of this wave's Biot-Savart chunk partials (chunks grp,
+  // grp + 4, ..., up to 8 of them; beyond S they read as zero, which adds
+  // nothing), loaded before the wave's own work so that the latencies overlap
+  const PT* __restrict__ P = (const PT*)A.P;
+  const long long jc = slot ? j : 0;  // in-bounds index for the unconditional loads
+  PT v0[8][3];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const bool ok = slot && grp + 4 * u < A.S;
+    const long long c = ok ? grp + 4 * u : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const PT x = P[(c * 3 + a) * nc + jc];
+      v0[u][a] = ok ? x : (PT)0;
+    }
+  }
   const Geom& g = A.g;
   const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
   const int per[3] = {!g.wall[0], !g.wall[1], !g.wall[2]};
 
-  if (live && grp == 1) {
+  if (slot && grp == 1) {
     const double p[3] = {A.Y[j], A.Y[nc + j], A.Y[2 * nc + j]};
     double vn[3];
     interp_vn<UT>((const UT*)A.ub, g, p[0], p[1], p[2], vn);
     for (int a = 0; a < 3; ++a) s_vn[a][lane] = vn[a];
-    if (A.skeys) {
+    if (live && A.skeys) {
       int b[3];
       A.skeys[j] = base_key(A.sg, p, b);
       for (int a = 0; a < 3; ++a) A.sfrac[a * nc + j] = p[a] - floor(p[a]);
     }
   }
   if (A.skeys && blockIdx.x == 0 && threadIdx.x == 0) A.cnt[11] = n;
-  if (live && grp == 2) {
+  if (slot && grp == 2) {
     // local geometry (three-point derivatives on a non-uniform arc length)
-    const int jn = A.nxt[j], jp = A.prv[j];
+    const int jn = min(max(A.nxt[j], 0), (int)nc - 1), jp = min(max(A.prv[j], 0), (int)nc - 1);
     double dp[3], dm[3];
     for (int a = 0; a < 3; ++a) {
       const double pa = A.Y[a * nc + j];
@@ -198,16 +218,17 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
     }
     const double lp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
     const double lm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
-    const double den = lp * lm * (lp + lm);
+    const double iden = 1.0 / (lp * lm * (lp + lm));
     double sp[3], spp[3];
     for (int a = 0; a < 3; ++a) {
-      sp[a] = (lm * lm * dp[a] + lp * lp * dm[a]) / den;
-      spp[a] = 2.0 * (lm * dp[a] - lp * dm[a]) / den;
+      sp[a] = (lm * lm * dp[a] + lp * lp * dm[a]) * iden;
+      spp[a] = 2.0 * (lm * dp[a] - lp * dm[a]) * iden;
     }
-    const double sn = sqrt(sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]);
-    for (int a = 0; a < 3; ++a) sp[a] /= sn;
+    const double isn = 1.0 / sqrt(sp[0] * sp[0] + sp[1] * sp[1] + sp[2] * sp[2]);
+    for (int a = 0; a < 3; ++a) sp[a] *= isn;
     // LIA: beta s' x s'', beta = kappa/(4 pi) ln(2 sqrt(l+ l-) / (e^C a))
-    const double beta = A.bs_scale * log(2.0 * sqrt(lp * lm) / A.ea);
+    //                          = kappa/(4 pi) (ln(l+ l-) / 2 + ln(2 / (e^C a)))
+    const double beta = A.bs_scale * fma(0.5, log(lp * lm), A.ln2_ea);
     s_geo[3][lane] = beta * (sp[1] * spp[2] - sp[2] * spp[1]);
     s_geo[4][lane] = beta * (sp[2] * spp[0] - sp[0] * spp[2]);
     s_geo[5][lane] = beta * (sp[0] * spp[1] - sp[1] * spp[0]);
@@ -215,7 +236,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
     s_geo[6][lane] = lp;
     s_geo[7][lane] = lm;
   }
-  if (live && grp == 3) {
+  if (slot && grp == 3) {
     if (!A.eval_only)
       for (int a = 0; a < 3; ++a) {
         s_rk[a][lane] = A.pos[a * nc + j];
@@ -234,17 +255,23 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
 
   // non-local Biot-Savart: chunk partials added in a fixed order
   double vs[3] = {0.0, 0.0, 0.0};
-  if (live) {
-    const PT* __restrict__ P = (const PT*)A.P;
-    // batches of up to 8 chunks, all loads of a batch in flight together;
-    // chunks beyond S read as zero (adding them changes nothing)
-    for (int s = grp; s < A.S; s += 32) {
+  if (slot) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vs[a] += (double)v0[u][a];
+    for (int s = grp + 32; s < A.S; s += 32) {
       PT v[8][3];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = s + 4 * u < A.S;
+        const long long c = ok ? s + 4 * u : 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-          v[u][a] = (s + 4 * u < A.S) ? P[((long long)(s + 4 * u) * 3 + a) * nc + j] : (PT)0;
+        for (int a = 0; a < 3; ++a) {
+          const PT x = P[(c * 3 + a) * nc + j];
+          v[u][a] = ok ? x : (PT)0;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -509,7 +536,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.kappa = r.vor.kappa;
   A.bs_scale = r.vor.kappa / (4.0 * M_PI);
   A.nl_scale = (r.prec != VLB_F64 && r.bsax.uniform) ? A.bs_scale * r.bsax.q[0] : A.bs_scale;
-  A.ea = exp(r.vor.core_c) * r.vor.core_a;
+  A.ln2_ea = log(2.0 / (exp(r.vor.core_c) * r.vor.core_a));
   A.alpha = r.vor.alpha;
   A.alpha_p = r.vor.alpha_p;
   A.rs_rn = r.vor.rho_s_over_rho_n;

@@ -49,6 +49,34 @@ __device__ inline void sep(const double* __restrict__ pos, long long nc, int i, 
   }
 }
 
+// the same from loaded positions: d = b - a at the nearest periodic image
+__device__ inline void sep_v(const double a[3], const double b[3], const TopoGeom& tg,
+                             double d[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double x = __dsub_rn(b[k], a[k]);
+    if (tg.periodic[k]) {
+      if (x > 0.5 * tg.L[k])
+        x = __dsub_rn(x, tg.L[k]);
+      else if (x < -0.5 * tg.L[k])
+        x = __dadd_rn(x, tg.L[k]);
+    }
+    d[k] = x;
+  }
+}
+
+__device__ inline void load3(const double* __restrict__ pos, long long nc, int i, double y[3]) {
+  y[0] = pos[i];
+  y[1] = pos[nc + i];
+  y[2] = pos[2 * nc + i];
+}
+
+// Index for loads issued before the point count is known: every slot below
+// the capacity is read, stale links are clamped into the arrays, and only
+// live points use what was read.
+__device__ inline int clamp_index(long long x, long long nc) {
+  return (int)(x < 0 ? 0 : (x >= nc ? nc - 1 : x));
+}
+
 __device__ inline double wrap1(double x, double L, int periodic) {
   if (periodic) {
     if (x < 0.0) x = __dadd_rn(x, L);
@@ -174,12 +202,23 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
                                                     TopoGeom tg, double mn2, double mx2,
                                                     int32_t* __restrict__ del) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  // the point's links and the three positions of its candidacy test are
+  // loaded before the point count arrives
+  const int jc = clamp_index(j, nc);
+  const int p0 = clamp_index(prv[jc], nc), q0 = clamp_index(nxt[jc], nc);
+  double yj[3], yp[3], yq[3];
+  load3(pos, nc, jc, yj);
+  load3(pos, nc, p0, yp);
+  load3(pos, nc, q0, yq);
   const int n = cnt[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
   if (j >= n) return;
   int dd = 0;
-  if (rm_cand(pos, nxt, prv, nc, tg, mn2, mx2, j)) {
-    int c = 0, p = prv[j];
+  double d[3], c3[3];
+  sep_v(yp, yj, tg, d);
+  sep_v(yp, yq, tg, c3);
+  if (sq3(d) < mn2 && sq3(c3) <= mx2) {  // the candidacy test of rm_cand for j
+    int c = 0, p = p0;
     while (c < kChainLimit && p != j && rm_cand(pos, nxt, prv, nc, tg, mn2, mx2, p)) {
       ++c;
       p = prv[p];
@@ -218,20 +257,30 @@ __global__ __launch_bounds__(kBlock) void k_rm_link(const double* __restrict__ p
                                                     int32_t* __restrict__ ipre,
                                                     int32_t* ticket) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  // loads before the point count arrives.  A deleted point's own links are
+  // not rewritten here (its neighbours are kept); a kept point's successor
+  // link may be read before or after a deleted successor rewrote it, and
+  // both lead to the same new successor.
+  const int jc = clamp_index(j, nc);
+  const int dj0 = del[jc];
+  const int p0 = prv[jc];
+  const int s0 = __hip_atomic_load(&nxt[jc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double yj[3];
+  load3(pos, nc, jc, yj);
   const int n = cnt[0];
   const bool valid = j < n;
-  const int dj = valid ? del[j] : 0;
+  const int dj = valid ? dj0 : 0;
   bool ins = false;
   if (valid) {
     if (dj) {
-      const int p = prv[j], q = nxt[j];
-      __hip_atomic_store(&nxt[p], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      prv[q] = p;
+      __hip_atomic_store(&nxt[p0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prv[s0] = p0;
     } else {
-      int s = __hip_atomic_load(&nxt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int s = s0;
       if (del[s]) s = nxt[s];
-      double d[3];
-      sep(pos, nc, j, s, tg, d);
+      double ys[3], d[3];
+      load3(pos, nc, s, ys);
+      sep_v(yj, ys, tg, d);
       ins = sq3(d) > mx2;
     }
   }
@@ -250,6 +299,15 @@ __global__ __launch_bounds__(kBlock) void k_rm_insert(double* __restrict__ pos,
                                                       const uint64_t* __restrict__ imask,
                                                       const int32_t* __restrict__ ipre) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  // loads before the point count arrives (only this thread rewrites the
+  // successor link of point j here)
+  const int jc = clamp_index(j, nc);
+  const uint64_t mw = imask[jc >> 6];
+  const int pw = ipre[jc >> 6];
+  const int k = clamp_index(nxt[jc], nc);
+  double yj[3], yk[3];
+  load3(pos, nc, jc, yj);
+  load3(pos, nc, k, yk);
   const int n = cnt[0];
   const int M = cnt[2];
   const bool fits = (long long)n + M <= nc;
@@ -257,14 +315,13 @@ __global__ __launch_bounds__(kBlock) void k_rm_insert(double* __restrict__ pos,
     cnt[9] = fits ? n + M : n;
     if (!fits && M > 0) atomicOr(&cnt[7], kFlagCapacity);
   }
-  if (j >= n || !fits || !flag_bit(imask, j)) return;
-  const int q = n + flag_rank(imask, ipre, j);
+  if (j >= n || !fits || !((mw >> (j & 63)) & 1ull)) return;
+  const int q = n + pw + __popcll(mw & lanes_below(j & 63));
   if (q >= nc) return;
-  const int k = nxt[j];
   double d[3];
-  sep(pos, nc, j, k, tg, d);
+  sep_v(yj, yk, tg, d);
   for (int a = 0; a < 3; ++a)
-    pos[a * nc + q] = wrap1(__dadd_rn(pos[a * nc + j], 0.5 * d[a]), tg.L[a], tg.periodic[a]);
+    pos[a * nc + q] = wrap1(__dadd_rn(yj[a], 0.5 * d[a]), tg.L[a], tg.periodic[a]);
   nxt[j] = q;
   prv[q] = j;
   nxt[q] = k;
@@ -319,12 +376,19 @@ struct SmallArgs {
 
 __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  const long long nc = A.nc;
+  // the flags and the first links are loaded before the bound arrives
+  const int jc = clamp_index(j, nc);
+  const int dead0 = A.dead_in ? A.dead_in[jc] : 0;
+  const int alive0 = A.alive_in ? A.alive_in[jc] : 1;
+  const int f1 = A.nxt[jc], b1 = A.prv[jc];
+  double yj[3] = {0.0, 0.0, 0.0};
+  if (A.rc_mode == 1) load3(A.pos, nc, jc, yj);
+  const uint32_t key0 = A.rc_mode == 2 ? A.rc_key[jc] : 0u;
   const int bound = A.bound9 ? A.cnt[9] : A.cnt[0];
   if (!A.bound9 && j == 0) A.cnt[9] = bound;
   const bool valid = j < bound;
-  bool in = valid;
-  if (in && A.dead_in) in = A.dead_in[j] == 0;
-  if (in && A.alive_in) in = A.alive_in[j] != 0;
+  const bool in = valid && dead0 == 0 && alive0 != 0;
   bool alive = false;
   if (in) {
     // the loop is shorter than min_pts iff nxt^k(j) = j for some k <=
@@ -335,8 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
     bool small = false;
     for (int i = 1; 2 * i - 1 <= m1 && !small; ++i) {
       const int bp = b;
-      f = A.nxt[f];
-      b = A.prv[b];
+      f = i == 1 ? f1 : A.nxt[f];
+      b = i == 1 ? b1 : A.prv[b];
       small = f == bp || (2 * i <= m1 && f == b);
     }
     alive = !small;
@@ -346,15 +410,14 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
   const uint64_t dm = __ballot(in && !alive);
   if ((threadIdx.x & 63) == 0 && dm) atomicAdd(&A.cnt[5], (int)__popcll(dm));
   if (A.rc_mode == 1 && alive) {
-    const long long nc = A.nc;
-    const int bx = bin_of(A.pos[j], A.bg, 0);
-    const int by = bin_of(A.pos[nc + j], A.bg, 1);
-    const int bz = bin_of(A.pos[2 * nc + j], A.bg, 2);
+    const int bx = bin_of(yj[0], A.bg, 0);
+    const int by = bin_of(yj[1], A.bg, 1);
+    const int bz = bin_of(yj[2], A.bg, 2);
     const uint32_t key = (uint32_t)(((long long)bz * A.bg.nb[1] + by) * A.bg.nb[0] + bx);
     A.rc_key[j] = key;
     A.rc_next[j] = atomicExch(&A.rc_head[key], j);
   }
-  if (A.rc_mode == 2 && in) A.rc_head[A.rc_key[j]] = -1;
+  if (A.rc_mode == 2 && in) A.rc_head[key0] = -1;
   if (A.mask) wave_scan_commit(alive, A.mask, A.pre, A.ticket, A.cnt + 8);
 }
 
@@ -382,17 +445,23 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(const double* __rest
                                                             int set_count,
                                                             uint32_t* __restrict__ X, BsAxes ax) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
+  // loads before the bound arrives
+  const int jc = clamp_index(j, nc);
+  const uint64_t mw = mask[jc >> 6];
+  const int pw = pre[jc >> 6];
+  const int nj = clamp_index(nxt[jc], nc), pj = clamp_index(prv[jc], nc);
+  double y[3];
+  load3(pos, nc, jc, y);
   if (set_count && j == 0) cnt[0] = cnt[8];
-  if (j >= cnt[9] || !flag_bit(mask, j)) return;
-  const int q = flag_rank(mask, pre, j);
+  if (j >= cnt[9] || !((mw >> (j & 63)) & 1ull)) return;
+  const int q = pw + __popcll(mw & lanes_below(j & 63));
   if (q >= nc) return;
   for (int a = 0; a < 3; ++a) {
-    const double y = pos[a * nc + j];
-    pos_t[a * nc + q] = y;
-    if (X) X[a * nc + q] = grid_coord(y, ax, a);
+    pos_t[a * nc + q] = y[a];
+    if (X) X[a * nc + q] = grid_coord(y[a], ax, a);
   }
-  nxt_t[q] = flag_rank(mask, pre, nxt[j]);
-  prv_t[q] = flag_rank(mask, pre, prv[j]);
+  nxt_t[q] = flag_rank(mask, pre, nj);
+  prv_t[q] = flag_rank(mask, pre, pj);
 }
 
 // The copy also writes the 32-bit grid coordinates of the new positions
@@ -463,10 +532,16 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
                                                     int32_t* __restrict__ used) {
   const long long id = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int i = (int)(id / 27), q = (int)(id % 27);
+  // the point's flag, position and links are loaded before the bound arrives
+  const int ic = clamp_index(i, nc);
+  const int alive0 = alive[ic];
+  double yi[3];
+  load3(pos, nc, ic, yi);
+  const int ni0 = clamp_index(nxt[ic], nc), pi0 = clamp_index(prv[ic], nc);
   if (i >= cnt[9]) return;
   if (q == 0) used[i] = 0;
-  if (!alive[i]) return;
-  const int b[3] = {bin_of(pos[i], bg, 0), bin_of(pos[nc + i], bg, 1), bin_of(pos[2 * nc + i], bg, 2)};
+  if (!alive0) return;
+  const int b[3] = {bin_of(yi[0], bg, 0), bin_of(yi[1], bg, 1), bin_of(yi[2], bg, 2)};
   int ox[3], oy[3], oz[3];
   const int mx = bin_offsets(bg, 0, b[0], ox);
   const int my = bin_offsets(bg, 1, b[1], oy);
@@ -476,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
   const long long key = ((long long)oz[iz] * bg.nb[1] + oy[iy]) * bg.nb[0] + ox[ix];
   int j = head[key];
   if (j < 0) return;
-  const int ni = nxt[i], nni = nxt[ni], pi = prv[i], ppi = prv[pi];
+  const int ni = ni0, nni = nxt[ni], pi = pi0, ppi = prv[pi];
   const int bound = cnt[9];
   for (int guard = 0; j >= 0 && guard < bound; ++guard) {  // bounded by the point count
     const int jc = j;

@@ -64,15 +64,16 @@ def make_workload(name, precision=None):
     return cfg
 
 
-def traffic_record(kernel_src):
+def traffic_record(kernel_src, workload):
     """HBM bytes per launch of the Biot-Savart kernel from committed
-    rocprofv3 counter runs, if they were taken on the current source."""
+    rocprofv3 counter runs, if they were taken on the current source and on
+    this workload (FP32 storage)."""
     path = os.path.join(ROOT, "profiles", "bs_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha") != h:
+    if rec.get("source_sha") != h or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 
@@ -285,7 +286,7 @@ def main():
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None if f64 else traffic_record(src),
+        "traffic": traffic_record(src, cfg["name"]) if lat["precision"] == "f32" else None,
         "avg_launch_us": round(bs_iso_ms * 1e3, 2),
         "pairs_per_launch": int(pairs_iso),
         "flops_per_pair": FLOPS_PER_PAIR,

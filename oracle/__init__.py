@@ -10,7 +10,7 @@ Source: S. Inui and M. Tsubota, "Coupled dynamics of quantized vortices and
 normal fluid in superfluid 4He based on lattice Boltzmann method",
 arXiv:2108.04435.  Each function cites the section / equation / table it
 follows.  Where the paper is silent the reading taken is named in the
-docstring (R-numbers); every reading is listed in the design doc.
+docstring (R-numbers, the same numbering throughout the package).
 
 Modules
 -------

@@ -4,7 +4,7 @@ Field layout: populations ``f`` have shape (19, nz, ny, nx); scalar fields
 (nz, ny, nx); vector fields (3, nz, ny, nx) with components (x, y, z).
 Lattice units: dx = dt = 1, c_s^2 = 1/3 (Sec. II.B, Step 1).
 
-Boundary conditions (readings, listed in the design doc):
+Boundary conditions (readings of the paper):
   * an axis is either periodic or closed by two halfway bounce-back walls
     that sit half a cell outside the first and last node (R15);
   * optional velocity planes at z = 0 (heater) and z = nz-1 (cooler): the

@@ -60,6 +60,25 @@ def test_line_velocity_and_force(case, precision):
     assert errF <= tol
 
 
+@pytest.mark.parametrize("n_cap", [13312, 40000])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_line_velocity_large_capacity(n_cap, precision):
+    # The Biot-Savart launch is sized by the capacity: with a few hundred
+    # points in it most source chunks hold a handful of sources (some
+    # waves get none) and the last chunks are empty; the sum must not care.
+    cfg = CASES["channel"](precision)
+    say("eval large capacity", precision, cfg["pos"].shape[0], "points, n_cap", n_cap)
+    run = vlb.run_from_config(cfg, n_cap=n_cap)
+    got = run.eval_line_velocity()
+    ref, _, _ = _oracle_eval(cfg)
+    tol = TOL[precision]
+    for k in ("vs", "sdot"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= tol, (k, err)
+    run.close()
+
+
 @pytest.mark.parametrize("case", ["ring32", "channel", "heater"])
 def test_coupled_steps_f64(case):
     cfg = CASES[case]("f64")

@@ -158,9 +158,13 @@ __device__ void wave_scan_commit(bool flag, uint64_t* __restrict__ mask, int32_t
     mask[w] = m;
     pre[w] = __popcll(m);
   }
-  __threadfence();
+  // one device-scope fence per block, after the barrier that orders the
+  // block's stores before it (the fence writes back the L2 as a whole)
   __syncthreads();
-  if (t == 0) s_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  if (t == 0) {
+    __threadfence();
+    s_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+  }
   __syncthreads();
   if (!s_last) return;
   __threadfence();

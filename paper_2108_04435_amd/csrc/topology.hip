@@ -176,19 +176,10 @@ __global__ void k_reset_stats(int32_t* cnt) {
   if (threadIdx.x == 0) cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
 }
 
-// Deletion candidate: incoming segment shorter than dxi_min, and the chord
-// that would replace the point's two segments not longer than dxi_max.
-__device__ inline bool rm_cand(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
-                               const int32_t* __restrict__ prv, long long nc, const TopoGeom& tg,
-                               double mn2, double mx2, int j) {
-  const int p = prv[j];
-  double d[3];
-  sep(pos, nc, p, j, tg, d);
-  if (!(sq3(d) < mn2)) return false;
-  double c[3];
-  sep(pos, nc, p, nxt[j], tg, c);
-  return sq3(c) <= mx2;
-}
+// Deletion candidate (the test written out in k_rm_mark): the incoming
+// segment is shorter than dxi_min, and the chord from the predecessor to the
+// successor, which would replace the point's two segments, is not longer
+// than dxi_max.
 
 // Along each run of consecutive deletion candidates every other point is
 // deleted: candidate j goes when the number c of candidates directly before
@@ -221,11 +212,29 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
   double d[3], c3[3];
   sep_v(yp, yj, tg, d);
   sep_v(yp, yq, tg, c3);
-  if (sq3(d) < mn2 && sq3(c3) <= mx2) {  // the candidacy test of rm_cand for j
+  if (sq3(d) < mn2 && sq3(c3) <= mx2) {  // j is a deletion candidate
+    // walk back over the candidates before j: the candidacy of point p
+    // needs the positions of its predecessor r, of p and of its successor
+    // (the point walked from); r's predecessor is loaded together with r's
+    // position, so every step costs one round of loads
     int c = 0, p = p0;
-    while (c < kChainLimit && p != j && rm_cand(pos, nxt, prv, nc, tg, mn2, mx2, p)) {
+    double yc[3] = {yp[0], yp[1], yp[2]};  // position of p
+    double ys[3] = {yj[0], yj[1], yj[2]};  // position of p's successor
+    int r = clamp_index(prv[p], nc);
+    while (c < kChainLimit && p != j) {
+      const int rr = clamp_index(prv[r], nc);
+      double yr[3], e[3], f[3];
+      load3(pos, nc, r, yr);
+      sep_v(yr, yc, tg, e);
+      sep_v(yr, ys, tg, f);
+      if (!(sq3(e) < mn2 && sq3(f) <= mx2)) break;  // p is no deletion candidate
       ++c;
-      p = prv[p];
+      for (int a = 0; a < 3; ++a) {
+        ys[a] = yc[a];
+        yc[a] = yr[a];
+      }
+      p = r;
+      r = rr;
     }
     if (p == j) {
       const int L = c + 1;
@@ -280,10 +289,14 @@ __global__ __launch_bounds__(kBlock) void k_rm_link(const double* __restrict__ p
       __hip_atomic_store(&nxt[p0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       prv[s0] = p0;
     } else {
-      int s = s0;
-      if (del[s]) s = nxt[s];
+      // the successor's flag, link and position in one round of loads; a
+      // deleted successor's link is stable, a kept one's is not used
+      const int ds = del[s0];
+      const int ns = clamp_index(
+          __hip_atomic_load(&nxt[s0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), nc);
       double ys[3], d[3];
-      load3(pos, nc, s, ys);
+      load3(pos, nc, s0, ys);
+      if (ds) load3(pos, nc, ns, ys);
       sep_v(yj, ys, tg, d);
       ins = sq3(d) > mx2;
     }

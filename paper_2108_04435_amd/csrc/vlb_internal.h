@@ -147,6 +147,50 @@ __device__ inline long long nbr_index(const Nbr& nb, int dx, int dy, int dz) {
   return nb.zo[dz + 1] + nb.yo[dy + 1] + nb.xo[dx + 1];
 }
 
+// The same in 32-bit integers, for lattices of fewer than 2^29 nodes whose
+// population array spans less than 4 GiB (a node beyond a wall gives a
+// negative index: one or two of the three terms are -2^29, the others sum
+// to less than 2^29).
+struct Nbr32 {
+  int zo[3], yo[3], xo[3];
+};
+constexpr int kBeyond32 = -(1 << 29);
+
+__device__ inline void make_nbr32(const Geom& g, int x, int y, int z, Nbr32& nb) {
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    int xx = x + d, yy = y + d, zz = z + d;
+    bool vx = true, vy = true, vz = true;
+    if (xx < 0 || xx >= g.nx) {
+      if (g.wall[0]) vx = false;
+      xx = xx < 0 ? xx + g.nx : xx - g.nx;
+    }
+    if (yy < 0 || yy >= g.ny) {
+      if (g.wall[1]) vy = false;
+      yy = yy < 0 ? yy + g.ny : yy - g.ny;
+    }
+    if (zz < 0 || zz >= g.nz) {
+      if (g.wall[2]) vz = false;
+      zz = zz < 0 ? zz + g.nz : zz - g.nz;
+    }
+    nb.xo[d + 1] = vx ? xx : kBeyond32;
+    nb.yo[d + 1] = vy ? yy * g.nx : kBeyond32;
+    nb.zo[d + 1] = vz ? zz * g.ny * g.nx : kBeyond32;
+  }
+}
+
+__device__ inline int nbr_index32(const Nbr32& nb, int dx, int dy, int dz) {
+  return nb.zo[dz + 1] + nb.yo[dy + 1] + nb.xo[dx + 1];
+}
+
+// Element i of M at a 32-bit byte offset from the (wave-uniform) base, so
+// that loads and stores take the base from scalar registers and one vector
+// register per address.
+template <class S>
+__device__ inline S* at_byte(S* M, uint32_t byte_off) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(M) + byte_off);
+}
+
 // Deviations of the populations at node (x, y, z) at a time whose storage
 // parity is P (0: natural layout, population i of node x in slot i of x;
 // 1: the AA-swapped layout written by an even step: population i of x sits

@@ -92,11 +92,11 @@ void release_streams(Run& r) {
   hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_join};
   for (hipEvent_t* ev : evs)
     if (*ev) {
-      hipEventDestroy(*ev);
+      (void)hipEventDestroy(*ev);  // teardown: nothing to report to
       *ev = nullptr;
     }
   if (r.side) {
-    hipStreamDestroy(r.side);
+    (void)hipStreamDestroy(r.side);
     r.side = nullptr;
   }
 }
@@ -268,7 +268,10 @@ void time_begin(Run& r, int cls, hipEvent_t* b) {
   if (!r.timing) return;
   hipEvent_t e0 = take_event(r);
   if (!e0) return;
-  hipEventRecord(e0, r.stream);
+  if (hipEventRecord(e0, r.stream) != hipSuccess) {  // the launch then goes untimed
+    r.ev_pool.push_back(e0);
+    return;
+  }
   *b = e0;
 }
 
@@ -276,7 +279,11 @@ void time_end(Run& r, int cls, hipEvent_t b) {
   if (!r.timing || !b) return;
   hipEvent_t e1 = take_event(r);
   if (!e1) return;
-  hipEventRecord(e1, r.stream);
+  if (hipEventRecord(e1, r.stream) != hipSuccess) {  // the launch then goes untimed
+    r.ev_pool.push_back(e1);
+    r.ev_pool.push_back(b);
+    return;
+  }
   r.ev_used[cls].emplace_back(b, e1);
 }
 
@@ -297,7 +304,7 @@ void recycle_events(Run& r) {
 
 void drop_events(Run& r) {
   recycle_events(r);
-  for (hipEvent_t e : r.ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : r.ev_pool) (void)hipEventDestroy(e);  // teardown
   r.ev_pool.clear();
 }
 
@@ -386,8 +393,8 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   r.ws_bytes = ws_bytes;
   layout(r, r.ws);
   r.stream = (hipStream_t)hip_stream;
-  hipGetDevice(&r.device);
-  hipError_t e = hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking);
+  hipError_t e = hipGetDevice(&r.device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&r.side, hipStreamNonBlocking);
   hipEvent_t* evs[] = {&r.ev_fork, &r.ev_mom, &r.ev_fin1, &r.ev_join};
   for (hipEvent_t* ev : evs)
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
@@ -517,7 +524,7 @@ int one_step(vlb_run* h, bool first, bool last) {
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
     if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
-    HIP_OR_FAIL(h, bs_sum(r, Ys[s]));
+    HIP_OR_FAIL(h, bs_sum(r));
     // the first finalize reads the velocity field and the superflow
     if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
@@ -631,7 +638,7 @@ int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, dou
   Run& r = h->r;
   HIP_OR_FAIL(h, lbm_moments(r));
   HIP_OR_FAIL(h, bs_prep(r, r.pos));
-  HIP_OR_FAIL(h, bs_sum(r, r.pos));
+  HIP_OR_FAIL(h, bs_sum(r));
   HIP_OR_FAIL(h, fil_finalize(r, 1, r.pos, r.ya, 1));
   if (r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
   int32_t n = 0;
@@ -708,26 +715,32 @@ int vlb_time_kernel(vlb_run* h, int32_t cls, int32_t reps, double* avg_ms) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   if (cls < 0 || cls > 1 || reps < 1 || !avg_ms) return fail(h, VLB_EINVAL, "bad kernel timing request");
   Run& r = h->r;
-  const bool was = r.timing;
+  // the events and the timing flag are restored on every exit
+  struct Guard {
+    Run& r;
+    bool was;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Guard() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      r.timing = was;
+    }
+  } gd{r, r.timing};
   r.timing = false;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_OR_FAIL(h, hipEventCreate(&e0));
-  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  HIP_OR_FAIL(h, hipEventCreate(&gd.e0));
+  HIP_OR_FAIL(h, hipEventCreate(&gd.e1));
   if (cls == 0) HIP_OR_FAIL(h, bs_prep(r, r.pos));
-  HIP_OR_FAIL(h, hipEventRecord(e0, r.stream));
+  HIP_OR_FAIL(h, hipEventRecord(gd.e0, r.stream));
   for (int k = 0; k < reps; ++k) {
     if (cls == 0)
-      HIP_OR_FAIL(h, bs_sum(r, r.pos));
+      HIP_OR_FAIL(h, bs_sum(r));
     else
       HIP_OR_FAIL(h, lbm_step(r));
   }
-  HIP_OR_FAIL(h, hipEventRecord(e1, r.stream));
-  HIP_OR_FAIL(h, hipEventSynchronize(e1));
+  HIP_OR_FAIL(h, hipEventRecord(gd.e1, r.stream));
+  HIP_OR_FAIL(h, hipEventSynchronize(gd.e1));
   float ms = 0.f;
-  HIP_OR_FAIL(h, hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  r.timing = was;
+  HIP_OR_FAIL(h, hipEventElapsedTime(&ms, gd.e0, gd.e1));
   *avg_ms = (double)ms / reps;
   return latched(h);
 }
@@ -779,17 +792,17 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
     r.point_parity = pparity0;
   }
   if (code != VLB_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return code;
   }
   if (ec != hipSuccess) return hip_fail(h, ec, "hipStreamEndCapture");
   hipGraphExec_t exec = nullptr;
   const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (ei != hipSuccess) return hip_fail(h, ei, "hipGraphInstantiate");
   vlb_graph* g = new (std::nothrow) vlb_graph();
   if (!g) {
-    hipGraphExecDestroy(exec);
+    (void)hipGraphExecDestroy(exec);
     return fail(h, VLB_EINVAL, "out of host memory");
   }
   g->run = h;
@@ -815,15 +828,16 @@ int vlb_graph_launch(vlb_graph* g) {
 
 int vlb_graph_destroy(vlb_graph* g) {
   if (!g) return VLB_OK;
-  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
   delete g;
   return VLB_OK;
 }
 
 int vlb_destroy(vlb_run* h) {
   if (!h) return VLB_OK;
-  hipStreamSynchronize(h->r.stream);
-  if (h->r.side) hipStreamSynchronize(h->r.side);
+  // teardown: a device error has nowhere to go any more (vlb_sync reports it)
+  (void)hipStreamSynchronize(h->r.stream);
+  if (h->r.side) (void)hipStreamSynchronize(h->r.side);
   drop_events(h->r);
   release_streams(h->r);
   delete h;

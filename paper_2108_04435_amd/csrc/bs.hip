@@ -352,7 +352,7 @@ hipError_t bs_prep(Run& r, const double* Y) {
   return hipGetLastError();
 }
 
-hipError_t bs_sum(Run& r, const double* Y) {
+hipError_t bs_sum(Run& r) {
   const int tb = (int)((r.ncap + kTargets - 1) / kTargets);
   dim3 grid(tb, r.bsS);
   hipEvent_t b = nullptr;

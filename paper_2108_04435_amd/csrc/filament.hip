@@ -369,8 +369,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
 //    wrote, and clear the previous spreading's bin marks.
 template <class FT>
 __global__ __launch_bounds__(kSortThreads) void k_spread_prepare(
-    const double* __restrict__ pos, const int32_t* __restrict__ cnt, long long ncap, SpreadGeom sg,
-    uint32_t pad, int dbits, int ntiles, uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+    const int32_t* __restrict__ cnt, long long ncap, uint32_t pad, int dbits, int ntiles, uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
     int32_t* __restrict__ counts, FT* __restrict__ F, long long cells,
     const int32_t* __restrict__ touched, const uint32_t* __restrict__ marked,
     int32_t* __restrict__ bins) {
@@ -505,11 +504,6 @@ __global__ void k_spread_gather(const uint32_t* __restrict__ skey, const int32_t
   touched[id] = (int32_t)node;
 }
 
-__global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 inline int nblocks(long long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -568,11 +562,11 @@ hipError_t fil_spread(Run& r) {
   const int nclear = nblocks(8 * r.ncap, kSortThreads);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_spread_prepare<double>, dim3(ntiles + nclear), dim3(kSortThreads), 0,
-                       r.stream, r.pos, r.cnt, r.ncap, sg, pad, dbits, ntiles, r.keys_a, r.vals_a,
+                       r.stream, r.cnt, r.ncap, pad, dbits, ntiles, r.keys_a, r.vals_a,
                        sort_counts(r), (double*)r.force, r.cells, r.touched, r.marked, r.bins);
   else
     hipLaunchKernelGGL(k_spread_prepare<float>, dim3(ntiles + nclear), dim3(kSortThreads), 0,
-                       r.stream, r.pos, r.cnt, r.ncap, sg, pad, dbits, ntiles, r.keys_a, r.vals_a,
+                       r.stream, r.cnt, r.ncap, pad, dbits, ntiles, r.keys_a, r.vals_a,
                        sort_counts(r), (float*)r.force, r.cells, r.touched, r.marked, r.bins);
   uint32_t* sk = nullptr;
   int32_t* sv = nullptr;

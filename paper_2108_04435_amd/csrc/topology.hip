@@ -107,10 +107,6 @@ __device__ inline int flag_rank(const uint64_t* __restrict__ mask, const int32_t
   return pre[w] + __popcll(mask[w] & lanes_below(x & 63));
 }
 
-__device__ inline bool flag_bit(const uint64_t* __restrict__ mask, int x) {
-  return (mask[x >> 6] >> (x & 63)) & 1ull;
-}
-
 // Exclusive scan of a[0..n) in place by one block of kBlock threads.
 __device__ void block_scan_inplace(int32_t* a, int n, int32_t* total) {
   __shared__ int32_t wsum[kBlock / 64];

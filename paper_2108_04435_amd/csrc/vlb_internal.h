@@ -427,7 +427,7 @@ hipError_t lbm_read_force(Run& r, double* out);
 hipError_t lbm_moments(Run& r);
 
 hipError_t bs_prep(Run& r, const double* Y);
-hipError_t bs_sum(Run& r, const double* Y);
+hipError_t bs_sum(Run& r);
 int bs_chunks(long long ncap);
 
 hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only);

@@ -494,10 +494,12 @@ struct OnStream {
 // nothing the later stages or the topology rewrite.  The LBM update follows
 // the spreading on the side stream, launched on a narrow grid (two blocks
 // per CU) so that it leaves most CU slots to the filament kernels beside
-// it.  The next step's moments overwrite the velocity field the stages
-// read, so they wait for finalize 4 and run beside the topology.  The first step of a call forks the side
-// stream from main and computes its own moments; the last one joins the
-// side stream back, so a call's work is ordered on the caller's stream.
+// it.  The next step's moments follow the LBM update on the side stream
+// and write the second velocity field (this step's stages read the first;
+// the two swap at the end of the step).  The first step of a call forks
+// the side stream from main and computes its own moments; the last one
+// joins the side stream back, so a call's work is ordered on the caller's
+// stream.
 int one_step(vlb_run* h, bool first, bool last) {
   Run& r = h->r;
   if (!r.has_points) {  // never seeded: the normal fluid alone

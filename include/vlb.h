@@ -124,7 +124,10 @@ int vlb_write_fields(vlb_run* run, const double* rho_dev, const double* u_dev);
 
 /* Replace the filaments by n_pts points (host xyz[n][3], lattice units) on
  * closed loops given by next (host, n ints, a permutation whose cycles are
- * the loops).  Positions on periodic axes are wrapped into [0, L).       */
+ * the loops).  Positions on periodic axes are wrapped into [0, L) by one
+ * shift of L; a wall axis mirrors a point beyond the wall plane (-1/2 or
+ * L - 1/2) once.  VLB_EINVAL when that leaves a coordinate outside the box
+ * (more than one length L away), or for a non-finite coordinate.          */
 int vlb_seed_vortices(vlb_run* run, int64_t n_pts, const double* xyz_host,
                       const int32_t* next_host);
 
@@ -207,8 +210,9 @@ int vlb_get_work(vlb_run* run, int64_t* node_updates, int64_t* bs_pairs);
  * stream (which must not be the null stream); nothing is executed.  Each
  * vlb_graph_launch enqueues the whole graph on the run's stream and
  * advances the run's step counter by n_steps; it returns VLB_ESTATE if the
- * run was stepped by an odd number of steps since the capture.  The graph
- * holds the run's pointers: destroy it before the run.                     */
+ * run was stepped by an odd number of steps since the capture, or if the
+ * first filaments were seeded after a capture of lattice-only steps.  The
+ * graph holds the run's pointers: destroy it before the run.              */
 typedef struct vlb_graph vlb_graph;
 int vlb_graph_create(vlb_run* run, int64_t n_steps, vlb_graph** out);
 int vlb_graph_launch(vlb_graph* graph);

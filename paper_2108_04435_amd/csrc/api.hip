@@ -21,6 +21,7 @@ struct vlb_graph {
   int64_t n_steps = 0;
   int parity = 0;
   int point_parity = 0;
+  bool has_points = false;  // filaments present at capture (else the LBM alone)
 };
 
 namespace {
@@ -451,7 +452,12 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
     for (int a = 0; a < 3; ++a) {
       const double x = xyz[3 * (size_t)j + a];
       if (!std::isfinite(x)) return fail(h, VLB_EINVAL, "non-finite position");
-      soa[(size_t)a * n + j] = wrap_host(x, (double)dims[a], !r.geom.wall[a]);
+      const double L = (double)dims[a];
+      const double w = wrap_host(x, L, !r.geom.wall[a]);
+      // one wrap (periodic) or one mirror (wall) must bring the point inside
+      if (r.geom.wall[a] ? !(w >= -0.5 && w <= L - 0.5) : !(w >= 0.0 && w < L))
+        return fail(h, VLB_EINVAL, "position more than one lattice length outside the box");
+      soa[(size_t)a * n + j] = w;
     }
   // loops shorter than min_loop_pts are accepted here and removed by the
   // next topology pass
@@ -812,6 +818,7 @@ int vlb_graph_create(vlb_run* h, int64_t n_steps, vlb_graph** out) {
   g->n_steps = n_steps;
   g->parity = parity0;
   g->point_parity = pparity0;
+  g->has_points = r.has_points;
   *out = g;
   return VLB_OK;
 }
@@ -822,6 +829,8 @@ int vlb_graph_launch(vlb_graph* g) {
   Run& r = h->r;
   if (r.parity != g->parity || r.point_parity != g->point_parity)
     return fail(h, VLB_ESTATE, "run parity differs from the captured one");
+  if (r.has_points != g->has_points)
+    return fail(h, VLB_ESTATE, "filaments were seeded after the graph was captured");
   HIP_OR_FAIL(h, hipGraphLaunch(g->exec, r.stream));
   r.step += g->n_steps;
   r.last_nodes += g->n_steps * r.cells;

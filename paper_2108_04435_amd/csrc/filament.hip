@@ -152,17 +152,19 @@ __device__ void interp_vn(const UT* __restrict__ ub, const Geom& g, double px, d
   }
 }
 
-// 64 points per block of 256 threads.  The four waves add the Biot-Savart
-// chunk partials of the block's points (wave g takes chunks g, g + 4, ...,
-// eight chunks' loads in flight at a time); before its share, wave 1
-// interpolates the normal-fluid velocity and wave 2 evaluates the local
-// geometry and the LIA term, so that these load chains overlap.  Wave 0
-// then combines the parts in a fixed order and does the rest per point.
+// 64 points per block of kFinWaves waves.  The waves add the Biot-Savart
+// chunk partials of the block's points (wave g takes chunks g, g + kFinWaves,
+// ..., eight chunks' loads in flight at a time); before its share, wave 1
+// interpolates the normal-fluid velocity, wave 2 evaluates the local
+// geometry and the LIA term and wave 3 loads the RK4 state, so that these
+// load chains overlap.  Wave 0 then combines the parts in a fixed order and
+// does the rest per point.
 constexpr int kFinPts = 64;
+constexpr int kFinWaves = 4;
 
 template <class UT, class PT>
-__global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
-  __shared__ double red[3][3][kFinPts];  // chunk sums of waves 1..3
+__global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
+  __shared__ double red[kFinWaves - 1][3][kFinPts];  // chunk sums of waves 1..kFinWaves-1
   __shared__ double s_vn[3][kFinPts];    // wave 1: normal-fluid velocity
   __shared__ double s_geo[8][kFinPts];   // wave 2: s' (3), LIA (3), l+, l-
   __shared__ double s_rk[7][kFinPts];    // wave 3: s^n (3), ksum (3), superflow
@@ -176,15 +178,16 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
   // harmless), and only live points write.
   const bool slot = j < nc;
   // the first batch of this wave's Biot-Savart chunk partials (chunks grp,
-  // grp + 4, ..., up to 8 of them; beyond S they read as zero, which adds
-  // nothing), loaded before the wave's own work so that the latencies overlap
+  // grp + kFinWaves, ..., up to 8 of them; beyond S they read as zero, which
+  // adds nothing), loaded before the wave's own work so that the latencies
+  // overlap
   const PT* __restrict__ P = (const PT*)A.P;
   const long long jc = slot ? j : 0;  // in-bounds index for the unconditional loads
   PT v0[8][3];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const bool ok = slot && grp + 4 * u < A.S;
-    const long long c = ok ? grp + 4 * u : 0;
+    const bool ok = slot && grp + kFinWaves * u < A.S;
+    const long long c = ok ? grp + kFinWaves * u : 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const PT x = P[(c * 3 + a) * nc + jc];
@@ -260,12 +263,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
     for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int a = 0; a < 3; ++a) vs[a] += (double)v0[u][a];
-    for (int s = grp + 32; s < A.S; s += 32) {
+    for (int s = grp + 8 * kFinWaves; s < A.S; s += 8 * kFinWaves) {
       PT v[8][3];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const bool ok = s + 4 * u < A.S;
-        const long long c = ok ? s + 4 * u : 0;
+        const bool ok = s + kFinWaves * u < A.S;
+        const long long c = ok ? s + kFinWaves * u : 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const PT x = P[(c * 3 + a) * nc + j];
@@ -282,8 +285,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs A) {
     for (int a = 0; a < 3; ++a) red[grp - 1][a][lane] = vs[a];
   __syncthreads();
   if (grp > 0 || !live) return;
-  for (int a = 0; a < 3; ++a)
-    vs[a] = (((vs[a] + red[0][a][lane]) + red[1][a][lane]) + red[2][a][lane]) * A.nl_scale;
+  for (int a = 0; a < 3; ++a) {
+    double t = vs[a];
+#pragma unroll
+    for (int w = 0; w < kFinWaves - 1; ++w) t += red[w][a][lane];
+    vs[a] = t * A.nl_scale;
+  }
 
   double sp[3];
   for (int a = 0; a < 3; ++a) {
@@ -547,8 +554,8 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.sfrac = r.sfrac;
   const int nb = nblocks(r.ncap, kFinPts);
   switch (r.prec) {
-    case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(256), 0, r.stream, A); break;
-    default: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(256), 0, r.stream, A); break;
+    case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(kFinWaves * 64), 0, r.stream, A); break;
+    default: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(kFinWaves * 64), 0, r.stream, A); break;
   }
   return hipGetLastError();
 }

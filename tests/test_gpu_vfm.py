@@ -415,3 +415,50 @@ def test_graph_rejects_odd_parity():
             np.testing.assert_array_equal(x, y)
         g.close()
         d.close()
+
+
+def test_seed_rejects_invalid_positions():
+    """Seeding checks on the host: a coordinate more than one length outside
+    the box, a non-finite one, or a next[] that is not a permutation gives
+    VLB_EINVAL and leaves the run usable; one period out is wrapped."""
+    lat = wl.lattice_preset(16, 16, 16, walls=(True, False, False), precision="f64")
+    vor = wl.vortex_preset()
+    pos, nxt = wl.random_rings(31, 1, 3.0, 4.0, (16, 16, 16), (True, False, False), 0.95)
+    say("seed checks", pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0])
+    bad_cases = []
+    p = pos.copy(); p[0, 1] = -17.0; bad_cases.append((p, nxt))  # periodic y, two periods
+    p = pos.copy(); p[0, 0] = 40.0; bad_cases.append((p, nxt))   # wall x, beyond one mirror
+    p = pos.copy(); p[0, 2] = np.inf; bad_cases.append((p, nxt))
+    q = nxt.copy(); q[1] = q[0]; bad_cases.append((pos, q))
+    for p, q in bad_cases:
+        with pytest.raises(vlb.VlbError) as ei:
+            run.seed(p, q)
+        assert ei.value.code == vlb.VLB_EINVAL
+    p = pos.copy(); p[:, 2] -= 16.0  # one period below on z
+    run.seed(p, nxt)
+    got, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, nxt)
+    np.testing.assert_allclose(got, pos, rtol=0, atol=1e-12)
+    run.close()
+
+
+def test_graph_rejects_seeding_after_lattice_only_capture():
+    """A graph captured before any filament was seeded replays the lattice
+    alone: after seeding it refuses to launch (VLB_ESTATE)."""
+    lat = wl.lattice_preset(16, 16, 16, precision="f32")
+    vor = wl.vortex_preset()
+    pos, nxt = wl.random_rings(32, 1, 3.0, 4.0, (16, 16, 16), (False, False, False), 0.95)
+    say("graph seeding")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0])
+        run.graph(2)
+        run.step_graph(2)
+        run.seed(pos, nxt)
+        with pytest.raises(vlb.VlbError) as ei:
+            run.step_graph(2)
+        assert ei.value.code == vlb.VLB_ESTATE
+        run.step(2)
+        run.sync()
+        run.close()

@@ -197,13 +197,14 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
 // FP64 pair sum (plain path).  R1 = (X_s - X_t) / q + (rho_s - rho_t): the
 // wrapped grid difference picks the image (the same decision as the FP32
 // sum), the residuals restore the FP64 separation of that image to
-// rounding; R2 = R1 + d.  The closed form is evaluated with the inverse
-// norms and the reciprocal of the hardware approximations (relative error
-// up to about 5e-8), each refined by one Newton step (which squares it: at
-// most 4.1e-15 for the inverse root and 2.1e-15 for the reciprocal over
-// 1e6 arguments from 1e-8 to 1e22, measured against long-double
-// references), and the same checked / unchecked tile split as the FP32
-// sum.
+// rounding; R2 = R1 + d enters through |R2|^2 = |R1|^2 + 2 R1.d + |d|^2 and
+// R1.R2 = |R1|^2 + R1.d, as in the FP32 sum.  The closed form is evaluated
+// with the inverse norms and the reciprocal of the hardware approximations
+// (relative error up to about 5e-8), each refined by one Newton step (which
+// squares it: at most 4.1e-15 for the inverse root and 2.1e-15 for the
+// reciprocal over 1e6 arguments from 1e-8 to 1e22, measured against
+// long-double references), and the same checked / unchecked tile split as
+// the FP32 sum.
 __device__ inline double rsq_nr(double n) {
   const double y = __builtin_amdgcn_rsq(n);
   const double e = fma(-(n * y), y, 1.0);  // 1 - n y^2
@@ -219,7 +220,8 @@ __device__ inline double rcp_nr(double d) {
 template <bool kCheck>
 __device__ inline void bs_tile_f64(const uint32_t* sx, const uint32_t* sy, const uint32_t* sz,
                                    const double* rx, const double* ry, const double* rz,
-                                   const double* dx, const double* dy, const double* dz, int cnt,
+                                   const double* dx, const double* dy, const double* dz,
+                                   const double* dq, int cnt,
                                    int t0, uint32_t xt, uint32_t yt, uint32_t zt, double rtx,
                                    double rty, double rtz, double gx, double gy, double gz, int jj,
                                    int pj, double& ax, double& ay, double& az) {
@@ -229,10 +231,10 @@ __device__ inline void bs_tile_f64(const uint32_t* sx, const uint32_t* sy, const
     const double r1y = fma((double)(int)(sy[s] - yt), gy, ry[s] - rty);
     const double r1z = fma((double)(int)(sz[s] - zt), gz, rz[s] - rtz);
     const double ex = dx[s], ey = dy[s], ez = dz[s];
-    const double r2x = r1x + ex, r2y = r1y + ey, r2z = r1z + ez;
+    const double t = r1x * ex + r1y * ey + r1z * ez;
     const double n1 = r1x * r1x + r1y * r1y + r1z * r1z;
-    const double n2 = r2x * r2x + r2y * r2y + r2z * r2z;
-    const double u = r1x * r2x + r1y * r2y + r1z * r2z;
+    const double n2 = fma(2.0, t, n1 + dq[s]);
+    const double u = n1 + t;
     const double crx = r1y * ez - r1z * ey;
     const double cry = r1z * ex - r1x * ez;
     const double crz = r1x * ey - r1y * ex;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   const int jj = valid ? j : -1;
   __shared__ __align__(16) uint32_t sx[kTile], sy[kTile], sz[kTile];
   __shared__ __align__(16) double rx[kTile], ry[kTile], rz[kTile];
-  __shared__ __align__(16) double dx[kTile], dy[kTile], dz[kTile];
+  __shared__ __align__(16) double dx[kTile], dy[kTile], dz[kTile], dq[kTile];
   __shared__ double red[3][3][kTargets];  // sums of waves 1..3
   double ax = 0.0, ay = 0.0, az = 0.0;
   for (int t0 = kb; t0 < ke; t0 += kTile) {
@@ -287,9 +289,11 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
       sx[threadIdx.x] = X[k];
       sy[threadIdx.x] = X[ncap + k];
       sz[threadIdx.x] = X[2 * ncap + k];
-      dx[threadIdx.x] = D[k];
-      dy[threadIdx.x] = D[ncap + k];
-      dz[threadIdx.x] = D[2 * ncap + k];
+      const double ex = D[k], ey = D[ncap + k], ez = D[2 * ncap + k];
+      dx[threadIdx.x] = ex;
+      dy[threadIdx.x] = ey;
+      dz[threadIdx.x] = ez;
+      dq[threadIdx.x] = ex * ex + ey * ey + ez * ez;
       rx[threadIdx.x] = D[3 * ncap + k];
       ry[threadIdx.x] = D[4 * ncap + k];
       rz[threadIdx.x] = D[5 * ncap + k];
@@ -302,12 +306,12 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
       const bool hit = valid && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
       if (__any(hit))
         bs_tile_f64<true>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
-                          dz + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj, pj, ax,
-                          ay, az);
+                          dz + lo, dq + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj,
+                          pj, ax, ay, az);
       else
         bs_tile_f64<false>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
-                           dz + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj, pj, ax,
-                           ay, az);
+                           dz + lo, dq + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj,
+                           pj, ax, ay, az);
     }
     __syncthreads();
   }

@@ -21,6 +21,8 @@ LBM_CASES = {
     "walls_xy": dict(n=(11, 13, 10), walls=(True, True, False), planes=False, body=(0.0, 0.0, 4e-5)),
     "walls_xyz": dict(n=(9, 8, 10), walls=(True, True, True), planes=False, body=(2e-5, 0.0, 1e-5)),
     "planes": dict(n=(10, 12, 14), walls=(True, True, False), planes=True, body=(0.0, 0.0, 0.0)),
+    # rows longer than one block (256 nodes) with a ragged second block
+    "wide_x": dict(n=(261, 5, 4), walls=(True, False, False), planes=False, body=(1e-5, 0.0, 2e-5)),
 }
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}

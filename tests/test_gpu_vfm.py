@@ -26,6 +26,9 @@ CASES = {
     "channel": lambda p: small_channel(precision=p),
     "periodic": lambda p: small_periodic(precision=p),
     "heater": lambda p: small_channel(precision=p, planes=True, seed=23),
+    # more than 512 LBM blocks: the update beside the filament kernels
+    # strides its narrow grid over them
+    "wide": lambda p: small_channel(precision=p, seed=28, n_rings=8, nxy=64, nz=40),
 }
 
 
@@ -79,7 +82,7 @@ def test_line_velocity_large_capacity(n_cap, precision):
     run.close()
 
 
-@pytest.mark.parametrize("case", ["ring32", "channel", "heater"])
+@pytest.mark.parametrize("case", ["ring32", "channel", "heater", "wide"])
 def test_coupled_steps_f64(case):
     cfg = CASES[case]("f64")
     steps = 12

@@ -605,6 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
 // sequential greedy pass.  Taken exchanges are disjoint, so their link
 // updates do not interact.  Values that atomics update are read and
 // written with device-scope atomics.
+constexpr int kMatchPer = 16;  // points per thread in the slot gather of k_rc_match
+
 __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
                                                    int32_t* __restrict__ prv,
                                                    int32_t* __restrict__ cnt, long long rcap,
@@ -624,15 +626,33 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = cnt[9];
   const bool overflow = cnt[10] != 0;
-  // gather the slots in (i, j) order: exclusive scan of the counts, 4
-  // points per thread; a point's slots go to their rank by j
+  // gather the slots in (i, j) order: exclusive scan of the counts,
+  // kMatchPer points per thread (one round up to 16384 points, vector loads
+  // where the round is full); a point's slots go to their rank by j
   int carry = 0;
-  for (int base = 0; base < n; base += 4096) {
-    const int k0 = base + 4 * t;
-    int v[4];
+  for (int base = 0; base < n; base += kMatchPer * 1024) {
+    const int k0 = base + kMatchPer * t;
+    int v[kMatchPer];
+    if (k0 + kMatchPer <= n) {
+      const int4* p = reinterpret_cast<const int4*>(count + k0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (k0 + q < n) ? min(count[k0 + q], kSlots) : 0;
-    const int mine = v[0] + v[1] + v[2] + v[3];
+      for (int q = 0; q < kMatchPer / 4; ++q) {
+        const int4 c4 = p[q];
+        v[4 * q] = c4.x;
+        v[4 * q + 1] = c4.y;
+        v[4 * q + 2] = c4.z;
+        v[4 * q + 3] = c4.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kMatchPer; ++q) v[q] = (k0 + q < n) ? count[k0 + q] : 0;
+    }
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < kMatchPer; ++q) {
+      v[q] = min(v[q], kSlots);
+      mine += v[q];
+    }
     int x = mine;
     for (int off = 1; off < 64; off <<= 1) {
       const int y = __shfl_up(x, off, 64);
@@ -648,7 +668,7 @@ __global__ __launch_bounds__(1024) void k_rc_match(int32_t* __restrict__ nxt,
     int run = carry + before + x - mine;
     if (!overflow) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kMatchPer; ++q) {
         const int32_t* sj = slot_j + (long long)(k0 + q) * kSlots;
         for (int m = 0; m < v[q]; ++m) {
           const int jm = sj[m];

@@ -104,11 +104,12 @@ def test_coupled_steps_f64(case):
     np.testing.assert_allclose(rho_g, rho_o, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("case", ["channel", "wide"])
 @pytest.mark.parametrize("precision", ["f32", "f16"])
-def test_coupled_steps_reduced_precision(precision):
-    cfg = small_channel(precision=precision)
+def test_coupled_steps_reduced_precision(precision, case):
+    cfg = CASES[case](precision)
     steps = 10
-    say("coupled reduced", precision)
+    say("coupled reduced", case, precision)
     run = vlb.run_from_config(cfg)
     run.step(steps)
     run.sync()

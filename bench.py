@@ -44,6 +44,13 @@ FLOPS_PER_PAIR = 41
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X published FP64 vector peak
 PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
+# Issue ceiling of the FP32 pair loop: packed FP32 is not used, so a SIMD
+# issues one VALU instruction per lane per cycle: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz.  The unrolled loop body of the built kernel holds 117
+# VALU instructions per 4 pairs (its 12 transcendental ones issue beside
+# them), i.e. 29.25 per pair.
+VALU_LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9
+VALU_PER_PAIR_F32 = 29.25
 
 WORKLOADS = ("counterflow", "ring32", "heater", "tangle", "serve")
 
@@ -292,6 +299,12 @@ def main():
         "flops_per_pair": FLOPS_PER_PAIR,
         "in_step": in_step,
     }
+    if not f64:
+        ceiling = VALU_LANE_ISSUE_PER_S / VALU_PER_PAIR_F32
+        rate = pairs_iso / (bs_iso_ms * 1e-3)
+        roofline["issue_ceiling"] = {"valu_per_pair": VALU_PER_PAIR_F32,
+                                     "pairs_per_s": round(ceiling / 1e12, 4) * 1e12,
+                                     "frac": round(rate / ceiling, 4)}
     b = {"f64": 8, "f32": 4, "f16": 2}[lat["precision"]]
     lbm_bytes = 2 * 19 * b * cells
     out = {

@@ -23,6 +23,8 @@ vfm       filament geometry, Biot-Savart, LIA, Schwarz EoM, mutual-friction
 topology  remeshing, reconnection, small-loop removal, compaction
                                                      (Sec. II.A, III.B)
 coupled   one coupled time step (RK4 on the filaments, one LBM update)
+diagnostics  vortex line length (total and per z slab), normal-fluid
+          velocity statistics, vorticity        (Sec. III.A, III.C, IV)
 
 All floating point is IEEE binary64 (numpy float64).  numpy never contracts
 a*b+c into a fused multiply-add, so every threshold decision below
@@ -30,4 +32,4 @@ a*b+c into a fused multiply-add, so every threshold decision below
 function of the stored positions.
 """
 
-from . import d3q19, lbm, vfm, topology, coupled  # noqa: F401
+from . import d3q19, lbm, vfm, topology, coupled, diagnostics  # noqa: F401

@@ -180,6 +180,35 @@ int vlb_eval_line_velocity(vlb_run* run, double* vs_host, double* vn_host,
  * removed with small loops.                                                */
 int vlb_apply_topology(vlb_run* run, int64_t* stats_host);
 
+/* Vortex line length of the current filaments (Sec. III.C and IV: the line
+ * density the paper follows in time and along the channel).  *total_host
+ * receives the sum of the segment lengths |s_next - s| (nearest periodic
+ * image); per_slab_host (nz doubles) the length inside each slab
+ * [z - 1/2, z + 1/2) along z (a periodic z axis wraps), every straight
+ * segment split in proportion to its z extent, a segment without z extent
+ * counted in the slab of its start point.  Either may be NULL, not both.
+ * Divide by the volume nx*ny*nz (resp. the slab volume nx*ny) for the line
+ * density.  Synchronises the run's stream.                                 */
+int vlb_line_length(vlb_run* run, double* total_host, double* per_slab_host);
+
+/* Statistics of the normal-fluid velocity (Sec. III.C: the mean flow V_n
+ * and its fluctuations delta v_n = v_n - V_n, component by component) of
+ * the bare velocity sum(c_i f_i)/sum(f_i) of the current populations
+ * (velocity planes applied, as vlb_read_fields).  Host outputs, any may be
+ * NULL: slice_mean and slice_rms ([nz][3]) the mean of each component over
+ * each z slice and the root mean square of its deviation from that mean;
+ * mean and rms ([3]) the same over the whole lattice.  All sums in FP64 in
+ * a fixed order.  Synchronises the run's stream.                          */
+int vlb_flow_stats(vlb_run* run, double* slice_mean_host, double* slice_rms_host,
+                   double* mean_host, double* rms_host);
+
+/* Vorticity of the normal fluid, omega = curl v (Sec. III.A).  u_dev
+ * (3*cells doubles, device, as vlb_read_fields) receives the bare velocity
+ * and omega_dev (3*cells doubles, device) its curl by central differences;
+ * periodic axes wrap and a node beyond a wall counts as u = 0.  Both
+ * required.  Synchronises the run's stream.                                */
+int vlb_read_vorticity(vlb_run* run, double* u_dev, double* omega_dev);
+
 /* Number of completed steps.                                               */
 int vlb_get_step(vlb_run* run, int64_t* step);
 

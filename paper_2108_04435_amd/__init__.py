@@ -31,7 +31,8 @@ PRECISION = {"f64": 0, "f32": 1, "f16": 2}
 SYMBOLS = [
     "vlb_query_footprint", "vlb_create_lattice", "vlb_write_fields", "vlb_seed_vortices",
     "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
-    "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology", "vlb_get_step",
+    "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology", "vlb_line_length",
+    "vlb_flow_stats", "vlb_read_vorticity", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
     "vlb_graph_launch", "vlb_graph_destroy", "vlb_destroy", "vlb_last_error",
 ]
@@ -99,6 +100,9 @@ def load_library(path=None):
     lib.vlb_read_fields.argtypes = [vp, vp, vp]
     lib.vlb_read_populations.argtypes = [vp, vp]
     lib.vlb_read_force.argtypes = [vp, vp]
+    lib.vlb_line_length.argtypes = [vp, vp, vp]
+    lib.vlb_flow_stats.argtypes = [vp, vp, vp, vp, vp]
+    lib.vlb_read_vorticity.argtypes = [vp, vp, vp]
     lib.vlb_read_filaments.argtypes = [vp, i64, vp, vp, ctypes.POINTER(i64)]
     lib.vlb_eval_line_velocity.argtypes = [vp, vp, vp, vp, vp]
     lib.vlb_apply_topology.argtypes = [vp, vp]
@@ -263,6 +267,31 @@ class Run:
         F = self.torch.empty((3,) + self.shape, dtype=self.torch.float64, device=self.device)
         self._check(self.lib.vlb_read_force(self.h, ctypes.c_void_p(F.data_ptr())))
         return F.cpu().numpy()
+
+    def line_length(self):
+        """(total line length, length per z slab)."""
+        tot = ctypes.c_double(0.0)
+        slabs = np.zeros(self.ld.nz)
+        self._check(self.lib.vlb_line_length(self.h, ctypes.byref(tot),
+                                             slabs.ctypes.data_as(ctypes.c_void_p)))
+        return float(tot.value), slabs
+
+    def flow_stats(self):
+        """Velocity statistics: slice_mean, slice_rms ((nz, 3)), mean, rms ((3,))."""
+        nz = self.ld.nz
+        sm, sr, m, r = np.zeros((nz, 3)), np.zeros((nz, 3)), np.zeros(3), np.zeros(3)
+        self._check(self.lib.vlb_flow_stats(self.h, *(a.ctypes.data_as(ctypes.c_void_p)
+                                                      for a in (sm, sr, m, r))))
+        return dict(slice_mean=sm, slice_rms=sr, mean=m, rms=r)
+
+    def read_vorticity(self):
+        """(bare velocity, vorticity), each (3, nz, ny, nx)."""
+        torch = self.torch
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        w = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.vlb_read_vorticity(self.h, ctypes.c_void_p(u.data_ptr()),
+                                                ctypes.c_void_p(w.data_ptr())))
+        return u.cpu().numpy(), w.cpu().numpy()
 
     def n_points(self):
         n = ctypes.c_int64(0)

@@ -118,6 +118,7 @@ size_t layout(Run& r, char* base) {
   r.force = B.take(3 * cells * fe);
   r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
   r.Vs_next = (double*)B.take(r.geom.nz * sizeof(double));
+  r.diag = (double*)B.take((8 + 6 * (size_t)r.geom.nz) * sizeof(double));
   r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
   double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage, &r.sfrac};
   for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
@@ -675,6 +676,62 @@ int vlb_apply_topology(vlb_run* h, int64_t* stats) {
     stats[2] = c[4];
     stats[3] = c[5];
   }
+  return latched(h);
+}
+
+int vlb_line_length(vlb_run* h, double* total, double* per_slab) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!total && !per_slab) return fail(h, VLB_EINVAL, "total and per_slab are both NULL");
+  Run& r = h->r;
+  const int nz = r.geom.nz;
+  HIP_OR_FAIL(h, diag_line_length(r, total ? r.diag : nullptr, per_slab ? r.diag + 8 : nullptr));
+  if (total)
+    HIP_OR_FAIL(h, hipMemcpyAsync(total, r.diag, sizeof(double), hipMemcpyDeviceToHost, r.stream));
+  if (per_slab)
+    HIP_OR_FAIL(h, hipMemcpyAsync(per_slab, r.diag + 8, nz * sizeof(double), hipMemcpyDeviceToHost,
+                                  r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  return latched(h);
+}
+
+int vlb_flow_stats(vlb_run* h, double* slice_mean, double* slice_rms, double* mean, double* rms) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  Run& r = h->r;
+  const int nz = r.geom.nz;
+  HIP_OR_FAIL(h, lbm_flow_stats(r, r.diag + 8));
+  std::vector<double> st(6 * (size_t)nz);
+  HIP_OR_FAIL(h, hipMemcpyAsync(st.data(), r.diag + 8, st.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  // slices hold the same number of nodes: the lattice mean is the mean of
+  // the slice means, and the lattice sum of squared deviations adds each
+  // slice's own and its mean's offset from the lattice mean
+  const double ns = (double)r.geom.nx * r.geom.ny;
+  double m[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
+  for (int z = 0; z < nz; ++z)
+    for (int a = 0; a < 3; ++a) m[a] += st[6 * z + a];
+  for (int a = 0; a < 3; ++a) m[a] /= nz;
+  for (int z = 0; z < nz; ++z)
+    for (int a = 0; a < 3; ++a) {
+      const double dm = st[6 * z + a] - m[a];
+      q[a] += st[6 * z + 3 + a] + ns * dm * dm;
+      if (slice_mean) slice_mean[3 * z + a] = st[6 * z + a];
+      if (slice_rms) slice_rms[3 * z + a] = std::sqrt(st[6 * z + 3 + a] / ns);
+    }
+  for (int a = 0; a < 3; ++a) {
+    if (mean) mean[a] = m[a];
+    if (rms) rms[a] = std::sqrt(q[a] / (ns * nz));
+  }
+  return latched(h);
+}
+
+int vlb_read_vorticity(vlb_run* h, double* u_dev, double* omega_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!u_dev || !omega_dev) return fail(h, VLB_EINVAL, "u and omega are required");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, lbm_read_fields(r, nullptr, u_dev));
+  HIP_OR_FAIL(h, diag_curl(r, u_dev, omega_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
   return latched(h);
 }
 

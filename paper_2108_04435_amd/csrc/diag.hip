@@ -1,0 +1,157 @@
+// Diagnostics of the coupled state (paper Sec. III.A, III.C, IV): the
+// vortex line length, in total and per slab along z (the line density the
+// paper follows in time and along the channel), and the vorticity of the
+// normal fluid.  (The velocity statistics of the mean flow and its
+// fluctuations are a lattice pass and live with the other lattice kernels.)
+//
+// Every sum runs in FP64 in a fixed order (per-thread strided sums, then a
+// fixed tree), so the results are bitwise reproducible.
+#include "vlb_internal.h"
+
+namespace vlb {
+
+namespace {
+
+// Segment j -> nxt[j] at the nearest periodic image; a separation of
+// exactly half the period is left alone.
+__device__ inline void segment(const double* __restrict__ pos, const int32_t* __restrict__ nxt,
+                               long long nc, const Geom& g, int j, double d[3], double& z0) {
+  const int k = nxt[j];
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a) {
+    const double p = pos[a * nc + j];
+    double x = pos[a * nc + k] - p;
+    if (!g.wall[a]) {
+      const double L = (double)n[a];
+      if (x > 0.5 * L)
+        x -= L;
+      else if (x < -0.5 * L)
+        x += L;
+    }
+    d[a] = x;
+    if (a == 2) z0 = p;
+  }
+}
+
+template <int B>
+__device__ inline double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = B / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Total length: one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_line_total(const double* __restrict__ pos,
+                                                     const int32_t* __restrict__ nxt,
+                                                     const int32_t* __restrict__ cnt, long long nc,
+                                                     Geom g, double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int n = cnt[0];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 1024) {
+    double d[3], z0;
+    segment(pos, nxt, nc, g, j, d, z0);
+    acc += sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  }
+  const double tot = block_sum<1024>(acc, red);
+  if (threadIdx.x == 0) out[0] = tot;
+}
+
+// Length inside slab z = [z - 1/2, z + 1/2) along z (periodic z wraps): one
+// block of 256 threads per slab walks every segment and adds the part of
+// its length in proportion to the overlap of its z extent with the slab
+// (its three periodic images on a periodic z axis); a segment with no z
+// extent belongs to the slab of its start point.
+__global__ __launch_bounds__(256) void k_line_slabs(const double* __restrict__ pos,
+                                                    const int32_t* __restrict__ nxt,
+                                                    const int32_t* __restrict__ cnt, long long nc,
+                                                    Geom g, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int z = blockIdx.x;
+  const int n = cnt[0];
+  const int nz = g.nz;
+  const bool periodic = !g.wall[2];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double d[3], a;
+    segment(pos, nxt, nc, g, j, d, a);
+    const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double b = a + d[2];
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    if (hi == lo) {
+      int k = (int)floor(a + 0.5);
+      k = periodic ? ((k % nz) + nz) % nz : min(max(k, 0), nz - 1);
+      if (k == z) acc += ell;
+      continue;
+    }
+    for (int img = periodic ? -1 : 0; img <= (periodic ? 1 : 0); ++img) {
+      const double s_lo = (double)z - 0.5 + (double)img * nz;
+      const double s_hi = s_lo + 1.0;
+      const double ov = fmax(0.0, fmin(hi, s_hi) - fmax(lo, s_lo));
+      acc += ell * ov / (hi - lo);
+    }
+  }
+  const double tot = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) out[z] = tot;
+}
+
+// Component comp of u at node (x, y, z) + s e_axis: periodic axes wrap,
+// beyond a wall the velocity is 0.
+__device__ inline double u_at(const double* __restrict__ u, const Geom& g, int comp, int x, int y,
+                              int z, int axis, int s) {
+  int p[3] = {x, y, z};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int v = p[axis] + s;
+  if (v < 0 || v >= n[axis]) {
+    if (g.wall[axis]) return 0.0;
+    v = v < 0 ? v + n[axis] : v - n[axis];
+  }
+  p[axis] = v;
+  return u[comp * g.cells + ((long long)p[2] * g.ny + p[1]) * g.nx + p[0]];
+}
+
+__device__ inline double ddx(const double* __restrict__ u, const Geom& g, int comp, int x, int y,
+                             int z, int axis) {
+  return 0.5 * (u_at(u, g, comp, x, y, z, axis, 1) - u_at(u, g, comp, x, y, z, axis, -1));
+}
+
+// omega = curl u by central differences, one thread per node.
+__global__ __launch_bounds__(256) void k_curl(const double* __restrict__ u, Geom g,
+                                              double* __restrict__ w) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  const double wx = ddx(u, g, 2, x, y, z, 1) - ddx(u, g, 1, x, y, z, 2);
+  const double wy = ddx(u, g, 0, x, y, z, 2) - ddx(u, g, 2, x, y, z, 0);
+  const double wz = ddx(u, g, 1, x, y, z, 0) - ddx(u, g, 0, x, y, z, 1);
+  w[c] = wx;
+  w[g.cells + c] = wy;
+  w[2 * g.cells + c] = wz;
+}
+
+}  // namespace
+
+hipError_t diag_line_length(Run& r, double* total, double* slabs) {
+  if (total)
+    hipLaunchKernelGGL(k_line_total, dim3(1), dim3(1024), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap,
+                       r.geom, total);
+  if (slabs)
+    hipLaunchKernelGGL(k_line_slabs, dim3(r.geom.nz), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt,
+                       r.ncap, r.geom, slabs);
+  return hipGetLastError();
+}
+
+hipError_t diag_curl(Run& r, const double* u, double* w) {
+  const int nb = (int)((r.cells + 255) / 256);
+  hipLaunchKernelGGL(k_curl, dim3(nb), dim3(256), 0, r.stream, u, r.geom, w);
+  return hipGetLastError();
+}
+
+}  // namespace vlb

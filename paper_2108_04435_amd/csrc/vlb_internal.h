@@ -324,6 +324,7 @@ struct Run {
   // update while the stages of this step still read ub (swapped at the
   // end of the step)
   double* Vs_next = nullptr;
+  double* diag = nullptr;      // diagnostics results (8 + 6 nz doubles)
   void* ub_next = nullptr;
   int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
   uint32_t* marked = nullptr;  // per sorted entry: the bin it marked (all ones: none)
@@ -425,6 +426,10 @@ hipError_t lbm_read_fields(Run& r, double* rho, double* u);
 hipError_t lbm_read_pops(Run& r, double* f);
 hipError_t lbm_read_force(Run& r, double* out);
 hipError_t lbm_moments(Run& r);
+hipError_t lbm_flow_stats(Run& r, double* out);
+
+hipError_t diag_line_length(Run& r, double* total, double* slabs);
+hipError_t diag_curl(Run& r, const double* u, double* w);
 
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r);

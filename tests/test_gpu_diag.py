@@ -1,0 +1,118 @@
+"""GPU parity of the diagnostics (vortex line length total and per z slab,
+normal-fluid velocity statistics, vorticity) against the oracle, through
+the C ABI, on the GPU's own state after coupled steps, at small sizes and
+at the full counterflow size; plus the empty and degenerate cases and
+bitwise reproducibility."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import diagnostics as dg
+from tests._cases import oracle_lattice, say, small_channel, small_periodic
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2108_04435_amd as vlb  # noqa: E402
+
+
+def _walled_box(precision):
+    dims = (16, 16, 20)
+    walls = (True, True, True)
+    lat = wl.lattice_preset(*dims, tau=0.8, walls=walls, precision=precision)
+    vor = wl.vortex_preset()
+    rho, u = wl.velocity_field(41, dims, (0.0, 0.0, 0.01), 2e-3)
+    pos, nxt = wl.random_rings(41, 4, 2.0, 4.0, dims, walls, 0.95)
+    return dict(name="box", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt, steps=4)
+
+
+CASES = {
+    "channel": lambda p: small_channel(precision=p),
+    "periodic": lambda p: small_periodic(precision=p),
+    "heater": lambda p: small_channel(precision=p, planes=True, seed=23),
+    "box": _walled_box,
+}
+
+
+def _check_state(run, cfg, tol):
+    lat = oracle_lattice(cfg["lattice"])
+    pos, nxt = run.read_filaments()
+    tot, slabs = run.line_length()
+    want_tot = dg.line_length(pos, nxt, lat)
+    want_slabs = dg.line_length_slabs(pos, nxt, lat)
+    say("line length", tot, want_tot)
+    assert abs(tot - want_tot) <= 1e-12 * max(1.0, want_tot)
+    np.testing.assert_allclose(slabs, want_slabs, rtol=0, atol=1e-12 * max(1.0, want_tot))
+    assert abs(slabs.sum() - tot) <= 1e-10 * max(1.0, tot)
+    _, u = run.read_fields()
+    st = run.flow_stats()
+    sm, sr, m, r = dg.flow_stats(u, lat)
+    for k, want in (("slice_mean", sm), ("slice_rms", sr), ("mean", m), ("rms", r)):
+        np.testing.assert_allclose(st[k], want, rtol=tol, atol=tol * 1e-3, err_msg=k)
+    ug, wg = run.read_vorticity()
+    np.testing.assert_array_equal(ug, u)
+    np.testing.assert_allclose(wg, dg.vorticity(u, lat), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
+def test_diagnostics_after_steps(case, precision):
+    cfg = CASES[case](precision)
+    say("diag", case, precision)
+    run = vlb.run_from_config(cfg)
+    run.step(4)
+    run.sync()
+    _check_state(run, cfg, 1e-10)
+    run.close()
+
+
+def test_diagnostics_fullsize_counterflow():
+    """The counterflow workload at its full size (64x64x256, ~1e4 points)
+    after two steps, in the capacity the bench uses."""
+    cfg = wl.config_counterflow(precision="f32")
+    n0 = cfg["pos"].shape[0]
+    say("diag fullsize", n0)
+    run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256, recon_cap=1 << 18)
+    run.step(2)
+    run.sync()
+    _check_state(run, cfg, 1e-10)
+    run.close()
+
+
+def test_diagnostics_empty_and_repeatable():
+    """No filaments: zero length everywhere; a uniform flow at rest has zero
+    fluctuation and zero vorticity; repeated calls are bitwise equal."""
+    lat = wl.lattice_preset(12, 10, 14, precision="f32")
+    vor = wl.vortex_preset()
+    say("diag empty")
+    run = vlb.Run(lat, vor, n_cap=8)
+    tot, slabs = run.line_length()
+    assert tot == 0.0 and not slabs.any()
+    st = run.flow_stats()
+    assert not st["rms"].any() and not st["slice_rms"].any() and not st["mean"].any()
+    _, w = run.read_vorticity()
+    assert not w.any()
+    cfg = small_channel(precision="f32", seed=29)
+    run2 = vlb.run_from_config(cfg)
+    run2.step(3)
+    a = run2.line_length(), run2.flow_stats()
+    b = run2.line_length(), run2.flow_stats()
+    assert a[0][0] == b[0][0]
+    np.testing.assert_array_equal(a[0][1], b[0][1])
+    for k in a[1]:
+        np.testing.assert_array_equal(a[1][k], b[1][k])
+    run.close()
+    run2.close()
+
+
+def test_line_length_rejects_two_null_outputs():
+    lat = wl.lattice_preset(8, 8, 8, precision="f64")
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=8)
+    say("diag null outputs")
+    assert run.lib.vlb_line_length(run.h, None, None) == vlb.VLB_EINVAL
+    assert b"NULL" in run.lib.vlb_last_error(run.h)
+    run.close()

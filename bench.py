@@ -191,6 +191,49 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def time_diagnostics(run, cells, precision, n_points, reps=10):
+    """Host-visible time of one call of each diagnostic at the final state
+    (median of reps calls; each call launches its kernels and synchronises
+    with its copy to the host), with the algorithmic bytes of the lattice
+    ones: the velocity statistics read the populations twice; the vorticity
+    reads them once, writes the velocity, reads it back and writes the curl."""
+    b = {"f64": 8, "f32": 4, "f16": 2}[precision]
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    import ctypes
+    import torch
+
+    u = torch.empty((3,) + run.shape, dtype=torch.float64, device=run.device)
+    w = torch.empty_like(u)
+    pu, pw = ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(w.data_ptr())
+
+    def vort():
+        if run.lib.vlb_read_vorticity(run.h, pu, pw) != 0:
+            raise RuntimeError("vlb_read_vorticity failed")
+
+    t_len = med(run.line_length)
+    t_st = med(run.flow_stats)
+    t_w = med(vort)
+    st_bytes = 2 * 19 * b * cells
+    w_bytes = (19 * b + 24 + 24 + 24) * cells
+    return {
+        "line_length": {"call_us": round(t_len * 1e6, 1), "points": int(n_points)},
+        "flow_stats": {"call_us": round(t_st * 1e6, 1), "bytes": st_bytes,
+                       "GBs": round(st_bytes / t_st / 1e9, 1)},
+        "vorticity": {"call_us": round(t_w * 1e6, 1), "bytes": w_bytes,
+                      "GBs": round(w_bytes / t_w / 1e9, 1),
+                      "note": "device outputs (u and omega stay in HBM)"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +323,7 @@ def main():
     pairs_iso = n_end * (n_end - 2)
     # the LBM update alone (advances the fluid; after the timed region)
     lbm_iso_ms = run.time_kernel(1, reps=20)
+    diagnostics = time_diagnostics(run, cells, lat["precision"], n_end)
 
     value = K / wall
     achieved = FLOPS_PER_PAIR * pairs_iso / (bs_iso_ms * 1e-3) / 1e12
@@ -342,6 +386,7 @@ def main():
                        "algorithmic_GBs": round(lbm_bytes / (lbm_iso_ms * 1e-3) / 1e9, 1),
                        "note": "20 launches back to back; this lattice fits the 256 MB last-level cache"},
         "roofline": roofline,
+        "diagnostics": diagnostics,
     }
     run.close()
     del run

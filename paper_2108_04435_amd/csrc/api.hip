@@ -118,7 +118,8 @@ size_t layout(Run& r, char* base) {
   r.force = B.take(3 * cells * fe);
   r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
   r.Vs_next = (double*)B.take(r.geom.nz * sizeof(double));
-  r.diag = (double*)B.take((8 + 6 * (size_t)r.geom.nz) * sizeof(double));
+  r.diag = (double*)B.take((8 + (size_t)kSlabChunks * r.geom.nz) * sizeof(double));
+  r.seg = (double*)B.take(3 * (size_t)nc * sizeof(double));
   r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
   double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage, &r.sfrac};
   for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
@@ -687,10 +688,17 @@ int vlb_line_length(vlb_run* h, double* total, double* per_slab) {
   HIP_OR_FAIL(h, diag_line_length(r, total ? r.diag : nullptr, per_slab ? r.diag + 8 : nullptr));
   if (total)
     HIP_OR_FAIL(h, hipMemcpyAsync(total, r.diag, sizeof(double), hipMemcpyDeviceToHost, r.stream));
+  std::vector<double> part(per_slab ? (size_t)kSlabChunks * nz : 0);
   if (per_slab)
-    HIP_OR_FAIL(h, hipMemcpyAsync(per_slab, r.diag + 8, nz * sizeof(double), hipMemcpyDeviceToHost,
-                                  r.stream));
+    HIP_OR_FAIL(h, hipMemcpyAsync(part.data(), r.diag + 8, part.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, r.stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  if (per_slab)  // the chunks' parts of each slab, added in chunk order
+    for (int z = 0; z < nz; ++z) {
+      double t = 0.0;
+      for (int c = 0; c < kSlabChunks; ++c) t += part[(size_t)c * nz + z];
+      per_slab[z] = t;
+    }
   return latched(h);
 }
 

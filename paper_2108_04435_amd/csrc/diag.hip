@@ -45,30 +45,43 @@ __device__ inline double block_sum(double v, double* red) {
   return red[0];
 }
 
+// Per segment j (one thread each): the ends of its z extent, lo and hi
+// (unwrapped: s_j and s_j + d at the nearest image), and its length.
+__global__ __launch_bounds__(256) void k_line_segs(const double* __restrict__ pos,
+                                                   const int32_t* __restrict__ nxt,
+                                                   const int32_t* __restrict__ cnt, long long nc,
+                                                   Geom g, double* __restrict__ seg) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt[0]) return;
+  double d[3], a;
+  segment(pos, nxt, nc, g, j, d, a);
+  const double b = a + d[2];
+  seg[j] = fmin(a, b);
+  seg[nc + j] = fmax(a, b);
+  seg[2 * nc + j] = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
 // Total length: one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_line_total(const double* __restrict__ pos,
-                                                     const int32_t* __restrict__ nxt,
+__global__ __launch_bounds__(1024) void k_line_total(const double* __restrict__ seg,
                                                      const int32_t* __restrict__ cnt, long long nc,
-                                                     Geom g, double* __restrict__ out) {
+                                                     double* __restrict__ out) {
   __shared__ double red[1024];
   const int n = cnt[0];
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += 1024) {
-    double d[3], z0;
-    segment(pos, nxt, nc, g, j, d, z0);
-    acc += sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  }
+#pragma unroll 8
+  for (int j = threadIdx.x; j < n; j += 1024) acc += seg[2 * nc + j];
   const double tot = block_sum<1024>(acc, red);
   if (threadIdx.x == 0) out[0] = tot;
 }
 
-// Length inside slab z = [z - 1/2, z + 1/2) along z (periodic z wraps): one
-// block of 256 threads per slab walks every segment and adds the part of
-// its length in proportion to the overlap of its z extent with the slab
-// (its three periodic images on a periodic z axis); a segment with no z
-// extent belongs to the slab of its start point.
-__global__ __launch_bounds__(256) void k_line_slabs(const double* __restrict__ pos,
-                                                    const int32_t* __restrict__ nxt,
+// Length inside slab z = [z - 1/2, z + 1/2) along z (periodic z wraps): the
+// block (z, c) walks chunk c of the segments (chunks of the segment range,
+// kSlabChunks of them) and adds the part of each length in proportion to
+// the overlap of its z extent with the slab (its three periodic images on a
+// periodic z axis); a segment with no z extent belongs to the slab of its
+// start point.  out[c * nz + z] receives the chunk's part; the caller adds
+// the chunks in order.
+__global__ __launch_bounds__(256) void k_line_slabs(const double* __restrict__ seg,
                                                     const int32_t* __restrict__ cnt, long long nc,
                                                     Geom g, double* __restrict__ out) {
   __shared__ double red[256];
@@ -76,28 +89,26 @@ __global__ __launch_bounds__(256) void k_line_slabs(const double* __restrict__ p
   const int n = cnt[0];
   const int nz = g.nz;
   const bool periodic = !g.wall[2];
+  const int per = (n + kSlabChunks - 1) / kSlabChunks;
+  const int j0 = blockIdx.y * per, j1 = min(n, j0 + per);
   double acc = 0.0;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    double d[3], a;
-    segment(pos, nxt, nc, g, j, d, a);
-    const double ell = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double b = a + d[2];
-    const double lo = fmin(a, b), hi = fmax(a, b);
+  for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+    const double lo = seg[j], hi = seg[nc + j], ell = seg[2 * nc + j];
     if (hi == lo) {
-      int k = (int)floor(a + 0.5);
+      int k = (int)floor(lo + 0.5);
       k = periodic ? ((k % nz) + nz) % nz : min(max(k, 0), nz - 1);
       if (k == z) acc += ell;
-      continue;
-    }
-    for (int img = periodic ? -1 : 0; img <= (periodic ? 1 : 0); ++img) {
-      const double s_lo = (double)z - 0.5 + (double)img * nz;
-      const double s_hi = s_lo + 1.0;
-      const double ov = fmax(0.0, fmin(hi, s_hi) - fmax(lo, s_lo));
-      acc += ell * ov / (hi - lo);
+    } else {
+      for (int img = periodic ? -1 : 0; img <= (periodic ? 1 : 0); ++img) {
+        const double s_lo = (double)z - 0.5 + (double)img * nz;
+        const double s_hi = s_lo + 1.0;
+        const double ov = fmin(hi, s_hi) - fmax(lo, s_lo);
+        if (ov > 0.0) acc += ell * ov / (hi - lo);  // (no overlap adds nothing)
+      }
     }
   }
   const double tot = block_sum<256>(acc, red);
-  if (threadIdx.x == 0) out[z] = tot;
+  if (threadIdx.x == 0) out[(long long)blockIdx.y * nz + z] = tot;
 }
 
 // Component comp of u at node (x, y, z) + s e_axis: periodic axes wrap,
@@ -139,12 +150,14 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ u, Geom
 }  // namespace
 
 hipError_t diag_line_length(Run& r, double* total, double* slabs) {
+  const int nb = (int)((r.ncap + 255) / 256);
+  hipLaunchKernelGGL(k_line_segs, dim3(nb), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap,
+                     r.geom, r.seg);
   if (total)
-    hipLaunchKernelGGL(k_line_total, dim3(1), dim3(1024), 0, r.stream, r.pos, r.nxt, r.cnt, r.ncap,
-                       r.geom, total);
+    hipLaunchKernelGGL(k_line_total, dim3(1), dim3(1024), 0, r.stream, r.seg, r.cnt, r.ncap, total);
   if (slabs)
-    hipLaunchKernelGGL(k_line_slabs, dim3(r.geom.nz), dim3(256), 0, r.stream, r.pos, r.nxt, r.cnt,
-                       r.ncap, r.geom, slabs);
+    hipLaunchKernelGGL(k_line_slabs, dim3(r.geom.nz, kSlabChunks), dim3(256), 0, r.stream, r.seg,
+                       r.cnt, r.ncap, r.geom, slabs);
   return hipGetLastError();
 }
 

@@ -244,13 +244,13 @@ __global__ __launch_bounds__(1024) void k_moments(const S* __restrict__ M, Geom 
   if (tid == 0) Vs[z] = scale * red[0];
 }
 
-// Sum of v[0..2] over the 256 threads of a block in a fixed tree; every
+// Sum of v[0..2] over the 1024 threads of a block in a fixed tree; every
 // thread returns the three totals.
-__device__ inline void block_sum3_256(double v[3], double (*red)[256]) {
+__device__ inline void block_sum3_1024(double v[3], double (*red)[1024]) {
   const int t = threadIdx.x;
   for (int a = 0; a < 3; ++a) red[a][t] = v[a];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if (t < s)
       for (int a = 0; a < 3; ++a) red[a][t] += red[a][t + s];
     __syncthreads();
@@ -260,33 +260,33 @@ __device__ inline void block_sum3_256(double v[3], double (*red)[256]) {
 }
 
 // Statistics of the bare velocity over each z slice (diagnostics of the
-// mean flow and its fluctuations, Sec. III.C): one block of 256 threads
+// mean flow and its fluctuations, Sec. III.C): one block of 1024 threads
 // per slice; the slice mean of each component, then the sum of the squared
 // deviations from that mean (the nodes' velocities are recomputed from the
 // populations in the second pass).  Each thread adds its nodes in order,
 // the block adds the threads in a fixed tree.  out[6 z + a] = mean of
 // component a, out[6 z + 3 + a] = sum of squared deviations.
 template <class S>
-__global__ __launch_bounds__(256) void k_flow_stats(const S* __restrict__ M, Geom g, int parity,
-                                                   double* __restrict__ out) {
-  __shared__ double red[3][256];
+__global__ __launch_bounds__(1024) void k_flow_stats(const S* __restrict__ M, Geom g, int parity,
+                                                    double* __restrict__ out) {
+  __shared__ double red[3][1024];
   const int z = blockIdx.x;
   const long long ns = (long long)g.nx * g.ny;
   double v[3] = {0.0, 0.0, 0.0};
-  for (long long k = threadIdx.x; k < ns; k += 256) {
+  for (long long k = threadIdx.x; k < ns; k += 1024) {
     double rho, u[3];
     node_rho_u<S>(M, g, parity, (int)(k % g.nx), (int)(k / g.nx), z, rho, u[0], u[1], u[2]);
     for (int a = 0; a < 3; ++a) v[a] += u[a];
   }
-  block_sum3_256(v, red);
+  block_sum3_1024(v, red);
   const double m[3] = {v[0] / (double)ns, v[1] / (double)ns, v[2] / (double)ns};
   double q[3] = {0.0, 0.0, 0.0};
-  for (long long k = threadIdx.x; k < ns; k += 256) {
+  for (long long k = threadIdx.x; k < ns; k += 1024) {
     double rho, u[3];
     node_rho_u<S>(M, g, parity, (int)(k % g.nx), (int)(k / g.nx), z, rho, u[0], u[1], u[2]);
     for (int a = 0; a < 3; ++a) q[a] += (u[a] - m[a]) * (u[a] - m[a]);
   }
-  block_sum3_256(q, red);
+  block_sum3_1024(q, red);
   if (threadIdx.x == 0)
     for (int a = 0; a < 3; ++a) {
       out[6 * z + a] = m[a];
@@ -400,13 +400,13 @@ hipError_t lbm_flow_stats(Run& r, double* out) {
   const int nz = r.geom.nz;
   switch (r.prec) {
     case VLB_F64:
-      hipLaunchKernelGGL(k_flow_stats<double>, dim3(nz), dim3(256), 0, r.stream, (const double*)r.pops, r.geom, r.parity, out);
+      hipLaunchKernelGGL(k_flow_stats<double>, dim3(nz), dim3(1024), 0, r.stream, (const double*)r.pops, r.geom, r.parity, out);
       break;
     case VLB_F32:
-      hipLaunchKernelGGL(k_flow_stats<float>, dim3(nz), dim3(256), 0, r.stream, (const float*)r.pops, r.geom, r.parity, out);
+      hipLaunchKernelGGL(k_flow_stats<float>, dim3(nz), dim3(1024), 0, r.stream, (const float*)r.pops, r.geom, r.parity, out);
       break;
     default:
-      hipLaunchKernelGGL(k_flow_stats<__half>, dim3(nz), dim3(256), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, out);
+      hipLaunchKernelGGL(k_flow_stats<__half>, dim3(nz), dim3(1024), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, out);
       break;
   }
   return hipGetLastError();

@@ -324,7 +324,8 @@ struct Run {
   // update while the stages of this step still read ub (swapped at the
   // end of the step)
   double* Vs_next = nullptr;
-  double* diag = nullptr;      // diagnostics results (8 + 6 nz doubles)
+  double* diag = nullptr;      // diagnostics results (8 + kSlabChunks nz doubles)
+  double* seg = nullptr;       // diagnostics: z extent and length per segment (3 n_cap doubles)
   void* ub_next = nullptr;
   int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
   uint32_t* marked = nullptr;  // per sorted entry: the bin it marked (all ones: none)
@@ -428,6 +429,8 @@ hipError_t lbm_read_force(Run& r, double* out);
 hipError_t lbm_moments(Run& r);
 hipError_t lbm_flow_stats(Run& r, double* out);
 
+// The per-slab line length is added over this many chunks of the segments.
+constexpr int kSlabChunks = 8;
 hipError_t diag_line_length(Run& r, double* total, double* slabs);
 hipError_t diag_curl(Run& r, const double* u, double* w);
 

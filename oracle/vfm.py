@@ -34,6 +34,11 @@ class VortexParams:
     coupling: bool = True       # False: prescribed normal fluid, no back-reaction
     mass_balance: bool = False  # superflow V_s(z) from Eq. (mass cons)
     vs_applied: tuple = (0.0, 0.0, 0.0)  # externally applied v_s,a (Sec. II.A)
+    # mutual-friction coefficients varying along z (Sec. IV: temperature
+    # dependent alpha, alpha' over the channel; reading D4): nz slice values
+    # each, or None for the constants above
+    alpha_z: tuple = None
+    alpha_p_z: tuple = None
 
 
 # ---------------------------------------------------------------- geometry
@@ -277,6 +282,30 @@ def superflow_at(Vs, z, nz):
     return (1.0 - fz) * Vs[np.mod(iz, nz)] + fz * Vs[np.mod(iz + 1, nz)]
 
 
+def friction_at(vp: VortexParams, z, lat: Lattice):
+    """alpha and alpha' at points of height z (reading D4): the constants, or
+    the slice profiles interpolated linearly between the slices floor(z) and
+    floor(z) + 1 (periodic z wraps; on a wall z axis the end slices' values
+    extend to the walls).  Returns two scalars or two (n, 1) arrays."""
+    if vp.alpha_z is None:
+        return vp.alpha, vp.alpha_p
+    nz = lat.nz
+    z = np.asarray(z, dtype=np.float64)
+    iz = np.floor(z)
+    t = z - iz
+    i0 = iz.astype(np.int64)
+    i1 = i0 + 1
+    if lat.walls[2]:
+        i0, i1 = np.clip(i0, 0, nz - 1), np.clip(i1, 0, nz - 1)
+    else:
+        i0, i1 = np.mod(i0, nz), np.mod(i1, nz)
+    out = []
+    for prof in (vp.alpha_z, vp.alpha_p_z):
+        p = np.asarray(prof, dtype=np.float64)
+        out.append(((1.0 - t) * p[i0] + t * p[i1])[:, None])
+    return out[0], out[1]
+
+
 def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_force=False):
     """Everything the equation of motion needs at the current positions:
     v_s = non-local BS + LIA + applied + mass-balance superflow, v_n from the
@@ -288,7 +317,8 @@ def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_fo
     if Vs is not None:
         vs[:, 2] = vs[:, 2] + superflow_at(Vs, pos[:, 2], lat.nz)
     vn = interpolate(ub, pos, lat)
-    sdot = schwarz_velocity(vs, vn, geo["sp"], vp.alpha, vp.alpha_p)
+    alpha, alpha_p = friction_at(vp, pos[:, 2], lat)
+    sdot = schwarz_velocity(vs, vn, geo["sp"], alpha, alpha_p)
     out = dict(vs=vs, vn=vn, sdot=sdot, geo=geo)
     if want_force:
         dxi = 0.5 * (geo["lp"] + geo["lm"])

@@ -253,3 +253,45 @@ def test_ring_one_step_one_way():
     dz = (s1[:, 2] - pos[:, 2]).mean()
     assert dz == pytest.approx(0.99 * V, rel=2e-3)
     assert 8.0 - R1 == pytest.approx(0.2 * V, rel=2e-3)
+
+
+def test_friction_profile_lookup():
+    """alpha(z), alpha'(z) between slices (reading D4): linear between
+    floor(z) and floor(z) + 1, periodic wrap, ends extended on a wall axis."""
+    nz = 6
+    prof = np.array([0.10, 0.30, 0.20, 0.25, 0.15, 0.05])
+    vp = VortexParams(alpha_z=tuple(prof), alpha_p_z=tuple(prof / 10))
+    lat = Lattice(8, 8, nz)
+    z = np.array([1.25, 5.5, 0.0, 3.0])
+    a, ap = vfm.friction_at(vp, z, lat)
+    want = [0.75 * prof[1] + 0.25 * prof[2], 0.5 * prof[5] + 0.5 * prof[0], prof[0], prof[3]]
+    np.testing.assert_allclose(a[:, 0], want, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ap[:, 0], np.array(want) / 10, rtol=0, atol=1e-16)
+    latw = Lattice(8, 8, nz, walls=(False, False, True))
+    a, _ = vfm.friction_at(vp, np.array([-0.3, nz - 0.7, 4.5]), latw)
+    np.testing.assert_allclose(a[:, 0], [prof[0], prof[-1], 0.5 * prof[4] + 0.5 * prof[5]],
+                               rtol=0, atol=1e-15)
+
+
+def test_friction_profile_at_constant_height():
+    """A ring in the plane z = z0 sees alpha(z0) at every point: with a
+    profile linear in z its line velocity is the one of the constants
+    alpha(z0), alpha'(z0); a uniform profile gives the constant result."""
+    lat, pos, nxt, prv = _ring_state(64, center=(32.0, 32.0, 32.37))
+    z0 = pos[0, 2]
+    assert abs(z0 - 32.37) < 1e-12
+    nz = lat.nz
+    zs = np.arange(nz, dtype=float)
+    prof_a = 0.1 + 0.004 * zs
+    prof_p = 0.02 - 0.0003 * zs
+    ub = np.zeros((3,) + lat.shape)
+    ub[2] = 0.01
+    vp_prof = VortexParams(alpha_z=tuple(prof_a), alpha_p_z=tuple(prof_p))
+    vp_const = VortexParams(alpha=0.1 + 0.004 * z0, alpha_p=0.02 - 0.0003 * z0)
+    got = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp_prof)["sdot"]
+    want = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp_const)["sdot"]
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-17)
+    vp_uni = VortexParams(alpha_z=(0.2,) * nz, alpha_p_z=(0.01,) * nz)
+    got = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp_uni)["sdot"]
+    want = vfm.line_velocity(pos, nxt, prv, ub, None, lat, VortexParams())["sdot"]
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-18)

@@ -180,6 +180,19 @@ int vlb_eval_line_velocity(vlb_run* run, double* vs_host, double* vn_host,
  * removed with small loops.                                                */
 int vlb_apply_topology(vlb_run* run, int64_t* stats_host);
 
+/* Mutual-friction coefficients varying along the channel (Sec. IV: alpha
+ * and alpha' depend on the temperature, which varies along the channel).
+ * alpha_z_host and alpha_p_z_host (nz doubles each, finite) replace the
+ * constants alpha and alpha' of the vortex descriptor: at a point of height
+ * z each is interpolated linearly between the slices floor(z) and
+ * floor(z) + 1 (a periodic z axis wraps; on a wall z axis the end slices'
+ * values extend to the walls).  Both NULL restores the constants; one NULL
+ * is VLB_EINVAL.  Applies to every later step, graph launch and
+ * vlb_eval_line_velocity (also of graphs captured before the call).
+ * Synchronises the run's stream.                                           */
+int vlb_set_friction_profile(vlb_run* run, const double* alpha_z_host,
+                             const double* alpha_p_z_host);
+
 /* Vortex line length of the current filaments (Sec. III.C and IV: the line
  * density the paper follows in time and along the channel).  *total_host
  * receives the sum of the segment lengths |s_next - s| (nearest periodic

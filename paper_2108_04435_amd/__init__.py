@@ -31,7 +31,8 @@ PRECISION = {"f64": 0, "f32": 1, "f16": 2}
 SYMBOLS = [
     "vlb_query_footprint", "vlb_create_lattice", "vlb_write_fields", "vlb_seed_vortices",
     "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
-    "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology", "vlb_line_length",
+    "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology",
+    "vlb_set_friction_profile", "vlb_line_length",
     "vlb_flow_stats", "vlb_read_vorticity", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
     "vlb_graph_launch", "vlb_graph_destroy", "vlb_destroy", "vlb_last_error",
@@ -100,6 +101,7 @@ def load_library(path=None):
     lib.vlb_read_fields.argtypes = [vp, vp, vp]
     lib.vlb_read_populations.argtypes = [vp, vp]
     lib.vlb_read_force.argtypes = [vp, vp]
+    lib.vlb_set_friction_profile.argtypes = [vp, vp, vp]
     lib.vlb_line_length.argtypes = [vp, vp, vp]
     lib.vlb_flow_stats.argtypes = [vp, vp, vp, vp, vp]
     lib.vlb_read_vorticity.argtypes = [vp, vp, vp]
@@ -268,6 +270,19 @@ class Run:
         self._check(self.lib.vlb_read_force(self.h, ctypes.c_void_p(F.data_ptr())))
         return F.cpu().numpy()
 
+    def set_friction_profile(self, alpha_z=None, alpha_p_z=None):
+        """alpha(z), alpha'(z) slice profiles (nz each), or None to restore
+        the constants."""
+        if alpha_z is None and alpha_p_z is None:
+            self._check(self.lib.vlb_set_friction_profile(self.h, None, None))
+            return
+        a = np.ascontiguousarray(alpha_z, dtype=np.float64).reshape(-1)
+        b = np.ascontiguousarray(alpha_p_z, dtype=np.float64).reshape(-1)
+        if a.shape[0] != self.ld.nz or b.shape[0] != self.ld.nz:
+            raise ValueError("friction profiles need nz values each")
+        self._check(self.lib.vlb_set_friction_profile(self.h, a.ctypes.data_as(ctypes.c_void_p),
+                                                      b.ctypes.data_as(ctypes.c_void_p)))
+
     def line_length(self):
         """(total line length, length per z slab)."""
         tot = ctypes.c_double(0.0)
@@ -357,4 +372,6 @@ def run_from_config(cfg: dict, n_cap=None, device=0, recon_cap=1 << 16):
     r.write_fields(cfg["rho"], cfg["u"])
     if n:
         r.seed(cfg["pos"], cfg["nxt"])
+    if cfg["vortex"].get("alpha_z") is not None:
+        r.set_friction_profile(cfg["vortex"]["alpha_z"], cfg["vortex"]["alpha_p_z"])
     return r

@@ -120,6 +120,7 @@ size_t layout(Run& r, char* base) {
   r.Vs_next = (double*)B.take(r.geom.nz * sizeof(double));
   r.diag = (double*)B.take((8 + (size_t)kSlabChunks * r.geom.nz) * sizeof(double));
   r.seg = (double*)B.take(3 * (size_t)nc * sizeof(double));
+  r.fric = (double*)B.take((2 * (size_t)r.geom.nz + 1) * sizeof(double));
   r.touched = (int32_t*)B.take(8 * nc * sizeof(int32_t));
   double** dbufs[] = {&r.pos, &r.ya, &r.yb, &r.ksum, &r.vs1, &r.vn1, &r.sd1, &r.gpt, &r.pos_t, &r.stage, &r.sfrac};
   for (double** p : dbufs) *p = (double*)B.take(3 * nc * sizeof(double));
@@ -404,6 +405,8 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, 
   // populations at rest, no force, no points
   if (e == hipSuccess) e = hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.cnt, 0, 32 * sizeof(int32_t), r.stream);
+  // no friction profiles: the constants apply
+  if (e == hipSuccess) e = hipMemsetAsync(r.fric, 0, (2 * (size_t)r.geom.nz + 1) * sizeof(double), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.pops, 0, 19 * r.cells * elt_size(r.prec), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.bins, 0xFF, (size_t)r.nbins_table * sizeof(int32_t), r.stream);
   if (e == hipSuccess) e = hipMemsetAsync(r.marked, 0xFF, (size_t)r.ncap * sizeof(uint32_t), r.stream);
@@ -678,6 +681,30 @@ int vlb_apply_topology(vlb_run* h, int64_t* stats) {
     stats[3] = c[5];
   }
   return latched(h);
+}
+
+int vlb_set_friction_profile(vlb_run* h, const double* alpha_z, const double* alpha_p_z) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if ((alpha_z == nullptr) != (alpha_p_z == nullptr))
+    return fail(h, VLB_EINVAL, "give both profiles or neither");
+  Run& r = h->r;
+  const int nz = r.geom.nz;
+  std::vector<double> buf(2 * (size_t)nz + 1, 0.0);
+  if (alpha_z) {
+    for (int z = 0; z < nz; ++z) {
+      if (!std::isfinite(alpha_z[z]) || !std::isfinite(alpha_p_z[z]))
+        return fail(h, VLB_EINVAL, "non-finite friction coefficient");
+      buf[z] = alpha_z[z];
+      buf[nz + z] = alpha_p_z[z];
+    }
+    buf[2 * (size_t)nz] = 1.0;
+  }
+  // ordered after the work already on the run's stream; later steps (and
+  // graph launches) read the new values
+  HIP_OR_FAIL(h, hipMemcpyAsync(r.fric, buf.data(), buf.size() * sizeof(double),
+                                hipMemcpyHostToDevice, r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  return VLB_OK;
 }
 
 int vlb_line_length(vlb_run* h, double* total, double* per_slab) {

@@ -77,6 +77,10 @@ struct FinArgs {
   double nl_scale;    // kappa / (4 pi) times the grid step when the sum ran in grid units
   double ln2_ea;      // ln(2 / (e^C a))
   double alpha, alpha_p;
+  // mutual-friction profiles along z: alpha at [0, nz), alpha' at
+  // [nz, 2 nz), and at [2 nz] 1.0 when they replace the constants (read at
+  // run time, so that a captured graph follows the current setting)
+  const double* fric;
   double rs_rn;
   double vs_app[3];
   double* vs1;
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   __shared__ double red[kFinWaves - 1][3][kFinPts];  // chunk sums of waves 1..kFinWaves-1
   __shared__ double s_vn[3][kFinPts];    // wave 1: normal-fluid velocity
   __shared__ double s_geo[8][kFinPts];   // wave 2: s' (3), LIA (3), l+, l-
-  __shared__ double s_rk[7][kFinPts];    // wave 3: s^n (3), ksum (3), superflow
+  __shared__ double s_rk[9][kFinPts];    // wave 3: s^n (3), ksum (3), superflow, alpha, alpha'
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int j = blockIdx.x * kFinPts + lane;
   const int n = A.cnt[0];
@@ -254,6 +258,26 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
       i1 = ((i1 % g.nz) + g.nz) % g.nz;
       s_rk[6][lane] = (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];
     }
+    // mutual-friction coefficients at the point's height: the constants,
+    // or the slice profiles linear between floor(z) and floor(z) + 1
+    // (periodic z wraps; a wall z axis extends its end values)
+    double al = A.alpha, alp = A.alpha_p;
+    if (A.fric[2 * g.nz] != 0.0) {
+      const double pz = A.Y[2 * nc + j];
+      const double t = pz - floor(pz);
+      int i0 = ifloor_safe(pz), i1 = i0 + 1;
+      if (g.wall[2]) {
+        i0 = min(max(i0, 0), g.nz - 1);
+        i1 = min(max(i1, 0), g.nz - 1);
+      } else {
+        i0 = ((i0 % g.nz) + g.nz) % g.nz;
+        i1 = ((i1 % g.nz) + g.nz) % g.nz;
+      }
+      al = (1.0 - t) * A.fric[i0] + t * A.fric[i1];
+      alp = (1.0 - t) * A.fric[g.nz + i0] + t * A.fric[g.nz + i1];
+    }
+    s_rk[7][lane] = al;
+    s_rk[8][lane] = alp;
   }
 
   // non-local Biot-Savart: chunk partials added in a fixed order
@@ -310,8 +334,9 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
                          sp[0] * w[1] - sp[1] * w[0]};
   const double ssw[3] = {sp[1] * sxw[2] - sp[2] * sxw[1], sp[2] * sxw[0] - sp[0] * sxw[2],
                          sp[0] * sxw[1] - sp[1] * sxw[0]};
+  const double al = s_rk[7][lane], alp = s_rk[8][lane];
   double sd[3];
-  for (int a = 0; a < 3; ++a) sd[a] = vs[a] + A.alpha * sxw[a] - A.alpha_p * ssw[a];
+  for (int a = 0; a < 3; ++a) sd[a] = vs[a] + al * sxw[a] - alp * ssw[a];
   if (!(isfinite(sd[0]) && isfinite(sd[1]) && isfinite(sd[2])))
     atomicOr(&A.cnt[7], kFlagNumeric);
 
@@ -540,6 +565,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.ln2_ea = log(2.0 / (exp(r.vor.core_c) * r.vor.core_a));
   A.alpha = r.vor.alpha;
   A.alpha_p = r.vor.alpha_p;
+  A.fric = r.fric;
   A.rs_rn = r.vor.rho_s_over_rho_n;
   for (int a = 0; a < 3; ++a) A.vs_app[a] = r.vor.vs_applied[a];
   A.vs1 = r.vs1;

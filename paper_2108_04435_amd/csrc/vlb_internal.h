@@ -326,6 +326,7 @@ struct Run {
   double* Vs_next = nullptr;
   double* diag = nullptr;      // diagnostics results (8 + kSlabChunks nz doubles)
   double* seg = nullptr;       // diagnostics: z extent and length per segment (3 n_cap doubles)
+  double* fric = nullptr;      // alpha(z), alpha'(z) profiles and their on flag (2 nz + 1 doubles)
   void* ub_next = nullptr;
   int32_t* bins = nullptr;     // spreading: dense bin -> first sorted entry (-1 = empty)
   uint32_t* marked = nullptr;  // per sorted entry: the bin it marked (all ones: none)

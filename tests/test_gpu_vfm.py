@@ -466,3 +466,93 @@ def test_graph_rejects_seeding_after_lattice_only_capture():
         run.step(2)
         run.sync()
         run.close()
+
+
+def _with_friction_profile(cfg):
+    nz = cfg["lattice"]["nz"]
+    z = np.arange(nz)
+    vor = dict(cfg["vortex"])
+    vor["alpha_z"] = tuple(0.2 + 0.08 * np.sin(2 * np.pi * z / nz))
+    vor["alpha_p_z"] = tuple(0.01 + 0.006 * np.cos(2 * np.pi * z / nz))
+    return dict(cfg, vortex=vor)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_friction_profile_line_velocity(precision):
+    """alpha(z), alpha'(z) profiles: the line velocity and force of the
+    first stage against the oracle."""
+    cfg = _with_friction_profile(CASES["channel"](precision))
+    say("friction profile eval", precision)
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    ref, F_o, _ = _oracle_eval(cfg)
+    for k in ("vs", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= TOL[precision], (k, err)
+    run.close()
+
+
+@pytest.mark.parametrize("case", ["channel", "periodic"])
+def test_friction_profile_coupled_f64(case):
+    cfg = _with_friction_profile(CASES[case]("f64"))
+    steps = 8
+    say("friction profile coupled", case)
+    run = vlb.run_from_config(cfg)
+    run.step(steps)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    assert vp.alpha_z is not None
+    for _ in range(steps):
+        st = coupled.coupled_step(st, lat, vp)
+    pos_g, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    assert np.abs(vfm.min_image(pos_g - st.pos, lat)).max() < 1e-10
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) < 1e-10
+    run.close()
+
+
+def test_friction_profile_reset_and_graph():
+    """Restoring the constants gives bitwise the run that never had a
+    profile; a graph captured before the profile was set follows it."""
+    cfg = small_channel(precision="f32", seed=30)
+    prof = _with_friction_profile(cfg)["vortex"]
+    say("friction profile reset / graph")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = vlb.run_from_config(cfg)
+        b = vlb.run_from_config(cfg)
+        b.set_friction_profile(prof["alpha_z"], prof["alpha_p_z"])
+        b.set_friction_profile(None, None)
+        a.step(4)
+        b.step(4)
+        for x, y in zip(_final_state(a), _final_state(b)):
+            np.testing.assert_array_equal(x, y)
+        g = vlb.run_from_config(cfg)
+        d = vlb.run_from_config(cfg)
+        g.graph(2)
+        g.set_friction_profile(prof["alpha_z"], prof["alpha_p_z"])
+        d.set_friction_profile(prof["alpha_z"], prof["alpha_p_z"])
+        g.step_graph(2)
+        d.step(2)
+        g.sync()
+        d.sync()
+        for x, y in zip(_final_state(g), _final_state(d)):
+            np.testing.assert_array_equal(x, y)
+        # and the profile changes the result
+        a2 = vlb.run_from_config(cfg)
+        a2.step(2)
+        a2.sync()
+        assert not np.array_equal(_final_state(a2)[0], _final_state(d)[0])
+        with pytest.raises(ValueError):
+            a.set_friction_profile(prof["alpha_z"][:-1], prof["alpha_p_z"][:-1])
+        one = np.zeros(1)
+        assert a.lib.vlb_set_friction_profile(a.h, None, one.ctypes.data) == vlb.VLB_EINVAL
+        bad = np.array(prof["alpha_z"])
+        bad[3] = np.nan
+        with pytest.raises(vlb.VlbError):
+            a.set_friction_profile(bad, prof["alpha_p_z"])
+        for r in (a, b, g, d, a2):
+            r.close()

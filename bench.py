@@ -97,7 +97,8 @@ def cpu_baseline(cfg, n_evals=2):
     lat = Lattice(L["nx"], L["ny"], L["nz"], tau=L["tau"], walls=tuple(L["walls"]),
                   plane_lo=L["plane_lo"], plane_hi=L["plane_hi"], plane_u=tuple(L["plane_u"]),
                   body_force=tuple(L["body_force"]))
-    vp = VortexParams(**{k: cfg["vortex"][k] for k in VortexParams.__dataclass_fields__})
+    vp = VortexParams(**{k: cfg["vortex"][k] for k in VortexParams.__dataclass_fields__
+                         if k in cfg["vortex"]})
     st = coupled.make_state(cfg["rho"], cfg["u"], cfg["pos"], cfg["nxt"], lat)
     n = st.pos.shape[0]
     t0 = time.perf_counter()

@@ -39,6 +39,9 @@ class VortexParams:
     # each, or None for the constants above
     alpha_z: tuple = None
     alpha_p_z: tuple = None
+    # reaction on the normal fluid: 0 = Magnus balance (reading R1),
+    # 1 = the printed Eq. (f) taken literally (for ablation)
+    force_model: int = 0
 
 
 # ---------------------------------------------------------------- geometry
@@ -270,8 +273,12 @@ def mutual_friction_force(sdot, vs, sp, dxi, vp: VortexParams):
     printed relation equates f/(rho_s kappa) with the velocity terms of the
     equation of motion, read as the Magnus balance, reading R1):
       g_j = (rho_s/rho_n) kappa  s' x (ds/dt - v_s)  dxi_j,
-    with dxi_j = (l+ + l-)/2 the line length carried by point j (R8)."""
-    return vp.rho_s_over_rho_n * vp.kappa * cross(sp, sdot - vs) * dxi[:, None]
+    with dxi_j = (l+ + l-)/2 the line length carried by point j (R8).  With
+    force_model = 1 the printed relation is taken literally instead: the
+    force per length is rho_s kappa times the velocity terms themselves,
+      g_j = (rho_s/rho_n) kappa  (ds/dt - v_s)  dxi_j."""
+    w = sdot - vs if vp.force_model == 1 else cross(sp, sdot - vs)
+    return vp.rho_s_over_rho_n * vp.kappa * w * dxi[:, None]
 
 
 def superflow_at(Vs, z, nz):

@@ -172,6 +172,27 @@ def test_force_drags_normal_fluid_forward():
     assert abs(tot[0]) < 1e-15 and abs(tot[1]) < 1e-15
 
 
+def test_literal_force_model_ring():
+    """The literal reading of Eq. (f) (force_model 1) for a ring in normal
+    fluid at rest: each point pushes the fluid by (rho_s/rho_n) kappa
+    (ds/dt - v_s) dxi, i.e. inward by alpha V and backward by alpha' V, so
+    the total is -(rho_s/rho_n) kappa alpha' V P along the travel direction
+    (no drag along the motion, the reason reading R1 is the default)."""
+    vp = VortexParams(kappa=0.1, alpha=0.2, alpha_p=0.01, rho_s_over_rho_n=1.35, force_model=1)
+    lat, pos, nxt, prv = _ring_state(64)
+    vs, geo = _ring_vs(lat, pos, nxt, prv, vp)
+    sdot = vfm.schwarz_velocity(vs, np.zeros_like(vs), geo["sp"], vp.alpha, vp.alpha_p)
+    dxi = 0.5 * (geo["lp"] + geo["lm"])
+    g = vfm.mutual_friction_force(sdot, vs, geo["sp"], dxi, vp)
+    V = vs[0, 2]
+    rad = pos - np.array([32.0, 32.0, 32.0])
+    rad[:, 2] = 0
+    rhat = rad / vfm.norm(rad)[:, None]
+    np.testing.assert_allclose(vfm.dot(g, rhat), -1.35 * 0.1 * 0.2 * V * dxi, rtol=1e-12)
+    tot = g.sum(axis=0)
+    assert tot[2] == pytest.approx(-1.35 * 0.1 * 0.01 * V * geo["lp"].sum(), rel=1e-12)
+
+
 def _brute_interp(field, p, lat):
     nz, ny, nx = lat.shape
     v = np.zeros(3)

@@ -98,7 +98,11 @@ typedef struct {
   int32_t mass_balance;   /* 1: superflow V_s(z) from mass conservation
                              along z (Sec. III.C, Eq. mass cons); z must be
                              periodic                                       */
-  int32_t reserved0;
+  int32_t force_model;    /* reaction on the normal fluid per length
+                             (Sec. II.B, Eq. f): 0 = rho_s kappa s' x
+                             (ds/dt - v_s), the Magnus balance; 1 = rho_s
+                             kappa (ds/dt - v_s), the relation as printed
+                             (for ablation)                                 */
   int64_t n_cap;          /* capacity in filament points (>= 1)             */
   int64_t recon_cap;      /* capacity in reconnection candidates per step   */
 } vlb_vortex_desc;

@@ -62,7 +62,7 @@ class VortexDesc(ctypes.Structure):
         ("vs_applied", ctypes.c_double * 3),
         ("remesh", ctypes.c_int32), ("reconnect", ctypes.c_int32),
         ("min_loop_pts", ctypes.c_int32), ("coupling", ctypes.c_int32),
-        ("mass_balance", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("mass_balance", ctypes.c_int32), ("force_model", ctypes.c_int32),
         ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
     ]
 
@@ -153,6 +153,7 @@ def vortex_desc(vor: dict, n_cap: int, recon_cap: int = 1 << 16) -> VortexDesc:
     d.min_loop_pts = int(vor.get("min_loop_pts", 5))
     d.coupling = int(bool(vor.get("coupling", True)))
     d.mass_balance = int(bool(vor.get("mass_balance", False)))
+    d.force_model = int(vor.get("force_model", 0))
     d.n_cap = int(n_cap)
     d.recon_cap = int(recon_cap)
     return d

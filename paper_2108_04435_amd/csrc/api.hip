@@ -82,6 +82,7 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
   if (!(vor->dxi_min > 0) || !(vor->dxi_max > vor->dxi_min)) { msg = "need 0 < dxi_min < dxi_max"; return VLB_EINVAL; }
   if (vor->min_loop_pts < 3) { msg = "min_loop_pts must be >= 3"; return VLB_EINVAL; }
   if (vor->mass_balance && (lat->wall_axes & 4u)) { msg = "mass balance needs a periodic z axis"; return VLB_EINVAL; }
+  if (vor->force_model != 0 && vor->force_model != 1) { msg = "force_model must be 0 or 1"; return VLB_EINVAL; }
   if (vor->reconnect) {
     if (!(vor->reconnect_dist > 0)) { msg = "reconnect_dist must be positive"; return VLB_EINVAL; }
     if (vor->recon_cap < 1 || vor->recon_cap > (1LL << 26)) { msg = "recon_cap must be in [1, 2^26]"; return VLB_EINVAL; }

@@ -72,6 +72,7 @@ struct FinArgs {
   int stage;
   int eval_only;
   int coupling;
+  int force_model;  // 0: s' x (ds/dt - v_s) (Magnus balance); 1: ds/dt - v_s
   double kappa;
   double bs_scale;    // kappa / (4 pi)
   double nl_scale;    // kappa / (4 pi) times the grid step when the sum ran in grid units
@@ -352,7 +353,10 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
     const double sxr[3] = {sp[1] * r[2] - sp[2] * r[1], sp[2] * r[0] - sp[0] * r[2],
                            sp[0] * r[1] - sp[1] * r[0]};
     const double dxi = 0.5 * (lp + lm);
-    for (int a = 0; a < 3; ++a) A.gpt[a * nc + j] = A.coupling ? A.rs_rn * A.kappa * sxr[a] * dxi : 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double w = A.force_model ? r[a] : sxr[a];  // literal reading: for ablation
+      A.gpt[a * nc + j] = A.coupling ? A.rs_rn * A.kappa * w * dxi : 0.0;
+    }
   }
   if (A.eval_only) return;
 
@@ -566,6 +570,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.alpha = r.vor.alpha;
   A.alpha_p = r.vor.alpha_p;
   A.fric = r.fric;
+  A.force_model = r.vor.force_model;
   A.rs_rn = r.vor.rho_s_over_rho_n;
   for (int a = 0; a < 3; ++a) A.vs_app[a] = r.vor.vs_applied[a];
   A.vs1 = r.vs1;

@@ -108,6 +108,7 @@ def test_invalid_lattice_rejected(bad, msg):
     (dict(dxi_min=1.0, dxi_max=0.9), "dxi_min"),
     (dict(min_loop_pts=2), "min_loop_pts"),
     (dict(kappa=0.0), "kappa"),
+    (dict(force_model=2), "force_model"),
 ])
 def test_invalid_vortex_rejected(bad, msg):
     vor = wl.vortex_preset()

@@ -556,3 +556,43 @@ def test_friction_profile_reset_and_graph():
             a.set_friction_profile(bad, prof["alpha_p_z"])
         for r in (a, b, g, d, a2):
             r.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_literal_force_model_eval(precision):
+    """force_model 1 (the printed Eq. (f), for ablation): the per-point force
+    and its spreading against the oracle."""
+    cfg = CASES["channel"](precision)
+    cfg = dict(cfg, vortex=dict(cfg["vortex"], force_model=1))
+    say("literal force eval", precision)
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    ref, F_o, _ = _oracle_eval(cfg)
+    for k in ("sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= TOL[precision], (k, err)
+    assert rel_l2(F_g, F_o) <= TOL[precision]
+    run.close()
+
+
+def test_literal_force_model_coupled_f64():
+    cfg = CASES["channel"]("f64")
+    cfg = dict(cfg, vortex=dict(cfg["vortex"], force_model=1))
+    steps = 8
+    say("literal force coupled")
+    run = vlb.run_from_config(cfg)
+    run.step(steps)
+    run.sync()
+    lat, vp, st = oracle_state(cfg)
+    assert vp.force_model == 1
+    for _ in range(steps):
+        st = coupled.coupled_step(st, lat, vp)
+    pos_g, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    assert np.abs(vfm.min_image(pos_g - st.pos, lat)).max() < 1e-10
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) < 1e-10
+    run.close()

@@ -100,6 +100,8 @@ class Server:
                       recon_cap=self.recon_cap, stream=self.streams[slot])
             run.write_fields(cfg["rho"], cfg["u"])
             run.seed(cfg["pos"], cfg["nxt"])
+            if cfg["vortex"].get("alpha_z") is not None:
+                run.set_friction_profile(cfg["vortex"]["alpha_z"], cfg["vortex"]["alpha_p_z"])
         return _Active(req=req, run=run, slot=slot, remaining=int(req["steps"]), admitted=now,
                        footprint=footprint(cfg, n_cap, self.recon_cap),
                        points_start=int(cfg["pos"].shape[0]))

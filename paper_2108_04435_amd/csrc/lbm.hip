@@ -92,19 +92,29 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
     const T deq = eq_dev<T>(i, drho, rho, ux, uy, uz);
     const T Fi = pref * T(wq(i)) * (T(3) * (cg - ug) + T(9) * cu * cg);
     const T dn = d[i] - om * (d[i] - deq) + Fi;
+    // Odd passes store to the neighbours' slots: a direction with an x
+    // component stores each wave's values one element off the cache lines,
+    // and those partial lines must meet their other part in L2, so only the
+    // line-aligned stores (no x component) take the non-temporal hint
+    // (256^3 FP32: 7% fewer bytes written, odd pass 537 -> 460 us).
+    const bool nt_st = NT && (P == 0 || cx(i) == 0);
     if (P == 0) {
       pop_st<S, NT>(M + (long long)opp(i) * g.cells + c, dn);
     } else if (I32) {
       const int s = nbr_index32(nb32, cx(i), cy(i), cz(i));
       const uint32_t e = (s >= 0) ? (uint32_t)i * cells32 + (uint32_t)s
                                   : (uint32_t)opp(i) * cells32 + c32;
-      pop_st<S, NT>(at_byte(M, e * kSz), dn);
+      if (nt_st)
+        pop_st<S, true>(at_byte(M, e * kSz), dn);
+      else
+        pop_st<S, false>(at_byte(M, e * kSz), dn);
     } else {
       const long long s = nbr_index(nb, cx(i), cy(i), cz(i));
-      if (s >= 0)
-        pop_st<S, NT>(M + (long long)i * g.cells + s, dn);
+      S* p = (s >= 0) ? M + (long long)i * g.cells + s : M + (long long)opp(i) * g.cells + c;
+      if (nt_st)
+        pop_st<S, true>(p, dn);
       else
-        pop_st<S, NT>(M + (long long)opp(i) * g.cells + c, dn);
+        pop_st<S, false>(p, dn);
     }
   }
 }

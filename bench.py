@@ -403,7 +403,7 @@ def main():
         del x, y
 
     if not args.no_lbm_probe:
-        out["lbm_256cubed"] = [lbm_only(torch, vlb, wl, 256, p) for p in ("f32", "f16")]
+        out["lbm_256cubed"] = [lbm_only(torch, vlb, wl, 256, p) for p in ("f32", "f16", "f64")]
         torch.cuda.empty_cache()
         out["hbm_copy"] = hbm_copy(torch)
 

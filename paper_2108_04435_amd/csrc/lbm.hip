@@ -54,7 +54,13 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
       const int s = nbr_index32(nb32, -cx(i), -cy(i), -cz(i));
       const uint32_t e = (s >= 0) ? (uint32_t)opp(i) * cells32 + (uint32_t)s
                                   : (uint32_t)i * cells32 + c32;
-      d[i] = pop_ld<S, NT>(at_byte(M, e * kSz));
+      // FP64: the x-shifted loads (a wave spans five lines instead of
+      // four) go through L2, where the neighbouring wave finds the shared
+      // line (256^3: 0.940 -> 0.932 ms per update; no gain for FP32/FP16)
+      if (NT && (sizeof(S) < 8 || cx(i) == 0))
+        d[i] = pop_ld<S, true>(at_byte(M, e * kSz));
+      else
+        d[i] = pop_ld<S, false>(at_byte(M, e * kSz));
     }
   } else {
 #pragma unroll

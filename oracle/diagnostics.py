@@ -24,6 +24,8 @@ discrete definition:
   D3  The vorticity is the curl of u_b by central differences; periodic
       axes wrap, and a node beyond a wall carries u = 0 (the convention of
       the interpolation, R14).
+  D5  Cylindrical components about an axis (point, direction): see
+      vorticity_cylindrical.
 """
 
 import numpy as np
@@ -114,3 +116,28 @@ def vorticity(u, lat: Lattice):
     wy = _ddx(ux, lat, 2) - _ddx(uz, lat, 0)
     wz = _ddx(uy, lat, 0) - _ddx(ux, lat, 1)
     return np.stack([wx, wy, wz])
+
+
+def vorticity_cylindrical(w, lat: Lattice, point, direction):
+    """Cylindrical components (omega_rho, omega_phi, omega_axis) of a vector
+    field w (3, nz, ny, nx) about the axis through ``point`` along
+    ``direction`` (Sec. III.A: the vorticity of a ring in the cylindrical
+    frame of its axis).  Reading D5: a node's offset from the point is taken
+    at the nearest periodic image; rho_hat is the unit offset perpendicular
+    to the axis and phi_hat = axis x rho_hat; on the axis itself (no
+    perpendicular offset) omega_rho = omega_phi = 0."""
+    w = np.asarray(w, dtype=np.float64)
+    a = np.asarray(direction, dtype=np.float64)
+    a = a / np.sqrt((a * a).sum())
+    z, y, x = np.meshgrid(np.arange(lat.nz), np.arange(lat.ny), np.arange(lat.nx), indexing="ij")
+    r = np.stack([x - point[0], y - point[1], z - point[2]], axis=-1).astype(np.float64)
+    r = min_image(r, lat)
+    ra = (r * a).sum(axis=-1)
+    rp = r - ra[..., None] * a
+    n = np.sqrt((rp * rp).sum(axis=-1))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rho_hat = np.where(n[..., None] > 0, rp / n[..., None], 0.0)
+    phi_hat = np.cross(a, rho_hat)
+    wv = np.moveaxis(w, 0, -1)
+    out = np.stack([(wv * rho_hat).sum(-1), (wv * phi_hat).sum(-1), (wv * a).sum(-1)])
+    return out

@@ -159,3 +159,41 @@ def test_vorticity_at_walls():
     np.testing.assert_allclose(w[1], np.broadcast_to(want, (nz, ny, nx)), atol=1e-15)
     np.testing.assert_allclose(w[0], 0.0, atol=1e-15)
     np.testing.assert_allclose(w[2], 0.0, atol=1e-15)
+
+
+def test_cylindrical_rigid_rotation():
+    """u = Omega x r (rigid rotation about an axis through c) has the
+    discrete curl 2 Omega away from the periodic seams; about that axis its
+    cylindrical components are (0, 0, 2 |Omega|)."""
+    n = 24
+    lat = Lattice(n, n, n)
+    c = np.array([11.3, 12.1, 12.7])
+    om = np.array([0.3, -0.2, 0.5])
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.stack([x - c[0], y - c[1], z - c[2]])
+    u = np.stack([om[1] * r[2] - om[2] * r[1], om[2] * r[0] - om[0] * r[2], om[0] * r[1] - om[1] * r[0]])
+    w = dg.vorticity(u, lat)
+    inner = (slice(None), slice(2, -2), slice(2, -2), slice(2, -2))
+    np.testing.assert_allclose(w[inner], np.broadcast_to(2 * om[:, None, None, None], w[inner].shape),
+                               atol=1e-12)
+    cyl = dg.vorticity_cylindrical(w, lat, c, om)
+    np.testing.assert_allclose(cyl[0][inner[1:]], 0.0, atol=1e-12)
+    np.testing.assert_allclose(cyl[1][inner[1:]], 0.0, atol=1e-12)
+    np.testing.assert_allclose(cyl[2][inner[1:]], 2 * np.linalg.norm(om), atol=1e-12)
+
+
+def test_cylindrical_hand_case_and_norm():
+    """omega = x_hat at the node one unit along +y from an axis along z:
+    rho_hat = y_hat, phi_hat = z_hat x y_hat = -x_hat, so (0, -1, 0); on the
+    axis the radial and azimuthal parts are 0; the three components keep
+    |omega| everywhere off the axis."""
+    lat = Lattice(8, 8, 8)
+    w = np.zeros((3, 8, 8, 8))
+    w[0] = 1.0
+    cyl = dg.vorticity_cylindrical(w, lat, (4.0, 3.0, 0.0), (0.0, 0.0, 1.0))
+    np.testing.assert_allclose(cyl[:, 5, 4, 4], [0.0, -1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(cyl[:, 2, 3, 4], [0.0, 0.0, 0.0], atol=1e-15)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal((3, 8, 8, 8))
+    cyl = dg.vorticity_cylindrical(w, lat, (3.7, 4.2, 1.1), (1.0, 2.0, -0.5))
+    np.testing.assert_allclose((cyl ** 2).sum(0), (w ** 2).sum(0), rtol=1e-12)

@@ -226,6 +226,20 @@ int vlb_flow_stats(vlb_run* run, double* slice_mean_host, double* slice_rms_host
  * required.  Synchronises the run's stream.                                */
 int vlb_read_vorticity(vlb_run* run, double* u_dev, double* omega_dev);
 
+/* Cylindrical components of a vector field about an axis (Sec. III.A: the
+ * vorticity of a ring in the frame of its axis): omega_dev (3*cells doubles,
+ * device, e.g. from vlb_read_vorticity) in, out_dev (3*cells doubles,
+ * device) receives (omega.rho_hat, omega.phi_hat, omega.axis) per node, the
+ * axis through point (3 doubles, host, lattice units) along direction (3
+ * doubles, host, normalised here); a node's offset from the point is taken
+ * at the nearest periodic image, rho_hat is the unit offset perpendicular
+ * to the axis and phi_hat = axis x rho_hat; on the axis both are 0.
+ * VLB_EINVAL for a zero or non-finite direction or a non-finite point.
+ * Synchronises the run's stream.                                           */
+int vlb_vorticity_cylindrical(vlb_run* run, const double* point_host,
+                              const double* direction_host, const double* omega_dev,
+                              double* out_dev);
+
 /* Number of completed steps.                                               */
 int vlb_get_step(vlb_run* run, int64_t* step);
 

@@ -33,7 +33,7 @@ SYMBOLS = [
     "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
     "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology",
     "vlb_set_friction_profile", "vlb_line_length",
-    "vlb_flow_stats", "vlb_read_vorticity", "vlb_get_step",
+    "vlb_flow_stats", "vlb_read_vorticity", "vlb_vorticity_cylindrical", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
     "vlb_graph_launch", "vlb_graph_destroy", "vlb_destroy", "vlb_last_error",
 ]
@@ -105,6 +105,7 @@ def load_library(path=None):
     lib.vlb_line_length.argtypes = [vp, vp, vp]
     lib.vlb_flow_stats.argtypes = [vp, vp, vp, vp, vp]
     lib.vlb_read_vorticity.argtypes = [vp, vp, vp]
+    lib.vlb_vorticity_cylindrical.argtypes = [vp, vp, vp, vp, vp]
     lib.vlb_read_filaments.argtypes = [vp, i64, vp, vp, ctypes.POINTER(i64)]
     lib.vlb_eval_line_velocity.argtypes = [vp, vp, vp, vp, vp]
     lib.vlb_apply_topology.argtypes = [vp, vp]
@@ -308,6 +309,22 @@ class Run:
         self._check(self.lib.vlb_read_vorticity(self.h, ctypes.c_void_p(u.data_ptr()),
                                                 ctypes.c_void_p(w.data_ptr())))
         return u.cpu().numpy(), w.cpu().numpy()
+
+    def vorticity_cylindrical(self, point, direction):
+        """(bare velocity, vorticity, cylindrical components of the vorticity
+        about the axis through point along direction), each (3, nz, ny, nx)."""
+        torch = self.torch
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        w = torch.empty_like(u)
+        c = torch.empty_like(u)
+        p = np.ascontiguousarray(point, dtype=np.float64)
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        self._check(self.lib.vlb_read_vorticity(self.h, ctypes.c_void_p(u.data_ptr()),
+                                                ctypes.c_void_p(w.data_ptr())))
+        self._check(self.lib.vlb_vorticity_cylindrical(
+            self.h, p.ctypes.data_as(ctypes.c_void_p), d.ctypes.data_as(ctypes.c_void_p),
+            ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(c.data_ptr())))
+        return u.cpu().numpy(), w.cpu().numpy(), c.cpu().numpy()
 
     def n_points(self):
         n = ctypes.c_int64(0)

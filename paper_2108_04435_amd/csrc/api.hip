@@ -771,6 +771,21 @@ int vlb_read_vorticity(vlb_run* h, double* u_dev, double* omega_dev) {
   return latched(h);
 }
 
+int vlb_vorticity_cylindrical(vlb_run* h, const double* point, const double* direction,
+                              const double* omega_dev, double* out_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!point || !direction || !omega_dev || !out_dev) return fail(h, VLB_EINVAL, "null argument");
+  double a[3] = {direction[0], direction[1], direction[2]};
+  const double nn = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(point[0]) || !std::isfinite(point[1]) ||
+      !std::isfinite(point[2]))
+    return fail(h, VLB_EINVAL, "need a finite point and a non-zero finite direction");
+  for (double& v : a) v /= nn;
+  HIP_OR_FAIL(h, diag_cylindrical(h->r, point, a, omega_dev, out_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
 int vlb_get_step(vlb_run* h, int64_t* step) {
   if (!h || !step) return fail(h, VLB_EINVAL, "null argument");
   *step = h->r.step;

@@ -147,7 +147,60 @@ __global__ __launch_bounds__(256) void k_curl(const double* __restrict__ u, Geom
   w[2 * g.cells + c] = wz;
 }
 
+// Cylindrical components (w.rho_hat, w.phi_hat, w.a) of a vector field
+// about the axis through p along the unit vector a, one thread per node; the
+// node's offset from p at the nearest periodic image; on the axis the
+// radial and azimuthal components are 0.
+struct Axis {
+  double p[3], a[3];
+};
+__global__ __launch_bounds__(256) void k_cyl(const double* __restrict__ w, Geom g, Axis ax,
+                                             double* __restrict__ out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  const int node[3] = {(int)(c % g.nx), (int)((c / g.nx) % g.ny),
+                       (int)(c / ((long long)g.nx * g.ny))};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  double r[3];
+  for (int k = 0; k < 3; ++k) {
+    double x = (double)node[k] - ax.p[k];
+    if (!g.wall[k]) {
+      const double L = (double)n[k];
+      if (x > 0.5 * L)
+        x -= L;
+      else if (x < -0.5 * L)
+        x += L;
+    }
+    r[k] = x;
+  }
+  const double ra = r[0] * ax.a[0] + r[1] * ax.a[1] + r[2] * ax.a[2];
+  double rp[3];
+  for (int k = 0; k < 3; ++k) rp[k] = r[k] - ra * ax.a[k];
+  const double nn = sqrt(rp[0] * rp[0] + rp[1] * rp[1] + rp[2] * rp[2]);
+  double rh[3] = {0.0, 0.0, 0.0};
+  if (nn > 0.0)
+    for (int k = 0; k < 3; ++k) rh[k] = rp[k] / nn;
+  const double ph[3] = {ax.a[1] * rh[2] - ax.a[2] * rh[1], ax.a[2] * rh[0] - ax.a[0] * rh[2],
+                        ax.a[0] * rh[1] - ax.a[1] * rh[0]};
+  const double wv[3] = {w[c], w[g.cells + c], w[2 * g.cells + c]};
+  out[c] = wv[0] * rh[0] + wv[1] * rh[1] + wv[2] * rh[2];
+  out[g.cells + c] = wv[0] * ph[0] + wv[1] * ph[1] + wv[2] * ph[2];
+  out[2 * g.cells + c] = wv[0] * ax.a[0] + wv[1] * ax.a[1] + wv[2] * ax.a[2];
+}
+
 }  // namespace
+
+hipError_t diag_cylindrical(Run& r, const double point[3], const double unit_dir[3],
+                            const double* w, double* out) {
+  Axis ax;
+  for (int k = 0; k < 3; ++k) {
+    ax.p[k] = point[k];
+    ax.a[k] = unit_dir[k];
+  }
+  const int nb = (int)((r.cells + 255) / 256);
+  hipLaunchKernelGGL(k_cyl, dim3(nb), dim3(256), 0, r.stream, w, r.geom, ax, out);
+  return hipGetLastError();
+}
 
 hipError_t diag_line_length(Run& r, double* total, double* slabs) {
   const int nb = (int)((r.ncap + 255) / 256);

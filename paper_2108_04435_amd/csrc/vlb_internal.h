@@ -434,6 +434,8 @@ hipError_t lbm_flow_stats(Run& r, double* out);
 constexpr int kSlabChunks = 8;
 hipError_t diag_line_length(Run& r, double* total, double* slabs);
 hipError_t diag_curl(Run& r, const double* u, double* w);
+hipError_t diag_cylindrical(Run& r, const double point[3], const double unit_dir[3],
+                            const double* w, double* out);
 
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r);

@@ -116,3 +116,24 @@ def test_line_length_rejects_two_null_outputs():
     assert run.lib.vlb_line_length(run.h, None, None) == vlb.VLB_EINVAL
     assert b"NULL" in run.lib.vlb_last_error(run.h)
     run.close()
+
+
+@pytest.mark.parametrize("case", ["periodic", "channel"])
+def test_vorticity_cylindrical(case):
+    """Cylindrical components of the vorticity about an axis, against the
+    oracle applied to the GPU's own vorticity field."""
+    cfg = CASES[case]("f64")
+    lat = oracle_lattice(cfg["lattice"])
+    say("cylindrical", case)
+    run = vlb.run_from_config(cfg)
+    run.step(3)
+    run.sync()
+    point = (0.37 * lat.nx, 0.61 * lat.ny, 0.5 * lat.nz)
+    direction = (0.2, -0.3, 1.0)
+    _, w, cyl = run.vorticity_cylindrical(point, direction)
+    want = dg.vorticity_cylindrical(w, lat, point, direction)
+    np.testing.assert_allclose(cyl, want, rtol=0, atol=1e-14)
+    np.testing.assert_allclose((cyl ** 2).sum(0), (w ** 2).sum(0), rtol=1e-12, atol=1e-30)
+    with pytest.raises(vlb.VlbError):
+        run.vorticity_cylindrical(point, (0.0, 0.0, 0.0))
+    run.close()

@@ -1,24 +1,34 @@
 """Benchmark of the coupled VFM-LBM step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision P] [--rows P,P] [--graph G]
 
-Default workload: the counterflow channel, 64x64x256 lattice with bounce-back
-walls on x and y, periodic z, Guo body force for a mean normal-fluid velocity
-of about 0.02, 200 seeded rings (R ~ U[4,12], ~1.0e4 points), remeshing
-spacing 1.0, mass balance on z, FP32 deviation storage and FP32
-Biot-Savart.  Inputs are synthetic and already resident in HBM when the
-timed region starts.  One step = one pass of the whole coupled step
-(mass-balance superflow, 4 RK stages of Biot-Savart + LIA + interpolation +
-Schwarz, force spreading, LBM collide+stream, remeshing).
+Default workload (the precision form, the largest single-GPU case): a 256^3
+periodic lattice, f^eq(1, 0.02 z + N(0, 1e-4^2)) initial populations, a
+seeded random tangle of 2000 rings (R ~ U[4, 12], about 1.04e5 points at
+remeshing spacing 0.95), mass balance on z, populations stored as FP16
+deviations with FP32 arithmetic, FP32 Biot-Savart, FP64 positions.  The
+same workload with FP32-deviation storage and on the plain FP64 path is
+measured beside it (``rows``).  Inputs are synthetic and already resident
+in HBM when the timed region starts.  One step = one pass of the whole
+coupled step (mass-balance superflow, 4 RK stages of Biot-Savart + LIA +
+interpolation + Schwarz, force spreading, LBM collide+stream, remeshing).
 
-The run advances in launches of a HIP graph holding 10 captured steps
-(``--graph 0``: steps enqueued one by one).
+Stepping: ``--graph 0`` (default for the 256^3 and 128x128x512 cases)
+enqueues steps one by one with HIP events around every step on the run's
+stream, so p50/p99 are per step; ``--graph G`` (G even, default for the
+small cases) advances in launches of a G-step HIP graph and steps any
+remainder of --steps / --warmup directly.
 
-Prints ONE JSON line.  ``value`` is coupled steps per second on the one GPU;
-``roofline`` is for the dominant kernel (the Biot-Savart pair sum), its
-launch duration measured with HIP events on the run's stream (50 launches
-back to back at the final state, after the timed steps); ``cpu_baseline``
-times the FP64 oracle on the host on a bounded sample of the same workload.
+Prints ONE JSON line.  ``value`` is coupled steps per second on the one GPU
+for the headline precision; ``roofline`` is the dominant kernel (the FP32
+Biot-Savart pair sum), priced at 35 flops per (target, segment) pair against
+the FP32 vector peak, its launch duration measured with HIP events around
+each of its launches inside the timed steps on the run's stream;
+``lbm_roofline`` is the LBM update against the HBM peak.  ``cpu_baseline``
+times the FP64 oracle on a bounded sample of the same workload on the
+host's cores; the same sample gives each precision's error against the
+oracle after one coupled step from the seeded state.
 """
 
 import argparse
@@ -34,48 +44,66 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic FP32 work of one (target, segment) pair of the straight-segment
-# Biot-Savart closed form as evaluated (R1 = s_k - r, d = segment vector,
-# R1 x R2 = R1 x d, |R2|^2 = |R1|^2 + 2 R1.d + |d|^2), counting a fused
-# multiply-add as 2 flops and a reciprocal / reciprocal square root as 1:
-# separation 3, R1.d 5, |R1|^2 5, |R2|^2 3, R1.R2 1, two inverse norms 2,
-# cross product 9, product of inverse norms 1, denominator 2, reciprocal 1,
-# numerator and scale 3, accumulation 6.
-FLOPS_PER_PAIR = 41
+# Biot-Savart closed form (Sec. II.A, Eq. Biot-Savart), counting a fused
+# multiply-add as 2 flops and a reciprocal / square root as 1.  Per source
+# point, amortised over the two segments that share it: separation R = s - r
+# (3), |R|^2 (5), its root (1) -> 9.  Per segment: R1 x R2 (9), R1.R2 (5),
+# the products and sums of the norms (4), a reciprocal (1), the scale (1),
+# the 3-component accumulation (6) -> 26.  Total 35.
+FLOPS_PER_PAIR = 35
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X published FP64 vector peak
 PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
-# Issue ceiling of the FP32 pair loop: packed FP32 is not used, so a SIMD
-# issues one VALU instruction per lane per cycle: 256 CUs x 4 SIMDs x 16
-# lanes x 2.4 GHz.  The unrolled loop body of the built kernel holds 117
-# VALU instructions per 4 pairs (its 12 transcendental ones issue beside
-# them), i.e. 29.25 per pair.
-VALU_LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9
-VALU_PER_PAIR_F32 = 29.25
+LLC_BYTES = 256 << 20             # MI355X last-level (Infinity) cache
 
-WORKLOADS = ("counterflow", "ring32", "heater", "tangle", "serve")
+WORKLOADS = ("tangle", "counterflow", "ring32", "heater", "serve")
+DEFAULT_PRECISION = {"tangle": "f16", "counterflow": "f32", "ring32": "f64", "heater": "f32"}
+DEFAULT_GRAPH = {"tangle": 0, "heater": 0, "counterflow": 10, "ring32": 10}
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
 def make_workload(name, precision=None):
     import workloads as wl
 
+    p = precision or DEFAULT_PRECISION.get(name)
     if name == "counterflow":
-        cfg = wl.config_counterflow(precision=precision or "f32")
-    elif name == "ring32":
-        cfg = wl.config_ring32(precision=precision or "f64")
-    elif name == "heater":
-        cfg = wl.config_heater(precision=precision or "f32")
-    elif name == "tangle":
-        cfg = wl.config_tangle(precision=precision or "f16")
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return cfg
+        return wl.config_counterflow(precision=p)
+    if name == "ring32":
+        return wl.config_ring32(precision=p)
+    if name == "heater":
+        return wl.config_heater(precision=p)
+    if name == "tangle":
+        return wl.config_tangle(precision=p)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def with_precision(cfg, precision):
+    out = dict(cfg)
+    out["lattice"] = dict(cfg["lattice"], precision=precision)
+    return out
+
+
+def step_plan(n, chunk):
+    """Split n steps into graph launches of ``chunk`` steps and a direct
+    remainder: a list of ("graph" | "direct", steps).  chunk = 0: every step
+    direct, one entry per step (so that each step gets its own events)."""
+    if n < 0:
+        raise ValueError("step count must be >= 0")
+    if chunk == 0:
+        return [("direct", 1)] * n
+    if chunk < 2 or chunk % 2:
+        raise ValueError("--graph needs an even chunk >= 2 (or 0 for direct stepping)")
+    plan = [("graph", chunk)] * (n // chunk)
+    if n % chunk:
+        plan.append(("direct", n % chunk))
+    return plan
 
 
 def traffic_record(kernel_src, workload):
     """HBM bytes per launch of the Biot-Savart kernel from committed
     rocprofv3 counter runs, if they were taken on the current source and on
-    this workload (FP32 storage)."""
-    path = os.path.join(ROOT, "profiles", "bs_counters.json")
+    this workload."""
+    path = os.path.join(ROOT, "profiles", "k_bs_f32_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -85,61 +113,334 @@ def traffic_record(kernel_src, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, n_evals=2):
-    """Oracle (plain FP64 numpy) on the host: one full LBM update of the
-    lattice plus n_evals full Biot-Savart sums (every target against every
-    segment), scaled to one coupled step (4 Biot-Savart evaluations)."""
+# ----------------------------------------------------------------- oracle leg
+# Everything under oracle/ is called from this leg only: the oracle is timed
+# on a bounded sample of the workload, and its values on that sample are
+# what each precision's GPU result is compared with.
+
+_POOL_ARGS = None
+
+
+def _pool_bs(targets):
+    from oracle import vfm
+
+    pos, nxt, prv, lat, kappa = _POOL_ARGS
+    t0 = time.perf_counter()
+    v = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, kappa, targets=targets, chunk=16)
+    return v, time.perf_counter() - t0
+
+
+def sample_window(cfg, width=32):
+    """Origin and width of the lattice crop the accuracy sample uses: a
+    cube of ``width`` nodes centred in the lattice (interior: no wall, plane
+    or periodic seam inside it)."""
+    L = cfg["lattice"]
+    dims = (L["nx"], L["ny"], L["nz"])
+    w = min(width, min(dims) // 2)
+    o = tuple((d - w) // 2 for d in dims)
+    return o, w
+
+
+def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
+    """The FP64 oracle on a bounded sample of the workload, on the host's
+    cores, from the seeded state:
+      * Biot-Savart sums (every segment) at sampled targets: the points of a
+        slab of the lattice around a centred crop (all points whose force
+        reaches the crop, plus a random draw from the slab), split over a
+        fork pool of ``workers`` processes; ``single`` of them again in this
+        process for the single-thread rate;
+      * the rest of the first RK stage at those targets (LIA, applied and
+        mass-balance superflow from the slab's slices, interpolated v_n,
+        Schwarz line velocity, mutual-friction force);
+      * one forced LBM update of the crop (with the force the sampled points
+        spread into it).
+    The rates are scaled to one coupled step of the whole workload (4
+    Biot-Savart evaluations of n (n - 2) pairs, one update of every node).
+    Returns (baseline dict, reference values for the accuracy check)."""
+    import multiprocessing as mp
+
     from oracle import coupled, lbm, vfm
     from oracle.lbm import Lattice
     from oracle.vfm import VortexParams
 
+    global _POOL_ARGS
     L = cfg["lattice"]
-    lat = Lattice(L["nx"], L["ny"], L["nz"], tau=L["tau"], walls=tuple(L["walls"]),
-                  plane_lo=L["plane_lo"], plane_hi=L["plane_hi"], plane_u=tuple(L["plane_u"]),
+    dims = (L["nx"], L["ny"], L["nz"])
+    walls = tuple(L["walls"])
+    lat = Lattice(*dims, tau=L["tau"], walls=walls, plane_lo=L["plane_lo"],
+                  plane_hi=L["plane_hi"], plane_u=tuple(L["plane_u"]),
                   body_force=tuple(L["body_force"]))
     vp = VortexParams(**{k: cfg["vortex"][k] for k in VortexParams.__dataclass_fields__
                          if k in cfg["vortex"]})
-    st = coupled.make_state(cfg["rho"], cfg["u"], cfg["pos"], cfg["nxt"], lat)
-    n = st.pos.shape[0]
+    pos = vfm.wrap_positions(np.asarray(cfg["pos"], dtype=np.float64), lat)
+    nxt = np.asarray(cfg["nxt"], dtype=np.int64)
+    prv = coupled.prev_from_next(nxt)
+    n = pos.shape[0]
+    o, w = sample_window(cfg, width)
+    o_arr = np.array(o, dtype=np.float64)
+
+    # targets: every point whose stencil reaches the crop, plus a random draw
+    # from the slab o_z - 1 < z < o_z + w (v_n and V_s known there)
+    box = np.all((pos > o_arr - 1.0) & (pos < o_arr + w), axis=1)
+    slab = (pos[:, 2] > o[2] - 1.0) & (pos[:, 2] < o[2] + w)
+    nw = workers or max(1, min(16, os.cpu_count() or 1))
+    want = nw * per_worker
+    rng = np.random.Generator(np.random.PCG64(12345))
+    box_idx = np.nonzero(box)[0]
+    rest = np.setdiff1d(np.nonzero(slab)[0], box_idx)
+    extra = rng.choice(rest, size=max(0, min(rest.size, want - box_idx.size)), replace=False)
+    targets = np.sort(np.concatenate([box_idx, extra])).astype(np.int64)
+
+    # Biot-Savart at the targets: fork pool (no GPU has been touched yet)
+    _POOL_ARGS = (pos, nxt, prv, lat, vp.kappa)
+    parts = np.array_split(targets, nw)
     t0 = time.perf_counter()
-    _, ub = lbm.bare_velocity(st.f, lat)
-    if vp.mass_balance:
-        lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n)
-    lbm.lbm_step(st.f, np.zeros((3,) + lat.shape), lat)
+    if nw > 1:
+        with mp.get_context("fork").Pool(nw) as pool:
+            res = pool.map(_pool_bs, parts)
+    else:
+        res = [_pool_bs(parts[0])]
+    t_pool = time.perf_counter() - t0
+    bs = np.concatenate([r[0] for r in res], axis=0)
+    pairs_pool = targets.size * (n - 2)
+    t_single = time.perf_counter()
+    vfm.biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa, targets=targets[:single], chunk=16)
+    t_single = time.perf_counter() - t_single
+    pairs_single = min(single, targets.size) * (n - 2)
+
+    # the rest of stage 1 at the targets, from the slab z in [o_z-2, o_z+w+2)
     t1 = time.perf_counter()
-    for _ in range(n_evals):
-        vfm.biot_savart_nonlocal(st.pos, st.nxt, st.prv, lat, vp.kappa)
+    z0, nzs = o[2] - 2, w + 4
+    zs = np.arange(z0, z0 + nzs) % dims[2]
+    slat = Lattice(dims[0], dims[1], nzs, tau=L["tau"], walls=(walls[0], walls[1], True))
+    f_slab = lbm.init_equilibrium(cfg["rho"][zs], cfg["u"][:, zs])
+    _, ub_slab = lbm.bare_velocity(f_slab, slat)
+    Vs = (lbm.mass_balance_superflow(f_slab, slat, vp.rho_s_over_rho_n)
+          if vp.mass_balance else None)
+    del f_slab
+    geo = vfm.geometry(pos, nxt, prv, lat)
+    pt = pos[targets]
+    pt_slab = pt - np.array([0.0, 0.0, float(z0)])
+    vs = bs + vfm.lia_velocity(geo, vp)[targets] + np.array(vp.vs_applied)[None, :]
+    if Vs is not None:
+        vs[:, 2] += vfm.superflow_at(Vs, pt_slab[:, 2], nzs)
+    vn = vfm.interpolate(ub_slab, pt_slab, slat)
+    alpha, alpha_p = vfm.friction_at(vp, pt[:, 2], lat)
+    sp = geo["sp"][targets]
+    sdot = vfm.schwarz_velocity(vs, vn, sp, alpha, alpha_p)
+    dxi = 0.5 * (geo["lp"] + geo["lm"])[targets]
+    force = vfm.mutual_friction_force(sdot, vs, sp, dxi, vp)
+    t_stage = time.perf_counter() - t1
+
+    # one forced LBM update of the crop [o, o+w)^3 (interior [o+1, o+w-1)^3
+    # is exact: its pulls stay inside the crop)
+    inbox = box[targets]
+    clat = Lattice(w, w, w, tau=L["tau"], walls=(True, True, True))
+    F = (vfm.spread(force[inbox], pt[inbox] - o_arr, clat) if vp.coupling
+         else np.zeros((3, w, w, w)))
+    sl = (slice(o[2], o[2] + w), slice(o[1], o[1] + w), slice(o[0], o[0] + w))
+    f_crop = lbm.init_equilibrium(cfg["rho"][sl], cfg["u"][(slice(None),) + sl])
+    plat = Lattice(w, w, w, tau=L["tau"], body_force=tuple(L["body_force"]))
     t2 = time.perf_counter()
-    t_step = (t1 - t0) + 4.0 * (t2 - t1) / n_evals
-    return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
-                sample=f"one FP64 LBM update of all {lat.nx}x{lat.ny}x{lat.nz} nodes plus "
-                       f"{n_evals} full Biot-Savart sums ({n} targets x all segments), scaled to "
-                       f"one coupled step (4 evaluations); numpy, single thread; "
-                       f"measured {t2 - t0:.1f} s")
+    f1 = lbm.lbm_step(f_crop, F, plat)
+    t_lbm = time.perf_counter() - t2
+    _, u1 = lbm.bare_velocity(f1, plat)
+    u_crop = u1[:, 1:-1, 1:-1, 1:-1]
+
+    cells = dims[0] * dims[1] * dims[2]
+    rate_pool = pairs_pool / t_pool
+    rate_single = pairs_single / t_single
+    rate_lbm = w ** 3 / t_lbm
+    pairs_step = 4.0 * n * (n - 2)
+    t_step = pairs_step / rate_pool + cells / rate_lbm
+    t_step_1 = pairs_step / rate_single + cells / rate_lbm
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    base = dict(
+        value=1.0 / t_step, unit="steps/s", cores=nw, kind="oracle",
+        single_thread_value=1.0 / t_step_1,
+        bs_gpairs_s=rate_pool / 1e9, bs_gpairs_s_single=rate_single / 1e9,
+        lbm_mlups_single=rate_lbm / 1e6,
+        host_cpu=cpu, host_nproc=os.cpu_count(),
+        sample=(f"FP64 numpy oracle: Biot-Savart sums at {targets.size} targets x {n - 2} "
+                f"segments on a fork pool of {nw} processes ({t_pool:.1f} s; {single} targets "
+                f"again in one process, {t_single:.1f} s), one LBM update of a {w}^3 crop "
+                f"({t_lbm:.2f} s, one thread), the rest of RK stage 1 at the targets "
+                f"({t_stage:.1f} s); scaled to one coupled step of the whole workload "
+                f"(4 x {n} x {n - 2} pairs + {cells} node updates; the O(N) filament work "
+                f"and the topology are not counted)"),
+    )
+    ref = dict(targets=targets, vs=vs, vn=vn, sdot=sdot, force=force, origin=o, width=w,
+               u_crop=u_crop)
+    return base, ref
 
 
-def lbm_only(torch, vlb, wl, n, precision, steps=20):
-    """Normal-fluid update alone on an n^3 periodic lattice (working set far
-    above the 256 MB last-level cache): kernel GB/s from HIP events."""
-    lat = wl.lattice_preset(n, n, n, tau=0.8, precision=precision)
-    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
-    rho, u = wl.velocity_field(4, (n, n, n), (0.0, 0.0, 0.02), 1e-4)
-    run.write_fields(rho, u)
-    del rho, u
-    run.step(4)
+# ------------------------------------------------------------------ GPU legs
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = float(np.sqrt((b * b).sum()))
+    return float(np.sqrt(((a - b) ** 2).sum()) / (den if den > 0 else 1.0))
+
+
+def accuracy(run, ref):
+    """Errors of the run's first coupled step from the seeded state against
+    the oracle's values on the sample: the first-stage velocities at the
+    sampled targets (evaluated, not advanced), then, after one step, the
+    bare normal-fluid velocity on the crop's interior.  Leaves the run one
+    step on."""
+    torch = run.torch
+    out = run.eval_line_velocity()
+    t = ref["targets"]
+    err = {k: rel_l2(out[k][t], ref[k]) for k in ("vs", "vn", "sdot", "force")}
+    run.step(1)
     run.sync()
-    run.set_timing(True, reserve=4 * steps)
-    run.step(steps)
+    u = torch.empty((3,) + run.shape, dtype=torch.float64, device=run.device)
+    run._check(run.lib.vlb_read_fields(run.h, None, run._ptr(u)))
+    o, w = ref["origin"], ref["width"]
+    crop = u[:, o[2] + 1:o[2] + w - 1, o[1] + 1:o[1] + w - 1, o[0] + 1:o[0] + w - 1]
+    err["u_crop"] = rel_l2(crop.cpu().numpy(), ref["u_crop"])
+    del u
+    return {"line_velocity_rel_l2": {k: float(f"{v:.3e}") for k, v in err.items() if k != "u_crop"},
+            "lattice_velocity_rel_l2": float(f"{err['u_crop']:.3e}"),
+            "sample": f"{t.size} targets; crop interior {w - 2}^3 nodes at {tuple(x + 1 for x in o)}"}
+
+
+def measure(cfg, args, ref, graph):
+    """One precision row: accuracy from the seeded state (if the oracle leg
+    ran), warm-up, the timed steps, and the kernel timings inside them."""
+    import torch
+
+    import paper_2108_04435_amd as vlb
+
+    lat = cfg["lattice"]
+    prec = lat["precision"]
+    n0 = cfg["pos"].shape[0]
+    stream = torch.cuda.Stream()   # default priority; graphs need a non-null stream
+    torch.cuda.set_stream(stream)
+    run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256, recon_cap=1 << 18)
+    cells = lat["nx"] * lat["ny"] * lat["nz"]
+    acc = accuracy(run, ref) if ref is not None else None
+
+    def advance(plan, events=None):
+        for kind, k in plan:
+            if events is not None:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            if kind == "graph":
+                run.step_graph(k)
+            else:
+                run.step(k)
+            if events is not None:
+                b.record(stream)
+                events.append((a, b, k))
+
+    advance(step_plan(args.warmup, graph))
     run.sync()
-    ms, k = run.timing(1)
-    b = {"f64": 8, "f32": 4, "f16": 2}[precision]
-    bytes_node = 2 * 19 * b
-    cells = n ** 3
-    gbs = bytes_node * cells * k / (ms * 1e-3) / 1e9
-    run.close()
-    return dict(lattice=f"{n}^3", precision=precision, kernel_ms=ms / k,
-                glups=cells * k / (ms * 1e-3) / 1e9, bytes_per_node=bytes_node,
-                achieved_GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
+    direct = graph == 0
+    run.set_timing(direct, reserve=2 * 2 * args.steps + 64)  # also zeroes the work counters
+    ev = []
+    plan = step_plan(args.steps, graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    advance(plan, ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run.sync()
+    step_ms = np.concatenate([np.full(k, a.elapsed_time(b) / k) for a, b, k in ev]) \
+        if ev else np.zeros(1)
+    nodes, pairs = run.work()
+    n_end = run.n_points()
+    if direct:
+        bs_ms, bs_n = run.timing(0)
+        lbm_ms, lbm_n = run.timing(1)
+        bs_basis = f"HIP events around each of the {bs_n} launches inside the timed steps"
+    else:   # graphs carry no per-launch events: the kernels alone at the final state
+        bs_ms, bs_n = run.time_kernel(0, reps=20) * 20, 20
+        pairs = 20 * n_end * (n_end - 2)
+        lbm_ms, lbm_n = run.time_kernel(1, reps=20) * 20, 20
+        bs_basis = "20 launches back to back at the final state (HIP events)"
+    bs_us = bs_ms * 1e3 / max(bs_n, 1)
+    pairs_launch = pairs / max(bs_n, 1)
+    lbm_us = lbm_ms * 1e3 / max(lbm_n, 1)
+    lbm_bytes = 2 * 19 * STORE_BYTES[prec] * cells
+    row = {
+        "precision": prec,
+        "value": round(args.steps / wall, 4),
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "step_time_basis": ("per step (HIP events around each step)" if direct else
+                            f"per graph launch of {graph} steps / {graph} (direct remainder "
+                            "per call)"),
+        "mlups": round(cells * args.steps / wall / 1e6, 1),
+        "bs_gpairs_s": round(pairs / max(bs_n, 1) * bs_n / wall / 1e9, 2) if direct else None,
+        "points_start": int(n0),
+        "points_end": int(n_end),
+        "bs_kernel": {"name": "k_bs_f64" if prec == "f64" else "k_bs_f32",
+                      "avg_launch_us": round(bs_us, 2), "launches": int(bs_n),
+                      "pairs_per_launch": int(pairs_launch),
+                      "tpairs_s": round(pairs_launch / (bs_us * 1e-6) / 1e12, 4),
+                      "basis": bs_basis},
+        "lbm_kernel": {"avg_launch_us": round(lbm_us, 2), "launches": int(lbm_n),
+                       "glups": round(cells / (lbm_us * 1e-6) / 1e9, 3),
+                       "bytes_per_node": 2 * 19 * STORE_BYTES[prec],
+                       "algorithmic_GBs": round(lbm_bytes / (lbm_us * 1e-6) / 1e9, 1),
+                       "population_bytes": lbm_bytes // 2,
+                       "cache_resident": lbm_bytes // 2 <= LLC_BYTES},
+        "accuracy_vs_oracle": acc,
+    }
+    extra = {"run": run, "cells": cells, "pairs_launch": pairs_launch, "bs_us": bs_us,
+             "lbm_us": lbm_us, "lbm_bytes": lbm_bytes, "n_end": n_end}
+    return row, extra
+
+
+def time_diagnostics(run, cells, precision, n_points, reps=10):
+    """Host-visible time of one call of each diagnostic at the final state
+    (median of reps calls; each call launches its kernels and synchronises
+    with its copy to the host), with the algorithmic bytes of the lattice
+    ones: the velocity statistics read the populations twice; the vorticity
+    reads them once, writes the velocity, reads it back and writes the curl."""
+    import torch
+
+    b = STORE_BYTES[precision]
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    u = torch.empty((3,) + run.shape, dtype=torch.float64, device=run.device)
+    w = torch.empty_like(u)
+    pu, pw = run._ptr(u), run._ptr(w)
+
+    def vort():
+        run._check(run.lib.vlb_read_vorticity(run.h, pu, pw))
+
+    t_len = med(run.line_length)
+    t_st = med(run.flow_stats)
+    t_w = med(vort)
+    st_bytes = 2 * 19 * b * cells
+    w_bytes = (19 * b + 24 + 24 + 24) * cells
+    return {
+        "line_length": {"call_us": round(t_len * 1e6, 1), "points": int(n_points)},
+        "flow_stats": {"call_us": round(t_st * 1e6, 1), "bytes": st_bytes,
+                       "GBs": round(st_bytes / t_st / 1e9, 1)},
+        "vorticity": {"call_us": round(t_w * 1e6, 1), "bytes": w_bytes,
+                      "GBs": round(w_bytes / t_w / 1e9, 1),
+                      "note": "device outputs (u and omega stay in HBM)"},
+    }
 
 
 def hbm_copy(torch, nbytes=1 << 30, reps=10):
@@ -148,11 +449,12 @@ def hbm_copy(torch, nbytes=1 << 30, reps=10):
     x = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     y = torch.empty_like(x)
     y.copy_(x)
+    s = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
+    a.record(s)
     for _ in range(reps):
         y.copy_(x)
-    b.record()
+    b.record(s)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     del x, y
@@ -192,223 +494,163 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def time_diagnostics(run, cells, precision, n_points, reps=10):
-    """Host-visible time of one call of each diagnostic at the final state
-    (median of reps calls; each call launches its kernels and synchronises
-    with its copy to the host), with the algorithmic bytes of the lattice
-    ones: the velocity statistics read the populations twice; the vorticity
-    reads them once, writes the velocity, reads it back and writes the curl."""
-    b = {"f64": 8, "f32": 4, "f16": 2}[precision]
-
-    def med(fn):
-        fn()
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            ts.append(time.perf_counter() - t0)
-        return float(np.median(ts))
-
-    import ctypes
-    import torch
-
-    u = torch.empty((3,) + run.shape, dtype=torch.float64, device=run.device)
-    w = torch.empty_like(u)
-    pu, pw = ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(w.data_ptr())
-
-    def vort():
-        if run.lib.vlb_read_vorticity(run.h, pu, pw) != 0:
-            raise RuntimeError("vlb_read_vorticity failed")
-
-    t_len = med(run.line_length)
-    t_st = med(run.flow_stats)
-    t_w = med(vort)
-    st_bytes = 2 * 19 * b * cells
-    w_bytes = (19 * b + 24 + 24 + 24) * cells
-    return {
-        "line_length": {"call_us": round(t_len * 1e6, 1), "points": int(n_points)},
-        "flow_stats": {"call_us": round(t_st * 1e6, 1), "bytes": st_bytes,
-                       "GBs": round(st_bytes / t_st / 1e9, 1)},
-        "vorticity": {"call_us": round(t_w * 1e6, 1), "bytes": w_bytes,
-                      "GBs": round(w_bytes / t_w / 1e9, 1),
-                      "note": "device outputs (u and omega stay in HBM)"},
-    }
-
-
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="counterflow", choices=WORKLOADS)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tangle", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=("f64", "f32", "f16"))
+    ap.add_argument("--rows", default=None,
+                    help="comma-separated precisions measured beside the headline "
+                         "(default for the 256^3 tangle: f32,f64; 'none' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", type=int, default=10,
+    ap.add_argument("--graph", type=int, default=None,
                     help="advance in HIP-graph launches of this many steps (even); 0: direct")
-    ap.add_argument("--no-lbm-probe", action="store_true")
+    ap.add_argument("--no-diagnostics", action="store_true")
+    ap.add_argument("--baseline-workers", type=int, default=None)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain device copy of known size (counter scaling)")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+    if args.workload != "serve":
+        if args.graph is None:
+            args.graph = DEFAULT_GRAPH[args.workload]
+        step_plan(args.steps, args.graph)   # validates the chunk
+        head = args.precision or DEFAULT_PRECISION[args.workload]
+        if args.rows is None:
+            rows = ["f32", "f64"] if args.workload == "tangle" else []
+        elif args.rows in ("", "none"):
+            rows = []
+        else:
+            rows = [p.strip() for p in args.rows.split(",") if p.strip()]
+        for p in rows:
+            if p not in STORE_BYTES:
+                ap.error(f"unknown precision {p} in --rows")
+        args.head_precision = head
+        args.row_precisions = [p for p in rows if p != head]
+    return args
 
+
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this program runs on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        import torch
+
+        torch.cuda.set_device(0)
+        serve_bench(args)
+        return
+
+    t_setup = time.perf_counter()
+    cfg = make_workload(args.workload, args.head_precision)
+    print(f"[bench] workload {cfg['name']}: {cfg['pos'].shape[0]} points, "
+          f"{time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+    base, ref = None, None
+    if not args.no_cpu_baseline:
+        # before any GPU work: the oracle leg forks its worker pool
+        base, ref = cpu_baseline(cfg, workers=args.baseline_workers)
+        print(f"[bench] oracle leg done: {base['sample']}", file=sys.stderr, flush=True)
 
     import torch
 
     import paper_2108_04435_amd as vlb
-    import workloads as wl
 
-    if not os.path.exists(vlb.LIB_PATH):
-        from paper_2108_04435_amd import build as b
-        b.build()
-
+    vlb.load_library()   # raises if the HIP library is not built
     torch.cuda.set_device(0)
-    if args.workload == "serve":
-        serve_bench(args)
-        return
-    cfg = make_workload(args.workload, args.precision)
+
     lat = cfg["lattice"]
-    n0 = cfg["pos"].shape[0]
-    run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256,
-                              recon_cap=1 << 18)
-    cells = lat["nx"] * lat["ny"] * lat["nz"]
+    prec = args.head_precision
+    head, hx = measure(cfg, args, ref, args.graph)
+    print(f"[bench] {prec}: {head['value']} steps/s", file=sys.stderr, flush=True)
+    diagnostics = None if args.no_diagnostics else time_diagnostics(
+        hx["run"], hx["cells"], prec, hx["n_end"])
+    hx["run"].close()
+    del hx["run"]
+    torch.cuda.empty_cache()
 
-    G = args.graph
-    if G:
-        if G % 2 or args.steps % G or args.warmup % G:
-            raise SystemExit("--graph needs an even chunk dividing --steps and --warmup")
-        stream = torch.cuda.Stream()
-        torch.cuda.set_stream(stream)
-        run.close()
-        run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256, recon_cap=1 << 18)
-        run.graph(G)
-        adv, unit = (lambda: run.step_graph(G)), G
-    else:
-        adv, unit = (lambda: run.step(1)), 1
-    for _ in range(args.warmup // unit):
-        adv()
-    run.sync()
-    K = args.steps
-    nev = K // unit
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(nev)]
-    # per-launch kernel events inside the steps only when stepping directly
-    run.set_timing(not G, reserve=2 * 6 * K + 64)  # also zeroes the work counters
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(nev):
-        ev[k][0].record(stream)
-        adv()
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run.sync()
-    wall = t1 - t0
-    step_ms = np.array([a.elapsed_time(b) for a, b in ev]) / unit
-    nodes, pairs = run.work()
-    in_step = None
-    if not G:
-        bs_ms, bs_n = run.timing(0)
-        in_step = {"bs_avg_launch_us": round(bs_ms * 1e3 / max(bs_n, 1), 2),
-                   "bs_pairs_per_launch": int(pairs / max(bs_n, 1)),
-                   "note": "HIP events around every launch inside the steps (adds event overhead)"}
-    n_end = run.n_points()
-    # the dominant kernel alone, launched back to back on the final state
-    bs_iso_ms = run.time_kernel(0, reps=50)
-    pairs_iso = n_end * (n_end - 2)
-    # the LBM update alone (advances the fluid; after the timed region)
-    lbm_iso_ms = run.time_kernel(1, reps=20)
-    diagnostics = time_diagnostics(run, cells, lat["precision"], n_end)
+    rows = []
+    for p in args.row_precisions:
+        r, rx = measure(with_precision(cfg, p), args, ref, args.graph)
+        rx["run"].close()
+        del rx["run"]
+        torch.cuda.empty_cache()
+        print(f"[bench] {p}: {r['value']} steps/s", file=sys.stderr, flush=True)
+        rows.append(r)
+    plain = [r for r in [head] + rows if r["precision"] == "f64"]
+    if plain:
+        for r in [head] + rows:
+            r["speedup_vs_f64"] = round(r["value"] / plain[0]["value"], 3)
 
-    value = K / wall
-    achieved = FLOPS_PER_PAIR * pairs_iso / (bs_iso_ms * 1e-3) / 1e12
-    src = os.path.join(ROOT, "paper_2108_04435_amd", "csrc", "bs.hip")
-    f64 = lat["precision"] == "f64"
+    f64 = prec == "f64"
     peak = PEAK_FP64_VECTOR_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS
+    achieved = FLOPS_PER_PAIR * hx["pairs_launch"] / (hx["bs_us"] * 1e-6) / 1e12
+    src = os.path.join(ROOT, "paper_2108_04435_amd", "csrc", "bs.hip")
     roofline = {
         "bound": "alu",
-        "kernel": "k_bs_f64" if f64 else "k_bs_f32",
+        "kernel": head["bs_kernel"]["name"],
         "achieved": round(achieved, 3),
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": traffic_record(src, cfg["name"]) if lat["precision"] == "f32" else None,
-        "avg_launch_us": round(bs_iso_ms * 1e3, 2),
-        "pairs_per_launch": int(pairs_iso),
+        "traffic": None if f64 else traffic_record(src, cfg["name"]),
+        "avg_launch_us": head["bs_kernel"]["avg_launch_us"],
+        "pairs_per_launch": head["bs_kernel"]["pairs_per_launch"],
         "flops_per_pair": FLOPS_PER_PAIR,
-        "in_step": in_step,
+        "basis": head["bs_kernel"]["basis"],
     }
-    if not f64:
-        ceiling = VALU_LANE_ISSUE_PER_S / VALU_PER_PAIR_F32
-        rate = pairs_iso / (bs_iso_ms * 1e-3)
-        roofline["issue_ceiling"] = {"valu_per_pair": VALU_PER_PAIR_F32,
-                                     "pairs_per_s": round(ceiling / 1e12, 4) * 1e12,
-                                     "frac": round(rate / ceiling, 4)}
-    b = {"f64": 8, "f32": 4, "f16": 2}[lat["precision"]]
-    lbm_bytes = 2 * 19 * b * cells
+    lbm_gbs = hx["lbm_bytes"] / (hx["lbm_us"] * 1e-6) / 1e9
+    lbm_roofline = {
+        "bound": "hbm", "kernel": "k_collide_stream",
+        "achieved": round(lbm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(lbm_gbs / PEAK_HBM_GBS, 4),
+        "bytes_per_launch": hx["lbm_bytes"],
+        "avg_launch_us": head["lbm_kernel"]["avg_launch_us"],
+        "cache_resident": head["lbm_kernel"]["cache_resident"],
+    }
     out = {
         "metric": "coupled steps/s (LBM MLUPS + Biot-Savart Gpairs/s), FP32/FP16 vs FP64; p99",
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "steps/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / K, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32"}[lat["precision"]],
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32"}[prec],
         "data": "synthetic",
         "config": {
             "workload": cfg["name"],
             "lattice": [lat["nx"], lat["ny"], lat["nz"]],
-            "precision": lat["precision"],
-            "points_start": int(n0),
-            "points_end": int(n_end),
+            "precision": prec,
+            "points_start": head["points_start"],
+            "points_end": head["points_end"],
             "walls": list(lat["walls"]),
             "mass_balance": bool(cfg["vortex"]["mass_balance"]),
             "reconnect": bool(cfg["vortex"]["reconnect"]),
+            "graph_steps": args.graph,
         },
-        "graph_steps": G,
-        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
-        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
-        "step_time_basis": (f"per graph launch of {G} steps / {G}" if G else "per step"),
-        "mlups": round(cells * K / wall / 1e6, 1),
-        "bs_gpairs_s": round(pairs / wall / 1e9, 2),
-        "bs_kernel_gpairs_s": round(pairs_iso / (bs_iso_ms * 1e-3) / 1e9, 2),
-        "lbm_kernel": {"avg_launch_us": round(lbm_iso_ms * 1e3, 2),
-                       "glups": round(cells / (lbm_iso_ms * 1e-3) / 1e9, 2),
-                       "algorithmic_GBs": round(lbm_bytes / (lbm_iso_ms * 1e-3) / 1e9, 1),
-                       "note": "20 launches back to back; this lattice fits the 256 MB last-level cache"},
+        "step_ms_p50": head["step_ms_p50"],
+        "step_ms_p99": head["step_ms_p99"],
+        "step_time_basis": head["step_time_basis"],
+        "mlups": head["mlups"],
+        "bs_gpairs_s": head["bs_gpairs_s"],
         "roofline": roofline,
+        "lbm_roofline": lbm_roofline,
+        "headline": head,
+        "rows": rows,
         "diagnostics": diagnostics,
     }
-    run.close()
-    del run
-    torch.cuda.empty_cache()
-
-    if args.copy_probe:
-        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = 2 * x.numel()
-        del x, y
-
-    if not args.no_lbm_probe:
-        out["lbm_256cubed"] = [lbm_only(torch, vlb, wl, 256, p) for p in ("f32", "f16", "f64")]
-        torch.cuda.empty_cache()
-        out["hbm_copy"] = hbm_copy(torch)
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+    out["hbm_copy"] = hbm_copy(torch)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 

@@ -203,6 +203,10 @@ class Run:
             msg = self.lib.vlb_last_error(hh)
             raise VlbError(code, msg.decode() if msg else "")
 
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr())
+
     def _dev(self, arr, shape):
         t = self.torch.as_tensor(np.ascontiguousarray(arr, dtype=np.float64)).reshape(shape)
         return t.to(self.device).contiguous()
@@ -216,18 +220,29 @@ class Run:
             self.h = None
 
     def graph(self, n_steps):
-        """Executable graph of n_steps (even) coupled steps, cached per size."""
+        """Executable graph of n_steps (even) coupled steps captured at the
+        run's current step parity (a graph replays only at the parity it was
+        captured at), cached per (size, parity)."""
         if not hasattr(self, "_graphs"):
             self._graphs = {}
-        if n_steps not in self._graphs:
+        key = (int(n_steps), self.get_step() % 2)
+        if key not in self._graphs:
             g = ctypes.c_void_p()
             self._check(self.lib.vlb_graph_create(self.h, int(n_steps), ctypes.byref(g)))
-            self._graphs[n_steps] = g
-        return self._graphs[n_steps]
+            self._graphs[key] = g
+        return self._graphs[key]
 
     def step_graph(self, n_steps):
         """Advance n_steps (even) coupled steps with one graph launch."""
-        self._check(self.lib.vlb_graph_launch(self.graph(n_steps)))
+        g = self.graph(n_steps)
+        code = self.lib.vlb_graph_launch(g)
+        if code == VLB_ESTATE:
+            # the point-array parity moved apart from the step parity (a step
+            # without filaments compacts nothing): capture again at this state
+            key = (int(n_steps), self.get_step() % 2)
+            self.lib.vlb_graph_destroy(self._graphs.pop(key))
+            code = self.lib.vlb_graph_launch(self.graph(n_steps))
+        self._check(code)
 
     def __del__(self):
         try:

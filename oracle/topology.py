@@ -36,17 +36,17 @@ def compact(pos, nxt, prv, alive):
     return pos2, nxt2, prv2
 
 
-CHAIN_LIMIT = 32
-
-
 def _deletion_flags(cand, nxt, prv):
     """Which deletion candidates go in one pass (reading R10).  Along a run
     of consecutive candidates the 1st, 3rd, 5th, ... go: candidate k is
     deleted when the number c of candidates directly before it (walking
-    back along prv, at most CHAIN_LIMIT) is even and below the limit.  A
-    loop made only of candidates is counted from its lowest index, and its
-    last point is kept when the loop length is odd.  No two neighbours are
-    ever deleted in the same pass."""
+    back along prv to the first point of the run, however long the run) is
+    even.  A loop made only of candidates is counted from its lowest index,
+    and its last point is kept when the loop length is odd.  No two
+    neighbours are ever deleted in the same pass, and a run of m candidates
+    loses ceil(m / 2) of them (a loop of L candidates floor(L / 2)), so that
+    every run is thinned in one pass however long it is (the segment-length
+    bounds of Sec. II.A hold for any resolution of the input)."""
     N = cand.shape[0]
     dele = np.zeros(N, dtype=bool)
     for k in range(N):
@@ -54,7 +54,7 @@ def _deletion_flags(cand, nxt, prv):
             continue
         c = 0
         p = prv[k]
-        while c < CHAIN_LIMIT and cand[p] and p != k:
+        while cand[p] and p != k:
             c += 1
             p = prv[p]
         if p == k:  # the whole loop (c + 1 points) is candidates
@@ -72,7 +72,7 @@ def _deletion_flags(cand, nxt, prv):
                 q = nxt[q]
             dele[k] = (pos % 2 == 0) and not (pos == L - 1 and L % 2 == 1)
         else:
-            dele[k] = (c < CHAIN_LIMIT) and (c % 2 == 0)
+            dele[k] = c % 2 == 0
     return dele
 
 

@@ -216,3 +216,69 @@ def test_compaction_renumbers_links():
     np.testing.assert_array_equal(p2, pos[6:])
     np.testing.assert_array_equal(n2, (np.arange(7) + 1) % 7)
     np.testing.assert_array_equal(q2, (np.arange(7) - 1) % 7)
+
+
+# ---- long runs of deletion candidates (reading R10: every run is thinned,
+# however long).  Hand counts: a loop of L points that are all candidates
+# loses floor(L / 2), the points at even distance from its lowest index
+# (the last one kept when L is odd); an open run of m candidates loses the
+# 1st, 3rd, ... of them, ceil(m / 2).
+
+def _fine_ring(L, spacing=0.45, centre=(16.0, 16.0, 16.0)):
+    """Regular L-gon of side ``spacing`` in the plane z = centre_z."""
+    R = spacing / (2.0 * np.sin(np.pi / L))
+    th = 2.0 * np.pi * (np.arange(L) + 0.5) / L
+    pts = np.stack([centre[0] + R * np.cos(th), centre[1] + R * np.sin(th),
+                    np.full(L, centre[2])], 1)
+    return _loop(pts)
+
+
+@pytest.mark.parametrize("L", [30, 33, 34, 40, 64])
+def test_all_candidate_ring_is_thinned(L):
+    pos, nxt, prv = _fine_ring(L)
+    # every point is a candidate: incoming side 0.45 < 0.70, chord over two
+    # sides 2 * 0.45 cos(pi / L) < 0.95
+    p2, n2, q2, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)
+    assert nd == L // 2 and ni == 0
+    keep = [k for k in range(L) if not (k % 2 == 0 and not (k == L - 1 and L % 2 == 1))]
+    np.testing.assert_array_equal(p2, pos[keep])
+    assert len(_loops_of(n2)) == 1
+    # every new side is the chord over two old sides (or one old side where
+    # the odd loop kept its last point)
+    seg = np.linalg.norm(vfm.min_image(p2[n2] - p2, LAT), axis=1)
+    assert seg.max() <= 0.95
+
+
+def test_open_run_of_forty_candidates():
+    """Arc of a circle of radius 10: 41 sides of 0.45 (points 0 .. 41), then
+    equal sides of about 0.807 closing the loop.  The candidates are points
+    1 .. 40 (incoming side 0.45 and chord over both sides <= 0.95; point 41's
+    chord includes a long side, point 0's incoming side is long): one run of
+    40, of which points 1, 3, ..., 39 go."""
+    R = 10.0
+    t1 = 2.0 * np.arcsin(0.45 / (2.0 * R))
+    rest = 2.0 * np.pi - 41 * t1
+    m = 55
+    th = np.concatenate([np.arange(42) * t1, 41 * t1 + np.arange(1, m) * rest / m])
+    pts = np.stack([16.0 + R * np.cos(th), 16.0 + R * np.sin(th), np.full(th.size, 16.0)], 1)
+    pos, nxt, prv = _loop(pts)
+    long_side = np.linalg.norm(pts[42] - pts[41])
+    assert 0.70 < long_side < 0.95
+    p2, n2, q2, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)
+    assert nd == 20 and ni == 0
+    gone = set(range(1, 40, 2))
+    keep = [k for k in range(pts.shape[0]) if k not in gone]
+    np.testing.assert_array_equal(p2, pos[keep])
+
+
+def test_shrinking_ring_keeps_the_lower_bound():
+    """Repeated passes on an over-resolved ring: each pass halves it until
+    every side is at least dxi_min (the resolution bound of Sec. II.A)."""
+    pos, nxt, prv = _fine_ring(96, spacing=0.2)
+    sizes = []
+    for _ in range(4):
+        pos, nxt, prv, nd, ni = topology.remesh(pos, nxt, prv, LAT, 0.7, 0.95)
+        sizes.append(pos.shape[0])
+    assert sizes[:2] == [48, 24]
+    seg = np.linalg.norm(vfm.min_image(pos[nxt] - pos, LAT), axis=1)
+    assert seg.min() >= 0.7 and seg.max() <= 0.95

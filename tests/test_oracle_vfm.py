@@ -316,3 +316,59 @@ def test_friction_profile_at_constant_height():
     got = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp_uni)["sdot"]
     want = vfm.line_velocity(pos, nxt, prv, ub, None, lat, VortexParams())["sdot"]
     np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-18)
+
+
+def test_wrap_positions_mirror_and_wrap_by_hand():
+    """Reading R13: on a wall axis a point beyond the wall plane at -1/2 or
+    n - 1/2 is mirrored about that plane; on a periodic axis it is shifted
+    by one length into [0, n).  Hand values (8 nodes, walls on x only)."""
+    lat = Lattice(8, 8, 8, walls=(True, False, False))
+    pos = np.array([[-0.7, -0.25, 3.0],
+                    [7.9, 8.5, 8.0],
+                    [3.2, 7.99, -8.0],
+                    [-0.5, 0.0, 7.5]])
+    got = vfm.wrap_positions(pos, lat)
+    want = np.array([[-0.3, 7.75, 3.0],
+                     [7.1, 0.5, 0.0],
+                     [3.2, 7.99, 0.0],
+                     [-0.5, 0.0, 7.5]])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+
+
+def test_applied_superflow_straight_line_by_hand():
+    """A straight periodic line along z induces nothing on itself, so with
+    an applied superflow v_s,a = (a, 0, 0) (Sec. II.A, Eq. Biot-Savart) and a
+    normal fluid at rest its points move with Eq. (E of M) at
+    (a (1 - alpha'), -alpha a, 0): the applied term enters v_s once, with
+    its sign, and the two friction terms rotate it about s' = z."""
+    a, alpha, alpha_p = 0.003, 0.2, 0.05
+    lat = Lattice(16, 16, 16)
+    n = 16
+    pos = np.stack([np.full(n, 5.3), np.full(n, 7.1), (np.arange(n) + 0.5)], 1)
+    nxt = (np.arange(n) + 1) % n
+    prv = coupled.prev_from_next(nxt)
+    vp = VortexParams(alpha=alpha, alpha_p=alpha_p, vs_applied=(a, 0.0, 0.0))
+    out = vfm.line_velocity(pos, nxt, prv, np.zeros((3,) + lat.shape), None, lat, vp)
+    np.testing.assert_allclose(out["vs"], np.tile([a, 0.0, 0.0], (n, 1)), rtol=0, atol=1e-17)
+    np.testing.assert_allclose(out["sdot"], np.tile([a * (1 - alpha_p), -alpha * a, 0.0], (n, 1)),
+                               rtol=0, atol=1e-17)
+
+
+def test_applied_superflow_galilean_shift():
+    """Adding the same uniform velocity D to the applied superflow and to the
+    normal fluid shifts v_s, v_n and ds/dt by D and leaves the
+    mutual-friction force unchanged (it depends on ds/dt - v_s and
+    v_n - v_s only)."""
+    lat, pos, nxt, prv = _ring_state(64, L=32, center=(16.0, 16.0, 16.0),
+                                     normal=(0.3, -0.5, 0.8))
+    rng = np.random.Generator(np.random.PCG64(9))
+    ub = rng.normal(0.0, 0.01, size=(3,) + lat.shape)
+    D = np.array([0.004, -0.002, 0.007])
+    vp0 = VortexParams(alpha=0.25, alpha_p=0.015)
+    vp1 = VortexParams(alpha=0.25, alpha_p=0.015, vs_applied=tuple(D))
+    o0 = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp0, want_force=True)
+    o1 = vfm.line_velocity(pos, nxt, prv, ub + D[:, None, None, None], None, lat, vp1,
+                           want_force=True)
+    for k in ("vs", "vn", "sdot"):
+        np.testing.assert_allclose(o1[k], o0[k] + D[None, :], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(o1["force"], o0["force"], rtol=0, atol=1e-15)

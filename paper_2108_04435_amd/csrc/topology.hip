@@ -179,12 +179,14 @@ __global__ void k_reset_stats(int32_t* cnt) {
 
 // Along each run of consecutive deletion candidates every other point is
 // deleted: candidate j goes when the number c of candidates directly before
-// it (walking back, at most kChainLimit) is even and below the limit; a
-// loop made only of candidates is counted from its lowest index and keeps
-// its last point when its length is odd.  No two neighbours are deleted.
-// Candidacy of the points walked over is evaluated on the way.  Block 0
-// also clears the step's statistics counters.
-constexpr int kChainLimit = 32;
+// it (walking back to the first point of the run, however long the run) is
+// even; a loop made only of candidates is counted from its lowest index and
+// keeps its last point when its length is odd.  No two neighbours are
+// deleted, and every run is thinned in one pass.  Candidacy of the points
+// walked over is evaluated on the way; a walk takes one round of loads per
+// point, so its latency grows with the length of the run (runs are a few
+// points long unless the input is over-resolved, and each pass halves
+// them).  Block 0 also clears the step's statistics counters.
 
 __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ pos,
                                                     const int32_t* __restrict__ nxt,
@@ -217,7 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
     double yc[3] = {yp[0], yp[1], yp[2]};  // position of p
     double ys[3] = {yj[0], yj[1], yj[2]};  // position of p's successor
     int r = clamp_index(prv[p], nc);
-    while (c < kChainLimit && p != j) {
+    // (a valid loop brings the walk back to j within n steps; the bound
+    // only guarantees termination on corrupted links)
+    while (p != j && c < n) {
       const int rr = clamp_index(prv[r], nc);
       double yr[3], e[3], f[3];
       load3(pos, nc, r, yr);
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
       const int ps = (L - tm) % L;
       dd = ((ps & 1) == 0 && !(ps == L - 1 && (L & 1))) ? 1 : 0;
     } else {
-      dd = (c < kChainLimit && (c & 1) == 0) ? 1 : 0;
+      dd = (c & 1) == 0 ? 1 : 0;
     }
   }
   del[j] = dd;

@@ -107,24 +107,83 @@ def test_coupled_steps_f64(case):
 @pytest.mark.parametrize("case", ["channel", "wide"])
 @pytest.mark.parametrize("precision", ["f32", "f16"])
 def test_coupled_steps_reduced_precision(precision, case):
+    """Step by step against the FP64 oracle: the topology (links) must be
+    the oracle's after every step, and then positions and velocity agree to
+    the precision form's tolerance."""
     cfg = CASES[case](precision)
     steps = 10
     say("coupled reduced", case, precision)
     run = vlb.run_from_config(cfg)
-    run.step(steps)
-    run.sync()
     lat, vp, st = oracle_state(cfg)
-    for _ in range(steps):
+    for k in range(steps):
+        run.step(1)
+        run.sync()
         st = coupled.coupled_step(st, lat, vp)
+        pos_g, nxt_g = run.read_filaments()
+        assert nxt_g.shape == st.nxt.shape and (nxt_g == st.nxt).all(), \
+            f"{precision} topology differs from the oracle's after step {k + 1}"
+        d = vfm.min_image(pos_g - st.pos, lat)
+        assert np.abs(d).max() < (1e-4 if precision == "f32" else 1e-2), (k, np.abs(d).max())
     _, u_g = run.read_fields()
     _, u_o = lbm.bare_velocity(st.f, lat)
     err = rel_l2(u_g, u_o)
     say("velocity", err)
     assert err <= TOL[precision]
-    pos_g, nxt_g = run.read_filaments()
-    if nxt_g.shape == st.nxt.shape and (nxt_g == st.nxt).all():
-        d = vfm.min_image(pos_g - st.pos, lat)
-        assert np.abs(d).max() < (1e-4 if precision == "f32" else 1e-2)
+
+
+def test_ring32_hundred_steps_f64():
+    """The plain small case in full: 32^3 periodic lattice, one ring of 64
+    points, 100 coupled FP64 steps against the oracle: links exact,
+    positions within 1e-10, velocity field and line velocity within 1e-10
+    (relative L2)."""
+    cfg = wl.config_ring32(precision="f64")
+    say("ring32 100 steps")
+    run = vlb.run_from_config(cfg)
+    lat, vp, st = oracle_state(cfg)
+    for _ in range(10):
+        run.step(10)
+        for _ in range(10):
+            st = coupled.coupled_step(st, lat, vp)
+        run.sync()
+        pos_g, nxt_g = run.read_filaments()
+        np.testing.assert_array_equal(nxt_g, st.nxt)
+        assert np.abs(vfm.min_image(pos_g - st.pos, lat)).max() < 1e-10
+    assert run.get_step() == 100
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) < 1e-10
+    got = run.eval_line_velocity()
+    _, ub = lbm.bare_velocity(st.f, lat)
+    ref = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, None, lat, vp, want_force=True)
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err < 1e-10, (k, err)
+    run.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["channel", "periodic"])
+def test_applied_superflow_eval(case, precision):
+    """A nonzero applied superflow v_s,a (Eq. Biot-Savart) in the line
+    velocity, the force and the spread force field."""
+    cfg = CASES[case](precision)
+    cfg["vortex"] = dict(cfg["vortex"], vs_applied=(0.004, -0.003, 0.006))
+    say("applied superflow", case, precision)
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    ref, F_o, _ = _oracle_eval(cfg)
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= TOL[precision], (k, err)
+    assert rel_l2(F_g, F_o) <= TOL[precision]
+    # the applied term is really in: without it v_s differs by about its size
+    cfg0 = dict(cfg, vortex=dict(cfg["vortex"], vs_applied=(0.0, 0.0, 0.0)))
+    ref0, _, _ = _oracle_eval(cfg0)
+    assert rel_l2(got["vs"], ref0["vs"]) > 100 * TOL[precision]
+    run.close()
 
 
 def _perturbed_rings(seed, n_rings, dims, walls, amp):
@@ -155,6 +214,53 @@ def test_remesh_exact(walls):
     assert st["deleted"] > 0 and st["inserted"] > 0
     np.testing.assert_array_equal(nxt_g, n1)
     np.testing.assert_array_equal(pos_g, p1)
+
+
+def _long_candidate_runs():
+    """Loops whose points are all deletion candidates (regular 30/33/34/40/64
+    and 150-gons of side 0.45, centred in separate places) plus one loop
+    with an open run of 40 candidates (an arc of 41 sides of 0.45 closed by
+    sides of about 0.81): the oracle thins every run, however long."""
+    loops = []
+    for i, L in enumerate((30, 33, 34, 40, 64, 150)):
+        R = 0.45 / (2.0 * np.sin(np.pi / L))
+        th = 2.0 * np.pi * (np.arange(L) + 0.5) / L
+        c = (24.0 + 0.0 * i, 24.0, 4.0 + 7.5 * i)
+        pts = np.stack([c[0] + R * np.cos(th), c[1] + R * np.sin(th), np.full(L, c[2])], 1)
+        loops.append((pts, (np.arange(L) + 1) % L))
+    R = 10.0
+    t1 = 2.0 * np.arcsin(0.45 / (2.0 * R))
+    rest = 2.0 * np.pi - 41 * t1
+    th = np.concatenate([np.arange(42) * t1, 41 * t1 + np.arange(1, 55) * rest / 55])
+    pts = np.stack([12.0 + R * np.cos(th), 12.0 + R * np.sin(th), np.full(th.size, 47.0)], 1)
+    loops.append((pts, (np.arange(th.size) + 1) % th.size))
+    return wl.concat_loops(loops)
+
+
+def test_remesh_long_runs_exact():
+    dims = (48, 48, 56)
+    lat = wl.lattice_preset(*dims, precision="f64")
+    vor = wl.vortex_preset()
+    pos, nxt = _long_candidate_runs()
+    say("remesh long runs", pos.shape[0])
+    run = vlb.Run(lat, vor, n_cap=2 * pos.shape[0])
+    run.seed(pos, nxt)
+    from tests._cases import oracle_lattice, oracle_vortex
+    olat = oracle_lattice(lat)
+    p0, n0 = vfm.wrap_positions(pos, olat), nxt
+    for rnd in range(3):
+        stats = run.apply_topology()
+        pos_g, nxt_g = run.read_filaments()
+        p0, n0, _, st = topology.topology_update(p0, n0, coupled.prev_from_next(n0), olat,
+                                                 oracle_vortex(vor))
+        say("round", rnd, "gpu", stats, "oracle", st)
+        assert stats["deleted"] == st["deleted"] and stats["inserted"] == st["inserted"]
+        np.testing.assert_array_equal(nxt_g, n0)
+        np.testing.assert_array_equal(pos_g, p0)
+        if rnd == 0:
+            # floor(L / 2) of each all-candidate loop, half the open run
+            assert st["deleted"] == 15 + 16 + 17 + 20 + 32 + 75 + 20
+    run.close()
 
 
 def test_reconnection_exact():

@@ -98,10 +98,16 @@ class Server:
         with torch.cuda.stream(self.streams[slot]):
             run = Run(cfg["lattice"], cfg["vortex"], n_cap, device=self.device.index,
                       recon_cap=self.recon_cap, stream=self.streams[slot])
-            run.write_fields(cfg["rho"], cfg["u"])
-            run.seed(cfg["pos"], cfg["nxt"])
-            if cfg["vortex"].get("alpha_z") is not None:
-                run.set_friction_profile(cfg["vortex"]["alpha_z"], cfg["vortex"]["alpha_p_z"])
+            try:
+                run.write_fields(cfg["rho"], cfg["u"])
+                run.seed(cfg["pos"], cfg["nxt"])
+                if cfg["vortex"].get("alpha_z") is not None:
+                    run.set_friction_profile(cfg["vortex"]["alpha_z"],
+                                             cfg["vortex"]["alpha_p_z"])
+            except Exception:
+                run.close()
+                run.ws = None
+                raise
         return _Active(req=req, run=run, slot=slot, remaining=int(req["steps"]), admitted=now,
                        footprint=footprint(cfg, n_cap, self.recon_cap),
                        points_start=int(cfg["pos"].shape[0]))
@@ -141,6 +147,14 @@ class Server:
         res.finished = time.perf_counter() - self.t0
         return res
 
+    def _failed(self, req, msg, admitted=0.0):
+        lat = req["cfg"]["lattice"]
+        return Result(rid=req["rid"], arrival=req["arrival"], admitted=admitted,
+                      finished=time.perf_counter() - self.t0, steps=int(req["steps"]),
+                      cells=lat["nx"] * lat["ny"] * lat["nz"],
+                      points_start=int(req["cfg"]["pos"].shape[0]), points_end=0, footprint=0,
+                      error=msg or "failed")
+
     def serve(self, requests, time_scale=1.0):
         """Run the request loop until every request is served.  ``requests``
         are dicts with rid, arrival (s from the start), steps, cfg.
@@ -150,11 +164,19 @@ class Server:
         free_slots = list(range(self.max_slots))
         used = 0
         results = []
-        fps = {r["rid"]: footprint(r["cfg"], self._n_cap(r["cfg"]), self.recon_cap) for r in requests}
-        for r in requests:
-            if fps[r["rid"]] > self.budget:
-                raise ValueError(f"request {r['rid']} needs {fps[r['rid']]} bytes, over the budget")
         self.t0 = time.perf_counter()
+        fps = {}
+        for r in list(pending):
+            # a request that cannot be served (invalid descriptors, or more
+            # memory than the whole budget) is answered with an error and
+            # does not stop the others
+            try:
+                fps[r["rid"]] = footprint(r["cfg"], self._n_cap(r["cfg"]), self.recon_cap)
+                if fps[r["rid"]] > self.budget:
+                    raise ValueError(f"needs {fps[r['rid']]} bytes, over the budget")
+            except (VlbError, ValueError) as e:
+                pending.remove(r)
+                results.append(self._failed(r, str(e)))
         while pending or active:
             now = time.perf_counter() - self.t0
             progressed = False
@@ -172,10 +194,17 @@ class Server:
                    and used + fps[pending[0]["rid"]] <= self.budget):
                 req = pending.popleft()
                 slot = free_slots.pop(0)
-                a = self._admit(req, slot, now)
+                progressed = True
+                try:
+                    a = self._admit(req, slot, now)
+                except (VlbError, ValueError, RuntimeError) as e:
+                    # e.g. seed points the library rejects: the slot is free again
+                    results.append(self._failed(req, str(e), admitted=now))
+                    free_slots.append(slot)
+                    free_slots.sort()
+                    continue
                 used += a.footprint
                 active.append(a)
-                progressed = True
             # keep every resident run busy
             for a in active:
                 if a.remaining > 0 and (a.event is None or a.event.query()):
@@ -189,8 +218,9 @@ class Server:
 
 
 def summarize(results, makespan):
-    lat = np.array([r.latency for r in results])
-    cells_steps = sum(r.cells * r.steps for r in results)
+    done = [r for r in results if not r.error]
+    lat = np.array([r.latency for r in done] or [0.0])
+    cells_steps = sum(r.cells * r.steps for r in done)
     return dict(
         requests=len(results),
         errors=sum(1 for r in results if r.error),
@@ -199,5 +229,5 @@ def summarize(results, makespan):
         latency_p50_s=round(float(np.percentile(lat, 50)), 4),
         latency_p99_s=round(float(np.percentile(lat, 99)), 4),
         aggregate_mlups=round(cells_steps / makespan / 1e6, 1),
-        steps_total=int(sum(r.steps for r in results)),
+        steps_total=int(sum(r.steps for r in done)),
     )

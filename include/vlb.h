@@ -278,6 +278,44 @@ int vlb_graph_create(vlb_run* run, int64_t n_steps, vlb_graph** out);
 int vlb_graph_launch(vlb_graph* graph);
 int vlb_graph_destroy(vlb_graph* graph);
 
+/* Stand-alone Biot-Savart sum (Sec. II.A, Eq. Biot-Savart), without a
+ * lattice: the non-local superfluid velocity of a caller's closed
+ * filaments, the same kernels as the first term of a step's line velocity.
+ * Point j receives v_j = kappa/(4 pi) times the sum, over every segment
+ * k -> next(k) except the two that touch j (k = prev(j) and k = j, the
+ * divergent local part that the LIA term replaces), of the exact integral
+ * over the straight segment, at the nearest periodic image decided on the
+ * library's 32-bit position grid.
+ *  - d: box of nx, ny, nz lattice units; an axis whose bit is set in
+ *    wall_axes is closed (no images; positions in [-1/2, n - 1/2]), the
+ *    others are periodic of length n (positions anywhere: the grid wraps).
+ *    precision VLB_F64 sums in FP64, VLB_F32 and VLB_F16 in FP32 (chunk
+ *    partials added in FP64 in a fixed order: bitwise reproducible).
+ *  - xyz_dev: device, n_pts x 3 doubles ([n][3], lattice units);
+ *    next_dev: device, n_pts int32, a permutation whose cycles are the
+ *    loops (not checked: an invalid one gives meaningless velocities, each
+ *    entry is clamped into [0, n_pts) so no access leaves the arrays);
+ *    v_dev: device output, n_pts x 3 doubles.
+ *  - dev_workspace: device scratch of at least vlb_biot_savart_workspace
+ *    bytes, 256-byte aligned, owned by the caller; the call only enqueues
+ *    work on hip_stream (NULL: the null stream) and returns: inputs,
+ *    output and workspace must stay untouched until that work completes.
+ *  - VLB_EINVAL for a bad descriptor, n_pts outside [0, 2^26] or a NULL
+ *    pointer (n_pts > 0); VLB_ENOSPACE for a small workspace; VLB_EDEVICE
+ *    if a launch fails.  Messages go to vlb_last_error(NULL).              */
+typedef struct {
+  int32_t nx, ny, nz;     /* box extent per axis, each in [1, 2^24]         */
+  uint32_t wall_axes;     /* bit a: axis a closed by walls; else periodic   */
+  int32_t precision;      /* vlb_precision of the sum                       */
+  int32_t reserved;       /* 0                                              */
+  double kappa;           /* circulation quantum, > 0                       */
+} vlb_bs_desc;
+
+int vlb_biot_savart_workspace(const vlb_bs_desc* d, int64_t n_pts, uint64_t* bytes);
+int vlb_biot_savart(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
+                    const int32_t* next_dev, double* v_dev, void* dev_workspace,
+                    uint64_t ws_bytes, void* hip_stream);
+
 /* Release the host handle.  The workspace is the caller's to free.         */
 int vlb_destroy(vlb_run* run);
 

@@ -35,7 +35,8 @@ SYMBOLS = [
     "vlb_set_friction_profile", "vlb_line_length",
     "vlb_flow_stats", "vlb_read_vorticity", "vlb_vorticity_cylindrical", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
-    "vlb_graph_launch", "vlb_graph_destroy", "vlb_destroy", "vlb_last_error",
+    "vlb_graph_launch", "vlb_graph_destroy", "vlb_biot_savart_workspace", "vlb_biot_savart",
+    "vlb_destroy", "vlb_last_error",
 ]
 
 
@@ -64,6 +65,14 @@ class VortexDesc(ctypes.Structure):
         ("min_loop_pts", ctypes.c_int32), ("coupling", ctypes.c_int32),
         ("mass_balance", ctypes.c_int32), ("force_model", ctypes.c_int32),
         ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
+    ]
+
+
+class BsDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("wall_axes", ctypes.c_uint32), ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("kappa", ctypes.c_double),
     ]
 
 
@@ -117,6 +126,10 @@ def load_library(path=None):
     lib.vlb_graph_create.argtypes = [vp, i64, ctypes.POINTER(vp)]
     lib.vlb_graph_launch.argtypes = [vp]
     lib.vlb_graph_destroy.argtypes = [vp]
+    lib.vlb_biot_savart_workspace.argtypes = [ctypes.POINTER(BsDesc), i64,
+                                              ctypes.POINTER(ctypes.c_uint64)]
+    lib.vlb_biot_savart.argtypes = [ctypes.POINTER(BsDesc), i64, vp, vp, vp, vp,
+                                    ctypes.c_uint64, vp]
     lib.vlb_destroy.argtypes = [vp]
     lib.vlb_last_error.argtypes = [vp]
     lib.vlb_last_error.restype = ctypes.c_char_p
@@ -234,15 +247,7 @@ class Run:
 
     def step_graph(self, n_steps):
         """Advance n_steps (even) coupled steps with one graph launch."""
-        g = self.graph(n_steps)
-        code = self.lib.vlb_graph_launch(g)
-        if code == VLB_ESTATE:
-            # the point-array parity moved apart from the step parity (a step
-            # without filaments compacts nothing): capture again at this state
-            key = (int(n_steps), self.get_step() % 2)
-            self.lib.vlb_graph_destroy(self._graphs.pop(key))
-            code = self.lib.vlb_graph_launch(self.graph(n_steps))
-        self._check(code)
+        self._check(self.lib.vlb_graph_launch(self.graph(n_steps)))
 
     def __del__(self):
         try:
@@ -395,6 +400,51 @@ class Run:
         b = ctypes.c_int64(0)
         self._check(self.lib.vlb_get_work(self.h, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+
+def bs_desc(dims, walls=(False, False, False), kappa=0.1, precision="f64") -> BsDesc:
+    d = BsDesc()
+    d.nx, d.ny, d.nz = (int(x) for x in dims)
+    d.wall_axes = sum(1 << a for a in range(3) if walls[a])
+    d.precision = PRECISION[precision]
+    d.reserved = 0
+    d.kappa = float(kappa)
+    return d
+
+
+def _raise(lib, code):
+    if code != VLB_OK:
+        msg = lib.vlb_last_error(None)
+        raise VlbError(code, msg.decode() if msg else "")
+
+
+def biot_savart(xyz, nxt, dims, walls=(False, False, False), kappa=0.1, precision="f64",
+                device=0):
+    """Non-local Biot-Savart velocity of closed filaments (vlb_biot_savart):
+    ``xyz`` (n, 3) positions, ``nxt`` (n,) successor links; returns (n, 3)
+    velocities as a host array.  Device buffers and the workspace are torch
+    tensors; the work runs on torch's current stream."""
+    import torch
+
+    lib = load_library()
+    dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+    d = bs_desc(dims, walls, kappa, precision)
+    p = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)).to(dev)
+    q = torch.as_tensor(np.ascontiguousarray(nxt, dtype=np.int32).reshape(-1)).to(dev)
+    n = p.shape[0]
+    nb = ctypes.c_uint64(0)
+    _raise(lib, lib.vlb_biot_savart_workspace(ctypes.byref(d), n, ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=dev)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    v = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    _raise(lib, lib.vlb_biot_savart(ctypes.byref(d), n, ctypes.c_void_p(p.data_ptr()),
+                                    ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                    ctypes.c_void_p(wp), ctypes.c_uint64(int(nb.value)),
+                                    ctypes.c_void_p(stream.cuda_stream)))
+    out = v.cpu().numpy()   # synchronises the stream
+    del ws
+    return out
 
 
 def run_from_config(cfg: dict, n_cap=None, device=0, recon_cap=1 << 16):

@@ -187,48 +187,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   g.omega = 1.0 / lat->tau;
   g.fpref = 1.0 - 1.0 / (2.0 * lat->tau);
   const int n[3] = {g.nx, g.ny, g.nz};
-  for (int a = 0; a < 3; ++a) {
-    BsAxes& ax = r.bsax;
-    ax.L[a] = (double)n[a];
-    ax.periodic[a] = !g.wall[a];
-    if (ax.periodic[a]) {
-      ax.q[a] = 4294967296.0 / (double)n[a];
-      ax.off[a] = 0.0;
-      ax.invq_d[a] = (double)n[a] / 4294967296.0;
-    } else {
-      int k = 0;
-      while ((double)(n[a] + 2) * std::ldexp(1.0, k + 1) <= 2147483648.0) ++k;
-      ax.q[a] = std::ldexp(1.0, k);
-      ax.off[a] = 1.0;
-      ax.invq_d[a] = std::ldexp(1.0, -k);
-    }
-    ax.invq_f[a] = (float)ax.invq_d[a];
-  }
-  {
-    // one power-of-two grid step for all axes when every periodic axis has
-    // the same power-of-two length and the wall axes fit that step
-    BsAxes& ax = r.bsax;
-    double q = 0.0;
-    for (int a = 0; a < 3; ++a)
-      if (ax.periodic[a]) q = ax.q[a];
-    if (q == 0.0)
-      for (int a = 0; a < 3; ++a) q = (q == 0.0 || ax.q[a] < q) ? ax.q[a] : q;
-    int ex = 0;
-    bool ok = std::frexp(q, &ex) == 0.5;
-    for (int a = 0; a < 3 && ok; ++a) {
-      if (ax.periodic[a])
-        ok = ax.q[a] == q;
-      else
-        ok = (double)(n[a] + 2) * q <= 2147483648.0;
-    }
-    ax.uniform = ok ? 1 : 0;
-    if (ok)
-      for (int a = 0; a < 3; ++a) {
-        ax.q[a] = q;
-        ax.invq_d[a] = 1.0 / q;
-        ax.invq_f[a] = (float)ax.invq_d[a];
-      }
-  }
+  r.bsax = bs_make_axes(n, g.wall);
   r.bsS = bs_chunks(r.ncap);
   // spreading bins: lower stencil corner, n (+1 on wall axes) per axis
   const unsigned long long ext = (unsigned long long)(n[0] + g.wall[0]) * (n[1] + g.wall[1]) * (n[2] + g.wall[2]);
@@ -253,6 +212,8 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
 }  // namespace
 
 namespace vlb {
+
+int fail_global(int code, const std::string& msg) { return fail(nullptr, code, msg); }
 
 // Events come from a pool filled by vlb_set_timing, so that timing a run
 // creates no events inside the timed region (the pool grows if it runs dry).
@@ -960,6 +921,37 @@ int vlb_destroy(vlb_run* h) {
   drop_events(h->r);
   release_streams(h->r);
   delete h;
+  return VLB_OK;
+}
+
+int vlb_biot_savart_workspace(const vlb_bs_desc* d, int64_t n_pts, uint64_t* bytes) {
+  std::string msg;
+  const int c = bs_check_desc(d, n_pts, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (!bytes) return fail(nullptr, VLB_EINVAL, "bytes is NULL");
+  *bytes = n_pts > 0 ? (uint64_t)bs_solo_layout(d->precision, n_pts, nullptr, nullptr) : 0;
+  return VLB_OK;
+}
+
+int vlb_biot_savart(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
+                    const int32_t* next_dev, double* v_dev, void* dev_workspace,
+                    uint64_t ws_bytes, void* hip_stream) {
+  std::string msg;
+  const int c = bs_check_desc(d, n_pts, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (n_pts == 0) return VLB_OK;
+  if (!xyz_dev || !next_dev || !v_dev || !dev_workspace)
+    return fail(nullptr, VLB_EINVAL, "null device pointer");
+  if ((uintptr_t)dev_workspace % 256) return fail(nullptr, VLB_EINVAL, "workspace not 256-byte aligned");
+  BsSolo b;
+  const size_t need = bs_solo_layout(d->precision, n_pts, (char*)dev_workspace, &b);
+  if (ws_bytes < need) return fail(nullptr, VLB_ENOSPACE, "workspace smaller than vlb_biot_savart_workspace");
+  const int n[3] = {d->nx, d->ny, d->nz};
+  const int wall[3] = {(int)(d->wall_axes & 1u), (int)((d->wall_axes >> 1) & 1u),
+                       (int)((d->wall_axes >> 2) & 1u)};
+  const hipError_t e = bs_solo(bs_make_axes(n, wall), d->precision, n_pts, xyz_dev, next_dev,
+                               d->kappa, v_dev, b, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "vlb_biot_savart");
   return VLB_OK;
 }
 

@@ -20,6 +20,8 @@
 //    the chunks in a fixed order (no atomics, bitwise reproducible).
 #include "vlb_internal.h"
 
+#include <cmath>
+
 namespace vlb {
 
 namespace {
@@ -329,7 +331,113 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   }
 }
 
+// ---- standalone sum (positions and links from the caller, no run)
+
+// Links and grid data of a caller's filaments: next is clamped into [0, n)
+// (an invalid permutation gives meaningless velocities, never an access out
+// of bounds) and inverted into prev; grid coordinates and, for the FP64
+// sum, segment vectors and residuals as k_prep, from [n][3] positions.
+// Thread 0 writes the point count and clears the pair counter.
+template <class T>
+__global__ void k_solo_prep(const double* __restrict__ xyz, const int32_t* __restrict__ next,
+                            int n, BsAxes ax, int32_t* __restrict__ cnt,
+                            uint32_t* __restrict__ X, T* __restrict__ D,
+                            int32_t* __restrict__ nxt, int32_t* __restrict__ prv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) {
+    cnt[0] = n;
+    for (int i = 1; i < 32; ++i) cnt[i] = 0;
+  }
+  if (j >= n) return;
+  const int k = min(max(next[j], 0), n - 1);
+  nxt[j] = k;
+  prv[k] = j;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double y = xyz[3LL * j + a];
+    const double s = floor((y + ax.off[a]) * ax.q[a]);
+    X[(long long)a * n + j] = ax.periodic[a] ? (uint32_t)(long long)s
+                                             : (uint32_t)(int)(long long)s;
+    if (sizeof(T) == 8) {
+      double d = xyz[3LL * k + a] - y;
+      if (ax.periodic[a]) {
+        if (d > 0.5 * ax.L[a])
+          d = d - ax.L[a];
+        else if (d < -0.5 * ax.L[a])
+          d = d + ax.L[a];
+      }
+      D[(long long)a * n + j] = (T)d;
+      D[(long long)(3 + a) * n + j] = (T)((y + ax.off[a]) - s * ax.invq_d[a]);
+    }
+  }
+}
+
+// v[j][a] = scale * (sum over the S chunk partials of target j, in chunk
+// order, in FP64).
+template <class PT>
+__global__ void k_solo_sum(const PT* __restrict__ P, int S, int n, double scale,
+                           double* __restrict__ v) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double t = 0.0;
+    for (int c = 0; c < S; ++c) t += (double)P[((long long)c * 3 + a) * n + j];
+    v[3LL * j + a] = t * scale;
+  }
+}
+
 }  // namespace
+
+// Grid of the Biot-Savart sum on a box of n[a] nodes per axis (wall[a]: the
+// axis is closed, positions in [-1/2, n - 1/2]; else periodic of length
+// n[a]): periodic axes map [0, L) onto the whole 32-bit range, so that
+// separations wrap exactly; wall axes use a power-of-two step with room
+// for [-1, n + 1).
+BsAxes bs_make_axes(const int n[3], const int wall[3]) {
+  BsAxes ax{};
+  for (int a = 0; a < 3; ++a) {
+    ax.L[a] = (double)n[a];
+    ax.periodic[a] = !wall[a];
+    if (ax.periodic[a]) {
+      ax.q[a] = 4294967296.0 / (double)n[a];
+      ax.off[a] = 0.0;
+      ax.invq_d[a] = (double)n[a] / 4294967296.0;
+    } else {
+      int k = 0;
+      while ((double)(n[a] + 2) * std::ldexp(1.0, k + 1) <= 2147483648.0) ++k;
+      ax.q[a] = std::ldexp(1.0, k);
+      ax.off[a] = 1.0;
+      ax.invq_d[a] = std::ldexp(1.0, -k);
+    }
+    ax.invq_f[a] = (float)ax.invq_d[a];
+  }
+  {
+    // one power-of-two grid step for all axes when every periodic axis has
+    // the same power-of-two length and the wall axes fit that step
+    double q = 0.0;
+    for (int a = 0; a < 3; ++a)
+      if (ax.periodic[a]) q = ax.q[a];
+    if (q == 0.0)
+      for (int a = 0; a < 3; ++a) q = (q == 0.0 || ax.q[a] < q) ? ax.q[a] : q;
+    int ex = 0;
+    bool ok = std::frexp(q, &ex) == 0.5;
+    for (int a = 0; a < 3 && ok; ++a) {
+      if (ax.periodic[a])
+        ok = ax.q[a] == q;
+      else
+        ok = (double)(n[a] + 2) * q <= 2147483648.0;
+    }
+    ax.uniform = ok ? 1 : 0;
+    if (ok)
+      for (int a = 0; a < 3; ++a) {
+        ax.q[a] = q;
+        ax.invq_d[a] = 1.0 / q;
+        ax.invq_f[a] = (float)ax.invq_d[a];
+      }
+  }
+  return ax;
+}
 
 // Source chunks S: about 16384 blocks over the target blocks, at least 256
 // sources per chunk (64 per wave), at most 256 chunks; the chunk partials
@@ -374,6 +482,78 @@ hipError_t bs_sum(Run& r) {
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
                        r.bsax.invq_f[2], (float*)r.bsP);
   time_end(r, 0, b);
+  return hipGetLastError();
+}
+
+int bs_check_desc(const vlb_bs_desc* d, int64_t n, std::string& msg) {
+  if (!d) { msg = "null descriptor"; return VLB_EINVAL; }
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > (1 << 24) || d->ny > (1 << 24) ||
+      d->nz > (1 << 24)) { msg = "box dimensions must be in [1, 2^24]"; return VLB_EINVAL; }
+  if (d->wall_axes & ~7u) { msg = "wall_axes uses bits 0..2 only"; return VLB_EINVAL; }
+  if (d->precision < 0 || d->precision > 2) { msg = "precision must be VLB_F64, VLB_F32 or VLB_F16"; return VLB_EINVAL; }
+  if (!(d->kappa > 0) || !std::isfinite(d->kappa)) { msg = "kappa must be positive and finite"; return VLB_EINVAL; }
+  if (n < 0 || n > kSoloMaxPoints) { msg = "n_pts must be in [0, 2^26]"; return VLB_EINVAL; }
+  return VLB_OK;
+}
+
+// Standalone sum: the chunk count, scratch layout and launches.  The
+// chunks are capped at kSoloChunks, so that the scratch of the largest
+// allocation-free call stays small.
+constexpr int kSoloChunks = 8;
+
+int bs_solo_chunks(long long n) {
+  const int S = bs_chunks(n);
+  return S < kSoloChunks ? S : kSoloChunks;
+}
+
+size_t bs_solo_layout(int prec, long long n, char* base, BsSolo* b) {
+  const size_t fe = prec == VLB_F64 ? 8 : 4;
+  const int S = bs_solo_chunks(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    off = (off + 255) / 256 * 256;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  BsSolo s{};
+  s.cnt = (int32_t*)take(32 * sizeof(int32_t));
+  s.X = (uint32_t*)take(3 * (size_t)n * sizeof(uint32_t));
+  s.D = take((prec == VLB_F64 ? 6 : 1) * (size_t)n * fe);
+  s.nxt = (int32_t*)take((size_t)n * sizeof(int32_t));
+  s.prv = (int32_t*)take((size_t)n * sizeof(int32_t));
+  s.P = take((size_t)S * 3 * n * fe);
+  s.S = S;
+  if (b) *b = s;
+  return (off + 255) / 256 * 256;
+}
+
+hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
+                   const int32_t* next, double kappa, double* v, const BsSolo& b,
+                   hipStream_t stream) {
+  const int nb = (int)((n + 255) / 256);
+  const int tb = (int)((n + kTargets - 1) / kTargets);
+  const dim3 grid(tb, b.S);
+  const double s = kappa / (4.0 * M_PI);
+  if (prec == VLB_F64) {
+    hipLaunchKernelGGL(k_solo_prep<double>, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n,
+                       ax, b.cnt, b.X, (double*)b.D, b.nxt, b.prv);
+    hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, stream, b.X, (const double*)b.D, b.prv,
+                       b.cnt, n, b.S, ax.invq_d[0], ax.invq_d[1], ax.invq_d[2], (double*)b.P);
+    hipLaunchKernelGGL(k_solo_sum<double>, dim3(nb), dim3(256), 0, stream, (const double*)b.P,
+                       b.S, (int)n, s, v);
+  } else {
+    hipLaunchKernelGGL(k_solo_prep<float>, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n,
+                       ax, b.cnt, b.X, (float*)b.D, b.nxt, b.prv);
+    if (ax.uniform)
+      hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P);
+    else
+      hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P);
+    hipLaunchKernelGGL(k_solo_sum<float>, dim3(nb), dim3(256), 0, stream, (const float*)b.P,
+                       b.S, (int)n, ax.uniform ? s * ax.q[0] : s, v);
+  }
   return hipGetLastError();
 }
 

@@ -437,6 +437,29 @@ hipError_t diag_curl(Run& r, const double* u, double* w);
 hipError_t diag_cylindrical(Run& r, const double point[3], const double unit_dir[3],
                             const double* w, double* out);
 
+BsAxes bs_make_axes(const int n[3], const int wall[3]);
+
+// Scratch of the standalone Biot-Savart sum (vlb_biot_savart*): point
+// count and pair counter, grid coordinates, FP64 segment data, sanitised
+// links, chunk partials.
+struct BsSolo {
+  int32_t* cnt;
+  uint32_t* X;
+  void* D;
+  int32_t* nxt;
+  int32_t* prv;
+  void* P;
+  int S;
+};
+constexpr long long kSoloMaxPoints = 1LL << 26;
+int bs_check_desc(const vlb_bs_desc* d, int64_t n, std::string& msg);
+int bs_solo_chunks(long long n);
+size_t bs_solo_layout(int prec, long long n, char* base, BsSolo* b);
+hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
+                   const int32_t* next, double kappa, double* v, const BsSolo& b,
+                   hipStream_t stream);
+// Error message of a call without a run (vlb_last_error(NULL)); returns code.
+int fail_global(int code, const std::string& msg);
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r);
 int bs_chunks(long long ncap);

@@ -48,6 +48,8 @@ int main(void) {
   O(vlb_lattice_desc, tau); O(vlb_lattice_desc, wall_axes); O(vlb_lattice_desc, plane_u);
   O(vlb_lattice_desc, body_force); O(vlb_vortex_desc, vs_applied); O(vlb_vortex_desc, remesh);
   O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap);
+  printf("bs %zu\n", sizeof(vlb_bs_desc));
+  O(vlb_bs_desc, wall_axes); O(vlb_bs_desc, precision); O(vlb_bs_desc, kappa);
   return 0;
 }
 '''
@@ -60,10 +62,13 @@ int main(void) {
     vals = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     assert int(vals["lat"]) == ctypes.sizeof(vlb.LatticeDesc)
     assert int(vals["vor"]) == ctypes.sizeof(vlb.VortexDesc)
+    assert int(vals["bs"]) == ctypes.sizeof(vlb.BsDesc)
+    classes = {"vlb_lattice_desc": vlb.LatticeDesc, "vlb_vortex_desc": vlb.VortexDesc,
+               "vlb_bs_desc": vlb.BsDesc}
     for key, v in vals.items():
         if "." in key:
             st, f = key.split(".")
-            cls = vlb.LatticeDesc if st == "vlb_lattice_desc" else vlb.VortexDesc
+            cls = classes[st]
             assert getattr(cls, f).offset == int(v), key
 
 
@@ -127,3 +132,42 @@ def test_mass_balance_needs_periodic_z():
 def test_zero_capacity_rejected():
     code, _, err = _query(wl.lattice_preset(16, 16, 16), wl.vortex_preset(), n_cap=0)
     assert code == vlb.VLB_EINVAL
+
+
+def _bs_query(n, **kw):
+    lib = vlb.load_library()
+    args = dict(dims=(32, 32, 32), walls=(False, False, False), kappa=0.1, precision="f32")
+    args.update(kw)
+    d = vlb.bs_desc(**args)
+    nb = ctypes.c_uint64(0)
+    code = lib.vlb_biot_savart_workspace(ctypes.byref(d), n, ctypes.byref(nb))
+    return code, nb.value, lib.vlb_last_error(None).decode()
+
+
+def test_biot_savart_workspace_query():
+    code, small, _ = _bs_query(1000)
+    assert code == vlb.VLB_OK and small > 0
+    code, big, _ = _bs_query(100000)
+    assert code == vlb.VLB_OK and big > 50 * small
+    code, f64, _ = _bs_query(1000, precision="f64")
+    assert f64 > small
+    assert _bs_query(0)[:2] == (vlb.VLB_OK, 0)
+
+
+@pytest.mark.parametrize("kw,n,msg", [
+    (dict(kappa=0.0), 10, "kappa"),
+    (dict(dims=(0, 8, 8)), 10, "box"),
+    (dict(), -1, "n_pts"),
+    (dict(), (1 << 26) + 1, "n_pts"),
+])
+def test_biot_savart_invalid_rejected(kw, n, msg):
+    code, _, err = _bs_query(n, **kw)
+    assert code == vlb.VLB_EINVAL and msg in err
+
+
+def test_biot_savart_null_pointers_rejected():
+    lib = vlb.load_library()
+    d = vlb.bs_desc((8, 8, 8))
+    code = lib.vlb_biot_savart(ctypes.byref(d), 10, None, None, None, None, 0, None)
+    assert code == vlb.VLB_EINVAL
+    assert "null" in lib.vlb_last_error(None).decode()

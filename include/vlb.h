@@ -316,6 +316,21 @@ int vlb_biot_savart(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
                     const int32_t* next_dev, double* v_dev, void* dev_workspace,
                     uint64_t ws_bytes, void* hip_stream);
 
+/* Allocation-free vlb_biot_savart, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the same sum, kernels and bits as vlb_biot_savart, with its
+ * scratch (grid coordinates, links, chunk partials) in a fixed device array
+ * of the library (about 4.5 MB per GPU, held until the process ends)
+ * instead of a caller workspace.  Arguments as vlb_biot_savart; call with
+ * the GPU of hip_stream current.  n_pts is limited to 16384 (VLB_EINVAL
+ * above).  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (other streams, other threads) race and give wrong
+ * results; calls ordered on one stream are safe.  The call itself
+ * allocates nothing (the first call on a device looks up the array's
+ * address, also nothing allocated).                                        */
+int vlb_biot_savart_noalloc(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
+                            const int32_t* next_dev, double* v_dev, void* hip_stream);
+
 /* Release the host handle.  The workspace is the caller's to free.         */
 int vlb_destroy(vlb_run* run);
 

@@ -36,7 +36,7 @@ SYMBOLS = [
     "vlb_flow_stats", "vlb_read_vorticity", "vlb_vorticity_cylindrical", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
     "vlb_graph_launch", "vlb_graph_destroy", "vlb_biot_savart_workspace", "vlb_biot_savart",
-    "vlb_destroy", "vlb_last_error",
+    "vlb_biot_savart_noalloc", "vlb_destroy", "vlb_last_error",
 ]
 
 
@@ -130,6 +130,7 @@ def load_library(path=None):
                                               ctypes.POINTER(ctypes.c_uint64)]
     lib.vlb_biot_savart.argtypes = [ctypes.POINTER(BsDesc), i64, vp, vp, vp, vp,
                                     ctypes.c_uint64, vp]
+    lib.vlb_biot_savart_noalloc.argtypes = [ctypes.POINTER(BsDesc), i64, vp, vp, vp, vp]
     lib.vlb_destroy.argtypes = [vp]
     lib.vlb_last_error.argtypes = [vp]
     lib.vlb_last_error.restype = ctypes.c_char_p

@@ -113,6 +113,23 @@ def traffic_record(kernel_src, workload):
     return rec.get("bytes_per_launch")
 
 
+def valu_record(kernel_src, workload):
+    """Measured shader clock and VALU issue rate of the Biot-Savart kernel
+    from committed rocprofv3 counter runs (SQ_INSTS_VALU, GRBM_GUI_ACTIVE),
+    if taken on the current source and on this workload."""
+    path = os.path.join(ROOT, "profiles", "k_bs_f32_valu.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha") != h or rec.get("workload") != workload:
+        return None
+    return {"clock_ghz": rec["clock_ghz"],
+            "valu_wave_instr_per_cu_cycle": rec["valu_wave_instr_per_cu_cycle"],
+            "note": "one wave64 VALU instruction per CU per cycle is the issue limit without "
+                    "packed FP32; transcendentals issue beside the others"}
+
+
 # ----------------------------------------------------------------- oracle leg
 # Everything under oracle/ is called from this leg only: the oracle is timed
 # on a bounded sample of the workload, and its values on that sample are
@@ -473,7 +490,7 @@ def serve_bench(args):
 
     reqs = wl.serving_requests(seed=5, n_requests=args.serve_requests)
     srv = serve.Server(budget_bytes=int(args.serve_budget_gb * (1 << 30)),
-                       max_slots=args.serve_slots, chunk=10)
+                       max_slots=args.serve_slots, chunk=10, group=not args.serve_per_run_graphs)
     res, makespan = srv.serve(reqs)
     s = serve.summarize(res, makespan)
     pairs = sum(r.steps * 4 * r.points_start * (r.points_start - 2) for r in res)
@@ -486,7 +503,8 @@ def serve_bench(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "serving_64_requests_poisson_2_per_s",
-                   "budget_gb": args.serve_budget_gb, "slots": args.serve_slots, "chunk": 10},
+                   "budget_gb": args.serve_budget_gb, "slots": args.serve_slots, "chunk": 10,
+                   "grouped_step_many": not args.serve_per_run_graphs},
         **s,
         "approx_bs_gpairs_s": round(pairs / makespan / 1e9, 1),
         "arrival_span_s": round(max(r["arrival"] for r in reqs), 2),
@@ -512,6 +530,9 @@ def parse_args(argv=None):
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-per-run-graphs", action="store_true",
+                    help="served form: each run launches its own chunk graph instead of the idle "
+                         "runs advancing together (one vlb_step_many call per chunk)")
     args = ap.parse_args(argv)
     if args.steps < 1 or args.warmup < 0:
         ap.error("--steps must be >= 1 and --warmup >= 0")
@@ -603,6 +624,7 @@ def main(argv=None):
         "pairs_per_launch": head["bs_kernel"]["pairs_per_launch"],
         "flops_per_pair": FLOPS_PER_PAIR,
         "basis": head["bs_kernel"]["basis"],
+        "issue": None if f64 else valu_record(src, cfg["name"]),
     }
     lbm_gbs = hx["lbm_bytes"] / (hx["lbm_us"] * 1e-6) / 1e9
     lbm_roofline = {

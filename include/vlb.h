@@ -143,6 +143,15 @@ int vlb_seed_vortices(vlb_run* run, int64_t n_pts, const double* xyz_host,
  * stream, with event dependencies where the two parts exchange data.      */
 int vlb_step(vlb_run* run, int64_t n_steps);
 
+/* Several runs advanced together (the served form): n_steps coupled steps
+ * of each of the n_runs distinct runs, enqueued step by step across the
+ * runs (step s of every run before step s + 1 of any), each run on its own
+ * stream, so that runs on different streams overlap on the GPU.  Each
+ * run's result is the one vlb_step(run, n_steps) gives, bit for bit.
+ * Returns after enqueueing; the first failing run's code is returned
+ * (runs before it may have been advanced).                                 */
+int vlb_step_many(vlb_run* const* runs, int32_t n_runs, int64_t n_steps);
+
 /* Wait for the run's streams; return a latched device error if any.       */
 int vlb_sync(vlb_run* run);
 
@@ -157,6 +166,22 @@ int vlb_read_fields(vlb_run* run, double* rho_dev, double* u_dev);
  * (-1,+1,0), (+1,0,+1),(-1,0,-1),(+1,0,-1),(-1,0,+1), (0,+1,+1),(0,-1,-1),
  * (0,+1,-1),(0,-1,+1).                                                      */
 int vlb_read_populations(vlb_run* run, double* f_dev);
+
+/* Checkpoint of the normal fluid: the stored populations as they are kept
+ * (deviations f_i - w_i in the run's precision: FP64, FP32, or FP16 scaled
+ * by 2^10), population-major in the D3Q19 order above, natural layout
+ * (population i of node c at index i * cells + c); device output of
+ * 19 * cells elements of 8, 4 or 2 bytes.  Together with
+ * vlb_read_filaments and vlb_get_step this is the whole state of a run:
+ * vlb_write_state and vlb_seed_vortices (and the friction profile, if one
+ * was set) on a run created with the same descriptors continue it bit for
+ * bit.  Synchronises the run's stream.                                     */
+int vlb_read_state(vlb_run* run, void* pops_dev);
+
+/* Restore populations saved by vlb_read_state (device input, same size and
+ * format) and set the step counter to step (>= 0); clears the spread force
+ * field, as vlb_write_fields.  Synchronises the run's stream.              */
+int vlb_write_state(vlb_run* run, const void* pops_dev, int64_t step);
 
 /* The force field spread by the last step (or vlb_eval_line_velocity):
  * device output of 3*cells doubles (body force not included).               */

@@ -30,7 +30,8 @@ PRECISION = {"f64": 0, "f32": 1, "f16": 2}
 # Exported symbols, in the order of include/vlb.h.
 SYMBOLS = [
     "vlb_query_footprint", "vlb_create_lattice", "vlb_write_fields", "vlb_seed_vortices",
-    "vlb_step", "vlb_sync", "vlb_read_fields", "vlb_read_populations", "vlb_read_force",
+    "vlb_step", "vlb_step_many", "vlb_sync", "vlb_read_fields", "vlb_read_populations",
+    "vlb_read_state", "vlb_write_state", "vlb_read_force",
     "vlb_read_filaments", "vlb_eval_line_velocity", "vlb_apply_topology",
     "vlb_set_friction_profile", "vlb_line_length",
     "vlb_flow_stats", "vlb_read_vorticity", "vlb_vorticity_cylindrical", "vlb_get_step",
@@ -106,6 +107,9 @@ def load_library(path=None):
     lib.vlb_write_fields.argtypes = [vp, vp, vp]
     lib.vlb_seed_vortices.argtypes = [vp, i64, vp, vp]
     lib.vlb_step.argtypes = [vp, i64]
+    lib.vlb_step_many.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64]
+    lib.vlb_read_state.argtypes = [vp, vp]
+    lib.vlb_write_state.argtypes = [vp, vp, i64]
     lib.vlb_sync.argtypes = [vp]
     lib.vlb_read_fields.argtypes = [vp, vp, vp]
     lib.vlb_read_populations.argtypes = [vp, vp]
@@ -288,6 +292,22 @@ class Run:
         self._check(self.lib.vlb_read_populations(self.h, ctypes.c_void_p(f.data_ptr())))
         return f.cpu().numpy()
 
+    def state_bytes(self):
+        return 19 * self.cells * {0: 8, 1: 4, 2: 2}[self.ld.precision]
+
+    def read_state(self):
+        """(stored populations as a device uint8 tensor, step): the run's
+        checkpoint together with read_filaments."""
+        buf = self.torch.empty(self.state_bytes(), dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.vlb_read_state(self.h, self._ptr(buf)))
+        return buf, self.get_step()
+
+    def write_state(self, buf, step):
+        if buf.numel() * buf.element_size() != self.state_bytes():
+            raise ValueError("state of another size")
+        buf = buf.to(self.device).contiguous()
+        self._check(self.lib.vlb_write_state(self.h, self._ptr(buf), int(step)))
+
     def read_force(self):
         F = self.torch.empty((3,) + self.shape, dtype=self.torch.float64, device=self.device)
         self._check(self.lib.vlb_read_force(self.h, ctypes.c_void_p(F.data_ptr())))
@@ -401,6 +421,17 @@ class Run:
         b = ctypes.c_int64(0)
         self._check(self.lib.vlb_get_work(self.h, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+
+def _handles(runs):
+    arr = (ctypes.c_void_p * len(runs))(*[r.h for r in runs])
+    return arr
+
+
+def step_many(runs, n_steps):
+    """Advance several runs by n_steps each (vlb_step_many)."""
+    lib = load_library()
+    _raise(lib, lib.vlb_step_many(_handles(runs), len(runs), int(n_steps)))
 
 
 def bs_desc(dims, walls=(False, False, False), kappa=0.1, precision="f64") -> BsDesc:

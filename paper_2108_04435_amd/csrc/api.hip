@@ -448,6 +448,17 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
 
 namespace {
 
+// Runs of a many-run call: non-null and distinct.
+int check_runs(vlb_run* const* runs, int32_t n) {
+  if (!runs || n < 1) return fail(nullptr, VLB_EINVAL, "need at least one run");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!runs[i]) return fail(nullptr, VLB_EINVAL, "run is NULL");
+    for (int32_t k = 0; k < i; ++k)
+      if (runs[k] == runs[i]) return fail(nullptr, VLB_EINVAL, "a run appears twice");
+  }
+  return VLB_OK;
+}
+
 // Launchers enqueue on r.stream; this points it at another stream for a
 // scope.
 struct OnStream {
@@ -557,6 +568,19 @@ int vlb_step(vlb_run* h, int64_t n_steps) {
   return VLB_OK;
 }
 
+int vlb_step_many(vlb_run* const* runs, int32_t n_runs, int64_t n_steps) {
+  int c = check_runs(runs, n_runs);
+  if (c != VLB_OK) return c;
+  if (n_steps < 0) return fail(nullptr, VLB_EINVAL, "n_steps must be >= 0");
+  // step-major: step s of every run is enqueued before step s + 1 of any
+  for (int64_t s = 0; s < n_steps; ++s)
+    for (int32_t i = 0; i < n_runs; ++i) {
+      c = one_step(runs[i], s == 0, s == n_steps - 1);
+      if (c != VLB_OK) return c;
+    }
+  return VLB_OK;
+}
+
 int vlb_sync(vlb_run* h) {
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
@@ -577,6 +601,30 @@ int vlb_read_populations(vlb_run* h, double* f_dev) {
   HIP_OR_FAIL(h, lbm_read_pops(h->r, f_dev));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
   return latched(h);
+}
+
+int vlb_read_state(vlb_run* h, void* pops_dev) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!pops_dev) return fail(h, VLB_EINVAL, "pops is NULL");
+  HIP_OR_FAIL(h, lbm_read_state(h->r, pops_dev));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->r.stream));
+  return latched(h);
+}
+
+int vlb_write_state(vlb_run* h, const void* pops_dev, int64_t step) {
+  if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
+  if (!pops_dev) return fail(h, VLB_EINVAL, "pops is NULL");
+  if (step < 0) return fail(h, VLB_EINVAL, "step must be >= 0");
+  Run& r = h->r;
+  HIP_OR_FAIL(h, hipMemcpyAsync(r.pops, pops_dev, 19 * (size_t)r.cells * elt_size(r.prec),
+                                hipMemcpyDeviceToDevice, r.stream));
+  HIP_OR_FAIL(h, hipMemsetAsync(r.force, 0, 3 * r.cells * (r.prec == VLB_F64 ? 8 : 4), r.stream));
+  HIP_OR_FAIL(h, hipMemsetAsync(r.cnt + 1, 0, sizeof(int32_t), r.stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(r.stream));
+  r.parity = 0;
+  r.step = step;
+  r.has_fields = true;
+  return VLB_OK;
 }
 
 int vlb_read_force(vlb_run* h, double* force_dev) {

@@ -215,6 +215,31 @@ __global__ void k_read_pops(const S* __restrict__ M, Geom g, int parity, double*
   for (int i = 0; i < 19; ++i) f[(long long)i * g.cells + c] = wq(i) + (double)d[i];
 }
 
+// The stored values (deviations in the storage format) of every node's
+// populations in natural layout (population i of node c in slot i of c),
+// gathered from the current AA layout.
+template <class S>
+__global__ void k_read_state(const S* __restrict__ M, Geom g, int parity, S* __restrict__ out) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.cells) return;
+  if (parity == 0) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) out[(long long)i * g.cells + c] = M[(long long)i * g.cells + c];
+    return;
+  }
+  const int x = (int)(c % g.nx);
+  const int y = (int)((c / g.nx) % g.ny);
+  const int z = (int)(c / ((long long)g.nx * g.ny));
+  Nbr nb;
+  make_nbr(g, x, y, z, nb);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const long long s = nbr_index(nb, -cx(i), -cy(i), -cz(i));
+    out[(long long)i * g.cells + c] = (s >= 0) ? M[(long long)opp(i) * g.cells + s]
+                                               : M[(long long)i * g.cells + c];
+  }
+}
+
 template <class T>
 __global__ void k_read_force(const T* __restrict__ F, long long n, double* out) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,6 +432,22 @@ hipError_t lbm_read_pops(Run& r, double* f) {
       break;
     default:
       hipLaunchKernelGGL(k_read_pops<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, f);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t lbm_read_state(Run& r, void* out) {
+  const int nb = blocks_for(r.cells, 256);
+  switch (r.prec) {
+    case VLB_F64:
+      hipLaunchKernelGGL(k_read_state<double>, dim3(nb), dim3(256), 0, r.stream, (const double*)r.pops, r.geom, r.parity, (double*)out);
+      break;
+    case VLB_F32:
+      hipLaunchKernelGGL(k_read_state<float>, dim3(nb), dim3(256), 0, r.stream, (const float*)r.pops, r.geom, r.parity, (float*)out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_read_state<__half>, dim3(nb), dim3(256), 0, r.stream, (const __half*)r.pops, r.geom, r.parity, (__half*)out);
       break;
   }
   return hipGetLastError();

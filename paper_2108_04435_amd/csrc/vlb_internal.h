@@ -426,6 +426,7 @@ hipError_t lbm_init_eq(Run& r, const double* rho, const double* u);
 hipError_t lbm_step(Run& r);
 hipError_t lbm_read_fields(Run& r, double* rho, double* u);
 hipError_t lbm_read_pops(Run& r, double* f);
+hipError_t lbm_read_state(Run& r, void* out);
 hipError_t lbm_read_force(Run& r, double* out);
 hipError_t lbm_moments(Run& r);
 hipError_t lbm_flow_stats(Run& r, double* out);

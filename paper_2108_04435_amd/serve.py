@@ -7,9 +7,12 @@ mutual-friction coefficients and heat fluxes) arrive over time.  The loop
     (``vlb_query_footprint``) fits in what is left of the HBM budget;
   * keeps every admitted run resident in its own workspace, on one stream of
     a fixed pool (one stream per slot, default priority);
-  * advances every resident run by chunks of steps, each chunk one launch of
-    a HIP graph captured once per run (an odd or short remainder is stepped
-    directly at the end), so runs on different streams overlap on the GPU;
+  * advances every resident run by chunks of steps: each chunk is one
+    launch of a HIP graph captured once per run, or (group=True) all the
+    idle runs that have a whole chunk left advance together, enqueued by
+    one library call (vlb_step_many, step by step across the runs); a
+    remainder is stepped directly at the end; runs on different streams
+    overlap on the GPU;
   * retires a run when its last chunk has completed: reads its final state,
     frees its workspace, and records arrival -> completion latency.
 A run's kernels touch only its own workspace and no result depends on a
@@ -22,7 +25,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Run, load_library, lattice_desc, vortex_desc, VlbError  # noqa: F401
+from . import Run, load_library, lattice_desc, step_many, vortex_desc, VlbError  # noqa: F401
 
 
 @dataclass
@@ -73,7 +76,7 @@ def footprint(cfg, n_cap, recon_cap):
 
 class Server:
     def __init__(self, budget_bytes, max_slots=16, chunk=10, device=0, keep_fields=False,
-                 cap_factor=6.0, recon_cap=1 << 16):
+                 cap_factor=6.0, recon_cap=1 << 16, group=False):
         import torch
 
         if chunk < 2 or chunk % 2:
@@ -87,6 +90,10 @@ class Server:
         self.cap_factor = cap_factor
         self.recon_cap = recon_cap
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_slots)]
+        # group=True: the idle runs with a whole chunk left advance together,
+        # enqueued by one vlb_step_many call; else each run launches its own
+        # chunk graph
+        self.group = bool(group)
 
     def _n_cap(self, cfg):
         return max(4096, int(cfg["pos"].shape[0] * self.cap_factor) + 256)
@@ -111,6 +118,17 @@ class Server:
         return _Active(req=req, run=run, slot=slot, remaining=int(req["steps"]), admitted=now,
                        footprint=footprint(cfg, n_cap, self.recon_cap),
                        points_start=int(cfg["pos"].shape[0]))
+
+    def _advance_group(self, group):
+        """One vlb_step_many call advancing every run of ``group`` (idle, a
+        whole chunk left) by one chunk, each on its own stream."""
+        torch = self.torch
+        step_many([a.run for a in group], self.chunk)
+        for a in group:
+            a.remaining -= self.chunk
+            ev = torch.cuda.Event()
+            ev.record(self.streams[a.slot])
+            a.event = ev
 
     def _advance(self, a):
         torch = self.torch
@@ -206,10 +224,16 @@ class Server:
                 used += a.footprint
                 active.append(a)
             # keep every resident run busy
-            for a in active:
-                if a.remaining > 0 and (a.event is None or a.event.query()):
-                    self._advance(a)
+            idle = [a for a in active if a.remaining > 0 and (a.event is None or a.event.query())]
+            if self.group:
+                full = [a for a in idle if a.remaining >= self.chunk]
+                if len(full) > 1:
+                    self._advance_group(full)
                     progressed = True
+                    idle = [a for a in idle if a not in full]
+            for a in idle:
+                self._advance(a)
+                progressed = True
             if not progressed:
                 time.sleep(2e-4)
         makespan = time.perf_counter() - self.t0

@@ -24,10 +24,11 @@ def _requests():
     return reqs
 
 
-def test_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("group", [False, True])
+def test_mix_equals_alone_bitwise(group):
     reqs = _requests()
-    say("serve mix", [(r["rid"], r["steps"], r["cfg"]["pos"].shape[0]) for r in reqs])
-    srv = serve.Server(budget_bytes=8 << 30, max_slots=3, chunk=4, keep_fields=True)
+    say("serve mix", group, [(r["rid"], r["steps"], r["cfg"]["pos"].shape[0]) for r in reqs])
+    srv = serve.Server(budget_bytes=8 << 30, max_slots=3, chunk=4, keep_fields=True, group=group)
     mix, makespan = srv.serve(reqs)
     summary = serve.summarize(mix, makespan)
     say("summary", summary)

@@ -42,6 +42,9 @@ class VortexParams:
     # reaction on the normal fluid: 0 = Magnus balance (reading R1),
     # 1 = the printed Eq. (f) taken literally (for ablation)
     force_model: int = 0
+    # superfluid boundary velocity v_s,b from image vortices in the wall
+    # planes (reading F1); False: v_s,b = 0 (reading R13)
+    wall_images: bool = False
 
 
 # ---------------------------------------------------------------- geometry
@@ -199,6 +202,67 @@ def biot_savart_nonlocal(pos, nxt, prv, lat: Lattice, kappa, targets=None, chunk
     return out
 
 
+def image_copies(lat: Lattice):
+    """The images of reading F1: for every closed axis the filaments are
+    mirrored in its lower wall plane (-1/2) or its upper one (n - 1/2), or
+    not at all, independently per axis; every combination but the identity
+    is one image copy.  Returns a list of (reflection per axis: 0 none,
+    1 lower wall, 2 upper wall; sign (-1)^(number of reflections)).  A
+    mirrored filament with the same point order carries circulation
+    -kappa per reflection: the mirror image of a vorticity field about a
+    plane, with its sign flipped, leaves no flow through that plane."""
+    walled = [a for a in range(3) if lat.walls[a]]
+    copies = []
+    for code in np.ndindex(*([3] * len(walled))):
+        if not any(code):
+            continue
+        refl = [0, 0, 0]
+        for a, c in zip(walled, code):
+            refl[a] = c
+        copies.append((tuple(refl), (-1.0) ** sum(1 for c in code if c)))
+    return copies
+
+
+def mirror(pos, refl, lat: Lattice):
+    """Positions mirrored per axis: 1 in the plane -1/2 (x -> 2(-1/2) - x),
+    2 in the plane n - 1/2 (x -> 2(n - 1/2) - x)."""
+    p = np.array(pos, dtype=np.float64, copy=True)
+    for a, n in enumerate(lat.dims):
+        if refl[a] == 1:
+            p[..., a] = 2.0 * (-0.5) - p[..., a]
+        elif refl[a] == 2:
+            p[..., a] = 2.0 * (n - 0.5) - p[..., a]
+    return p
+
+
+def biot_savart_images(pos, nxt, lat: Lattice, kappa, targets=None, chunk=64):
+    """Boundary superflow v_s,b of Sec. II.A, Eq. (Biot-Savart), from image
+    filaments (reading F1): for every image copy (image_copies) the sum over
+    all of its segments (mirrored start, mirrored segment vector) of the
+    straight-segment integral, times the copy's sign; none is excluded.  On
+    periodic axes each image segment is taken at the nearest image of its
+    start, as the real ones."""
+    N = pos.shape[0]
+    if targets is None:
+        targets = np.arange(N)
+    targets = np.asarray(targets, dtype=np.int64)
+    out = np.zeros((targets.size, 3), dtype=np.float64)
+    seg = min_image(pos[nxt] - pos, lat)
+    for refl, sign in image_copies(lat):
+        mp = mirror(pos, refl, lat)
+        mseg = seg.copy()
+        for a in range(3):
+            if refl[a]:
+                mseg[:, a] = -mseg[:, a]
+        for c0 in range(0, targets.size, chunk):
+            tj = targets[c0:c0 + chunk]
+            R1 = bs_image_offsets(mp[None, :, :], pos[tj][:, None, :], lat)
+            R2 = R1 + mseg[None, :, :]
+            v = segment_velocity(R1, R2, kappa)
+            out[c0:c0 + chunk] += sign * v.sum(axis=1)
+    return out
+
+
 # ------------------------------------------------ interpolation / spreading
 
 def delta2pt(r):
@@ -320,6 +384,8 @@ def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_fo
     field; ``Vs`` the slice superflow (or None)."""
     geo = geometry(pos, nxt, prv, lat)
     vs = biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa) + lia_velocity(geo, vp)
+    if vp.wall_images:
+        vs = vs + biot_savart_images(pos, nxt, lat, vp.kappa)
     vs = vs + np.array(vp.vs_applied, dtype=np.float64)[None, :]
     if Vs is not None:
         vs[:, 2] = vs[:, 2] + superflow_at(Vs, pos[:, 2], lat.nz)

@@ -103,6 +103,16 @@ typedef struct {
                              (ds/dt - v_s), the Magnus balance; 1 = rho_s
                              kappa (ds/dt - v_s), the relation as printed
                              (for ablation)                                 */
+  int32_t wall_images;    /* 1: superfluid wall term v_s,b (Sec. II.A, Eq.
+                             Biot-Savart) from image filaments: on every
+                             closed axis the filaments are mirrored in the
+                             wall planes -1/2 and n - 1/2 with circulation
+                             -kappa per reflection, every combination of
+                             reflections across the closed axes (3^w - 1
+                             copies for w closed axes, each summed like the
+                             real filaments, none excluded); 0: v_s,b = 0.
+                             The Biot-Savart work grows 3^w-fold.           */
+  int32_t reserved1;      /* 0                                              */
   int64_t n_cap;          /* capacity in filament points (>= 1)             */
   int64_t recon_cap;      /* capacity in reconnection candidates per step   */
 } vlb_vortex_desc;

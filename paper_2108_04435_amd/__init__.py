@@ -65,6 +65,7 @@ class VortexDesc(ctypes.Structure):
         ("remesh", ctypes.c_int32), ("reconnect", ctypes.c_int32),
         ("min_loop_pts", ctypes.c_int32), ("coupling", ctypes.c_int32),
         ("mass_balance", ctypes.c_int32), ("force_model", ctypes.c_int32),
+        ("wall_images", ctypes.c_int32), ("reserved1", ctypes.c_int32),
         ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
     ]
 
@@ -173,6 +174,8 @@ def vortex_desc(vor: dict, n_cap: int, recon_cap: int = 1 << 16) -> VortexDesc:
     d.coupling = int(bool(vor.get("coupling", True)))
     d.mass_balance = int(bool(vor.get("mass_balance", False)))
     d.force_model = int(vor.get("force_model", 0))
+    d.wall_images = int(bool(vor.get("wall_images", False)))
+    d.reserved1 = 0
     d.n_cap = int(n_cap)
     d.recon_cap = int(recon_cap)
     return d

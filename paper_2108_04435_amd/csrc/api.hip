@@ -83,6 +83,7 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
   if (vor->min_loop_pts < 3) { msg = "min_loop_pts must be >= 3"; return VLB_EINVAL; }
   if (vor->mass_balance && (lat->wall_axes & 4u)) { msg = "mass balance needs a periodic z axis"; return VLB_EINVAL; }
   if (vor->force_model != 0 && vor->force_model != 1) { msg = "force_model must be 0 or 1"; return VLB_EINVAL; }
+  if (vor->wall_images != 0 && vor->wall_images != 1) { msg = "wall_images must be 0 or 1"; return VLB_EINVAL; }
   if (vor->reconnect) {
     if (!(vor->reconnect_dist > 0)) { msg = "reconnect_dist must be positive"; return VLB_EINVAL; }
     if (vor->recon_cap < 1 || vor->recon_cap > (1LL << 26)) { msg = "recon_cap must be in [1, 2^26]"; return VLB_EINVAL; }
@@ -128,9 +129,10 @@ size_t layout(Run& r, char* base) {
   int32_t** ibufs[] = {&r.nxt, &r.prv, &r.nxt_t, &r.prv_t, &r.stage_i, &r.flag_a, &r.flag_b,
                        &r.scan_a, &r.scan_b, &r.used};
   for (int32_t** p : ibufs) *p = (int32_t*)B.take((nc + 1) * sizeof(int32_t));
-  r.bsX = (uint32_t*)B.take(3 * nc * sizeof(uint32_t));
-  r.bsD = B.take((r.prec == VLB_F64 ? 6 : 4) * nc * fe);  // FP64: d (3) and residuals (3)
-  size_t pbytes = (size_t)r.bsS * 3 * nc * fe;
+  const int nco = r.bsax.copies;
+  r.bsX = (uint32_t*)B.take((size_t)nco * 3 * nc * sizeof(uint32_t));
+  r.bsD = B.take((size_t)nco * (r.prec == VLB_F64 ? 6 : 4) * nc * fe);  // FP64: d (3) and residuals (3)
+  size_t pbytes = (size_t)nco * r.bsS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
   r.marked = (uint32_t*)B.take(nc * sizeof(uint32_t));
@@ -187,7 +189,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   g.omega = 1.0 / lat->tau;
   g.fpref = 1.0 - 1.0 / (2.0 * lat->tau);
   const int n[3] = {g.nx, g.ny, g.nz};
-  r.bsax = bs_make_axes(n, g.wall);
+  r.bsax = bs_make_axes(n, g.wall, vor->wall_images != 0);
   r.bsS = bs_chunks(r.ncap);
   // spreading bins: lower stencil corner, n (+1 on wall axes) per axis
   const unsigned long long ext = (unsigned long long)(n[0] + g.wall[0]) * (n[1] + g.wall[1]) * (n[2] + g.wall[2]);
@@ -509,7 +511,7 @@ int one_step(vlb_run* h, bool first, bool last) {
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
-    if (r.prec == VLB_F64) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
+    if (r.prec == VLB_F64 || r.bsax.copies > 1) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
     HIP_OR_FAIL(h, bs_sum(r));
     // the first finalize reads the velocity field and the superflow
     if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
@@ -997,7 +999,7 @@ int vlb_biot_savart(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
   const int n[3] = {d->nx, d->ny, d->nz};
   const int wall[3] = {(int)(d->wall_axes & 1u), (int)((d->wall_axes >> 1) & 1u),
                        (int)((d->wall_axes >> 2) & 1u)};
-  const hipError_t e = bs_solo(bs_make_axes(n, wall), d->precision, n_pts, xyz_dev, next_dev,
+  const hipError_t e = bs_solo(bs_make_axes(n, wall, false), d->precision, n_pts, xyz_dev, next_dev,
                                d->kappa, v_dev, b, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(nullptr, e, "vlb_biot_savart");
   return VLB_OK;

@@ -52,21 +52,31 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
   const int n = cnt[0];
   if (j >= n) return;
   const int k = nxt[j];
+  double y[3], d[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double y = Y[a * ncap + j];
-    const double s = floor((y + ax.off[a]) * ax.q[a]);
-    X[a * ncap + j] = ax.periodic[a] ? (uint32_t)(long long)s : (uint32_t)(int)(long long)s;
-    double d = Y[a * ncap + k] - y;
+    y[a] = Y[a * ncap + j];
+    d[a] = Y[a * ncap + k] - y[a];
     if (ax.periodic[a]) {
-      if (d > 0.5 * ax.L[a])
-        d = d - ax.L[a];
-      else if (d < -0.5 * ax.L[a])
-        d = d + ax.L[a];
+      if (d[a] > 0.5 * ax.L[a])
+        d[a] = d[a] - ax.L[a];
+      else if (d[a] < -0.5 * ax.L[a])
+        d[a] = d[a] + ax.L[a];
     }
-    if (sizeof(T) == 8) {
-      D[a * ncap + j] = (T)d;
-      D[(3 + a) * ncap + j] = (T)((y + ax.off[a]) - s * ax.invq_d[a]);
+  }
+  // copy 0: the point itself; copies 1..: its images in the wall planes
+  for (int c = 0; c < ax.copies; ++c) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int m = ax.refl[c][a];
+      const double yc = m == 0 ? y[a] : (m == 1 ? 2.0 * (-0.5) - y[a] : 2.0 * (ax.L[a] - 0.5) - y[a]);
+      const double s = floor((yc + ax.off[a]) * ax.q[a]);
+      X[((long long)c * 3 + a) * ncap + j] =
+          ax.periodic[a] ? (uint32_t)(long long)s : (uint32_t)(int)(long long)s;
+      if (sizeof(T) == 8) {
+        D[((long long)c * 6 + a) * ncap + j] = (T)(m == 0 ? d[a] : -d[a]);
+        D[((long long)c * 6 + 3 + a) * ncap + j] = (T)((yc + ax.off[a]) - s * ax.invq_d[a]);
+      }
     }
   }
 }
@@ -116,25 +126,29 @@ __device__ inline void bs_tile_f32(const uint32_t* sx, const uint32_t* sy, const
   }
 }
 
+// Grid y: S chunks of every source copy (copy 0 the filaments, the others
+// their wall images, which take no exclusion and carry the copy's sign).
 template <bool kUniform>
 __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
                                                const int32_t* __restrict__ nxt,
                                                const int32_t* __restrict__ prv,
                                                int32_t* __restrict__ cntp, long long ncap,
                                                int S, float iqx, float iqy, float iqz,
-                                               float* __restrict__ P) {
+                                               float* __restrict__ P, BsAxes bx) {
   const int n = cntp[0];
   // work counter: (target, segment) pairs of this sum
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
-    *(long long*)(cntp + 16) += (long long)n * (n - 2);
+    *(long long*)(cntp + 16) += (long long)n * (n - 2) + (long long)(bx.copies - 1) * n * n;
   const int j0 = blockIdx.x * kTargets;
   if (j0 >= n) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int j = j0 + lane;
   const bool valid = j < n;
+  const int copy = blockIdx.y / S;
+  const uint32_t* __restrict__ Xs = X + (long long)copy * 3 * ncap;  // this copy's sources
   const int per = (n + S - 1) / S;
-  const int kb = blockIdx.y * per;
+  const int kb = (blockIdx.y - copy * S) * per;
   const int ke = min(n, kb + per);
   const uint32_t xt = valid ? X[j] : 0u;
   const uint32_t yt = valid ? X[ncap + j] : 0u;
@@ -150,10 +164,10 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
     if (k < ke) {
       // segment vector: wrapped grid difference to the successor
       const int kn = nxt[k];
-      const uint32_t ax0 = X[k], ay0 = X[ncap + k], az0 = X[2 * ncap + k];
-      float ex = (float)(int)(X[kn] - ax0);
-      float ey = (float)(int)(X[ncap + kn] - ay0);
-      float ez = (float)(int)(X[2 * ncap + kn] - az0);
+      const uint32_t ax0 = Xs[k], ay0 = Xs[ncap + k], az0 = Xs[2 * ncap + k];
+      float ex = (float)(int)(Xs[kn] - ax0);
+      float ey = (float)(int)(Xs[ncap + kn] - ay0);
+      float ez = (float)(int)(Xs[2 * ncap + kn] - az0);
       if (!kUniform) {
         ex *= iqx;
         ey *= iqy;
@@ -172,7 +186,7 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
     wave_range(min(kTile, ke - t0), w, lo, hi);
     if (lo < hi) {
       const int s0 = t0 + lo, s1 = t0 + hi;
-      const bool hit = valid && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      const bool hit = valid && copy == 0 && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
       if (__any(hit))
         bs_tile_f32<true, kUniform>(sx + lo, sy + lo, sz + lo, dx + lo, dy + lo, dz + lo, dq + lo,
                                     hi - lo, s0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
@@ -189,10 +203,11 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   }
   __syncthreads();
   if (w == 0 && valid) {
+    const float sg = bx.sign[copy];
     float* out = P + (long long)blockIdx.y * 3 * ncap;
-    out[j] = ((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
-    out[ncap + j] = ((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
-    out[2 * ncap + j] = ((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
+    out[j] = sg * (((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane]);
+    out[ncap + j] = sg * (((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane]);
+    out[2 * ncap + j] = sg * (((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane]);
   }
 }
 
@@ -259,18 +274,21 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
                                                const int32_t* __restrict__ prv,
                                                int32_t* __restrict__ cntp, long long ncap,
                                                int S, double gx, double gy, double gz,
-                                               double* __restrict__ P) {
+                                               double* __restrict__ P, BsAxes bx) {
   const int n = cntp[0];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
-    *(long long*)(cntp + 16) += (long long)n * (n - 2);
+    *(long long*)(cntp + 16) += (long long)n * (n - 2) + (long long)(bx.copies - 1) * n * n;
   const int j0 = blockIdx.x * kTargets;
   if (j0 >= n) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int j = j0 + lane;
   const bool valid = j < n;
+  const int copy = blockIdx.y / S;
+  const uint32_t* __restrict__ Xs = X + (long long)copy * 3 * ncap;  // this copy's sources
+  const double* __restrict__ Ds = D + (long long)copy * 6 * ncap;
   const int per = (n + S - 1) / S;
-  const int kb = blockIdx.y * per;
+  const int kb = (blockIdx.y - copy * S) * per;
   const int ke = min(n, kb + per);
   const uint32_t xt = valid ? X[j] : 0u;
   const uint32_t yt = valid ? X[ncap + j] : 0u;
@@ -288,24 +306,24 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   for (int t0 = kb; t0 < ke; t0 += kTile) {
     const int k = t0 + threadIdx.x;
     if (k < ke) {
-      sx[threadIdx.x] = X[k];
-      sy[threadIdx.x] = X[ncap + k];
-      sz[threadIdx.x] = X[2 * ncap + k];
-      const double ex = D[k], ey = D[ncap + k], ez = D[2 * ncap + k];
+      sx[threadIdx.x] = Xs[k];
+      sy[threadIdx.x] = Xs[ncap + k];
+      sz[threadIdx.x] = Xs[2 * ncap + k];
+      const double ex = Ds[k], ey = Ds[ncap + k], ez = Ds[2 * ncap + k];
       dx[threadIdx.x] = ex;
       dy[threadIdx.x] = ey;
       dz[threadIdx.x] = ez;
       dq[threadIdx.x] = ex * ex + ey * ey + ez * ez;
-      rx[threadIdx.x] = D[3 * ncap + k];
-      ry[threadIdx.x] = D[4 * ncap + k];
-      rz[threadIdx.x] = D[5 * ncap + k];
+      rx[threadIdx.x] = Ds[3 * ncap + k];
+      ry[threadIdx.x] = Ds[4 * ncap + k];
+      rz[threadIdx.x] = Ds[5 * ncap + k];
     }
     __syncthreads();
     int lo, hi;
     wave_range(min(kTile, ke - t0), w, lo, hi);
     if (lo < hi) {
       const int s0 = t0 + lo, s1 = t0 + hi;
-      const bool hit = valid && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      const bool hit = valid && copy == 0 && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
       if (__any(hit))
         bs_tile_f64<true>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
                           dz + lo, dq + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj,
@@ -324,10 +342,11 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   }
   __syncthreads();
   if (w == 0 && valid) {
+    const double sg = (double)bx.sign[copy];
     double* out = P + (long long)blockIdx.y * 3 * ncap;
-    out[j] = ((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
-    out[ncap + j] = ((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
-    out[2 * ncap + j] = ((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
+    out[j] = sg * (((ax + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane]);
+    out[ncap + j] = sg * (((ay + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane]);
+    out[2 * ncap + j] = sg * (((az + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane]);
   }
 }
 
@@ -394,7 +413,7 @@ __global__ void k_solo_sum(const PT* __restrict__ P, int S, int n, double scale,
 // n[a]): periodic axes map [0, L) onto the whole 32-bit range, so that
 // separations wrap exactly; wall axes use a power-of-two step with room
 // for [-1, n + 1).
-BsAxes bs_make_axes(const int n[3], const int wall[3]) {
+BsAxes bs_make_axes(const int n[3], const int wall[3], bool images) {
   BsAxes ax{};
   for (int a = 0; a < 3; ++a) {
     ax.L[a] = (double)n[a];
@@ -404,10 +423,12 @@ BsAxes bs_make_axes(const int n[3], const int wall[3]) {
       ax.off[a] = 0.0;
       ax.invq_d[a] = (double)n[a] / 4294967296.0;
     } else {
+      // [-1, n + 1), or with wall images [-n - 1, 2n + 1)
+      const double span = images ? 3.0 * n[a] + 2.0 : n[a] + 2.0;
       int k = 0;
-      while ((double)(n[a] + 2) * std::ldexp(1.0, k + 1) <= 2147483648.0) ++k;
+      while (span * std::ldexp(1.0, k + 1) <= 2147483648.0) ++k;
       ax.q[a] = std::ldexp(1.0, k);
-      ax.off[a] = 1.0;
+      ax.off[a] = images ? n[a] + 1.0 : 1.0;
       ax.invq_d[a] = std::ldexp(1.0, -k);
     }
     ax.invq_f[a] = (float)ax.invq_d[a];
@@ -426,7 +447,7 @@ BsAxes bs_make_axes(const int n[3], const int wall[3]) {
       if (ax.periodic[a])
         ok = ax.q[a] == q;
       else
-        ok = (double)(n[a] + 2) * q <= 2147483648.0;
+        ok = (images ? 3.0 * n[a] + 2.0 : n[a] + 2.0) * q <= 2147483648.0;
     }
     ax.uniform = ok ? 1 : 0;
     if (ok)
@@ -436,6 +457,24 @@ BsAxes bs_make_axes(const int n[3], const int wall[3]) {
         ax.invq_f[a] = (float)ax.invq_d[a];
       }
   }
+  // source copies: every combination of no / lower / upper reflection on
+  // the closed axes (the identity first)
+  ax.copies = 0;
+  for (int cz = 0; cz < 3; ++cz)
+    for (int cy = 0; cy < 3; ++cy)
+      for (int cx = 0; cx < 3; ++cx) {
+        const int code[3] = {cx, cy, cz};
+        bool ok = true;
+        int refl = 0;
+        for (int a = 0; a < 3; ++a) {
+          if (code[a] && (!images || !wall[a])) ok = false;
+          if (code[a]) ++refl;
+        }
+        if (!ok) continue;
+        for (int a = 0; a < 3; ++a) ax.refl[ax.copies][a] = (int8_t)code[a];
+        ax.sign[ax.copies] = (refl & 1) ? -1.0f : 1.0f;
+        ++ax.copies;
+      }
   return ax;
 }
 
@@ -466,21 +505,21 @@ hipError_t bs_prep(Run& r, const double* Y) {
 
 hipError_t bs_sum(Run& r) {
   const int tb = (int)((r.ncap + kTargets - 1) / kTargets);
-  dim3 grid(tb, r.bsS);
+  dim3 grid(tb, r.bsS * r.bsax.copies);
   hipEvent_t b = nullptr;
   time_begin(r, 0, &b);
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_d[0], r.bsax.invq_d[1],
-                       r.bsax.invq_d[2], (double*)r.bsP);
+                       r.bsax.invq_d[2], (double*)r.bsP, r.bsax);
   else if (r.bsax.uniform)
     hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
-                       r.bsax.invq_f[2], (float*)r.bsP);
+                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax);
   else
     hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
-                       r.bsax.invq_f[2], (float*)r.bsP);
+                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax);
   time_end(r, 0, b);
   return hipGetLastError();
 }
@@ -539,7 +578,7 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
     hipLaunchKernelGGL(k_solo_prep<double>, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n,
                        ax, b.cnt, b.X, (double*)b.D, b.nxt, b.prv);
     hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, stream, b.X, (const double*)b.D, b.prv,
-                       b.cnt, n, b.S, ax.invq_d[0], ax.invq_d[1], ax.invq_d[2], (double*)b.P);
+                       b.cnt, n, b.S, ax.invq_d[0], ax.invq_d[1], ax.invq_d[2], (double*)b.P, ax);
     hipLaunchKernelGGL(k_solo_sum<double>, dim3(nb), dim3(256), 0, stream, (const double*)b.P,
                        b.S, (int)n, s, v);
   } else {
@@ -547,10 +586,10 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
                        ax, b.cnt, b.X, (float*)b.D, b.nxt, b.prv);
     if (ax.uniform)
       hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
-                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P);
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax);
     else
       hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
-                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P);
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax);
     hipLaunchKernelGGL(k_solo_sum<float>, dim3(nb), dim3(256), 0, stream, (const float*)b.P,
                        b.S, (int)n, ax.uniform ? s * ax.q[0] : s, v);
   }

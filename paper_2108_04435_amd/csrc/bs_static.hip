@@ -66,7 +66,7 @@ extern "C" int vlb_biot_savart_noalloc(const vlb_bs_desc* d, int64_t n_pts, cons
   const int n[3] = {d->nx, d->ny, d->nz};
   const int wall[3] = {(int)(d->wall_axes & 1u), (int)((d->wall_axes >> 1) & 1u),
                        (int)((d->wall_axes >> 2) & 1u)};
-  const hipError_t e = bs_solo(bs_make_axes(n, wall), d->precision, n_pts, xyz_dev, next_dev,
+  const hipError_t e = bs_solo(bs_make_axes(n, wall, false), d->precision, n_pts, xyz_dev, next_dev,
                                d->kappa, v_dev, b, (hipStream_t)hip_stream);
   if (e != hipSuccess)
     return fail_global(VLB_EDEVICE, std::string("vlb_biot_savart_noalloc: ") + hipGetErrorString(e));

@@ -556,7 +556,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.prv = r.prv;
   A.cnt = r.cnt;
   A.P = r.bsP;
-  A.S = r.bsS;
+  A.S = r.bsS * r.bsax.copies;
   A.ncap = r.ncap;
   A.Vs = r.Vs;
   A.mass_balance = r.vor.mass_balance;

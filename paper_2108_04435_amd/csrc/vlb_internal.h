@@ -264,6 +264,12 @@ struct BsAxes {
   double L[3];
   int periodic[3];
   int uniform;      // 1: one grid step q for all axes (FP32 sum in grid units)
+  // source copies of the sum: copy 0 the filaments, copies 1.. their
+  // images in the wall planes (refl per axis: 0 none, 1 the plane -1/2,
+  // 2 the plane n - 1/2; sign (-1)^(reflections))
+  int copies;
+  int8_t refl[27][3];
+  float sign[27];
 };
 
 // Radix-sort tiles: one key per thread, one tile per block.
@@ -438,7 +444,7 @@ hipError_t diag_curl(Run& r, const double* u, double* w);
 hipError_t diag_cylindrical(Run& r, const double point[3], const double unit_dir[3],
                             const double* w, double* out);
 
-BsAxes bs_make_axes(const int n[3], const int wall[3]);
+BsAxes bs_make_axes(const int n[3], const int wall[3], bool images);
 
 // Scratch of the standalone Biot-Savart sum (vlb_biot_savart*): point
 // count and pair counter, grid coordinates, FP64 segment data, sanitised

@@ -47,7 +47,7 @@ int main(void) {
   printf("lat %zu\nvor %zu\n", sizeof(vlb_lattice_desc), sizeof(vlb_vortex_desc));
   O(vlb_lattice_desc, tau); O(vlb_lattice_desc, wall_axes); O(vlb_lattice_desc, plane_u);
   O(vlb_lattice_desc, body_force); O(vlb_vortex_desc, vs_applied); O(vlb_vortex_desc, remesh);
-  O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap);
+  O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap); O(vlb_vortex_desc, wall_images);
   printf("bs %zu\n", sizeof(vlb_bs_desc));
   O(vlb_bs_desc, wall_axes); O(vlb_bs_desc, precision); O(vlb_bs_desc, kappa);
   return 0;

@@ -707,3 +707,56 @@ def test_literal_force_model_coupled_f64():
     _, u_o = lbm.bare_velocity(st.f, lat)
     assert rel_l2(u_g, u_o) < 1e-10
     run.close()
+
+
+def _walled_case(walls, precision, seed=61, n_rings=5, dims=(20, 18, 24)):
+    lat = wl.lattice_preset(*dims, walls=walls, precision=precision,
+                            body_force=(0.0, 0.0, 0.0 if walls[2] else 1e-5))
+    vor = wl.vortex_preset(wall_images=True, mass_balance=not walls[2])
+    rho, u = wl.velocity_field(seed, dims, (0.0, 0.0, 0.01), 2e-3)
+    # rings close to the walls (margin 0.3): the image terms are large there
+    pos, nxt = wl.random_rings(seed, n_rings, 2.0, 4.0, dims, walls, 0.95, margin=0.3)
+    return dict(name=f"walled{walls}", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos,
+                nxt=nxt, steps=6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("walls", [(True, False, False), (True, True, False), (True, True, True)])
+def test_wall_images_eval(walls, precision):
+    """Superfluid wall term from image filaments (3^w - 1 mirrored copies):
+    line velocity, force and spread force against the oracle; without the
+    images the velocity differs by far more than the tolerance."""
+    cfg = _walled_case(walls, precision, n_rings=16)
+    say("wall images", walls, precision, cfg["pos"].shape[0])
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    ref, F_o, _ = _oracle_eval(cfg)
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= TOL[precision], (k, err)
+    assert rel_l2(F_g, F_o) <= TOL[precision]
+    cfg0 = dict(cfg, vortex=dict(cfg["vortex"], wall_images=False))
+    ref0, _, _ = _oracle_eval(cfg0)
+    assert rel_l2(ref0["vs"], ref["vs"]) > 100 * TOL[precision]
+    run.close()
+
+
+def test_wall_images_coupled_f64():
+    cfg = _walled_case((True, True, False), "f64", seed=62)
+    say("wall images coupled")
+    run = vlb.run_from_config(cfg)
+    lat, vp, st = oracle_state(cfg)
+    assert vp.wall_images
+    for _ in range(6):
+        run.step(1)
+        st = coupled.coupled_step(st, lat, vp)
+    run.sync()
+    pos_g, nxt_g = run.read_filaments()
+    np.testing.assert_array_equal(nxt_g, st.nxt)
+    assert np.abs(vfm.min_image(pos_g - st.pos, lat)).max() < 1e-10
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) < 1e-10
+    run.close()

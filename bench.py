@@ -141,9 +141,11 @@ _POOL_ARGS = None
 def _pool_bs(targets):
     from oracle import vfm
 
-    pos, nxt, prv, lat, kappa = _POOL_ARGS
+    pos, nxt, prv, lat, kappa, images = _POOL_ARGS
     t0 = time.perf_counter()
     v = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, kappa, targets=targets, chunk=16)
+    if images:
+        v = v + vfm.biot_savart_images(pos, nxt, lat, kappa, targets=targets, chunk=16)
     return v, time.perf_counter() - t0
 
 
@@ -209,7 +211,8 @@ def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
     targets = np.sort(np.concatenate([box_idx, extra])).astype(np.int64)
 
     # Biot-Savart at the targets: fork pool (no GPU has been touched yet)
-    _POOL_ARGS = (pos, nxt, prv, lat, vp.kappa)
+    _POOL_ARGS = (pos, nxt, prv, lat, vp.kappa, vp.wall_images)
+    copies = len(vfm.image_copies(lat)) + 1 if vp.wall_images else 1
     parts = np.array_split(targets, nw)
     t0 = time.perf_counter()
     if nw > 1:
@@ -219,11 +222,11 @@ def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
         res = [_pool_bs(parts[0])]
     t_pool = time.perf_counter() - t0
     bs = np.concatenate([r[0] for r in res], axis=0)
-    pairs_pool = targets.size * (n - 2)
+    pairs_pool = targets.size * ((n - 2) + (copies - 1) * n)
     t_single = time.perf_counter()
-    vfm.biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa, targets=targets[:single], chunk=16)
+    _pool_bs(targets[:single])
     t_single = time.perf_counter() - t_single
-    pairs_single = min(single, targets.size) * (n - 2)
+    pairs_single = min(single, targets.size) * ((n - 2) + (copies - 1) * n)
 
     # the rest of stage 1 at the targets, from the slab z in [o_z-2, o_z+w+2)
     t1 = time.perf_counter()
@@ -268,7 +271,7 @@ def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
     rate_pool = pairs_pool / t_pool
     rate_single = pairs_single / t_single
     rate_lbm = w ** 3 / t_lbm
-    pairs_step = 4.0 * n * (n - 2)
+    pairs_step = 4.0 * n * ((n - 2) + (copies - 1) * n)
     t_step = pairs_step / rate_pool + cells / rate_lbm
     t_step_1 = pairs_step / rate_single + cells / rate_lbm
     cpu = "unknown"
@@ -290,7 +293,8 @@ def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
                 f"again in one process, {t_single:.1f} s), one LBM update of a {w}^3 crop "
                 f"({t_lbm:.2f} s, one thread), the rest of RK stage 1 at the targets "
                 f"({t_stage:.1f} s); scaled to one coupled step of the whole workload "
-                f"(4 x {n} x {n - 2} pairs + {cells} node updates; the O(N) filament work "
+                f"(4 x {n} targets x {(n - 2) + (copies - 1) * n} segments + {cells} node updates; "
+                f"the O(N) filament work "
                 f"and the topology are not counted)"),
     )
     ref = dict(targets=targets, vs=vs, vn=vn, sdot=sdot, force=force, origin=o, width=w,
@@ -523,6 +527,8 @@ def parse_args(argv=None):
                     help="comma-separated precisions measured beside the headline "
                          "(default for the 256^3 tangle: f32,f64; 'none' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wall-images", action="store_true",
+                    help="superfluid wall term from image filaments (walled workloads)")
     ap.add_argument("--graph", type=int, default=None,
                     help="advance in HIP-graph launches of this many steps (even); 0: direct")
     ap.add_argument("--no-diagnostics", action="store_true")
@@ -570,6 +576,8 @@ def main(argv=None):
 
     t_setup = time.perf_counter()
     cfg = make_workload(args.workload, args.head_precision)
+    if args.wall_images:
+        cfg["vortex"] = dict(cfg["vortex"], wall_images=True)
     print(f"[bench] workload {cfg['name']}: {cfg['pos'].shape[0]} points, "
           f"{time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     base, ref = None, None
@@ -657,6 +665,7 @@ def main(argv=None):
             "walls": list(lat["walls"]),
             "mass_balance": bool(cfg["vortex"]["mass_balance"]),
             "reconnect": bool(cfg["vortex"]["reconnect"]),
+            "wall_images": bool(cfg["vortex"].get("wall_images", False)),
             "graph_steps": args.graph,
         },
         "step_ms_p50": head["step_ms_p50"],

@@ -84,3 +84,23 @@ def test_cpu_baseline_with_friction_profile_keys():
     cfg["vortex"] = dict(cfg["vortex"], alpha_z=(0.2,) * nz, alpha_p_z=(0.01,) * nz)
     base, _ = bench.cpu_baseline(cfg, workers=1, per_worker=8, single=4)
     assert base["value"] > 0
+
+
+def test_cpu_baseline_sample_with_wall_images():
+    """The oracle leg on a walled channel with the image term: the sampled
+    first-stage values equal the oracle's full-state computation."""
+    from oracle import lbm, vfm
+    import tests._cases as cases
+
+    cfg = cases.small_channel(precision="f64", seed=71, n_rings=8, nxy=24, nz=32)
+    cfg["vortex"] = dict(cfg["vortex"], wall_images=True)
+    base, ref = bench.cpu_baseline(cfg, workers=1, per_worker=40, single=4)
+    lat, vp, st = cases.oracle_state(cfg)
+    assert vp.wall_images
+    _, ub = lbm.bare_velocity(st.f, lat)
+    Vs = lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n)
+    full = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, Vs, lat, vp, want_force=True)
+    t = ref["targets"]
+    assert t.size > 0
+    for k in ("vs", "vn", "sdot", "force"):
+        np.testing.assert_allclose(ref[k], full[k][t], rtol=0, atol=1e-14)

@@ -423,6 +423,33 @@ def measure(cfg, args, ref, graph):
     return row, extra
 
 
+def lbm_only(n, precision, steps=20):
+    """The normal-fluid update alone on an n^3 periodic lattice (working set
+    far above the 256 MB last-level cache), full grid: kernel time from HIP
+    events around each launch, per AA parity."""
+    import paper_2108_04435_amd as vlb
+    import workloads as wl
+
+    lat = wl.lattice_preset(n, n, n, tau=0.8, precision=precision)
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
+    rho, u = wl.velocity_field(4, (n, n, n), (0.0, 0.0, 0.02), 1e-4)
+    run.write_fields(rho, u)
+    del rho, u
+    run.step(4)
+    run.sync()
+    run.set_timing(True, reserve=4 * steps)
+    run.step(steps)
+    run.sync()
+    ms, k = run.timing(1)
+    bytes_node = 2 * 19 * STORE_BYTES[precision]
+    cells = n ** 3
+    gbs = bytes_node * cells * k / (ms * 1e-3) / 1e9
+    run.close()
+    return dict(lattice=f"{n}^3", precision=precision, kernel_us=round(ms * 1e3 / k, 1),
+                glups=round(cells * k / (ms * 1e-3) / 1e9, 2), bytes_per_node=bytes_node,
+                achieved_GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
+
+
 def time_diagnostics(run, cells, precision, n_points, reps=10):
     """Host-visible time of one call of each diagnostic at the final state
     (median of reps calls; each call launches its kernels and synchronises
@@ -532,6 +559,8 @@ def parse_args(argv=None):
     ap.add_argument("--graph", type=int, default=None,
                     help="advance in HIP-graph launches of this many steps (even); 0: direct")
     ap.add_argument("--no-diagnostics", action="store_true")
+    ap.add_argument("--lbm-probe", action="store_true",
+                    help="also time the LBM update alone on 256^3 (FP16, FP32, FP64 storage)")
     ap.add_argument("--baseline-workers", type=int, default=None)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=6.0)
@@ -679,6 +708,9 @@ def main(argv=None):
         "rows": rows,
         "diagnostics": diagnostics,
     }
+    if args.lbm_probe:
+        out["lbm_256cubed"] = [lbm_only(256, p) for p in ("f16", "f32", "f64")]
+        torch.cuda.empty_cache()
     out["hbm_copy"] = hbm_copy(torch)
     if base is not None:
         out["cpu_baseline"] = base

@@ -188,6 +188,12 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   }
   g.omega = 1.0 / lat->tau;
   g.fpref = 1.0 - 1.0 / (2.0 * lat->tau);
+  for (int a = 0; a < 3; ++a) {
+    g.plane_u_f[a] = (float)g.plane_u[a];
+    g.body_f[a] = (float)g.body[a];
+  }
+  g.omega_f = (float)g.omega;
+  g.fpref_f = (float)g.fpref;
   const int n[3] = {g.nx, g.ny, g.nz};
   r.bsax = bs_make_axes(n, g.wall, vor->wall_images != 0);
   r.bsS = bs_chunks(r.ncap);

@@ -12,6 +12,12 @@
 // that node's thread only, so the update is in place and race-free.
 #include "vlb_internal.h"
 
+// Multiplies and adds fuse only within one source expression, so that every
+// variant of a kernel (even or odd pass, any addressing) rounds the same
+// arithmetic the same way, whatever the surrounding control flow: a run
+// resumed in the natural layout continues bit for bit.
+#pragma clang fp contract(on)
+
 namespace vlb {
 
 namespace {
@@ -20,12 +26,20 @@ namespace {
 // f''' = f - (f - f^eq)/tau + F, with f^eq and the Cheng-Li/Guo term F built
 // from rho and u = (sum c f + g/2)/rho.
 //
-// I32 (odd passes): the lattice has fewer than 2^29 nodes and its
-// population array spans less than 4 GiB, so every neighbour slot is
-// addressed by a 32-bit byte offset from the array base (one vector
-// register per address instead of two: 147 -> 106 VGPRs for FP32 and FP16
-// storage).  Even passes address a node's own slots from one base and a
-// uniform population stride already.
+// I32: the lattice has fewer than 2^29 nodes and its population array
+// spans less than 4 GiB, so a slot has a 32-bit byte offset.  With FP16
+// storage, where the vector arithmetic is a large share of the update, the
+// array is accessed as a raw buffer: a slot's byte offset is a per-lane part
+// plus a uniform part.  Even passes use the node's own offset for all 38
+// accesses and the slot's slab as the uniform part.  Odd passes of a tile
+// that is periodic in x and y and has both z neighbours (a tile is one z
+// slice: the choice is uniform) use nine per-lane offsets, one per (dx, dy)
+// in {-1, 0, 1}^2, and the slab plus the neighbour slice as the uniform
+// part, so that no access costs vector arithmetic (256^3: odd pass 626 ->
+// 395 VALU instructions per wave, 308 -> 247 us).  Other tiles, and FP32
+// and FP64 storage (bound by HBM, and 1-3% faster with plain global
+// accesses), find each neighbour's slot (or the bounce-back slot) per lane
+// from one base.
 template <class S, int P, bool NT, bool I32>
 __device__ __forceinline__ void collide_node(S* __restrict__ M,
                                              const typename Store<S>::T* __restrict__ F,
@@ -35,92 +49,188 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
   const uint32_t c32 = (uint32_t)c;
   const uint32_t cells32 = (uint32_t)g.cells;
   constexpr uint32_t kSz = sizeof(S);
+  constexpr bool kBuf = I32 && sizeof(S) == 2;
+  const bool fast = P == 1 && kBuf && !g.wall[0] && !g.wall[1] &&
+                    (!g.wall[2] || (z > 0 && z < g.nz - 1));
+  __amdgpu_buffer_rsrc_t rs;
+  if (kBuf) rs = pop_rsrc(M, (uint32_t)(19ull * g.cells * kSz));
 
-  T d[19];
+  // raw stored values (deviations times kScale)
+  T D[19];
   Nbr nb;
   Nbr32 nb32;
-  if (P == 1) {
+  uint32_t off[3][3];  // [dy + 1][dx + 1]: byte offset of (x + dx, y + dy) in a slice
+  uint32_t zo[3];      // [dz + 1]: byte offset of slice z + dz (periodic)
+  if (P == 1 && fast) {
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
+    const uint32_t ux = (uint32_t)x, uy = (uint32_t)y, uz = (uint32_t)z;
+    const uint32_t xo[3] = {ux == 0 ? nx - 1 : ux - 1, ux, ux + 1 == nx ? 0u : ux + 1};
+    const uint32_t yo[3] = {(uy == 0 ? ny - 1 : uy - 1) * nx, uy * nx,
+                            (uy + 1 == ny ? 0u : uy + 1) * nx};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) off[a][b] = (yo[a] + xo[b]) * kSz;
+    const uint32_t sl = nx * ny * kSz;
+    zo[0] = (uz == 0 ? nz - 1 : uz - 1) * sl;
+    zo[1] = uz * sl;
+    zo[2] = (uz + 1 == nz ? 0u : uz + 1) * sl;
+  } else if (P == 1) {
     if (I32)
       make_nbr32(g, x, y, z, nb32);
     else
       make_nbr(g, x, y, z, nb);
   }
-  if (P == 0) {
+  if (P == 0 && kBuf) {
+    const uint32_t vo = c32 * kSz;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = pop_ld<S, NT>(M + (long long)i * g.cells + c);
+    for (int i = 0; i < 19; ++i) D[i] = Buf<S>::template ld<NT>(rs, vo, (uint32_t)i * cells32 * kSz);
+  } else if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) D[i] = Raw<S>::template ld<NT>(M + (long long)i * g.cells + c);
+  } else if (fast) {
+    // slot opp(i) of x - c_i
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const uint32_t o = off[1 - cy(i)][1 - cx(i)];
+      const uint32_t so = (uint32_t)opp(i) * cells32 * kSz + zo[1 - cz(i)];
+      // FP64: the x-shifted loads (a wave spans five lines instead of
+      // four) go through L2, where the neighbouring wave finds the shared
+      // line (256^3: 0.940 -> 0.932 ms per update; no gain for FP32/FP16)
+      if (NT && (sizeof(S) < 8 || cx(i) == 0))
+        D[i] = Buf<S>::template ld<true>(rs, o, so);
+      else
+        D[i] = Buf<S>::template ld<false>(rs, o, so);
+    }
   } else if (I32) {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const int s = nbr_index32(nb32, -cx(i), -cy(i), -cz(i));
       const uint32_t e = (s >= 0) ? (uint32_t)opp(i) * cells32 + (uint32_t)s
                                   : (uint32_t)i * cells32 + c32;
-      // FP64: the x-shifted loads (a wave spans five lines instead of
-      // four) go through L2, where the neighbouring wave finds the shared
-      // line (256^3: 0.940 -> 0.932 ms per update; no gain for FP32/FP16)
       if (NT && (sizeof(S) < 8 || cx(i) == 0))
-        d[i] = pop_ld<S, true>(at_byte(M, e * kSz));
+        D[i] = Raw<S>::template ld<true>(at_byte(M, e * kSz));
       else
-        d[i] = pop_ld<S, false>(at_byte(M, e * kSz));
+        D[i] = Raw<S>::template ld<false>(at_byte(M, e * kSz));
     }
   } else {
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const long long s = nbr_index(nb, -cx(i), -cy(i), -cz(i));
-      d[i] = (s >= 0) ? pop_ld<S, NT>(M + (long long)opp(i) * g.cells + s)
-                      : pop_ld<S, NT>(M + (long long)i * g.cells + c);
+      D[i] = (s >= 0) ? Raw<S>::template ld<NT>(M + (long long)opp(i) * g.cells + s)
+                      : Raw<S>::template ld<NT>(M + (long long)i * g.cells + c);
     }
   }
+  const T kS = T(Raw<S>::kScale);
+  const T kInvS = T(1) / kS;  // a power of two: exact
+  T om, pref, body[3], plane[3];
+  geom_params<T>(g, om, pref, body, plane);
   if (is_plane(g, z)) {
-    const T ux = T(g.plane_u[0]), uy = T(g.plane_u[1]), uz = T(g.plane_u[2]);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) d[i] = eq_dev<T>(i, T(0), T(1), ux, uy, uz);
+    for (int i = 0; i < 19; ++i) D[i] = kS * eq_dev<T>(i, T(0), T(1), plane[0], plane[1], plane[2]);
   }
-  T gx = T(g.body[0]), gy = T(g.body[1]), gz = T(g.body[2]);
+  T gx = body[0], gy = body[1], gz = body[2];
   if (F) {
-    gx += F[c];
-    gy += F[g.cells + c];
-    gz += F[2 * g.cells + c];
+    if (I32) {
+      const uint32_t fo = c32 * (uint32_t)sizeof(T);
+      gx += *at_byte(F, fo);
+      gy += *at_byte(F + g.cells, fo);
+      gz += *at_byte(F + 2 * g.cells, fo);
+    } else {
+      gx += F[c];
+      gy += F[g.cells + c];
+      gz += F[2 * g.cells + c];
+    }
   }
-  T drho, jx, jy, jz;
-  moments<T>(d, drho, jx, jy, jz);
+  T sD, sx, sy, sz;
+  moments<T>(D, sD, sx, sy, sz);
+  const T drho = kInvS * sD;
   const T rho = T(1) + drho;
-  const T inv = T(1) / rho;
-  const T ux = (jx + T(0.5) * gx) * inv;
-  const T uy = (jy + T(0.5) * gy) * inv;
-  const T uz = (jz + T(0.5) * gz) * inv;
-  const T om = T(g.omega);
-  const T pref = T(g.fpref);
+  T inv;
+  if constexpr (sizeof(T) == 4) {
+    // hardware reciprocal refined by one Newton step (within an ulp of 1/rho)
+    const T r0 = __builtin_amdgcn_rcpf(rho);
+    inv = fmaf(r0, fmaf(-rho, r0, 1.0f), r0);
+  } else {
+    inv = T(1) / rho;
+  }
+  const T ux = (kInvS * sx + T(0.5) * gx) * inv;
+  const T uy = (kInvS * sy + T(0.5) * gy) * inv;
+  const T uz = (kInvS * sz + T(0.5) * gz) * inv;
   const T ug = ux * gx + uy * gy + uz * gz;
+  // Post-collision value f - (f - f^eq)/tau + F_i with f^eq and the
+  // Cheng-Li/Guo term F_i built from rho and u = (sum c f + g/2)/rho
+  // (Sec. II.B, Eqs. LBM 1-3 collapsed).  It is (1 - 1/tau) d_i +
+  // [d^eq_i/tau + F_i], and the bracket splits into parts even and odd in
+  // c_i, shared by each pair (i, opp(i)): with cu = c_i.u and cg = c_i.g it
+  // is w_i (P + Q) for i and w_i (P - Q) for opp(i),
+  //   P = om (drho - 1.5 rho u.u) - 3 pref u.g + cu (4.5 om rho cu + 9 pref cg),
+  //   Q = 3 om rho cu + 3 pref cg,
+  // all of it times kScale, the storage scale.  Half the directional terms
+  // of the direct form; it matters with FP16 storage, where the arithmetic
+  // is a large share of the update.
+  T Dn[19];
+  {
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T om1 = T(1) - om;
+    const T Kp = om * (drho - T(1.5) * rho * uu) - T(3) * pref * ug;
+    const T a1 = T(4.5) * om * rho, a2 = T(9) * pref;
+    const T b1 = T(3) * om * rho, b2 = T(3) * pref;
+    Dn[0] = fma(om1, D[0], (T(wq(0)) * kS) * Kp);
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+      const int i = 2 * k - 1;  // i and opp(i) = i + 1
+      const T ws = T(wq(i)) * kS;
+      const T cu = cdot<T>(i, ux, uy, uz);
+      const T cg = cdot<T>(i, gx, gy, gz);
+      const T Pk = ws * fma(cu, fma(a1, cu, a2 * cg), Kp);
+      const T Qk = ws * fma(b1, cu, b2 * cg);
+      Dn[i] = fma(om1, D[i], Pk + Qk);
+      Dn[i + 1] = fma(om1, D[i + 1], Pk - Qk);
+    }
+  }
+  // Values in the storage format, encoded here, before the passes'
+  // addressing branches: a conversion to FP16 that the compiler fuses with
+  // the last multiply-add rounds once, and it must do so in every variant.
+  S En[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) En[i] = Raw<S>::enc(Dn[i]);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
-    const T cg = T(cx(i)) * gx + T(cy(i)) * gy + T(cz(i)) * gz;
-    const T deq = eq_dev<T>(i, drho, rho, ux, uy, uz);
-    const T Fi = pref * T(wq(i)) * (T(3) * (cg - ug) + T(9) * cu * cg);
-    const T dn = d[i] - om * (d[i] - deq) + Fi;
+    const S dn = En[i];
     // Odd passes store to the neighbours' slots: a direction with an x
     // component stores each wave's values one element off the cache lines,
     // and those partial lines must meet their other part in L2, so only the
-    // line-aligned stores (no x component) take the non-temporal hint
+    // directions without an x component bypass it with non-temporal stores
     // (256^3 FP32: 7% fewer bytes written, odd pass 537 -> 460 us).
     const bool nt_st = NT && (P == 0 || cx(i) == 0);
-    if (P == 0) {
-      pop_st<S, NT>(M + (long long)opp(i) * g.cells + c, dn);
+    if (P == 0 && kBuf) {
+      Buf<S>::template st<NT>(rs, c32 * kSz, (uint32_t)opp(i) * cells32 * kSz, dn);
+    } else if (P == 0) {
+      Raw<S>::template st_enc<NT>(M + (long long)opp(i) * g.cells + c, dn);
+    } else if (fast) {
+      // slot i of x + c_i
+      const uint32_t o = off[1 + cy(i)][1 + cx(i)];
+      const uint32_t so = (uint32_t)i * cells32 * kSz + zo[1 + cz(i)];
+      if (nt_st)
+        Buf<S>::template st<true>(rs, o, so, dn);
+      else
+        Buf<S>::template st<false>(rs, o, so, dn);
     } else if (I32) {
       const int s = nbr_index32(nb32, cx(i), cy(i), cz(i));
       const uint32_t e = (s >= 0) ? (uint32_t)i * cells32 + (uint32_t)s
                                   : (uint32_t)opp(i) * cells32 + c32;
       if (nt_st)
-        pop_st<S, true>(at_byte(M, e * kSz), dn);
+        Raw<S>::template st_enc<true>(at_byte(M, e * kSz), dn);
       else
-        pop_st<S, false>(at_byte(M, e * kSz), dn);
+        Raw<S>::template st_enc<false>(at_byte(M, e * kSz), dn);
     } else {
       const long long s = nbr_index(nb, cx(i), cy(i), cz(i));
       S* p = (s >= 0) ? M + (long long)i * g.cells + s : M + (long long)opp(i) * g.cells + c;
       if (nt_st)
-        pop_st<S, true>(p, dn);
+        Raw<S>::template st_enc<true>(p, dn);
       else
-        pop_st<S, false>(p, dn);
+        Raw<S>::template st_enc<false>(p, dn);
     }
   }
 }
@@ -128,17 +238,20 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
 // Tiles of (bx, 256 / bx) nodes (x, y) of one z slice; hardware blocks are mapped
 // so that the blocks of one XCD cover one contiguous range of tiles.  The
 // grid may be smaller than the tile count (a multiple of 8): each block
-// then walks tiles b, b + grid, ..., which stay on its XCD's range.
+// then walks tiles b, b + grid, ..., which stay on its XCD's range.  The
+// tile id splits into (x tile, y tile, z) by divisions by the launch's
+// tile counts.
 template <class S, int P, bool NT, bool I32>
 __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
                                                         const typename Store<S>::T* __restrict__ F,
-                                                        Geom g, int nbx, int nby, int nblk) {
+                                                        Geom g, FastDiv fbx, FastDiv fby, int nblk) {
   for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
-    const int t = xcd_remap(it, nblk);
-    const int bxi = t % nbx;
-    const int rr = t / nbx;
-    const int byi = rr % nby;
-    const int z = rr / nby;
+    const uint32_t t = (uint32_t)xcd_remap(it, nblk);
+    const uint32_t rr = fdiv(t, fbx);
+    const uint32_t zq = fdiv(rr, fby);
+    const int bxi = (int)(t - rr * fbx.d);
+    const int byi = (int)(rr - zq * fby.d);
+    const int z = (int)zq;
     const int x = bxi * blockDim.x + threadIdx.x;
     const int y = byi * blockDim.y + threadIdx.y;
     if (x < g.nx && y < g.ny) collide_node<S, P, NT, I32>(M, F, g, x, y, z);
@@ -365,10 +478,12 @@ hipError_t launch_collide(Run& r) {
   // odd passes: 32-bit slot offsets when the population array spans less than 4 GiB
   const bool i32 = g.cells < (1LL << 29) && 19.0 * (double)g.cells * sizeof(S) < 4294967296.0;
   auto kern = r.parity == 0
-                  ? (nt ? k_collide_stream<S, 0, true, false> : k_collide_stream<S, 0, false, false>)
+                  ? (i32 ? (nt ? k_collide_stream<S, 0, true, true> : k_collide_stream<S, 0, false, true>)
+                         : (nt ? k_collide_stream<S, 0, true, false> : k_collide_stream<S, 0, false, false>))
                   : (i32 ? (nt ? k_collide_stream<S, 1, true, true> : k_collide_stream<S, 1, false, true>)
                          : (nt ? k_collide_stream<S, 1, true, false> : k_collide_stream<S, 1, false, false>));
-  hipLaunchKernelGGL(kern, dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g, nbx, nby, nblk);
+  hipLaunchKernelGGL(kern, dim3(grid), blk, 0, r.stream, (S*)r.pops, F, g, make_fastdiv(nbx),
+                     make_fastdiv(nby), nblk);
   return hipGetLastError();
 }
 

@@ -81,6 +81,83 @@ __device__ inline void pop_st(S* p, typename Store<S>::T v) {
     Store<S>::st(p, v);
 }
 
+// Stored values as they are kept (FP16: the deviation times 2^10; otherwise
+// the deviation itself) and that scale: deviation = raw / kScale.  The
+// non-temporal choice is a template argument: as a run-time flag, the two
+// forms of an access merge into one plain access and the hint is lost.
+template <class S> struct Raw;
+template <> struct Raw<double> {
+  static constexpr double kScale = 1.0;
+  template <bool NT> __device__ static double ld(const double* p) { return pop_ld<double, NT>(p); }
+  template <bool NT> __device__ static void st(double* p, double v) { pop_st<double, NT>(p, v); }
+  __device__ static double enc(double v) { return v; }
+  template <bool NT> __device__ static void st_enc(double* p, double v) { pop_st<double, NT>(p, v); }
+};
+template <> struct Raw<float> {
+  static constexpr float kScale = 1.0f;
+  template <bool NT> __device__ static float ld(const float* p) { return pop_ld<float, NT>(p); }
+  template <bool NT> __device__ static void st(float* p, float v) { pop_st<float, NT>(p, v); }
+  __device__ static float enc(float v) { return v; }
+  template <bool NT> __device__ static void st_enc(float* p, float v) { pop_st<float, NT>(p, v); }
+};
+template <> struct Raw<__half> {
+  static constexpr float kScale = kHalfScale;
+  template <bool NT> __device__ static float ld(const __half* p) {
+    if (NT) return __half2float(__ushort_as_half(__builtin_nontemporal_load((const unsigned short*)p)));
+    return __half2float(*p);
+  }
+  template <bool NT> __device__ static void st(__half* p, float v) {
+    if (NT)
+      __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short*)p);
+    else
+      *p = __float2half_rn(v);
+  }
+  // the stored value, rounded to nearest
+  __device__ static __half enc(float v) { return __float2half_rn(v); }
+  template <bool NT> __device__ static void st_enc(__half* p, __half h) {
+    if (NT)
+      __builtin_nontemporal_store(__half_as_ushort(h), (unsigned short*)p);
+    else
+      *p = h;
+  }
+};
+
+// Population array as a raw buffer (I32 lattices: fewer than 4 GiB): an
+// access names a per-lane byte offset (VGPR) and a uniform one (SGPR), so
+// that a slot at a uniform distance from a lane's node costs no vector
+// arithmetic.  Cache policy 2 is the non-temporal hint.
+typedef unsigned int vlb_u32x2 __attribute__((ext_vector_type(2)));
+template <class S>
+__device__ inline __amdgpu_buffer_rsrc_t pop_rsrc(S* M, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(M, 0, (int)bytes, 0x00020000);
+}
+template <class S> struct Buf;
+template <> struct Buf<double> {
+  template <bool NT> __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, NT ? 2 : 0));
+  }
+  template <bool NT> __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vlb_u32x2, v), r, vo, so, NT ? 2 : 0);
+  }
+};
+template <> struct Buf<float> {
+  template <bool NT> __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, NT ? 2 : 0));
+  }
+  template <bool NT> __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, NT ? 2 : 0);
+  }
+};
+template <> struct Buf<__half> {
+  template <bool NT> __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, NT ? 2 : 0)));
+  }
+  template <bool NT> __device__ static void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, __half h) {
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(h), r, vo, so, NT ? 2 : 0);
+  }
+};
+
+
 // Lattice description as passed to kernels.
 struct Geom {
   int nx, ny, nz;
@@ -91,7 +168,76 @@ struct Geom {
   double body[3];
   double omega;       // 1/tau
   double fpref;       // 1 - 1/(2 tau)
+  // the same parameters rounded to FP32 once, for the FP32 arithmetic
+  float plane_u_f[3];
+  float body_f[3];
+  float omega_f;
+  float fpref_f;
 };
+
+// Geometry parameters in the arithmetic type T.
+template <class T>
+__device__ inline void geom_params(const Geom& g, T& om, T& pref, T body[3], T plane[3]) {
+  if constexpr (sizeof(T) == 4) {
+    om = g.omega_f;
+    pref = g.fpref_f;
+    for (int a = 0; a < 3; ++a) {
+      body[a] = g.body_f[a];
+      plane[a] = g.plane_u_f[a];
+    }
+  } else {
+    om = g.omega;
+    pref = g.fpref;
+    for (int a = 0; a < 3; ++a) {
+      body[a] = g.body[a];
+      plane[a] = g.plane_u[a];
+    }
+  }
+}
+
+// c_i . (x, y, z) summed over the nonzero components of c_i only (they are
+// +-1), so that no product with a zero component is evaluated.
+template <class T>
+__device__ __forceinline__ T cdot(int i, T x, T y, T z) {
+  const int a = cx(i), b = cy(i), c = cz(i);
+  T r = T(0);
+  bool any = false;
+  if (a != 0) {
+    r = a > 0 ? x : -x;
+    any = true;
+  }
+  if (b != 0) {
+    const T v = b > 0 ? y : -y;
+    r = any ? r + v : v;
+    any = true;
+  }
+  if (c != 0) {
+    const T v = c > 0 ? z : -z;
+    r = any ? r + v : v;
+  }
+  return r;
+}
+
+// Quotient by a divisor d >= 1 fixed for a launch, by multiplication
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, Fig. 4.1): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, t / d = (h + ((t - h) >> s1)) >> s2
+// for h = mulhi(m, t), s1 = min(l, 1), s2 = max(l - 1, 0); exact for every
+// 32-bit t.  Uniform operands keep it on the scalar unit.
+struct FastDiv {
+  uint32_t d, m;
+  int s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  int l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  const uint32_t m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  return FastDiv{d, m, l < 1 ? l : 1, l > 1 ? l - 1 : 0};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t t, const FastDiv& f) {
+  const uint32_t h = __umulhi(f.m, t);
+  return (h + ((t - h) >> f.s1)) >> f.s2;
+}
 
 // Index of node (x, y, z) + (dx, dy, dz), or -1 when that node lies beyond
 // a wall (periodic axes wrap).
@@ -190,6 +336,10 @@ template <class S>
 __device__ inline S* at_byte(S* M, uint32_t byte_off) {
   return reinterpret_cast<S*>(reinterpret_cast<char*>(M) + byte_off);
 }
+template <class S>
+__device__ inline const S* at_byte(const S* M, uint32_t byte_off) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(M) + byte_off);
+}
 
 // Deviations of the populations at node (x, y, z) at a time whose storage
 // parity is P (0: natural layout, population i of node x in slot i of x;
@@ -222,7 +372,7 @@ __device__ inline bool is_plane(const Geom& g, int z) {
 // Equilibrium deviation f^eq_i(rho, u) - w_i for rho = 1 + drho.
 template <class T>
 __device__ inline T eq_dev(int i, T drho, T rho, T ux, T uy, T uz) {
-  const T cu = T(cx(i)) * ux + T(cy(i)) * uy + T(cz(i)) * uz;
+  const T cu = cdot<T>(i, ux, uy, uz);
   const T uu = ux * ux + uy * uy + uz * uz;
   return T(wq(i)) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu));
 }
@@ -230,13 +380,27 @@ __device__ inline T eq_dev(int i, T drho, T rho, T ux, T uy, T uz) {
 // Density deviation and momentum of a node's deviations.
 template <class T>
 __device__ inline void moments(const T d[19], T& drho, T& jx, T& jy, T& jz) {
-  T r = 0, a = 0, b = 0, c = 0;
+  // each sum starts from its first term (no addition of a zero)
+  T r = d[0], a = T(0), b = T(0), c = T(0);
+  bool ha = false, hb = false, hc = false;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 1; i < 19; ++i) {
     r += d[i];
-    if (cx(i)) a += T(cx(i)) * d[i];
-    if (cy(i)) b += T(cy(i)) * d[i];
-    if (cz(i)) c += T(cz(i)) * d[i];
+    if (cx(i)) {
+      const T v = cx(i) > 0 ? d[i] : -d[i];
+      a = ha ? a + v : v;
+      ha = true;
+    }
+    if (cy(i)) {
+      const T v = cy(i) > 0 ? d[i] : -d[i];
+      b = hb ? b + v : v;
+      hb = true;
+    }
+    if (cz(i)) {
+      const T v = cz(i) > 0 ? d[i] : -d[i];
+      c = hc ? c + v : v;
+      hc = true;
+    }
   }
   drho = r;
   jx = a;

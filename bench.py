@@ -391,7 +391,11 @@ def measure(cfg, args, ref, graph):
     bs_us = bs_ms * 1e3 / max(bs_n, 1)
     pairs_launch = pairs / max(bs_n, 1)
     lbm_us = lbm_ms * 1e3 / max(lbm_n, 1)
-    lbm_bytes = 2 * 19 * STORE_BYTES[prec] * cells
+    # populations read and written, plus the spread force field (three
+    # components in the arithmetic type) that a coupled update reads
+    force_node = 3 * (8 if prec == "f64" else 4) if cfg["vortex"].get("coupling", True) else 0
+    lbm_node = 2 * 19 * STORE_BYTES[prec] + force_node
+    lbm_bytes = lbm_node * cells
     row = {
         "precision": prec,
         "value": round(args.steps / wall, 4),
@@ -412,10 +416,11 @@ def measure(cfg, args, ref, graph):
                       "basis": bs_basis},
         "lbm_kernel": {"avg_launch_us": round(lbm_us, 2), "launches": int(lbm_n),
                        "glups": round(cells / (lbm_us * 1e-6) / 1e9, 3),
-                       "bytes_per_node": 2 * 19 * STORE_BYTES[prec],
+                       "bytes_per_node": lbm_node,
+                       "force_bytes_per_node": force_node,
                        "algorithmic_GBs": round(lbm_bytes / (lbm_us * 1e-6) / 1e9, 1),
-                       "population_bytes": lbm_bytes // 2,
-                       "cache_resident": lbm_bytes // 2 <= LLC_BYTES},
+                       "population_bytes": 19 * STORE_BYTES[prec] * cells,
+                       "cache_resident": 19 * STORE_BYTES[prec] * cells <= LLC_BYTES},
         "accuracy_vs_oracle": acc,
     }
     extra = {"run": run, "cells": cells, "pairs_launch": pairs_launch, "bs_us": bs_us,

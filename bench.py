@@ -145,7 +145,7 @@ def _pool_bs(targets):
     t0 = time.perf_counter()
     v = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, kappa, targets=targets, chunk=16)
     if images:
-        v = v + vfm.biot_savart_images(pos, nxt, lat, kappa, targets=targets, chunk=16)
+        v = v + vfm.biot_savart_images(pos, nxt, prv, lat, kappa, targets=targets, chunk=16)
     return v, time.perf_counter() - t0
 
 

@@ -33,8 +33,13 @@ class State:
 
 
 def prev_from_next(nxt):
-    prv = np.empty_like(nxt)
-    prv[nxt] = np.arange(nxt.shape[0])
+    """Predecessors: prv[nxt[k]] = k for every real link; the first point
+    of an open line (no predecessor) is its own (reading F1b)."""
+    nxt = np.asarray(nxt)
+    ks = np.arange(nxt.shape[0])
+    prv = ks.copy()
+    real = nxt != ks
+    prv[nxt[real]] = ks[real]
     return prv
 
 

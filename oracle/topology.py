@@ -79,7 +79,8 @@ def _deletion_flags(cand, nxt, prv):
 def remesh(pos, nxt, prv, lat: Lattice, dxi_min, dxi_max):
     """Keep segment lengths inside [dxi_min, dxi_max] (Sec. II.A; reading R10).
 
-    1. Deletion.  Point k is a candidate when its incoming segment
+    1. Deletion.  The ends of an open line are never deleted (reading
+       F1b); any other point k is a candidate when its incoming segment
        (prv[k] -> k) is shorter than dxi_min and the chord prv[k] -> nxt[k]
        that would replace its two segments is not longer than dxi_max (so a
        deletion never calls for a new insertion: with the paper's bounds,
@@ -101,6 +102,8 @@ def remesh(pos, nxt, prv, lat: Lattice, dxi_min, dxi_max):
     mx2 = dxi_max * dxi_max
     cand = np.zeros(N, dtype=bool)
     for k in range(N):
+        if nxt[k] == k or prv[k] == k:
+            continue  # the ends of an open line stay on their walls (F1b)
         d = min_image((pos[k] - pos[prv[k]])[None, :], lat)[0]
         chord = min_image((pos[nxt[k]] - pos[prv[k]])[None, :], lat)[0]
         cand[k] = (_sq(d) < mn2) and (_sq(chord) <= mx2)
@@ -140,7 +143,10 @@ def reconnect(pos, nxt, prv, lat: Lattice, dist):
     (Sec. II.A and III.B; reading R11).
 
     Candidates: pairs i < j with |s_j - s_i| < dist (nearest image) that are
-    more than two links apart along the loop.  A candidate is kept if the
+    more than two links apart along the loop, and both of which have a
+    segment (the last point of an open line has none, reading F1b; the
+    exchange keeps every open line open, with its ends on the walls).  A
+    candidate is kept if the
     exchange i -> nxt[j], j -> nxt[i] does not lengthen the line:
     |s_nxt[j] - s_i| + |s_nxt[i] - s_j| <= |s_nxt[i] - s_i| + |s_nxt[j] - s_j|.
     Kept candidates are taken greedily in ascending (d^2, i, j); a point
@@ -152,9 +158,11 @@ def reconnect(pos, nxt, prv, lat: Lattice, dist):
     d2max = dist * dist
     cands = []
     for i in range(N):
+        if nxt[i] == i:
+            continue
         near = {nxt[i], nxt[nxt[i]], prv[i], prv[prv[i]]}
         for j in range(i + 1, N):
-            if j in near:
+            if j in near or nxt[j] == j:
                 continue
             d = min_image((pos[j] - pos[i])[None, :], lat)[0]
             d2 = _sq(d)
@@ -184,20 +192,70 @@ def reconnect(pos, nxt, prv, lat: Lattice, dist):
     return nxt, prv, n_rec
 
 
-def small_loops(nxt, min_pts):
-    """Mark points on loops with fewer than ``min_pts`` points (they are
-    removed: such loops are below the resolution).  Returns alive mask."""
+def small_loops(nxt, min_pts, prv=None):
+    """Mark points on filaments with fewer than ``min_pts`` points (they are
+    removed: such loops are below the resolution): closed loops, and open
+    lines counted from their first to their last point (reading F1b; needs
+    ``prv``).  Returns alive mask."""
     N = nxt.shape[0]
     alive = np.ones(N, dtype=bool)
     for k in range(N):
-        p = nxt[k]
-        steps = 1
-        while p != k and steps < min_pts:
-            p = nxt[p]
-            steps += 1
-        if p == k and steps < min_pts:
+        # forward: back to k (a loop), or to the last point of an open line
+        p = k
+        fwd = 0
+        closed = False
+        while fwd < min_pts:
+            q = nxt[p]
+            if q == p:
+                break
+            if q == k:
+                closed = True
+                break
+            p = q
+            fwd += 1
+        if closed:
+            alive[k] = fwd + 1 >= min_pts
+            continue
+        if nxt[p] != p:
+            continue  # min_pts points ahead already
+        # open line: back to its first point
+        b = 0
+        p = k
+        while b < min_pts and prv[p] != p:
+            p = prv[p]
+            b += 1
+        if prv[p] == p and fwd + b + 1 < min_pts:
             alive[k] = False
     return alive
+
+
+def check_lines(pos, nxt, lat: Lattice):
+    """Validate the links of a filament state (reading F1b): every point has
+    at most one predecessor besides itself, and the ends of open lines (a
+    point that links to itself, or that no other point links to) lie on a
+    wall plane of a closed axis; a single point that is both is not a line.
+    Raises ValueError."""
+    nxt = np.asarray(nxt)
+    N = nxt.shape[0]
+    if N == 0:
+        return
+    if nxt.min() < 0 or nxt.max() >= N:
+        raise ValueError("next[] out of range")
+    ks = np.arange(N)
+    real = nxt != ks
+    indeg = np.bincount(nxt[real], minlength=N)
+    if indeg.max(initial=0) > 1:
+        raise ValueError("a point has two predecessors")
+    last = ~real
+    first = indeg == 0
+    if np.any(last & first):
+        raise ValueError("a one-point line")
+    on_wall = np.zeros(N, dtype=bool)
+    for a in range(3):
+        if lat.walls[a]:
+            on_wall |= (pos[:, a] == -0.5) | (pos[:, a] == lat.dims[a] - 0.5)
+    if np.any((last | first) & ~on_wall):
+        raise ValueError("an open line ends off the wall planes")
 
 
 def topology_update(pos, nxt, prv, lat: Lattice, vp):
@@ -207,13 +265,13 @@ def topology_update(pos, nxt, prv, lat: Lattice, vp):
     if vp.remesh:
         pos, nxt, prv, nd, ni = remesh(pos, nxt, prv, lat, vp.dxi_min, vp.dxi_max)
         stats["deleted"], stats["inserted"] = nd, ni
-    alive = small_loops(nxt, vp.min_loop_pts)
+    alive = small_loops(nxt, vp.min_loop_pts, prv)
     stats["loops_removed_pts"] += int((~alive).sum())
     pos, nxt, prv = compact(pos, nxt, prv, alive)
     if vp.reconnect:
         nxt, prv, nr = reconnect(pos, nxt, prv, lat, vp.reconnect_dist)
         stats["reconnections"] = nr
-        alive = small_loops(nxt, vp.min_loop_pts)
+        alive = small_loops(nxt, vp.min_loop_pts, prv)
         stats["loops_removed_pts"] += int((~alive).sum())
         pos, nxt, prv = compact(pos, nxt, prv, alive)
     return pos, nxt, prv, stats

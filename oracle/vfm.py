@@ -6,8 +6,12 @@ spreading); Sec. III.C (mass-balance superflow).
 
 Filament state: ``pos`` (N, 3) float64 in lattice units (x, y, z), and two
 int arrays ``nxt`` / ``prv`` linking every point to its successor and
-predecessor on a closed loop (the arc-length parametrisation of Sec. II.A).
-Segment k runs from point k to point nxt[k].
+predecessor (the arc-length parametrisation of Sec. II.A).  Segment k runs
+from point k to point nxt[k].  A filament is a closed loop or an open line
+bound to the walls (Sec. IV: vortex lines bound to the solid walls; reading
+F1b): the last point of an open line links to itself (nxt[e] = e, so its
+segment has zero length) and the first point is its own predecessor
+(prv[s] = s); both lie on a wall plane of a closed axis.
 """
 
 from dataclasses import dataclass
@@ -103,6 +107,38 @@ def dot(a, b):
     return a[..., 0] * b[..., 0] + a[..., 1] * b[..., 1] + a[..., 2] * b[..., 2]
 
 
+def end_walls(pos, nxt, prv, lat: Lattice):
+    """The wall an open line's end point is bound to (reading F1b): for every
+    point, the first closed axis a (x, y, z order) whose wall plane -1/2
+    (side 1) or n - 1/2 (side 2) the point lies on exactly, if the point is
+    an end (nxt[k] = k or prv[k] = k); axis -1 otherwise.  Returns
+    (axis, side) int arrays."""
+    N = pos.shape[0]
+    axis = np.full(N, -1, dtype=np.int64)
+    side = np.zeros(N, dtype=np.int64)
+    ks = np.arange(N)
+    end = (np.asarray(nxt) == ks) | (np.asarray(prv) == ks)
+    for a in (2, 1, 0):  # lowest axis wins
+        if not lat.walls[a]:
+            continue
+        for sd, w in ((1, -0.5), (2, lat.dims[a] - 0.5)):
+            on = end & (pos[:, a] == w)
+            axis = np.where(on, a, axis)
+            side = np.where(on, sd, side)
+    return axis, side
+
+
+def reflect_except(v, axis):
+    """v with every component but the one along ``axis`` negated (per row;
+    rows with axis -1 unchanged): the mirror image, in a plane normal to
+    that axis, of a vector that crosses the plane."""
+    v = np.array(v, dtype=np.float64, copy=True)
+    for a in range(3):
+        m = (axis >= 0) & (axis != a)
+        v[m, a] = -v[m, a]
+    return v
+
+
 def geometry(pos, nxt, prv, lat: Lattice):
     """Local geometry at every point (Sec. II.A; formulas are reading R5).
 
@@ -110,16 +146,31 @@ def geometry(pos, nxt, prv, lat: Lattice):
     non-uniform three-point derivatives along the arc length
       s'  = (l-^2 d+ + l+^2 d-) / (l+ l- (l+ + l-)),   then normalised,
       s'' = 2 (l- d+ - l+ d-) / (l+ l- (l+ + l-)).
-    """
+    At the end of an open line (reading F1b) the line continues into its
+    mirror image in the wall: the missing neighbour is the mirror image of
+    the existing one, so d+ of a last point is d- reflected in the wall
+    plane (normal component kept, the others negated) and d- of a first
+    point is d+ reflected; s' is then normal to the wall and s'' lies in it.
+    ``lp_real`` / ``lm_real`` are the lengths of the segments that exist
+    (0 for the missing one)."""
     dp = min_image(pos[nxt] - pos, lat)
     dm = min_image(pos - pos[prv], lat)
+    lp_real = norm(dp)
+    lm_real = norm(dm)
+    ks = np.arange(pos.shape[0])
+    axis, _ = end_walls(pos, nxt, prv, lat)
+    last = (np.asarray(nxt) == ks) & (axis >= 0)
+    first = (np.asarray(prv) == ks) & (axis >= 0)
+    dp = np.where(last[:, None], reflect_except(dm, axis), dp)
+    dm = np.where(first[:, None], reflect_except(dp, axis), dm)
     lp = norm(dp)
     lm = norm(dm)
     den = (lp * lm * (lp + lm))[:, None]
     sp = (lm[:, None] ** 2 * dp + lp[:, None] ** 2 * dm) / den
     sp = sp / norm(sp)[:, None]
     spp = 2.0 * (lm[:, None] * dp - lp[:, None] * dm) / den
-    return dict(dp=dp, dm=dm, lp=lp, lm=lm, sp=sp, spp=spp)
+    return dict(dp=dp, dm=dm, lp=lp, lm=lm, sp=sp, spp=spp, lp_real=lp_real,
+                lm_real=lm_real, end_axis=axis)
 
 
 def lia_velocity(geo, vp: VortexParams):
@@ -235,30 +286,44 @@ def mirror(pos, refl, lat: Lattice):
     return p
 
 
-def biot_savart_images(pos, nxt, lat: Lattice, kappa, targets=None, chunk=64):
+def biot_savart_images(pos, nxt, prv, lat: Lattice, kappa, targets=None, chunk=64):
     """Boundary superflow v_s,b of Sec. II.A, Eq. (Biot-Savart), from image
     filaments (reading F1): for every image copy (image_copies) the sum over
     all of its segments (mirrored start, mirrored segment vector) of the
-    straight-segment integral, times the copy's sign; none is excluded.  On
-    periodic axes each image segment is taken at the nearest image of its
-    start, as the real ones."""
+    straight-segment integral, times the copy's sign.  On periodic axes each
+    image segment is taken at the nearest image of its start, as the real
+    ones.  Nothing is excluded except at the end of an open line (reading
+    F1b): in the copy mirrored in that end's own wall only, the images of the
+    two segments that touch the end (k = prv[j], k = j) meet the target;
+    with the real ones they are the local part of the line continued through
+    the wall, which the LIA term with the mirrored neighbour replaces."""
     N = pos.shape[0]
     if targets is None:
         targets = np.arange(N)
     targets = np.asarray(targets, dtype=np.int64)
     out = np.zeros((targets.size, 3), dtype=np.float64)
     seg = min_image(pos[nxt] - pos, lat)
+    axis, side = end_walls(pos, nxt, prv, lat)
+    ks = np.arange(N)
     for refl, sign in image_copies(lat):
         mp = mirror(pos, refl, lat)
         mseg = seg.copy()
         for a in range(3):
             if refl[a]:
                 mseg[:, a] = -mseg[:, a]
+        # targets whose own wall is this copy's only reflection
+        own = np.zeros(N, dtype=bool)
+        if sum(1 for r in refl if r) == 1:
+            a = [i for i in range(3) if refl[i]][0]
+            own = (axis == a) & (side == refl[a])
         for c0 in range(0, targets.size, chunk):
             tj = targets[c0:c0 + chunk]
             R1 = bs_image_offsets(mp[None, :, :], pos[tj][:, None, :], lat)
             R2 = R1 + mseg[None, :, :]
-            v = segment_velocity(R1, R2, kappa)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                v = segment_velocity(R1, R2, kappa)  # excluded pairs may be 0/0
+            drop = own[tj][:, None] & ((ks[None, :] == tj[:, None]) | (ks[None, :] == prv[tj][:, None]))
+            v = np.where(drop[:, :, None], 0.0, v)
             out[c0:c0 + chunk] += sign * v.sum(axis=1)
     return out
 
@@ -385,15 +450,20 @@ def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_fo
     geo = geometry(pos, nxt, prv, lat)
     vs = biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa) + lia_velocity(geo, vp)
     if vp.wall_images:
-        vs = vs + biot_savart_images(pos, nxt, lat, vp.kappa)
+        vs = vs + biot_savart_images(pos, nxt, prv, lat, vp.kappa)
     vs = vs + np.array(vp.vs_applied, dtype=np.float64)[None, :]
     if Vs is not None:
         vs[:, 2] = vs[:, 2] + superflow_at(Vs, pos[:, 2], lat.nz)
     vn = interpolate(ub, pos, lat)
     alpha, alpha_p = friction_at(vp, pos[:, 2], lat)
     sdot = schwarz_velocity(vs, vn, geo["sp"], alpha, alpha_p)
+    # an open line's end slides on its wall: no velocity normal to it (F1b)
+    ax = geo["end_axis"]
+    for a in range(3):
+        sdot[ax == a, a] = 0.0
     out = dict(vs=vs, vn=vn, sdot=sdot, geo=geo)
     if want_force:
-        dxi = 0.5 * (geo["lp"] + geo["lm"])
+        # the line length a point carries: half of each segment that exists
+        dxi = 0.5 * (geo["lp_real"] + geo["lm_real"])
         out["force"] = mutual_friction_force(sdot, vs, geo["sp"], dxi, vp)
     return out

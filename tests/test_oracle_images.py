@@ -55,7 +55,7 @@ def test_line_parallel_to_one_pair_of_walls():
     x0, y0 = 3.3, 4.1
     pos, nxt = _line(x0, y0, nz)
     prv = coupled.prev_from_next(nxt)
-    got = vfm.biot_savart_images(pos, nxt, lat, KAPPA)
+    got = vfm.biot_savart_images(pos, nxt, coupled.prev_from_next(nxt), lat, KAPPA)
     want = _line_images_by_hand([(-1.0 - x0, y0, -1.0), (2 * nx - 1.0 - x0, y0, -1.0)],
                                 x0, y0, nz)
     np.testing.assert_allclose(got, np.tile(want, (nz, 1)), rtol=0, atol=1e-15)
@@ -85,7 +85,7 @@ def test_line_in_a_channel_corner():
     images = [(xs[i], ys[k], (-1.0) ** ((i > 0) + (k > 0)))
               for i in range(3) for k in range(3) if (i, k) != (0, 0)]
     want = _line_images_by_hand(images, x0, y0, nz)
-    got = vfm.biot_savart_images(pos, nxt, lat, KAPPA)
+    got = vfm.biot_savart_images(pos, nxt, coupled.prev_from_next(nxt), lat, KAPPA)
     np.testing.assert_allclose(got, np.tile(want, (nz, 1)), rtol=0, atol=1e-15)
     assert len(vfm.image_copies(lat)) == 8
 
@@ -101,7 +101,7 @@ def test_ring_approaching_a_wall_is_slowed_and_stretched():
     geo = vfm.geometry(pos, nxt, prv, lat)
     v_self = vs + vfm.lia_velocity(geo, VortexParams(kappa=KAPPA))
     assert (v_self[:, 0] < 0).all()        # the ring moves toward the wall
-    vb = vfm.biot_savart_images(pos, nxt, lat, KAPPA)
+    vb = vfm.biot_savart_images(pos, nxt, coupled.prev_from_next(nxt), lat, KAPPA)
     rad = pos[:, 1:] - 16.0
     rad /= np.linalg.norm(rad, axis=1)[:, None]
     radial = (vb[:, 1:] * rad).sum(axis=1)
@@ -134,5 +134,5 @@ def test_images_equal_mirrored_loops_run_backwards():
     Pv = coupled.prev_from_next(Nx)
     combined = vfm.biot_savart_nonlocal(P, Nx, Pv, lat, KAPPA, targets=np.arange(n))
     real = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, KAPPA)
-    got = vfm.biot_savart_images(pos, nxt, lat, KAPPA)
+    got = vfm.biot_savart_images(pos, nxt, coupled.prev_from_next(nxt), lat, KAPPA)
     np.testing.assert_allclose(got, combined - real, rtol=1e-12, atol=1e-16)

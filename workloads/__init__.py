@@ -31,6 +31,31 @@ def ring(center, radius, normal, n_pts, phase=0.5):
     return pos, nxt.astype(np.int64)
 
 
+def wall_line(foot, axis, n_axis, n_pts, reverse=False, amp=0.0, turns=0.0, phase=0.0):
+    """Open vortex line bound to the two walls of a closed axis: ``n_pts``
+    points evenly spaced along ``axis`` from the wall plane -1/2 to
+    n_axis - 1/2 (both ends exactly on the planes), at transverse position
+    ``foot`` (the two other coordinates, in axis order), displaced
+    transversally by a helix of amplitude ``amp`` and ``turns`` turns.
+    ``reverse`` runs it from the upper wall to the lower one (opposite
+    circulation).  The last point links to itself.
+    Returns (pos (n, 3) float64, nxt (n,) int64)."""
+    t = np.linspace(0.0, 1.0, n_pts)
+    if reverse:
+        t = t[::-1]
+    others = [a for a in range(3) if a != axis]
+    pos = np.zeros((n_pts, 3))
+    pos[:, axis] = -0.5 + t * float(n_axis)
+    pos[0, axis] = n_axis - 0.5 if reverse else -0.5
+    pos[-1, axis] = -0.5 if reverse else n_axis - 0.5
+    ang = 2.0 * np.pi * (turns * t + phase)
+    pos[:, others[0]] = foot[0] + amp * np.cos(ang)
+    pos[:, others[1]] = foot[1] + amp * np.sin(ang)
+    nxt = np.arange(1, n_pts + 1)
+    nxt[-1] = n_pts - 1
+    return pos, nxt.astype(np.int64)
+
+
 def concat_loops(loops):
     """Concatenate (pos, nxt) loops into one point set with global links."""
     if not loops:
@@ -201,6 +226,32 @@ def config_heater(precision="f32", n_rings=1500, nxy=128, nz=512, seed=3):
                             min_sep=1.5)
     return dict(name="heater_128x128x512", lattice=lat, vortex=vor, rho=rho, u=u,
                 pos=pos, nxt=nxt, steps=2000)
+
+
+def config_closed_channel(precision="f64", nxy=48, nz=128, seed=6):
+    """Closed channel with lines bound to its end walls (the paper's Sec. IV
+    initial condition, synthetic stand-in): walls on z (the streaming axis),
+    x and y periodic; velocity planes z = 0 / z = nz-1 at v_n = 0.03 z; four
+    lines from wall to wall along z (two each way, feet on a square of side
+    nxy/2, helical displacement 0.5 with 3 turns) and two rings R = nxy/8
+    beside them; wall images, reconnection and mass balance on."""
+    rng = np.random.default_rng(seed)
+    lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(False, False, True), plane_lo=True,
+                         plane_hi=True, plane_u=(0.0, 0.0, 0.03), precision=precision)
+    vor = vortex_preset(reconnect=True, mass_balance=True, wall_images=True)
+    rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.03), 1e-4)
+    n_pts = int(math.ceil(nz / 0.9)) + 1
+    q = nxy / 4.0
+    feet = ((q, q), (3 * q, q), (3 * q, 3 * q), (q, 3 * q))
+    loops = [wall_line(f, 2, nz, n_pts, reverse=(i % 2 == 1), amp=0.5, turns=3.0,
+                       phase=float(rng.uniform())) for i, f in enumerate(feet)]
+    R = nxy / 8.0
+    m = int(math.ceil(2.0 * np.pi * R / 0.9))
+    loops.append(ring((2 * q, q, nz / 4.0), R, (0.0, 0.0, 1.0), m))
+    loops.append(ring((2 * q, 3 * q, 3 * nz / 4.0), R, (0.0, 0.0, -1.0), m))
+    pos, nxt = concat_loops(loops)
+    return dict(name=f"closed_channel_{nxy}x{nxy}x{nz}", lattice=lat, vortex=vor, rho=rho, u=u,
+                pos=pos, nxt=nxt, steps=100)
 
 
 def config_tangle(precision="f16", n=256, n_rings=2000, seed=4):

@@ -136,12 +136,18 @@ int vlb_create_lattice(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor,
  * spread force field.                                                      */
 int vlb_write_fields(vlb_run* run, const double* rho_dev, const double* u_dev);
 
-/* Replace the filaments by n_pts points (host xyz[n][3], lattice units) on
- * closed loops given by next (host, n ints, a permutation whose cycles are
- * the loops).  Positions on periodic axes are wrapped into [0, L) by one
- * shift of L; a wall axis mirrors a point beyond the wall plane (-1/2 or
- * L - 1/2) once.  VLB_EINVAL when that leaves a coordinate outside the box
- * (more than one length L away), or for a non-finite coordinate.          */
+/* Replace the filaments by n_pts points (host xyz[n][3], lattice units)
+ * linked by next (host, n ints, the successor of each point).  A filament
+ * is a closed loop or an open line bound to the walls (Sec. IV: lines bound
+ * to the solid walls): its last point links to itself (next[e] = e) and no
+ * point links to its first; both ends must lie exactly on a wall plane
+ * (-1/2 or L - 1/2) of a closed axis and stay on it (they slide along the
+ * wall).  Every point has at most one predecessor besides itself.
+ * Positions on periodic axes are wrapped into [0, L) by one shift of L; a
+ * wall axis mirrors a point beyond the wall plane once.  VLB_EINVAL when
+ * that leaves a coordinate outside the box (more than one length L away),
+ * for a non-finite coordinate, an index out of range, a point with two
+ * predecessors, a one-point line or an end off the wall planes.            */
 int vlb_seed_vortices(vlb_run* run, int64_t n_pts, const double* xyz_host,
                       const int32_t* next_host);
 
@@ -327,9 +333,11 @@ int vlb_graph_destroy(vlb_graph* graph);
  *    precision VLB_F64 sums in FP64, VLB_F32 and VLB_F16 in FP32 (chunk
  *    partials added in FP64 in a fixed order: bitwise reproducible).
  *  - xyz_dev: device, n_pts x 3 doubles ([n][3], lattice units);
- *    next_dev: device, n_pts int32, a permutation whose cycles are the
- *    loops (not checked: an invalid one gives meaningless velocities, each
- *    entry is clamped into [0, n_pts) so no access leaves the arrays);
+ *    next_dev: device, n_pts int32, the successor of each point: closed
+ *    loops, or open lines whose last point links to itself (its zero
+ *    segment adds nothing; not checked: invalid links give meaningless
+ *    velocities, each entry is clamped into [0, n_pts) so no access leaves
+ *    the arrays);
  *    v_dev: device output, n_pts x 3 doubles.
  *  - dev_workspace: device scratch of at least vlb_biot_savart_workspace
  *    bytes, 256-byte aligned, owned by the caller; the call only enqueues

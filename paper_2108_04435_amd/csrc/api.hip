@@ -134,6 +134,7 @@ size_t layout(Run& r, char* base) {
   r.bsD = B.take((size_t)nco * (r.prec == VLB_F64 ? 6 : 4) * nc * fe);  // FP64: d (3) and residuals (3)
   size_t pbytes = (size_t)nco * r.bsS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
+  r.bsown = nco > 1 ? (int32_t*)B.take(nc * sizeof(int32_t)) : nullptr;
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
   r.marked = (uint32_t*)B.take(nc * sizeof(uint32_t));
   r.keys_a = (uint32_t*)B.take(nc * sizeof(uint32_t));
@@ -414,11 +415,18 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
   if (n_pts < 0 || n_pts > r.ncap) return fail(h, VLB_EINVAL, "n_pts must be in [0, n_cap]");
   if (n_pts > 0 && (!xyz || !next)) return fail(h, VLB_EINVAL, "xyz and next are required");
   const int n = (int)n_pts;
-  std::vector<int32_t> prv(n, -1);
+  // links: at most one predecessor besides itself per point; a point that
+  // links to itself is the last point of an open line, one that no other
+  // point links to is the first (it keeps itself as its predecessor)
+  std::vector<int32_t> prv(n);
+  std::vector<uint8_t> has_pred(n, 0);
+  for (int j = 0; j < n; ++j) prv[j] = j;
   for (int j = 0; j < n; ++j) {
     const int k = next[j];
     if (k < 0 || k >= n) return fail(h, VLB_EINVAL, "next[] out of range");
-    if (prv[k] != -1) return fail(h, VLB_EINVAL, "next[] is not a permutation");
+    if (k == j) continue;
+    if (has_pred[k]) return fail(h, VLB_EINVAL, "next[]: a point has two predecessors");
+    has_pred[k] = 1;
     prv[k] = j;
   }
   std::vector<double> soa(3 * (size_t)n);
@@ -434,8 +442,21 @@ int vlb_seed_vortices(vlb_run* h, int64_t n_pts, const double* xyz, const int32_
         return fail(h, VLB_EINVAL, "position more than one lattice length outside the box");
       soa[(size_t)a * n + j] = w;
     }
-  // loops shorter than min_loop_pts are accepted here and removed by the
-  // next topology pass
+  // the ends of open lines lie on a wall plane of a closed axis (the
+  // positions as wrapped, exactly)
+  for (int j = 0; j < n; ++j) {
+    const bool last = next[j] == j, first = !has_pred[j];
+    if (!last && !first) continue;
+    if (last && first) return fail(h, VLB_EINVAL, "next[]: a one-point line");
+    bool on = false;
+    for (int a = 0; a < 3; ++a) {
+      const double w = soa[(size_t)a * n + j];
+      if (r.geom.wall[a] && (w == -0.5 || w == (double)dims[a] - 0.5)) on = true;
+    }
+    if (!on) return fail(h, VLB_EINVAL, "an open line ends off the wall planes");
+  }
+  // loops and lines shorter than min_loop_pts are accepted here and removed
+  // by the next topology pass
   if (n > 0) {
     for (int a = 0; a < 3; ++a)
       HIP_OR_FAIL(h, hipMemcpyAsync(r.pos + a * r.ncap, soa.data() + (size_t)a * n, n * sizeof(double),

@@ -44,10 +44,17 @@ __device__ inline void wave_range(int cnt, int w, int& lo, int& hi) {
 // with the unwrapped grid value), so that y_s - y_t of the image the grid
 // difference chooses is (X_s - X_t) / q + rho_s - rho_t.  The FP32 sum
 // takes each segment vector as the wrapped grid difference to the successor.
+//
+// With image copies (own non-null), own[j] is the copy mirrored in the wall
+// that point j is bound to when j is an end of an open line (the lowest
+// closed axis whose wall plane it lies on; nothing else reflected), else 0:
+// in that copy the images of j's two segments meet j and are excluded, as
+// the real ones are in copy 0.
 template <class T>
 __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
-                       const int32_t* __restrict__ cnt, long long ncap, BsAxes ax,
-                       uint32_t* __restrict__ X, T* __restrict__ D) {
+                       const int32_t* __restrict__ prv, const int32_t* __restrict__ cnt,
+                       long long ncap, BsAxes ax, uint32_t* __restrict__ X, T* __restrict__ D,
+                       int32_t* __restrict__ own) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = cnt[0];
   if (j >= n) return;
@@ -63,6 +70,24 @@ __global__ void k_prep(const double* __restrict__ Y, const int32_t* __restrict__
       else if (d[a] < -0.5 * ax.L[a])
         d[a] = d[a] + ax.L[a];
     }
+  }
+  if (own) {
+    int oc = 0;
+    if (k == j || prv[j] == j) {
+      int ea = -1, es = 0;
+      for (int a = 2; a >= 0; --a)
+        if (!ax.periodic[a] && (y[a] == -0.5 || y[a] == ax.L[a] - 0.5)) {
+          ea = a;
+          es = y[a] == -0.5 ? 1 : 2;
+        }
+      if (ea >= 0)
+        for (int c = 1; c < ax.copies; ++c) {
+          bool only = true;
+          for (int a = 0; a < 3; ++a) only = only && ax.refl[c][a] == (a == ea ? es : 0);
+          if (only) oc = c;
+        }
+    }
+    own[j] = oc;
   }
   // copy 0: the point itself; copies 1..: its images in the wall planes
   for (int c = 0; c < ax.copies; ++c) {
@@ -134,7 +159,8 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
                                                const int32_t* __restrict__ prv,
                                                int32_t* __restrict__ cntp, long long ncap,
                                                int S, float iqx, float iqy, float iqz,
-                                               float* __restrict__ P, BsAxes bx) {
+                                               float* __restrict__ P, BsAxes bx,
+                                               const int32_t* __restrict__ own) {
   const int n = cntp[0];
   // work counter: (target, segment) pairs of this sum
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
@@ -153,8 +179,12 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
   const uint32_t xt = valid ? X[j] : 0u;
   const uint32_t yt = valid ? X[ncap + j] : 0u;
   const uint32_t zt = valid ? X[2 * ncap + j] : 0u;
-  const int pj = valid ? prv[j] : -1;
-  const int jj = valid ? j : -1;
+  // the target's own two segments are excluded in copy 0 and, for the end
+  // of an open line, in the copy mirrored in its wall
+  const int oc = (valid && own) ? own[j] : 0;
+  const bool exl = valid && (copy == 0 || copy == oc);
+  const int pj = exl ? prv[j] : -1;
+  const int jj = exl ? j : -1;
   __shared__ __align__(16) uint32_t sx[kTile], sy[kTile], sz[kTile];
   __shared__ __align__(16) float dx[kTile], dy[kTile], dz[kTile], dq[kTile];
   __shared__ float red[3][3][kTargets];  // sums of waves 1..3
@@ -186,7 +216,7 @@ __global__ __launch_bounds__(256) void k_bs_f32(const uint32_t* __restrict__ X,
     wave_range(min(kTile, ke - t0), w, lo, hi);
     if (lo < hi) {
       const int s0 = t0 + lo, s1 = t0 + hi;
-      const bool hit = valid && copy == 0 && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      const bool hit = exl && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
       if (__any(hit))
         bs_tile_f32<true, kUniform>(sx + lo, sy + lo, sz + lo, dx + lo, dy + lo, dz + lo, dq + lo,
                                     hi - lo, s0, xt, yt, zt, iqx, iqy, iqz, jj, pj, ax, ay, az);
@@ -274,7 +304,8 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
                                                const int32_t* __restrict__ prv,
                                                int32_t* __restrict__ cntp, long long ncap,
                                                int S, double gx, double gy, double gz,
-                                               double* __restrict__ P, BsAxes bx) {
+                                               double* __restrict__ P, BsAxes bx,
+                                               const int32_t* __restrict__ own) {
   const int n = cntp[0];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && n > 2)
     *(long long*)(cntp + 16) += (long long)n * (n - 2) + (long long)(bx.copies - 1) * n * n;
@@ -296,8 +327,10 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
   const double rtx = valid ? D[3 * ncap + j] : 0.0;
   const double rty = valid ? D[4 * ncap + j] : 0.0;
   const double rtz = valid ? D[5 * ncap + j] : 0.0;
-  const int pj = valid ? prv[j] : -1;
-  const int jj = valid ? j : -1;
+  const int oc = (valid && own) ? own[j] : 0;
+  const bool exl = valid && (copy == 0 || copy == oc);
+  const int pj = exl ? prv[j] : -1;
+  const int jj = exl ? j : -1;
   __shared__ __align__(16) uint32_t sx[kTile], sy[kTile], sz[kTile];
   __shared__ __align__(16) double rx[kTile], ry[kTile], rz[kTile];
   __shared__ __align__(16) double dx[kTile], dy[kTile], dz[kTile], dq[kTile];
@@ -323,7 +356,7 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
     wave_range(min(kTile, ke - t0), w, lo, hi);
     if (lo < hi) {
       const int s0 = t0 + lo, s1 = t0 + hi;
-      const bool hit = valid && copy == 0 && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
+      const bool hit = exl && ((jj >= s0 && jj < s1) || (pj >= s0 && pj < s1));
       if (__any(hit))
         bs_tile_f64<true>(sx + lo, sy + lo, sz + lo, rx + lo, ry + lo, rz + lo, dx + lo, dy + lo,
                           dz + lo, dq + lo, hi - lo, s0, xt, yt, zt, rtx, rty, rtz, gx, gy, gz, jj,
@@ -357,6 +390,12 @@ __global__ __launch_bounds__(256) void k_bs_f64(const uint32_t* __restrict__ X,
 // of bounds) and inverted into prev; grid coordinates and, for the FP64
 // sum, segment vectors and residuals as k_prep, from [n][3] positions.
 // Thread 0 writes the point count and clears the pair counter.
+// prv[j] = j: the first point of an open line keeps it (no real link to it)
+__global__ void k_solo_init(int32_t* __restrict__ prv, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) prv[j] = j;
+}
+
 template <class T>
 __global__ void k_solo_prep(const double* __restrict__ xyz, const int32_t* __restrict__ next,
                             int n, BsAxes ax, int32_t* __restrict__ cnt,
@@ -370,7 +409,7 @@ __global__ void k_solo_prep(const double* __restrict__ xyz, const int32_t* __res
   if (j >= n) return;
   const int k = min(max(next[j], 0), n - 1);
   nxt[j] = k;
-  prv[k] = j;
+  if (k != j) prv[k] = j;  // the last point of an open line links to itself
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double y = xyz[3LL * j + a];
@@ -494,12 +533,13 @@ int bs_chunks(long long ncap) {
 
 hipError_t bs_prep(Run& r, const double* Y) {
   const int nb = (int)((r.ncap + 255) / 256);
+  int32_t* own = r.bsax.copies > 1 ? r.bsown : nullptr;
   if (r.prec == VLB_F64)
-    hipLaunchKernelGGL(k_prep<double>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, r.bsX, (double*)r.bsD);
+    hipLaunchKernelGGL(k_prep<double>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.prv, r.cnt,
+                       r.ncap, r.bsax, r.bsX, (double*)r.bsD, own);
   else
-    hipLaunchKernelGGL(k_prep<float>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.cnt, r.ncap,
-                       r.bsax, r.bsX, (float*)r.bsD);
+    hipLaunchKernelGGL(k_prep<float>, dim3(nb), dim3(256), 0, r.stream, Y, r.nxt, r.prv, r.cnt,
+                       r.ncap, r.bsax, r.bsX, (float*)r.bsD, own);
   return hipGetLastError();
 }
 
@@ -508,18 +548,19 @@ hipError_t bs_sum(Run& r) {
   dim3 grid(tb, r.bsS * r.bsax.copies);
   hipEvent_t b = nullptr;
   time_begin(r, 0, &b);
+  const int32_t* own = r.bsax.copies > 1 ? r.bsown : nullptr;
   if (r.prec == VLB_F64)
     hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, r.stream, r.bsX, (const double*)r.bsD,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_d[0], r.bsax.invq_d[1],
-                       r.bsax.invq_d[2], (double*)r.bsP, r.bsax);
+                       r.bsax.invq_d[2], (double*)r.bsP, r.bsax, own);
   else if (r.bsax.uniform)
     hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
-                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax);
+                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax, own);
   else
     hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, r.stream, r.bsX, r.nxt,
                        r.prv, r.cnt, r.ncap, r.bsS, r.bsax.invq_f[0], r.bsax.invq_f[1],
-                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax);
+                       r.bsax.invq_f[2], (float*)r.bsP, r.bsax, own);
   time_end(r, 0, b);
   return hipGetLastError();
 }
@@ -574,11 +615,13 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
   const int tb = (int)((n + kTargets - 1) / kTargets);
   const dim3 grid(tb, b.S);
   const double s = kappa / (4.0 * M_PI);
+  hipLaunchKernelGGL(k_solo_init, dim3(nb), dim3(256), 0, stream, b.prv, (int)n);
   if (prec == VLB_F64) {
     hipLaunchKernelGGL(k_solo_prep<double>, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n,
                        ax, b.cnt, b.X, (double*)b.D, b.nxt, b.prv);
     hipLaunchKernelGGL(k_bs_f64, grid, dim3(256), 0, stream, b.X, (const double*)b.D, b.prv,
-                       b.cnt, n, b.S, ax.invq_d[0], ax.invq_d[1], ax.invq_d[2], (double*)b.P, ax);
+                       b.cnt, n, b.S, ax.invq_d[0], ax.invq_d[1], ax.invq_d[2], (double*)b.P, ax,
+                       nullptr);
     hipLaunchKernelGGL(k_solo_sum<double>, dim3(nb), dim3(256), 0, stream, (const double*)b.P,
                        b.S, (int)n, s, v);
   } else {
@@ -586,10 +629,12 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
                        ax, b.cnt, b.X, (float*)b.D, b.nxt, b.prv);
     if (ax.uniform)
       hipLaunchKernelGGL(k_bs_f32<true>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
-                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax);
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax,
+                         nullptr);
     else
       hipLaunchKernelGGL(k_bs_f32<false>, grid, dim3(256), 0, stream, b.X, b.nxt, b.prv, b.cnt,
-                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax);
+                         n, b.S, ax.invq_f[0], ax.invq_f[1], ax.invq_f[2], (float*)b.P, ax,
+                         nullptr);
     hipLaunchKernelGGL(k_solo_sum<float>, dim3(nb), dim3(256), 0, stream, (const float*)b.P,
                        b.S, (int)n, ax.uniform ? s * ax.q[0] : s, v);
   }

@@ -171,7 +171,8 @@ template <class UT, class PT>
 __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   __shared__ double red[kFinWaves - 1][3][kFinPts];  // chunk sums of waves 1..kFinWaves-1
   __shared__ double s_vn[3][kFinPts];    // wave 1: normal-fluid velocity
-  __shared__ double s_geo[8][kFinPts];   // wave 2: s' (3), LIA (3), l+, l-
+  __shared__ double s_geo[8][kFinPts];   // wave 2: s' (3), LIA (3), real l+, l-
+  __shared__ int s_end[kFinPts];         // wave 2: wall axis of an open line's end, or -1
   __shared__ double s_rk[9][kFinPts];    // wave 3: s^n (3), ksum (3), superflow, alpha, alpha'
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int j = blockIdx.x * kFinPts + lane;
@@ -218,12 +219,32 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   if (slot && grp == 2) {
     // local geometry (three-point derivatives on a non-uniform arc length)
     const int jn = min(max(A.nxt[j], 0), (int)nc - 1), jp = min(max(A.prv[j], 0), (int)nc - 1);
-    double dp[3], dm[3];
+    double dp[3], dm[3], pj[3];
     for (int a = 0; a < 3; ++a) {
       const double pa = A.Y[a * nc + j];
+      pj[a] = pa;
       dp[a] = mimg(A.Y[a * nc + jn] - pa, L[a], per[a]);
       dm[a] = mimg(pa - A.Y[a * nc + jp], L[a], per[a]);
     }
+    // the lengths of the segments that exist (the line length carried)
+    const double lp_real = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
+    const double lm_real = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
+    // An end of an open line lies on a wall plane (the lowest such closed
+    // axis); the line continues into its mirror image there, so the
+    // missing neighbour is the mirrored existing one: the missing segment
+    // vector is the existing one with its components along the wall negated.
+    int ea = -1;
+    if (jn == j || jp == j)
+      for (int a = 2; a >= 0; --a)
+        if (!per[a] && (pj[a] == -0.5 || pj[a] == L[a] - 0.5)) ea = a;
+    if (ea >= 0) {
+      if (jn == j) {
+        for (int a = 0; a < 3; ++a) dp[a] = a == ea ? dm[a] : -dm[a];
+      } else {
+        for (int a = 0; a < 3; ++a) dm[a] = a == ea ? dp[a] : -dp[a];
+      }
+    }
+    s_end[lane] = ea;
     const double lp = sqrt(dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2]);
     const double lm = sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
     const double iden = 1.0 / (lp * lm * (lp + lm));
@@ -241,8 +262,8 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
     s_geo[4][lane] = beta * (sp[2] * spp[0] - sp[0] * spp[2]);
     s_geo[5][lane] = beta * (sp[0] * spp[1] - sp[1] * spp[0]);
     for (int a = 0; a < 3; ++a) s_geo[a][lane] = sp[a];
-    s_geo[6][lane] = lp;
-    s_geo[7][lane] = lm;
+    s_geo[6][lane] = lp_real;
+    s_geo[7][lane] = lm_real;
   }
   if (slot && grp == 3) {
     if (!A.eval_only)
@@ -338,6 +359,9 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   const double al = s_rk[7][lane], alp = s_rk[8][lane];
   double sd[3];
   for (int a = 0; a < 3; ++a) sd[a] = vs[a] + al * sxw[a] - alp * ssw[a];
+  // an open line's end slides on its wall: no velocity normal to it
+  const int ea = s_end[lane];
+  if (ea >= 0) sd[ea] = 0.0;
   if (!(isfinite(sd[0]) && isfinite(sd[1]) && isfinite(sd[2])))
     atomicOr(&A.cnt[7], kFlagNumeric);
 
@@ -348,7 +372,7 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
       A.sd1[a * nc + j] = sd[a];
     }
     // reaction on the normal fluid (Magnus balance), per point, with the
-    // line length (l+ + l-)/2 carried by the point
+    // line length (l+ + l-)/2 carried by the point (the real segments)
     const double r[3] = {sd[0] - vs[0], sd[1] - vs[1], sd[2] - vs[2]};
     const double sxr[3] = {sp[1] * r[2] - sp[2] * r[1], sp[2] * r[0] - sp[0] * r[2],
                            sp[0] * r[1] - sp[1] * r[0]};

@@ -172,10 +172,10 @@ __global__ void k_reset_stats(int32_t* cnt) {
   if (threadIdx.x == 0) cnt[2] = cnt[3] = cnt[4] = cnt[5] = cnt[6] = 0;
 }
 
-// Deletion candidate (the test written out in k_rm_mark): the incoming
-// segment is shorter than dxi_min, and the chord from the predecessor to the
-// successor, which would replace the point's two segments, is not longer
-// than dxi_max.
+// Deletion candidate (the test written out in k_rm_mark): not an end of an
+// open line (those stay on their walls), the incoming segment is shorter
+// than dxi_min, and the chord from the predecessor to the successor, which
+// would replace the point's two segments, is not longer than dxi_max.
 
 // Along each run of consecutive deletion candidates every other point is
 // deleted: candidate j goes when the number c of candidates directly before
@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
   double d[3], c3[3];
   sep_v(yp, yj, tg, d);
   sep_v(yp, yq, tg, c3);
-  if (sq3(d) < mn2 && sq3(c3) <= mx2) {  // j is a deletion candidate
+  const bool end = p0 == j || q0 == j;  // the first or the last point of an open line
+  if (!end && sq3(d) < mn2 && sq3(c3) <= mx2) {  // j is a deletion candidate
     // walk back over the candidates before j: the candidacy of point p
     // needs the positions of its predecessor r, of p and of its successor
     // (the point walked from); r's predecessor is loaded together with r's
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_rm_mark(const double* __restrict__ p
     // (a valid loop brings the walk back to j within n steps; the bound
     // only guarantees termination on corrupted links)
     while (p != j && c < n) {
+      if (r == p) break;  // p is the first point of an open line: no candidate
       const int rr = clamp_index(prv[r], nc);
       double yr[3], e[3], f[3];
       load3(pos, nc, r, yr);
@@ -362,8 +364,9 @@ __device__ inline int bin_of(double x, const BinGeom& bg, int a) {
 }
 
 // Small-loop pass over the points below the bound: a point is alive when
-// it is kept (not deleted / alive before) and its loop has at least
-// min_pts points.  Optionally the alive points are pushed on per-bin lists
+// it is kept (not deleted / alive before) and its filament has at least
+// min_pts points (a closed loop, or an open line counted from its first to
+// its last point).  Optionally the alive points are pushed on per-bin lists
 // for the reconnection search (integer exchange on the bin head; the order
 // inside a list is irrelevant, every consumer sorts what it collects), or
 // the lists of an earlier pass are cleared, or the alive points are ranked
@@ -408,17 +411,30 @@ __global__ __launch_bounds__(kBlock) void k_small_pass(SmallArgs A) {
   const bool in = valid && dead0 == 0 && alive0 != 0;
   bool alive = false;
   if (in) {
-    // the loop is shorter than min_pts iff nxt^k(j) = j for some k <=
-    // min_pts - 1; walking i links forward (f) and back (b) together,
-    // f == prv^(i-1)(j) tests k = 2i - 1 and f == b tests k = 2i
+    // A loop is shorter than min_pts iff nxt^k(j) = j for some k <=
+    // min_pts - 1: walking i links forward (f) and back (b) together,
+    // f == prv^(i-1)(j) tests k = 2i - 1 and f == b tests k = 2i.  An open
+    // line is shorter iff fe + be + 1 <= min_pts - 1, with fe (be) the
+    // number of links from j to its last (first) point; a walk stops at the
+    // end it reaches.  The walk ends once every loop length up to
+    // min_pts - 1 has been tested and the line is known to be long enough.
     const int m1 = A.min_pts - 1;
-    int f = j, b = j;
+    int f = j, b = j, fe = -1, be = -1;
     bool small = false;
-    for (int i = 1; 2 * i - 1 <= m1 && !small; ++i) {
+    for (int i = 1; i <= m1 && !small; ++i) {
       const int bp = b;
-      f = i == 1 ? f1 : A.nxt[f];
-      b = i == 1 ? b1 : A.prv[b];
-      small = f == bp || (2 * i <= m1 && f == b);
+      const int fn = fe >= 0 ? f : (i == 1 ? f1 : A.nxt[f]);
+      const int bn = be >= 0 ? b : (i == 1 ? b1 : A.prv[b]);
+      if (fe < 0 && fn == f) fe = i - 1;  // f is the last point of an open line
+      if (be < 0 && bn == b) be = i - 1;  // b is the first point
+      f = fn;
+      b = bn;
+      if (fe >= 0 && be >= 0)
+        small = fe + be + 1 <= m1;
+      else if (fe < 0 && be < 0 && 2 * i - 1 <= m1)
+        small = f == bp || (2 * i <= m1 && f == b);
+      const int lf = fe >= 0 ? fe : i, lb = be >= 0 ? be : i;
+      if (2 * i >= m1 && lf + lb + 1 > m1) break;
     }
     alive = !small;
   }
@@ -557,7 +573,8 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
   const int ni0 = clamp_index(nxt[ic], nc), pi0 = clamp_index(prv[ic], nc);
   if (i >= cnt[9]) return;
   if (q == 0) used[i] = 0;
-  if (!alive0) return;
+  // the last point of an open line has no segment to exchange
+  if (!alive0 || ni0 == i) return;
   const int b[3] = {bin_of(yi[0], bg, 0), bin_of(yi[1], bg, 1), bin_of(yi[2], bg, 2)};
   int ox[3], oy[3], oz[3];
   const int mx = bin_offsets(bg, 0, b[0], ox);
@@ -579,6 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_find(const double* __restrict__ p
     const double d2 = sq3(d);
     if (!(d2 < d2max)) continue;
     const int nj = nxt[jc];
+    if (nj == jc) continue;  // the last point of an open line
     double ea[3], eb[3], ec[3], ee[3];
     sep(pos, nc, i, ni, tg, ea);
     sep(pos, nc, jc, nj, tg, eb);

@@ -522,6 +522,7 @@ struct Run {
   uint32_t* bsX = nullptr;  // 3 * ncap grid coordinates
   void* bsD = nullptr;      // 3 * ncap segment vectors (float or double)
   void* bsP = nullptr;      // S * 3 * ncap partial sums
+  int32_t* bsown = nullptr; // ncap, with image copies: the copy mirrored in an end's own wall
   int bsS = 1;
 
   // counters on the device: [0] n points, [1] n touched slots,

@@ -231,16 +231,18 @@ def config_heater(precision="f32", n_rings=1500, nxy=128, nz=512, seed=3):
 def config_closed_channel(precision="f64", nxy=48, nz=128, seed=6):
     """Closed channel with lines bound to its end walls (the paper's Sec. IV
     initial condition, synthetic stand-in): walls on z (the streaming axis),
-    x and y periodic; velocity planes z = 0 / z = nz-1 at v_n = 0.03 z; four
-    lines from wall to wall along z (two each way, feet on a square of side
-    nxy/2, helical displacement 0.5 with 3 turns) and two rings R = nxy/8
-    beside them; wall images, reconnection and mass balance on."""
+    x and y periodic; normal fluid at rest with N(0, 1e-4^2) noise (the
+    heater efflux through the end walls is not among the lattice's
+    boundaries); four lines from wall to wall along z (two each way, feet on
+    a square of side nxy/2, helical displacement 0.5 with 3 turns) and two
+    rings R = nxy/8 beside them; wall images and reconnection on (mass
+    balance off: with the fluid at rest it is zero)."""
     rng = np.random.default_rng(seed)
-    lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(False, False, True), plane_lo=True,
-                         plane_hi=True, plane_u=(0.0, 0.0, 0.03), precision=precision)
-    vor = vortex_preset(reconnect=True, mass_balance=True, wall_images=True)
-    rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.03), 1e-4)
-    n_pts = int(math.ceil(nz / 0.9)) + 1
+    lat = lattice_preset(nxy, nxy, nz, tau=0.8, walls=(False, False, True), precision=precision)
+    vor = vortex_preset(reconnect=True, wall_images=True)
+    rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.0), 1e-4)
+    # axial spacing <= 0.85: with the helix the segments stay below 0.95
+    n_pts = int(math.ceil(nz / 0.85)) + 1
     q = nxy / 4.0
     feet = ((q, q), (3 * q, q), (3 * q, 3 * q), (q, 3 * q))
     loops = [wall_line(f, 2, nz, n_pts, reverse=(i % 2 == 1), amp=0.5, turns=3.0,

@@ -56,9 +56,10 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X published FP64 vector peak
 PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
 LLC_BYTES = 256 << 20             # MI355X last-level (Infinity) cache
 
-WORKLOADS = ("tangle", "counterflow", "ring32", "heater", "serve")
-DEFAULT_PRECISION = {"tangle": "f16", "counterflow": "f32", "ring32": "f64", "heater": "f32"}
-DEFAULT_GRAPH = {"tangle": 0, "heater": 0, "counterflow": 10, "ring32": 10}
+WORKLOADS = ("tangle", "counterflow", "ring32", "heater", "closed_channel", "serve")
+DEFAULT_PRECISION = {"tangle": "f16", "counterflow": "f32", "ring32": "f64", "heater": "f32",
+                     "closed_channel": "f64"}
+DEFAULT_GRAPH = {"tangle": 0, "heater": 0, "counterflow": 10, "ring32": 10, "closed_channel": 10}
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
@@ -74,6 +75,8 @@ def make_workload(name, precision=None):
         return wl.config_heater(precision=p)
     if name == "tangle":
         return wl.config_tangle(precision=p)
+    if name == "closed_channel":
+        return wl.config_closed_channel(precision=p)
     raise SystemExit(f"unknown workload {name}")
 
 

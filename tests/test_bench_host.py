@@ -104,3 +104,22 @@ def test_cpu_baseline_sample_with_wall_images():
     assert t.size > 0
     for k in ("vs", "vn", "sdot", "force"):
         np.testing.assert_allclose(ref[k], full[k][t], rtol=0, atol=1e-14)
+
+
+def test_cpu_baseline_sample_with_wall_bound_lines():
+    """The oracle leg on the closed channel (open lines bound to the end
+    walls, wall images on): the sampled first-stage values equal the
+    oracle's full-state computation."""
+    from oracle import lbm, vfm
+    import tests._cases as cases
+
+    cfg = wl.config_closed_channel(nxy=16, nz=24)
+    base, ref = bench.cpu_baseline(cfg, workers=1, per_worker=40, single=4)
+    lat, vp, st = cases.oracle_state(cfg)
+    assert vp.wall_images and not vp.mass_balance
+    _, ub = lbm.bare_velocity(st.f, lat)
+    full = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, None, lat, vp, want_force=True)
+    t = ref["targets"]
+    assert t.size > 0 and base["value"] > 0
+    for k in ("vs", "vn", "sdot", "force"):
+        np.testing.assert_allclose(ref[k], full[k][t], rtol=0, atol=1e-14)

@@ -455,8 +455,9 @@ def _raise(lib, code):
 
 def biot_savart(xyz, nxt, dims, walls=(False, False, False), kappa=0.1, precision="f64",
                 device=0):
-    """Non-local Biot-Savart velocity of closed filaments (vlb_biot_savart):
-    ``xyz`` (n, 3) positions, ``nxt`` (n,) successor links; returns (n, 3)
+    """Non-local Biot-Savart velocity of filaments (vlb_biot_savart): closed
+    loops, or open lines whose last point links to itself; ``xyz`` (n, 3)
+    positions, ``nxt`` (n,) successor links; returns (n, 3)
     velocities as a host array.  Device buffers and the workspace are torch
     tensors; the work runs on torch's current stream."""
     import torch

@@ -175,3 +175,102 @@ def test_ring_reconnects_with_a_wall_line_f64():
     assert (nxt_g == ks).sum() == 1
     topology.check_lines(pos_g, nxt_g, lat)
     run.close()
+
+
+def _state(run):
+    buf, step = run.read_state()
+    pos, nxt = run.read_filaments()
+    return buf.cpu().numpy(), pos, nxt, step
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
+def test_wall_lines_checkpoint_resume_bitwise(precision):
+    """Checkpoint at an odd step (swapped AA layout) of a closed channel and
+    resume in a new run: bitwise equal to the uninterrupted run."""
+    cfg = _case(precision)
+    say("wall lines checkpoint", precision)
+    a = vlb.run_from_config(cfg)
+    a.step(5)
+    a.sync()
+    buf, step = a.read_state()
+    pos, nxt = a.read_filaments()
+    b = vlb.Run(cfg["lattice"], cfg["vortex"], a.n_cap)
+    b.write_state(buf, step)
+    b.seed(pos, nxt)
+    a.step(6)
+    b.step(6)
+    a.sync()
+    b.sync()
+    sa, sb = _state(a), _state(b)
+    for x, y in zip(sa[:3], sb[:3]):
+        np.testing.assert_array_equal(x, y)
+    assert sa[3] == sb[3]
+    a.close()
+    b.close()
+
+
+def test_wall_lines_graph_replay_matches_direct_steps():
+    """Steps of a closed channel replayed from a captured HIP graph are
+    bitwise equal to steps enqueued one by one (several replays)."""
+    cfg = _case("f32")
+    say("wall lines graph replay")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        direct = vlb.run_from_config(cfg)
+    with torch.cuda.stream(s2):
+        graphed = vlb.run_from_config(cfg)
+        for _ in range(3):
+            direct.step(4)
+            graphed.step_graph(4)
+            direct.sync()
+            graphed.sync()
+            pa, na = direct.read_filaments()
+            pb, nb = graphed.read_filaments()
+            np.testing.assert_array_equal(na, nb)
+            np.testing.assert_array_equal(pa, pb)
+            np.testing.assert_array_equal(direct.read_populations(), graphed.read_populations())
+    direct.close()
+    graphed.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_wall_lines_coupled_reduced_precision(precision):
+    """Step by step against the FP64 oracle: the links equal the oracle's
+    after every step, positions agree to the precision form's tolerance."""
+    cfg = _case(precision)
+    say("wall lines coupled", precision)
+    run = vlb.run_from_config(cfg)
+    lat, vp, st = oracle_state(cfg)
+    for k in range(8):
+        run.step(1)
+        run.sync()
+        st = coupled.coupled_step(st, lat, vp)
+        pos_g, nxt_g = run.read_filaments()
+        assert nxt_g.shape == st.nxt.shape and (nxt_g == st.nxt).all(), k
+        d = np.abs(vfm.min_image(pos_g - st.pos, lat)).max()
+        assert d < (1e-4 if precision == "f32" else 1e-2), (k, d)
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) <= TOL[precision]
+    run.close()
+
+
+def test_wall_lines_step_many_equals_single_runs():
+    """Closed channels of three seeds advanced by one vlb_step_many call are
+    bitwise equal to the same runs stepped one by one."""
+    cfgs = [_case("f32", seed=s) for s in (6, 7, 8)]
+    together = [vlb.run_from_config(c) for c in cfgs]
+    alone = [vlb.run_from_config(c) for c in cfgs]
+    vlb.step_many(together, 5)
+    for r in alone:
+        r.step(5)
+    for a, b in zip(together, alone):
+        a.sync()
+        b.sync()
+        pa, na = a.read_filaments()
+        pb, nb = b.read_filaments()
+        np.testing.assert_array_equal(na, nb)
+        np.testing.assert_array_equal(pa, pb)
+        np.testing.assert_array_equal(a.read_populations(), b.read_populations())
+    for r in together + alone:
+        r.close()

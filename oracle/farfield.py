@@ -1,9 +1,9 @@
 """Cell-multipole approximation of the non-local Biot-Savart sum, plain
 FP64 (an extension for large tangles: Sec. II.A computes the full
 non-local integral, which grows as N^2 while the tangles of Sec. III.C
-grow; reading F2).  Test infrastructure: this module is the oracle of the
-library's far-field mode and is used by tests and the benchmark's oracle
-leg only.
+grow; reading F2).  Test infrastructure only (see the package docstring):
+the reference of the far-field analysis, which has no GPU counterpart in
+the library (the direct sum is kept; the analysis is in the pins).
 
 The box is cut into a uniform grid of cells of edge h_a = L_a / nc_a.  Each
 segment k (start s_k, vector d_k at the nearest image, circulation kappa)

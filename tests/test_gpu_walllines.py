@@ -274,3 +274,25 @@ def test_wall_lines_step_many_equals_single_runs():
         np.testing.assert_array_equal(a.read_populations(), b.read_populations())
     for r in together + alone:
         r.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_wall_lines_eval_full_size(precision):
+    """The closed-channel workload at its full size (48 x 48 x 128, 692
+    points, the bench's configuration): first-stage line velocity, force and
+    spread force against the oracle."""
+    cfg = wl.config_closed_channel(precision=precision)
+    say("wall lines full size", precision, cfg["pos"].shape[0])
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    lat, vp, st = oracle_state(cfg)
+    _, ub = lbm.bare_velocity(st.f, lat)
+    ref = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, None, lat, vp, want_force=True)
+    F_o = vfm.spread(ref["force"], st.pos, lat)
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(k, err)
+        assert err <= TOL[precision], (k, err)
+    assert rel_l2(F_g, F_o) <= TOL[precision]
+    run.close()

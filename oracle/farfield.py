@@ -2,38 +2,52 @@
 FP64 (an extension for large tangles: Sec. II.A computes the full
 non-local integral, which grows as N^2 while the tangles of Sec. III.C
 grow; reading F2).  Test infrastructure only (see the package docstring):
-the reference of the far-field analysis, which has no GPU counterpart in
-the library (the direct sum is kept; the analysis is in the pins).
+the reference that the library's far-field sum is checked against.
 
-The box is cut into a uniform grid of cells of edge h_a = L_a / nc_a.  Each
-segment k (start s_k, vector d_k at the nearest image, circulation kappa)
-belongs to the cell of its midpoint m_k.  About the cell centre c the
-segment's vorticity kappa d_k is spread along y = m_k - c + t d_k,
-t in [-1/2, 1/2]; its moments are
+Positions are first reduced into [0, L) on every axis (the box is periodic
+on all three axes).  The box is cut into a uniform grid of cells of edge
+h (h divides every L_a).  Each segment k (start s_k, vector d_k at the
+nearest image, circulation kappa) belongs to the cell of its midpoint m_k
+(reduced into [0, L)).  About the cell centre c, with y_k = m_k - c at the
+nearest image, the segment's vorticity kappa d_k is spread along
+y_k + t d_k, t in [-1/2, 1/2]; the cell's moments are
     M0 = sum kappa d,  M1 = sum kappa d (x) y,
-    M2 = sum kappa d (x) (y (x) y + d (x) d / 12).
+    M2 = sum kappa d (x) (y (x) y + d (x) d / 12),
+and its radius rad = max_k (|y_k| + |d_k| / 2).
 The field of a vortex element a at offset y seen from r, a x (r - y) /
 |r - y|^3 / (4 pi), expanded about the centre to second order in y, gives
-the cell's velocity at R = r - c (nearest image of the centre)
+the velocity at R = r - c
     v_m = eps_mnp g_np / (4 pi),
     g_np = M0_n R_p / r^3 - M1_np / r^3 + 3 (M1 R)_n R_p / r^5
          + (15 (R M2_n R) R_p / r^7 - 3 tr(M2_n) R_p / r^5 - 6 (M2_n R)_p / r^5) / 2.
-A cell is far from target r when |R| theta >= rad (rad: the largest
-|y| + |d|/2 of its segments) and, on every periodic axis a,
-|R_a| + ext_a < L_a / 2 (ext_a: the largest |s_k,a - c_a| of its segment
-starts), so that every segment start of the cell takes the nearest image
-of the centre (reading R12 decides images per segment start).  Far cells
-contribute their expansion; every other cell contributes the exact
-straight-segment integrals of its segments (nearest image per segment
-start, the target's own two segments excluded, as in
-vfm.biot_savart_nonlocal).  Decisions are made in FP64 with the sums
-written left to right.
+
+Periodic images (reading R12 decides the image of each segment by its
+start, per target).  For target r, segment k of cell c sits at the image
+whose start is s_k - r + n_k L (the nearest image on the 32-bit grid, as
+in the direct sum); that image places the cell centre at
+    C_k = (s_k - r + n_k L) + d_k / 2 - y_k = (c - r) + K_k L,
+with an integer vector K_k, the segment's image class.  The segments of a
+cell take one class unless the plane half a box from the target crosses
+their starts.  Per target and cell:
+  * one class K: the cell is far when |R|^2 theta^2 >= rad^2 with
+    R = (c - r) + K L, and contributes its expansion at that image;
+  * two classes differing on one axis (the plane crosses the starts on
+    that axis only): when both images pass the same test the cell is
+    split, each class contributing the expansion of its own segments'
+    moments at its image;
+  * otherwise (an image too close, or starts crossed on two or more axes)
+    the cell's segments are summed directly with the exact straight-
+    segment integral at their own images, the target's own two segments
+    excluded, as in vfm.biot_savart_nonlocal.
+theta < 1 keeps the target's own segments in direct cells (a segment that
+touches r lies within rad of its cell centre).  Decisions are made in FP64
+with the sums written left to right.
 """
 
 import numpy as np
 
 from .lbm import Lattice
-from .vfm import bs_image_offsets, min_image, segment_velocity
+from .vfm import bs_image_offsets, min_image, segment_velocity, wrap_positions
 
 
 def cell_grid(lat: Lattice, h):
@@ -47,10 +61,11 @@ def cell_grid(lat: Lattice, h):
 
 
 def cell_moments(pos, nxt, lat: Lattice, h, kappa):
-    """Segment cells and the per-cell moments (see the module docstring).
-    Returns a dict: key (N,), order (segments sorted by cell, stable),
-    starts / ends (per cell), centre (C, 3), M0 (C, 3), M1 (C, 3, 3),
-    M2 (C, 3, 3, 3), rad (C,), ext (C, 3)."""
+    """Segment cells and the per-cell moments (module docstring), for
+    positions already in [0, L).  Returns a dict: key (N,) cell of each
+    segment, order (segments sorted by cell, stable), starts / ends (per
+    cell, into order), centre (C, 3), y (N, 3), d (N, 3), M0 (C, 3),
+    M1 (C, 3, 3), M2 (C, 3, 3, 3), rad (C,)."""
     nc, hh = cell_grid(lat, h)
     L = np.array(lat.dims, dtype=np.float64)
     d = min_image(pos[nxt] - pos, lat)
@@ -63,6 +78,20 @@ def cell_moments(pos, nxt, lat: Lattice, h, kappa):
     ci = np.stack([cid % nc[0], (cid // nc[0]) % nc[1], cid // (nc[0] * nc[1])], 1)
     centre = (ci + 0.5) * hh
     y = min_image(mid - centre[key], lat)
+    M0, M1, M2 = _moments(key, y, d, kappa, C)
+    ny = np.sqrt(y[:, 0] * y[:, 0] + y[:, 1] * y[:, 1] + y[:, 2] * y[:, 2])
+    nd = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
+    rad = np.zeros(C)
+    np.maximum.at(rad, key, ny + 0.5 * nd)
+    order = np.argsort(key, kind="stable")
+    starts = np.searchsorted(key[order], cid)
+    ends = np.searchsorted(key[order], cid, side="right")
+    return dict(key=key, order=order, starts=starts, ends=ends, centre=centre, y=y, d=d, M0=M0,
+                M1=M1, M2=M2, rad=rad)
+
+
+def _moments(key, y, d, kappa, C):
+    """M0, M1, M2 of the segments (key, y, d) added into C cells."""
     a = kappa * d
     M0 = np.zeros((C, 3))
     M1 = np.zeros((C, 3, 3))
@@ -71,17 +100,7 @@ def cell_moments(pos, nxt, lat: Lattice, h, kappa):
     np.add.at(M1, key, a[:, :, None] * y[:, None, :])
     yy = y[:, :, None] * y[:, None, :] + d[:, :, None] * d[:, None, :] / 12.0
     np.add.at(M2, key, a[:, :, None, None] * yy[:, None, :, :])
-    ny = np.sqrt(y[:, 0] * y[:, 0] + y[:, 1] * y[:, 1] + y[:, 2] * y[:, 2])
-    nd = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
-    rad = np.zeros(C)
-    np.maximum.at(rad, key, ny + 0.5 * nd)
-    ext = np.zeros((C, 3))
-    np.maximum.at(ext, key, np.abs(min_image(pos - centre[key], lat)))
-    order = np.argsort(key, kind="stable")
-    starts = np.searchsorted(key[order], cid)
-    ends = np.searchsorted(key[order], cid, side="right")
-    return dict(key=key, order=order, starts=starts, ends=ends, centre=centre, M0=M0, M1=M1,
-                M2=M2, rad=rad, ext=ext, d=d)
+    return M0, M1, M2
 
 
 def m2p(R, M0, M1, M2):
@@ -106,39 +125,87 @@ def m2p(R, M0, M1, M2):
     return v.sum(axis=0)
 
 
-def far_mask(r, cm, lat: Lattice, theta):
-    """Which cells are far from target r (module docstring): (C,) bool.
-    Empty cells are never far (they add nothing either way)."""
-    R = min_image(r[None, :] - cm["centre"], lat)
-    d2 = R[:, 0] * R[:, 0] + R[:, 1] * R[:, 1] + R[:, 2] * R[:, 2]
-    far = (d2 * (theta * theta) >= cm["rad"] * cm["rad"]) & (cm["ends"] > cm["starts"])
-    for a, n in enumerate(lat.dims):
-        if lat.walls[a]:
-            continue
-        far &= np.abs(R[:, a]) + cm["ext"][:, a] < 0.5 * float(n)
-    return far, R
+EMPTY, FAR, SPLIT, NEAR = 0, 1, 2, 3
+
+
+def classify(r, pos, cm, lat: Lattice, theta):
+    """Per-cell decisions for target r (module docstring).  Returns a dict:
+    kind (C,) in EMPTY / FAR / SPLIT / NEAR, K (N, 3) image class of every
+    segment, Kmin / Kmax (C, 3) the classes' extremes per axis, axis (C,)
+    the crossed axis of a split cell, Rlo / Rhi (C, 3) the centre's images
+    (c - r) + K L for Kmin and Kmax (source minus target)."""
+    L = np.array(lat.dims, dtype=np.float64)
+    key = cm["key"]
+    C = cm["centre"].shape[0]
+    base = cm["centre"] - r[None, :]
+    R1 = bs_image_offsets(pos, r[None, :], lat)
+    Cimg = R1 + 0.5 * cm["d"] - cm["y"]
+    K = np.rint((Cimg - base[key]) / L).astype(np.int64)
+    big = np.iinfo(np.int64).max
+    Kmin = np.full((C, 3), big)
+    Kmax = np.full((C, 3), -big)
+    np.minimum.at(Kmin, key, K)
+    np.maximum.at(Kmax, key, K)
+    ne = cm["ends"] > cm["starts"]
+    Kmin[~ne] = 0
+    Kmax[~ne] = 0
+    crossed = Kmax > Kmin
+    ncross = crossed.sum(axis=1)
+    Rlo = base + Kmin * L
+    Rhi = base + Kmax * L
+    th2 = theta * theta
+    rad2 = cm["rad"] * cm["rad"]
+    ok_lo = (Rlo[:, 0] * Rlo[:, 0] + Rlo[:, 1] * Rlo[:, 1] + Rlo[:, 2] * Rlo[:, 2]) * th2 >= rad2
+    ok_hi = (Rhi[:, 0] * Rhi[:, 0] + Rhi[:, 1] * Rhi[:, 1] + Rhi[:, 2] * Rhi[:, 2]) * th2 >= rad2
+    kind = np.full(C, NEAR, dtype=np.int64)
+    kind[ne & (ncross == 0) & ok_lo] = FAR
+    kind[ne & (ncross == 1) & ok_lo & ok_hi] = SPLIT
+    kind[~ne] = EMPTY
+    return dict(kind=kind, K=K, Kmin=Kmin, Kmax=Kmax, axis=np.argmax(crossed, axis=1), Rlo=Rlo,
+                Rhi=Rhi)
 
 
 def biot_savart_farfield(pos, nxt, prv, lat: Lattice, kappa, h, theta, targets=None):
     """Non-local superfluid velocity at ``targets`` (default: all) by the
-    cell-multipole approximation (module docstring).  Returns (T, 3) and the
-    mean numbers of far cells and direct pairs per target."""
+    cell-multipole approximation (module docstring).  Returns (T, 3) and a
+    dict of the mean numbers of far cells, split cells and direct pairs per
+    target."""
     if any(lat.walls):
         raise ValueError("the far-field sum is defined for periodic boxes")
+    if not 0.0 < theta < 1.0:
+        raise ValueError("theta must lie in (0, 1)")
+    pos = wrap_positions(pos, lat)
     N = pos.shape[0]
     if targets is None:
         targets = np.arange(N)
     cm = cell_moments(pos, nxt, lat, h, kappa)
-    d = cm["d"]
+    key, d, y = cm["key"], cm["d"], cm["y"]
+    C = cm["centre"].shape[0]
     out = np.zeros((len(targets), 3))
-    n_far = 0
-    n_dir = 0
+    n_far = n_split = n_dir = 0
     for t, j in enumerate(targets):
         r = pos[j]
-        far, R = far_mask(r, cm, lat, theta)
-        v = m2p(R[far], cm["M0"][far], cm["M1"][far], cm["M2"][far]) / (4.0 * np.pi) \
-            if far.any() else np.zeros(3)
-        near = np.nonzero(~far & (cm["ends"] > cm["starts"]))[0]
+        cl = classify(r, pos, cm, lat, theta)
+        kind = cl["kind"]
+        v = np.zeros(3)
+        far = kind == FAR
+        if far.any():
+            v += m2p(-cl["Rlo"][far], cm["M0"][far], cm["M1"][far], cm["M2"][far])
+        split = kind == SPLIT
+        if split.any():
+            # lower class: the segments of split cells whose class on the
+            # crossed axis is the smaller one; the others form the upper
+            ks = np.nonzero(split[key])[0]
+            kc = key[ks]
+            ax = cl["axis"][kc]
+            lower = cl["K"][ks, ax] == cl["Kmin"][kc, ax]
+            lo, hi = ks[lower], ks[~lower]
+            M0l, M1l, M2l = _moments(key[lo], y[lo], d[lo], kappa, C)
+            M0h, M1h, M2h = _moments(key[hi], y[hi], d[hi], kappa, C)
+            v += m2p(-cl["Rlo"][split], M0l[split], M1l[split], M2l[split])
+            v += m2p(-cl["Rhi"][split], M0h[split], M1h[split], M2h[split])
+        v = v / (4.0 * np.pi)
+        near = np.nonzero(kind == NEAR)[0]
         if near.size:
             ks = np.concatenate([cm["order"][cm["starts"][c]:cm["ends"][c]] for c in near])
             ks = ks[(ks != j) & (ks != prv[j])]
@@ -146,5 +213,7 @@ def biot_savart_farfield(pos, nxt, prv, lat: Lattice, kappa, h, theta, targets=N
             v = v + segment_velocity(R1, R1 + d[ks], kappa).sum(axis=0)
             n_dir += ks.size
         n_far += int(far.sum())
+        n_split += int(split.sum())
         out[t] = v
-    return out, n_far / max(len(targets), 1), n_dir / max(len(targets), 1)
+    T = max(len(targets), 1)
+    return out, dict(far=n_far / T, split=n_split / T, direct=n_dir / T)

@@ -37,7 +37,8 @@ SYMBOLS = [
     "vlb_flow_stats", "vlb_read_vorticity", "vlb_vorticity_cylindrical", "vlb_get_step",
     "vlb_set_timing", "vlb_get_timing", "vlb_time_kernel", "vlb_get_work", "vlb_graph_create",
     "vlb_graph_launch", "vlb_graph_destroy", "vlb_biot_savart_workspace", "vlb_biot_savart",
-    "vlb_biot_savart_noalloc", "vlb_destroy", "vlb_last_error",
+    "vlb_biot_savart_noalloc", "vlb_biot_savart_farfield_workspace", "vlb_biot_savart_farfield",
+    "vlb_destroy", "vlb_last_error",
 ]
 
 
@@ -76,6 +77,11 @@ class BsDesc(ctypes.Structure):
         ("wall_axes", ctypes.c_uint32), ("precision", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("kappa", ctypes.c_double),
     ]
+
+
+class FfParams(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("theta", ctypes.c_double)]
 
 
 class VlbError(RuntimeError):
@@ -136,6 +142,10 @@ def load_library(path=None):
     lib.vlb_biot_savart.argtypes = [ctypes.POINTER(BsDesc), i64, vp, vp, vp, vp,
                                     ctypes.c_uint64, vp]
     lib.vlb_biot_savart_noalloc.argtypes = [ctypes.POINTER(BsDesc), i64, vp, vp, vp, vp]
+    lib.vlb_biot_savart_farfield_workspace.argtypes = [
+        ctypes.POINTER(BsDesc), ctypes.POINTER(FfParams), i64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.vlb_biot_savart_farfield.argtypes = [ctypes.POINTER(BsDesc), ctypes.POINTER(FfParams),
+                                             i64, vp, vp, vp, vp, ctypes.c_uint64, vp]
     lib.vlb_destroy.argtypes = [vp]
     lib.vlb_last_error.argtypes = [vp]
     lib.vlb_last_error.restype = ctypes.c_char_p
@@ -481,6 +491,61 @@ def biot_savart(xyz, nxt, dims, walls=(False, False, False), kappa=0.1, precisio
     out = v.cpu().numpy()   # synchronises the stream
     del ws
     return out
+
+
+class FarField:
+    """Far-field approximation of the stand-alone Biot-Savart sum
+    (vlb_biot_savart_farfield) for n points in a periodic box ``dims``:
+    cells of edge ``cell``, opening parameter ``theta``; FP32.  The
+    workspace is allocated once; ``run`` enqueues one sum on torch's current
+    stream from device tensors (positions (n, 3) float64, links (n,) int32)
+    into ``v`` ((n, 3) float64)."""
+
+    def __init__(self, dims, n, cell, theta, kappa=0.1, device=0):
+        import torch
+
+        self.lib = load_library()
+        self.dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.desc = bs_desc(dims, (False, False, False), kappa, "f32")
+        self.par = FfParams(int(cell), 0, float(theta))
+        self.n = int(n)
+        nb = ctypes.c_uint64(0)
+        _raise(self.lib, self.lib.vlb_biot_savart_farfield_workspace(
+            ctypes.byref(self.desc), ctypes.byref(self.par), self.n, ctypes.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.dev)
+        self._wp = (self._ws.data_ptr() + 255) // 256 * 256
+
+    def run(self, p, q, v):
+        import torch
+
+        for t, shape, dt in ((p, (self.n, 3), torch.float64), (q, (self.n,), torch.int32),
+                             (v, (self.n, 3), torch.float64)):
+            if tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous() \
+                    or t.device != self.dev:
+                raise ValueError(f"expected a contiguous {dt} tensor of shape {shape} on {self.dev}")
+        stream = torch.cuda.current_stream(self.dev)
+        _raise(self.lib, self.lib.vlb_biot_savart_farfield(
+            ctypes.byref(self.desc), ctypes.byref(self.par), self.n, ctypes.c_void_p(p.data_ptr()),
+            ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(self._wp),
+            ctypes.c_uint64(self.ws_bytes), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def biot_savart_farfield(xyz, nxt, dims, cell, theta, kappa=0.1, device=0):
+    """Far-field approximation of the non-local velocity (FarField) of
+    filaments ``xyz`` (n, 3), ``nxt`` (n,) in a periodic box; returns (n, 3)
+    velocities as a host array."""
+    import torch
+
+    n = int(np.asarray(nxt).size)
+    ff = FarField(dims, max(n, 1), cell, theta, kappa, device)
+    if n == 0:
+        return np.zeros((0, 3))
+    p = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)).to(ff.dev)
+    q = torch.as_tensor(np.ascontiguousarray(nxt, dtype=np.int32).reshape(-1)).to(ff.dev)
+    v = torch.empty((n, 3), dtype=torch.float64, device=ff.dev)
+    ff.run(p, q, v)
+    return v.cpu().numpy()   # synchronises the stream
 
 
 def run_from_config(cfg: dict, n_cap=None, device=0, recon_cap=1 << 16):

@@ -1032,6 +1032,34 @@ int vlb_biot_savart(const vlb_bs_desc* d, int64_t n_pts, const double* xyz_dev,
   return VLB_OK;
 }
 
+int vlb_biot_savart_farfield_workspace(const vlb_bs_desc* d, const vlb_ff_params* p,
+                                       int64_t n_pts, uint64_t* bytes) {
+  std::string msg;
+  const int c = ff_check(d, p, n_pts, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (!bytes) return fail(nullptr, VLB_EINVAL, "bytes is NULL");
+  *bytes = n_pts > 0 ? (uint64_t)ff_workspace(d, p, n_pts) : 0;
+  return VLB_OK;
+}
+
+int vlb_biot_savart_farfield(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n_pts,
+                             const double* xyz_dev, const int32_t* next_dev, double* v_dev,
+                             void* dev_workspace, uint64_t ws_bytes, void* hip_stream) {
+  std::string msg;
+  const int c = ff_check(d, p, n_pts, msg);
+  if (c != VLB_OK) return fail(nullptr, c, msg);
+  if (n_pts == 0) return VLB_OK;
+  if (!xyz_dev || !next_dev || !v_dev || !dev_workspace)
+    return fail(nullptr, VLB_EINVAL, "null device pointer");
+  if ((uintptr_t)dev_workspace % 256) return fail(nullptr, VLB_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < ff_workspace(d, p, n_pts))
+    return fail(nullptr, VLB_ENOSPACE, "workspace smaller than vlb_biot_savart_farfield_workspace");
+  const hipError_t e = ff_solo(d, p, n_pts, xyz_dev, next_dev, v_dev, dev_workspace,
+                               (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "vlb_biot_savart_farfield");
+  return VLB_OK;
+}
+
 const char* vlb_last_error(const vlb_run* h) {
   if (h) return h->r.err.c_str();
   std::lock_guard<std::mutex> lk(g_err_mu);

@@ -144,29 +144,32 @@ void sort_first_digit(int bits, int* dbits) {
 
 int32_t* sort_counts(Run& r) { return (int32_t*)r.sort_tmp; }
 
-// Sort ncap pairs (keys_a, vals_a) by the low `bits` bits of the key.
-// first_counted: the tile counts of the first pass are already in the
-// count table.  Result pointers are returned (they alternate between the a
-// and b buffers with the number of passes).
-hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int32_t** vres) {
-  const int n = (int)r.ncap;
+// Sort n pairs (ka, va) by the low `bits` bits of the key, with tmp of
+// sort_tmp_bytes(n) bytes and the second buffers kb, vb.  first_counted: the
+// tile counts of the first pass are already in the count table at tmp.
+// Result pointers are returned (they alternate between the a and b buffers
+// with the number of passes).
+hipError_t sort_pairs_raw(long long nn, int bits, int first_counted, void* tmp, uint32_t* ka,
+                          uint32_t* kb, int32_t* va, int32_t* vb, hipStream_t stream,
+                          uint32_t** kres, int32_t** vres) {
+  const int n = (int)nn;
   const int ntiles = sort_tiles(n);
-  int32_t* counts = (int32_t*)r.sort_tmp;
+  int32_t* counts = (int32_t*)tmp;
   int32_t* offs = counts + (((long long)kSortMaxBins * ntiles + 63) & ~63LL);
-  uint32_t* kin = r.keys_a;
-  uint32_t* kout = r.keys_b;
-  int32_t* vin = r.vals_a;
-  int32_t* vout = r.vals_b;
+  uint32_t* kin = ka;
+  uint32_t* kout = kb;
+  int32_t* vin = va;
+  int32_t* vout = vb;
   const int passes = (bits + kSortMaxBits - 1) / kSortMaxBits;
   const int dbits = (bits + passes - 1) / passes;
   for (int p = 0; p < passes; ++p) {
     const int shift = dbits * p;
     const int pb = (shift + dbits <= bits) ? dbits : bits - shift;
     if (p > 0 || !first_counted)
-      hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kSortThreads), 0, r.stream, kin, n, shift,
+      hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(kSortThreads), 0, stream, kin, n, shift,
                          pb, ntiles, counts);
-    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, r.stream, counts, ntiles << pb, offs);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, r.stream, kin, vin,
+    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(1024), 0, stream, counts, ntiles << pb, offs);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kSortThreads), 0, stream, kin, vin,
                        kout, vout, n, shift, pb, ntiles, offs);
     uint32_t* tk = kin;
     kin = kout;
@@ -178,6 +181,12 @@ hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int3
   *kres = kin;
   *vres = vin;
   return hipGetLastError();
+}
+
+// The run's ncap pairs (keys_a, vals_a).
+hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int32_t** vres) {
+  return sort_pairs_raw(r.ncap, bits, first_counted, r.sort_tmp, r.keys_a, r.keys_b, r.vals_a,
+                        r.vals_b, r.stream, kres, vres);
 }
 
 }  // namespace vlb

@@ -632,6 +632,11 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
                    hipStream_t stream);
 // Error message of a call without a run (vlb_last_error(NULL)); returns code.
 int fail_global(int code, const std::string& msg);
+// Far-field approximation of the standalone sum (vlb_biot_savart_farfield).
+int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::string& msg);
+size_t ff_workspace(const vlb_bs_desc* d, const vlb_ff_params* p, long long n);
+hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, const double* xyz,
+                   const int32_t* next, double* v, void* ws, hipStream_t stream);
 hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r);
 int bs_chunks(long long ncap);
@@ -649,6 +654,9 @@ int sort_tiles(long long n);
 void sort_first_digit(int bits, int* dbits);
 int32_t* sort_counts(Run& r);
 hipError_t sort_pairs(Run& r, int bits, int first_counted, uint32_t** kres, int32_t** vres);
+hipError_t sort_pairs_raw(long long n, int bits, int first_counted, void* tmp, uint32_t* ka,
+                          uint32_t* kb, int32_t* va, int32_t* vb, hipStream_t stream,
+                          uint32_t** kres, int32_t** vres);
 
 // timing helpers (api.cpp)
 void time_begin(Run& r, int cls, hipEvent_t* b);

@@ -171,3 +171,54 @@ def test_biot_savart_null_pointers_rejected():
     code = lib.vlb_biot_savart(ctypes.byref(d), 10, None, None, None, None, 0, None)
     assert code == vlb.VLB_EINVAL
     assert "null" in lib.vlb_last_error(None).decode()
+
+
+def _ff_query(n, cell=8, theta=0.5, **kw):
+    lib = vlb.load_library()
+    args = dict(dims=(32, 32, 32), walls=(False, False, False), kappa=0.1, precision="f32")
+    args.update(kw)
+    d = vlb.bs_desc(**args)
+    p = vlb.FfParams(cell, 0, theta)
+    nb = ctypes.c_uint64(0)
+    code = lib.vlb_biot_savart_farfield_workspace(ctypes.byref(d), ctypes.byref(p), n,
+                                                  ctypes.byref(nb))
+    return code, nb.value, lib.vlb_last_error(None).decode()
+
+
+def test_farfield_workspace_query():
+    code, small, _ = _ff_query(1000)
+    assert code == vlb.VLB_OK and small > 1000 * 600
+    code, big, _ = _ff_query(100000)
+    assert code == vlb.VLB_OK and big > 50 * small
+    # finer cells need more (per-cell records and prefix rows)
+    assert _ff_query(1000, cell=2)[1] > small
+    assert _ff_query(0)[:2] == (vlb.VLB_OK, 0)
+    assert ctypes.sizeof(vlb.FfParams) == 16
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(walls=(False, False, True)), "periodic"),
+    (dict(precision="f64"), "FP32"),
+    (dict(theta=0.0), "theta"),
+    (dict(theta=1.0), "theta"),
+    (dict(cell=5), "divide"),
+    (dict(cell=0), "divide"),
+    (dict(cell=1, dims=(256, 256, 128)), "2^22"),
+    (dict(kappa=-1.0), "kappa"),
+])
+def test_farfield_invalid_rejected(kw, msg):
+    code, _, err = _ff_query(100, **kw)
+    assert code == vlb.VLB_EINVAL and msg in err
+
+
+def test_farfield_null_pointers_rejected():
+    lib = vlb.load_library()
+    d = vlb.bs_desc((8, 8, 8), precision="f32")
+    p = vlb.FfParams(4, 0, 0.5)
+    code = lib.vlb_biot_savart_farfield(ctypes.byref(d), ctypes.byref(p), 10, None, None, None,
+                                        None, 0, None)
+    assert code == vlb.VLB_EINVAL
+    assert "null" in lib.vlb_last_error(None).decode()
+    code = lib.vlb_biot_savart_farfield(ctypes.byref(d), None, 10, None, None, None, None, 0,
+                                        None)
+    assert code == vlb.VLB_EINVAL

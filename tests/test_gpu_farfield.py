@@ -1,0 +1,132 @@
+"""GPU parity of the far-field approximation of the non-local Biot-Savart
+sum (vlb_biot_savart_farfield, reading F2) against the oracle of the same
+approximation (oracle/farfield.py) through the C ABI: every target of
+small periodic tangles (uniform and non-uniform grids, several cell edges
+and opening parameters), sampled targets of a 128^3 tangle with many split
+cells and of the 256^3 tangle at full size, open lines, determinism, and
+the approximation's error against the GPU's direct FP32 sum."""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import coupled, farfield, vfm
+from oracle.lbm import Lattice
+from tests._cases import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2108_04435_amd as vlb  # noqa: E402
+
+KAPPA = 0.1
+# FP32 arithmetic against the FP64 oracle of the same approximation
+TOL = 1e-5
+
+
+def _tangle(dims, n_rings, seed, r_lo=2.0, r_hi=6.0):
+    lat = Lattice(*dims)
+    pos, nxt = wl.random_rings(seed, n_rings, r_lo, r_hi, dims, (False, False, False), 0.95,
+                               min_sep=1.0)
+    pos = vfm.wrap_positions(pos, lat)
+    return lat, pos, nxt, coupled.prev_from_next(nxt)
+
+
+def _check(got, ref, tag):
+    e = rel_l2(got, ref)
+    emax = np.abs(got - ref).max() / np.abs(ref).max()
+    say(f"{tag}: rel L2 {e:.2e}, max {emax:.2e}")
+    assert e <= TOL
+    assert emax <= 5 * TOL
+
+
+@pytest.mark.parametrize("dims,cell,theta", [
+    ((64, 64, 64), 16, 0.5), ((64, 64, 64), 8, 0.25), ((64, 64, 64), 8, 0.6),
+    ((64, 64, 128), 8, 0.4), ((48, 48, 48), 6, 0.5)])
+def test_farfield_every_target(dims, cell, theta):
+    """Small tangles, every target: 64^3 is a uniform grid (direct pairs in
+    grid units), 64x64x128 and 48^3 are not (lattice units)."""
+    lat, pos, nxt, prv = _tangle(dims, 60, 5)
+    say(f"farfield every target {dims} cell {cell} theta {theta}: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, cell, theta, KAPPA)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, cell, theta)
+    say(f"  oracle far {st['far']:.1f}, split {st['split']:.1f}, direct {st['direct']:.0f}")
+    assert st["far"] > 0
+    _check(got, ref, "every target")
+
+
+def test_farfield_many_split_cells():
+    """128^3, 8^3 cells, theta 0.25: about 60 split cells per target."""
+    dims = (128, 128, 128)
+    lat, pos, nxt, prv = _tangle(dims, 260, 9)
+    say(f"farfield 128^3 split cells: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA)
+    t = np.random.default_rng(3).choice(pos.shape[0], 300, replace=False)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25, targets=t)
+    assert st["split"] > 20
+    _check(got[t], ref, "128^3 sampled")
+
+
+def test_farfield_open_lines_and_split_pin():
+    """An open chain crossing the half-box plane of a ring's point (the
+    oracle's split pin) plus a few rings: every target."""
+    dims = (64, 64, 64)
+    lat = Lattice(*dims)
+    t = np.linspace(0.0, 1.0, 13)[:, None]
+    chain = np.array([32.4, 40.6, 44.6]) + t * np.array([6.8, 6.8, 0.0])
+    pos_r, nxt_r = wl.random_rings(4, 6, 2.0, 4.0, dims, (False, False, False), 0.95, min_sep=1.0)
+    phi = np.arange(12) * (2.0 * np.pi / 12)
+    ring = np.array([3.8, 20.2, 20.7]) + np.stack([np.cos(phi) - 1.0, np.sin(phi), 0 * phi], 1)
+    pos = vfm.wrap_positions(np.concatenate([chain, ring, pos_r]), lat)
+    nxt = np.concatenate([np.arange(1, 13), [12], 13 + (np.arange(1, 13) % 12), 25 + nxt_r])
+    prv = coupled.prev_from_next(nxt)
+    say(f"farfield open chain: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25)
+    assert st["split"] > 0
+    _check(got, ref, "open chain")
+
+
+def test_farfield_deterministic_and_degenerate():
+    """Two calls give the same bits; one point and no points are handled;
+    a cell as large as the box (one cell: nothing is far) is the direct
+    sum."""
+    dims = (32, 32, 32)
+    lat, pos, nxt, prv = _tangle(dims, 12, 3, 2.0, 5.0)
+    say(f"farfield determinism: {pos.shape[0]} points")
+    a = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA)
+    b = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA)
+    assert np.array_equal(a, b)
+    one = vlb.biot_savart_farfield(np.array([[1.0, 2.0, 3.0]]), np.array([0]), dims, 8, 0.5, KAPPA)
+    assert np.array_equal(one, np.zeros((1, 3)))
+    assert vlb.biot_savart_farfield(np.zeros((0, 3)), np.zeros(0, np.int32), dims, 8, 0.5,
+                                    KAPPA).shape == (0, 3)
+    whole = vlb.biot_savart_farfield(pos, nxt, dims, 32, 0.5, KAPPA)
+    direct = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, KAPPA)
+    _check(whole, direct, "one cell")
+
+
+def test_farfield_tangle_256_full_size():
+    """The 256^3 tangle (2000 rings, about 1e5 points), 16^3 cells, theta
+    0.25: 64 sampled targets against the oracle of the approximation, and
+    every target against the GPU's direct FP32 sum within the
+    approximation's error (relative L2 <= 1e-3)."""
+    cfg = wl.config_tangle()
+    dims = (256, 256, 256)
+    lat = Lattice(*dims)
+    pos = vfm.wrap_positions(cfg["pos"], lat)
+    nxt = cfg["nxt"]
+    prv = coupled.prev_from_next(nxt)
+    say(f"farfield 256^3 tangle: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, 16, 0.25, KAPPA)
+    t = np.random.default_rng(11).choice(pos.shape[0], 64, replace=False)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 16, 0.25, targets=t)
+    say(f"  oracle far {st['far']:.0f}, split {st['split']:.0f}, direct {st['direct']:.0f}")
+    _check(got[t], ref, "256^3 sampled")
+    direct = vlb.biot_savart(pos, nxt, dims, kappa=KAPPA, precision="f32")
+    e = rel_l2(got, direct)
+    say(f"  approximation error against the direct sum: {e:.2e}")
+    assert e <= 1e-3

@@ -187,8 +187,8 @@ __global__ void k_ff_bounds(const uint32_t* __restrict__ sk, int n, int C,
   cells[c].count = hi - lo;
 }
 
-// One thread per cell: moments (FP64, in the sorted order), radius, grid
-// centre and the extremes of the start offsets.
+// One thread per cell: radius, grid centre and the extremes of the start
+// offsets (the moments come from the prefix sums).
 __global__ void k_ff_cell(const int32_t* __restrict__ so, const double* __restrict__ Y,
                           const double* __restrict__ D, const uint32_t* __restrict__ X, int n,
                           FfAxes ax, FfCell* __restrict__ cells) {
@@ -203,9 +203,6 @@ __global__ void k_ff_cell(const int32_t* __restrict__ so, const double* __restri
     cen[a] = ((double)ci[a] + 0.5) * ax.h;
     xc[a] = (uint32_t)(long long)floor(cen[a] * ax.q[a]);
   }
-  double acc[kMom];
-#pragma unroll
-  for (int i = 0; i < kMom; ++i) acc[i] = 0.0;
   double rad = 0.0;
   int dmin[3] = {0, 0, 0}, dmax[3] = {0, 0, 0};
   for (int p = s; p < e; ++p) {
@@ -218,8 +215,6 @@ __global__ void k_ff_cell(const int32_t* __restrict__ so, const double* __restri
       dmin[a] = p == s ? dl : min(dmin[a], dl);
       dmax[a] = p == s ? dl : max(dmax[a], dl);
     }
-#pragma unroll
-    for (int i = 0; i < kMom; ++i) acc[i] = acc[i] + comp_value(i, y, d);
     const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     rad = fmax(rad, ny + 0.5 * nd);
@@ -233,8 +228,6 @@ __global__ void k_ff_cell(const int32_t* __restrict__ so, const double* __restri
     o.dmax[a] = dmax[a];
   }
   o.pad = 0;
-#pragma unroll
-  for (int i = 0; i < kMom; ++i) o.m[i] = (float)acc[i];
 }
 
 // Per sorted position: the direct loop's segment record.
@@ -286,7 +279,8 @@ __global__ void k_ff_rank(const uint32_t* __restrict__ sk, const int32_t* __rest
 // Per (cell, axis, component): prefix sums (FP64, stored FP32) of the
 // component over the cell's segments in ascending offset order on the
 // axis; rows a (n + C) + start + c + i for i = 0..count (row 0 is zero).
-__global__ void k_ff_prefix(const FfCell* __restrict__ cells, const int32_t* __restrict__ sidx,
+// The axis-0 totals are the cell's moments.
+__global__ void k_ff_prefix(FfCell* __restrict__ cells, const int32_t* __restrict__ sidx,
                             const double* __restrict__ Y, const double* __restrict__ D, int n,
                             int C, float* __restrict__ pre) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,6 +302,7 @@ __global__ void k_ff_prefix(const FfCell* __restrict__ cells, const int32_t* __r
     acc = acc + comp_value(comp, y, d);
     row[(long long)(i + 1) * kMom] = (float)acc;
   }
+  if (a == 0) cells[c].m[comp] = (float)acc;
 }
 
 // Velocity times 4 pi (no kappa) at R = target - centre of the moments m
@@ -315,7 +310,20 @@ __global__ void k_ff_prefix(const FfCell* __restrict__ cells, const int32_t* __r
 //   v += (M0 x R - A) / r^3 + W x R - 3 B / r^5,
 //   W_n = (3 (M1 R)_n - 3/2 tr_n) / r^5 + 15/2 (R M2_n R) / r^7,
 //   B_m = eps_mnp (M2_n R)_p.
-__device__ inline void m2p_f32(float Rx, float Ry, float Rz, const float* m, float& vx, float& vy,
+// Moments: one array, or the difference of two (the upper class of a split
+// cell: the cell's totals minus the prefix of the lower class).
+struct MomA {
+  const float* p;
+  __device__ float operator()(int i) const { return p[i]; }
+};
+struct MomD {
+  const float* t;
+  const float* p;
+  __device__ float operator()(int i) const { return t[i] - p[i]; }
+};
+
+template <class M>
+__device__ inline void m2p_f32(float Rx, float Ry, float Rz, const M& m, float& vx, float& vy,
                                float& vz) {
   const float r2 = fmaf(Rx, Rx, fmaf(Ry, Ry, Rz * Rz));
   const float ir = __builtin_amdgcn_rsqf(r2);
@@ -326,20 +334,23 @@ __device__ inline void m2p_f32(float Rx, float Ry, float Rz, const float* m, flo
   float S[3][3], W[3];
 #pragma unroll
   for (int nn = 0; nn < 3; ++nn) {
-    const float* q = m + 15 + 6 * nn;
-    S[nn][0] = fmaf(q[0], Rx, fmaf(q[1], Ry, q[2] * Rz));
-    S[nn][1] = fmaf(q[1], Rx, fmaf(q[3], Ry, q[4] * Rz));
-    S[nn][2] = fmaf(q[2], Rx, fmaf(q[4], Ry, q[5] * Rz));
+    const int q = 15 + 6 * nn;
+    const float q0 = m(q), q1 = m(q + 1), q2 = m(q + 2), q3 = m(q + 3), q4 = m(q + 4),
+                q5 = m(q + 5);
+    S[nn][0] = fmaf(q0, Rx, fmaf(q1, Ry, q2 * Rz));
+    S[nn][1] = fmaf(q1, Rx, fmaf(q3, Ry, q4 * Rz));
+    S[nn][2] = fmaf(q2, Rx, fmaf(q4, Ry, q5 * Rz));
     const float Q = fmaf(Rx, S[nn][0], fmaf(Ry, S[nn][1], Rz * S[nn][2]));
-    const float a = fmaf(m[6 + 3 * nn], Rx, fmaf(m[7 + 3 * nn], Ry, m[8 + 3 * nn] * Rz));
-    W[nn] = fmaf(r5, fmaf(3.0f, a, -1.5f * m[33 + nn]), r7h * Q);
+    const float a = fmaf(m(6 + 3 * nn), Rx, fmaf(m(7 + 3 * nn), Ry, m(8 + 3 * nn) * Rz));
+    W[nn] = fmaf(r5, fmaf(3.0f, a, -1.5f * m(33 + nn)), r7h * Q);
   }
   const float B0 = S[1][2] - S[2][1];
   const float B1 = S[2][0] - S[0][2];
   const float B2 = S[0][1] - S[1][0];
-  const float V0 = fmaf(m[1], Rz, -fmaf(m[2], Ry, m[3]));
-  const float V1 = fmaf(m[2], Rx, -fmaf(m[0], Rz, m[4]));
-  const float V2 = fmaf(m[0], Ry, -fmaf(m[1], Rx, m[5]));
+  const float m0 = m(0), m1 = m(1), m2 = m(2);
+  const float V0 = fmaf(m1, Rz, -fmaf(m2, Ry, m(3)));
+  const float V1 = fmaf(m2, Rx, -fmaf(m0, Rz, m(4)));
+  const float V2 = fmaf(m0, Ry, -fmaf(m1, Rx, m(5)));
   const float t5 = 3.0f * r5;
   vx = fmaf(r3, V0, vx + fmaf(W[1], Rz, -fmaf(W[2], Ry, t5 * B0)));
   vy = fmaf(r3, V1, vy + fmaf(W[2], Rx, -fmaf(W[0], Rz, t5 * B1)));
@@ -378,6 +389,28 @@ __device__ inline void ff_pair(const FfSeg& g, uint32_t xt, uint32_t yt, uint32_
   vz = fmaf(f, crz, vz);
 }
 
+// The decision fields of a cell record, loaded one cell ahead.
+struct FfHead {
+  int32_t start, count;
+  double rad2;
+  double c[3];
+  uint32_t xc[3];
+  int32_t dmin[3], dmax[3];
+};
+
+__device__ inline void ff_head(const FfCell* __restrict__ cm, FfHead& h) {
+  h.start = cm->start;
+  h.count = cm->count;
+  h.rad2 = cm->rad2;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h.c[a] = cm->c[a];
+    h.xc[a] = cm->xc[a];
+    h.dmin[a] = cm->dmin[a];
+    h.dmax[a] = cm->dmax[a];
+  }
+}
+
 // Per-lane decision for one cell (FP64 and integers, no contraction).
 struct FfDecision {
   double R0[3];  // (c - r) + K L of the class of the smallest start offset
@@ -387,8 +420,8 @@ struct FfDecision {
   bool ok0;      // R0 passes the opening test
 };
 
-__device__ inline void ff_decide(const FfCell* __restrict__ cm, const double* r,
-                                 const uint32_t* xt, const FfAxes& ax, FfDecision& o) {
+__device__ inline void ff_decide(const FfHead* cm, const double* r, const uint32_t* xt,
+                                 const FfAxes& ax, FfDecision& o) {
 #pragma clang fp contract(off)
   o.ncross = 0;
   o.axis = 0;
@@ -415,8 +448,8 @@ __device__ inline void ff_decide(const FfCell* __restrict__ cm, const double* r,
 // The class of the largest offset on the crossed axis: its wrapped offset
 // dropped by 2^32 at the crossing, so its K there is one less.  Returns
 // whether that image passes the opening test.
-__device__ inline bool ff_other(const FfCell* __restrict__ cm, const FfDecision& o,
-                                const double* r, const FfAxes& ax, double* R1) {
+__device__ inline bool ff_other(const FfHead* cm, const FfDecision& o, const double* r,
+                                const FfAxes& ax, double* R1) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -452,61 +485,65 @@ __global__ __launch_bounds__(256) void k_ff_eval(
   float dx = 0.f, dy = 0.f, dz = 0.f;  // direct part (grid units when uniform)
   const int C = ax.C;
   const int step = 4 * S;
-  for (int c = blockIdx.y * 4 + w; c < C; c += step) {
+  int c = blockIdx.y * 4 + w;
+  FfHead hc;
+  if (c < C) ff_head(cells + c, hc);
+  for (; c < C; c += step) {
+    // the next cell's decision fields are loaded while this one is summed
+    FfHead hn;
+    if (c + step < C) ff_head(cells + c + step, hn);
     const FfCell* __restrict__ cm = cells + c;
-    const int cnt = cm->count;
-    if (cnt == 0) continue;
-    FfDecision dc;
-    ff_decide(cm, r, xt, ax, dc);
-    const bool far = valid && dc.ncross == 0 && dc.ok0;
-    bool split = false;
-    double R1[3] = {0.0, 0.0, 0.0};
-    if (valid && dc.ncross == 1 && dc.ok0) split = ff_other(cm, dc, r, ax, R1);
-    const bool near = valid && !far && !split;
-    if (__any(far)) {
-      if (far) m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], cm->m, fx, fy, fz);
-    }
-    if (__any(split)) {
-      if (split) {
-        // offsets below the crossing: u + delta < 2^31
-        const int a = dc.axis;
-        const uint32_t u = cm->xc[a] - xt[a];
-        const int db = (int)(0x80000000u - u);
-        const int32_t* dl = sdel + (long long)a * n + cm->start;
-        int lo = 0, hi = cnt;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (dl[mid] < db)
-            lo = mid + 1;
-          else
-            hi = mid;
-        }
-        const float* pr = pre + ((long long)a * (n + C) + cm->start + c + lo) * kMom;
-        float ml[kMom], mh[kMom];
-#pragma unroll
-        for (int i = 0; i < kMom; ++i) {
-          ml[i] = pr[i];
-          mh[i] = cm->m[i] - ml[i];
-        }
-        m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], ml, fx, fy, fz);
-        m2p_f32((float)-R1[0], (float)-R1[1], (float)-R1[2], mh, fx, fy, fz);
+    const int cnt = hc.count;
+    if (cnt > 0) {
+      FfDecision dc;
+      ff_decide(&hc, r, xt, ax, dc);
+      const bool far = valid && dc.ncross == 0 && dc.ok0;
+      bool split = false;
+      double R1[3] = {0.0, 0.0, 0.0};
+      if (valid && dc.ncross == 1 && dc.ok0) split = ff_other(&hc, dc, r, ax, R1);
+      const bool near = valid && !far && !split;
+      if (__any(far)) {
+        if (far)
+          m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{cm->m}, fx, fy, fz);
       }
-    }
-    if (__any(near)) {
-      const int s0 = cm->start;
-      const bool own = __any(kj == c || kp == c);
-      if (own) {
-        for (int p = s0; p < s0 + cnt; ++p) {
-          const FfSeg g = recs[p];
-          if (near) ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, g.idx == jj || g.idx == pj);
+      if (__any(split)) {
+        if (split) {
+          // offsets below the crossing: u + delta < 2^31
+          const int a = dc.axis;
+          const uint32_t u = hc.xc[a] - xt[a];
+          const int db = (int)(0x80000000u - u);
+          const int32_t* dl = sdel + (long long)a * n + hc.start;
+          int lo = 0, hi = cnt;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (dl[mid] < db)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          const float* pr = pre + ((long long)a * (n + C) + hc.start + c + lo) * kMom;
+          m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{pr}, fx, fy, fz);
+          m2p_f32((float)-R1[0], (float)-R1[1], (float)-R1[2], MomD{cm->m, pr}, fx, fy, fz);
         }
-      } else {
-        for (int p = s0; p < s0 + cnt; ++p) {
-          const FfSeg g = recs[p];
-          if (near) ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, false);
+      }
+      if (__any(near)) {
+        const int s0 = hc.start;
+        const bool own = __any(kj == c || kp == c);
+        if (own) {
+          for (int p = s0; p < s0 + cnt; ++p) {
+            const FfSeg g = recs[p];
+            if (near)
+              ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, g.idx == jj || g.idx == pj);
+          }
+        } else {
+          for (int p = s0; p < s0 + cnt; ++p) {
+            const FfSeg g = recs[p];
+            if (near) ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, false);
+          }
         }
       }
     }
+    hc = hn;
   }
   if (kUniform) {
     fx = fmaf(dx, ax.qf, fx);
@@ -570,7 +607,7 @@ FfAxes ff_axes(const vlb_bs_desc* d, const vlb_ff_params* p) {
 
 int ff_chunks(long long n, int C) {
   const long long tb = (n + kFfTargets - 1) / kFfTargets;
-  long long S = (2048 + tb - 1) / tb;
+  long long S = (8192 + tb - 1) / tb;
   if (S > C / 4) S = C / 4;
   if (S > 64) S = 64;
   if (S < 1) S = 1;

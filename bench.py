@@ -519,6 +519,69 @@ def hbm_copy(torch, nbytes=1 << 30, reps=10):
     return dict(bytes=2 * nbytes, ms=round(ms, 4), GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
 
 
+def farfield_bench(torch, vlb, cfg, cell, theta, reps=10):
+    """The far-field approximation of the non-local Biot-Savart sum
+    (vlb_biot_savart_farfield, reading F2) beside the direct FP32 sum
+    (vlb_biot_savart) on the workload's filaments, both through the C ABI
+    with device-resident inputs: time per call (HIP events around ``reps``
+    calls on torch's stream, every kernel of each call inside) and the
+    approximation's relative L2 error against the direct sum.  Periodic
+    boxes only (None otherwise)."""
+    lat = cfg["lattice"]
+    dims = (lat["nx"], lat["ny"], lat["nz"])
+    if any(lat["walls"]) or any(d % cell for d in dims):
+        return None
+    L = np.array(dims, dtype=np.float64)
+    pos = np.mod(cfg["pos"], L)
+    nxt = np.ascontiguousarray(cfg["nxt"], dtype=np.int32)
+    n = pos.shape[0]
+    kappa = cfg["vortex"]["kappa"]
+    p = torch.as_tensor(np.ascontiguousarray(pos)).cuda()
+    q = torch.as_tensor(nxt).cuda()
+    v = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    lib = vlb.load_library()
+    d = vlb.bs_desc(dims, (False, False, False), kappa, "f32")
+    nb = vlb.ctypes.c_uint64(0)
+    vlb._raise(lib, lib.vlb_biot_savart_workspace(vlb.ctypes.byref(d), n, vlb.ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device="cuda")
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    s = torch.cuda.current_stream()
+    vp = vlb.ctypes.c_void_p
+
+    def direct():
+        vlb._raise(lib, lib.vlb_biot_savart(vlb.ctypes.byref(d), n, vp(p.data_ptr()),
+                                            vp(q.data_ptr()), vp(v.data_ptr()), vp(wp),
+                                            vlb.ctypes.c_uint64(int(nb.value)), vp(s.cuda_stream)))
+
+    ff = vlb.FarField(dims, n, cell, theta, kappa)
+
+    def far():
+        ff.run(p, q, v)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(reps):
+            fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_dir = timed(direct)
+    v_dir = v.cpu().numpy()
+    t_far = timed(far)
+    v_far = v.cpu().numpy()
+    err = float(np.linalg.norm(v_far - v_dir) / np.linalg.norm(v_dir))
+    del ws, ff, p, q, v
+    torch.cuda.empty_cache()
+    return dict(points=n, cell=cell, theta=theta, cells=int(np.prod([x // cell for x in dims])),
+                direct_f32_ms=round(t_dir, 4), farfield_ms=round(t_far, 4),
+                speedup=round(t_dir / t_far, 3), rel_l2_vs_direct=float(f"{err:.3e}"),
+                basis="HIP events around %d calls each, inputs resident on the GPU" % reps)
+
+
 def serve_bench(args):
     """Served form: 64 counterflow requests arriving as a Poisson stream at
     2/s, lattices {32^3, 64^3, 64x64x256, 128x128x256}, 1k-20k points,
@@ -570,6 +633,10 @@ def parse_args(argv=None):
     ap.add_argument("--lbm-probe", action="store_true",
                     help="also time the LBM update alone on 256^3 (FP16, FP32, FP64 storage)")
     ap.add_argument("--baseline-workers", type=int, default=None)
+    ap.add_argument("--ff-cell", type=int, default=16,
+                    help="cell edge of the far-field approximation measured beside the direct "
+                         "sum (periodic workloads; 0: not measured)")
+    ap.add_argument("--ff-theta", type=float, default=0.25)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -719,6 +786,8 @@ def main(argv=None):
     if args.lbm_probe:
         out["lbm_256cubed"] = [lbm_only(256, p) for p in ("f16", "f32", "f64")]
         torch.cuda.empty_cache()
+    if args.ff_cell > 0:
+        out["farfield"] = farfield_bench(torch, vlb, cfg, args.ff_cell, args.ff_theta)
     out["hbm_copy"] = hbm_copy(torch)
     if base is not None:
         out["cpu_baseline"] = base

@@ -42,6 +42,14 @@ their starts.  Per target and cell:
 theta < 1 keeps the target's own segments in direct cells (a segment that
 touches r lies within rad of its cell centre).  Decisions are made in FP64
 with the sums written left to right.
+
+Levels.  With ``levels`` = l > 1 the cells of edge h 2^m (m = 0 .. l - 1)
+form a hierarchy, each cell the union of 8 cells of the level below, each
+with its own moments and radius about its own centre.  Per target the
+cells of the coarsest level are classified as above; a coarse cell that is
+neither far nor split is opened: its 8 children are classified in turn,
+down to edge h, where the cells that are neither far nor split are summed
+directly.
 """
 
 import numpy as np
@@ -165,55 +173,75 @@ def classify(r, pos, cm, lat: Lattice, theta):
                 Rhi=Rhi)
 
 
-def biot_savart_farfield(pos, nxt, prv, lat: Lattice, kappa, h, theta, targets=None):
+def _children(nc_fine):
+    """Parent index (at the level with half the cells per axis) of every
+    cell of a level with nc_fine cells per axis."""
+    cid = np.arange(int(np.prod(nc_fine)))
+    ci = np.stack([cid % nc_fine[0], (cid // nc_fine[0]) % nc_fine[1],
+                   cid // (nc_fine[0] * nc_fine[1])], 1) // 2
+    pn = np.asarray(nc_fine) // 2
+    return (ci[:, 2] * pn[1] + ci[:, 1]) * pn[0] + ci[:, 0]
+
+
+def biot_savart_farfield(pos, nxt, prv, lat: Lattice, kappa, h, theta, targets=None, levels=1):
     """Non-local superfluid velocity at ``targets`` (default: all) by the
-    cell-multipole approximation (module docstring).  Returns (T, 3) and a
-    dict of the mean numbers of far cells, split cells and direct pairs per
+    cell-multipole approximation (module docstring), with ``levels`` levels
+    of cells (edge h at the finest).  Returns (T, 3) and a dict of the mean
+    numbers of far cells, split cells (all levels) and direct pairs per
     target."""
     if any(lat.walls):
         raise ValueError("the far-field sum is defined for periodic boxes")
     if not 0.0 < theta < 1.0:
         raise ValueError("theta must lie in (0, 1)")
+    if levels < 1:
+        raise ValueError("levels must be >= 1")
     pos = wrap_positions(pos, lat)
     N = pos.shape[0]
     if targets is None:
         targets = np.arange(N)
-    cm = cell_moments(pos, nxt, lat, h, kappa)
-    key, d, y = cm["key"], cm["d"], cm["y"]
-    C = cm["centre"].shape[0]
+    cms = [cell_moments(pos, nxt, lat, h * 2 ** m, kappa) for m in range(levels)]
+    parents = [_children(cell_grid(lat, h * 2 ** m)[0]) for m in range(levels - 1)]
     out = np.zeros((len(targets), 3))
     n_far = n_split = n_dir = 0
     for t, j in enumerate(targets):
         r = pos[j]
-        cl = classify(r, pos, cm, lat, theta)
-        kind = cl["kind"]
         v = np.zeros(3)
-        far = kind == FAR
-        if far.any():
-            v += m2p(-cl["Rlo"][far], cm["M0"][far], cm["M1"][far], cm["M2"][far])
-        split = kind == SPLIT
-        if split.any():
-            # lower class: the segments of split cells whose class on the
-            # crossed axis is the smaller one; the others form the upper
-            ks = np.nonzero(split[key])[0]
-            kc = key[ks]
-            ax = cl["axis"][kc]
-            lower = cl["K"][ks, ax] == cl["Kmin"][kc, ax]
-            lo, hi = ks[lower], ks[~lower]
-            M0l, M1l, M2l = _moments(key[lo], y[lo], d[lo], kappa, C)
-            M0h, M1h, M2h = _moments(key[hi], y[hi], d[hi], kappa, C)
-            v += m2p(-cl["Rlo"][split], M0l[split], M1l[split], M2l[split])
-            v += m2p(-cl["Rhi"][split], M0h[split], M1h[split], M2h[split])
-        v = v / (4.0 * np.pi)
-        near = np.nonzero(kind == NEAR)[0]
-        if near.size:
-            ks = np.concatenate([cm["order"][cm["starts"][c]:cm["ends"][c]] for c in near])
-            ks = ks[(ks != j) & (ks != prv[j])]
-            R1 = bs_image_offsets(pos[ks], r[None, :], lat)
-            v = v + segment_velocity(R1, R1 + d[ks], kappa).sum(axis=0)
-            n_dir += ks.size
-        n_far += int(far.sum())
-        n_split += int(split.sum())
+        consider = np.ones(cms[-1]["centre"].shape[0], dtype=bool)
+        for m in range(levels - 1, -1, -1):
+            cm = cms[m]
+            key, d, y = cm["key"], cm["d"], cm["y"]
+            C = cm["centre"].shape[0]
+            cl = classify(r, pos, cm, lat, theta)
+            kind = np.where(consider, cl["kind"], EMPTY)
+            far = kind == FAR
+            if far.any():
+                v += m2p(-cl["Rlo"][far], cm["M0"][far], cm["M1"][far], cm["M2"][far]) / (4.0 * np.pi)
+            split = kind == SPLIT
+            if split.any():
+                # lower class: the segments of split cells whose class on the
+                # crossed axis is the smaller one; the others form the upper
+                ks = np.nonzero(split[key])[0]
+                kc = key[ks]
+                ax = cl["axis"][kc]
+                lower = cl["K"][ks, ax] == cl["Kmin"][kc, ax]
+                lo, hi = ks[lower], ks[~lower]
+                M0l, M1l, M2l = _moments(key[lo], y[lo], d[lo], kappa, C)
+                M0h, M1h, M2h = _moments(key[hi], y[hi], d[hi], kappa, C)
+                v += m2p(-cl["Rlo"][split], M0l[split], M1l[split], M2l[split]) / (4.0 * np.pi)
+                v += m2p(-cl["Rhi"][split], M0h[split], M1h[split], M2h[split]) / (4.0 * np.pi)
+            n_far += int(far.sum())
+            n_split += int(split.sum())
+            opened = kind == NEAR
+            if m > 0:
+                consider = opened[parents[m - 1]]
+                continue
+            near = np.nonzero(opened)[0]
+            if near.size:
+                ks = np.concatenate([cm["order"][cm["starts"][c]:cm["ends"][c]] for c in near])
+                ks = ks[(ks != j) & (ks != prv[j])]
+                R1 = bs_image_offsets(pos[ks], r[None, :], lat)
+                v = v + segment_velocity(R1, R1 + d[ks], kappa).sum(axis=0)
+                n_dir += ks.size
         out[t] = v
     T = max(len(targets), 1)
     return out, dict(far=n_far / T, split=n_split / T, direct=n_dir / T)

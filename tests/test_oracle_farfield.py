@@ -26,10 +26,12 @@ def _tangle(n, n_rings, seed, r_lo=2.0, r_hi=5.0):
     return lat, pos, nxt, coupled.prev_from_next(nxt)
 
 
-def test_all_cells_near_is_the_direct_sum():
+@pytest.mark.parametrize("levels", [1, 2])
+def test_all_cells_near_is_the_direct_sum(levels):
     lat, pos, nxt, prv = _tangle(32, 12, 3)
-    for h in (8, 16):
-        got, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, h, 1e-9)
+    for h in (4, 8):
+        got, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, h, 1e-9,
+                                                levels=levels)
         assert st["far"] == 0 and st["split"] == 0
         ref = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, KAPPA)
         np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
@@ -132,20 +134,28 @@ def test_a_cell_crossed_on_two_axes_is_summed_directly():
     np.testing.assert_allclose(got, ref, rtol=1e-3)
 
 
+@pytest.mark.parametrize("levels", [1, 2])
 @pytest.mark.parametrize("n,h,n_rings,seed", [(64, 16, 60, 5), (128, 8, 260, 9)])
-def test_error_bound_on_a_random_tangle(n, h, n_rings, seed):
+def test_error_bound_on_a_random_tangle(n, h, n_rings, seed, levels):
     """Random rings: relative L2 error of the non-local velocity at 150
     sampled targets <= 1e-3 at theta = 0.25, larger at theta = 0.5; the
-    128^3 box with 8^3 cells has many far and split cells per target."""
+    128^3 box with 8^3 cells has many far and split cells per target, and
+    with a second level of 16^3 cells fewer of them."""
     lat, pos, nxt, prv = _tangle(n, n_rings, seed, 2.0, 6.0)
     t = np.random.default_rng(7).choice(pos.shape[0], 150, replace=False)
     ref = vfm.biot_savart_nonlocal(pos, nxt, prv, lat, KAPPA, targets=t)
     errs = {}
     for theta in (0.25, 0.5):
-        got, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, h, theta, targets=t)
+        got, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, h, theta, targets=t,
+                                                levels=levels)
         errs[theta] = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert st["far"] > 0
         if n == 128:
             assert st["split"] > 20
+            if levels == 2:
+                # coarse cells stand for groups of fine ones
+                _, st1 = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, h, theta,
+                                                       targets=t)
+                assert st["far"] + st["split"] < st1["far"] + st1["split"]
     assert errs[0.25] <= 1e-3
     assert errs[0.5] > errs[0.25]

@@ -394,11 +394,15 @@ int vlb_biot_savart_noalloc(const vlb_bs_desc* d, int64_t n_pts, const double* x
  * meaningless results, never an access outside the buffers).
  * Approximation error: relative L2 of the non-local velocity about 5e-4
  * at theta = 0.25 on tangles of random rings (it grows with theta).
+ *  With p->levels = 2 the cells of edge 2 p->cell are taken first: a coarse
+ *  cell that is neither far nor split is opened and its 8 children follow
+ *  the same rule (fewer expansions per target: about 2x faster on a 256^3
+ *  tangle of 1e5 points, error 6e-4 at theta = 0.25).
  *  - d: as vlb_biot_savart with wall_axes 0 and precision VLB_F32 (the
  *    sum is FP32; chunk partials added in FP64 in a fixed order, bitwise
- *    reproducible); p->cell >= 1 divides nx, ny and nz, at most 2^22
- *    cells; 0 < p->theta < 1 (which keeps each target's own segments in
- *    cells it sums directly).
+ *    reproducible); p->cell >= 1 divides nx, ny and nz (2 p->cell does with
+ *    two levels), at most 2^22 cells of edge p->cell; 0 < p->theta < 1
+ *    (which keeps each target's own segments in cells it sums directly).
  *  - xyz_dev, next_dev, v_dev, dev_workspace, hip_stream: as
  *    vlb_biot_savart, the workspace sized by
  *    vlb_biot_savart_farfield_workspace (about 620 bytes per point, 700
@@ -407,8 +411,10 @@ int vlb_biot_savart_noalloc(const vlb_bs_desc* d, int64_t n_pts, const double* x
  *    [0, 2^26] or a NULL pointer (n_pts > 0); VLB_ENOSPACE for a small
  *    workspace; VLB_EDEVICE if a launch fails.                             */
 typedef struct {
-  int32_t cell;           /* cell edge in lattice units                      */
-  int32_t reserved;       /* 0                                               */
+  int32_t cell;           /* finest cell edge in lattice units               */
+  int32_t levels;         /* 1 (or 0): one grid of cells; 2: cells of edge   */
+                          /* 2 cell first, opened ones handing their 8       */
+                          /* children of edge cell to the same rule          */
   double theta;           /* opening parameter, 0 < theta < 1               */
 } vlb_ff_params;
 

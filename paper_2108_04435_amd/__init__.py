@@ -80,7 +80,7 @@ class BsDesc(ctypes.Structure):
 
 
 class FfParams(ctypes.Structure):
-    _fields_ = [("cell", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("cell", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("theta", ctypes.c_double)]
 
 
@@ -496,18 +496,19 @@ def biot_savart(xyz, nxt, dims, walls=(False, False, False), kappa=0.1, precisio
 class FarField:
     """Far-field approximation of the stand-alone Biot-Savart sum
     (vlb_biot_savart_farfield) for n points in a periodic box ``dims``:
-    cells of edge ``cell``, opening parameter ``theta``; FP32.  The
-    workspace is allocated once; ``run`` enqueues one sum on torch's current
-    stream from device tensors (positions (n, 3) float64, links (n,) int32)
-    into ``v`` ((n, 3) float64)."""
+    cells of edge ``cell`` (``levels`` 2: cells of edge 2 cell first),
+    opening parameter ``theta``; FP32.  The workspace is allocated once;
+    ``run`` enqueues one sum on torch's current stream from device tensors
+    (positions (n, 3) float64, links (n,) int32) into ``v`` ((n, 3)
+    float64)."""
 
-    def __init__(self, dims, n, cell, theta, kappa=0.1, device=0):
+    def __init__(self, dims, n, cell, theta, kappa=0.1, device=0, levels=1):
         import torch
 
         self.lib = load_library()
         self.dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.desc = bs_desc(dims, (False, False, False), kappa, "f32")
-        self.par = FfParams(int(cell), 0, float(theta))
+        self.par = FfParams(int(cell), int(levels), float(theta))
         self.n = int(n)
         nb = ctypes.c_uint64(0)
         _raise(self.lib, self.lib.vlb_biot_savart_farfield_workspace(
@@ -531,14 +532,14 @@ class FarField:
             ctypes.c_uint64(self.ws_bytes), ctypes.c_void_p(stream.cuda_stream)))
 
 
-def biot_savart_farfield(xyz, nxt, dims, cell, theta, kappa=0.1, device=0):
+def biot_savart_farfield(xyz, nxt, dims, cell, theta, kappa=0.1, device=0, levels=1):
     """Far-field approximation of the non-local velocity (FarField) of
     filaments ``xyz`` (n, 3), ``nxt`` (n,) in a periodic box; returns (n, 3)
     velocities as a host array."""
     import torch
 
     n = int(np.asarray(nxt).size)
-    ff = FarField(dims, max(n, 1), cell, theta, kappa, device)
+    ff = FarField(dims, max(n, 1), cell, theta, kappa, device, levels)
     if n == 0:
         return np.zeros((0, 3))
     p = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)).to(ff.dev)

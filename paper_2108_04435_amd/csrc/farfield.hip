@@ -20,22 +20,28 @@
 //    classes differing on one axis (delta_min and delta_max on opposite
 //    sides): split when both images pass, the class below the crossing
 //    taking the prefix moments of the cell's segments sorted by delta on
-//    that axis, the other the rest; otherwise direct.
+//    that axis, the other the rest; otherwise direct;
+//  * with two levels the cells of edge 2h are classified first and an
+//    opened one (neither far nor split) hands its 8 children of edge h to
+//    the same rule, the lanes that opened it taking part.
 //
 // Layout (workspace, all per call):
 //  * per point: wrapped FP64 positions, grid coordinates, links, y and d
 //    (FP64), cell key;
 //  * segments sorted by cell (stable radix sort, so ascending index inside
-//    a cell), one 32-byte record each for the direct loop;
+//    a cell; with two levels the key is coarse cell * 8 + child, so each
+//    coarse cell's children are consecutive), one 32-byte record each for
+//    the direct loop;
 //  * one 256-byte record per cell (range, rad^2, centre, grid centre,
 //    delta extremes, 36 moments), read with scalar loads;
 //  * per axis: each cell's deltas in ascending order and the prefix sums of
 //    the 36 moment components over that order (cnt + 1 rows per cell);
 //  * the evaluation grid: blockIdx.x picks 64 targets (consecutive in the
 //    cell order, so a wave's targets are close), blockIdx.y one of S cell
-//    chunks; the 4 waves of a block take interleaved cells (c = 4 y + w
-//    modulo 4 S) and add their sums in LDS in a fixed order; the chunk
-//    partials are added in FP64 in chunk order (bitwise reproducible).
+//    chunks; the 4 waves of a block take interleaved cells of the coarsest
+//    level (c = 4 y + w modulo 4 S) and add their sums in LDS in a fixed
+//    order; the chunk partials are added in FP64 in chunk order (bitwise
+//    reproducible).
 #include "vlb_internal.h"
 
 #include <cmath>
@@ -76,13 +82,40 @@ __device__ inline double comp_value(int comp, const double* y, const double* d) 
 }
 
 struct FfAxes {
-  double L[3], q[3], h, th2;
+  double L[3], q[3], th2;
+  double h[2];   // cell edge per level (level 0 the finest)
   float iqf[3];  // lattice units per grid step
   float qf;      // one grid step count per lattice unit when uniform
-  int nc[3];
-  int C;
+  int nc[2][3];  // cells per axis per level
+  int C[2];      // cells per level
+  int levels;    // 1 or 2
   int uniform;
 };
+
+// Cell coordinates at a level from its record index: one level, x fastest;
+// two levels, the coarse cell x fastest and, at the fine level, index =
+// coarse * 8 + child with child bits x | y << 1 | z << 2.
+__device__ inline void ff_coords(const FfAxes& ax, int level, int idx, int* ci) {
+  if (ax.levels == 1 || level == 1) {
+    const int* nc = ax.nc[level];
+    ci[0] = idx % nc[0];
+    ci[1] = (idx / nc[0]) % nc[1];
+    ci[2] = idx / (nc[0] * nc[1]);
+  } else {
+    const int t = idx >> 3, ch = idx & 7;
+    const int* nc = ax.nc[1];
+    ci[0] = 2 * (t % nc[0]) + (ch & 1);
+    ci[1] = 2 * ((t / nc[0]) % nc[1]) + ((ch >> 1) & 1);
+    ci[2] = 2 * (t / (nc[0] * nc[1])) + ((ch >> 2) & 1);
+  }
+}
+
+__device__ inline double ff_min_image(double x, double L) {
+#pragma clang fp contract(off)
+  if (x > 0.5 * L) return x - L;
+  if (x < -0.5 * L) return x + L;
+  return x;
+}
 
 struct __align__(256) FfCell {
   int32_t start, count;      // range in the sorted order
@@ -115,11 +148,11 @@ __global__ void k_ff_init(int32_t* __restrict__ prv, int n) {
 }
 
 // Per point: wrapped position, grid coordinate, links, segment vector,
-// midpoint cell, y; sort keys (cell) and values (index).
+// midpoint and its finest cell; sort keys (cell) and values (index).
 __global__ void k_ff_prep(const double* __restrict__ xyz, const int32_t* __restrict__ next, int n,
                           FfAxes ax, int32_t* __restrict__ cnt, double* __restrict__ P,
                           uint32_t* __restrict__ X, int32_t* __restrict__ nxt,
-                          int32_t* __restrict__ prv, double* __restrict__ Y,
+                          int32_t* __restrict__ prv, double* __restrict__ M,
                           double* __restrict__ D, uint32_t* __restrict__ keys,
                           int32_t* __restrict__ kidx, int32_t* __restrict__ vals) {
 #pragma clang fp contract(off)
@@ -140,25 +173,21 @@ __global__ void k_ff_prep(const double* __restrict__ xyz, const int32_t* __restr
     const double pk = ff_wrap(xyz[3LL * k + a], L);
     P[(long long)a * n + j] = p;
     X[(long long)a * n + j] = (uint32_t)(long long)floor(p * ax.q[a]);
-    double d = pk - p;
-    if (d > 0.5 * L)
-      d = d - L;
-    else if (d < -0.5 * L)
-      d = d + L;
+    const double d = ff_min_image(pk - p, L);
     double mid = p + 0.5 * d;
     mid = mid - L * floor(mid / L);
-    int i = (int)floor(mid / ax.h);
-    i = min(max(i, 0), ax.nc[a] - 1);
-    idx[a] = i;
-    double y = mid - ((double)i + 0.5) * ax.h;
-    if (y > 0.5 * L)
-      y = y - L;
-    else if (y < -0.5 * L)
-      y = y + L;
-    Y[(long long)a * n + j] = y;
+    int i = (int)floor(mid / ax.h[0]);
+    idx[a] = min(max(i, 0), ax.nc[0][a] - 1);
+    M[(long long)a * n + j] = mid;
     D[(long long)a * n + j] = d;
   }
-  const int key = (idx[2] * ax.nc[1] + idx[1]) * ax.nc[0] + idx[0];
+  int key;
+  if (ax.levels == 1) {
+    key = (idx[2] * ax.nc[0][1] + idx[1]) * ax.nc[0][0] + idx[0];
+  } else {
+    const int t = ((idx[2] >> 1) * ax.nc[1][1] + (idx[1] >> 1)) * ax.nc[1][0] + (idx[0] >> 1);
+    key = t * 8 + ((idx[0] & 1) | ((idx[1] & 1) << 1) | ((idx[2] & 1) << 2));
+  }
   keys[j] = (uint32_t)key;
   kidx[j] = key;
   vals[j] = j;
@@ -177,57 +206,15 @@ __device__ inline int lower_bound_u32(const uint32_t* a, int n, uint32_t v) {
   return lo;
 }
 
-__global__ void k_ff_bounds(const uint32_t* __restrict__ sk, int n, int C,
+// Level records cover the sorted keys [c << shift, (c + 1) << shift).
+__global__ void k_ff_bounds(const uint32_t* __restrict__ sk, int n, int C, int shift,
                             FfCell* __restrict__ cells) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
-  const int lo = lower_bound_u32(sk, n, (uint32_t)c);
-  const int hi = lower_bound_u32(sk, n, (uint32_t)c + 1u);
+  const int lo = lower_bound_u32(sk, n, (uint32_t)c << shift);
+  const int hi = lower_bound_u32(sk, n, ((uint32_t)c + 1u) << shift);
   cells[c].start = lo;
   cells[c].count = hi - lo;
-}
-
-// One thread per cell: radius, grid centre and the extremes of the start
-// offsets (the moments come from the prefix sums).
-__global__ void k_ff_cell(const int32_t* __restrict__ so, const double* __restrict__ Y,
-                          const double* __restrict__ D, const uint32_t* __restrict__ X, int n,
-                          FfAxes ax, FfCell* __restrict__ cells) {
-#pragma clang fp contract(off)
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ax.C) return;
-  const int s = cells[c].start, e = s + cells[c].count;
-  const int ci[3] = {c % ax.nc[0], (c / ax.nc[0]) % ax.nc[1], c / (ax.nc[0] * ax.nc[1])};
-  double cen[3];
-  uint32_t xc[3];
-  for (int a = 0; a < 3; ++a) {
-    cen[a] = ((double)ci[a] + 0.5) * ax.h;
-    xc[a] = (uint32_t)(long long)floor(cen[a] * ax.q[a]);
-  }
-  double rad = 0.0;
-  int dmin[3] = {0, 0, 0}, dmax[3] = {0, 0, 0};
-  for (int p = s; p < e; ++p) {
-    const int k = so[p];
-    double y[3], d[3];
-    for (int a = 0; a < 3; ++a) {
-      y[a] = Y[(long long)a * n + k];
-      d[a] = D[(long long)a * n + k];
-      const int dl = (int)(X[(long long)a * n + k] - xc[a]);
-      dmin[a] = p == s ? dl : min(dmin[a], dl);
-      dmax[a] = p == s ? dl : max(dmax[a], dl);
-    }
-    const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    rad = fmax(rad, ny + 0.5 * nd);
-  }
-  FfCell& o = cells[c];
-  o.rad2 = rad * rad;
-  for (int a = 0; a < 3; ++a) {
-    o.c[a] = cen[a];
-    o.xc[a] = xc[a];
-    o.dmin[a] = dmin[a];
-    o.dmax[a] = dmax[a];
-  }
-  o.pad = 0;
 }
 
 // Per sorted position: the direct loop's segment record.
@@ -253,63 +240,116 @@ __global__ void k_ff_seg(const int32_t* __restrict__ so, const uint32_t* __restr
   recs[p] = r;
 }
 
-// Per (sorted position, axis): rank of the segment's start offset inside
-// its cell (ties by position), giving each cell's segments in ascending
-// offset order: sdel (the offsets) and sidx (the segment indices).
-__global__ void k_ff_rank(const uint32_t* __restrict__ sk, const int32_t* __restrict__ so,
-                          const uint32_t* __restrict__ X, const FfCell* __restrict__ cells,
-                          int n, int32_t* __restrict__ sdel, int32_t* __restrict__ sidx) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3LL * n) return;
-  const int a = (int)(t / n), p = (int)(t - (long long)a * n);
-  const int c = (int)sk[p];
-  const int s = cells[c].start, e = s + cells[c].count;
-  const uint32_t xc = cells[c].xc[a];
-  const uint32_t* Xa = X + (long long)a * n;
-  const int dp = (int)(Xa[so[p]] - xc);
-  int rank = 0;
-  for (int q = s; q < e; ++q) {
-    const int dq = (int)(Xa[so[q]] - xc);
-    rank += (dq < dp || (dq == dp && q < p)) ? 1 : 0;
-  }
-  sdel[(long long)a * n + s + rank] = dp;
-  sidx[(long long)a * n + s + rank] = so[p];
+__device__ inline double ff_lane_d(double x, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), k);
+  return __hiloint2double(hi, lo);
 }
 
-// Per (cell, axis, component): prefix sums (FP64, stored FP32) of the
-// component over the cell's segments in ascending offset order on the
-// axis; rows a (n + C) + start + c + i for i = 0..count (row 0 is zero).
-// The axis-0 totals are the cell's moments.
-__global__ void k_ff_prefix(FfCell* __restrict__ cells, const int32_t* __restrict__ sidx,
-                            const double* __restrict__ Y, const double* __restrict__ D, int n,
-                            int C, float* __restrict__ pre) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3LL * kMom * C) return;
-  const int comp = (int)(t % kMom);
-  const long long ca = t / kMom;
-  const int a = (int)(ca % 3), c = (int)(ca / 3);
+// One wave (a block of 64) per (cell of a level, axis): the cell's start
+// offsets on the axis in ascending order (ties by sorted position) with
+// their segment indices (sdel, sidx), the prefix sums of the 36 moment
+// components over that order (FP64 sums stored FP32, rows
+// a (n + C) + start + c + i for i = 0 .. count, row 0 zero), and the
+// record's fields for the axis (centre, grid centre, offset extremes); the
+// axis-0 wave also writes the radius and the moments (its prefix totals).
+// Segments are taken 64 at a time into registers and broadcast with
+// readlane, so no load waits inside the pairwise loops.
+__global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
+                                                 const double* __restrict__ M,
+                                                 const double* __restrict__ D,
+                                                 const uint32_t* __restrict__ X, int n, FfAxes ax,
+                                                 int level, FfCell* __restrict__ cells,
+                                                 int32_t* __restrict__ sdel,
+                                                 int32_t* __restrict__ sidx,
+                                                 float* __restrict__ pre) {
+#pragma clang fp contract(off)
+  const int c = blockIdx.x / 3, a = blockIdx.x - 3 * (blockIdx.x / 3);
+  const int lane = threadIdx.x;
+  const int C = ax.C[level];
   const int s = cells[c].start, cnt = cells[c].count;
-  float* row = pre + ((long long)a * (n + C) + s + c) * kMom + comp;
-  double acc = 0.0;
-  row[0] = 0.f;
-  for (int i = 0; i < cnt; ++i) {
-    const int k = sidx[(long long)a * n + s + i];
-    double y[3], d[3];
-    for (int b = 0; b < 3; ++b) {
-      y[b] = Y[(long long)b * n + k];
-      d[b] = D[(long long)b * n + k];
+  int ci[3];
+  ff_coords(ax, level, c, ci);
+  double cen[3];
+  for (int b = 0; b < 3; ++b) cen[b] = ((double)ci[b] + 0.5) * ax.h[level];
+  const uint32_t xc = (uint32_t)(long long)floor(cen[a] * ax.q[a]);
+  const uint32_t* Xa = X + (long long)a * n;
+  int32_t* sd = sdel + (long long)a * n + s;
+  int32_t* si = sidx + (long long)a * n + s;
+  int dmn = 0x7fffffff, dmx = -0x7fffffff - 1;
+  for (int b0 = 0; b0 < cnt; b0 += 64) {
+    const int i = b0 + lane;
+    const bool vi = i < cnt;
+    const int ki = vi ? so[s + i] : 0;
+    const int di = vi ? (int)(Xa[ki] - xc) : 0;
+    if (vi) {
+      dmn = min(dmn, di);
+      dmx = max(dmx, di);
     }
-    acc = acc + comp_value(comp, y, d);
-    row[(long long)(i + 1) * kMom] = (float)acc;
+    int rank = 0;
+    for (int j0 = 0; j0 < cnt; j0 += 64) {
+      const int jj = j0 + lane;
+      const int dj = jj < cnt ? (int)(Xa[so[s + jj]] - xc) : 0;
+      const int m = min(64, cnt - j0);
+      for (int k = 0; k < m; ++k) {
+        const int dk = __builtin_amdgcn_readlane(dj, k);
+        rank += (dk < di || (dk == di && j0 + k < i)) ? 1 : 0;
+      }
+    }
+    if (vi) {
+      sd[rank] = di;
+      si[rank] = ki;
+    }
   }
-  if (a == 0) cells[c].m[comp] = (float)acc;
+  for (int off = 32; off > 0; off >>= 1) {
+    dmn = min(dmn, __shfl_xor(dmn, off));
+    dmx = max(dmx, __shfl_xor(dmx, off));
+  }
+  __syncthreads();  // the sorted order, written above, is read below
+  float* row = pre + ((long long)a * (n + C) + s + c) * kMom;
+  if (lane < kMom) row[lane] = 0.f;
+  double acc = 0.0, rad = 0.0;
+  for (int b0 = 0; b0 < cnt; b0 += 64) {
+    const int i = b0 + lane;
+    double y[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+    if (i < cnt) {
+      const int k = si[i];
+      for (int b = 0; b < 3; ++b) {
+        y[b] = ff_min_image(M[(long long)b * n + k] - cen[b], ax.L[b]);
+        d[b] = D[(long long)b * n + k];
+      }
+      const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+      const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      rad = fmax(rad, ny + 0.5 * nd);
+    }
+    const int m = min(64, cnt - b0);
+    for (int k = 0; k < m; ++k) {
+      double yk[3], dk[3];
+      for (int b = 0; b < 3; ++b) {
+        yk[b] = ff_lane_d(y[b], k);
+        dk[b] = ff_lane_d(d[b], k);
+      }
+      if (lane < kMom) {
+        acc = acc + comp_value(lane, yk, dk);
+        row[(long long)(b0 + k + 1) * kMom + lane] = (float)acc;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
+  FfCell& o = cells[c];
+  if (lane == 0) {
+    o.c[a] = cen[a];
+    o.xc[a] = xc;
+    o.dmin[a] = cnt > 0 ? dmn : 0;
+    o.dmax[a] = cnt > 0 ? dmx : 0;
+    if (a == 0) {
+      o.rad2 = rad * rad;
+      o.pad = 0;
+    }
+  }
+  if (a == 0 && lane < kMom) o.m[lane] = (float)acc;
 }
 
-// Velocity times 4 pi (no kappa) at R = target - centre of the moments m
-// (module comment), accumulated into v:
-//   v += (M0 x R - A) / r^3 + W x R - 3 B / r^5,
-//   W_n = (3 (M1 R)_n - 3/2 tr_n) / r^5 + 15/2 (R M2_n R) / r^7,
-//   B_m = eps_mnp (M2_n R)_p.
 // Moments: one array, or the difference of two (the upper class of a split
 // cell: the cell's totals minus the prefix of the lower class).
 struct MomA {
@@ -458,13 +498,91 @@ __device__ inline bool ff_other(const FfHead* cm, const FfDecision& o, const dou
   return d2 * ax.th2 >= cm->rad2;
 }
 
+// Far and split contributions of one cell for the active lanes; returns
+// whether this lane opens the cell (active, neither far nor split).
+__device__ inline bool ff_cell_eval(const FfHead& hc, const FfCell* __restrict__ cm, int c,
+                                    const int32_t* __restrict__ sdel,
+                                    const float* __restrict__ pre, int n, int C, bool active,
+                                    const double* r, const uint32_t* xt, const FfAxes& ax,
+                                    float& fx, float& fy, float& fz) {
+  FfDecision dc;
+  ff_decide(&hc, r, xt, ax, dc);
+  const bool far = active && dc.ncross == 0 && dc.ok0;
+  bool split = false;
+  double R1[3] = {0.0, 0.0, 0.0};
+  if (active && dc.ncross == 1 && dc.ok0) split = ff_other(&hc, dc, r, ax, R1);
+  if (__any(far)) {
+    if (far)
+      m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{cm->m}, fx, fy, fz);
+  }
+  if (__any(split)) {
+    if (split) {
+      // offsets below the crossing: u + delta < 2^31
+      const int a = dc.axis;
+      const uint32_t u = hc.xc[a] - xt[a];
+      const int db = (int)(0x80000000u - u);
+      const int32_t* dl = sdel + (long long)a * n + hc.start;
+      int lo = 0, hi = hc.count;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dl[mid] < db)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const float* pr = pre + ((long long)a * (n + C) + hc.start + c + lo) * kMom;
+      m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{pr}, fx, fy, fz);
+      m2p_f32((float)-R1[0], (float)-R1[1], (float)-R1[2], MomD{cm->m, pr}, fx, fy, fz);
+    }
+  }
+  return active && !far && !split;
+}
+
+// The exact pairs of a finest cell for the lanes in `near`; the target's
+// own two segments excluded where the cell holds them (kCheck).  The
+// cell's records are staged 64 at a time in the wave's own LDS slots
+// (lds, 64 records) and read back with broadcast LDS loads, so the loop
+// waits on no scalar load.
+template <bool kUniform, bool kCheck>
+__device__ inline void ff_direct_loop(int s0, int e, const FfSeg* __restrict__ recs,
+                                      FfSeg* lds, bool near, int jj, int pj, const uint32_t* xt,
+                                      const FfAxes& ax, float& dx, float& dy, float& dz) {
+  const int lane = threadIdx.x & 63;
+  for (int c0 = s0; c0 < e; c0 += 64) {
+    const int m = min(64, e - c0);
+    if (lane < m) lds[lane] = recs[c0 + lane];
+    __builtin_amdgcn_wave_barrier();
+    for (int k = 0; k < m; ++k) {
+      const FfSeg g = lds[k];
+      if (near)
+        ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz,
+                          kCheck && (g.idx == jj || g.idx == pj));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 template <bool kUniform>
+__device__ inline void ff_direct(const FfHead& hc, int c, const FfSeg* __restrict__ recs,
+                                 FfSeg* lds, bool near, int kj, int kp, int jj, int pj,
+                                 const uint32_t* xt, const FfAxes& ax, float& dx, float& dy,
+                                 float& dz) {
+  const int s0 = hc.start, e = hc.start + hc.count;
+  if (__any(kj == c || kp == c))
+    ff_direct_loop<kUniform, true>(s0, e, recs, lds, near, jj, pj, xt, ax, dx, dy, dz);
+  else
+    ff_direct_loop<kUniform, false>(s0, e, recs, lds, near, jj, pj, xt, ax, dx, dy, dz);
+}
+
+template <bool kUniform, int kLevels>
 __global__ __launch_bounds__(256) void k_ff_eval(
-    const FfCell* __restrict__ cells, const FfSeg* __restrict__ recs,
-    const int32_t* __restrict__ so, const int32_t* __restrict__ kidx,
-    const int32_t* __restrict__ prv, const double* __restrict__ Pw,
-    const uint32_t* __restrict__ X, const int32_t* __restrict__ sdel,
-    const float* __restrict__ pre, int n, int S, FfAxes ax, float* __restrict__ Pout) {
+    const FfCell* __restrict__ cells0, const FfCell* __restrict__ cells1,
+    const FfSeg* __restrict__ recs, const int32_t* __restrict__ so,
+    const int32_t* __restrict__ kidx, const int32_t* __restrict__ prv,
+    const double* __restrict__ Pw, const uint32_t* __restrict__ X,
+    const int32_t* __restrict__ sdel0, const int32_t* __restrict__ sdel1,
+    const float* __restrict__ pre0, const float* __restrict__ pre1, int n, int S, FfAxes ax,
+    float* __restrict__ Pout) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = blockIdx.x * kFfTargets + lane;
@@ -481,65 +599,43 @@ __global__ __launch_bounds__(256) void k_ff_eval(
   const int jj = valid ? j : -1;
   const int kj = valid ? kidx[j] : -1;
   const int kp = valid ? kidx[pj] : -1;
-  float fx = 0.f, fy = 0.f, fz = 0.f;  // far part (lattice units)
-  float dx = 0.f, dy = 0.f, dz = 0.f;  // direct part (grid units when uniform)
-  const int C = ax.C;
+  float fx = 0.f, fy = 0.f, fz = 0.f;  // expansions (lattice units)
+  float dx = 0.f, dy = 0.f, dz = 0.f;  // direct pairs (grid units when uniform)
+  const FfCell* __restrict__ top = kLevels == 2 ? cells1 : cells0;
+  const int32_t* __restrict__ sdt = kLevels == 2 ? sdel1 : sdel0;
+  const float* __restrict__ prt = kLevels == 2 ? pre1 : pre0;
+  const int Ct = ax.C[kLevels - 1];
   const int step = 4 * S;
+  __shared__ FfSeg stage[4][64];  // each wave's staged segment records
+  FfSeg* lds = stage[w];
   int c = blockIdx.y * 4 + w;
   FfHead hc;
-  if (c < C) ff_head(cells + c, hc);
-  for (; c < C; c += step) {
+  if (c < Ct) ff_head(top + c, hc);
+  for (; c < Ct; c += step) {
     // the next cell's decision fields are loaded while this one is summed
     FfHead hn;
-    if (c + step < C) ff_head(cells + c + step, hn);
-    const FfCell* __restrict__ cm = cells + c;
-    const int cnt = hc.count;
-    if (cnt > 0) {
-      FfDecision dc;
-      ff_decide(&hc, r, xt, ax, dc);
-      const bool far = valid && dc.ncross == 0 && dc.ok0;
-      bool split = false;
-      double R1[3] = {0.0, 0.0, 0.0};
-      if (valid && dc.ncross == 1 && dc.ok0) split = ff_other(&hc, dc, r, ax, R1);
-      const bool near = valid && !far && !split;
-      if (__any(far)) {
-        if (far)
-          m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{cm->m}, fx, fy, fz);
-      }
-      if (__any(split)) {
-        if (split) {
-          // offsets below the crossing: u + delta < 2^31
-          const int a = dc.axis;
-          const uint32_t u = hc.xc[a] - xt[a];
-          const int db = (int)(0x80000000u - u);
-          const int32_t* dl = sdel + (long long)a * n + hc.start;
-          int lo = 0, hi = cnt;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (dl[mid] < db)
-              lo = mid + 1;
-            else
-              hi = mid;
+    if (c + step < Ct) ff_head(top + c + step, hn);
+    if (hc.count > 0) {
+      const bool open =
+          ff_cell_eval(hc, top + c, c, sdt, prt, n, Ct, valid, r, xt, ax, fx, fy, fz);
+      if (kLevels == 1) {
+        if (__any(open))
+          ff_direct<kUniform>(hc, c, recs, lds, open, kj, kp, jj, pj, xt, ax, dx, dy, dz);
+      } else if (__any(open)) {
+        // the children, each child's decision fields loaded one child ahead
+        FfHead hf;
+        ff_head(cells0 + c * 8, hf);
+        for (int ch = 0; ch < 8; ++ch) {
+          const int f = c * 8 + ch;
+          FfHead hfn;
+          if (ch < 7) ff_head(cells0 + f + 1, hfn);
+          if (hf.count > 0) {
+            const bool near = ff_cell_eval(hf, cells0 + f, f, sdel0, pre0, n, ax.C[0], open, r,
+                                           xt, ax, fx, fy, fz);
+            if (__any(near))
+              ff_direct<kUniform>(hf, f, recs, lds, near, kj, kp, jj, pj, xt, ax, dx, dy, dz);
           }
-          const float* pr = pre + ((long long)a * (n + C) + hc.start + c + lo) * kMom;
-          m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{pr}, fx, fy, fz);
-          m2p_f32((float)-R1[0], (float)-R1[1], (float)-R1[2], MomD{cm->m, pr}, fx, fy, fz);
-        }
-      }
-      if (__any(near)) {
-        const int s0 = hc.start;
-        const bool own = __any(kj == c || kp == c);
-        if (own) {
-          for (int p = s0; p < s0 + cnt; ++p) {
-            const FfSeg g = recs[p];
-            if (near)
-              ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, g.idx == jj || g.idx == pj);
-          }
-        } else {
-          for (int p = s0; p < s0 + cnt; ++p) {
-            const FfSeg g = recs[p];
-            if (near) ff_pair<kUniform>(g, xt[0], xt[1], xt[2], ax, dx, dy, dz, false);
-          }
+          hf = hfn;
         }
       }
     }
@@ -586,12 +682,14 @@ __global__ void k_ff_sum(const float* __restrict__ P, int S, int n, double scale
 FfAxes ff_axes(const vlb_bs_desc* d, const vlb_ff_params* p) {
   FfAxes ax{};
   const int nn[3] = {d->nx, d->ny, d->nz};
+  ax.levels = p->levels == 2 ? 2 : 1;
   bool uniform = true;
   for (int a = 0; a < 3; ++a) {
     ax.L[a] = (double)nn[a];
     ax.q[a] = 4294967296.0 / (double)nn[a];
     ax.iqf[a] = (float)((double)nn[a] / 4294967296.0);
-    ax.nc[a] = nn[a] / p->cell;
+    ax.nc[0][a] = nn[a] / p->cell;
+    ax.nc[1][a] = ax.levels == 2 ? nn[a] / (2 * p->cell) : 0;
     uniform = uniform && nn[a] == nn[0];
   }
   // one grid step for all axes: equal power-of-two lengths
@@ -599,16 +697,17 @@ FfAxes ff_axes(const vlb_bs_desc* d, const vlb_ff_params* p) {
   uniform = uniform && std::frexp((double)nn[0], &ex) == 0.5;
   ax.uniform = uniform ? 1 : 0;
   ax.qf = (float)ax.q[0];
-  ax.h = (double)p->cell;
+  ax.h[0] = (double)p->cell;
+  ax.h[1] = 2.0 * p->cell;
   ax.th2 = p->theta * p->theta;
-  ax.C = ax.nc[0] * ax.nc[1] * ax.nc[2];
+  for (int l = 0; l < 2; ++l) ax.C[l] = ax.nc[l][0] * ax.nc[l][1] * ax.nc[l][2];
   return ax;
 }
 
-int ff_chunks(long long n, int C) {
+int ff_chunks(long long n, int Ctop) {
   const long long tb = (n + kFfTargets - 1) / kFfTargets;
   long long S = (8192 + tb - 1) / tb;
-  if (S > C / 4) S = C / 4;
+  if (S > Ctop / 4) S = Ctop / 4;
   if (S > 64) S = 64;
   if (S < 1) S = 1;
   return (int)S;
@@ -620,7 +719,7 @@ struct FfBufs {
   uint32_t* X;
   int32_t* nxt;
   int32_t* prv;
-  double* Y;
+  double* M;
   double* D;
   uint32_t* ka;
   uint32_t* kb;
@@ -628,16 +727,16 @@ struct FfBufs {
   int32_t* vb;
   int32_t* kidx;
   void* stmp;
-  FfCell* cells;
   FfSeg* recs;
-  int32_t* sdel;
-  int32_t* sidx;
-  float* pre;
+  FfCell* cells[2];
+  int32_t* sdel[2];
+  int32_t* sidx[2];
+  float* pre[2];
   float* P;
   int S;
 };
 
-size_t ff_layout(long long n, int C, char* base, FfBufs* b) {
+size_t ff_layout(long long n, const FfAxes& ax, char* base, FfBufs* b) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
     off = (off + 255) / 256 * 256;
@@ -646,13 +745,13 @@ size_t ff_layout(long long n, int C, char* base, FfBufs* b) {
     return q;
   };
   FfBufs s{};
-  s.S = ff_chunks(n, C);
+  s.S = ff_chunks(n, ax.C[ax.levels - 1]);
   s.cnt = (int32_t*)take(32 * sizeof(int32_t));
   s.Pw = (double*)take(3 * (size_t)n * sizeof(double));
   s.X = (uint32_t*)take(3 * (size_t)n * sizeof(uint32_t));
   s.nxt = (int32_t*)take((size_t)n * sizeof(int32_t));
   s.prv = (int32_t*)take((size_t)n * sizeof(int32_t));
-  s.Y = (double*)take(3 * (size_t)n * sizeof(double));
+  s.M = (double*)take(3 * (size_t)n * sizeof(double));
   s.D = (double*)take(3 * (size_t)n * sizeof(double));
   s.ka = (uint32_t*)take((size_t)n * sizeof(uint32_t));
   s.kb = (uint32_t*)take((size_t)n * sizeof(uint32_t));
@@ -660,11 +759,20 @@ size_t ff_layout(long long n, int C, char* base, FfBufs* b) {
   s.vb = (int32_t*)take((size_t)n * sizeof(int32_t));
   s.kidx = (int32_t*)take((size_t)n * sizeof(int32_t));
   s.stmp = take(sort_tmp_bytes(n));
-  s.cells = (FfCell*)take((size_t)C * sizeof(FfCell));
   s.recs = (FfSeg*)take((size_t)n * sizeof(FfSeg));
-  s.sdel = (int32_t*)take(3 * (size_t)n * sizeof(int32_t));
-  s.sidx = (int32_t*)take(3 * (size_t)n * sizeof(int32_t));
-  s.pre = (float*)take(3 * ((size_t)n + C) * kMom * sizeof(float));
+  for (int l = 0; l < ax.levels; ++l) {
+    const size_t C = (size_t)ax.C[l];
+    s.cells[l] = (FfCell*)take(C * sizeof(FfCell));
+    s.sdel[l] = (int32_t*)take(3 * (size_t)n * sizeof(int32_t));
+    s.sidx[l] = (int32_t*)take(3 * (size_t)n * sizeof(int32_t));
+    s.pre[l] = (float*)take(3 * ((size_t)n + C) * kMom * sizeof(float));
+  }
+  if (ax.levels == 1) {
+    s.cells[1] = s.cells[0];
+    s.sdel[1] = s.sdel[0];
+    s.sidx[1] = s.sidx[0];
+    s.pre[1] = s.pre[0];
+  }
   s.P = (float*)take((size_t)s.S * 3 * n * sizeof(float));
   if (b) *b = s;
   return (off + 255) / 256 * 256;
@@ -679,8 +787,11 @@ int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::strin
   if (d->wall_axes != 0) { msg = "the far-field sum needs a periodic box (wall_axes 0)"; return VLB_EINVAL; }
   if (d->precision != VLB_F32) { msg = "the far-field sum is FP32 (precision VLB_F32)"; return VLB_EINVAL; }
   if (!(p->theta > 0.0 && p->theta < 1.0)) { msg = "theta must lie in (0, 1)"; return VLB_EINVAL; }
-  if (p->cell < 1 || d->nx % p->cell || d->ny % p->cell || d->nz % p->cell) {
-    msg = "the cell edge must be >= 1 and divide nx, ny and nz";
+  if (p->levels < 0 || p->levels > 2) { msg = "levels must be 0, 1 or 2"; return VLB_EINVAL; }
+  const int top = p->levels == 2 ? 2 * p->cell : p->cell;
+  if (p->cell < 1 || d->nx % top || d->ny % top || d->nz % top) {
+    msg = p->levels == 2 ? "the cell edge must be >= 1 and twice it divide nx, ny and nz"
+                         : "the cell edge must be >= 1 and divide nx, ny and nz";
     return VLB_EINVAL;
   }
   const long long C = (long long)(d->nx / p->cell) * (d->ny / p->cell) * (d->nz / p->cell);
@@ -689,43 +800,43 @@ int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::strin
 }
 
 size_t ff_workspace(const vlb_bs_desc* d, const vlb_ff_params* p, long long n) {
-  const int C = (d->nx / p->cell) * (d->ny / p->cell) * (d->nz / p->cell);
-  return ff_layout(n, C, nullptr, nullptr);
+  return ff_layout(n, ff_axes(d, p), nullptr, nullptr);
 }
 
 hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, const double* xyz,
                    const int32_t* next, double* v, void* ws, hipStream_t stream) {
   const FfAxes ax = ff_axes(d, p);
   FfBufs b;
-  ff_layout(n, ax.C, (char*)ws, &b);
+  ff_layout(n, ax, (char*)ws, &b);
   const int nb = (int)((n + 255) / 256);
   hipLaunchKernelGGL(k_ff_init, dim3(nb), dim3(256), 0, stream, b.prv, (int)n);
   hipLaunchKernelGGL(k_ff_prep, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n, ax, b.cnt, b.Pw,
-                     b.X, b.nxt, b.prv, b.Y, b.D, b.ka, b.kidx, b.va);
+                     b.X, b.nxt, b.prv, b.M, b.D, b.ka, b.kidx, b.va);
   int bits = 1;
-  while ((1LL << bits) < ax.C) ++bits;
+  while ((1LL << bits) < ax.C[0]) ++bits;
   uint32_t* sk = nullptr;
   int32_t* so = nullptr;
   hipError_t e = sort_pairs_raw(n, bits, 0, b.stmp, b.ka, b.kb, b.va, b.vb, stream, &sk, &so);
   if (e != hipSuccess) return e;
-  const int cb = (ax.C + 255) / 256;
-  hipLaunchKernelGGL(k_ff_bounds, dim3(cb), dim3(256), 0, stream, sk, (int)n, ax.C, b.cells);
-  hipLaunchKernelGGL(k_ff_cell, dim3(cb), dim3(256), 0, stream, so, b.Y, b.D, b.X, (int)n, ax,
-                     b.cells);
   hipLaunchKernelGGL(k_ff_seg, dim3(nb), dim3(256), 0, stream, so, b.X, b.nxt, (int)n, ax, b.recs);
-  const long long nr = 3LL * n;
-  hipLaunchKernelGGL(k_ff_rank, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, sk, so,
-                     b.X, b.cells, (int)n, b.sdel, b.sidx);
-  const long long np = 3LL * kMom * ax.C;
-  hipLaunchKernelGGL(k_ff_prefix, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,
-                     b.cells, b.sidx, b.Y, b.D, (int)n, ax.C, b.pre);
+  for (int l = 0; l < ax.levels; ++l) {
+    const int C = ax.C[l];
+    hipLaunchKernelGGL(k_ff_bounds, dim3((C + 255) / 256), dim3(256), 0, stream, sk, (int)n, C,
+                       3 * l, b.cells[l]);
+    hipLaunchKernelGGL(k_ff_order, dim3((unsigned)(3 * C)), dim3(64), 0, stream, so, b.M, b.D,
+                       b.X, (int)n, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
+  }
   const dim3 grid((unsigned)((n + kFfTargets - 1) / kFfTargets), b.S);
-  if (ax.uniform)
-    hipLaunchKernelGGL(k_ff_eval<true>, grid, dim3(256), 0, stream, b.cells, b.recs, so, b.kidx,
-                       b.prv, b.Pw, b.X, b.sdel, b.pre, (int)n, b.S, ax, b.P);
-  else
-    hipLaunchKernelGGL(k_ff_eval<false>, grid, dim3(256), 0, stream, b.cells, b.recs, so, b.kidx,
-                       b.prv, b.Pw, b.X, b.sdel, b.pre, (int)n, b.S, ax, b.P);
+#define FF_EVAL(U, LV)                                                                         \
+  hipLaunchKernelGGL((k_ff_eval<U, LV>), grid, dim3(256), 0, stream, b.cells[0], b.cells[1],   \
+                     b.recs, so, b.kidx, b.prv, b.Pw, b.X, b.sdel[0], b.sdel[1], b.pre[0],     \
+                     b.pre[1], (int)n, b.S, ax, b.P)
+  if (ax.uniform) {
+    if (ax.levels == 2) FF_EVAL(true, 2); else FF_EVAL(true, 1);
+  } else {
+    if (ax.levels == 2) FF_EVAL(false, 2); else FF_EVAL(false, 1);
+  }
+#undef FF_EVAL
   hipLaunchKernelGGL(k_ff_sum, dim3(nb), dim3(256), 0, stream, b.P, b.S, (int)n,
                      d->kappa / (4.0 * M_PI), v);
   return hipGetLastError();

@@ -173,12 +173,12 @@ def test_biot_savart_null_pointers_rejected():
     assert "null" in lib.vlb_last_error(None).decode()
 
 
-def _ff_query(n, cell=8, theta=0.5, **kw):
+def _ff_query(n, cell=8, theta=0.5, levels=1, **kw):
     lib = vlb.load_library()
     args = dict(dims=(32, 32, 32), walls=(False, False, False), kappa=0.1, precision="f32")
     args.update(kw)
     d = vlb.bs_desc(**args)
-    p = vlb.FfParams(cell, 0, theta)
+    p = vlb.FfParams(cell, levels, theta)
     nb = ctypes.c_uint64(0)
     code = lib.vlb_biot_savart_farfield_workspace(ctypes.byref(d), ctypes.byref(p), n,
                                                   ctypes.byref(nb))
@@ -190,8 +190,10 @@ def test_farfield_workspace_query():
     assert code == vlb.VLB_OK and small > 1000 * 600
     code, big, _ = _ff_query(100000)
     assert code == vlb.VLB_OK and big > 50 * small
-    # finer cells need more (per-cell records and prefix rows)
+    # finer cells need more (per-cell records and prefix rows), and so does
+    # a second level
     assert _ff_query(1000, cell=2)[1] > small
+    assert _ff_query(1000, levels=2)[1] > small
     assert _ff_query(0)[:2] == (vlb.VLB_OK, 0)
     assert ctypes.sizeof(vlb.FfParams) == 16
 
@@ -205,6 +207,8 @@ def test_farfield_workspace_query():
     (dict(cell=0), "divide"),
     (dict(cell=1, dims=(256, 256, 128)), "2^22"),
     (dict(kappa=-1.0), "kappa"),
+    (dict(levels=3), "levels"),
+    (dict(levels=2, cell=8, dims=(32, 32, 24)), "twice"),
 ])
 def test_farfield_invalid_rejected(kw, msg):
     code, _, err = _ff_query(100, **kw)

@@ -43,29 +43,36 @@ def _check(got, ref, tag):
     assert emax <= 5 * TOL
 
 
+@pytest.mark.parametrize("levels", [1, 2])
 @pytest.mark.parametrize("dims,cell,theta", [
     ((64, 64, 64), 16, 0.5), ((64, 64, 64), 8, 0.25), ((64, 64, 64), 8, 0.6),
     ((64, 64, 128), 8, 0.4), ((48, 48, 48), 6, 0.5)])
-def test_farfield_every_target(dims, cell, theta):
+def test_farfield_every_target(dims, cell, theta, levels):
     """Small tangles, every target: 64^3 is a uniform grid (direct pairs in
-    grid units), 64x64x128 and 48^3 are not (lattice units)."""
+    grid units), 64x64x128 and 48^3 are not (lattice units); one level of
+    cells and two."""
     lat, pos, nxt, prv = _tangle(dims, 60, 5)
-    say(f"farfield every target {dims} cell {cell} theta {theta}: {pos.shape[0]} points")
-    got = vlb.biot_savart_farfield(pos, nxt, dims, cell, theta, KAPPA)
-    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, cell, theta)
+    say(f"farfield every target {dims} cell {cell} theta {theta} levels {levels}: "
+        f"{pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, cell, theta, KAPPA, levels=levels)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, cell, theta,
+                                            levels=levels)
     say(f"  oracle far {st['far']:.1f}, split {st['split']:.1f}, direct {st['direct']:.0f}")
     assert st["far"] > 0
     _check(got, ref, "every target")
 
 
-def test_farfield_many_split_cells():
-    """128^3, 8^3 cells, theta 0.25: about 60 split cells per target."""
+@pytest.mark.parametrize("levels", [1, 2])
+def test_farfield_many_split_cells(levels):
+    """128^3, 8^3 cells (and 16^3 above them), theta 0.25: about 60 split
+    cells per target."""
     dims = (128, 128, 128)
     lat, pos, nxt, prv = _tangle(dims, 260, 9)
-    say(f"farfield 128^3 split cells: {pos.shape[0]} points")
-    got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA)
+    say(f"farfield 128^3 split cells, levels {levels}: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA, levels=levels)
     t = np.random.default_rng(3).choice(pos.shape[0], 300, replace=False)
-    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25, targets=t)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25, targets=t,
+                                            levels=levels)
     assert st["split"] > 20
     _check(got[t], ref, "128^3 sampled")
 
@@ -84,10 +91,12 @@ def test_farfield_open_lines_and_split_pin():
     nxt = np.concatenate([np.arange(1, 13), [12], 13 + (np.arange(1, 13) % 12), 25 + nxt_r])
     prv = coupled.prev_from_next(nxt)
     say(f"farfield open chain: {pos.shape[0]} points")
-    got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA)
-    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25)
-    assert st["split"] > 0
-    _check(got, ref, "open chain")
+    for levels in (1, 2):
+        got = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.25, KAPPA, levels=levels)
+        ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 8, 0.25,
+                                                levels=levels)
+        assert st["split"] > 0
+        _check(got, ref, f"open chain, levels {levels}")
 
 
 def test_farfield_deterministic_and_degenerate():
@@ -97,9 +106,10 @@ def test_farfield_deterministic_and_degenerate():
     dims = (32, 32, 32)
     lat, pos, nxt, prv = _tangle(dims, 12, 3, 2.0, 5.0)
     say(f"farfield determinism: {pos.shape[0]} points")
-    a = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA)
-    b = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA)
-    assert np.array_equal(a, b)
+    for levels in (1, 2):
+        a = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA, levels=levels)
+        b = vlb.biot_savart_farfield(pos, nxt, dims, 8, 0.5, KAPPA, levels=levels)
+        assert np.array_equal(a, b)
     one = vlb.biot_savart_farfield(np.array([[1.0, 2.0, 3.0]]), np.array([0]), dims, 8, 0.5, KAPPA)
     assert np.array_equal(one, np.zeros((1, 3)))
     assert vlb.biot_savart_farfield(np.zeros((0, 3)), np.zeros(0, np.int32), dims, 8, 0.5,
@@ -109,21 +119,23 @@ def test_farfield_deterministic_and_degenerate():
     _check(whole, direct, "one cell")
 
 
-def test_farfield_tangle_256_full_size():
-    """The 256^3 tangle (2000 rings, about 1e5 points), 16^3 cells, theta
-    0.25: 64 sampled targets against the oracle of the approximation, and
-    every target against the GPU's direct FP32 sum within the
-    approximation's error (relative L2 <= 1e-3)."""
+@pytest.mark.parametrize("levels", [1, 2])
+def test_farfield_tangle_256_full_size(levels):
+    """The 256^3 tangle (2000 rings, about 1e5 points), 16^3 cells (and
+    32^3 above them), theta 0.25: 64 sampled targets against the oracle of
+    the approximation, and every target against the GPU's direct FP32 sum
+    within the approximation's error (relative L2 <= 1e-3)."""
     cfg = wl.config_tangle()
     dims = (256, 256, 256)
     lat = Lattice(*dims)
     pos = vfm.wrap_positions(cfg["pos"], lat)
     nxt = cfg["nxt"]
     prv = coupled.prev_from_next(nxt)
-    say(f"farfield 256^3 tangle: {pos.shape[0]} points")
-    got = vlb.biot_savart_farfield(pos, nxt, dims, 16, 0.25, KAPPA)
+    say(f"farfield 256^3 tangle, levels {levels}: {pos.shape[0]} points")
+    got = vlb.biot_savart_farfield(pos, nxt, dims, 16, 0.25, KAPPA, levels=levels)
     t = np.random.default_rng(11).choice(pos.shape[0], 64, replace=False)
-    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 16, 0.25, targets=t)
+    ref, st = farfield.biot_savart_farfield(pos, nxt, prv, lat, KAPPA, 16, 0.25, targets=t,
+                                            levels=levels)
     say(f"  oracle far {st['far']:.0f}, split {st['split']:.0f}, direct {st['direct']:.0f}")
     _check(got[t], ref, "256^3 sampled")
     direct = vlb.biot_savart(pos, nxt, dims, kappa=KAPPA, precision="f32")

@@ -246,6 +246,29 @@ __device__ inline double ff_lane_d(double x, int k) {
   return __hiloint2double(hi, lo);
 }
 
+// Per segment, at one level: the 36 moment components about its cell's
+// centre (FP64, row k of comps) and |y| + |d| / 2 (srad).
+__global__ void k_ff_comps(const double* __restrict__ M, const double* __restrict__ D,
+                           const int32_t* __restrict__ kidx, int n, FfAxes ax, int level,
+                           double* __restrict__ comps, double* __restrict__ srad) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int ci[3];
+  ff_coords(ax, level, kidx[k] >> (3 * level), ci);
+  double y[3], d[3];
+  for (int b = 0; b < 3; ++b) {
+    y[b] = ff_min_image(M[(long long)b * n + k] - ((double)ci[b] + 0.5) * ax.h[level], ax.L[b]);
+    d[b] = D[(long long)b * n + k];
+  }
+  double* row = comps + (long long)k * kMom;
+#pragma unroll
+  for (int i = 0; i < kMom; ++i) row[i] = comp_value(i, y, d);
+  const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+  const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  srad[k] = ny + 0.5 * nd;
+}
+
 // One wave (a block of 64) per (cell of a level, axis): the cell's start
 // offsets on the axis in ascending order (ties by sorted position) with
 // their segment indices (sdel, sidx), the prefix sums of the 36 moment
@@ -253,11 +276,12 @@ __device__ inline double ff_lane_d(double x, int k) {
 // a (n + C) + start + c + i for i = 0 .. count, row 0 zero), and the
 // record's fields for the axis (centre, grid centre, offset extremes); the
 // axis-0 wave also writes the radius and the moments (its prefix totals).
-// Segments are taken 64 at a time into registers and broadcast with
-// readlane, so no load waits inside the pairwise loops.
+// The ranks compare offsets held in registers (64 at a time, broadcast
+// with readlane); the prefix sums add the components of k_ff_comps, one
+// lane per component.
 __global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
-                                                 const double* __restrict__ M,
-                                                 const double* __restrict__ D,
+                                                 const double* __restrict__ comps,
+                                                 const double* __restrict__ srad,
                                                  const uint32_t* __restrict__ X, int n, FfAxes ax,
                                                  int level, FfCell* __restrict__ cells,
                                                  int32_t* __restrict__ sdel,
@@ -307,32 +331,14 @@ __global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
   }
   __syncthreads();  // the sorted order, written above, is read below
   float* row = pre + ((long long)a * (n + C) + s + c) * kMom;
-  if (lane < kMom) row[lane] = 0.f;
   double acc = 0.0, rad = 0.0;
-  for (int b0 = 0; b0 < cnt; b0 += 64) {
-    const int i = b0 + lane;
-    double y[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
-    if (i < cnt) {
-      const int k = si[i];
-      for (int b = 0; b < 3; ++b) {
-        y[b] = ff_min_image(M[(long long)b * n + k] - cen[b], ax.L[b]);
-        d[b] = D[(long long)b * n + k];
-      }
-      const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-      const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      rad = fmax(rad, ny + 0.5 * nd);
-    }
-    const int m = min(64, cnt - b0);
-    for (int k = 0; k < m; ++k) {
-      double yk[3], dk[3];
-      for (int b = 0; b < 3; ++b) {
-        yk[b] = ff_lane_d(y[b], k);
-        dk[b] = ff_lane_d(d[b], k);
-      }
-      if (lane < kMom) {
-        acc = acc + comp_value(lane, yk, dk);
-        row[(long long)(b0 + k + 1) * kMom + lane] = (float)acc;
-      }
+  for (int i = lane; i < cnt; i += 64) rad = fmax(rad, srad[so[s + i]]);
+  if (lane < kMom) {
+    row[lane] = 0.f;
+#pragma unroll 8
+    for (int i = 0; i < cnt; ++i) {
+      acc = acc + comps[(long long)si[i] * kMom + lane];
+      row[(long long)(i + 1) * kMom + lane] = (float)acc;
     }
   }
   for (int off = 32; off > 0; off >>= 1) rad = fmax(rad, __shfl_xor(rad, off));
@@ -728,6 +734,8 @@ struct FfBufs {
   int32_t* kidx;
   void* stmp;
   FfSeg* recs;
+  double* comps;  // per segment, one level at a time
+  double* srad;
   FfCell* cells[2];
   int32_t* sdel[2];
   int32_t* sidx[2];
@@ -760,6 +768,8 @@ size_t ff_layout(long long n, const FfAxes& ax, char* base, FfBufs* b) {
   s.kidx = (int32_t*)take((size_t)n * sizeof(int32_t));
   s.stmp = take(sort_tmp_bytes(n));
   s.recs = (FfSeg*)take((size_t)n * sizeof(FfSeg));
+  s.comps = (double*)take((size_t)n * kMom * sizeof(double));
+  s.srad = (double*)take((size_t)n * sizeof(double));
   for (int l = 0; l < ax.levels; ++l) {
     const size_t C = (size_t)ax.C[l];
     s.cells[l] = (FfCell*)take(C * sizeof(FfCell));
@@ -823,8 +833,10 @@ hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, co
     const int C = ax.C[l];
     hipLaunchKernelGGL(k_ff_bounds, dim3((C + 255) / 256), dim3(256), 0, stream, sk, (int)n, C,
                        3 * l, b.cells[l]);
-    hipLaunchKernelGGL(k_ff_order, dim3((unsigned)(3 * C)), dim3(64), 0, stream, so, b.M, b.D,
-                       b.X, (int)n, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
+    hipLaunchKernelGGL(k_ff_comps, dim3(nb), dim3(256), 0, stream, b.M, b.D, b.kidx, (int)n, ax,
+                       l, b.comps, b.srad);
+    hipLaunchKernelGGL(k_ff_order, dim3((unsigned)(3 * C)), dim3(64), 0, stream, so, b.comps,
+                       b.srad, b.X, (int)n, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
   }
   const dim3 grid((unsigned)((n + kFfTargets - 1) / kFfTargets), b.S);
 #define FF_EVAL(U, LV)                                                                         \

@@ -519,7 +519,7 @@ def hbm_copy(torch, nbytes=1 << 30, reps=10):
     return dict(bytes=2 * nbytes, ms=round(ms, 4), GBs=round(gbs, 1), frac=round(gbs / PEAK_HBM_GBS, 4))
 
 
-def farfield_bench(torch, vlb, cfg, cell, theta, reps=10):
+def farfield_bench(torch, vlb, cfg, cell, theta, levels, reps=10):
     """The far-field approximation of the non-local Biot-Savart sum
     (vlb_biot_savart_farfield, reading F2) beside the direct FP32 sum
     (vlb_biot_savart) on the workload's filaments, both through the C ABI
@@ -553,7 +553,7 @@ def farfield_bench(torch, vlb, cfg, cell, theta, reps=10):
                                             vp(q.data_ptr()), vp(v.data_ptr()), vp(wp),
                                             vlb.ctypes.c_uint64(int(nb.value)), vp(s.cuda_stream)))
 
-    ff = vlb.FarField(dims, n, cell, theta, kappa)
+    ff = vlb.FarField(dims, n, cell, theta, kappa, levels=levels)
 
     def far():
         ff.run(p, q, v)
@@ -576,7 +576,8 @@ def farfield_bench(torch, vlb, cfg, cell, theta, reps=10):
     err = float(np.linalg.norm(v_far - v_dir) / np.linalg.norm(v_dir))
     del ws, ff, p, q, v
     torch.cuda.empty_cache()
-    return dict(points=n, cell=cell, theta=theta, cells=int(np.prod([x // cell for x in dims])),
+    return dict(points=n, cell=cell, levels=levels, theta=theta,
+                cells=int(np.prod([x // cell for x in dims])),
                 direct_f32_ms=round(t_dir, 4), farfield_ms=round(t_far, 4),
                 speedup=round(t_dir / t_far, 3), rel_l2_vs_direct=float(f"{err:.3e}"),
                 basis="HIP events around %d calls each, inputs resident on the GPU" % reps)
@@ -637,6 +638,7 @@ def parse_args(argv=None):
                     help="cell edge of the far-field approximation measured beside the direct "
                          "sum (periodic workloads; 0: not measured)")
     ap.add_argument("--ff-theta", type=float, default=0.25)
+    ap.add_argument("--ff-levels", type=int, default=2, choices=(1, 2))
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -787,7 +789,8 @@ def main(argv=None):
         out["lbm_256cubed"] = [lbm_only(256, p) for p in ("f16", "f32", "f64")]
         torch.cuda.empty_cache()
     if args.ff_cell > 0:
-        out["farfield"] = farfield_bench(torch, vlb, cfg, args.ff_cell, args.ff_theta)
+        out["farfield"] = farfield_bench(torch, vlb, cfg, args.ff_cell, args.ff_theta,
+                                         args.ff_levels)
     out["hbm_copy"] = hbm_copy(torch)
     if base is not None:
         out["cpu_baseline"] = base

@@ -115,6 +115,15 @@ typedef struct {
   int32_t reserved1;      /* 0                                              */
   int64_t n_cap;          /* capacity in filament points (>= 1)             */
   int64_t recon_cap;      /* capacity in reconnection candidates per step   */
+  int32_t ff_cell;        /* 0: the non-local sum of every stage is the
+                             direct sum over all segment pairs (Sec. II.A);
+                             > 0: its far-field approximation (the
+                             definition at vlb_biot_savart_farfield) with
+                             cells of this edge, for large tangles; needs a
+                             periodic box, FP32 or FP16 precision and no
+                             wall images                                    */
+  int32_t ff_levels;      /* levels of cells of that approximation (0, 1, 2) */
+  double ff_theta;        /* its opening parameter, 0 < ff_theta < 1        */
 } vlb_vortex_desc;
 
 /* Bytes of device workspace a run with these descriptors needs.           */

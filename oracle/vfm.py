@@ -49,6 +49,12 @@ class VortexParams:
     # superfluid boundary velocity v_s,b from image vortices in the wall
     # planes (reading F1); False: v_s,b = 0 (reading R13)
     wall_images: bool = False
+    # non-local sum: 0 = the direct sum over all segments (Sec. II.A); > 0 =
+    # its cell-multipole approximation with cells of this edge (reading F2,
+    # oracle/farfield.py), ff_levels levels, opening parameter ff_theta
+    ff_cell: int = 0
+    ff_levels: int = 1
+    ff_theta: float = 0.25
 
 
 # ---------------------------------------------------------------- geometry
@@ -448,7 +454,14 @@ def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_fo
     lattice, and ds/dt (Sec. II.A).  ``ub`` is the bare normal-fluid velocity
     field; ``Vs`` the slice superflow (or None)."""
     geo = geometry(pos, nxt, prv, lat)
-    vs = biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa) + lia_velocity(geo, vp)
+    if vp.ff_cell > 0:
+        from .farfield import biot_savart_farfield  # it builds on this module
+
+        nonlocal_v, _ = biot_savart_farfield(pos, nxt, prv, lat, vp.kappa, vp.ff_cell,
+                                             vp.ff_theta, levels=max(vp.ff_levels, 1))
+    else:
+        nonlocal_v = biot_savart_nonlocal(pos, nxt, prv, lat, vp.kappa)
+    vs = nonlocal_v + lia_velocity(geo, vp)
     if vp.wall_images:
         vs = vs + biot_savart_images(pos, nxt, prv, lat, vp.kappa)
     vs = vs + np.array(vp.vs_applied, dtype=np.float64)[None, :]

@@ -68,6 +68,8 @@ class VortexDesc(ctypes.Structure):
         ("mass_balance", ctypes.c_int32), ("force_model", ctypes.c_int32),
         ("wall_images", ctypes.c_int32), ("reserved1", ctypes.c_int32),
         ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
+        ("ff_cell", ctypes.c_int32), ("ff_levels", ctypes.c_int32),
+        ("ff_theta", ctypes.c_double),
     ]
 
 
@@ -188,6 +190,9 @@ def vortex_desc(vor: dict, n_cap: int, recon_cap: int = 1 << 16) -> VortexDesc:
     d.reserved1 = 0
     d.n_cap = int(n_cap)
     d.recon_cap = int(recon_cap)
+    d.ff_cell = int(vor.get("ff_cell", 0))
+    d.ff_levels = int(vor.get("ff_levels", 1))
+    d.ff_theta = float(vor.get("ff_theta", 0.25))
     return d
 
 

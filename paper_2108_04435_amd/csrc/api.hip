@@ -84,6 +84,15 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
   if (vor->mass_balance && (lat->wall_axes & 4u)) { msg = "mass balance needs a periodic z axis"; return VLB_EINVAL; }
   if (vor->force_model != 0 && vor->force_model != 1) { msg = "force_model must be 0 or 1"; return VLB_EINVAL; }
   if (vor->wall_images != 0 && vor->wall_images != 1) { msg = "wall_images must be 0 or 1"; return VLB_EINVAL; }
+  if (vor->ff_cell < 0) { msg = "ff_cell must be >= 0"; return VLB_EINVAL; }
+  if (vor->ff_cell > 0) {
+    if (lat->precision == VLB_F64) { msg = "the far-field sum is FP32: precision VLB_F32 or VLB_F16"; return VLB_EINVAL; }
+    if (vor->wall_images) { msg = "the far-field sum takes no wall images"; return VLB_EINVAL; }
+    vlb_bs_desc bd{lat->nx, lat->ny, lat->nz, lat->wall_axes, VLB_F32, 0, vor->kappa};
+    vlb_ff_params fp{vor->ff_cell, vor->ff_levels, vor->ff_theta};
+    const int c = ff_check(&bd, &fp, vor->n_cap, msg);
+    if (c != VLB_OK) return c;
+  }
   if (vor->reconnect) {
     if (!(vor->reconnect_dist > 0)) { msg = "reconnect_dist must be positive"; return VLB_EINVAL; }
     if (vor->recon_cap < 1 || vor->recon_cap > (1LL << 26)) { msg = "recon_cap must be in [1, 2^26]"; return VLB_EINVAL; }
@@ -133,7 +142,9 @@ size_t layout(Run& r, char* base) {
   r.bsX = (uint32_t*)B.take((size_t)nco * 3 * nc * sizeof(uint32_t));
   r.bsD = B.take((size_t)nco * (r.prec == VLB_F64 ? 6 : 4) * nc * fe);  // FP64: d (3) and residuals (3)
   size_t pbytes = (size_t)nco * r.bsS * 3 * nc * fe;
+  if (r.vor.ff_cell > 0 && (size_t)r.ffS * 3 * nc * fe > pbytes) pbytes = (size_t)r.ffS * 3 * nc * fe;
   r.bsP = B.take(pbytes);
+  r.ffws = r.vor.ff_cell > 0 ? B.take(ff_run_bytes(r)) : nullptr;
   r.bsown = nco > 1 ? (int32_t*)B.take(nc * sizeof(int32_t)) : nullptr;
   r.cnt = (int32_t*)B.take(32 * sizeof(int32_t));
   r.marked = (uint32_t*)B.take(nc * sizeof(uint32_t));
@@ -198,6 +209,7 @@ void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   const int n[3] = {g.nx, g.ny, g.nz};
   r.bsax = bs_make_axes(n, g.wall, vor->wall_images != 0);
   r.bsS = bs_chunks(r.ncap);
+  r.ffS = vor->ff_cell > 0 ? ff_run_chunks(r) : 0;
   // spreading bins: lower stencil corner, n (+1 on wall axes) per axis
   const unsigned long long ext = (unsigned long long)(n[0] + g.wall[0]) * (n[1] + g.wall[1]) * (n[2] + g.wall[2]);
   r.key_bits = bits_for(ext);  // pad key 2^bits - 1 >= ext
@@ -538,8 +550,12 @@ int one_step(vlb_run* h, bool first, bool last) {
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
     // for stage 1, the previous finalize for stages 2-4)
-    if (r.prec == VLB_F64 || r.bsax.copies > 1) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
-    HIP_OR_FAIL(h, bs_sum(r));
+    if (r.vor.ff_cell > 0) {
+      HIP_OR_FAIL(h, ff_run_sum(r, Ys[s]));
+    } else {
+      if (r.prec == VLB_F64 || r.bsax.copies > 1) HIP_OR_FAIL(h, bs_prep(r, Ys[s]));
+      HIP_OR_FAIL(h, bs_sum(r));
+    }
     // the first finalize reads the velocity field and the superflow
     if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
     HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
@@ -689,8 +705,12 @@ int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, dou
   if (!h) return fail(nullptr, VLB_EINVAL, "run is NULL");
   Run& r = h->r;
   HIP_OR_FAIL(h, lbm_moments(r));
-  HIP_OR_FAIL(h, bs_prep(r, r.pos));
-  HIP_OR_FAIL(h, bs_sum(r));
+  if (r.vor.ff_cell > 0) {
+    HIP_OR_FAIL(h, ff_run_sum(r, r.pos));
+  } else {
+    HIP_OR_FAIL(h, bs_prep(r, r.pos));
+    HIP_OR_FAIL(h, bs_sum(r));
+  }
   HIP_OR_FAIL(h, fil_finalize(r, 1, r.pos, r.ya, 1));
   if (r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
   int32_t n = 0;
@@ -883,10 +903,13 @@ int vlb_time_kernel(vlb_run* h, int32_t cls, int32_t reps, double* avg_ms) {
   r.timing = false;
   HIP_OR_FAIL(h, hipEventCreate(&gd.e0));
   HIP_OR_FAIL(h, hipEventCreate(&gd.e1));
-  if (cls == 0) HIP_OR_FAIL(h, bs_prep(r, r.pos));
+  const bool ff = cls == 0 && r.vor.ff_cell > 0;
+  if (cls == 0 && !ff) HIP_OR_FAIL(h, bs_prep(r, r.pos));
   HIP_OR_FAIL(h, hipEventRecord(gd.e0, r.stream));
   for (int k = 0; k < reps; ++k) {
-    if (cls == 0)
+    if (ff)
+      HIP_OR_FAIL(h, ff_run_sum(r, r.pos));
+    else if (cls == 0)
       HIP_OR_FAIL(h, bs_sum(r));
     else
       HIP_OR_FAIL(h, lbm_step(r));

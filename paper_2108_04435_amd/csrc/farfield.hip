@@ -147,39 +147,29 @@ __global__ void k_ff_init(int32_t* __restrict__ prv, int n) {
   if (j < n) prv[j] = j;
 }
 
-// Per point: wrapped position, grid coordinate, links, segment vector,
-// midpoint and its finest cell; sort keys (cell) and values (index).
-__global__ void k_ff_prep(const double* __restrict__ xyz, const int32_t* __restrict__ next, int n,
-                          FfAxes ax, int32_t* __restrict__ cnt, double* __restrict__ P,
-                          uint32_t* __restrict__ X, int32_t* __restrict__ nxt,
-                          int32_t* __restrict__ prv, double* __restrict__ M,
-                          double* __restrict__ D, uint32_t* __restrict__ keys,
-                          int32_t* __restrict__ kidx, int32_t* __restrict__ vals) {
+// Point j with successor k (positions y_j, y_k): wrapped position, grid
+// coordinate, segment vector, midpoint and the sort key of its finest cell.
+__device__ inline void ff_point(const double* yj, const double* yk, int j, long long nc,
+                                const FfAxes& ax, double* __restrict__ P,
+                                uint32_t* __restrict__ X, double* __restrict__ M,
+                                double* __restrict__ D, uint32_t* __restrict__ keys,
+                                int32_t* __restrict__ kidx, int32_t* __restrict__ vals) {
 #pragma clang fp contract(off)
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0) {
-    cnt[0] = n;
-    for (int i = 1; i < 32; ++i) cnt[i] = 0;
-  }
-  if (j >= n) return;
-  const int k = min(max(next[j], 0), n - 1);
-  nxt[j] = k;
-  if (k != j) prv[k] = j;
   int idx[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double L = ax.L[a];
-    const double p = ff_wrap(xyz[3LL * j + a], L);
-    const double pk = ff_wrap(xyz[3LL * k + a], L);
-    P[(long long)a * n + j] = p;
-    X[(long long)a * n + j] = (uint32_t)(long long)floor(p * ax.q[a]);
+    const double p = ff_wrap(yj[a], L);
+    const double pk = ff_wrap(yk[a], L);
+    P[(long long)a * nc + j] = p;
+    X[(long long)a * nc + j] = (uint32_t)(long long)floor(p * ax.q[a]);
     const double d = ff_min_image(pk - p, L);
     double mid = p + 0.5 * d;
     mid = mid - L * floor(mid / L);
     int i = (int)floor(mid / ax.h[0]);
     idx[a] = min(max(i, 0), ax.nc[0][a] - 1);
-    M[(long long)a * n + j] = mid;
-    D[(long long)a * n + j] = d;
+    M[(long long)a * nc + j] = mid;
+    D[(long long)a * nc + j] = d;
   }
   int key;
   if (ax.levels == 1) {
@@ -191,6 +181,51 @@ __global__ void k_ff_prep(const double* __restrict__ xyz, const int32_t* __restr
   keys[j] = (uint32_t)key;
   kidx[j] = key;
   vals[j] = j;
+}
+
+// Stand-alone sum: links sanitised from the caller's (clamped into
+// [0, n), inverted into prv, which k_ff_init set to self), positions
+// [n][3]; thread 0 writes the point count.
+__global__ void k_ff_prep(const double* __restrict__ xyz, const int32_t* __restrict__ next, int n,
+                          FfAxes ax, int32_t* __restrict__ cnt, double* __restrict__ P,
+                          uint32_t* __restrict__ X, int32_t* __restrict__ nxt,
+                          int32_t* __restrict__ prv, double* __restrict__ M,
+                          double* __restrict__ D, uint32_t* __restrict__ keys,
+                          int32_t* __restrict__ kidx, int32_t* __restrict__ vals) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) {
+    cnt[0] = n;
+    for (int i = 1; i < 32; ++i) cnt[i] = 0;
+  }
+  if (j >= n) return;
+  const int k = min(max(next[j], 0), n - 1);
+  nxt[j] = k;
+  if (k != j) prv[k] = j;
+  const double yj[3] = {xyz[3LL * j], xyz[3LL * j + 1], xyz[3LL * j + 2]};
+  const double yk[3] = {xyz[3LL * k], xyz[3LL * k + 1], xyz[3LL * k + 2]};
+  ff_point(yj, yk, j, n, ax, P, X, M, D, keys, kidx, vals);
+}
+
+// In a run: positions Y (3 x nc, SoA) and the run's links, the live count
+// cnt[0]; slots beyond it get the largest key (they sort last).
+__global__ void k_ff_prep_run(const double* __restrict__ Y, const int32_t* __restrict__ nxt,
+                              const int32_t* __restrict__ cnt, long long nc, FfAxes ax,
+                              double* __restrict__ P, uint32_t* __restrict__ X,
+                              double* __restrict__ M, double* __restrict__ D,
+                              uint32_t* __restrict__ keys, int32_t* __restrict__ kidx,
+                              int32_t* __restrict__ vals) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  if (j >= cnt[0]) {
+    keys[j] = 0xffffffffu;
+    kidx[j] = 0;
+    vals[j] = j;
+    return;
+  }
+  const int k = nxt[j];
+  const double yj[3] = {Y[j], Y[nc + j], Y[2 * nc + j]};
+  const double yk[3] = {Y[k], Y[nc + k], Y[2 * nc + k]};
+  ff_point(yj, yk, j, nc, ax, P, X, M, D, keys, kidx, vals);
 }
 
 // Cell ranges in the sorted keys (binary search; empty cells get count 0).
@@ -219,17 +254,17 @@ __global__ void k_ff_bounds(const uint32_t* __restrict__ sk, int n, int C, int s
 
 // Per sorted position: the direct loop's segment record.
 __global__ void k_ff_seg(const int32_t* __restrict__ so, const uint32_t* __restrict__ X,
-                         const int32_t* __restrict__ nxt, int n, FfAxes ax,
-                         FfSeg* __restrict__ recs) {
+                         const int32_t* __restrict__ nxt, const int32_t* __restrict__ cntp,
+                         long long nc, FfAxes ax, FfSeg* __restrict__ recs) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= cntp[0]) return;
   const int k = so[p];
   const int kn = nxt[k];
   FfSeg r;
   float dq = 0.f;
   for (int a = 0; a < 3; ++a) {
-    const uint32_t x0 = X[(long long)a * n + k];
-    float e = (float)(int)(X[(long long)a * n + kn] - x0);
+    const uint32_t x0 = X[(long long)a * nc + k];
+    float e = (float)(int)(X[(long long)a * nc + kn] - x0);
     if (!ax.uniform) e *= ax.iqf[a];
     r.x[a] = x0;
     r.d[a] = e;
@@ -249,17 +284,18 @@ __device__ inline double ff_lane_d(double x, int k) {
 // Per segment, at one level: the 36 moment components about its cell's
 // centre (FP64, row k of comps) and |y| + |d| / 2 (srad).
 __global__ void k_ff_comps(const double* __restrict__ M, const double* __restrict__ D,
-                           const int32_t* __restrict__ kidx, int n, FfAxes ax, int level,
-                           double* __restrict__ comps, double* __restrict__ srad) {
+                           const int32_t* __restrict__ kidx, const int32_t* __restrict__ cntp,
+                           long long nc, FfAxes ax, int level, double* __restrict__ comps,
+                           double* __restrict__ srad) {
 #pragma clang fp contract(off)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  if (k >= cntp[0]) return;
   int ci[3];
   ff_coords(ax, level, kidx[k] >> (3 * level), ci);
   double y[3], d[3];
   for (int b = 0; b < 3; ++b) {
-    y[b] = ff_min_image(M[(long long)b * n + k] - ((double)ci[b] + 0.5) * ax.h[level], ax.L[b]);
-    d[b] = D[(long long)b * n + k];
+    y[b] = ff_min_image(M[(long long)b * nc + k] - ((double)ci[b] + 0.5) * ax.h[level], ax.L[b]);
+    d[b] = D[(long long)b * nc + k];
   }
   double* row = comps + (long long)k * kMom;
 #pragma unroll
@@ -273,7 +309,8 @@ __global__ void k_ff_comps(const double* __restrict__ M, const double* __restric
 // offsets on the axis in ascending order (ties by sorted position) with
 // their segment indices (sdel, sidx), the prefix sums of the 36 moment
 // components over that order (FP64 sums stored FP32, rows
-// a (n + C) + start + c + i for i = 0 .. count, row 0 zero), and the
+// a (nc + C) + start + c + i for i = 0 .. count, row 0 zero; nc the
+// capacity of the point arrays), and the
 // record's fields for the axis (centre, grid centre, offset extremes); the
 // axis-0 wave also writes the radius and the moments (its prefix totals).
 // The ranks compare offsets held in registers (64 at a time, broadcast
@@ -282,7 +319,8 @@ __global__ void k_ff_comps(const double* __restrict__ M, const double* __restric
 __global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
                                                  const double* __restrict__ comps,
                                                  const double* __restrict__ srad,
-                                                 const uint32_t* __restrict__ X, int n, FfAxes ax,
+                                                 const uint32_t* __restrict__ X, long long nc,
+                                                 FfAxes ax,
                                                  int level, FfCell* __restrict__ cells,
                                                  int32_t* __restrict__ sdel,
                                                  int32_t* __restrict__ sidx,
@@ -297,9 +335,9 @@ __global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
   double cen[3];
   for (int b = 0; b < 3; ++b) cen[b] = ((double)ci[b] + 0.5) * ax.h[level];
   const uint32_t xc = (uint32_t)(long long)floor(cen[a] * ax.q[a]);
-  const uint32_t* Xa = X + (long long)a * n;
-  int32_t* sd = sdel + (long long)a * n + s;
-  int32_t* si = sidx + (long long)a * n + s;
+  const uint32_t* Xa = X + (long long)a * nc;
+  int32_t* sd = sdel + (long long)a * nc + s;
+  int32_t* si = sidx + (long long)a * nc + s;
   int dmn = 0x7fffffff, dmx = -0x7fffffff - 1;
   for (int b0 = 0; b0 < cnt; b0 += 64) {
     const int i = b0 + lane;
@@ -330,7 +368,7 @@ __global__ __launch_bounds__(64) void k_ff_order(const int32_t* __restrict__ so,
     dmx = max(dmx, __shfl_xor(dmx, off));
   }
   __syncthreads();  // the sorted order, written above, is read below
-  float* row = pre + ((long long)a * (n + C) + s + c) * kMom;
+  float* row = pre + ((long long)a * (nc + C) + s + c) * kMom;
   double acc = 0.0, rad = 0.0;
   for (int i = lane; i < cnt; i += 64) rad = fmax(rad, srad[so[s + i]]);
   if (lane < kMom) {
@@ -508,7 +546,8 @@ __device__ inline bool ff_other(const FfHead* cm, const FfDecision& o, const dou
 // whether this lane opens the cell (active, neither far nor split).
 __device__ inline bool ff_cell_eval(const FfHead& hc, const FfCell* __restrict__ cm, int c,
                                     const int32_t* __restrict__ sdel,
-                                    const float* __restrict__ pre, int n, int C, bool active,
+                                    const float* __restrict__ pre, long long nc, int C,
+                                    bool active,
                                     const double* r, const uint32_t* xt, const FfAxes& ax,
                                     float& fx, float& fy, float& fz) {
   FfDecision dc;
@@ -527,7 +566,7 @@ __device__ inline bool ff_cell_eval(const FfHead& hc, const FfCell* __restrict__
       const int a = dc.axis;
       const uint32_t u = hc.xc[a] - xt[a];
       const int db = (int)(0x80000000u - u);
-      const int32_t* dl = sdel + (long long)a * n + hc.start;
+      const int32_t* dl = sdel + (long long)a * nc + hc.start;
       int lo = 0, hi = hc.count;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -536,7 +575,7 @@ __device__ inline bool ff_cell_eval(const FfHead& hc, const FfCell* __restrict__
         else
           hi = mid;
       }
-      const float* pr = pre + ((long long)a * (n + C) + hc.start + c + lo) * kMom;
+      const float* pr = pre + ((long long)a * (nc + C) + hc.start + c + lo) * kMom;
       m2p_f32((float)-dc.R0[0], (float)-dc.R0[1], (float)-dc.R0[2], MomA{pr}, fx, fy, fz);
       m2p_f32((float)-R1[0], (float)-R1[1], (float)-R1[2], MomD{cm->m, pr}, fx, fy, fz);
     }
@@ -587,8 +626,10 @@ __global__ __launch_bounds__(256) void k_ff_eval(
     const int32_t* __restrict__ kidx, const int32_t* __restrict__ prv,
     const double* __restrict__ Pw, const uint32_t* __restrict__ X,
     const int32_t* __restrict__ sdel0, const int32_t* __restrict__ sdel1,
-    const float* __restrict__ pre0, const float* __restrict__ pre1, int n, int S, FfAxes ax,
-    float* __restrict__ Pout) {
+    const float* __restrict__ pre0, const float* __restrict__ pre1,
+    const int32_t* __restrict__ cntp, long long nc, int S, FfAxes ax, float* __restrict__ Pout) {
+  const int n = cntp[0];
+  if (blockIdx.x * kFfTargets >= n) return;  // whole block beyond the live points
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int t = blockIdx.x * kFfTargets + lane;
@@ -598,8 +639,8 @@ __global__ __launch_bounds__(256) void k_ff_eval(
   uint32_t xt[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    r[a] = Pw[(long long)a * n + j];
-    xt[a] = X[(long long)a * n + j];
+    r[a] = Pw[(long long)a * nc + j];
+    xt[a] = X[(long long)a * nc + j];
   }
   const int pj = valid ? prv[j] : -1;
   const int jj = valid ? j : -1;
@@ -623,7 +664,7 @@ __global__ __launch_bounds__(256) void k_ff_eval(
     if (c + step < Ct) ff_head(top + c + step, hn);
     if (hc.count > 0) {
       const bool open =
-          ff_cell_eval(hc, top + c, c, sdt, prt, n, Ct, valid, r, xt, ax, fx, fy, fz);
+          ff_cell_eval(hc, top + c, c, sdt, prt, nc, Ct, valid, r, xt, ax, fx, fy, fz);
       if (kLevels == 1) {
         if (__any(open))
           ff_direct<kUniform>(hc, c, recs, lds, open, kj, kp, jj, pj, xt, ax, dx, dy, dz);
@@ -636,7 +677,7 @@ __global__ __launch_bounds__(256) void k_ff_eval(
           FfHead hfn;
           if (ch < 7) ff_head(cells0 + f + 1, hfn);
           if (hf.count > 0) {
-            const bool near = ff_cell_eval(hf, cells0 + f, f, sdel0, pre0, n, ax.C[0], open, r,
+            const bool near = ff_cell_eval(hf, cells0 + f, f, sdel0, pre0, nc, ax.C[0], open, r,
                                            xt, ax, fx, fy, fz);
             if (__any(near))
               ff_direct<kUniform>(hf, f, recs, lds, near, kj, kp, jj, pj, xt, ax, dx, dy, dz);
@@ -664,10 +705,10 @@ __global__ __launch_bounds__(256) void k_ff_eval(
   }
   __syncthreads();
   if (w == 0 && valid) {
-    float* out = Pout + (long long)blockIdx.y * 3 * n;
+    float* out = Pout + (long long)blockIdx.y * 3 * nc;
     out[j] = ((fx + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
-    out[n + j] = ((fy + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
-    out[2LL * n + j] = ((fz + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
+    out[nc + j] = ((fy + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
+    out[2 * nc + j] = ((fz + red[0][2][lane]) + red[1][2][lane]) + red[2][2][lane];
   }
 }
 
@@ -828,21 +869,22 @@ hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, co
   int32_t* so = nullptr;
   hipError_t e = sort_pairs_raw(n, bits, 0, b.stmp, b.ka, b.kb, b.va, b.vb, stream, &sk, &so);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ff_seg, dim3(nb), dim3(256), 0, stream, so, b.X, b.nxt, (int)n, ax, b.recs);
+  hipLaunchKernelGGL(k_ff_seg, dim3(nb), dim3(256), 0, stream, so, b.X, b.nxt, b.cnt, n, ax,
+                     b.recs);
   for (int l = 0; l < ax.levels; ++l) {
     const int C = ax.C[l];
     hipLaunchKernelGGL(k_ff_bounds, dim3((C + 255) / 256), dim3(256), 0, stream, sk, (int)n, C,
                        3 * l, b.cells[l]);
-    hipLaunchKernelGGL(k_ff_comps, dim3(nb), dim3(256), 0, stream, b.M, b.D, b.kidx, (int)n, ax,
-                       l, b.comps, b.srad);
+    hipLaunchKernelGGL(k_ff_comps, dim3(nb), dim3(256), 0, stream, b.M, b.D, b.kidx, b.cnt, n,
+                       ax, l, b.comps, b.srad);
     hipLaunchKernelGGL(k_ff_order, dim3((unsigned)(3 * C)), dim3(64), 0, stream, so, b.comps,
-                       b.srad, b.X, (int)n, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
+                       b.srad, b.X, n, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
   }
   const dim3 grid((unsigned)((n + kFfTargets - 1) / kFfTargets), b.S);
 #define FF_EVAL(U, LV)                                                                         \
   hipLaunchKernelGGL((k_ff_eval<U, LV>), grid, dim3(256), 0, stream, b.cells[0], b.cells[1],   \
                      b.recs, so, b.kidx, b.prv, b.Pw, b.X, b.sdel[0], b.sdel[1], b.pre[0],     \
-                     b.pre[1], (int)n, b.S, ax, b.P)
+                     b.pre[1], b.cnt, n, b.S, ax, b.P)
   if (ax.uniform) {
     if (ax.levels == 2) FF_EVAL(true, 2); else FF_EVAL(true, 1);
   } else {
@@ -851,6 +893,66 @@ hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, co
 #undef FF_EVAL
   hipLaunchKernelGGL(k_ff_sum, dim3(nb), dim3(256), 0, stream, b.P, b.S, (int)n,
                      d->kappa / (4.0 * M_PI), v);
+  return hipGetLastError();
+}
+
+namespace {
+
+FfAxes ff_run_axes(const Run& r) {
+  const vlb_bs_desc bd{r.lat.nx, r.lat.ny, r.lat.nz, 0u, VLB_F32, 0, r.vor.kappa};
+  const vlb_ff_params fp{r.vor.ff_cell, r.vor.ff_levels, r.vor.ff_theta};
+  return ff_axes(&bd, &fp);
+}
+
+}  // namespace
+
+size_t ff_run_bytes(const Run& r) { return ff_layout(r.ncap, ff_run_axes(r), nullptr, nullptr); }
+
+int ff_run_chunks(const Run& r) {
+  const FfAxes ax = ff_run_axes(r);
+  return ff_chunks(r.ncap, ax.C[ax.levels - 1]);
+}
+
+hipError_t ff_run_sum(Run& r, const double* Y) {
+  const FfAxes ax = ff_run_axes(r);
+  const long long nc = r.ncap;
+  hipStream_t stream = r.stream;
+  FfBufs b;
+  ff_layout(nc, ax, (char*)r.ffws, &b);
+  hipEvent_t t0 = nullptr;
+  time_begin(r, 0, &t0);
+  const int nb = (int)((nc + 255) / 256);
+  hipLaunchKernelGGL(k_ff_prep_run, dim3(nb), dim3(256), 0, stream, Y, r.nxt, r.cnt, nc, ax, b.Pw,
+                     b.X, b.M, b.D, b.ka, b.kidx, b.va);
+  int bits = 1;
+  while ((1LL << bits) < ax.C[0]) ++bits;
+  uint32_t* sk = nullptr;
+  int32_t* so = nullptr;
+  hipError_t e = sort_pairs_raw(nc, bits, 0, b.stmp, b.ka, b.kb, b.va, b.vb, stream, &sk, &so);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ff_seg, dim3(nb), dim3(256), 0, stream, so, b.X, r.nxt, r.cnt, nc, ax,
+                     b.recs);
+  for (int l = 0; l < ax.levels; ++l) {
+    const int C = ax.C[l];
+    hipLaunchKernelGGL(k_ff_bounds, dim3((C + 255) / 256), dim3(256), 0, stream, sk, (int)nc, C,
+                       3 * l, b.cells[l]);
+    hipLaunchKernelGGL(k_ff_comps, dim3(nb), dim3(256), 0, stream, b.M, b.D, b.kidx, r.cnt, nc,
+                       ax, l, b.comps, b.srad);
+    hipLaunchKernelGGL(k_ff_order, dim3((unsigned)(3 * C)), dim3(64), 0, stream, so, b.comps,
+                       b.srad, b.X, nc, ax, l, b.cells[l], b.sdel[l], b.sidx[l], b.pre[l]);
+  }
+  const dim3 grid((unsigned)((nc + kFfTargets - 1) / kFfTargets), r.ffS);
+#define FF_EVAL(U, LV)                                                                         \
+  hipLaunchKernelGGL((k_ff_eval<U, LV>), grid, dim3(256), 0, stream, b.cells[0], b.cells[1],   \
+                     b.recs, so, b.kidx, r.prv, b.Pw, b.X, b.sdel[0], b.sdel[1], b.pre[0],     \
+                     b.pre[1], r.cnt, nc, r.ffS, ax, (float*)r.bsP)
+  if (ax.uniform) {
+    if (ax.levels == 2) FF_EVAL(true, 2); else FF_EVAL(true, 1);
+  } else {
+    if (ax.levels == 2) FF_EVAL(false, 2); else FF_EVAL(false, 1);
+  }
+#undef FF_EVAL
+  time_end(r, 0, t0);
   return hipGetLastError();
 }
 

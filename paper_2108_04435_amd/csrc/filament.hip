@@ -580,7 +580,7 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.prv = r.prv;
   A.cnt = r.cnt;
   A.P = r.bsP;
-  A.S = r.bsS * r.bsax.copies;
+  A.S = r.vor.ff_cell > 0 ? r.ffS : r.bsS * r.bsax.copies;
   A.ncap = r.ncap;
   A.Vs = r.Vs;
   A.mass_balance = r.vor.mass_balance;
@@ -589,7 +589,11 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.coupling = r.vor.coupling;
   A.kappa = r.vor.kappa;
   A.bs_scale = r.vor.kappa / (4.0 * M_PI);
-  A.nl_scale = (r.prec != VLB_F64 && r.bsax.uniform) ? A.bs_scale * r.bsax.q[0] : A.bs_scale;
+  // the direct FP32 sum on a uniform grid leaves grid units; the far-field
+  // sum lattice units
+  A.nl_scale = (r.prec != VLB_F64 && r.bsax.uniform && r.vor.ff_cell <= 0)
+                   ? A.bs_scale * r.bsax.q[0]
+                   : A.bs_scale;
   A.ln2_ea = log(2.0 / (exp(r.vor.core_c) * r.vor.core_a));
   A.alpha = r.vor.alpha;
   A.alpha_p = r.vor.alpha_p;

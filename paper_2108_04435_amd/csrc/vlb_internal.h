@@ -522,7 +522,11 @@ struct Run {
   uint32_t* bsX = nullptr;  // 3 * ncap grid coordinates
   void* bsD = nullptr;      // 3 * ncap segment vectors (float or double)
   void* bsP = nullptr;      // S * 3 * ncap partial sums
-  int32_t* bsown = nullptr; // ncap, with image copies: the copy mirrored in an end's own wall
+  int32_t* bsown = nullptr;
+  // far-field approximation of the non-local sum (vor.ff_cell > 0): its
+  // workspace and chunk count (its partials go to bsP)
+  void* ffws = nullptr;
+  int ffS = 0; // ncap, with image copies: the copy mirrored in an end's own wall
   int bsS = 1;
 
   // counters on the device: [0] n points, [1] n touched slots,
@@ -632,6 +636,13 @@ hipError_t bs_solo(const BsAxes& ax, int prec, long long n, const double* xyz,
                    hipStream_t stream);
 // Error message of a call without a run (vlb_last_error(NULL)); returns code.
 int fail_global(int code, const std::string& msg);
+// Far-field approximation of the non-local sum inside a run: workspace
+// bytes and chunk count for the run's capacity, and the sum of one stage's
+// positions Y (3 x n_cap, SoA) into the run's chunk partials bsP (lattice
+// units, FP32), with the live point count on the device.
+size_t ff_run_bytes(const Run& r);
+int ff_run_chunks(const Run& r);
+hipError_t ff_run_sum(Run& r, const double* Y);
 // Far-field approximation of the standalone sum (vlb_biot_savart_farfield).
 int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::string& msg);
 size_t ff_workspace(const vlb_bs_desc* d, const vlb_ff_params* p, long long n);

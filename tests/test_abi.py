@@ -48,6 +48,7 @@ int main(void) {
   O(vlb_lattice_desc, tau); O(vlb_lattice_desc, wall_axes); O(vlb_lattice_desc, plane_u);
   O(vlb_lattice_desc, body_force); O(vlb_vortex_desc, vs_applied); O(vlb_vortex_desc, remesh);
   O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap); O(vlb_vortex_desc, wall_images);
+  O(vlb_vortex_desc, ff_cell); O(vlb_vortex_desc, ff_levels); O(vlb_vortex_desc, ff_theta);
   printf("bs %zu\n", sizeof(vlb_bs_desc));
   O(vlb_bs_desc, wall_axes); O(vlb_bs_desc, precision); O(vlb_bs_desc, kappa);
   return 0;
@@ -121,6 +122,32 @@ def test_invalid_vortex_rejected(bad, msg):
     code, _, err = _query(wl.lattice_preset(16, 16, 16), vor)
     assert code == vlb.VLB_EINVAL
     assert msg in err
+
+
+@pytest.mark.parametrize("lat_kw,vor_kw,msg", [
+    (dict(precision="f64"), dict(ff_cell=4), "FP32"),
+    (dict(precision="f32", walls=(False, False, True)), dict(ff_cell=4), "periodic"),
+    (dict(precision="f32"), dict(ff_cell=4, wall_images=True), "wall images"),
+    (dict(precision="f32"), dict(ff_cell=5), "divide"),
+    (dict(precision="f32"), dict(ff_cell=16, ff_levels=2, ff_theta=0.5), "twice"),
+    (dict(precision="f16"), dict(ff_cell=4, ff_theta=1.5), "theta"),
+    (dict(precision="f32"), dict(ff_cell=-1), "ff_cell"),
+])
+def test_farfield_run_rejected(lat_kw, vor_kw, msg):
+    """A run's far-field switch: FP32 or FP16, a periodic box, no wall
+    images, and the stand-alone sum's cell rules."""
+    lat = wl.lattice_preset(16, 16, 16, **lat_kw)
+    code, _, err = _query(lat, wl.vortex_preset(**vor_kw))
+    assert code == vlb.VLB_EINVAL
+    assert msg in err
+
+
+def test_farfield_run_footprint():
+    """The far-field switch adds its workspace to a run's footprint."""
+    lat = wl.lattice_preset(32, 32, 32, precision="f32")
+    _, base, _ = _query(lat, wl.vortex_preset(), n_cap=4096)
+    code, ff, _ = _query(lat, wl.vortex_preset(ff_cell=8, ff_levels=2, ff_theta=0.3), n_cap=4096)
+    assert code == vlb.VLB_OK and ff > base + 4096 * 600
 
 
 def test_mass_balance_needs_periodic_z():

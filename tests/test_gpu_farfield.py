@@ -142,3 +142,102 @@ def test_farfield_tangle_256_full_size(levels):
     e = rel_l2(got, direct)
     say(f"  approximation error against the direct sum: {e:.2e}")
     assert e <= 1e-3
+
+
+# ---- the far-field sum inside coupled runs (vortex descriptor ff_cell)
+
+RUN_TOL = {"f32": 1e-5, "f16": 1e-3}
+
+
+def _ff_run_case(precision, levels, n_rings=20):
+    """64^3 periodic tangle of 20 rings with mass balance; the non-local sum
+    of every stage by the far field (cells of 8, theta 0.3)."""
+    cfg = wl.config_tangle(precision=precision, n=64, n_rings=n_rings, seed=5)
+    cfg["vortex"] = dict(cfg["vortex"], ff_cell=8, ff_levels=levels, ff_theta=0.3)
+    return cfg
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_run_eval_with_farfield(precision, levels):
+    """First-stage line velocity, force and spread force of a run whose
+    non-local sum is the far field, against the oracle's line velocity with
+    the same approximation; it differs from the direct sum's by about the
+    approximation's error (so the approximation is the one in use)."""
+    import dataclasses
+
+    from oracle import lbm
+    from tests._cases import oracle_state
+
+    cfg = _ff_run_case(precision, levels)
+    say(f"run eval with far field {precision} levels {levels}: {cfg['pos'].shape[0]} points")
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F_g = run.read_force()
+    lat, vp, st = oracle_state(cfg)
+    assert vp.ff_cell == 8 and vp.ff_levels == levels
+    _, ub = lbm.bare_velocity(st.f, lat)
+    Vs = lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n) if vp.mass_balance else None
+    ref = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, Vs, lat, vp, want_force=True)
+    for k in ("vs", "vn", "sdot", "force"):
+        err = rel_l2(got[k], ref[k])
+        say(f"  {k}: {err:.2e}")
+        assert err <= RUN_TOL[precision], (k, err)
+    F_o = vfm.spread(ref["force"], st.pos, lat)
+    assert rel_l2(F_g, F_o) <= RUN_TOL[precision]
+    direct = vfm.line_velocity(st.pos, st.nxt, st.prv, ub, Vs, lat,
+                               dataclasses.replace(vp, ff_cell=0))
+    e = rel_l2(got["vs"], direct["vs"])
+    say(f"  against the direct sum: {e:.2e}")
+    assert 1e-7 < e < 1e-2
+    run.close()
+
+
+def test_run_steps_with_farfield():
+    """FP32 coupled steps with the two-level far field against the oracle's
+    steps with the same approximation: links equal after every step,
+    positions within 1e-4, velocity field within 1e-5."""
+    from oracle import lbm
+    from tests._cases import oracle_state
+
+    cfg = _ff_run_case("f32", 2)
+    say(f"run steps with far field: {cfg['pos'].shape[0]} points")
+    run = vlb.run_from_config(cfg)
+    lat, vp, st = oracle_state(cfg)
+    for k in range(3):
+        run.step(1)
+        run.sync()
+        st = coupled.coupled_step(st, lat, vp)
+        pos_g, nxt_g = run.read_filaments()
+        assert nxt_g.shape == st.nxt.shape and (nxt_g == st.nxt).all(), k
+        d = np.abs(vfm.min_image(pos_g - st.pos, lat)).max()
+        say(f"  step {k + 1}: max position difference {d:.2e}")
+        assert d < 1e-4
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    assert rel_l2(u_g, u_o) <= 1e-5
+    run.close()
+
+
+def test_run_farfield_graph_replay_matches_direct_steps():
+    """Steps with the far field replayed from a captured HIP graph are
+    bitwise equal to steps enqueued one by one (several replays)."""
+    cfg = _ff_run_case("f16", 2)
+    say("run far field graph replay")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        direct = vlb.run_from_config(cfg)
+    with torch.cuda.stream(s2):
+        graphed = vlb.run_from_config(cfg)
+        for _ in range(3):
+            direct.step(4)
+            graphed.step_graph(4)
+            direct.sync()
+            graphed.sync()
+            pa, na = direct.read_filaments()
+            pb, nb = graphed.read_filaments()
+            np.testing.assert_array_equal(na, nb)
+            np.testing.assert_array_equal(pa, pb)
+            np.testing.assert_array_equal(direct.read_populations(), graphed.read_populations())
+    direct.close()
+    graphed.close()

@@ -159,3 +159,22 @@ def test_error_bound_on_a_random_tangle(n, h, n_rings, seed, levels):
                 assert st["far"] + st["split"] < st1["far"] + st1["split"]
     assert errs[0.25] <= 1e-3
     assert errs[0.5] > errs[0.25]
+
+
+def test_line_velocity_switch():
+    """VortexParams.ff_cell routes the non-local term of the line velocity
+    through the far field: with nothing far (theta tiny) it is the direct
+    line velocity, at theta 0.3 it differs by the approximation's size."""
+    import dataclasses
+
+    lat, pos, nxt, prv = _tangle(32, 12, 3)
+    vp = vfm.VortexParams(kappa=KAPPA)
+    ub = np.zeros((3, lat.nz, lat.ny, lat.nx))
+    ref = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp)
+    tiny = vfm.line_velocity(pos, nxt, prv, ub, None, lat,
+                             dataclasses.replace(vp, ff_cell=8, ff_levels=2, ff_theta=1e-9))
+    np.testing.assert_allclose(tiny["vs"], ref["vs"], rtol=0, atol=1e-13 * np.abs(ref["vs"]).max())
+    ff = vfm.line_velocity(pos, nxt, prv, ub, None, lat,
+                           dataclasses.replace(vp, ff_cell=4, ff_theta=0.3))
+    e = np.linalg.norm(ff["vs"] - ref["vs"]) / np.linalg.norm(ref["vs"])
+    assert 1e-8 < e < 1e-2

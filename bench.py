@@ -583,6 +583,57 @@ def farfield_bench(torch, vlb, cfg, cell, theta, levels, reps=10):
                 basis="HIP events around %d calls each, inputs resident on the GPU" % reps)
 
 
+def farfield_steps(torch, vlb, cfg, args, cell, theta, levels):
+    """Coupled steps of the workload with the far-field approximation as the
+    non-local sum of every stage (vortex descriptor ff_cell), timed as the
+    headline is (same warm-up, steps and graph chunks).  Periodic boxes
+    with FP32 arithmetic only (None otherwise)."""
+    lat = cfg["lattice"]
+    dims = (lat["nx"], lat["ny"], lat["nz"])
+    if any(lat["walls"]) or lat["precision"] == "f64" or any(d % (cell * levels) for d in dims):
+        return None
+    cfg = dict(cfg, vortex=dict(cfg["vortex"], ff_cell=cell, ff_levels=levels, ff_theta=theta))
+    n0 = cfg["pos"].shape[0]
+    stream = torch.cuda.Stream()   # default priority; graphs need a non-null stream
+    torch.cuda.set_stream(stream)
+    run = vlb.run_from_config(cfg, n_cap=int(n0 * 1.4) + 256, recon_cap=1 << 18)
+    graph = args.graph
+
+    def advance(plan, events=None):
+        for kind, k in plan:
+            if events is not None:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            if kind == "graph":
+                run.step_graph(k)
+            else:
+                run.step(k)
+            if events is not None:
+                b.record(stream)
+                events.append((a, b, k))
+
+    advance(step_plan(args.warmup, graph))
+    run.sync()
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    advance(step_plan(args.steps, graph), ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run.sync()
+    step_ms = np.concatenate([np.full(k, a.elapsed_time(b) / k) for a, b, k in ev])
+    n_end = run.n_points()
+    run.close()
+    torch.cuda.empty_cache()
+    cells = dims[0] * dims[1] * dims[2]
+    return dict(value=round(args.steps / wall, 4), unit="steps/s",
+                ms_per_step=round(1e3 * wall / args.steps, 4),
+                step_ms_p50=round(float(np.percentile(step_ms, 50)), 4),
+                step_ms_p99=round(float(np.percentile(step_ms, 99)), 4),
+                mlups=round(cells * args.steps / wall / 1e6, 1), precision=lat["precision"],
+                points_start=int(n0), points_end=int(n_end), graph_steps=graph)
+
+
 def serve_bench(args):
     """Served form: 64 counterflow requests arriving as a Poisson stream at
     2/s, lattices {32^3, 64^3, 64x64x256, 128x128x256}, 1k-20k points,
@@ -791,6 +842,14 @@ def main(argv=None):
     if args.ff_cell > 0:
         out["farfield"] = farfield_bench(torch, vlb, cfg, args.ff_cell, args.ff_theta,
                                          args.ff_levels)
+        if out["farfield"] is not None:
+            st = farfield_steps(torch, vlb, cfg, args, args.ff_cell, args.ff_theta,
+                                args.ff_levels)
+            if st is not None:
+                st["speedup_vs_direct_steps"] = round(st["value"] / head["value"], 3)
+                print(f"[bench] {prec} with the far field: {st['value']} steps/s",
+                      file=sys.stderr, flush=True)
+            out["farfield"]["coupled_steps"] = st
     out["hbm_copy"] = hbm_copy(torch)
     if base is not None:
         out["cpu_baseline"] = base

@@ -22,6 +22,86 @@ namespace vlb {
 
 namespace {
 
+// The forced BGK collision of one node (Sec. II.B, Eqs. LBM 1-3 collapsed)
+// from its 19 raw stored values D (deviations times kScale; overwritten on a
+// velocity plane) and the spread force (fx, fy, fz) when has_f: the 19
+// post-collision values in the storage format.  Every kernel variant calls
+// this one function, so every variant rounds the update identically.
+template <class S>
+__device__ __forceinline__ void collide_values(typename Store<S>::T* D, bool has_f,
+                                               typename Store<S>::T fx,
+                                               typename Store<S>::T fy,
+                                               typename Store<S>::T fz, const Geom& g,
+                                               bool on_plane, S* En) {
+  using T = typename Store<S>::T;
+  const T kS = T(Raw<S>::kScale);
+  const T kInvS = T(1) / kS;  // a power of two: exact
+  T om, pref, body[3], plane[3];
+  geom_params<T>(g, om, pref, body, plane);
+  if (on_plane) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) D[i] = kS * eq_dev<T>(i, T(0), T(1), plane[0], plane[1], plane[2]);
+  }
+  T gx = body[0], gy = body[1], gz = body[2];
+  if (has_f) {
+    gx += fx;
+    gy += fy;
+    gz += fz;
+  }
+  T sD, sx, sy, sz;
+  moments<T>(D, sD, sx, sy, sz);
+  const T drho = kInvS * sD;
+  const T rho = T(1) + drho;
+  T inv;
+  if constexpr (sizeof(T) == 4) {
+    // hardware reciprocal refined by one Newton step (within an ulp of 1/rho)
+    const T r0 = __builtin_amdgcn_rcpf(rho);
+    inv = fmaf(r0, fmaf(-rho, r0, 1.0f), r0);
+  } else {
+    inv = T(1) / rho;
+  }
+  const T ux = (kInvS * sx + T(0.5) * gx) * inv;
+  const T uy = (kInvS * sy + T(0.5) * gy) * inv;
+  const T uz = (kInvS * sz + T(0.5) * gz) * inv;
+  const T ug = ux * gx + uy * gy + uz * gz;
+  // Post-collision value f - (f - f^eq)/tau + F_i with f^eq and the
+  // Cheng-Li/Guo term F_i built from rho and u = (sum c f + g/2)/rho
+  // (Sec. II.B, Eqs. LBM 1-3 collapsed).  It is (1 - 1/tau) d_i +
+  // [d^eq_i/tau + F_i], and the bracket splits into parts even and odd in
+  // c_i, shared by each pair (i, opp(i)): with cu = c_i.u and cg = c_i.g it
+  // is w_i (P + Q) for i and w_i (P - Q) for opp(i),
+  //   P = om (drho - 1.5 rho u.u) - 3 pref u.g + cu (4.5 om rho cu + 9 pref cg),
+  //   Q = 3 om rho cu + 3 pref cg,
+  // all of it times kScale, the storage scale.  Half the directional terms
+  // of the direct form; it matters with FP16 storage, where the arithmetic
+  // is a large share of the update.
+  T Dn[19];
+  {
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T om1 = T(1) - om;
+    const T Kp = om * (drho - T(1.5) * rho * uu) - T(3) * pref * ug;
+    const T a1 = T(4.5) * om * rho, a2 = T(9) * pref;
+    const T b1 = T(3) * om * rho, b2 = T(3) * pref;
+    Dn[0] = fma(om1, D[0], (T(wq(0)) * kS) * Kp);
+#pragma unroll
+    for (int k = 1; k <= 9; ++k) {
+      const int i = 2 * k - 1;  // i and opp(i) = i + 1
+      const T ws = T(wq(i)) * kS;
+      const T cu = cdot<T>(i, ux, uy, uz);
+      const T cg = cdot<T>(i, gx, gy, gz);
+      const T Pk = ws * fma(cu, fma(a1, cu, a2 * cg), Kp);
+      const T Qk = ws * fma(b1, cu, b2 * cg);
+      Dn[i] = fma(om1, D[i], Pk + Qk);
+      Dn[i + 1] = fma(om1, D[i + 1], Pk - Qk);
+    }
+  }
+  // Values in the storage format, encoded here, before the passes'
+  // addressing branches: a conversion to FP16 that the compiler fuses with
+  // the last multiply-add rounds once, and it must do so in every variant.
+#pragma unroll
+  for (int i = 0; i < 19; ++i) En[i] = Raw<S>::enc(Dn[i]);
+}
+
 // Post-collision deviation (Sec. II.B, Eqs. LBM 1-3 collapsed):
 // f''' = f - (f - f^eq)/tau + F, with f^eq and the Cheng-Li/Guo term F built
 // from rho and u = (sum c f + g/2)/rho.
@@ -121,80 +201,21 @@ __device__ __forceinline__ void collide_node(S* __restrict__ M,
                       : Raw<S>::template ld<NT>(M + (long long)i * g.cells + c);
     }
   }
-  const T kS = T(Raw<S>::kScale);
-  const T kInvS = T(1) / kS;  // a power of two: exact
-  T om, pref, body[3], plane[3];
-  geom_params<T>(g, om, pref, body, plane);
-  if (is_plane(g, z)) {
-#pragma unroll
-    for (int i = 0; i < 19; ++i) D[i] = kS * eq_dev<T>(i, T(0), T(1), plane[0], plane[1], plane[2]);
-  }
-  T gx = body[0], gy = body[1], gz = body[2];
+  T fxv = T(0), fyv = T(0), fzv = T(0);
   if (F) {
     if (I32) {
       const uint32_t fo = c32 * (uint32_t)sizeof(T);
-      gx += *at_byte(F, fo);
-      gy += *at_byte(F + g.cells, fo);
-      gz += *at_byte(F + 2 * g.cells, fo);
+      fxv = *at_byte(F, fo);
+      fyv = *at_byte(F + g.cells, fo);
+      fzv = *at_byte(F + 2 * g.cells, fo);
     } else {
-      gx += F[c];
-      gy += F[g.cells + c];
-      gz += F[2 * g.cells + c];
+      fxv = F[c];
+      fyv = F[g.cells + c];
+      fzv = F[2 * g.cells + c];
     }
   }
-  T sD, sx, sy, sz;
-  moments<T>(D, sD, sx, sy, sz);
-  const T drho = kInvS * sD;
-  const T rho = T(1) + drho;
-  T inv;
-  if constexpr (sizeof(T) == 4) {
-    // hardware reciprocal refined by one Newton step (within an ulp of 1/rho)
-    const T r0 = __builtin_amdgcn_rcpf(rho);
-    inv = fmaf(r0, fmaf(-rho, r0, 1.0f), r0);
-  } else {
-    inv = T(1) / rho;
-  }
-  const T ux = (kInvS * sx + T(0.5) * gx) * inv;
-  const T uy = (kInvS * sy + T(0.5) * gy) * inv;
-  const T uz = (kInvS * sz + T(0.5) * gz) * inv;
-  const T ug = ux * gx + uy * gy + uz * gz;
-  // Post-collision value f - (f - f^eq)/tau + F_i with f^eq and the
-  // Cheng-Li/Guo term F_i built from rho and u = (sum c f + g/2)/rho
-  // (Sec. II.B, Eqs. LBM 1-3 collapsed).  It is (1 - 1/tau) d_i +
-  // [d^eq_i/tau + F_i], and the bracket splits into parts even and odd in
-  // c_i, shared by each pair (i, opp(i)): with cu = c_i.u and cg = c_i.g it
-  // is w_i (P + Q) for i and w_i (P - Q) for opp(i),
-  //   P = om (drho - 1.5 rho u.u) - 3 pref u.g + cu (4.5 om rho cu + 9 pref cg),
-  //   Q = 3 om rho cu + 3 pref cg,
-  // all of it times kScale, the storage scale.  Half the directional terms
-  // of the direct form; it matters with FP16 storage, where the arithmetic
-  // is a large share of the update.
-  T Dn[19];
-  {
-    const T uu = ux * ux + uy * uy + uz * uz;
-    const T om1 = T(1) - om;
-    const T Kp = om * (drho - T(1.5) * rho * uu) - T(3) * pref * ug;
-    const T a1 = T(4.5) * om * rho, a2 = T(9) * pref;
-    const T b1 = T(3) * om * rho, b2 = T(3) * pref;
-    Dn[0] = fma(om1, D[0], (T(wq(0)) * kS) * Kp);
-#pragma unroll
-    for (int k = 1; k <= 9; ++k) {
-      const int i = 2 * k - 1;  // i and opp(i) = i + 1
-      const T ws = T(wq(i)) * kS;
-      const T cu = cdot<T>(i, ux, uy, uz);
-      const T cg = cdot<T>(i, gx, gy, gz);
-      const T Pk = ws * fma(cu, fma(a1, cu, a2 * cg), Kp);
-      const T Qk = ws * fma(b1, cu, b2 * cg);
-      Dn[i] = fma(om1, D[i], Pk + Qk);
-      Dn[i + 1] = fma(om1, D[i + 1], Pk - Qk);
-    }
-  }
-  // Values in the storage format, encoded here, before the passes'
-  // addressing branches: a conversion to FP16 that the compiler fuses with
-  // the last multiply-add rounds once, and it must do so in every variant.
   S En[19];
-#pragma unroll
-  for (int i = 0; i < 19; ++i) En[i] = Raw<S>::enc(Dn[i]);
+  collide_values<S>(D, F != nullptr, fxv, fyv, fzv, g, is_plane(g, z), En);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
     const S dn = En[i];
@@ -255,6 +276,134 @@ __global__ __launch_bounds__(256) void k_collide_stream(S* __restrict__ M,
     const int x = bxi * blockDim.x + threadIdx.x;
     const int y = byi * blockDim.y + threadIdx.y;
     if (x < g.nx && y < g.ny) collide_node<S, P, NT, I32>(M, F, g, x, y, z);
+  }
+}
+
+// FP16 storage on rows of exactly 256 nodes, periodic in x and y: one wave
+// per row (z, y), four x-consecutive nodes per lane, every slot of the
+// four read or written with one aligned 8-byte buffer access (2-byte
+// accesses cap the pattern at about 0.71 of the HBM peak, 8-byte ones at
+// about 0.77: pure-memory probes on this chip).  The lane's byte offset in
+// a row is the same for all 38 accesses; rows and slabs are uniform.  The
+// x-shifted directions of odd passes move one node across lanes: the
+// element entering from the previous lane (or, for -x, from the next) comes
+// with a one-lane rotation of the whole wave, which also wraps x
+// periodically (lane 0 takes lane 63's last node).  Each slot is still read
+// and written by its own node's lane only.  Odd passes of the slices next
+// to z walls take the per-node path (collide_node) for the lane's four
+// nodes.
+__device__ inline uint32_t rot_prev(uint32_t v) {  // lane L gets lane L - 1's value (wave_ror:1)
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xF, 0xF, false);
+}
+__device__ inline uint32_t rot_next(uint32_t v) {  // lane L gets lane L + 1's value (wave_rol:1)
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xF, 0xF, false);
+}
+// The lane's four nodes (halves e0..e3 in lo/hi of .x, .y) as seen one
+// node to the left: [e3 of lane L - 1, e0, e1, e2]; and to the right:
+// [e1, e2, e3, e0 of lane L + 1].
+__device__ inline vlb_u32x2 shift_in_prev(vlb_u32x2 g) {
+  const uint32_t p3 = rot_prev(g.y) >> 16;
+  vlb_u32x2 o;
+  o.x = (g.x << 16) | p3;
+  o.y = (g.y << 16) | (g.x >> 16);
+  return o;
+}
+__device__ inline vlb_u32x2 shift_in_next(vlb_u32x2 g) {
+  const uint32_t n0 = rot_next(g.x) & 0xffffu;
+  vlb_u32x2 o;
+  o.x = (g.x >> 16) | (g.y << 16);
+  o.y = (g.y >> 16) | (n0 << 16);
+  return o;
+}
+
+template <int P, bool NT>
+__global__ __launch_bounds__(256) void k_collide_rows4(__half* __restrict__ M,
+                                                       const float* __restrict__ F, Geom g,
+                                                       int nblk) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rows = g.ny * g.nz;
+  const uint32_t cells32 = (uint32_t)g.cells;
+  const uint32_t slab = cells32 * 2u;
+  const __amdgpu_buffer_rsrc_t rs = pop_rsrc(M, 19u * slab);
+  const uint32_t vo = (uint32_t)lane * 8u;  // byte offset of the lane's nodes in a row
+  for (int it = blockIdx.x; it < nblk; it += gridDim.x) {
+    const int row = __builtin_amdgcn_readfirstlane(xcd_remap(it, nblk) * 4 + w);
+    if (row >= rows) continue;
+    const int z = row / g.ny, y = row - z * g.ny;
+    if (P == 1 && g.wall[2] && (z == 0 || z == g.nz - 1)) {
+#pragma unroll 1
+      for (int k = 0; k < 4; ++k) collide_node<__half, 1, NT, true>(M, F, g, 4 * lane + k, y, z);
+      continue;
+    }
+    // byte offsets of the rows (y + dy, z + dz), periodic
+    uint32_t ro[3][3];  // [dz + 1][dy + 1]
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        int zz = z + dz, yy = y + dy;
+        zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
+        yy = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
+        ro[dz + 1][dy + 1] = (uint32_t)(zz * g.ny + yy) * 512u;
+      }
+    vlb_u32x2 G[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      if (P == 0) {
+        G[i] = __builtin_bit_cast(vlb_u32x2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                 rs, vo, (uint32_t)i * slab + ro[1][1], NT ? 2 : 0));
+      } else {
+        // slot opp(i) of x - c_i
+        const vlb_u32x2 v = __builtin_bit_cast(
+            vlb_u32x2, __builtin_amdgcn_raw_buffer_load_b64(
+                           rs, vo, (uint32_t)opp(i) * slab + ro[1 - cz(i)][1 - cy(i)], NT ? 2 : 0));
+        G[i] = cx(i) == 1 ? shift_in_prev(v) : (cx(i) == -1 ? shift_in_next(v) : v);
+      }
+    }
+    const long long fo = (long long)row * 256 + 4 * lane;  // the lane's first node
+    const bool pl = is_plane(g, z);
+    vlb_u32x2 O[19];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float D[19];
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const uint32_t word = (k < 2) ? G[i].x : G[i].y;
+        const unsigned short h = (unsigned short)((k & 1) ? (word >> 16) : (word & 0xffffu));
+        D[i] = __half2float(__ushort_as_half(h));
+      }
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+      if (F) {
+        fx = F[fo + k];
+        fy = F[g.cells + fo + k];
+        fz = F[2 * g.cells + fo + k];
+      }
+      __half En[19];
+      collide_values<__half>(D, F != nullptr, fx, fy, fz, g, pl, En);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const uint32_t h = (uint32_t)__half_as_ushort(En[i]);
+        if (k == 0) O[i].x = h;
+        else if (k == 1) O[i].x |= h << 16;
+        else if (k == 2) O[i].y = h;
+        else O[i].y |= h << 16;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      if (P == 0) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vlb_u32x2, O[i]), rs, vo,
+                                              (uint32_t)opp(i) * slab + ro[1][1], NT ? 2 : 0);
+      } else {
+        // slot i of x + c_i: the lane's group holds the values of the nodes
+        // one to the left (+x) or right (-x)
+        const vlb_u32x2 v = cx(i) == 1 ? shift_in_prev(O[i]) : (cx(i) == -1 ? shift_in_next(O[i]) : O[i]);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vlb_u32x2, v), rs, vo,
+                                              (uint32_t)i * slab + ro[1 + cz(i)][1 + cy(i)],
+                                              NT ? 2 : 0);
+      }
+    }
   }
 }
 
@@ -477,6 +626,19 @@ hipError_t launch_collide(Run& r) {
   const bool nt = 19.0 * (double)g.cells * sizeof(S) > kStreamBytes;
   // odd passes: 32-bit slot offsets when the population array spans less than 4 GiB
   const bool i32 = g.cells < (1LL << 29) && 19.0 * (double)g.cells * sizeof(S) < 4294967296.0;
+  if constexpr (sizeof(S) == 2) {
+    // rows of 256 nodes periodic in x and y: four nodes per lane
+    if (i32 && g.nx == 256 && !g.wall[0] && !g.wall[1]) {
+      const int nrb = (g.ny * g.nz + 3) / 4;  // blocks of four rows
+      int grid4 = nrb;
+      if (r.lbm_narrow && grid4 > 512) grid4 = 512;
+      auto k4 = r.parity == 0 ? (nt ? k_collide_rows4<0, true> : k_collide_rows4<0, false>)
+                              : (nt ? k_collide_rows4<1, true> : k_collide_rows4<1, false>);
+      hipLaunchKernelGGL(k4, dim3(grid4), dim3(256), 0, r.stream, (__half*)r.pops, (const float*)F,
+                         g, nrb);
+      return hipGetLastError();
+    }
+  }
   auto kern = r.parity == 0
                   ? (i32 ? (nt ? k_collide_stream<S, 0, true, true> : k_collide_stream<S, 0, false, true>)
                          : (nt ? k_collide_stream<S, 0, true, false> : k_collide_stream<S, 0, false, false>))

@@ -24,6 +24,13 @@ LBM_CASES = {
     "planes": dict(n=(10, 12, 14), walls=(True, True, False), planes=True, body=(0.0, 0.0, 0.0)),
     # rows longer than one block (256 nodes) with a ragged second block
     "wide_x": dict(n=(261, 5, 4), walls=(True, False, False), planes=False, body=(1e-5, 0.0, 2e-5)),
+    # rows of exactly 256 nodes periodic in x and y: with FP16 storage four
+    # nodes per lane (x-shifted directions across lanes, x wrapping at lane
+    # 63), also next to z walls (per-node path for those slices' odd passes)
+    # and on velocity planes
+    "rows256": dict(n=(256, 6, 5), walls=(False, False, False), planes=False, body=(1e-5, -2e-5, 3e-5)),
+    "rows256_zwalls": dict(n=(256, 5, 6), walls=(False, False, True), planes=False, body=(2e-5, 1e-5, 0.0)),
+    "rows256_planes": dict(n=(256, 4, 8), walls=(False, False, False), planes=True, body=(0.0, 0.0, 0.0)),
 }
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
@@ -134,3 +141,61 @@ def test_lbm_large_array_crop(precision, dims):
     err = rel_l2(got, u_o[inner])
     say("large array crop velocity", precision, err)
     assert err <= (1e-12 if precision == "f64" else 1e-5)
+
+
+def _rows256_coupled(precision="f16", seed=41):
+    """256 x 8 x 8 periodic lattice (rows of 256 nodes) with a ring of 16
+    points around the x axis, so that the update reads a spread force."""
+    lat = wl.lattice_preset(256, 8, 8, tau=0.8, precision=precision)
+    vor = wl.vortex_preset()
+    rho, u = wl.velocity_field(seed, (256, 8, 8), (0.01, 0.0, 0.005), 1e-3)
+    pos, nxt = wl.ring((128.3, 4.1, 3.9), 2.2, (1.0, 0.0, 0.0), 16, phase=0.5)
+    return dict(name="rows256_ring", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt)
+
+
+def test_rows256_coupled_f16_against_oracle():
+    """Coupled FP16-storage steps on rows of 256 nodes (four nodes per lane,
+    spread force read as four-node groups) against the FP64 oracle: links
+    equal, positions within 1e-2, velocity field within 1e-3."""
+    from oracle import coupled, vfm
+    from tests._cases import oracle_state
+
+    cfg = _rows256_coupled()
+    say("rows256 coupled f16")
+    run = vlb.run_from_config(cfg)
+    olat, vp, st = oracle_state(cfg)
+    for k in range(6):
+        run.step(1)
+        run.sync()
+        st = coupled.coupled_step(st, olat, vp)
+        pos_g, nxt_g = run.read_filaments()
+        assert (nxt_g == st.nxt).all(), k
+        assert np.abs(vfm.min_image(pos_g - st.pos, olat)).max() < 1e-2, k
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, olat)
+    err = rel_l2(u_g, u_o)
+    say("velocity L2 rel", err)
+    assert err <= TOL["f16"]
+    run.close()
+
+
+def test_rows256_checkpoint_resume_bitwise():
+    """FP16 rows of 256 nodes: a run resumed from the state read after an
+    odd number of steps (swapped AA layout) continues bit for bit."""
+    cfg = _rows256_coupled(seed=42)
+    a = vlb.run_from_config(cfg)
+    a.step(5)
+    a.sync()
+    buf, step = a.read_state()
+    pos, nxt = a.read_filaments()
+    b = vlb.Run(cfg["lattice"], cfg["vortex"], a.n_cap)
+    b.write_state(buf, step)
+    b.seed(pos, nxt)
+    a.step(6)
+    b.step(6)
+    a.sync()
+    b.sync()
+    np.testing.assert_array_equal(a.read_state()[0].cpu().numpy(), b.read_state()[0].cpu().numpy())
+    np.testing.assert_array_equal(a.read_filaments()[0], b.read_filaments()[0])
+    a.close()
+    b.close()

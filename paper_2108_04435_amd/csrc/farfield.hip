@@ -785,7 +785,11 @@ struct FfBufs {
   int S;
 };
 
-size_t ff_layout(long long n, const FfAxes& ax, char* base, FfBufs* b) {
+// Workspace of the sum for n points (the capacity in a run).  solo: the
+// stand-alone call, which also needs the sanitised links, the point count
+// and its own chunk partials (a run has its own and writes into its
+// Biot-Savart partials).
+size_t ff_layout(long long n, const FfAxes& ax, bool solo, char* base, FfBufs* b) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
     off = (off + 255) / 256 * 256;
@@ -795,11 +799,13 @@ size_t ff_layout(long long n, const FfAxes& ax, char* base, FfBufs* b) {
   };
   FfBufs s{};
   s.S = ff_chunks(n, ax.C[ax.levels - 1]);
-  s.cnt = (int32_t*)take(32 * sizeof(int32_t));
+  if (solo) {
+    s.cnt = (int32_t*)take(32 * sizeof(int32_t));
+    s.nxt = (int32_t*)take((size_t)n * sizeof(int32_t));
+    s.prv = (int32_t*)take((size_t)n * sizeof(int32_t));
+  }
   s.Pw = (double*)take(3 * (size_t)n * sizeof(double));
   s.X = (uint32_t*)take(3 * (size_t)n * sizeof(uint32_t));
-  s.nxt = (int32_t*)take((size_t)n * sizeof(int32_t));
-  s.prv = (int32_t*)take((size_t)n * sizeof(int32_t));
   s.M = (double*)take(3 * (size_t)n * sizeof(double));
   s.D = (double*)take(3 * (size_t)n * sizeof(double));
   s.ka = (uint32_t*)take((size_t)n * sizeof(uint32_t));
@@ -824,7 +830,7 @@ size_t ff_layout(long long n, const FfAxes& ax, char* base, FfBufs* b) {
     s.sidx[1] = s.sidx[0];
     s.pre[1] = s.pre[0];
   }
-  s.P = (float*)take((size_t)s.S * 3 * n * sizeof(float));
+  if (solo) s.P = (float*)take((size_t)s.S * 3 * n * sizeof(float));
   if (b) *b = s;
   return (off + 255) / 256 * 256;
 }
@@ -841,7 +847,7 @@ int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::strin
   if (p->levels < 0 || p->levels > 2) { msg = "levels must be 0, 1 or 2"; return VLB_EINVAL; }
   const int top = p->levels == 2 ? 2 * p->cell : p->cell;
   if (p->cell < 1 || d->nx % top || d->ny % top || d->nz % top) {
-    msg = p->levels == 2 ? "the cell edge must be >= 1 and twice it divide nx, ny and nz"
+    msg = p->levels == 2 ? "the cell edge must be >= 1 and twice the cell edge divide nx, ny and nz"
                          : "the cell edge must be >= 1 and divide nx, ny and nz";
     return VLB_EINVAL;
   }
@@ -851,14 +857,14 @@ int ff_check(const vlb_bs_desc* d, const vlb_ff_params* p, int64_t n, std::strin
 }
 
 size_t ff_workspace(const vlb_bs_desc* d, const vlb_ff_params* p, long long n) {
-  return ff_layout(n, ff_axes(d, p), nullptr, nullptr);
+  return ff_layout(n, ff_axes(d, p), true, nullptr, nullptr);
 }
 
 hipError_t ff_solo(const vlb_bs_desc* d, const vlb_ff_params* p, long long n, const double* xyz,
                    const int32_t* next, double* v, void* ws, hipStream_t stream) {
   const FfAxes ax = ff_axes(d, p);
   FfBufs b;
-  ff_layout(n, ax, (char*)ws, &b);
+  ff_layout(n, ax, true, (char*)ws, &b);
   const int nb = (int)((n + 255) / 256);
   hipLaunchKernelGGL(k_ff_init, dim3(nb), dim3(256), 0, stream, b.prv, (int)n);
   hipLaunchKernelGGL(k_ff_prep, dim3(nb), dim3(256), 0, stream, xyz, next, (int)n, ax, b.cnt, b.Pw,
@@ -906,7 +912,9 @@ FfAxes ff_run_axes(const Run& r) {
 
 }  // namespace
 
-size_t ff_run_bytes(const Run& r) { return ff_layout(r.ncap, ff_run_axes(r), nullptr, nullptr); }
+size_t ff_run_bytes(const Run& r) {
+  return ff_layout(r.ncap, ff_run_axes(r), false, nullptr, nullptr);
+}
 
 int ff_run_chunks(const Run& r) {
   const FfAxes ax = ff_run_axes(r);
@@ -918,7 +926,7 @@ hipError_t ff_run_sum(Run& r, const double* Y) {
   const long long nc = r.ncap;
   hipStream_t stream = r.stream;
   FfBufs b;
-  ff_layout(nc, ax, (char*)r.ffws, &b);
+  ff_layout(nc, ax, false, (char*)r.ffws, &b);
   hipEvent_t t0 = nullptr;
   time_begin(r, 0, &t0);
   const int nb = (int)((nc + 255) / 256);

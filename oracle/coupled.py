@@ -2,11 +2,14 @@
 
 Order inside a step (the paper does not state one; reading R17):
   1. From the normal-fluid state f^n: bare velocity field u_b and, if
-     enabled, the mass-balance superflow V_s(z) (Sec. III.C).
-  2. Filaments: classical RK4 with dt = 1 lattice step (reading R6) on the
-     equation of motion (Sec. II.A, Eq. E of M), with u_b and V_s frozen at
-     time n.  The mutual-friction force is taken from the first stage (the
-     positions s^n).
+     enabled, the mass-balance superflow V_s along the flow axis (Sec.
+     III.C).
+  2. Filaments: the equation of motion (Sec. II.A, Eq. E of M) integrated
+     over dt = 1 lattice step (reading R6) by an explicit Runge-Kutta
+     method (by default the classical RK4 in one step; optionally 1 or 2
+     stages and several substeps of 1/m), with u_b and V_s frozen at time
+     n.  The mutual-friction force is taken from the first stage of the
+     first substep (the positions s^n).
   3. Normal fluid: the force is spread onto the lattice (Sec. II.B) and one
      forced LBM update f^n -> f^{n+1} is made.
   4. Topology: remeshing, reconnection, small-loop removal (Sec. II.A, III.B).
@@ -52,28 +55,56 @@ def make_state(rho, u, pos, nxt, lat: Lattice):
                  force=np.zeros((3,) + lat.shape))
 
 
-def filament_rk4(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams):
-    """Classical RK4 of ds/dt on the filaments; returns the new positions,
-    the stage-1 quantities (velocities and force per point)."""
-    s0 = pos
-    st1 = vfm.line_velocity(s0, nxt, prv, ub, Vs, lat, vp, want_force=vp.coupling)
-    k1 = st1["sdot"]
-    y = vfm.wrap_positions(s0 + 0.5 * k1, lat)
-    k2 = vfm.line_velocity(y, nxt, prv, ub, Vs, lat, vp)["sdot"]
-    y = vfm.wrap_positions(s0 + 0.5 * k2, lat)
-    k3 = vfm.line_velocity(y, nxt, prv, ub, Vs, lat, vp)["sdot"]
-    y = vfm.wrap_positions(s0 + k3, lat)
-    k4 = vfm.line_velocity(y, nxt, prv, ub, Vs, lat, vp)["sdot"]
-    s1 = vfm.wrap_positions(s0 + (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0, lat)
-    return s1, st1
+def rk_step(s0, velocity, wrap, h, stages, k1=None):
+    """One step of length h of ds/dt = velocity(s) by an explicit
+    Runge-Kutta method: stages = 1 forward Euler, 2 the midpoint rule, 4 the
+    classical fourth-order method.  ``wrap`` maps positions back into the
+    box after every update; ``k1`` is velocity(s0) when already known."""
+    if k1 is None:
+        k1 = velocity(s0)
+    if stages == 1:
+        return wrap(s0 + h * k1)
+    hh = 0.5 * h
+    k2 = velocity(wrap(s0 + hh * k1))
+    if stages == 2:
+        return wrap(s0 + h * k2)
+    if stages != 4:
+        raise ValueError("rk_stages must be 1, 2 or 4")
+    k3 = velocity(wrap(s0 + hh * k2))
+    k4 = velocity(wrap(s0 + h * k3))
+    return wrap(s0 + h * ((k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0))
+
+
+def filament_advance(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams):
+    """Positions after one lattice step: vp.vfm_substeps steps of length
+    1/vfm_substeps of the vp.rk_stages-stage method, with u_b and V_s
+    frozen.  Returns the new positions and the quantities of the first
+    stage of the first substep (velocities and force per point)."""
+    m = int(vp.vfm_substeps)
+    if m < 1:
+        raise ValueError("vfm_substeps must be >= 1")
+    h = 1.0 / m
+    st1 = vfm.line_velocity(pos, nxt, prv, ub, Vs, lat, vp, want_force=vp.coupling)
+
+    def velocity(y):
+        return vfm.line_velocity(y, nxt, prv, ub, Vs, lat, vp)["sdot"]
+
+    def wrap(y):
+        return vfm.wrap_positions(y, lat)
+
+    s = pos
+    for i in range(m):
+        s = rk_step(s, velocity, wrap, h, vp.rk_stages, k1=st1["sdot"] if i == 0 else None)
+    return s, st1
 
 
 def coupled_step(st: State, lat: Lattice, vp: VortexParams):
     """Advance the state by one step (see module docstring)."""
     _, ub = lbm.bare_velocity(st.f, lat)
-    Vs = lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n) if vp.mass_balance else None
+    Vs = (lbm.mass_balance_superflow(st.f, lat, vp.rho_s_over_rho_n, vp.mass_balance_axis)
+          if vp.mass_balance else None)
     if st.pos.shape[0] > 0:
-        s1, st1 = filament_rk4(st.pos, st.nxt, st.prv, ub, Vs, lat, vp)
+        s1, st1 = filament_advance(st.pos, st.nxt, st.prv, ub, Vs, lat, vp)
         if vp.coupling:
             F = vfm.spread(st1["force"], st.pos, lat)
         else:

@@ -174,11 +174,15 @@ def init_equilibrium(rho, u):
     return equilibrium(rho, u)
 
 
-def mass_balance_superflow(f, lat: Lattice, rho_s_over_rho_n):
-    """Superflow from mass conservation (Sec. III.C, Eq. mass cons):
-    V_s(z) = -(rho_n/rho_s) (1/A) sum over the cross-section of u_n,z.
-    The flow axis is z here (the paper's x); u_n is the bare velocity of the
-    effective populations.  Returns an array of nz values."""
+def mass_balance_superflow(f, lat: Lattice, rho_s_over_rho_n, axis=2):
+    """Superflow from mass conservation (Sec. III.C, Eq. mass cons) along the
+    flow axis a (the paper's is x; the channel workloads here use z):
+    V_s(x_a) = -(rho_n/rho_s) (1/A) sum over the cross-section normal to
+    axis a of u_n,a, with u_n the bare velocity of the effective
+    populations and A the node count of a cross-section.  Returns one value
+    per node along axis a."""
     _, ub = bare_velocity(f, lat)
-    area = lat.nx * lat.ny
-    return -(1.0 / rho_s_over_rho_n) * ub[2].sum(axis=(1, 2)) / area
+    # ub[c] is indexed [z, y, x]: lattice axis a is array axis 2 - a
+    others = tuple(k for k in range(3) if k != 2 - axis)
+    area = (lat.nx * lat.ny * lat.nz) // lat.dims[axis]
+    return -(1.0 / rho_s_over_rho_n) * ub[axis].sum(axis=others) / area

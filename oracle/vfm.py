@@ -36,7 +36,8 @@ class VortexParams:
     reconnect: bool = False
     min_loop_pts: int = 5
     coupling: bool = True       # False: prescribed normal fluid, no back-reaction
-    mass_balance: bool = False  # superflow V_s(z) from Eq. (mass cons)
+    mass_balance: bool = False  # superflow V_s from Eq. (mass cons)
+    mass_balance_axis: int = 2  # its flow axis (0, 1, 2 = x, y, z; periodic)
     vs_applied: tuple = (0.0, 0.0, 0.0)  # externally applied v_s,a (Sec. II.A)
     # mutual-friction coefficients varying along z (Sec. IV: temperature
     # dependent alpha, alpha' over the channel; reading D4): nz slice values
@@ -55,6 +56,12 @@ class VortexParams:
     ff_cell: int = 0
     ff_levels: int = 1
     ff_theta: float = 0.25
+    # time integration of ds/dt over one lattice step (reading R6): an
+    # explicit Runge-Kutta method of rk_stages stages (1 forward Euler, 2
+    # the midpoint rule, 4 the classical method) applied vfm_substeps times
+    # with steps of 1/vfm_substeps
+    rk_stages: int = 4
+    vfm_substeps: int = 1
 
 
 # ---------------------------------------------------------------- geometry
@@ -416,12 +423,13 @@ def mutual_friction_force(sdot, vs, sp, dxi, vp: VortexParams):
     return vp.rho_s_over_rho_n * vp.kappa * w * dxi[:, None]
 
 
-def superflow_at(Vs, z, nz):
-    """Mass-balance superflow at a point: V_s(z) between slice values,
-    delta_2pt-weighted along z with periodic wrap."""
-    iz = np.floor(z).astype(np.int64)
-    fz = z - iz
-    return (1.0 - fz) * Vs[np.mod(iz, nz)] + fz * Vs[np.mod(iz + 1, nz)]
+def superflow_at(Vs, x, n):
+    """Mass-balance superflow at points of coordinate x along the flow axis
+    (n nodes, periodic): V_s between the slice values at floor(x) and
+    floor(x) + 1, delta_2pt-weighted (linear)."""
+    ix = np.floor(x).astype(np.int64)
+    fx = x - ix
+    return (1.0 - fx) * Vs[np.mod(ix, n)] + fx * Vs[np.mod(ix + 1, n)]
 
 
 def friction_at(vp: VortexParams, z, lat: Lattice):
@@ -466,7 +474,8 @@ def line_velocity(pos, nxt, prv, ub, Vs, lat: Lattice, vp: VortexParams, want_fo
         vs = vs + biot_savart_images(pos, nxt, prv, lat, vp.kappa)
     vs = vs + np.array(vp.vs_applied, dtype=np.float64)[None, :]
     if Vs is not None:
-        vs[:, 2] = vs[:, 2] + superflow_at(Vs, pos[:, 2], lat.nz)
+        a = vp.mass_balance_axis
+        vs[:, a] = vs[:, a] + superflow_at(Vs, pos[:, a], lat.dims[a])
     vn = interpolate(ub, pos, lat)
     alpha, alpha_p = friction_at(vp, pos[:, 2], lat)
     sdot = schwarz_velocity(vs, vn, geo["sp"], alpha, alpha_p)

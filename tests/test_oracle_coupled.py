@@ -49,7 +49,7 @@ def test_lia_ring_decay_trend():
     for _ in range(40):
         c = pos.mean(axis=0)
         R2.append(((pos[:, :2] - c[:2]) ** 2).sum(axis=1).mean())
-        pos, _ = coupled.filament_rk4(pos, nxt, prv, ub, None, lat, vp)
+        pos, _ = coupled.filament_advance(pos, nxt, prv, ub, None, lat, vp)
     R2 = np.array(R2)
     slope = np.polyfit(np.arange(40), R2, 1)[0]
     V = 0.1 / (4 * np.pi * 8.0) * (math.log(64 / 1e-3) - 0.5) * 1.0073

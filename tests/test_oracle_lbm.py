@@ -235,3 +235,27 @@ def test_mass_balance_uniform_flow():
     f = lbm.init_equilibrium(rho, u)
     Vs = lbm.mass_balance_superflow(f, lat, 1.35)
     np.testing.assert_allclose(Vs, -0.02 / 1.35, rtol=1e-13)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mass_balance_along_each_axis(axis):
+    """The superflow follows the flow axis a (Sec. III.C, Eq. mass cons: the
+    mean over each cross-section normal to a of u_a): with u_a = g(x_a)
+    plus a part of zero mean over every cross-section, V_s = -(rho_n/rho_s)
+    g exactly; the other components, made large here, do not enter."""
+    lat = Lattice(6, 4, 5)
+    n = lat.dims[axis]
+    rho = np.ones(lat.shape)
+    z, y, x = np.meshgrid(np.arange(5), np.arange(4), np.arange(6), indexing="ij")
+    coord = (x, y, z)
+    g = 0.01 + 0.004 * np.arange(n) / n
+    u = np.zeros((3,) + lat.shape)
+    for c in range(3):
+        u[c] = 0.05 * (c + 1)
+    o1, o2 = [b for b in range(3) if b != axis]
+    u[axis] = (g[coord[axis]] + 0.003 * np.cos(2 * np.pi * coord[o1] / lat.dims[o1])
+               + 0.002 * np.sin(2 * np.pi * coord[o2] / lat.dims[o2]))
+    f = lbm.init_equilibrium(rho, u)
+    Vs = lbm.mass_balance_superflow(f, lat, 1.35, axis)
+    assert Vs.shape == (n,)
+    np.testing.assert_allclose(Vs, -g / 1.35, rtol=0, atol=1e-15)

@@ -260,6 +260,84 @@ def test_superflow_lookup():
     np.testing.assert_allclose(vfm.superflow_at(Vs, z, 4), [1.0, 1.5, 5.0, 4.5])
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_superflow_on_its_axis(axis):
+    """The mass-balance superflow adds to v_s along the flow axis only, at
+    the point's coordinate on that axis: slice values equal to their index
+    shift v_s,a by the coordinate itself (linear between slices)."""
+    vp = VortexParams(mass_balance=True, mass_balance_axis=axis)
+    lat, pos, nxt, prv = _ring_state(64, R=6.0, L=32, center=(13.0, 15.0, 17.0),
+                                     normal=(0.3, -0.5, 0.8))
+    ub = np.zeros((3,) + lat.shape)
+    base = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp)["vs"]
+    Vs = np.arange(lat.dims[axis], dtype=np.float64)
+    got = vfm.line_velocity(pos, nxt, prv, ub, Vs, lat, vp)["vs"]
+    for a in range(3):
+        want = base[:, a] + (pos[:, a] if a == axis else 0.0)
+        np.testing.assert_allclose(got[:, a], want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 4])
+def test_rk_step_is_the_taylor_polynomial_on_a_linear_system(stages):
+    """On ds/dt = A s an explicit Runge-Kutta method of p = 1, 2, 4 stages
+    and order p (forward Euler, the midpoint rule, the classical method)
+    maps s0 to sum_{k <= p} (hA)^k / k! s0 exactly (a textbook property);
+    a wrong stage weight or offset breaks the polynomial."""
+    rng = np.random.default_rng(7)
+    A = rng.normal(size=(3, 3))
+    s0 = rng.normal(size=(5, 3))
+    h = 0.3
+    got = coupled.rk_step(s0, lambda s: s @ A.T, lambda s: s, h, stages)
+    P = np.eye(3)
+    term = np.eye(3)
+    for k in range(1, stages + 1):
+        term = term @ (h * A) / k
+        P = P + term
+    np.testing.assert_allclose(got, s0 @ P.T, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("stages,substeps", [(4, 1), (4, 3), (2, 2), (1, 4)])
+def test_straight_line_in_rotating_normal_fluid(stages, substeps):
+    """A straight line along z through the periodic box has v_s = 0 (every
+    segment is collinear with every point; no curvature).  In a normal
+    fluid rotating rigidly about z, v_n = Omega z x (s - c) is linear in the
+    position, so the equation of motion (Sec. II.A, Eq. E of M) reduces to
+    d(s - c)/dt = B (s - c) in the xy plane, B = Omega (-alpha I + alpha' J)
+    with J the rotation by 90 degrees.  m substeps of the p-stage method
+    therefore give (sum_{k <= p} (B/m)^k / k!)^m (s - c) exactly, z
+    unchanged."""
+    n = 32
+    lat = Lattice(n, n, n)
+    om, al, alp = 0.5, 0.2, 0.1
+    vp = VortexParams(alpha=al, alpha_p=alp, coupling=False, rk_stages=stages,
+                      vfm_substeps=substeps)
+    c = np.array([15.5, 15.5])
+    npts = n
+    pos = np.zeros((npts, 3))
+    pos[:, 0] = 18.25
+    pos[:, 1] = 13.75
+    pos[:, 2] = np.arange(npts) + 0.5
+    nxt = (np.arange(npts) + 1) % npts
+    prv = coupled.prev_from_next(nxt)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ub = np.zeros((3,) + lat.shape)
+    ub[0] = -om * (y - c[1])
+    ub[1] = om * (x - c[0])
+    s1, _ = coupled.filament_advance(pos, nxt, prv, ub, None, lat, vp)
+    B = om * np.array([[-al, -alp], [alp, -al]])
+    hB = B / substeps
+    P = np.eye(2)
+    term = np.eye(2)
+    for k in range(1, stages + 1):
+        term = term @ hB / k
+        P = P + term
+    r = pos[0, :2] - c
+    for _ in range(substeps):
+        r = P @ r
+    np.testing.assert_allclose(s1[:, :2], np.broadcast_to(c + r, (npts, 2)), rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(s1[:, 2], pos[:, 2])
+
+
 def test_ring_one_step_one_way():
     """Prescribed still normal fluid, no back-reaction: one RK4 step moves the
     ring forward by (1 - alpha')V and shrinks it by alpha V (V nearly constant
@@ -269,7 +347,7 @@ def test_ring_one_step_one_way():
     vs, _ = _ring_vs(lat, pos, nxt, prv, vp)
     V = vs[0, 2]
     ub = np.zeros((3,) + lat.shape)
-    s1, _ = coupled.filament_rk4(pos, nxt, prv, ub, None, lat, vp)
+    s1, _ = coupled.filament_advance(pos, nxt, prv, ub, None, lat, vp)
     R1 = np.sqrt(((s1[:, :2] - 16.0) ** 2).sum(axis=1)).mean()
     dz = (s1[:, 2] - pos[:, 2]).mean()
     assert dz == pytest.approx(0.99 * V, rel=2e-3)

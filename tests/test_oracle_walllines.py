@@ -163,7 +163,7 @@ def test_end_points_slide_and_carry_half_their_segment():
     out = vfm.line_velocity(pos, nxt, prv, ub, None, lat, vp, want_force=True)
     assert out["sdot"][0, 2] == 0.0 and out["sdot"][-1, 2] == 0.0
     assert np.abs(out["sdot"][1:-1, 2]).min() > 0.0
-    s1, _ = coupled.filament_rk4(pos, nxt, prv, ub, None, lat, vp)
+    s1, _ = coupled.filament_advance(pos, nxt, prv, ub, None, lat, vp)
     assert s1[0, 2] == -0.5 and s1[-1, 2] == nz - 0.5
     geo = out["geo"]
     l_first = np.linalg.norm(pos[1] - pos[0])

@@ -162,7 +162,8 @@ VORTEX_DEFAULTS = dict(
     kappa=0.1, core_a=1e-3, core_c=0.5, alpha=0.2, alpha_p=0.01,
     rho_s_over_rho_n=1.35, dxi_min=0.70, dxi_max=0.95, reconnect_dist=0.95,
     remesh=True, reconnect=False, min_loop_pts=5, coupling=True,
-    mass_balance=False, vs_applied=(0.0, 0.0, 0.0),
+    mass_balance=False, mass_balance_axis=2, vs_applied=(0.0, 0.0, 0.0),
+    rk_stages=4, vfm_substeps=1,
 )
 
 

@@ -95,9 +95,13 @@ typedef struct {
   int32_t min_loop_pts;   /* loops with fewer points are removed (>= 3)     */
   int32_t coupling;       /* 1: the mutual-friction force acts on the
                              normal fluid; 0: prescribed normal fluid       */
-  int32_t mass_balance;   /* 1: superflow V_s(z) from mass conservation
-                             along z (Sec. III.C, Eq. mass cons); z must be
-                             periodic                                       */
+  int32_t mass_balance;   /* 1: superflow V_s from mass conservation
+                             along the flow axis mass_balance_axis (Sec.
+                             III.C, Eq. mass cons): minus rho_n/rho_s times
+                             the mean of u_n along that axis over each
+                             cross-section normal to it, added to v_s along
+                             it (linear between cross-sections); that axis
+                             must be periodic                               */
   int32_t force_model;    /* reaction on the normal fluid per length
                              (Sec. II.B, Eq. f): 0 = rho_s kappa s' x
                              (ds/dt - v_s), the Magnus balance; 1 = rho_s
@@ -112,7 +116,8 @@ typedef struct {
                              copies for w closed axes, each summed like the
                              real filaments, none excluded); 0: v_s,b = 0.
                              The Biot-Savart work grows 3^w-fold.           */
-  int32_t reserved1;      /* 0                                              */
+  int32_t mass_balance_axis; /* flow axis of the mass balance: 0, 1, 2 for
+                             x, y, z (the paper's channel flows along x)    */
   int64_t n_cap;          /* capacity in filament points (>= 1)             */
   int64_t recon_cap;      /* capacity in reconnection candidates per step   */
   int32_t ff_cell;        /* 0: the non-local sum of every stage is the
@@ -124,6 +129,21 @@ typedef struct {
                              wall images                                    */
   int32_t ff_levels;      /* levels of cells of that approximation (0, 1, 2) */
   double ff_theta;        /* its opening parameter, 0 < ff_theta < 1        */
+  int32_t rk_stages;      /* time integration of the filaments over one
+                             lattice step (Sec. II.A, Eq. E of M; the paper
+                             names no method): an explicit Runge-Kutta
+                             method of 1 (forward Euler), 2 (the midpoint
+                             rule) or 4 (the classical method) stages; 0
+                             means 4.  Each stage is one Biot-Savart sum    */
+  int32_t vfm_substeps;   /* that method applied this many times per
+                             lattice step with steps of 1/vfm_substeps, in
+                             [1, 64] (0 means 1), for stiff filaments (large
+                             kappa, short segments).  The normal-fluid
+                             velocity and the superflow stay those of the
+                             step's start; the force on the normal fluid is
+                             that of the step's start positions; remeshing
+                             and reconnection follow the last substep       */
+  int32_t reserved2;      /* 0                                              */
 } vlb_vortex_desc;
 
 /* Bytes of device workspace a run with these descriptors needs.           */

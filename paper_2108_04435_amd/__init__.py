@@ -66,10 +66,12 @@ class VortexDesc(ctypes.Structure):
         ("remesh", ctypes.c_int32), ("reconnect", ctypes.c_int32),
         ("min_loop_pts", ctypes.c_int32), ("coupling", ctypes.c_int32),
         ("mass_balance", ctypes.c_int32), ("force_model", ctypes.c_int32),
-        ("wall_images", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("wall_images", ctypes.c_int32), ("mass_balance_axis", ctypes.c_int32),
         ("n_cap", ctypes.c_int64), ("recon_cap", ctypes.c_int64),
         ("ff_cell", ctypes.c_int32), ("ff_levels", ctypes.c_int32),
         ("ff_theta", ctypes.c_double),
+        ("rk_stages", ctypes.c_int32), ("vfm_substeps", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -187,12 +189,15 @@ def vortex_desc(vor: dict, n_cap: int, recon_cap: int = 1 << 16) -> VortexDesc:
     d.mass_balance = int(bool(vor.get("mass_balance", False)))
     d.force_model = int(vor.get("force_model", 0))
     d.wall_images = int(bool(vor.get("wall_images", False)))
-    d.reserved1 = 0
+    d.mass_balance_axis = int(vor.get("mass_balance_axis", 2))
     d.n_cap = int(n_cap)
     d.recon_cap = int(recon_cap)
     d.ff_cell = int(vor.get("ff_cell", 0))
     d.ff_levels = int(vor.get("ff_levels", 1))
     d.ff_theta = float(vor.get("ff_theta", 0.25))
+    d.rk_stages = int(vor.get("rk_stages", 4))
+    d.vfm_substeps = int(vor.get("vfm_substeps", 1))
+    d.reserved2 = 0
     return d
 
 

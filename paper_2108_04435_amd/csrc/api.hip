@@ -81,7 +81,11 @@ int check_desc(const vlb_lattice_desc* lat, const vlb_vortex_desc* vor, std::str
   if (!(vor->kappa > 0) || !(vor->core_a > 0)) { msg = "kappa and core_a must be positive"; return VLB_EINVAL; }
   if (!(vor->dxi_min > 0) || !(vor->dxi_max > vor->dxi_min)) { msg = "need 0 < dxi_min < dxi_max"; return VLB_EINVAL; }
   if (vor->min_loop_pts < 3) { msg = "min_loop_pts must be >= 3"; return VLB_EINVAL; }
-  if (vor->mass_balance && (lat->wall_axes & 4u)) { msg = "mass balance needs a periodic z axis"; return VLB_EINVAL; }
+  if (vor->mass_balance_axis < 0 || vor->mass_balance_axis > 2) { msg = "mass_balance_axis must be 0, 1 or 2"; return VLB_EINVAL; }
+  if (vor->mass_balance && ((lat->wall_axes >> vor->mass_balance_axis) & 1u)) { msg = "mass balance needs a periodic flow axis"; return VLB_EINVAL; }
+  if (vor->rk_stages != 0 && vor->rk_stages != 1 && vor->rk_stages != 2 && vor->rk_stages != 4) { msg = "rk_stages must be 1, 2 or 4 (0: 4)"; return VLB_EINVAL; }
+  if (vor->vfm_substeps < 0 || vor->vfm_substeps > 64) { msg = "vfm_substeps must be in [1, 64] (0: 1)"; return VLB_EINVAL; }
+  if (vor->reserved2 != 0) { msg = "reserved2 must be 0"; return VLB_EINVAL; }
   if (vor->force_model != 0 && vor->force_model != 1) { msg = "force_model must be 0 or 1"; return VLB_EINVAL; }
   if (vor->wall_images != 0 && vor->wall_images != 1) { msg = "wall_images must be 0 or 1"; return VLB_EINVAL; }
   if (vor->ff_cell < 0) { msg = "ff_cell must be >= 0"; return VLB_EINVAL; }
@@ -127,8 +131,13 @@ size_t layout(Run& r, char* base) {
   const size_t fe = r.prec == VLB_F64 ? 8 : 4;
   r.pops = B.take(19 * cells * elt_size(r.prec));
   r.force = B.take(3 * cells * fe);
-  r.Vs = (double*)B.take(r.geom.nz * sizeof(double));
-  r.Vs_next = (double*)B.take(r.geom.nz * sizeof(double));
+  // superflow per cross-section along the flow axis; along x or y also the
+  // per-z-slice partial sums of its mean
+  const int mba = r.vor.mass_balance_axis;
+  const int nmb = mba == 0 ? r.geom.nx : (mba == 1 ? r.geom.ny : r.geom.nz);
+  r.Vs = (double*)B.take(nmb * sizeof(double));
+  r.Vs_next = (double*)B.take(nmb * sizeof(double));
+  r.mbP = (double*)B.take((r.vor.mass_balance && mba != 2 ? (size_t)r.geom.nz * nmb : 0) * sizeof(double));
   r.diag = (double*)B.take((8 + (size_t)kSlabChunks * r.geom.nz) * sizeof(double));
   r.seg = (double*)B.take(3 * (size_t)nc * sizeof(double));
   r.fric = (double*)B.take((2 * (size_t)r.geom.nz + 1) * sizeof(double));
@@ -182,6 +191,8 @@ size_t layout(Run& r, char* base) {
 void init_run(Run& r, const vlb_lattice_desc* lat, const vlb_vortex_desc* vor) {
   r.lat = *lat;
   r.vor = *vor;
+  if (r.vor.rk_stages == 0) r.vor.rk_stages = 4;
+  if (r.vor.vfm_substeps == 0) r.vor.vfm_substeps = 1;
   r.prec = lat->precision;
   r.cells = (long long)lat->nx * lat->ny * lat->nz;
   r.ncap = vor->n_cap;
@@ -542,14 +553,28 @@ int one_step(vlb_run* h, bool first, bool last) {
     HIP_OR_FAIL(h, lbm_moments(r));
     HIP_OR_FAIL(h, hipEventRecord(r.ev_mom, S));
   }
-  // filament RK4: stage positions s^n (pos) -> ya -> yb -> ya -> pos
-  double* Ys[4] = {r.pos, r.ya, r.yb, r.ya};
-  double* Yn[4] = {r.ya, r.yb, r.ya, r.pos};
+  // filament stages: vfm_substeps substeps of the rk_stages-stage method,
+  // each from the positions in pos back into pos; stage positions
+  // classical: pos -> ya -> yb -> ya -> pos; midpoint: pos -> ya -> pos;
+  // Euler: pos -> ya, copied back
+  const int K = r.vor.rk_stages;
+  const int G = K * r.vor.vfm_substeps;
+  double* Ys4[4] = {r.pos, r.ya, r.yb, r.ya};
+  double* Yn4[4] = {r.ya, r.yb, r.ya, r.pos};
+  double* Ys2[2] = {r.pos, r.ya};
+  double* Yn2[2] = {r.ya, r.pos};
+  double* Yn1[1] = {r.ya};
+  double** Ys = K == 4 ? Ys4 : Ys2;
+  double** Yn = K == 4 ? Yn4 : (K == 2 ? Yn2 : Yn1);
   const bool spread = r.vor.coupling != 0;
-  for (int s = 0; s < 4; ++s) {
+  // the side stream's work follows the second stage (the first if there is
+  // only one)
+  const int gside = G > 1 ? 1 : 0;
+  for (int gs = 0; gs < G; ++gs) {
+    const int s = gs % K;
     // FP32: the grid coordinates of every stage's positions were written by
     // the kernel that wrote the positions (seeding and the topology's copy
-    // for stage 1, the previous finalize for stages 2-4)
+    // for the step's first stage, the previous finalize for the others)
     if (r.vor.ff_cell > 0) {
       HIP_OR_FAIL(h, ff_run_sum(r, Ys[s]));
     } else {
@@ -557,14 +582,15 @@ int one_step(vlb_run* h, bool first, bool last) {
       HIP_OR_FAIL(h, bs_sum(r));
     }
     // the first finalize reads the velocity field and the superflow
-    if (s == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
-    HIP_OR_FAIL(h, fil_finalize(r, s + 1, Ys[s], Yn[s], 0));
+    if (gs == 0) HIP_OR_FAIL(h, hipStreamWaitEvent(M, r.ev_mom, 0));
+    HIP_OR_FAIL(h, fil_finalize(r, s + 1, gs == 0, gs == G - 1, Ys[s], Yn[s], 0));
+    if (K == 1) HIP_OR_FAIL(h, fil_copy_positions(r, r.ya, r.pos));
     // finalize 1 leaves the spreading everything it reads, and it follows
     // the previous step's last reads of the field the next moments overwrite
-    if (s == 0) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
+    if (gs == 0) HIP_OR_FAIL(h, hipEventRecord(r.ev_fin1, M));
     // the side stream's work is enqueued after the main stream's next
     // kernel, so that a graph keeps the main chain on one queue
-    if (s == 1) {
+    if (gs == gside) {
       HIP_OR_FAIL(h, hipStreamWaitEvent(S, r.ev_fin1, 0));
       OnStream on(r, S);
       if (spread) HIP_OR_FAIL(h, fil_spread(r));
@@ -711,7 +737,7 @@ int vlb_eval_line_velocity(vlb_run* h, double* vs, double* vn, double* sdot, dou
     HIP_OR_FAIL(h, bs_prep(r, r.pos));
     HIP_OR_FAIL(h, bs_sum(r));
   }
-  HIP_OR_FAIL(h, fil_finalize(r, 1, r.pos, r.ya, 1));
+  HIP_OR_FAIL(h, fil_finalize(r, 1, 1, 1, r.pos, r.ya, 1));
   if (r.vor.coupling) HIP_OR_FAIL(h, fil_spread(r));
   int32_t n = 0;
   int c = read_count(h, &n);

@@ -69,7 +69,11 @@ struct FinArgs {
   long long ncap;
   const double* Vs;
   int mass_balance;
-  int stage;
+  int mb_axis;      // flow axis of the superflow
+  int stage;        // stage of the Runge-Kutta method, 1..rk
+  int rk;           // stages of the method: 1, 2 or 4
+  int first;        // first stage of the step's first substep: stage-1 outputs
+  double h, hh;     // substep length 1/m and half of it
   int eval_only;
   int coupling;
   int force_model;  // 0: s' x (ds/dt - v_s) (Magnus balance); 1: ds/dt - v_s
@@ -272,12 +276,14 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
         s_rk[3 + a][lane] = A.stage > 1 ? A.ksum[a * nc + j] : 0.0;
       }
     if (A.mass_balance) {
-      const double pz = A.Y[2 * nc + j];
+      const int ma = A.mb_axis;
+      const int nm = ma == 0 ? g.nx : (ma == 1 ? g.ny : g.nz);
+      const double pz = A.Y[ma * nc + j];
       const double fz = floor(pz);
       const double t = pz - fz;
       int i0 = ifloor_safe(pz), i1 = i0 + 1;
-      i0 = ((i0 % g.nz) + g.nz) % g.nz;
-      i1 = ((i1 % g.nz) + g.nz) % g.nz;
+      i0 = ((i0 % nm) + nm) % nm;
+      i1 = ((i1 % nm) + nm) % nm;
       s_rk[6][lane] = (1.0 - t) * A.Vs[i0] + t * A.Vs[i1];
     }
     // mutual-friction coefficients at the point's height: the constants,
@@ -345,7 +351,7 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   }
   const double lp = s_geo[6][lane], lm = s_geo[7][lane];
   for (int a = 0; a < 3; ++a) vs[a] += A.vs_app[a];
-  if (A.mass_balance) vs[2] += s_rk[6][lane];
+  if (A.mass_balance) vs[A.mb_axis] += s_rk[6][lane];
 
   // normal-fluid velocity at the point
   const double vn[3] = {s_vn[0][lane], s_vn[1][lane], s_vn[2][lane]};
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   if (!(isfinite(sd[0]) && isfinite(sd[1]) && isfinite(sd[2])))
     atomicOr(&A.cnt[7], kFlagNumeric);
 
-  if (A.stage == 1) {
+  if (A.first) {
     for (int a = 0; a < 3; ++a) {
       A.vs1[a * nc + j] = vs[a];
       A.vn1[a * nc + j] = vn[a];
@@ -384,29 +390,37 @@ __global__ __launch_bounds__(kFinWaves * 64) void k_finalize(FinArgs A) {
   }
   if (A.eval_only) return;
 
-  // RK4: ksum = k1 + 2 k2 + 2 k3 + k4, stage positions s^n + c k
+  // Runge-Kutta over a substep of length h from s0 (the substep's start):
+  // classical (4 stages): ksum = k1 + 2 k2 + 2 k3 + k4, stage positions
+  // s0 + (h/2) k1, s0 + (h/2) k2, s0 + h k3, result s0 + h ksum / 6;
+  // midpoint (2): s0 + (h/2) k1, result s0 + h k2; Euler (1): s0 + h k1
   for (int a = 0; a < 3; ++a) {
     const double s0 = s_rk[a][lane];
     const double kp = s_rk[3 + a][lane];
-    double ks;
+    double ks = sd[a];
     double y;
-    switch (A.stage) {
-      case 1:
-        ks = sd[a];
-        y = s0 + 0.5 * sd[a];
-        break;
-      case 2:
-        ks = kp + 2.0 * sd[a];
-        y = s0 + 0.5 * sd[a];
-        break;
-      case 3:
-        ks = kp + 2.0 * sd[a];
-        y = s0 + sd[a];
-        break;
-      default:
-        ks = kp + sd[a];
-        y = s0 + ks / 6.0;
-        break;
+    if (A.rk == 4) {
+      switch (A.stage) {
+        case 1:
+          y = s0 + A.hh * sd[a];
+          break;
+        case 2:
+          ks = kp + 2.0 * sd[a];
+          y = s0 + A.hh * sd[a];
+          break;
+        case 3:
+          ks = kp + 2.0 * sd[a];
+          y = s0 + A.h * sd[a];
+          break;
+        default:
+          ks = kp + sd[a];
+          y = s0 + A.h * (ks / 6.0);
+          break;
+      }
+    } else if (A.rk == 2 && A.stage == 1) {
+      y = s0 + A.hh * sd[a];
+    } else {
+      y = s0 + A.h * sd[a];
     }
     A.ksum[a * nc + j] = ks;
     const double yw = wrap_coord(y, L[a], per[a]);
@@ -568,7 +582,8 @@ inline int nblocks(long long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only) {
+hipError_t fil_finalize(Run& r, int stage, int first, int last, const double* Y, double* Ynext,
+                        int eval_only) {
   FinArgs A;
   A.ub = r.ub;
   A.g = r.geom;
@@ -584,7 +599,12 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.ncap = r.ncap;
   A.Vs = r.Vs;
   A.mass_balance = r.vor.mass_balance;
+  A.mb_axis = r.vor.mass_balance_axis;
   A.stage = stage;
+  A.rk = r.vor.rk_stages;
+  A.first = first;
+  A.h = 1.0 / r.vor.vfm_substeps;
+  A.hh = 0.5 * A.h;
   A.eval_only = eval_only;
   A.coupling = r.vor.coupling;
   A.kappa = r.vor.kappa;
@@ -606,16 +626,29 @@ hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int e
   A.sd1 = r.sd1;
   A.gpt = r.gpt;
   // the FP32 sum of the next stage reads grid coordinates written here
-  A.X = (r.prec != VLB_F64 && stage < 4 && !eval_only) ? r.bsX : nullptr;
+  A.X = (r.prec != VLB_F64 && !last && !eval_only) ? r.bsX : nullptr;
   A.ax = r.bsax;
   A.sg = spread_geom(r);
-  A.skeys = (stage == 1 && r.vor.coupling) ? r.keys_a : nullptr;
+  A.skeys = (first && r.vor.coupling) ? r.keys_a : nullptr;
   A.sfrac = r.sfrac;
   const int nb = nblocks(r.ncap, kFinPts);
   switch (r.prec) {
     case VLB_F64: hipLaunchKernelGGL((k_finalize<double, double>), dim3(nb), dim3(kFinWaves * 64), 0, r.stream, A); break;
     default: hipLaunchKernelGGL((k_finalize<float, float>), dim3(nb), dim3(kFinWaves * 64), 0, r.stream, A); break;
   }
+  return hipGetLastError();
+}
+
+// Positions copied slot by slot (3 n_cap values): forward Euler writes its
+// result beside the positions it reads and copies it back.
+__global__ void k_copy_pos(const double* __restrict__ src, double* __restrict__ dst, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t fil_copy_positions(Run& r, const double* src, double* dst) {
+  const long long n = 3 * r.ncap;
+  hipLaunchKernelGGL(k_copy_pos, dim3(nblocks(n, 256)), dim3(256), 0, r.stream, src, dst, n);
   return hipGetLastError();
 }
 

@@ -547,6 +547,35 @@ __global__ __launch_bounds__(1024) void k_moments(const S* __restrict__ M, Geom 
   if (tid == 0) Vs[z] = scale * red[0];
 }
 
+// Mass balance along x or y (flow axis a): for each z slice and each node
+// position i along a, the sum of u_a over the slice's other axis in
+// ascending order (one thread per (i, z)); then for each i the slice sums
+// in ascending z, Vs[i] = scale * total.  u_a is the bare velocity the
+// moments kernel wrote.
+template <class UT>
+__global__ void k_mb_partial(const UT* __restrict__ ua, Geom g, int axis, double* __restrict__ P) {
+  const int z = blockIdx.y;
+  const int n = axis == 0 ? g.nx : g.ny;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long slice = (long long)z * g.ny * g.nx;
+  double s = 0.0;
+  if (axis == 0)
+    for (int y = 0; y < g.ny; ++y) s += (double)ua[slice + (long long)y * g.nx + i];
+  else
+    for (int x = 0; x < g.nx; ++x) s += (double)ua[slice + (long long)i * g.nx + x];
+  P[(long long)z * n + i] = s;
+}
+
+__global__ void k_mb_total(const double* __restrict__ P, int nz, int n, double scale,
+                           double* __restrict__ Vs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += P[(long long)z * n + i];
+  Vs[i] = scale * s;
+}
+
 // Sum of v[0..2] over the 1024 threads of a block in a fixed tree; every
 // thread returns the three totals.
 __device__ inline void block_sum3_1024(double v[3], double (*red)[1024]) {
@@ -764,8 +793,12 @@ hipError_t lbm_moments(Run& r) {
   if (by < 1) by = 1;
   if (by > g.ny) by = g.ny;
   dim3 blk(bx, by);
-  double* Vs = r.vor.mass_balance ? r.Vs : nullptr;
-  const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.nx * g.ny);
+  // flow along z: the slice means come with the moments (one block per z
+  // slice); along x or y: two small passes over u_a afterwards
+  const int axis = r.vor.mass_balance_axis;
+  const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+  double* Vs = (r.vor.mass_balance && axis == 2) ? r.Vs : nullptr;
+  const double scale = -(1.0 / r.vor.rho_s_over_rho_n) / ((double)g.cells / n);
   switch (r.prec) {
     case VLB_F64:
       hipLaunchKernelGGL((k_moments<double, double>), dim3(g.nz), blk, 0, r.stream, (const double*)r.pops, g, r.parity, (double*)r.ub, scale, Vs);
@@ -776,6 +809,14 @@ hipError_t lbm_moments(Run& r) {
     default:
       hipLaunchKernelGGL((k_moments<__half, float>), dim3(g.nz), blk, 0, r.stream, (const __half*)r.pops, g, r.parity, (float*)r.ub, scale, Vs);
       break;
+  }
+  if (r.vor.mass_balance && axis != 2) {
+    const dim3 pg((n + 63) / 64, g.nz);
+    if (r.prec == VLB_F64)
+      hipLaunchKernelGGL(k_mb_partial<double>, pg, dim3(64), 0, r.stream, (const double*)r.ub + (long long)axis * g.cells, g, axis, r.mbP);
+    else
+      hipLaunchKernelGGL(k_mb_partial<float>, pg, dim3(64), 0, r.stream, (const float*)r.ub + (long long)axis * g.cells, g, axis, r.mbP);
+    hipLaunchKernelGGL(k_mb_total, dim3((n + 63) / 64), dim3(64), 0, r.stream, (const double*)r.mbP, g.nz, n, scale, r.Vs);
   }
   return hipGetLastError();
 }

@@ -488,12 +488,13 @@ struct Run {
   void* pops = nullptr;   // 19 * cells storage values (deviations)
   void* force = nullptr;  // 3 * cells (double for F64, float otherwise)
   int32_t* touched = nullptr;  // 8 * ncap node indices written by spreading
-  double* Vs = nullptr;        // nz slice superflow
+  double* Vs = nullptr;        // superflow per cross-section along the flow axis
   void* ub = nullptr;          // 3 * cells bare velocity of the current step
   // the same for the next step: its moments are taken right after the LBM
   // update while the stages of this step still read ub (swapped at the
   // end of the step)
   double* Vs_next = nullptr;
+  double* mbP = nullptr;       // flow along x or y: per (z, cross-section) partial sums of the mass balance
   double* diag = nullptr;      // diagnostics results (8 + kSlabChunks nz doubles)
   double* seg = nullptr;       // diagnostics: z extent and length per segment (3 n_cap doubles)
   double* fric = nullptr;      // alpha(z), alpha'(z) profiles and their on flag (2 nz + 1 doubles)
@@ -652,7 +653,13 @@ hipError_t bs_prep(Run& r, const double* Y);
 hipError_t bs_sum(Run& r);
 int bs_chunks(long long ncap);
 
-hipError_t fil_finalize(Run& r, int stage, const double* Y, double* Ynext, int eval_only);
+// One finalize of a filament stage: stage of the Runge-Kutta method (1..rk),
+// first = the first stage of the step's first substep (leaves the stage-1
+// velocities, forces and spreading keys), last = the step's last stage (no
+// grid coordinates for a next sum).
+hipError_t fil_finalize(Run& r, int stage, int first, int last, const double* Y, double* Ynext,
+                        int eval_only);
+hipError_t fil_copy_positions(Run& r, const double* src, double* dst);
 hipError_t fil_spread(Run& r);
 hipError_t fil_seed(Run& r, long long n);
 

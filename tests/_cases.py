@@ -62,3 +62,25 @@ def small_periodic(precision="f64", seed=22, n_rings=5, n=(20, 16, 24)):
     pos, nxt = wl.random_rings(seed, n_rings, 2.0, 5.0, n, (False, False, False), 0.95)
     return dict(name=f"periodic{n}", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
                 steps=10)
+
+
+def duct(axis, precision="f64", seed=31, n_rings=6, n_flow=32, n_side=16, body=2e-5):
+    """Walled duct along `axis` (bounce-back walls on the other two axes,
+    periodic along it) with a body force and the mass-balance superflow
+    along it, and a few rings; the flow axis is longer than the others so
+    that an axis mix-up changes shapes."""
+    dims = [n_side] * 3
+    dims[axis] = n_flow
+    walls = [True] * 3
+    walls[axis] = False
+    bf = [0.0] * 3
+    bf[axis] = body
+    u0 = [0.0] * 3
+    u0[axis] = 0.015
+    lat = wl.lattice_preset(*dims, tau=0.8, walls=tuple(walls), body_force=tuple(bf),
+                            precision=precision)
+    vor = wl.vortex_preset(mass_balance=True, mass_balance_axis=axis)
+    rho, u = wl.velocity_field(seed, tuple(dims), tuple(u0), 2e-3)
+    pos, nxt = wl.random_rings(seed, n_rings, 2.0, 4.5, tuple(dims), tuple(walls), 0.95)
+    return dict(name=f"duct{'xyz'[axis]}{tuple(dims)}", lattice=lat, vortex=vor, rho=rho, u=u,
+                pos=pos, nxt=nxt, steps=8)

@@ -49,6 +49,8 @@ int main(void) {
   O(vlb_lattice_desc, body_force); O(vlb_vortex_desc, vs_applied); O(vlb_vortex_desc, remesh);
   O(vlb_vortex_desc, n_cap); O(vlb_vortex_desc, recon_cap); O(vlb_vortex_desc, wall_images);
   O(vlb_vortex_desc, ff_cell); O(vlb_vortex_desc, ff_levels); O(vlb_vortex_desc, ff_theta);
+  O(vlb_vortex_desc, mass_balance_axis); O(vlb_vortex_desc, rk_stages);
+  O(vlb_vortex_desc, vfm_substeps); O(vlb_vortex_desc, reserved2);
   printf("bs %zu\n", sizeof(vlb_bs_desc));
   O(vlb_bs_desc, wall_axes); O(vlb_bs_desc, precision); O(vlb_bs_desc, kappa);
   return 0;
@@ -150,10 +152,39 @@ def test_farfield_run_footprint():
     assert code == vlb.VLB_OK and ff > base + 4096 * 600
 
 
-def test_mass_balance_needs_periodic_z():
-    lat = wl.lattice_preset(16, 16, 16, walls=(False, False, True))
-    code, _, err = _query(lat, wl.vortex_preset(mass_balance=True))
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mass_balance_needs_a_periodic_flow_axis(axis):
+    walls = [True, True, True]
+    walls[axis] = False
+    lat = wl.lattice_preset(16, 16, 16, walls=tuple(walls))
+    code, _, _ = _query(lat, wl.vortex_preset(mass_balance=True, mass_balance_axis=axis))
+    assert code == vlb.VLB_OK
+    walls = [False, False, False]
+    walls[axis] = True
+    lat = wl.lattice_preset(16, 16, 16, walls=tuple(walls))
+    code, _, err = _query(lat, wl.vortex_preset(mass_balance=True, mass_balance_axis=axis))
     assert code == vlb.VLB_EINVAL and "mass balance" in err
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(mass_balance_axis=3), "mass_balance_axis"),
+    (dict(mass_balance_axis=-1), "mass_balance_axis"),
+    (dict(rk_stages=3), "rk_stages"),
+    (dict(rk_stages=-4), "rk_stages"),
+    (dict(vfm_substeps=65), "vfm_substeps"),
+    (dict(vfm_substeps=-1), "vfm_substeps"),
+])
+def test_integration_fields_rejected(bad, msg):
+    code, _, err = _query(wl.lattice_preset(16, 16, 16), wl.vortex_preset(**bad))
+    assert code == vlb.VLB_EINVAL and msg in err
+
+
+def test_zero_integration_fields_are_the_defaults():
+    """rk_stages 0 and vfm_substeps 0 mean the classical method in one step."""
+    lat = wl.lattice_preset(16, 16, 16)
+    code0, b0, _ = _query(lat, wl.vortex_preset(rk_stages=0, vfm_substeps=0))
+    code1, b1, _ = _query(lat, wl.vortex_preset())
+    assert code0 == code1 == vlb.VLB_OK and b0 == b1
 
 
 def test_zero_capacity_rejected():

@@ -510,11 +510,11 @@ __global__ void k_read_force(const T* __restrict__ F, long long n, double* out) 
 
 // Bare normal-fluid velocity u_b = sum(c f)/sum(f) of every node (velocity
 // planes applied), written once per step for the interpolation onto the
-// filaments, fused with the mean of u_z over each z slice that the
-// mass-balance superflow needs (Sec. III.C, Eq. mass cons): one block per
-// slice walks the slice in tiles (x fastest), each thread adds its nodes'
-// u_z in order, the block adds the threads' sums in a fixed tree, and
-// Vs[z] = scale * sum.
+// filaments, fused (flow along z) with the mean of u_z over each z slice
+// that the mass-balance superflow needs (Sec. III.C, Eq. mass cons): one
+// block per slice walks the slice in tiles (x fastest), each thread adds
+// its nodes' u_z in order, the block adds the threads' sums in a fixed
+// tree, and Vs[z] = scale * sum.  Vs is null otherwise.
 template <class S, class UT>
 __global__ __launch_bounds__(1024) void k_moments(const S* __restrict__ M, Geom g, int parity,
                                                  UT* __restrict__ ub, double scale,

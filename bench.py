@@ -163,7 +163,7 @@ def sample_window(cfg, width=32):
     return o, w
 
 
-def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
+def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=None):
     """The FP64 oracle on a bounded sample of the workload, on the host's
     cores, from the seeded state:
       * Biot-Savart sums (every segment) at sampled targets: the points of a
@@ -198,7 +198,7 @@ def cpu_baseline(cfg, workers=None, per_worker=128, single=48, width=32):
     nxt = np.asarray(cfg["nxt"], dtype=np.int64)
     prv = coupled.prev_from_next(nxt)
     n = pos.shape[0]
-    o, w = sample_window(cfg, width)
+    o, w = sample_window(cfg, width if width is not None else cfg.get("crop_width", 32))
     o_arr = np.array(o, dtype=np.float64)
 
     # targets: every point whose stencil reaches the crop, plus a random draw

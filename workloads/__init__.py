@@ -225,8 +225,9 @@ def config_heater(precision="f32", n_rings=1500, nxy=128, nz=512, seed=3):
     rho, u = velocity_field(seed, (nxy, nxy, nz), (0.0, 0.0, 0.03), 0.0)
     pos, nxt = random_rings(seed, n_rings, 3.0, 7.6, (nxy, nxy, nz), (True, True, False), 0.95,
                             min_sep=1.5)
+    # the accuracy sample's lattice crop: 64^3 centred at (64, 64, 256)
     return dict(name="heater_128x128x512", lattice=lat, vortex=vor, rho=rho, u=u,
-                pos=pos, nxt=nxt, steps=2000)
+                pos=pos, nxt=nxt, steps=2000, crop_width=64)
 
 
 def config_closed_channel(precision="f64", nxy=48, nz=128, seed=6):

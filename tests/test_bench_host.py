@@ -123,3 +123,15 @@ def test_cpu_baseline_sample_with_wall_bound_lines():
     assert t.size > 0 and base["value"] > 0
     for k in ("vs", "vn", "sdot", "force"):
         np.testing.assert_allclose(ref[k], full[k][t], rtol=0, atol=1e-14)
+
+
+def test_accuracy_crops():
+    """The heater channel is checked on a 64^3 crop centred at (64, 64, 256);
+    the other workloads on a centred 32^3 crop (at most half the smallest
+    extent)."""
+    heater = wl.config_heater("f32", n_rings=4)
+    assert bench.sample_window(heater, heater["crop_width"]) == ((32, 32, 224), 64)
+    tangle = dict(lattice=wl.lattice_preset(256, 256, 256))
+    assert bench.sample_window(tangle) == ((112, 112, 112), 32)
+    small = dict(lattice=wl.lattice_preset(32, 32, 32))
+    assert bench.sample_window(small) == ((8, 8, 8), 16)

@@ -6,6 +6,7 @@ mass cons), against the oracle."""
 import numpy as np
 import pytest
 
+import workloads as wl
 from oracle import coupled, lbm, vfm
 from tests._cases import duct, oracle_state, rel_l2, say, small_channel
 
@@ -73,7 +74,7 @@ def _compare_steps(cfg, steps, precision):
 
 
 @pytest.mark.parametrize("axis", [0, 1])
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
 def test_mass_balance_axis_coupled(axis, precision):
     cfg = duct(axis, precision)
     say("mass balance coupled", cfg["name"], precision)
@@ -108,6 +109,18 @@ def test_integration_coupled_reduced(stages, substeps, precision):
     cfg["vortex"].update(rk_stages=stages, vfm_substeps=substeps)
     say("integration", precision, stages, "stages", substeps, "substeps")
     _compare_steps(cfg, 5, precision)
+
+
+def test_integration_with_farfield():
+    """The midpoint rule in two substeps with the two-level far-field sum in
+    every stage (FP32, 64^3 tangle of 20 rings): links equal to the
+    oracle's (same approximation) after every step, positions within 1e-4,
+    velocity within 1e-5."""
+    cfg = wl.config_tangle(precision="f32", n=64, n_rings=20, seed=5)
+    cfg["vortex"] = dict(cfg["vortex"], ff_cell=8, ff_levels=2, ff_theta=0.3, rk_stages=2,
+                         vfm_substeps=2)
+    say("integration with far field", cfg["pos"].shape[0], "points")
+    _compare_steps(cfg, 2, "f32")
 
 
 def test_integration_graph_replay():

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from tests._cases import say, small_channel, small_periodic
+from tests._cases import duct, say, small_channel, small_periodic
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +34,16 @@ def _assert_same(a, b):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("case", ["channel", "periodic"])
+@pytest.mark.parametrize("case", ["channel", "periodic", "duct_x_midpoint"])
 def test_checkpoint_resume_bitwise(case, precision):
-    cfg = (small_channel(precision=precision, reconnect=True, seed=51) if case == "channel"
-           else small_periodic(precision=precision, seed=52))
+    if case == "channel":
+        cfg = small_channel(precision=precision, reconnect=True, seed=51)
+    elif case == "duct_x_midpoint":
+        # flow and mass balance along x; the midpoint rule in two substeps
+        cfg = duct(0, precision=precision, seed=53)
+        cfg["vortex"].update(rk_stages=2, vfm_substeps=2, reconnect=True)
+    else:
+        cfg = small_periodic(precision=precision, seed=52)
     k, m = 5, 6   # odd k: the checkpoint is taken in the swapped AA layout
     say("checkpoint", case, precision, k, m)
     a = vlb.run_from_config(cfg)

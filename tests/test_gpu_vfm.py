@@ -162,6 +162,40 @@ def test_ring32_hundred_steps_f64():
     run.close()
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_ring32_hundred_steps_reduced_precision(precision):
+    """The precision forms over the plain small case: 100 coupled steps with
+    FP32 or FP16 population storage against the FP64 oracle; the ring stays
+    inside the remeshing bounds (no topology event), so the links stay the
+    oracle's; velocity field and line velocity within the form's tolerance
+    (FP32 1e-5, FP16 1e-3, relative L2)."""
+    cfg = wl.config_ring32(precision=precision)
+    say("ring32 100 steps", precision)
+    run = vlb.run_from_config(cfg)
+    lat, vp, st = oracle_state(cfg)
+    for _ in range(10):
+        run.step(10)
+        for _ in range(10):
+            st = coupled.coupled_step(st, lat, vp)
+        run.sync()
+        pos_g, nxt_g = run.read_filaments()
+        np.testing.assert_array_equal(nxt_g, st.nxt)
+        d = np.abs(vfm.min_image(pos_g - st.pos, lat)).max()
+        assert d < (1e-4 if precision == "f32" else 1e-2), d
+    _, u_g = run.read_fields()
+    _, u_o = lbm.bare_velocity(st.f, lat)
+    err = rel_l2(u_g, u_o)
+    say("velocity field", err, "positions", d)
+    assert err <= TOL[precision]
+    got = run.eval_line_velocity()
+    ref = vfm.line_velocity(st.pos, st.nxt, st.prv, u_o, None, lat, vp, want_force=True)
+    for k in ("vs", "vn", "sdot"):
+        e = rel_l2(got[k], ref[k])
+        say(k, e)
+        assert e <= TOL[precision], (k, e)
+    run.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["channel", "periodic"])
 def test_applied_superflow_eval(case, precision):

@@ -113,6 +113,49 @@ def test_lbm_mass_drift_ten_thousand_steps(precision):
     run.close()
 
 
+def test_uniform_equilibrium_is_a_fixed_point_f64():
+    """A uniform flow at equilibrium with no force on a periodic lattice
+    stays where it is (Sec. II.B: f^eq collides to itself, streaming moves
+    equal values): populations after 100 steps equal the initial ones to
+    round-off."""
+    n = (12, 10, 9)
+    lat = wl.lattice_preset(*n, tau=0.8, precision="f64")
+    rho = np.full((n[2], n[1], n[0]), 1.0)
+    u = np.zeros((3, n[2], n[1], n[0]))
+    u[0], u[1], u[2] = 0.01, -0.02, 0.015
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
+    run.write_fields(rho, u)
+    f0 = run.read_populations()
+    run.step(100)
+    run.sync()
+    f1 = run.read_populations()
+    assert np.abs(f1 - f0).max() <= 1e-15
+    run.close()
+
+
+def test_body_force_momentum_bookkeeping_f64():
+    """Guo forcing adds exactly the body force to the momentum of a periodic
+    lattice per step (Sec. II.B, Eq. F_i: collision gives g / (2 tau), the
+    forcing term (1 - 1 / (2 tau)) g): after N steps sum(rho u) has grown by
+    N cells g, u being the force-shifted velocity."""
+    n = (10, 8, 12)
+    g = np.array([2e-5, -1e-5, 3e-5])
+    lat = wl.lattice_preset(*n, tau=0.9, body_force=tuple(g), precision="f64")
+    rho, u = wl.velocity_field(34, n, (0.005, 0.0, -0.01), 2e-3)
+    run = vlb.Run(lat, wl.vortex_preset(), n_cap=1)
+    run.write_fields(rho, u)
+    r0, u0 = run.read_fields()
+    steps = 40
+    run.step(steps)
+    run.sync()
+    r1, u1 = run.read_fields()
+    cells = n[0] * n[1] * n[2]
+    for a in range(3):
+        gain = (r1 * u1[a]).sum() - (r0 * u0[a]).sum()
+        assert abs(gain - steps * cells * g[a]) < 1e-12, (a, gain, steps * cells * g[a])
+    run.close()
+
+
 def test_poiseuille_gpu_f64():
     """Exact discrete Poiseuille profile reached by the GPU (plane channel,
     walls on y, body force along x)."""

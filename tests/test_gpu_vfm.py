@@ -162,6 +162,48 @@ def test_ring32_hundred_steps_f64():
     run.close()
 
 
+def test_ring_relations_in_fluid_at_rest_f64():
+    """Sec. II.A, Eq. (E of M) for a circular ring in a normal fluid at rest
+    (v_n = 0): the line moves with (1 - alpha') V along its axis and shrinks
+    at alpha V, V the self-induced speed, which the GPU's own v_s gives."""
+    n = 32
+    lat = wl.lattice_preset(n, n, n, tau=0.8, precision="f64")
+    vor = wl.vortex_preset(alpha=0.2, alpha_p=0.05, coupling=False)
+    pos, nxt = wl.ring((16.0, 16.0, 16.0), 8.0, (0.0, 0.0, 1.0), 64, phase=0.5)
+    rho = np.ones((n, n, n))
+    u = np.zeros((3, n, n, n))
+    cfg = dict(name="ring_at_rest", lattice=lat, vortex=vor, rho=rho, u=u, pos=pos, nxt=nxt,
+               steps=1)
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    pos_g, _ = run.read_filaments()
+    radial = pos_g[:, :2] - 16.0
+    radial /= np.linalg.norm(radial, axis=1)[:, None]
+    V = got["vs"][:, 2]
+    assert np.abs(got["vn"]).max() < 1e-15
+    np.testing.assert_allclose(got["sdot"][:, 2], (1.0 - 0.05) * V, rtol=1e-12, atol=0)
+    dr = (got["sdot"][:, :2] * radial).sum(axis=1)
+    np.testing.assert_allclose(dr, -0.2 * V, rtol=1e-12, atol=0)
+    run.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_spread_force_sums_to_the_point_forces(precision):
+    """Spreading with delta_2pt weights that sum to one (Sec. II.B) keeps
+    the total: away from walls the lattice force field adds up to the sum
+    of the point forces."""
+    cfg = small_periodic(precision=precision)
+    run = vlb.run_from_config(cfg)
+    got = run.eval_line_velocity()
+    F = run.read_force()
+    tot_pts = got["force"].sum(axis=0)
+    tot_lat = F.reshape(3, -1).sum(axis=1)
+    scale = np.abs(got["force"]).sum(axis=0)
+    tol = 1e-13 if precision == "f64" else 1e-6
+    assert (np.abs(tot_lat - tot_pts) <= tol * scale).all(), (tot_lat, tot_pts)
+    run.close()
+
+
 @pytest.mark.parametrize("precision", ["f32", "f16"])
 def test_ring32_hundred_steps_reduced_precision(precision):
     """The precision forms over the plain small case: 100 coupled steps with

@@ -187,6 +187,29 @@ def test_ring_relations_in_fluid_at_rest_f64():
     run.close()
 
 
+def test_interpolation_exact_on_a_linear_field_f64():
+    """The two-point delta interpolation (Sec. II.B, Eq. delta_2pt) is
+    trilinear, so it reproduces a linear normal-fluid velocity u = A x + b
+    at every point whose stencil lies away from the periodic seams."""
+    n = 32
+    lat = wl.lattice_preset(n, n, n, tau=0.8, precision="f64")
+    A = np.array([[1e-4, -2e-4, 3e-4], [2e-4, 1e-4, -1e-4], [-3e-4, 2e-4, 2e-4]])
+    b = np.array([0.002, -0.001, 0.004])
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X = np.stack([x, y, z]).astype(np.float64)
+    u = np.einsum("ab,b...->a...", A, X) + b[:, None, None, None]
+    rho = np.ones((n, n, n))
+    pos, nxt = wl.ring((15.3, 16.1, 15.7), 6.0, (0.3, -0.4, 0.866), 48, phase=0.5)
+    cfg = dict(name="linear_field", lattice=lat, vortex=wl.vortex_preset(coupling=False),
+               rho=rho, u=u, pos=pos, nxt=nxt, steps=1)
+    run = vlb.run_from_config(cfg)
+    vn = run.eval_line_velocity()["vn"]
+    p, _ = run.read_filaments()
+    want = p @ A.T + b
+    np.testing.assert_allclose(vn, want, rtol=0, atol=1e-15)
+    run.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_thin_ring_speed_closed_form(precision):
     """Biot-Savart sum plus LIA term (Sec. II.A, reading R3, C = 1/2) of a

@@ -370,7 +370,9 @@ def measure(cfg, args, ref, graph):
     advance(step_plan(args.warmup, graph))
     run.sync()
     direct = graph == 0
-    run.set_timing(direct, reserve=2 * 2 * args.steps + 64)  # also zeroes the work counters
+    # two events per timed launch: every stage's sum and the LBM update
+    launches = int(cfg["vortex"].get("rk_stages", 4)) * int(cfg["vortex"].get("vfm_substeps", 1)) + 1
+    run.set_timing(direct, reserve=2 * launches * args.steps + 64)  # also zeroes the work counters
     ev = []
     plan = step_plan(args.steps, graph)
     torch.cuda.synchronize()
@@ -724,6 +726,10 @@ def parse_args(argv=None):
                          "sum (periodic workloads; 0: not measured)")
     ap.add_argument("--ff-theta", type=float, default=0.25)
     ap.add_argument("--ff-levels", type=int, default=2, choices=(1, 2))
+    ap.add_argument("--rk-stages", type=int, default=None, choices=(1, 2, 4),
+                    help="Runge-Kutta stages of the filament integration (default: the workload's, 4)")
+    ap.add_argument("--vfm-substeps", type=int, default=None,
+                    help="filament substeps per lattice step (default: the workload's, 1)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=16,
                     help="requests of the short served mix in the tangle line (0: none)")
@@ -771,6 +777,11 @@ def main(argv=None):
     cfg = make_workload(args.workload, args.head_precision)
     if args.wall_images:
         cfg["vortex"] = dict(cfg["vortex"], wall_images=True)
+    # time integration of the filaments (classical RK4 in one step unless set)
+    if args.rk_stages is not None or args.vfm_substeps is not None:
+        cfg["vortex"] = dict(cfg["vortex"],
+                             rk_stages=args.rk_stages or cfg["vortex"].get("rk_stages", 4),
+                             vfm_substeps=args.vfm_substeps or cfg["vortex"].get("vfm_substeps", 1))
     print(f"[bench] workload {cfg['name']}: {cfg['pos'].shape[0]} points, "
           f"{time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     base, ref = None, None
@@ -873,6 +884,8 @@ def main(argv=None):
             "mass_balance": bool(cfg["vortex"]["mass_balance"]),
             "reconnect": bool(cfg["vortex"]["reconnect"]),
             "wall_images": bool(cfg["vortex"].get("wall_images", False)),
+            "rk_stages": int(cfg["vortex"].get("rk_stages", 4)),
+            "vfm_substeps": int(cfg["vortex"].get("vfm_substeps", 1)),
             "graph_steps": args.graph,
         },
         "step_ms_p50": head["step_ms_p50"],

@@ -123,6 +123,16 @@ def test_integration_with_farfield():
     _compare_steps(cfg, 2, "f32")
 
 
+def test_integration_with_wall_images():
+    """Forward Euler in two substeps with the superfluid wall term (image
+    copies prepared at every stage's positions), FP64 channel: links exact,
+    positions and velocity within 1e-10 of the oracle."""
+    cfg = small_channel(precision="f64", seed=29)
+    cfg["vortex"].update(wall_images=True, rk_stages=1, vfm_substeps=2)
+    say("integration with wall images")
+    _compare_steps(cfg, 4, "f64")
+
+
 def test_integration_graph_replay():
     """Midpoint rule in two substeps, reconnection on: graph replays are
     bitwise equal to direct steps."""

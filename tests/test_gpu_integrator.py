@@ -133,6 +133,17 @@ def test_integration_with_wall_images():
     _compare_steps(cfg, 4, "f64")
 
 
+def test_integration_with_wall_bound_lines():
+    """The midpoint rule in two substeps on the closed channel (four lines
+    bound to the end walls, two rings, wall images; FP64): the ends keep
+    sliding on their walls at every stage; links exact, positions and
+    velocity within 1e-10 of the oracle."""
+    cfg = wl.config_closed_channel("f64")
+    cfg["vortex"] = dict(cfg["vortex"], rk_stages=2, vfm_substeps=2)
+    say("integration with wall-bound lines", cfg["pos"].shape[0], "points")
+    _compare_steps(cfg, 2, "f64")
+
+
 def test_integration_graph_replay():
     """Midpoint rule in two substeps, reconnection on: graph replays are
     bitwise equal to direct steps."""

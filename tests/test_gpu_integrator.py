@@ -144,6 +144,28 @@ def test_integration_with_wall_bound_lines():
     _compare_steps(cfg, 2, "f64")
 
 
+@pytest.mark.parametrize("seed", [101, 102, 103, 104, 105, 106, 107, 108])
+def test_option_combinations(seed):
+    """Seeded draws of the run options together (precision, stages,
+    substeps, flow axis of a duct, reconnection, force model, coupling),
+    three coupled steps each against the oracle: links exact after every
+    step, positions and velocity within the precision form's tolerance."""
+    rng = np.random.default_rng(seed)
+    precision = ("f64", "f32", "f16")[rng.integers(3)]
+    axis = int(rng.integers(3))
+    cfg = duct(axis, precision=precision, seed=seed)
+    cfg["vortex"].update(rk_stages=int((1, 2, 4)[rng.integers(3)]),
+                         vfm_substeps=int(rng.integers(1, 4)),
+                         reconnect=bool(rng.integers(2)),
+                         force_model=int(rng.integers(2)),
+                         coupling=bool(rng.integers(4) > 0))
+    v = cfg["vortex"]
+    say("options", seed, precision, "axis", axis, "rk", v["rk_stages"], "substeps",
+        v["vfm_substeps"], "reconnect", v["reconnect"], "force model", v["force_model"],
+        "coupling", v["coupling"])
+    _compare_steps(cfg, 3, precision)
+
+
 def test_integration_graph_replay():
     """Midpoint rule in two substeps, reconnection on: graph replays are
     bitwise equal to direct steps."""

@@ -349,7 +349,7 @@ def measure(cfg, args, ref, graph):
     n0 = cfg["pos"].shape[0]
     stream = torch.cuda.Stream()   # default priority; graphs need a non-null stream
     torch.cuda.set_stream(stream)
-    run = vlb.run_from_config(cfg, n_cap=point_capacity(n0, args.steps + args.warmup + 1),
+    run = vlb.run_from_config(cfg, n_cap=point_capacity(n0, args.capacity_factor),
                               recon_cap=1 << 18)
     cells = lat["nx"] * lat["ny"] * lat["nz"]
     acc = accuracy(run, ref) if ref is not None else None
@@ -434,11 +434,11 @@ def measure(cfg, args, ref, graph):
     return row, extra
 
 
-def point_capacity(n0, steps):
-    """Point capacity of a run of ``steps`` coupled steps from n0 points:
-    remeshing adds about 0.6% per step on the tangle (1.04e5 -> 1.20e5 in
-    26 steps); twice that, at least 1.4 n0."""
-    return int(n0 * max(1.4, 1.0 + 0.012 * steps)) + 256
+def point_capacity(n0, factor=1.4):
+    """Point capacity of a run from n0 points: room for the remeshing's
+    growth (the tangle grows by 28% over 100 steps, counterflow by 26% over
+    220); the capacity also sizes the Biot-Savart launch."""
+    return int(n0 * factor) + 256
 
 
 def lbm_kernel_name(lat):
@@ -619,7 +619,7 @@ def farfield_steps(torch, vlb, cfg, args, cell, theta, levels):
     n0 = cfg["pos"].shape[0]
     stream = torch.cuda.Stream()   # default priority; graphs need a non-null stream
     torch.cuda.set_stream(stream)
-    run = vlb.run_from_config(cfg, n_cap=point_capacity(n0, args.steps + args.warmup + 1),
+    run = vlb.run_from_config(cfg, n_cap=point_capacity(n0, args.capacity_factor),
                               recon_cap=1 << 18)
     graph = args.graph
 
@@ -730,6 +730,9 @@ def parse_args(argv=None):
                     help="Runge-Kutta stages of the filament integration (default: the workload's, 4)")
     ap.add_argument("--vfm-substeps", type=int, default=None,
                     help="filament substeps per lattice step (default: the workload's, 1)")
+    ap.add_argument("--capacity-factor", type=float, default=1.4,
+                    help="point capacity of the runs as a multiple of the seeded points "
+                         "(raise it for long runs)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--served-requests", type=int, default=16,
                     help="requests of the short served mix in the tangle line (0: none)")

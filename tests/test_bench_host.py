@@ -137,8 +137,8 @@ def test_accuracy_crops():
     assert bench.sample_window(small) == ((8, 8, 8), 16)
 
 
-def test_point_capacity_grows_with_the_run():
-    """The default run (26 steps) keeps 1.4 n0; longer runs get room for the
-    remeshing's growth."""
-    assert bench.point_capacity(104175, 26) == int(104175 * 1.4) + 256
-    assert bench.point_capacity(104175, 200) == int(104175 * 3.4) + 256
+def test_point_capacity():
+    """1.4 n0 (+ 256) by default, the factor on request."""
+    assert bench.point_capacity(104175) == int(104175 * 1.4) + 256
+    assert bench.point_capacity(104175, 2.5) == int(104175 * 2.5) + 256
+    assert bench.parse_args([]).capacity_factor == 1.4
